@@ -1,0 +1,126 @@
+"""FP64 CPU oracle for the tangent-point energy and its gradient.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py``.  The library's product path never imports, links or calls anything here.
+
+The arithmetic lives in ``tpe_oracle.c`` (plain C, FP64, OpenMP over rows); this module builds it with
+gcc and calls it through ctypes on NumPy arrays.  See ``tpe_oracle.c`` for the definition it follows
+(paper Sec. 2, eq. (TP), one-point centroid quadrature on flat triangles, ordered pairs of faces that
+share no vertex) and for the gradient's chain rule.
+
+Parity pins: closed forms (two-triangle example, sphere limit), exact identities (scaling law, Euler
+identity, zero net force and torque, rigid-motion, orientation and permutation invariance), brute-force
+pair counts and central finite differences -- see tests/test_oracle.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tpe_oracle.c")
+_LIB = os.path.join(_HERE, "libtpe_oracle.so")
+_lib = None
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "degenerate face", -3: "non-finite"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"oracle error {code}: {ERRORS.get(code, '?')}")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+            "-fno-fast-math", _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        D, I64, I32, P = ctypes.c_double, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        lib.tpeo_energy.argtypes = [P, I64, P, I64, D, D, D, I32, P]
+        lib.tpeo_energy_rows.argtypes = [P, I64, P, I64, D, D, D, I64, I64, I32, P]
+        lib.tpeo_gradient.argtypes = [P, I64, P, I64, D, D, D, I32, P, P]
+        lib.tpeo_gradient_at.argtypes = [P, I64, P, I64, D, D, D, P, I64, I32, P]
+        lib.tpeo_pair_count.argtypes = [P, I64]
+        lib.tpeo_pair_count.restype = I64
+        lib.tpeo_num_threads.argtypes = [I32]
+        for f in (lib.tpeo_energy, lib.tpeo_energy_rows, lib.tpeo_gradient, lib.tpeo_gradient_at):
+            f.restype = I32
+        _lib = lib
+    return _lib
+
+
+def _prep(X, F):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    assert X.ndim == 2 and X.shape[1] == 3 and F.ndim == 2 and F.shape[1] == 3
+    return X, F
+
+
+def num_threads(nthreads: int = 0) -> int:
+    return int(_load().tpeo_num_threads(nthreads))
+
+
+def energy(X, F, q=6.0, p=12.0, scale=1.0, nthreads=0) -> float:
+    X, F = _prep(X, F)
+    E = np.zeros(1)
+    rc = _load().tpeo_energy(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
+                             nthreads, E.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0])
+
+
+def energy_rows(X, F, r0, r1, q=6.0, p=12.0, scale=1.0, nthreads=0) -> float:
+    """Sum over rows S in [r0, r1) of a_S sum_T a_T k(S,T) (times scale)."""
+    X, F = _prep(X, F)
+    E = np.zeros(1)
+    rc = _load().tpeo_energy_rows(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
+                                  r0, r1, nthreads, E.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0])
+
+
+def gradient(X, F, q=6.0, p=12.0, scale=1.0, nthreads=0):
+    """Returns (E, G) with G = dE/dX, shape [V, 3]."""
+    X, F = _prep(X, F)
+    E = np.zeros(1)
+    G = np.zeros_like(X)
+    rc = _load().tpeo_gradient(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
+                               nthreads, E.ctypes.data, G.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G
+
+
+def gradient_at(X, F, verts, q=6.0, p=12.0, scale=1.0, nthreads=0):
+    """Exact dE/dx_v for the listed vertices only, shape [len(verts), 3]."""
+    X, F = _prep(X, F)
+    verts = np.ascontiguousarray(verts, dtype=np.int32)
+    G = np.zeros((verts.size, 3))
+    rc = _load().tpeo_gradient_at(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
+                                  verts.ctypes.data, verts.size, nthreads, G.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return G
+
+
+def pair_count(F) -> int:
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    return int(_load().tpeo_pair_count(F.ctypes.data, F.shape[0]))

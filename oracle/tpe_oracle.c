@@ -1,0 +1,345 @@
+/*
+ * FP64 CPU oracle for the discrete tangent-point energy and its vertex gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path may link, load or call
+ * this file: it exists so that tests, the smoke check and the benchmark's CPU-baseline leg
+ * can compare the HIP implementation against a plain, slow, obviously correct evaluation of
+ * the definition.  It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes (paper, Sec. 2 "Self-avoidance", eq. (TP), with one-point centroid
+ * quadrature on flat triangles):
+ *
+ *   For each face T = (i, j, k):  w_T = (x_j - x_i) x (x_k - x_i),  a_T = |w_T| / 2,
+ *                                 n_T = w_T / |w_T|,               c_T = (x_i + x_j + x_k) / 3.
+ *
+ *   E(X) = scale * sum_S sum_{T : S and T share no vertex}  a_S a_T |n_S . (c_S - c_T)|^q
+ *                                                                 / |c_S - c_T|^p
+ *
+ * over ORDERED face pairs (the double integral over S x S counts both orders).  The paper's
+ * energy is q = alpha, p = 2 alpha, scale = rho / alpha (the kernel (1/R)^alpha with the
+ * tangent-point radius R = |x-y|^2 / (2 |n(x).(x-y)|) equals 2^alpha |n.(x-y)|^alpha/|x-y|^{2 alpha},
+ * and the prefactor 2^-alpha cancels the 2^alpha).
+ *
+ * The gradient is the exact derivative of that expression with respect to X by the chain
+ * rule through c, a and n (the discrete counterpart of the paper's deformation derivative,
+ * eq. (dTP)):  with u = n_S . d, d = c_S - c_T, r = |d|,  k(d; n) = |u|^q r^-p,
+ *     dk/dd = q |u|^(q-2) u r^-p n  -  p |u|^q r^-(p+2) d,     dk/dn = q |u|^(q-2) u r^-p d.
+ * Every pair's derivative is pushed straight to the (up to six) vertices of S and T.  This is
+ * deliberately a different organisation from any per-face accumulation scheme.
+ *
+ * Summation: rows ascending, columns ascending, FP64 with Neumaier compensation; with
+ * OpenMP, rows are split statically over threads, each thread keeps its own compensated
+ * buffers and the buffers are merged in thread order (deterministic for a fixed thread count).
+ *
+ * Return codes: 0 ok, -1 invalid argument, -2 degenerate face (area <= 1e-300),
+ * -3 non-finite input or a coincident non-adjacent centroid pair (E = +inf there).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OK 0
+#define EINVAL_ -1
+#define EDEGEN -2
+#define ENONFIN -3
+
+typedef struct { double s, c; } nsum; /* Neumaier running sum */
+
+static void nadd(nsum* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum* a) { return a->s + a->c; }
+
+/* x^e for a non-negative real exponent; integer exponents by plain repeated multiplication */
+static double powr(double x, double e) {
+    if (e >= 0.0 && e == floor(e) && e <= 64.0) {
+        double r = 1.0;
+        for (int i = 0; i < (int)e; ++i) r *= x;
+        return r;
+    }
+    return pow(x, e);
+}
+
+typedef struct { double w[3], a, n[3], c[3], wn; } face_t;
+
+static void sub3(const double* a, const double* b, double* o) { o[0]=a[0]-b[0]; o[1]=a[1]-b[1]; o[2]=a[2]-b[2]; }
+static double dot3(const double* a, const double* b) { return a[0]*b[0]+a[1]*b[1]+a[2]*b[2]; }
+static void cross3(const double* a, const double* b, double* o) {
+    o[0] = a[1]*b[2] - a[2]*b[1];
+    o[1] = a[2]*b[0] - a[0]*b[2];
+    o[2] = a[0]*b[1] - a[1]*b[0];
+}
+
+static int face_geom(const double* X, const int32_t* F, int64_t f, face_t* g) {
+    const double* xi = X + 3 * (int64_t)F[3*f+0];
+    const double* xj = X + 3 * (int64_t)F[3*f+1];
+    const double* xk = X + 3 * (int64_t)F[3*f+2];
+    double e1[3], e2[3];
+    sub3(xj, xi, e1); sub3(xk, xi, e2);
+    cross3(e1, e2, g->w);
+    g->wn = sqrt(dot3(g->w, g->w));
+    g->a = 0.5 * g->wn;
+    if (!(g->a > 1e-300)) return EDEGEN;
+    for (int d = 0; d < 3; ++d) {
+        g->n[d] = g->w[d] / g->wn;
+        g->c[d] = (xi[d] + xj[d] + xk[d]) / 3.0;
+    }
+    return OK;
+}
+
+static int share_vertex(const int32_t* F, int64_t s, int64_t t) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (F[3*s+i] == F[3*t+j]) return 1;
+    return 0;
+}
+
+static int check_inputs(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p) {
+    if (!X || !F || V <= 0 || nF <= 0) return EINVAL_;
+    if (!(q >= 2.0) || !(p > q)) return EINVAL_;
+    for (int64_t i = 0; i < 3 * nF; ++i)
+        if (F[i] < 0 || F[i] >= V) return EINVAL_;
+    for (int64_t i = 0; i < 3 * V; ++i)
+        if (!isfinite(X[i])) return ENONFIN;
+    return OK;
+}
+
+static int all_faces(const double* X, const int32_t* F, int64_t nF, face_t* G) {
+    for (int64_t f = 0; f < nF; ++f) {
+        int rc = face_geom(X, F, f, &G[f]);
+        if (rc) return rc;
+    }
+    return OK;
+}
+
+/* Kernel value and its partial derivatives for one ordered pair (S as x, T as y). */
+typedef struct { double k, dkdd[3], dkdn[3]; } pairval;
+
+static int pair_eval(const face_t* S, const face_t* T, double q, double p, int want_grad, pairval* o) {
+    double d[3];
+    sub3(S->c, T->c, d);
+    double r2 = dot3(d, d);
+    if (!(r2 > 0.0)) return ENONFIN;
+    double u = dot3(S->n, d);
+    double au = fabs(u);
+    double rmp = 1.0 / powr(sqrt(r2), p);       /* r^-p */
+    double auq = powr(au, q);                   /* |u|^q */
+    o->k = auq * rmp;
+    if (want_grad) {
+        double uq1 = powr(au, q - 2.0) * u;     /* |u|^(q-2) u */
+        double A = q * uq1 * rmp;
+        double B = p * auq * rmp / r2;
+        for (int i = 0; i < 3; ++i) {
+            o->dkdd[i] = A * S->n[i] - B * d[i];
+            o->dkdn[i] = A * d[i];
+        }
+    }
+    return OK;
+}
+
+/* Push dE/dc, dE/dn, dE/da of face f onto its vertices (chain rule through c, n, a). */
+static void face_vjp(const double* X, const int32_t* F, int64_t f, const face_t* g,
+                     const double* dc, const double* dn, double da, nsum* GV) {
+    int32_t v[3] = {F[3*f+0], F[3*f+1], F[3*f+2]};
+    double gw[3];
+    double ndn = dn ? dot3(g->n, dn) : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        gw[d] = 0.5 * da * g->n[d];
+        if (dn) gw[d] += (dn[d] - ndn * g->n[d]) / g->wn;
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double* xj = X + 3 * (int64_t)v[(c + 1) % 3];
+        const double* xk = X + 3 * (int64_t)v[(c + 2) % 3];
+        double e[3], cr[3];
+        sub3(xj, xk, e);
+        cross3(e, gw, cr);
+        for (int d = 0; d < 3; ++d) nadd(&GV[3 * (int64_t)v[c] + d], dc[d] / 3.0 + cr[d]);
+    }
+}
+
+static int nthreads_of(int req) {
+#ifdef _OPENMP
+    return req > 0 ? req : omp_get_max_threads();
+#else
+    (void)req; return 1;
+#endif
+}
+
+int tpeo_num_threads(int req) { return nthreads_of(req); }
+
+int64_t tpeo_pair_count(const int32_t* F, int64_t nF) {
+    int64_t n = 0;
+    for (int64_t s = 0; s < nF; ++s)
+        for (int64_t t = 0; t < nF; ++t)
+            if (!share_vertex(F, s, t)) ++n;
+    return n;
+}
+
+/* E over the row range [r0, r1) of faces S (full columns).  Used for the full energy and for
+ * row-sampled partial energies. */
+int tpeo_energy_rows(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                     double scale, int64_t r0, int64_t r1, int nthreads, double* E_out) {
+    int rc = check_inputs(X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (r0 < 0 || r1 > nF || r0 > r1 || !E_out) return EINVAL_;
+    face_t* G = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
+    if (!G) return EINVAL_;
+    rc = all_faces(X, F, nF, G);
+    if (rc) { free(G); return rc; }
+    int nt = nthreads_of(nthreads);
+    nsum* part = (nsum*)calloc((size_t)nt, sizeof(nsum));
+    int err = OK;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        nsum acc = {0.0, 0.0};
+        int lerr = OK;
+#pragma omp for schedule(static)
+        for (int64_t s = r0; s < r1; ++s) {
+            for (int64_t t = 0; t < nF; ++t) {
+                if (share_vertex(F, s, t)) continue;
+                pairval pv;
+                if (pair_eval(&G[s], &G[t], q, p, 0, &pv)) { lerr = ENONFIN; continue; }
+                nadd(&acc, G[s].a * G[t].a * pv.k);
+            }
+        }
+        part[tid] = acc;
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    nsum tot = {0.0, 0.0};
+    for (int i = 0; i < nt; ++i) { nadd(&tot, part[i].s); nadd(&tot, part[i].c); }
+    *E_out = err ? INFINITY : scale * nval(&tot);
+    free(part); free(G);
+    return err;
+}
+
+int tpeo_energy(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                double scale, int nthreads, double* E_out) {
+    return tpeo_energy_rows(X, V, F, nF, q, p, scale, 0, nF, nthreads, E_out);
+}
+
+/* Full energy and gradient G[V*3] = dE/dX (row-major like X). */
+int tpeo_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                  double scale, int nthreads, double* E_out, double* G_out) {
+    int rc = check_inputs(X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (!G_out) return EINVAL_;
+    face_t* G = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
+    if (!G) return EINVAL_;
+    rc = all_faces(X, F, nF, G);
+    if (rc) { free(G); return rc; }
+    int nt = nthreads_of(nthreads);
+    nsum* GV = (nsum*)calloc((size_t)nt * (size_t)V * 3, sizeof(nsum));
+    nsum* part = (nsum*)calloc((size_t)nt, sizeof(nsum));
+    if (!GV || !part) { free(G); free(GV); free(part); return EINVAL_; }
+    int err = OK;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        nsum* myG = GV + (size_t)tid * (size_t)V * 3;
+        nsum acc = {0.0, 0.0};
+        int lerr = OK;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < nF; ++s) {
+            for (int64_t t = 0; t < nF; ++t) {
+                if (share_vertex(F, s, t)) continue;
+                pairval pv;
+                if (pair_eval(&G[s], &G[t], q, p, 1, &pv)) { lerr = ENONFIN; continue; }
+                double aa = G[s].a * G[t].a;
+                nadd(&acc, aa * pv.k);
+                double dcS[3], dcT[3], dnS[3];
+                for (int i = 0; i < 3; ++i) {
+                    dcS[i] = scale * aa * pv.dkdd[i];
+                    dcT[i] = -dcS[i];
+                    dnS[i] = scale * aa * pv.dkdn[i];
+                }
+                face_vjp(X, F, s, &G[s], dcS, dnS, scale * G[t].a * pv.k, myG);
+                face_vjp(X, F, t, &G[t], dcT, NULL, scale * G[s].a * pv.k, myG);
+            }
+        }
+        part[tid] = acc;
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    nsum tot = {0.0, 0.0};
+    for (int i = 0; i < nt; ++i) { nadd(&tot, part[i].s); nadd(&tot, part[i].c); }
+    if (E_out) *E_out = err ? INFINITY : scale * nval(&tot);
+    for (int64_t i = 0; i < V * 3; ++i) {
+        nsum g = {0.0, 0.0};
+        for (int th = 0; th < nt; ++th) {
+            nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].s);
+            nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].c);
+        }
+        G_out[i] = nval(&g);
+    }
+    free(GV); free(part); free(G);
+    return err;
+}
+
+/* Exact gradient at selected vertices only: G_out[nv*3] = dE/dx_v for v = verts[i].
+ * Visits, for every face S incident to v, all pairs (S, T) and (T, S); only S depends on x_v
+ * (a pair in which both faces contain v is excluded by definition). */
+int tpeo_gradient_at(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                     double scale, const int32_t* verts, int64_t nv, int nthreads, double* G_out) {
+    int rc = check_inputs(X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (!verts || nv < 0 || !G_out) return EINVAL_;
+    for (int64_t i = 0; i < nv; ++i) if (verts[i] < 0 || verts[i] >= V) return EINVAL_;
+    face_t* G = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
+    if (!G) return EINVAL_;
+    rc = all_faces(X, F, nF, G);
+    if (rc) { free(G); return rc; }
+    int nt = nthreads_of(nthreads);
+    int err = OK;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+    for (int64_t iv = 0; iv < nv; ++iv) {
+        int32_t v = verts[iv];
+        nsum* GV = (nsum*)calloc((size_t)V * 3, sizeof(nsum)); /* scratch for face_vjp */
+        int lerr = OK;
+        for (int64_t s = 0; s < nF; ++s) {
+            if (F[3*s] != v && F[3*s+1] != v && F[3*s+2] != v) continue;
+            for (int64_t t = 0; t < nF; ++t) {
+                if (share_vertex(F, s, t)) continue;
+                pairval f1, f2;
+                if (pair_eval(&G[s], &G[t], q, p, 1, &f1) || pair_eval(&G[t], &G[s], q, p, 1, &f2)) {
+                    lerr = ENONFIN; continue;
+                }
+                double aa = G[s].a * G[t].a;
+                double dc[3], dn[3];
+                for (int i = 0; i < 3; ++i) {
+                    /* (S,T): S is x; (T,S): S is y, d = c_T - c_S so dd/dc_S = -I */
+                    dc[i] = scale * aa * (f1.dkdd[i] - f2.dkdd[i]);
+                    dn[i] = scale * aa * f1.dkdn[i];
+                }
+                double da = scale * G[t].a * (f1.k + f2.k);
+                face_vjp(X, F, s, &G[s], dc, dn, da, GV);
+            }
+        }
+        for (int d = 0; d < 3; ++d) G_out[3*iv + d] = nval(&GV[3 * (int64_t)v + d]);
+        free(GV);
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    free(G);
+    return err;
+}
