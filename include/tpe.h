@@ -1,0 +1,107 @@
+/*
+ * libtpe — discrete tangent-point energy and its vertex gradient on MI355X (gfx950).
+ *
+ * The energy follows the paper's definition of the tangent-point energy of a closed surface
+ * (Sec. 2 "Self-avoidance", eq. (TP)): with the tangent-point radius
+ * R(x,y) = |x-y|^2 / (2 |n(x).(x-y)|),  Phi = rho 2^-alpha / alpha  int_S int_S R^-alpha
+ *       = rho / alpha  int_S int_S |n(x).(x-y)|^alpha / |x-y|^(2 alpha).
+ * It is discretised on flat triangles with one quadrature point per face (the centroid), and
+ * pairs of faces that share a vertex index are left out (the continuous integrand has no
+ * exclusion; on a mesh those pairs sit on the diagonal of the double integral).  For faces
+ * S, T with area a, unit normal n and centroid c:
+ *
+ *     E(X) = scale * sum_S sum_{T: S,T share no vertex} a_S a_T |n_S.(c_S-c_T)|^q / |c_S-c_T|^p
+ *
+ * over ORDERED pairs (both orders, as the double integral counts them).  The paper's Phi is
+ * q = alpha, p = 2 alpha, scale = rho / alpha (it uses alpha = 6, rho = 1e-4).  The gradient is
+ * dE/dX, i.e. the deformation derivative of eq. (dTP) for the discrete surface, evaluated in the
+ * reordered form eq. (dTP_reordered) (Sec. 3.3): each face collects its own inner integrals
+ * and no pair writes into another face.  The self-avoidance force is -dE/dX.
+ *
+ * Conventions for every call below:
+ *   - Array arguments are DEVICE pointers owned by the caller (e.g. PyTorch tensors) unless the
+ *     argument says "host".  X is row-major float64 [V][3]; F is row-major int32 [nF][3], 0-based
+ *     vertex indices; face orientation does not matter for the exact path (|.| in the kernel).
+ *   - Work is enqueued on the context's stream and is asynchronous.  Outputs are valid once the
+ *     stream reaches them.  The library owns only opaque objects (context, scratch arena).
+ *   - Return value: TPE_OK or a negative tpe_status; tpe_last_error() gives a message.  Inputs
+ *     that can only be checked on the device (vertex indices in range, finite coordinates,
+ *     non-degenerate faces, finite result) are checked by the kernels, which never read out of
+ *     bounds; with the sync-checks option on (default) the call waits for the stream and
+ *     returns the corresponding status, with it off the status is collected by tpe_check().
+ *   - A context is not thread-safe; use one per host thread or serialise calls.
+ *   - Supported exponents: (q, p) = (6, 12) (the paper's alpha = 6).  Others return
+ *     TPE_ERR_UNSUPPORTED.
+ */
+#ifndef TPE_H
+#define TPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpe_ctx tpe_ctx;
+
+typedef enum {
+    TPE_OK = 0,
+    TPE_ERR_INVALID_ARG = -1, /* null pointer, bad size, vertex index out of range, bad exponents */
+    TPE_ERR_DEGENERATE = -2,  /* a face with area <= 1e-300 */
+    TPE_ERR_NONFINITE = -3,   /* non-finite coordinate, or coincident centroids of a non-adjacent
+                                 pair (the energy is infinite for such a non-embedded surface) */
+    TPE_ERR_OOM = -4,         /* device allocation of the scratch arena failed */
+    TPE_ERR_HIP = -5,         /* a HIP runtime call failed */
+    TPE_ERR_UNSUPPORTED = -6  /* exponents outside the supported set */
+} tpe_status;
+
+typedef enum {
+    TPE_OPT_SYNC_CHECKS = 1,  /* 1 (default): every call synchronises and reports device-side
+                                 errors; 0: calls stay asynchronous, tpe_check() reports */
+    TPE_OPT_TARGET_WAVES = 2  /* work-groups the exact pair kernel aims to launch (>= 1;
+                                 default 8192); rows are split over column ranges to reach it */
+} tpe_option;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tpe_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  *out receives the context; ownership passes to the caller (tpe_destroy). */
+int tpe_create(tpe_ctx** out, int device, void* hip_stream);
+
+/* Destroy a context and free its scratch arena.  Waits for the context's stream first. */
+int tpe_destroy(tpe_ctx* ctx);
+
+/* Rebind the stream work is enqueued on (e.g. PyTorch's current stream). */
+int tpe_set_stream(tpe_ctx* ctx, void* hip_stream);
+
+/* Set an option (tpe_option).  Returns TPE_ERR_INVALID_ARG for unknown options or values. */
+int tpe_set_option(tpe_ctx* ctx, int option, int64_t value);
+
+/* Message describing the last error on this context ("" if none).  Owned by the context. */
+const char* tpe_last_error(const tpe_ctx* ctx);
+
+/* Wait for the context's stream and report device-side errors raised since the last report
+ * (only needed with TPE_OPT_SYNC_CHECKS = 0). */
+int tpe_check(tpe_ctx* ctx);
+
+/* E_dev (device, one double) <- E(X).  Paper eq. (TP) as discretised above.
+ * X: device f64 [V][3]; F: device i32 [nF][3]; V, nF >= 1; q, p exponents; scale multiplies E. */
+int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
+               double q, double p, double scale, double* E_dev);
+
+/* G_dev (device f64 [V][3]) <- dE/dX and, if E_dev != NULL, E_dev <- E(X).
+ * Paper eqs. (dTP) / (dTP_reordered) for the discrete energy above.  Vertices that belong to no
+ * face get a zero gradient.  G_dev must not alias X. */
+int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                 double q, double p, double scale, double* E_dev, double* G_dev);
+
+/* *out_host (host int64) <- number of ordered face pairs (S, T) that share no vertex, i.e. the
+ * number of pair interactions one evaluation performs.  Synchronises the stream. */
+int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_t* out_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPE_H */

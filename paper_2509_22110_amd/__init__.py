@@ -1,0 +1,184 @@
+"""MI355X-native tangent-point energy: Python binding of libtpe (see include/tpe.h).
+
+This module only marshals arguments: every step of the computation runs in the HIP kernels of
+``libtpe.so``.  PyTorch supplies device memory and the stream.  The library must have been built
+(``python -m paper_2509_22110_amd.build``); if it is missing, importing the binding's functions
+raises — there is no CPU fallback.
+
+    E = energy(X, F)                   # X: cuda float64 [V,3], F: cuda int32 [nF,3]
+    E, G = gradient(X, F)              # G = dE/dX
+    E = TPEFunction.apply(X, F)        # autograd: backward runs the hand-written gradient
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+__all__ = ["TPEError", "lib", "energy", "gradient", "pair_count", "TPEFunction", "tpe_energy",
+           "context", "LIB_PATH", "STATUS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtpe.so")
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "degenerate face", -3: "non-finite",
+          -4: "out of memory", -5: "HIP error", -6: "unsupported"}
+
+OPT_SYNC_CHECKS = 1
+OPT_TARGET_WAVES = 2
+
+
+class TPEError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"libtpe error {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.RLock()
+
+
+def lib():
+    """Load libtpe.so (after torch, so both share one HIP runtime).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2509_22110_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "tpe_version": ([], I),
+            "tpe_create": ([ctypes.POINTER(P), I, P], I),
+            "tpe_destroy": ([P], I),
+            "tpe_set_stream": ([P, P], I),
+            "tpe_set_option": ([P, I, I64], I),
+            "tpe_last_error": ([P], ctypes.c_char_p),
+            "tpe_check": ([P], I),
+            "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
+            "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
+            "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+        return L
+
+
+class _Ctx:
+    def __init__(self, device: int):
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = lib().tpe_create(ctypes.byref(h), device, None)
+        if rc:
+            raise TPEError(rc, "tpe_create")
+        self.h = h
+
+    def check(self, rc: int):
+        if rc:
+            msg = lib().tpe_last_error(self.h)
+            raise TPEError(rc, msg.decode() if msg else "")
+
+    def bind(self, device):
+        s = torch.cuda.current_stream(device)
+        self.check(lib().tpe_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)))
+        return self
+
+    def set_option(self, opt: int, value: int):
+        self.check(lib().tpe_set_option(self.h, opt, int(value)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.tpe_destroy(self.h)
+        except Exception:
+            pass
+
+
+_ctxs: dict[int, _Ctx] = {}
+
+
+def context(device=None) -> _Ctx:
+    """Per-device library context, bound to torch's current stream on that device."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    lib()
+    with _lock:
+        c = _ctxs.get(idx)
+        if c is None:
+            c = _ctxs[idx] = _Ctx(idx)
+    return c.bind(torch.device("cuda", idx))
+
+
+def _check_mesh(X: torch.Tensor, F: torch.Tensor):
+    if not (isinstance(X, torch.Tensor) and isinstance(F, torch.Tensor)):
+        raise TypeError("X and F must be tensors")
+    if X.device.type != "cuda" or F.device != X.device:
+        raise ValueError("X and F must be on the same CUDA/HIP device")
+    if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != 3:
+        raise ValueError("X must be float64 [V, 3]")
+    if F.dtype != torch.int32 or F.dim() != 2 or F.shape[1] != 3:
+        raise ValueError("F must be int32 [nF, 3]")
+    return X.contiguous(), F.contiguous()
+
+
+def energy(X, F, q=6.0, p=12.0, scale=1.0, out=None) -> torch.Tensor:
+    """E(X) as a 0-dim float64 device tensor (exact all-pairs, paper eq. (TP) discretised)."""
+    X, F = _check_mesh(X, F)
+    E = out if out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_energy(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
+                             float(q), float(p), float(scale), E.data_ptr()))
+    return E
+
+
+def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
+    """(E, G) with G = dE/dX float64 [V, 3] (exact all-pairs)."""
+    X, F = _check_mesh(X, F)
+    G = out if out is not None else torch.empty_like(X)
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
+                               float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
+    return E, G
+
+
+def pair_count(F, V: int) -> int:
+    """Number of ordered face pairs sharing no vertex (pair interactions per evaluation)."""
+    if F.device.type != "cuda" or F.dtype != torch.int32:
+        raise ValueError("F must be a cuda int32 tensor")
+    F = F.contiguous()
+    c = context(F.device)
+    n = ctypes.c_int64(0)
+    c.check(lib().tpe_pair_count(c.h, F.data_ptr(), F.shape[0], int(V), ctypes.byref(n)))
+    return int(n.value)
+
+
+class TPEFunction(torch.autograd.Function):
+    """E = TPEFunction.apply(X, F, q, p, scale): forward runs the energy kernel; backward runs the
+    hand-written gradient (tpe_gradient) and scales it by the incoming gradient.  Only X and F are
+    saved; everything else is recomputed in backward."""
+
+    @staticmethod
+    def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0):
+        ctx.save_for_backward(X, F)
+        ctx.params = (q, p, scale)
+        return energy(X.detach(), F, q, p, scale)
+
+    @staticmethod
+    def backward(ctx, gE):
+        X, F = ctx.saved_tensors
+        q, p, scale = ctx.params
+        _, G = gradient(X.detach(), F, q, p, scale)
+        return G * gE, None, None, None, None
+
+
+def tpe_energy(X, F, q=6.0, p=12.0, scale=1.0):
+    """Differentiable energy (autograd through TPEFunction)."""
+    return TPEFunction.apply(X, F, q, p, scale)

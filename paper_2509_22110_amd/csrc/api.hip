@@ -1,0 +1,399 @@
+// C ABI of libtpe: context, scratch arena, validation and the exact energy / gradient pipeline.
+//
+// Pipeline of one tpe_gradient call (all on the context's stream, no host synchronisation
+// unless sync checks are on):
+//   face_bbox -> morton_keys -> radix sort (4 passes) -> tile_origins -> face_records
+//   -> vertex->corner CSR (count, scan, fill, per-vertex sort) -> tile-pair exclusion map
+//   -> pair_kernel (exact all-pairs row sums) -> finalize (FP64 adjoint + energy partials)
+//   -> energy_final -> vertex_gather.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/tpe.h"
+#include "common.hpp"
+
+namespace tpe {
+hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox, uint32_t* flags,
+                       hipStream_t st);
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
+                         uint32_t* keys, uint32_t* vals, hipStream_t st);
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
+                      uint32_t* hist, uint32_t* off, hipStream_t st);
+hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp, const uint32_t* perm,
+                          const uint32_t* bbox, double* org, ColRec* cols, int4* colv, double* c64, double* geo,
+                          uint32_t* flags, hipStream_t st);
+hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off, uint32_t* cursor,
+                            uint32_t* list, hipStream_t st);
+hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
+                        int touch_words, uint32_t* touch, hipStream_t st);
+hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                       const uint32_t* touch, int touch_words, int Fp, int ntiles, int tiles_per_split, int nsplits,
+                       float* part, hipStream_t st);
+hipError_t launch_finalize(bool grad, const float* part, int nsplits, int64_t Fp, int64_t nF, const double* geo,
+                           const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
+                           double* corner, double* epart, uint32_t* flags, double* E, hipStream_t st);
+hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
+                         hipStream_t st);
+int finalize_blocks(int64_t nF);
+
+// Per sorted face: number of faces (itself included) that share at least one vertex with it.
+__global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
+                               const uint32_t* __restrict__ list, unsigned long long* __restrict__ total) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    unsigned long long c = 0;
+    if (i < nF) {
+        const int4 v = colv[i];
+        const int vv[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3; ++k) {
+            if (vv[k] < 0 || vv[k] >= V) continue;
+            for (uint32_t e = off[vv[k]]; e < off[vv[k] + 1]; ++e) {
+                const uint32_t j = list[e] / 3;
+                // count j once: only at the first of i's vertices whose list contains j
+                bool seen = false;
+                for (int k2 = 0; k2 < k && !seen; ++k2) {
+                    if (vv[k2] < 0 || vv[k2] >= V) continue;
+                    for (uint32_t e2 = off[vv[k2]]; e2 < off[vv[k2] + 1]; ++e2)
+                        if (list[e2] / 3 == j) { seen = true; break; }
+                }
+                if (!seen) ++c;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, c);
+}
+
+// Vertex ids of each face in input order (used where no sorting is needed).
+__global__ void face_ids(const int32_t* __restrict__ F, int64_t nF, int64_t V, int4* __restrict__ colv,
+                         uint32_t* __restrict__ flags) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    const int a = F[3 * i], b = F[3 * i + 1], c = F[3 * i + 2];
+    const bool ok = a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V;
+    if (!ok) atomicOr(flags, (uint32_t)FLAG_BAD_INDEX);
+    colv[i] = ok ? make_int4(a, b, c, 0) : make_int4(-3, -3, -3, 0);
+}
+}  // namespace tpe
+
+using namespace tpe;
+
+struct tpe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool sync_checks = true;
+    int64_t target_waves = 8192;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    uint32_t* dflags = nullptr;   // device error word
+    uint32_t* hflags = nullptr;   // pinned host mirror
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int fail(tpe_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(tpe_ctx* c, hipError_t e, const char* where) {
+    return fail(c, TPE_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                              \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);    \
+    } while (0)
+
+// Bump allocator over the arena; 256-byte aligned slices.
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(char* b) : base(b) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Plan {
+    int64_t nF, V, Fp;
+    int ntiles, nrb, touch_words, nsplits, tiles_per_split, sort_blocks, fin_blocks;
+    // buffers
+    uint32_t *keys, *vals, *ktmp, *vtmp, *hist, *hoff, *bbox;
+    uint32_t *zero_begin, *cnt, *cursor, *touch, *zero_end;
+    uint32_t *voff, *list;
+    double *org, *c64, *geo, *corner, *epart;
+    ColRec* cols;
+    int4* colv;
+    float* part;
+    unsigned long long* counter;
+    size_t bytes;
+};
+
+void layout(Plan& P, char* base, bool grad) {
+    Carve c(base);
+    const int64_t nF = P.nF, V = P.V, Fp = P.Fp;
+    P.keys = c.take<uint32_t>(nF);
+    P.vals = c.take<uint32_t>(nF);
+    P.ktmp = c.take<uint32_t>(nF);
+    P.vtmp = c.take<uint32_t>(nF);
+    P.hist = c.take<uint32_t>((size_t)256 * P.sort_blocks + 1);
+    P.hoff = c.take<uint32_t>((size_t)256 * P.sort_blocks + 1);
+    P.bbox = c.take<uint32_t>(8);
+    P.counter = c.take<unsigned long long>(1);
+    // one contiguous zero-initialised region
+    P.zero_begin = c.take<uint32_t>(0);
+    P.cnt = c.take<uint32_t>(V);
+    P.cursor = c.take<uint32_t>(V);
+    P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
+    P.zero_end = c.take<uint32_t>(0);
+    P.voff = c.take<uint32_t>(V + 1);
+    P.list = c.take<uint32_t>(3 * nF);
+    P.org = c.take<double>(3 * (size_t)P.ntiles);
+    P.cols = c.take<ColRec>(Fp);
+    P.colv = c.take<int4>(Fp);
+    P.c64 = c.take<double>(3 * Fp);
+    P.geo = c.take<double>(5 * Fp);
+    P.part = c.take<float>((size_t)P.nsplits * 2 * (grad ? NACC : 1) * Fp);
+    P.corner = c.take<double>(grad ? 9 * nF : 1);
+    P.epart = c.take<double>(P.fin_blocks);
+    P.bytes = c.off + 256;
+}
+
+void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad) {
+    P.nF = nF;
+    P.V = V;
+    P.Fp = round_up(nF, std::max(ROWB, CTILE));
+    P.ntiles = (int)(P.Fp / CTILE);
+    P.nrb = (int)(P.Fp / ROWB);
+    P.touch_words = (P.ntiles + 31) / 32;
+    int64_t want = std::max<int64_t>(1, ceil_div(ctx->target_waves, P.nrb));
+    want = std::min<int64_t>(want, P.ntiles);
+    P.tiles_per_split = (int)ceil_div(P.ntiles, want);
+    P.nsplits = (int)ceil_div(P.ntiles, P.tiles_per_split);
+    P.sort_blocks = (int)ceil_div(nF, 4096);
+    P.fin_blocks = finalize_blocks(nF);
+    layout(P, nullptr, grad);
+}
+
+int ensure_arena(tpe_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->arena_bytes) return TPE_OK;
+    if (ctx->arena) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+        (void)hipFree(ctx->arena);
+        ctx->arena = nullptr;
+        ctx->arena_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&ctx->arena, want) != hipSuccess) {
+        ctx->arena = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, TPE_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    ctx->arena_bytes = want;
+    return TPE_OK;
+}
+
+int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!X || !F) return fail(ctx, TPE_ERR_INVALID_ARG, "null X or F");
+    if (V < 1 || nF < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "V and nF must be >= 1");
+    if (nF > (int64_t)1 << 28 || V > (int64_t)1 << 30)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^28, V <= 2^30)");
+    if (!(q >= 2.0) || !(p > q) || !std::isfinite(q) || !std::isfinite(p))
+        return fail(ctx, TPE_ERR_INVALID_ARG, "exponents must satisfy 2 <= q < p");
+    if (q != 6.0 || p != 12.0) return fail(ctx, TPE_ERR_UNSUPPORTED, "only (q, p) = (6, 12) is implemented");
+    return TPE_OK;
+}
+
+int report_flags(tpe_ctx* ctx) {
+    HIPCHK(hipMemcpyAsync(ctx->hflags, ctx->dflags, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const uint32_t f = *ctx->hflags;
+    if (f & FLAG_BAD_INDEX) return fail(ctx, TPE_ERR_INVALID_ARG, "face vertex index out of range");
+    if (f & FLAG_NONFINITE)
+        return fail(ctx, TPE_ERR_NONFINITE, "non-finite input or result (coincident non-adjacent centroids?)");
+    if (f & FLAG_DEGENERATE) return fail(ctx, TPE_ERR_DEGENERATE, "degenerate face (area <= 1e-300)");
+    return TPE_OK;
+}
+
+// Shared front half: sort faces, build records, adjacency and exclusion map.
+int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_fill(P.zero_begin, 0u, P.zero_end - P.zero_begin, st));
+    HIPCHK(launch_fill(P.bbox, 0xffffffffu, 3, st));
+    HIPCHK(launch_fill(P.bbox + 3, 0u, 3, st));
+    HIPCHK(launch_bbox(X, P.V, F, P.nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_morton(X, P.V, F, P.nF, P.bbox, P.keys, P.vals, st));
+    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nF, 30, P.hist, P.hoff, st));
+    HIPCHK(launch_records(X, P.V, F, P.nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, ctx->dflags, st));
+    HIPCHK(launch_adjacency(P.colv, P.nF, P.V, P.cnt, P.voff, P.cursor, P.list, st));
+    HIPCHK(launch_touch(P.colv, P.nF, P.V, P.voff, P.list, P.touch_words, P.touch, st));
+    return TPE_OK;
+}
+
+int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+              double scale, double* E, double* G) {
+    int rc = check_common(ctx, X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
+    const bool grad = G != nullptr;
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    plan(P, ctx, nF, V, grad);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, grad);
+    hipStream_t st = ctx->stream;
+    if (ctx->sync_checks) HIPCHK(launch_fill(ctx->dflags, 0u, 1, st));
+    if ((rc = prepare(ctx, P, X, F))) return rc;
+    HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, (int)P.Fp, P.ntiles,
+                       P.tiles_per_split, P.nsplits, P.part, st));
+    HIPCHK(launch_finalize(grad, P.part, P.nsplits, P.Fp, nF, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
+                           ctx->dflags, E, st));
+    if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpe_version(void) { return 100; }
+
+int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
+    if (!out) return TPE_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TPE_ERR_INVALID_ARG;
+    tpe_ctx* ctx = new tpe_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    DeviceGuard dg(device);
+    if (hipMalloc(&ctx->dflags, 256) != hipSuccess) {
+        delete ctx;
+        return TPE_ERR_OOM;
+    }
+    if (hipHostMalloc(&ctx->hflags, sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(ctx->dflags);
+        delete ctx;
+        return TPE_ERR_OOM;
+    }
+    *ctx->hflags = 0;
+    if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        (void)hipFree(ctx->dflags);
+        (void)hipHostFree(ctx->hflags);
+        delete ctx;
+        return TPE_ERR_HIP;
+    }
+    *out = ctx;
+    return TPE_OK;
+}
+
+int tpe_destroy(tpe_ctx* ctx) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->dflags) (void)hipFree(ctx->dflags);
+    if (ctx->hflags) (void)hipHostFree(ctx->hflags);
+    delete ctx;
+    return TPE_OK;
+}
+
+int tpe_set_stream(tpe_ctx* ctx, void* hip_stream) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return TPE_OK;
+}
+
+int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    switch (option) {
+        case TPE_OPT_SYNC_CHECKS:
+            if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "sync checks: 0 or 1");
+            ctx->sync_checks = value != 0;
+            return TPE_OK;
+        case TPE_OPT_TARGET_WAVES:
+            if (value < 1 || value > (int64_t)1 << 24) return fail(ctx, TPE_ERR_INVALID_ARG, "target waves");
+            ctx->target_waves = value;
+            return TPE_OK;
+        default:
+            return fail(ctx, TPE_ERR_INVALID_ARG, "unknown option");
+    }
+}
+
+const char* tpe_last_error(const tpe_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int tpe_check(tpe_ctx* ctx) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = report_flags(ctx);
+    if (launch_fill(ctx->dflags, 0u, 1, ctx->stream) != hipSuccess) return hip_fail(ctx, hipGetLastError(), "fill");
+    return rc;
+}
+
+int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+               double scale, double* E_dev) {
+    if (ctx && !E_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null E_dev");
+    return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, nullptr);
+}
+
+int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                 double scale, double* E_dev, double* G_dev) {
+    if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
+    if (ctx && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
+}
+
+int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_t* out_host) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!F || !out_host || nF < 1 || V < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    plan(P, ctx, nF, V, false);
+    int rc = ensure_arena(ctx, P.bytes);
+    if (rc) return rc;
+    layout(P, ctx->arena, false);
+    hipStream_t st = ctx->stream;
+    // sorted order is irrelevant for counting: use the identity permutation
+    HIPCHK(launch_fill(P.zero_begin, 0u, P.zero_end - P.zero_begin, st));
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(P.counter), 0u, 2, st));
+    HIPCHK(launch_fill(ctx->dflags, 0u, 1, st));
+    hipLaunchKernelGGL(face_ids, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, F, nF, V, P.colv, ctx->dflags);
+    HIPCHK(hipGetLastError());
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, st));
+    hipLaunchKernelGGL(excluded_count, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, P.colv, nF, V, P.voff, P.list,
+                       P.counter);
+    HIPCHK(hipGetLastError());
+    unsigned long long h = 0;
+    HIPCHK(hipMemcpyAsync(&h, P.counter, sizeof(h), hipMemcpyDeviceToHost, st));
+    if ((rc = report_flags(ctx))) return rc;
+    *out_host = nF * nF - (int64_t)h;
+    return TPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Internal helpers shared by the HIP sources of libtpe (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpe {
+
+// Device-side error flags, OR-ed into one word by the kernels and read back by the host.
+enum : uint32_t {
+    FLAG_BAD_INDEX = 1u,   // a face refers to a vertex outside [0, V)
+    FLAG_DEGENERATE = 2u,  // a face with area <= 1e-300
+    FLAG_NONFINITE = 4u,   // non-finite coordinate, or a non-finite accumulated result
+};
+
+// Geometry of the exact all-pairs kernel.
+constexpr int WAVE = 64;
+constexpr int RPL = 2;                  // rows (target faces) per lane
+constexpr int ROWB = WAVE * RPL;        // rows per wave (one wave per work-group)
+constexpr int CTILE = 256;              // columns per tile (one FP64 origin per tile)
+constexpr int CHUNK = 64;               // columns summed in plain FP32 before a compensated fold
+constexpr int NACC = 11;                // accumulators per row face (see pair.hip)
+
+// Column record read with scalar loads: centroid relative to its tile origin, area, normal.
+struct __align__(32) ColRec {
+    float cx, cy, cz, a;
+    float nx, ny, nz, pad;
+};
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+__device__ __forceinline__ float ordered_to_float(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Exponent k of the power of two s = 2^k with (largest centroid-bounding-box extent) * s in
+// [0.5, 1); 0 if the box is empty or degenerate.  bbox holds order-preserving encodings of
+// (min xyz, max xyz).
+__device__ __forceinline__ int norm_exp(const uint32_t* bbox) {
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = (double)ordered_to_float(bbox[3 + d]) - (double)ordered_to_float(bbox[d]);
+        if (e > ext && isfinite(e)) ext = e;
+    }
+    if (!(ext > 0.0) || !isfinite(ext)) return 0;
+    int ex;
+    (void)frexp(ext, &ex);
+    return -ex;
+}
+__device__ __forceinline__ double norm_scale(const uint32_t* bbox) { return ldexp(1.0, norm_exp(bbox)); }
+
+// s^m for s = 2^k and an integer-valued m, exactly.
+__device__ __forceinline__ double pow2i(int k, double m) { return ldexp(1.0, (int)llrint(k * m)); }
+
+// Far-away padding for rows/columns past the last face (area 0, so they contribute exactly 0).
+constexpr float PAD_COORD = 1.0e4f;
+
+}  // namespace tpe

@@ -1,0 +1,148 @@
+// Finalize: merge the pair kernel's column splits in FP64, turn the per-face row sums into the
+// gradient contributions of the face's three corners, and reduce the energy; then the
+// scatter-free vertex gather.
+//
+// With the row sums of pair.hip (K, S0, Sd, Sdd, Sn) for face S and the kernel k = t^q with
+// p = 2q, the partial derivatives of E with respect to the face's own geometry are
+//     dE/da_S = K,   dE/dn_S = q a_S Sd,   dE/dc_S = a_S (q (n_S S0 + Sn) - p Sdd),
+// which are the paper's inner integrals f_K, f_nu and f (Sec. 3.3, eq. (dTP_reordered)) at the
+// face's quadrature point.  They reach the vertices through w = (x_j - x_i) x (x_k - x_i):
+//     g_w = (dE/da) n / 2 + (I - n n^T) (dE/dn) / |w|,
+//     dE/dx_i = (dE/dc)/3 + (x_j - x_k) x g_w      (and cyclically for j, k).
+// The energy is E = (1/2) sum_S a_S K_S (each ordered pair is counted once in the forward and
+// once in the reverse part of K).  Everything here is FP64.
+#include "common.hpp"
+
+namespace tpe {
+
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// One thread per sorted face; block of 256 threads writes one FP64 energy partial.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__ part, int nsplits, int64_t Fp,
+                                                       int64_t nF, const double* __restrict__ geo,
+                                                       const int4* __restrict__ colv,
+                                                       const double* __restrict__ X,
+                                                       const uint32_t* __restrict__ bbox, double q, double p,
+                                                       double scale, double* __restrict__ corner,
+                                                       double* __restrict__ epart, uint32_t* __restrict__ flags) {
+    constexpr int NA = GRAD ? NACC : 1;
+    __shared__ double ws[4];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double e = 0.0;
+    // the row sums were taken on positions multiplied by s: G(X) = s^(p-q-3) G(sX), exactly
+    const int kexp = norm_exp(bbox);
+    const double s = ldexp(1.0, kexp);
+    const double gs = scale * pow2i(kexp, p - q - 3.0);
+    if (i < nF) {
+        double acc[NA];
+        for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+        for (int sp = 0; sp < nsplits; ++sp) {
+            const float* ps = part + (size_t)sp * 2 * NA * Fp;
+            for (int k = 0; k < NA; ++k)
+                acc[k] += (double)ps[(size_t)k * Fp + i] + (double)ps[(size_t)(NA + k) * Fp + i];
+        }
+        const double a = geo[5 * i + 0], wn = geo[5 * i + 1];
+        const double n[3] = {geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]};
+        bool finite = true;
+        for (int k = 0; k < NA; ++k) finite &= isfinite(acc[k]);
+        if (!GRAD) {
+            e = a * acc[0];
+        } else {
+            e = 0.5 * a * acc[0];
+            const double Ga = gs * acc[0];
+            double Gn[3], Gc[3];
+            for (int d = 0; d < 3; ++d) {
+                Gn[d] = gs * q * a * acc[2 + d];
+                Gc[d] = gs * a * (q * (n[d] * acc[1] + acc[8 + d]) - p * acc[5 + d]);
+            }
+            const double nGn = n[0] * Gn[0] + n[1] * Gn[1] + n[2] * Gn[2];
+            double gw[3];
+            for (int d = 0; d < 3; ++d) gw[d] = 0.5 * Ga * n[d] + (Gn[d] - nGn * n[d]) / wn;
+            const int4 v = colv[i];
+            const int vv[3] = {v.x, v.y, v.z};
+            double x[3][3];
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) x[c][d] = vv[c] >= 0 ? s * X[3 * (int64_t)vv[c] + d] : 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double* xj = x[(c + 1) % 3];
+                const double* xk = x[(c + 2) % 3];
+                const double ed[3] = {xj[0] - xk[0], xj[1] - xk[1], xj[2] - xk[2]};
+                const double cr[3] = {ed[1] * gw[2] - ed[2] * gw[1], ed[2] * gw[0] - ed[0] * gw[2],
+                                      ed[0] * gw[1] - ed[1] * gw[0]};
+                for (int d = 0; d < 3; ++d) {
+                    const double g = Gc[d] / 3.0 + cr[d];
+                    finite &= isfinite(g);
+                    corner[9 * i + 3 * c + d] = g;
+                }
+            }
+        }
+        if (!finite) atomicOr(flags, (uint32_t)FLAG_NONFINITE);
+    }
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+}
+
+// Deterministic final energy sum (one work-group, fixed order).
+__global__ __launch_bounds__(256) void energy_final(const double* __restrict__ epart, int nb,
+                                                    const uint32_t* __restrict__ bbox, double q, double p,
+                                                    double scale, double* __restrict__ E) {
+    __shared__ double ws[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += epart[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // E(X) = s^(p-q-4) E(sX), exactly for a power of two s
+        double t = scale * pow2i(norm_exp(bbox), p - q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+        E[0] = t;
+    }
+}
+
+// G[v] = sum over the (sorted face, corner) slots incident to v, ascending slot order.
+__global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list, int64_t V,
+                              const double* __restrict__ corner, double* __restrict__ G) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    const uint32_t b = off[v], e = off[v + 1];
+    for (uint32_t k = b; k < e; ++k) {
+        const double* c = corner + 3 * (size_t)list[k];
+        g0 += c[0];
+        g1 += c[1];
+        g2 += c[2];
+    }
+    G[3 * v + 0] = g0;
+    G[3 * v + 1] = g1;
+    G[3 * v + 2] = g2;
+}
+
+int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
+
+hipError_t launch_finalize(bool grad, const float* part, int nsplits, int64_t Fp, int64_t nF, const double* geo,
+                           const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
+                           double* corner, double* epart, uint32_t* flags, double* E, hipStream_t st) {
+    const int nb = finalize_blocks(nF);
+    if (grad)
+        hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, nsplits, Fp, nF, geo, colv, X,
+                           bbox, q, p, scale, corner, epart, flags);
+    else
+        hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, nsplits, Fp, nF, geo, colv,
+                           X, bbox, q, p, scale, corner, epart, flags);
+    if (E) hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, epart, nb, bbox, q, p, scale, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(vertex_gather, dim3((int)((V + 255) / 256)), dim3(256), 0, st, off, list, V, corner, G);
+    return hipGetLastError();
+}
+
+}  // namespace tpe

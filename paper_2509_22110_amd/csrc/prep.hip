@@ -1,0 +1,316 @@
+// Geometry preparation, spatial (Morton) ordering, vertex->corner adjacency and the tile-pair
+// exclusion map.
+//
+// Per face T = (i, j, k) (paper Sec. 3.3: positions, area elements and normals are cached per
+// quadrature point, contiguously, and iterated in memory order):
+//     w = (x_j - x_i) x (x_k - x_i),  a = |w|/2,  n = w/|w|,  c = (x_i + x_j + x_k)/3   (FP64)
+// Faces are reordered along a 30-bit Morton curve of their centroids so that a tile of 256
+// consecutive faces is spatially compact: that keeps tile-relative FP32 coordinates small and
+// confines faces sharing a vertex (the excluded pairs) to few tile pairs.
+#include "common.hpp"
+
+namespace tpe {
+
+__device__ __forceinline__ uint32_t float_to_ordered(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids; must start at
+// (0xffffffff x3, 0 x3).  Also validates indices / coordinates and flags errors.
+__global__ void face_bbox(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
+                          int64_t nF, uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags) {
+    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t fl = 0;
+    if (f < nF) {
+        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+        double c[3] = {0, 0, 0};
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+            if (v[k] < 0 || v[k] >= V) { ok = false; fl |= FLAG_BAD_INDEX; }
+        }
+        if (ok) {
+            for (int k = 0; k < 3; ++k)
+                for (int d = 0; d < 3; ++d) {
+                    double x = X[3 * (int64_t)v[k] + d];
+                    if (!isfinite(x)) fl |= FLAG_NONFINITE;
+                    c[d] += x;
+                }
+            for (int d = 0; d < 3; ++d) {
+                float cf = (float)(c[d] / 3.0);
+                if (isfinite(cf)) { mn[d] = cf; mx[d] = cf; }
+            }
+        }
+    }
+    // wave reduction then one atomic per wave
+    for (int d = 0; d < 3; ++d) {
+        float a = mn[d], b = mx[d];
+        for (int off = 32; off > 0; off >>= 1) {
+            a = fminf(a, __shfl_xor(a, off));
+            b = fmaxf(b, __shfl_xor(b, off));
+        }
+        mn[d] = a; mx[d] = b;
+    }
+    for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
+    if ((threadIdx.x & 63) == 0) {
+        for (int d = 0; d < 3; ++d) {
+            if (mn[d] <= mx[d]) {
+                atomicMin(&bbox[d], float_to_ordered(mn[d]));
+                atomicMax(&bbox[3 + d], float_to_ordered(mx[d]));
+            }
+        }
+        if (fl) atomicOr(flags, fl);
+    }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// 30-bit Morton key of each face centroid inside the centroid bounding box; value = face id.
+__global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
+                            int64_t nF, const uint32_t* __restrict__ bbox, uint32_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals) {
+    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    float lo[3], ext[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = ordered_to_float(bbox[d]);
+        float hi = ordered_to_float(bbox[3 + d]);
+        ext[d] = hi - lo[d];
+        if (!(ext[d] > 0.f) || !isfinite(ext[d])) ext[d] = 1.f;
+        if (!isfinite(lo[d])) lo[d] = 0.f;
+    }
+    uint32_t q[3] = {0, 0, 0};
+    int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+    bool ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
+    if (ok) {
+        for (int d = 0; d < 3; ++d) {
+            double c = (X[3 * (int64_t)v[0] + d] + X[3 * (int64_t)v[1] + d] + X[3 * (int64_t)v[2] + d]) / 3.0;
+            float s = ((float)c - lo[d]) / ext[d];
+            s = fminf(fmaxf(s * 1024.f, 0.f), 1023.f);
+            q[d] = isfinite(s) ? (uint32_t)s : 0u;
+        }
+    }
+    keys[f] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    vals[f] = (uint32_t)f;
+}
+
+// Sorted face records.  For sorted position i < nF: face f = perm[i].  Positions in [nF, Fp) are
+// padding: far away, zero area, vertex ids -1 (never equal to a real id; padded rows are never
+// read back, padded columns contribute exactly zero).  All positions are multiplied by the exact
+// power of two s = norm_scale(bbox) that brings the mesh extent into [0.5, 1), so the FP32 pair
+// arithmetic stays in range at any physical scale; the finalize pass undoes s exactly.
+//   cols[i]  : centroid relative to the FP64 origin of tile i/CTILE, area, unit normal (FP32)
+//   colv[i]  : vertex ids (for the exclusion test)
+//   c64[i]   : centroid (FP64)
+//   org[t]   : FP64 origin of tile t = centroid of its first face
+//   geo[i]   : FP64 {a, |w|, n.x, n.y, n.z} for the finalize pass
+__global__ void tile_origins(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
+                             int64_t nF, const uint32_t* __restrict__ perm, int ntiles,
+                             const uint32_t* __restrict__ bbox, double* __restrict__ org) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const double s = norm_scale(bbox);
+    int64_t i = (int64_t)t * CTILE;
+    double o[3] = {0, 0, 0};
+    if (i < nF) {
+        int64_t f = perm[i];
+        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+        if (v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V)
+            for (int d = 0; d < 3; ++d)
+                o[d] = s * (X[3 * (int64_t)v[0] + d] + X[3 * (int64_t)v[1] + d] + X[3 * (int64_t)v[2] + d]) / 3.0;
+    }
+    for (int d = 0; d < 3; ++d) org[3 * t + d] = isfinite(o[d]) ? o[d] : 0.0;
+}
+
+__global__ void face_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
+                             int64_t nF, int64_t Fp, const uint32_t* __restrict__ perm,
+                             const uint32_t* __restrict__ bbox, const double* __restrict__ org,
+                             ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
+                             double* __restrict__ geo, uint32_t* __restrict__ flags) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= Fp) return;
+    const double s = norm_scale(bbox);
+    const int t = (int)(i / CTILE);
+    ColRec r;
+    if (i < nF) {
+        int64_t f = perm[i];
+        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+        bool ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
+        double xi[3] = {0, 0, 0}, xj[3] = {1, 0, 0}, xk[3] = {0, 1, 0};
+        if (ok)
+            for (int d = 0; d < 3; ++d) {
+                xi[d] = s * X[3 * (int64_t)v[0] + d];
+                xj[d] = s * X[3 * (int64_t)v[1] + d];
+                xk[d] = s * X[3 * (int64_t)v[2] + d];
+            }
+        bool fin = true;
+        for (int d = 0; d < 3; ++d) fin &= isfinite(xi[d]) && isfinite(xj[d]) && isfinite(xk[d]);
+        if (!fin) {  // reported as non-finite input, not as a degenerate face
+            atomicOr(flags, (uint32_t)FLAG_NONFINITE);
+            for (int d = 0; d < 3; ++d) { xi[d] = 0.0; xj[d] = d == 0 ? 1.0 : 0.0; xk[d] = d == 1 ? 1.0 : 0.0; }
+        }
+        double e1[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        double e2[3] = {xk[0] - xi[0], xk[1] - xi[1], xk[2] - xi[2]};
+        double w[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        double a = 0.5 * wn;
+        uint32_t fl = 0;
+        if (!(a > 1e-300 * s * s)) { fl |= FLAG_DEGENERATE; wn = 1.0; a = 0.0; }
+        double n[3] = {w[0] / wn, w[1] / wn, w[2] / wn};
+        double c[3];
+        for (int d = 0; d < 3; ++d) c[d] = (xi[d] + xj[d] + xk[d]) / 3.0;
+        if (!isfinite(c[0] + c[1] + c[2] + n[0] + n[1] + n[2])) {
+            fl |= FLAG_NONFINITE;
+            c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
+        }
+        if (fl) atomicOr(flags, fl);
+        r.cx = (float)(c[0] - org[3 * t + 0]);
+        r.cy = (float)(c[1] - org[3 * t + 1]);
+        r.cz = (float)(c[2] - org[3 * t + 2]);
+        r.a = (float)a;
+        r.nx = (float)n[0]; r.ny = (float)n[1]; r.nz = (float)n[2];
+        r.pad = 0.f;
+        colv[i] = ok ? make_int4(v[0], v[1], v[2], 0) : make_int4(-3, -3, -3, 0);
+        c64[3 * i + 0] = c[0]; c64[3 * i + 1] = c[1]; c64[3 * i + 2] = c[2];
+        geo[5 * i + 0] = a; geo[5 * i + 1] = wn;
+        geo[5 * i + 2] = n[0]; geo[5 * i + 3] = n[1]; geo[5 * i + 4] = n[2];
+    } else {
+        // padding: far from everything, zero area; row padding ids differ from column ids
+        r.cx = PAD_COORD; r.cy = PAD_COORD; r.cz = PAD_COORD; r.a = 0.f;
+        r.nx = 0.f; r.ny = 0.f; r.nz = 0.f; r.pad = 0.f;
+        colv[i] = make_int4(-1, -1, -1, 0);
+        c64[3 * i + 0] = org[3 * t + 0] + PAD_COORD;
+        c64[3 * i + 1] = org[3 * t + 1] + PAD_COORD;
+        c64[3 * i + 2] = org[3 * t + 2] + PAD_COORD;
+        for (int k = 0; k < 5; ++k) geo[5 * i + k] = 0.0;
+    }
+    cols[i] = r;
+}
+
+// ---- vertex -> (sorted face, corner) adjacency, CSR, deterministic order ----------------------
+
+__global__ void corner_count(const int4* __restrict__ colv, int64_t nF, int64_t V,
+                             uint32_t* __restrict__ cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    int4 v = colv[i];
+    int vv[3] = {v.x, v.y, v.z};
+    for (int k = 0; k < 3; ++k)
+        if (vv[k] >= 0 && vv[k] < V) atomicAdd(&cnt[vv[k]], 1u);
+}
+
+__global__ void corner_fill(const int4* __restrict__ colv, int64_t nF, int64_t V,
+                            const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                            uint32_t* __restrict__ list) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    int4 v = colv[i];
+    int vv[3] = {v.x, v.y, v.z};
+    for (int k = 0; k < 3; ++k)
+        if (vv[k] >= 0 && vv[k] < V) {
+            uint32_t pos = atomicAdd(&cursor[vv[k]], 1u);
+            list[off[vv[k]] + pos] = (uint32_t)(3 * i + k);
+        }
+}
+
+// Sort each vertex's list ascending (insertion sort): makes the gather order deterministic.
+__global__ void corner_sort(const uint32_t* __restrict__ off, int64_t V, uint32_t* __restrict__ list) {
+    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    uint32_t b = off[v], e = off[v + 1];
+    for (uint32_t i = b + 1; i < e; ++i) {
+        uint32_t x = list[i];
+        uint32_t j = i;
+        while (j > b && list[j - 1] > x) { list[j] = list[j - 1]; --j; }
+        list[j] = x;
+    }
+}
+
+// Tile-pair exclusion map: bit (rb, t) set iff some row of row block rb shares a vertex with some
+// column of tile t.  Rows/columns are sorted positions.
+__global__ void touch_map(const int4* __restrict__ colv, int64_t nF, int64_t V,
+                          const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
+                          int touch_words, uint32_t* __restrict__ touch) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    int4 v = colv[i];
+    int vv[3] = {v.x, v.y, v.z};
+    const int64_t rb = i / ROWB;
+    for (int k = 0; k < 3; ++k) {
+        if (vv[k] < 0 || vv[k] >= V) continue;
+        for (uint32_t e = off[vv[k]]; e < off[vv[k] + 1]; ++e) {
+            uint32_t j = list[e] / 3;
+            uint32_t t = j / CTILE;
+            atomicOr(&touch[rb * touch_words + (t >> 5)], 1u << (t & 31));
+        }
+    }
+}
+
+// ---- host launchers ----------------------------------------------------------------------------
+
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, hipStream_t st);
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int g = (int)std::min<int64_t>(nblk(n, 256), 4096);
+    hipLaunchKernelGGL(fill_u32, dim3(g), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox,
+                       uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(face_bbox, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
+                         uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp,
+                          const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
+                          double* c64, double* geo, uint32_t* flags, hipStream_t st) {
+    int ntiles = (int)(Fp / CTILE);
+    hipLaunchKernelGGL(tile_origins, dim3(nblk(ntiles, 256)), dim3(256), 0, st, X, V, F, nF, perm, ntiles, bbox, org);
+    hipLaunchKernelGGL(face_records, dim3(nblk(Fp, 256)), dim3(256), 0, st, X, V, F, nF, Fp, perm, bbox, org, cols,
+                       colv, c64, geo, flags);
+    return hipGetLastError();
+}
+
+// cnt and cursor must be zeroed by the caller (V entries each).
+hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off,
+                            uint32_t* cursor, uint32_t* list, hipStream_t st) {
+    hipLaunchKernelGGL(corner_count, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, cnt);
+    hipError_t e = launch_exclusive_scan(cnt, V, off, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(corner_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, cursor, list);
+    hipLaunchKernelGGL(corner_sort, dim3(nblk(V, 256)), dim3(256), 0, st, off, V, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
+                        int touch_words, uint32_t* touch, hipStream_t st) {
+    hipLaunchKernelGGL(touch_map, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, list, touch_words,
+                       touch);
+    return hipGetLastError();
+}
+
+}  // namespace tpe

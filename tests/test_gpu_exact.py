@@ -1,0 +1,230 @@
+"""Parity of the exact HIP path (tpe_energy / tpe_gradient through the C ABI) with the FP64 oracle.
+
+Tolerances: energy relative error <= 1e-6, gradient max-norm relative error <= 1e-5 (FP32 pair
+arithmetic with compensated sums, FP64 finalize and gather).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import HAVE_GPU, log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+E_TOL = 1e-6
+G_TOL = 1e-5
+
+
+def _patch(X, F, center, nfaces):
+    c = X[F].mean(1)
+    sel = np.sort(np.argsort(np.linalg.norm(c - center, axis=1), kind="stable")[:nfaces])
+    Fs = F[sel]
+    used, inv = np.unique(Fs, return_inverse=True)
+    return X[used].copy(), inv.reshape(Fs.shape).astype(np.int32)
+
+
+def small_meshes():
+    X, F = M.icosphere(0)
+    yield "L0-icosahedron", M.radial_jitter(X, 0.02, 1), F
+    X, F = M.icosphere(1)
+    yield "L1-jitter", M.radial_jitter(X, 0.01, 0), F
+    X, F = M.icosphere(2)
+    Xb, _, _ = M.bump(X, 0, 0.3, 0.15)
+    yield "L2-bump", Xb, F
+    X, F = M.icosphere(3)
+    Xb, _, _ = M.bump(X, 0, 0.3, 0.05)
+    yield "L3-gap-patch", *_patch(Xb, F, Xb[3] * 0.97, 333)
+    X, F = M.icosphere(4)
+    yield "L4-sh", M.sh_deform(X, 2, 6, 0.05, 3)[0], F
+
+
+@pytest.mark.parametrize("name,X,F", list(small_meshes()), ids=lambda v: v if isinstance(v, str) else "")
+def test_small_meshes_parity(name, X, F):
+    T = tpe()
+    log("case", name, F.shape[0])
+    Eo, Go = oracle.gradient(X, F)
+    Xd, Fd = upload(X, F)
+    E, G = T.gradient(Xd, Fd)
+    E = float(E.cpu()); G = G.cpu().numpy()
+    Ee = float(T.energy(Xd, Fd).cpu())
+    log(name, "rel E", rel_energy(E, Eo), "rel E(energy kernel)", rel_energy(Ee, Eo), "rel G", rel_grad_maxnorm(G, Go))
+    assert rel_energy(E, Eo) <= E_TOL
+    assert rel_energy(Ee, Eo) <= E_TOL
+    assert rel_grad_maxnorm(G, Go) <= G_TOL
+
+
+def test_two_triangles_closed_form():
+    T = tpe()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 0, 1], [2, 0, 1], [1, 1, 1]], dtype=np.float64)
+    F = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    Xd, Fd = upload(X, F)
+    E, G = T.gradient(Xd, Fd)
+    assert float(E.cpu()) == pytest.approx(1.0 / 128.0, rel=1e-6)
+    assert float(T.energy(Xd, Fd).cpu()) == pytest.approx(1.0 / 128.0, rel=1e-6)
+    Eo, Go = oracle.gradient(X, F)
+    assert rel_grad_maxnorm(G.cpu().numpy(), Go) <= G_TOL
+
+
+def test_c1_parity():
+    T = tpe()
+    c = M.make_config("C1")
+    Eo, Go = oracle.gradient(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    E, G = T.gradient(Xd, Fd)
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("C1 rel E", eE, "rel G", eG)
+    assert eE <= E_TOL and eG <= G_TOL
+
+
+def test_c2_parity():
+    T = tpe()
+    c = M.make_config("C2")
+    log("C2 oracle start", c.nF)
+    Eo, Go = oracle.gradient(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    E, G = T.gradient(Xd, Fd)
+    Ee = T.energy(Xd, Fd)
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    eEe = rel_energy(float(Ee.cpu()), Eo)
+    log("C2 rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
+    assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
+
+
+def test_c3_parity_sampled():
+    """Level-6 bump at gap 0.02: full oracle energy, oracle gradient at sampled vertices that
+    include the closest-approach region (where the gradient is largest)."""
+    T = tpe()
+    c = M.make_config("C3")
+    scale = 1e-4 / 6
+    Xd, Fd = upload(c.X, c.F)
+    E, G = T.gradient(Xd, Fd, scale=scale)
+    G = G.cpu().numpy()
+    E = float(E.cpu())
+    log("C3 oracle energy start", c.nF)
+    Eo = oracle.energy(c.X, c.F, scale=scale)
+    rng = np.random.default_rng(0)
+    top = np.argsort(-np.abs(G).max(1))[:16]
+    verts = np.unique(np.concatenate([top, rng.choice(c.V, 16, replace=False)])).astype(np.int32)
+    Go = oracle.gradient_at(c.X, c.F, verts, scale=scale)
+    # max-norm relative to the largest gradient component (the closest-approach vertices are sampled)
+    eG = float(np.abs(G[verts] - Go).max() / np.abs(Go).max())
+    log("C3 rel E", rel_energy(E, Eo), "rel G(sampled)", eG)
+    assert rel_energy(E, Eo) <= E_TOL
+    assert eG <= G_TOL
+
+
+def test_scaling_and_euler_identity():
+    """E(2X) = E(X)/4 and sum_v x_v . G_v = -2 E hold for any mesh (homogeneity of degree 4+q-p)."""
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    E1, G1 = T.gradient(Xd, Fd)
+    E2, G2 = T.gradient(2 * Xd, Fd)
+    E1, E2 = float(E1.cpu()), float(E2.cpu())
+    # power-of-two scaling is exact inside the library
+    assert E2 == E1 / 4
+    assert float((Xd * G1).sum().cpu()) == pytest.approx(-2 * E1, rel=1e-6)
+    assert np.abs(G2.cpu().numpy() * 8 - G1.cpu().numpy()).max() == 0.0
+
+
+def test_rigid_motion_gpu():
+    T = tpe()
+    c = M.make_config("C1")
+    R = M.random_rotation(5)
+    Xd, Fd = upload(c.X, c.F)
+    Xr, _ = upload(c.X @ R.T + np.array([0.25, -3.0, 1.0]), c.F)
+    E1, G1 = T.gradient(Xd, Fd)
+    E2, G2 = T.gradient(Xr, Fd)
+    assert rel_energy(float(E2.cpu()), float(E1.cpu())) <= 2e-6
+    G1 = G1.cpu().numpy(); G2 = G2.cpu().numpy()
+    assert rel_grad_maxnorm(G2, G1 @ R.T) <= 2e-5
+    # zero net force and torque
+    scale = np.abs(G1).max()
+    assert np.abs(G1.sum(0)).max() <= 1e-5 * scale
+    assert np.abs(np.cross(c.X, G1).sum(0)).max() <= 1e-5 * scale
+
+
+def test_determinism():
+    T = tpe()
+    c = M.make_config("C1")
+    Xd, Fd = upload(c.X, c.F)
+    E1, G1 = T.gradient(Xd, Fd)
+    E2, G2 = T.gradient(Xd, Fd)
+    assert float(E1.cpu()) == float(E2.cpu())
+    assert np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+
+
+@pytest.mark.parametrize("waves", [1, 64, 100000])
+def test_split_independence(waves):
+    """Different column splits of the pair kernel give the same result within tolerance."""
+    T = tpe()
+    c = M.make_config("C1")
+    Eo, Go = oracle.gradient(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    ctx = T.context(Xd.device)
+    ctx.set_option(T.OPT_TARGET_WAVES, waves)
+    try:
+        E, G = T.gradient(Xd, Fd)
+    finally:
+        ctx.set_option(T.OPT_TARGET_WAVES, 8192)
+    assert rel_energy(float(E.cpu()), Eo) <= E_TOL
+    assert rel_grad_maxnorm(G.cpu().numpy(), Go) <= G_TOL
+
+
+def test_pair_count():
+    T = tpe()
+    for level in (1, 3, 5):
+        X, F = M.icosphere(level)
+        _, Fd = upload(X, F)
+        nF = F.shape[0]
+        assert T.pair_count(Fd, X.shape[0]) == nF * nF - 13 * nF + 60
+    X, F = M.icosphere(2)
+    _, Fd = upload(X, F)
+    assert T.pair_count(Fd, X.shape[0]) == oracle.pair_count(F)
+
+
+def test_unreferenced_vertices_and_face_order():
+    """Extra vertices get zero gradient; permuting faces does not change the result."""
+    T = tpe()
+    c = M.make_config("C1")
+    X = np.concatenate([c.X, np.array([[5.0, 5.0, 5.0]])], 0)
+    F = c.F[np.random.default_rng(2).permutation(c.nF)]
+    Eo, Go = oracle.gradient(X, F)
+    Xd, Fd = upload(X, F)
+    E, G = T.gradient(Xd, Fd)
+    G = G.cpu().numpy()
+    assert np.all(G[-1] == 0.0)
+    assert rel_energy(float(E.cpu()), Eo) <= E_TOL
+    assert rel_grad_maxnorm(G, Go) <= G_TOL
+
+
+def test_error_paths():
+    T = tpe()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 0, 1], [2, 0, 1], [1, 1, 1]], dtype=np.float64)
+    F = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    Xd, Fd = upload(X, F)
+    with pytest.raises(T.TPEError) as e:
+        T.gradient(Xd, upload(X, np.array([[0, 1, 2], [3, 4, 9]], dtype=np.int32))[1])
+    assert e.value.code == -1
+    Xdeg = X.copy(); Xdeg[5] = Xdeg[4]
+    with pytest.raises(T.TPEError) as e:
+        T.gradient(upload(Xdeg, F)[0], Fd)
+    assert e.value.code == -2
+    Xnan = X.copy(); Xnan[0, 0] = np.nan
+    with pytest.raises(T.TPEError) as e:
+        T.energy(upload(Xnan, F)[0], Fd)
+    assert e.value.code == -3
+    Xc = np.concatenate([X[:3], X[:3][:, [1, 0, 2]]], 0)
+    with pytest.raises(T.TPEError) as e:
+        T.gradient(upload(Xc, F)[0], Fd)
+    assert e.value.code == -3
+    with pytest.raises(T.TPEError) as e:
+        T.energy(Xd, Fd, q=4.0, p=10.0)
+    assert e.value.code == -6
+    with pytest.raises(T.TPEError) as e:
+        T.energy(Xd, Fd, q=6.0, p=5.0)
+    assert e.value.code == -1
+    # the context keeps working after errors
+    E = T.energy(Xd, Fd)
+    assert float(E.cpu()) == pytest.approx(1.0 / 128.0, rel=1e-6)
