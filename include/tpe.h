@@ -58,8 +58,12 @@ typedef enum {
 typedef enum {
     TPE_OPT_SYNC_CHECKS = 1,  /* 1 (default): every call synchronises and reports device-side
                                  errors; 0: calls stay asynchronous, tpe_check() reports */
-    TPE_OPT_TARGET_WAVES = 2  /* work-groups the exact pair kernel aims to launch (>= 1;
-                                 default 8192); rows are split over column ranges to reach it */
+    TPE_OPT_TARGET_WAVES = 2, /* waves (work-groups) of the persistent exact pair kernel; 0
+                                 (default) = as many as the device keeps resident at once.  The
+                                 work is split evenly over them; results agree to rounding */
+    TPE_OPT_KERNEL_TIMING = 3 /* 1: record HIP events around every launch of the dominant
+                                 kernel (the pair kernel) on the context's stream, read back
+                                 with tpe_kernel_time(); 0 (default): off */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -95,6 +99,11 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
  * face get a zero gradient.  G_dev must not alias X. */
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
+
+/* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed
+ * duration of the pair-kernel launches recorded since the last call and *count (host) <- their
+ * number; the record is cleared. */
+int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count);
 
 /* *out_host (host int64) <- number of ordered face pairs (S, T) that share no vertex, i.e. the
  * number of pair interactions one evaluation performs.  Synchronises the stream. */

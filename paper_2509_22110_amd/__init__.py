@@ -27,6 +27,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "degenerate face", -3: "non-finit
 
 OPT_SYNC_CHECKS = 1
 OPT_TARGET_WAVES = 2
+OPT_KERNEL_TIMING = 3
 
 
 class TPEError(RuntimeError):
@@ -62,6 +63,7 @@ def lib():
             "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
+            "tpe_kernel_time": ([P, ctypes.POINTER(D), ctypes.POINTER(I64)], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -92,6 +94,16 @@ class _Ctx:
 
     def set_option(self, opt: int, value: int):
         self.check(lib().tpe_set_option(self.h, opt, int(value)))
+
+    def kernel_time(self):
+        """(total_ms, count) of the dominant kernel's launches recorded since the last read."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+        self.check(lib().tpe_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def sync_check(self):
+        """Wait for the stream and raise on device-side errors (when sync checks are off)."""
+        self.check(lib().tpe_check(self.h))
 
     def __del__(self):
         try:

@@ -2,40 +2,47 @@
 //
 // Pipeline of one tpe_gradient call (all on the context's stream, no host synchronisation
 // unless sync checks are on):
-//   face_bbox -> morton_keys -> radix sort (4 passes) -> tile_origins -> face_records
-//   -> vertex->corner CSR (count, scan, fill, per-vertex sort) -> tile-pair exclusion map
-//   -> pair_kernel (exact all-pairs row sums) -> finalize (FP64 adjoint + energy partials)
-//   -> energy_final -> vertex_gather.
+//   init_scratch -> face_bbox -> morton_keys -> radix sort (3 or 4 passes) -> face_records
+//   (+ per-vertex corner counts) -> vertex->corner CSR (scan, fill, per-vertex sort)
+//   -> tile-pair exclusion map -> pair_kernel (exact all-pairs row sums) -> merge_segments
+//   -> finalize (FP64 adjoint, energy) -> vertex_gather.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/tpe.h"
 #include "common.hpp"
 
 namespace tpe {
 hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st);
 hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox, uint32_t* flags,
                        hipStream_t st);
 hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
-                         uint32_t* keys, uint32_t* vals, hipStream_t st);
+                         int bits, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st);
+int64_t radix_hist_words(int64_t n);
 hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp, const uint32_t* perm,
                           const uint32_t* bbox, double* org, ColRec* cols, int4* colv, double* c64, double* geo,
-                          uint32_t* flags, hipStream_t st);
+                          uint32_t* cnt, uint32_t* flags, hipStream_t st);
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off, uint32_t* cursor,
                             uint32_t* list, hipStream_t st);
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
-                        int touch_words, uint32_t* touch, hipStream_t st);
+                        int nrb, int touch_words, uint32_t* touch, hipStream_t st);
+int pair_blocks_per_cu(bool grad);
+Sched make_sched(int64_t Fp, int waves);
+int64_t pair_part_floats(const Sched& sc, bool grad);
 hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
-                       const uint32_t* touch, int touch_words, int Fp, int ntiles, int tiles_per_split, int nsplits,
-                       float* part, hipStream_t st);
-hipError_t launch_finalize(bool grad, const float* part, int nsplits, int64_t Fp, int64_t nF, const double* geo,
+                       const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st);
+hipError_t launch_merge(bool grad, const float* part, const Sched& sc, int64_t Fp, double* acc, hipStream_t st);
+hipError_t launch_finalize(bool grad, int64_t Fp, int64_t nF, const double* acc64, const double* geo,
                            const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
-                           double* corner, double* epart, uint32_t* flags, double* E, hipStream_t st);
+                           double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                           hipStream_t st);
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
                          hipStream_t st);
 int finalize_blocks(int64_t nF);
@@ -69,13 +76,18 @@ __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_
 
 // Vertex ids of each face in input order (used where no sorting is needed).
 __global__ void face_ids(const int32_t* __restrict__ F, int64_t nF, int64_t V, int4* __restrict__ colv,
-                         uint32_t* __restrict__ flags) {
+                         uint32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nF) return;
     const int a = F[3 * i], b = F[3 * i + 1], c = F[3 * i + 2];
     const bool ok = a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V;
     if (!ok) atomicOr(flags, (uint32_t)FLAG_BAD_INDEX);
     colv[i] = ok ? make_int4(a, b, c, 0) : make_int4(-3, -3, -3, 0);
+    if (ok) {
+        atomicAdd(&cnt[a], 1u);
+        atomicAdd(&cnt[b], 1u);
+        atomicAdd(&cnt[c], 1u);
+    }
 }
 }  // namespace tpe
 
@@ -86,11 +98,15 @@ struct tpe_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool sync_checks = true;
-    int64_t target_waves = 8192;
+    int64_t target_waves = 0;     // 0: resident-wave capacity of the pair kernel
+    int resident[2] = {0, 0};     // pair-kernel waves resident on the device (energy, gradient)
     char* arena = nullptr;
     size_t arena_bytes = 0;
     uint32_t* dflags = nullptr;   // device error word
     uint32_t* hflags = nullptr;   // pinned host mirror
+    bool kernel_timing = false;
+    std::vector<hipEvent_t> ev_pool;  // pairs (start, stop), reused
+    size_t ev_used = 0;               // events recorded since the last tpe_kernel_time
 };
 
 namespace {
@@ -138,12 +154,15 @@ struct Carve {
 
 struct Plan {
     int64_t nF, V, Fp;
-    int ntiles, nrb, touch_words, nsplits, tiles_per_split, sort_blocks, fin_blocks;
+    int ntiles, nrb, touch_words, sort_blocks, fin_blocks;
+    Sched sc;
     // buffers
     uint32_t *keys, *vals, *ktmp, *vtmp, *hist, *hoff, *bbox;
     uint32_t *zero_begin, *cnt, *cursor, *touch, *zero_end;
     uint32_t *voff, *list;
-    double *org, *c64, *geo, *corner, *epart;
+    double *org, *c64, *geo, *corner, *epart, *acc64;
+    uint32_t* ticket;
+    int morton_bits;
     ColRec* cols;
     int4* colv;
     float* part;
@@ -158,16 +177,17 @@ void layout(Plan& P, char* base, bool grad) {
     P.vals = c.take<uint32_t>(nF);
     P.ktmp = c.take<uint32_t>(nF);
     P.vtmp = c.take<uint32_t>(nF);
-    P.hist = c.take<uint32_t>((size_t)256 * P.sort_blocks + 1);
-    P.hoff = c.take<uint32_t>((size_t)256 * P.sort_blocks + 1);
+    P.hist = c.take<uint32_t>((size_t)radix_hist_words(nF));
+    P.hoff = c.take<uint32_t>((size_t)radix_hist_words(nF));
     P.bbox = c.take<uint32_t>(8);
     P.counter = c.take<unsigned long long>(1);
     // one contiguous zero-initialised region
     P.zero_begin = c.take<uint32_t>(0);
+    P.ticket = c.take<uint32_t>(64);
     P.cnt = c.take<uint32_t>(V);
     P.cursor = c.take<uint32_t>(V);
-    P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.zero_end = c.take<uint32_t>(0);
+    P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.voff = c.take<uint32_t>(V + 1);
     P.list = c.take<uint32_t>(3 * nF);
     P.org = c.take<double>(3 * (size_t)P.ntiles);
@@ -175,8 +195,9 @@ void layout(Plan& P, char* base, bool grad) {
     P.colv = c.take<int4>(Fp);
     P.c64 = c.take<double>(3 * Fp);
     P.geo = c.take<double>(5 * Fp);
-    P.part = c.take<float>((size_t)P.nsplits * 2 * (grad ? NACC : 1) * Fp);
+    P.part = c.take<float>((size_t)pair_part_floats(P.sc, grad));
     P.corner = c.take<double>(grad ? 9 * nF : 1);
+    P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
     P.bytes = c.off + 256;
 }
@@ -188,11 +209,10 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad) {
     P.ntiles = (int)(P.Fp / CTILE);
     P.nrb = (int)(P.Fp / ROWB);
     P.touch_words = (P.ntiles + 31) / 32;
-    int64_t want = std::max<int64_t>(1, ceil_div(ctx->target_waves, P.nrb));
-    want = std::min<int64_t>(want, P.ntiles);
-    P.tiles_per_split = (int)ceil_div(P.ntiles, want);
-    P.nsplits = (int)ceil_div(P.ntiles, P.tiles_per_split);
+    P.sc = make_sched(P.Fp, ctx->target_waves > 0 ? (int)ctx->target_waves : ctx->resident[grad ? 1 : 0]);
     P.sort_blocks = (int)ceil_div(nF, 4096);
+    // Morton resolution: 6 bits per axis (2 radix passes of 9 bits) up to 2^18 faces, 10 above
+    P.morton_bits = nF <= (int64_t)1 << 18 ? 6 : 10;
     P.fin_blocks = finalize_blocks(nF);
     layout(P, nullptr, grad);
 }
@@ -220,8 +240,8 @@ int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!X || !F) return fail(ctx, TPE_ERR_INVALID_ARG, "null X or F");
     if (V < 1 || nF < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "V and nF must be >= 1");
-    if (nF > (int64_t)1 << 28 || V > (int64_t)1 << 30)
-        return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^28, V <= 2^30)");
+    if (nF > (int64_t)1 << 26 || V > (int64_t)1 << 28)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^26, V <= 2^28)");
     if (!(q >= 2.0) || !(p > q) || !std::isfinite(q) || !std::isfinite(p))
         return fail(ctx, TPE_ERR_INVALID_ARG, "exponents must satisfy 2 <= q < p");
     if (q != 6.0 || p != 12.0) return fail(ctx, TPE_ERR_UNSUPPORTED, "only (q, p) = (6, 12) is implemented");
@@ -239,18 +259,30 @@ int report_flags(tpe_ctx* ctx) {
     return TPE_OK;
 }
 
+// Next (start, stop) event pair for kernel timing; the pool grows on demand.
+int timing_events(tpe_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    *a = ctx->ev_pool[ctx->ev_used];
+    *b = ctx->ev_pool[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    return TPE_OK;
+}
+
 // Shared front half: sort faces, build records, adjacency and exclusion map.
 int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
     hipStream_t st = ctx->stream;
-    HIPCHK(launch_fill(P.zero_begin, 0u, P.zero_end - P.zero_begin, st));
-    HIPCHK(launch_fill(P.bbox, 0xffffffffu, 3, st));
-    HIPCHK(launch_fill(P.bbox + 3, 0u, 3, st));
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
     HIPCHK(launch_bbox(X, P.V, F, P.nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_morton(X, P.V, F, P.nF, P.bbox, P.keys, P.vals, st));
-    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nF, 30, P.hist, P.hoff, st));
-    HIPCHK(launch_records(X, P.V, F, P.nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, ctx->dflags, st));
+    HIPCHK(launch_morton(X, P.V, F, P.nF, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nF, 3 * P.morton_bits, P.hist, P.hoff, st));
+    HIPCHK(launch_records(X, P.V, F, P.nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                          ctx->dflags, st));
     HIPCHK(launch_adjacency(P.colv, P.nF, P.V, P.cnt, P.voff, P.cursor, P.list, st));
-    HIPCHK(launch_touch(P.colv, P.nF, P.V, P.voff, P.list, P.touch_words, P.touch, st));
+    HIPCHK(launch_touch(P.colv, P.nF, P.V, P.voff, P.list, P.nrb, P.touch_words, P.touch, st));
     return TPE_OK;
 }
 
@@ -266,12 +298,17 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
-    if (ctx->sync_checks) HIPCHK(launch_fill(ctx->dflags, 0u, 1, st));
     if ((rc = prepare(ctx, P, X, F))) return rc;
-    HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, (int)P.Fp, P.ntiles,
-                       P.tiles_per_split, P.nsplits, P.part, st));
-    HIPCHK(launch_finalize(grad, P.part, P.nsplits, P.Fp, nF, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
-                           ctx->dflags, E, st));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->kernel_timing) {
+        if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
+        HIPCHK(hipEventRecord(ev0, st));
+    }
+    HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
+    if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
+    HIPCHK(launch_merge(grad, P.part, P.sc, P.Fp, P.acc64, st));
+    HIPCHK(launch_finalize(grad, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
+                           P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -302,6 +339,13 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         return TPE_ERR_OOM;
     }
     *ctx->hflags = 0;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
+            ncu = 1;
+        ctx->resident[0] = ncu * pair_blocks_per_cu(false);
+        ctx->resident[1] = ncu * pair_blocks_per_cu(true);
+    }
     if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         (void)hipFree(ctx->dflags);
@@ -320,6 +364,7 @@ int tpe_destroy(tpe_ctx* ctx) {
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->dflags) (void)hipFree(ctx->dflags);
     if (ctx->hflags) (void)hipHostFree(ctx->hflags);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return TPE_OK;
 }
@@ -338,8 +383,12 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
             ctx->sync_checks = value != 0;
             return TPE_OK;
         case TPE_OPT_TARGET_WAVES:
-            if (value < 1 || value > (int64_t)1 << 24) return fail(ctx, TPE_ERR_INVALID_ARG, "target waves");
+            if (value < 0 || value > (int64_t)1 << 24) return fail(ctx, TPE_ERR_INVALID_ARG, "target waves");
             ctx->target_waves = value;
+            return TPE_OK;
+        case TPE_OPT_KERNEL_TIMING:
+            if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0 or 1");
+            ctx->kernel_timing = value != 0;
             return TPE_OK;
         default:
             return fail(ctx, TPE_ERR_INVALID_ARG, "unknown option");
@@ -369,6 +418,23 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
 }
 
+int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!total_ms || !count) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *count = (int64_t)(ctx->ev_used / 2);
+    ctx->ev_used = 0;
+    return TPE_OK;
+}
+
 int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_t* out_host) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!F || !out_host || nF < 1 || V < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
@@ -380,10 +446,9 @@ int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_
     layout(P, ctx->arena, false);
     hipStream_t st = ctx->stream;
     // sorted order is irrelevant for counting: use the identity permutation
-    HIPCHK(launch_fill(P.zero_begin, 0u, P.zero_end - P.zero_begin, st));
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->dflags, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(P.counter), 0u, 2, st));
-    HIPCHK(launch_fill(ctx->dflags, 0u, 1, st));
-    hipLaunchKernelGGL(face_ids, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, F, nF, V, P.colv, ctx->dflags);
+    hipLaunchKernelGGL(face_ids, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, F, nF, V, P.colv, P.cnt, ctx->dflags);
     HIPCHK(hipGetLastError());
     HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, st));
     hipLaunchKernelGGL(excluded_count, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, P.colv, nF, V, P.voff, P.list,

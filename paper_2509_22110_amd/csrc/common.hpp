@@ -26,6 +26,21 @@ struct __align__(32) ColRec {
     float nx, ny, nz, pad;
 };
 
+// Balanced persistent schedule.  The work is U = nrb * upr units, a unit being one chunk of CHUNK
+// columns for one row block of ROWB rows (upr = Fp / CHUNK units per row block, in column order).
+// Wave w of W takes the contiguous units [floor(w U / W), floor((w+1) U / W)), so every wave does
+// the same work to within one unit and, with W equal to the number of resident waves, the launch
+// has no tail.  A wave's range may cover the end of one row block and the start of the next: it
+// writes one partial-sum segment per row block it touches (at most maxseg), and the merge pass
+// adds, for each row block, the segments of the waves that cover it, in wave order.
+struct Sched {
+    int64_t U;
+    int W, upr, maxseg;
+    __host__ __device__ int64_t begin(int w) const { return (int64_t)w * U / W; }
+    // the wave whose range contains unit x
+    __host__ __device__ int wave_of(int64_t x) const { return (int)(((x + 1) * (int64_t)W - 1) / U); }
+};
+
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 

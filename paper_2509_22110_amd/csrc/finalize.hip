@@ -1,6 +1,6 @@
-// Finalize: merge the pair kernel's column splits in FP64, turn the per-face row sums into the
+// Finalize: turn the per-face row sums (merged in FP64 by merge_segments) into the
 // gradient contributions of the face's three corners, and reduce the energy; then the
-// scatter-free vertex gather.
+// scatter-free vertex gather.  No floating-point atomics anywhere: every sum has a fixed order.
 //
 // With the row sums of pair.hip (K, S0, Sd, Sdd, Sn) for face S and the kernel k = t^q with
 // p = 2q, the partial derivatives of E with respect to the face's own geometry are
@@ -20,31 +20,31 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// One thread per sorted face; block of 256 threads writes one FP64 energy partial.
+// One thread per sorted face; every work-group writes one FP64 energy partial and the last
+// work-group to finish (ticket counter, zero on entry) adds the partials in index order, so the
+// energy is deterministic.
 template <bool GRAD>
-__global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__ part, int nsplits, int64_t Fp,
-                                                       int64_t nF, const double* __restrict__ geo,
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ accs, int64_t Fp, int64_t nF,
+                                                       const double* __restrict__ geo,
                                                        const int4* __restrict__ colv,
                                                        const double* __restrict__ X,
                                                        const uint32_t* __restrict__ bbox, double q, double p,
                                                        double scale, double* __restrict__ corner,
-                                                       double* __restrict__ epart, uint32_t* __restrict__ flags) {
+                                                       double* __restrict__ epart, uint32_t* __restrict__ ticket,
+                                                       double* __restrict__ E, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
     __shared__ double ws[4];
+    __shared__ bool last;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double e = 0.0;
-    // the row sums were taken on positions multiplied by s: G(X) = s^(p-q-3) G(sX), exactly
+    // the row sums were taken on positions multiplied by s = 2^k: G(X) = s^(p-q-3) G(sX) and
+    // E(X) = s^(p-q-4) E(sX), exactly
     const int kexp = norm_exp(bbox);
     const double s = ldexp(1.0, kexp);
     const double gs = scale * pow2i(kexp, p - q - 3.0);
     if (i < nF) {
         double acc[NA];
-        for (int k = 0; k < NA; ++k) acc[k] = 0.0;
-        for (int sp = 0; sp < nsplits; ++sp) {
-            const float* ps = part + (size_t)sp * 2 * NA * Fp;
-            for (int k = 0; k < NA; ++k)
-                acc[k] += (double)ps[(size_t)k * Fp + i] + (double)ps[(size_t)(NA + k) * Fp + i];
-        }
+        for (int k = 0; k < NA; ++k) acc[k] = accs[(size_t)k * Fp + i];
         const double a = geo[5 * i + 0], wn = geo[5 * i + 1];
         const double n[3] = {geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]};
         bool finite = true;
@@ -85,24 +85,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
     e = wave_sum(e);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e;
     __syncthreads();
-    if (threadIdx.x == 0) epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
-}
-
-// Deterministic final energy sum (one work-group, fixed order).
-__global__ __launch_bounds__(256) void energy_final(const double* __restrict__ epart, int nb,
-                                                    const uint32_t* __restrict__ bbox, double q, double p,
-                                                    double scale, double* __restrict__ E) {
-    __shared__ double ws[4];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) s += epart[b];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        // E(X) = s^(p-q-4) E(sX), exactly for a power of two s
-        double t = scale * pow2i(norm_exp(bbox), p - q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
-        E[0] = t;
+        epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
     }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
+        t += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = wave_sum(t);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0 && E) E[0] = scale * pow2i(kexp, p - q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
 }
 
 // G[v] = sum over the (sorted face, corner) slots incident to v, ascending slot order.
@@ -125,17 +123,18 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 
-hipError_t launch_finalize(bool grad, const float* part, int nsplits, int64_t Fp, int64_t nF, const double* geo,
+// acc64: NA x Fp merged row sums; ticket: one word, zero on entry.
+hipError_t launch_finalize(bool grad, int64_t Fp, int64_t nF, const double* acc64, const double* geo,
                            const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
-                           double* corner, double* epart, uint32_t* flags, double* E, hipStream_t st) {
+                           double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                           hipStream_t st) {
     const int nb = finalize_blocks(nF);
     if (grad)
-        hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, nsplits, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, corner, epart, flags);
+        hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, acc64, Fp, nF, geo, colv, X, bbox, q, p,
+                           scale, corner, epart, ticket, E, flags);
     else
-        hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, nsplits, Fp, nF, geo, colv,
-                           X, bbox, q, p, scale, corner, epart, flags);
-    if (E) hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, epart, nb, bbox, q, p, scale, E);
+        hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, acc64, Fp, nF, geo, colv, X, bbox, q,
+                           p, scale, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 // (11 scalars).  The finalize pass turns them into corner gradients in FP64.
 //
 // MI355X mapping: one wave64 per work-group holds ROWB = 128 row faces (2 per lane) in VGPRs.
+// The launch is persistent and balanced (see Sched below).
 // All lanes visit the same column at the same time, so column records are wave-uniform and are
 // fetched with scalar loads into SGPRs (one 32-byte record per column); no LDS is needed and every
 // VALU instruction takes the column operand straight from an SGPR.  Columns come in tiles of 256
@@ -23,6 +24,8 @@
 // run over CHUNK columns and are folded into Kahan-compensated (hi, lo) FP32 pairs.  Tile pairs in
 // which some row shares a vertex with some column (a few percent, faces being in Morton order)
 // take a masked variant that compares vertex indices; all other tiles run with no exclusion test.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace tpe {
@@ -105,112 +108,166 @@ __device__ __forceinline__ void pair_update(const ColRec& cr, int4 cv, float rx,
     }
 }
 
+// One chunk of CHUNK columns for the wave's RPL x 64 rows: plain FP32 sums over the chunk, then a
+// Kahan fold into the rows' (hi, lo) accumulators.
 template <int Q, bool GRAD, bool MASK>
-__device__ __forceinline__ void tile_pass(const ColRec* __restrict__ tc, const int4* __restrict__ tv,
-                                          const float (&rx)[RPL], const float (&ry)[RPL],
-                                          const float (&rz)[RPL], const float (&nx)[RPL],
-                                          const float (&ny)[RPL], const float (&nz)[RPL],
-                                          const int (&rv)[RPL][3], float (&hi)[RPL][NACC],
-                                          float (&lo)[RPL][NACC]) {
+__device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const int4* __restrict__ tv,
+                                           const float (&rx)[RPL], const float (&ry)[RPL],
+                                           const float (&rz)[RPL], const float (&nx)[RPL],
+                                           const float (&ny)[RPL], const float (&nz)[RPL],
+                                           const int (&rv)[RPL][3], float (&hi)[RPL][NACC],
+                                           float (&lo)[RPL][NACC]) {
     constexpr int NA = GRAD ? NACC : 1;
-    for (int c0 = 0; c0 < CTILE; c0 += CHUNK) {
-        float acc[RPL][NA];
+    float acc[RPL][NA];
 #pragma unroll
-        for (int r = 0; r < RPL; ++r)
+    for (int r = 0; r < RPL; ++r)
 #pragma unroll
-            for (int k = 0; k < NA; ++k) acc[r][k] = 0.f;
+        for (int k = 0; k < NA; ++k) acc[r][k] = 0.f;
 #pragma unroll 4
-        for (int j = c0; j < c0 + CHUNK; ++j) {
-            const ColRec cr = tc[j];
-            int4 cv = make_int4(0, 0, 0, 0);
-            if constexpr (MASK) cv = tv[j];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r)
-                pair_update<Q, GRAD, MASK>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r],
-                                           rv[r][0], rv[r][1], rv[r][2], acc[r]);
-        }
+    for (int j = 0; j < CHUNK; ++j) {
+        const ColRec cr = tc[j];
+        int4 cv = make_int4(0, 0, 0, 0);
+        if constexpr (MASK) cv = tv[j];
 #pragma unroll
         for (int r = 0; r < RPL; ++r)
-#pragma unroll
-            for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
+            pair_update<Q, GRAD, MASK>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0], rv[r][1],
+                                       rv[r][2], acc[r]);
     }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
 }
 
-// grid: (n_rowblocks, n_splits); block: one wave.  part layout: [split][2*NA][Fp] FP32, first NA
-// rows hold hi, next NA rows hold the compensation to ADD (i.e. -c of Kahan's running error).
+// grid: W work-groups of one wave.  part layout: [W * maxseg segments][2 * NA][ROWB] FP32; the
+// first NA rows of a segment hold hi, the next NA the compensation to ADD (-c of Kahan's error).
 template <int Q, bool GRAD>
 __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ cols,
                                                     const int4* __restrict__ colv,
                                                     const double* __restrict__ c64,
                                                     const double* __restrict__ org,
                                                     const uint32_t* __restrict__ touch, int touch_words,
-                                                    int Fp, int ntiles, int tiles_per_split,
-                                                    float* __restrict__ part) {
+                                                    Sched sc, float* __restrict__ part) {
     constexpr int NA = GRAD ? NACC : 1;
+    constexpr int CPT = CTILE / CHUNK;  // chunks per tile
     const int lane = threadIdx.x;
-    const int rb = blockIdx.x;
-    const int split = blockIdx.y;
-    const int t0 = split * tiles_per_split;
-    const int t1 = min(ntiles, t0 + tiles_per_split);
-
-    double cxd[RPL], cyd[RPL], czd[RPL];
-    float nx[RPL], ny[RPL], nz[RPL];
-    int rv[RPL][3];
-    float hi[RPL][NACC], lo[RPL][NACC];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = rb * ROWB + r * WAVE + lane;
-        cxd[r] = c64[3 * (size_t)i + 0];
-        cyd[r] = c64[3 * (size_t)i + 1];
-        czd[r] = c64[3 * (size_t)i + 2];
-        const ColRec me = cols[i];
-        nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz;
-        const int4 v = colv[i];
-        rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
-#pragma unroll
-        for (int k = 0; k < NACC; ++k) { hi[r][k] = 0.f; lo[r][k] = 0.f; }
-    }
-    const uint32_t* my_touch = touch + (size_t)rb * touch_words;
-    for (int t = t0; t < t1; ++t) {
-        const double ox = org[3 * t + 0], oy = org[3 * t + 1], oz = org[3 * t + 2];
-        float rx[RPL], ry[RPL], rz[RPL];
+    const int w = blockIdx.x;
+    int64_t u = sc.begin(w);
+    const int64_t u1 = sc.begin(w + 1);
+    int seg = 0;
+    while (u < u1) {
+        const int rb = (int)(u / sc.upr);
+        const int64_t uend = min(u1, (int64_t)(rb + 1) * sc.upr);
+        double cxd[RPL], cyd[RPL], czd[RPL];
+        float nx[RPL], ny[RPL], nz[RPL];
+        int rv[RPL][3];
+        float hi[RPL][NACC], lo[RPL][NACC];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            rx[r] = (float)(cxd[r] - ox);
-            ry[r] = (float)(cyd[r] - oy);
-            rz[r] = (float)(czd[r] - oz);
-        }
-        const bool masked = (my_touch[t >> 5] >> (t & 31)) & 1u;
-        const ColRec* tc = cols + (size_t)t * CTILE;
-        const int4* tv = colv + (size_t)t * CTILE;
-        if (masked)
-            tile_pass<Q, GRAD, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
-        else
-            tile_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
-    }
-    float* out = part + (size_t)split * 2 * NA * Fp;
+            const int i = rb * ROWB + r * WAVE + lane;
+            cxd[r] = c64[3 * (size_t)i + 0];
+            cyd[r] = c64[3 * (size_t)i + 1];
+            czd[r] = c64[3 * (size_t)i + 2];
+            const ColRec me = cols[i];
+            nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz;
+            const int4 v = colv[i];
+            rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = rb * ROWB + r * WAVE + lane;
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-            out[(size_t)k * Fp + i] = hi[r][k];
-            out[(size_t)(NA + k) * Fp + i] = -lo[r][k];
+            for (int k = 0; k < NACC; ++k) { hi[r][k] = 0.f; lo[r][k] = 0.f; }
         }
+        const uint32_t* my_touch = touch + (size_t)rb * touch_words;
+        int cur_t = -1;
+        bool masked = false;
+        float rx[RPL], ry[RPL], rz[RPL];
+        for (; u < uend; ++u) {
+            const int cu = (int)(u - (int64_t)rb * sc.upr);
+            const int t = cu / CPT;
+            if (t != cur_t) {
+                // rows relative to this tile's FP64 origin (columns are stored relative to it)
+                const double ox = org[3 * t + 0], oy = org[3 * t + 1], oz = org[3 * t + 2];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    rx[r] = (float)(cxd[r] - ox);
+                    ry[r] = (float)(cyd[r] - oy);
+                    rz[r] = (float)(czd[r] - oz);
+                }
+                masked = (my_touch[t >> 5] >> (t & 31)) & 1u;
+                cur_t = t;
+            }
+            const ColRec* tc = cols + (size_t)cu * CHUNK;
+            const int4* tv = colv + (size_t)cu * CHUNK;
+            if (masked)
+                chunk_pass<Q, GRAD, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+            else
+                chunk_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+        }
+        float* out = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                out[(size_t)k * ROWB + r * WAVE + lane] = hi[r][k];
+                out[(size_t)(NA + k) * ROWB + r * WAVE + lane] = -lo[r][k];
+            }
+        }
+        ++seg;
     }
 }
 
-// Host-side launchers (declared in kernels.hpp).
-hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64,
-                       const double* org, const uint32_t* touch, int touch_words, int Fp, int ntiles,
-                       int tiles_per_split, int nsplits, float* part, hipStream_t st) {
-    dim3 grid(Fp / ROWB, nsplits);
+// acc[k][i] = sum, in wave order, of the segments covering row i's block: (hi + lo) in FP64.
+// One thread per (accumulator k = blockIdx.y, row i).
+__global__ __launch_bounds__(256) void merge_segments(const float* __restrict__ part, Sched sc, int NA, int64_t Fp,
+                                                      double* __restrict__ acc) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= Fp) return;
+    const int rb = (int)(i / ROWB), rr = (int)(i % ROWB);
+    const int w0 = sc.wave_of((int64_t)rb * sc.upr), w1 = sc.wave_of((int64_t)(rb + 1) * sc.upr - 1);
+    double s = 0.0;
+    for (int w = w0; w <= w1; ++w) {
+        const int seg = rb - (int)(sc.begin(w) / sc.upr);
+        const float* ps = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB;
+        s += (double)ps[(size_t)k * ROWB + rr] + (double)ps[(size_t)(NA + k) * ROWB + rr];
+    }
+    acc[(size_t)k * Fp + i] = s;
+}
+
+int pair_blocks_per_cu(bool grad) {
+    int nb = 0;
+    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, true>, WAVE, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, false>, WAVE, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+Sched make_sched(int64_t Fp, int waves) {
+    Sched sc;
+    const int nrb = (int)(Fp / ROWB);
+    sc.upr = (int)(Fp / CHUNK);
+    sc.U = (int64_t)nrb * sc.upr;
+    sc.W = (int)std::max<int64_t>(1, std::min<int64_t>(waves, sc.U));
+    const int64_t per = (sc.U + sc.W - 1) / sc.W;
+    sc.maxseg = (int)((per + sc.upr - 1) / sc.upr) + 1;
+    return sc;
+}
+
+int64_t pair_part_floats(const Sched& sc, bool grad) {
+    return (int64_t)sc.W * sc.maxseg * 2 * (grad ? NACC : 1) * ROWB;
+}
+
+hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                       const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st) {
     if (grad)
-        hipLaunchKernelGGL((pair_kernel<6, true>), grid, dim3(WAVE), 0, st, cols, colv, c64, org,
-                           touch, touch_words, Fp, ntiles, tiles_per_split, part);
+        hipLaunchKernelGGL((pair_kernel<6, true>), dim3(sc.W), dim3(WAVE), 0, st, cols, colv, c64, org, touch,
+                           touch_words, sc, part);
     else
-        hipLaunchKernelGGL((pair_kernel<6, false>), grid, dim3(WAVE), 0, st, cols, colv, c64, org,
-                           touch, touch_words, Fp, ntiles, tiles_per_split, part);
+        hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE), 0, st, cols, colv, c64, org, touch,
+                           touch_words, sc, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(bool grad, const float* part, const Sched& sc, int64_t Fp, double* acc, hipStream_t st) {
+    const int NA = grad ? NACC : 1;
+    hipLaunchKernelGGL(merge_segments, dim3((unsigned)((Fp + 255) / 256), NA), dim3(256), 0, st, part, sc, NA, Fp, acc);
     return hipGetLastError();
 }
 

@@ -21,34 +21,45 @@ __global__ void fill_u32(uint32_t* p, uint32_t v, int64_t n) {
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids; must start at
-// (0xffffffff x3, 0 x3).  Also validates indices / coordinates and flags errors.
-__global__ void face_bbox(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
-                          int64_t nF, uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags) {
-    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// One launch that prepares the scratch state of a call: zero [zero, zero+nzero), bbox to
+// (+max x3, 0 x3) in the order-preserving encoding, and optionally the error word.
+__global__ void init_scratch(uint32_t* __restrict__ zero, int64_t nzero, uint32_t* __restrict__ bbox,
+                             uint32_t* __restrict__ flags) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < 6) bbox[i] = i < 3 ? 0xffffffffu : 0u;
+    if (i == 6 && flags) flags[0] = 0u;
+    for (; i < nzero; i += (int64_t)gridDim.x * blockDim.x) zero[i] = 0u;
+}
+
+// bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids (FP32); must start at
+// (0xffffffff x3, 0 x3).  Also validates indices / coordinates and flags errors.  Grid-stride
+// loop, reduction over the work-group, then six atomics per work-group.
+__global__ __launch_bounds__(256) void face_bbox(const double* __restrict__ X, int64_t V,
+                                                  const int32_t* __restrict__ F, int64_t nF,
+                                                  uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags) {
+    __shared__ float smn[4][3], smx[4][3];
+    __shared__ uint32_t sfl[4];
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     uint32_t fl = 0;
-    if (f < nF) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nF; f += (int64_t)gridDim.x * blockDim.x) {
         int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
         double c[3] = {0, 0, 0};
         bool ok = true;
         for (int k = 0; k < 3; ++k) {
             if (v[k] < 0 || v[k] >= V) { ok = false; fl |= FLAG_BAD_INDEX; }
         }
-        if (ok) {
-            for (int k = 0; k < 3; ++k)
-                for (int d = 0; d < 3; ++d) {
-                    double x = X[3 * (int64_t)v[k] + d];
-                    if (!isfinite(x)) fl |= FLAG_NONFINITE;
-                    c[d] += x;
-                }
+        if (!ok) continue;
+        for (int k = 0; k < 3; ++k)
             for (int d = 0; d < 3; ++d) {
-                float cf = (float)(c[d] / 3.0);
-                if (isfinite(cf)) { mn[d] = cf; mx[d] = cf; }
+                double x = X[3 * (int64_t)v[k] + d];
+                if (!isfinite(x)) fl |= FLAG_NONFINITE;
+                c[d] += x;
             }
+        for (int d = 0; d < 3; ++d) {
+            float cf = (float)(c[d] / 3.0);
+            if (isfinite(cf)) { mn[d] = fminf(mn[d], cf); mx[d] = fmaxf(mx[d], cf); }
         }
     }
-    // wave reduction then one atomic per wave
     for (int d = 0; d < 3; ++d) {
         float a = mn[d], b = mx[d];
         for (int off = 32; off > 0; off >>= 1) {
@@ -58,19 +69,28 @@ __global__ void face_bbox(const double* __restrict__ X, int64_t V, const int32_t
         mn[d] = a; mx[d] = b;
     }
     for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        for (int d = 0; d < 3; ++d) { smn[w][d] = mn[d]; smx[w][d] = mx[d]; }
+        sfl[w] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t f = sfl[0] | sfl[1] | sfl[2] | sfl[3];
         for (int d = 0; d < 3; ++d) {
-            if (mn[d] <= mx[d]) {
-                atomicMin(&bbox[d], float_to_ordered(mn[d]));
-                atomicMax(&bbox[3 + d], float_to_ordered(mx[d]));
+            float a = fminf(fminf(smn[0][d], smn[1][d]), fminf(smn[2][d], smn[3][d]));
+            float b = fmaxf(fmaxf(smx[0][d], smx[1][d]), fmaxf(smx[2][d], smx[3][d]));
+            if (a <= b) {
+                atomicMin(&bbox[d], float_to_ordered(a));
+                atomicMax(&bbox[3 + d], float_to_ordered(b));
             }
         }
-        if (fl) atomicOr(flags, fl);
+        if (f) atomicOr(flags, f);
     }
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
-    x &= 0x3ffu;
+    x &= 0x3ffu;  // interleave the low 10 bits with two zero bits each
     x = (x | (x << 16)) & 0x030000ffu;
     x = (x | (x << 8)) & 0x0300f00fu;
     x = (x | (x << 4)) & 0x030c30c3u;
@@ -78,10 +98,11 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-// 30-bit Morton key of each face centroid inside the centroid bounding box; value = face id.
+// 3*bits-bit Morton key (bits <= 10 per axis) of each face centroid inside the centroid bounding
+// box; value = face id.
 __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
-                            int64_t nF, const uint32_t* __restrict__ bbox, uint32_t* __restrict__ keys,
-                            uint32_t* __restrict__ vals) {
+                            int64_t nF, const uint32_t* __restrict__ bbox, int bits,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (f >= nF) return;
     float lo[3], ext[3];
@@ -98,8 +119,9 @@ __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32
     if (ok) {
         for (int d = 0; d < 3; ++d) {
             double c = (X[3 * (int64_t)v[0] + d] + X[3 * (int64_t)v[1] + d] + X[3 * (int64_t)v[2] + d]) / 3.0;
+            const float cells = (float)(1u << bits);
             float s = ((float)c - lo[d]) / ext[d];
-            s = fminf(fmaxf(s * 1024.f, 0.f), 1023.f);
+            s = fminf(fmaxf(s * cells, 0.f), cells - 1.f);
             q[d] = isfinite(s) ? (uint32_t)s : 0u;
         }
     }
@@ -117,33 +139,34 @@ __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32
 //   c64[i]   : centroid (FP64)
 //   org[t]   : FP64 origin of tile t = centroid of its first face
 //   geo[i]   : FP64 {a, |w|, n.x, n.y, n.z} for the finalize pass
-__global__ void tile_origins(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
-                             int64_t nF, const uint32_t* __restrict__ perm, int ntiles,
-                             const uint32_t* __restrict__ bbox, double* __restrict__ org) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    const double s = norm_scale(bbox);
-    int64_t i = (int64_t)t * CTILE;
-    double o[3] = {0, 0, 0};
-    if (i < nF) {
-        int64_t f = perm[i];
-        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
-        if (v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V)
-            for (int d = 0; d < 3; ++d)
-                o[d] = s * (X[3 * (int64_t)v[0] + d] + X[3 * (int64_t)v[1] + d] + X[3 * (int64_t)v[2] + d]) / 3.0;
-    }
-    for (int d = 0; d < 3; ++d) org[3 * t + d] = isfinite(o[d]) ? o[d] : 0.0;
-}
-
 __global__ void face_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
                              int64_t nF, int64_t Fp, const uint32_t* __restrict__ perm,
-                             const uint32_t* __restrict__ bbox, const double* __restrict__ org,
+                             const uint32_t* __restrict__ bbox, double* __restrict__ org,
                              ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
-                             double* __restrict__ geo, uint32_t* __restrict__ flags) {
+                             double* __restrict__ geo, uint32_t* __restrict__ cnt,
+                             uint32_t* __restrict__ flags) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= Fp) return;
     const double s = norm_scale(bbox);
     const int t = (int)(i / CTILE);
+    // tile origin = scaled centroid of the tile's first face (every thread of the tile derives
+    // the same value; the first thread stores it for the pair kernel)
+    double o[3] = {0.0, 0.0, 0.0};
+    {
+        const int64_t i0 = (int64_t)t * CTILE;
+        if (i0 < nF) {
+            const int64_t f0 = perm[i0];
+            const int32_t u0 = F[3 * f0], u1 = F[3 * f0 + 1], u2 = F[3 * f0 + 2];
+            if (u0 >= 0 && u0 < V && u1 >= 0 && u1 < V && u2 >= 0 && u2 < V)
+                for (int d = 0; d < 3; ++d) {
+                    const double od = s * (X[3 * (int64_t)u0 + d] + X[3 * (int64_t)u1 + d] +
+                                           X[3 * (int64_t)u2 + d]) / 3.0;
+                    o[d] = isfinite(od) ? od : 0.0;
+                }
+        }
+        if (i == i0)
+            for (int d = 0; d < 3; ++d) org[3 * t + d] = o[d];
+    }
     ColRec r;
     if (i < nF) {
         int64_t f = perm[i];
@@ -178,9 +201,11 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
             c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
         }
         if (fl) atomicOr(flags, fl);
-        r.cx = (float)(c[0] - org[3 * t + 0]);
-        r.cy = (float)(c[1] - org[3 * t + 1]);
-        r.cz = (float)(c[2] - org[3 * t + 2]);
+        r.cx = (float)(c[0] - o[0]);
+        r.cy = (float)(c[1] - o[1]);
+        r.cz = (float)(c[2] - o[2]);
+        if (ok)
+            for (int k = 0; k < 3; ++k) atomicAdd(&cnt[v[k]], 1u);
         r.a = (float)a;
         r.nx = (float)n[0]; r.ny = (float)n[1]; r.nz = (float)n[2];
         r.pad = 0.f;
@@ -193,25 +218,16 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         r.cx = PAD_COORD; r.cy = PAD_COORD; r.cz = PAD_COORD; r.a = 0.f;
         r.nx = 0.f; r.ny = 0.f; r.nz = 0.f; r.pad = 0.f;
         colv[i] = make_int4(-1, -1, -1, 0);
-        c64[3 * i + 0] = org[3 * t + 0] + PAD_COORD;
-        c64[3 * i + 1] = org[3 * t + 1] + PAD_COORD;
-        c64[3 * i + 2] = org[3 * t + 2] + PAD_COORD;
+        c64[3 * i + 0] = o[0] + PAD_COORD;
+        c64[3 * i + 1] = o[1] + PAD_COORD;
+        c64[3 * i + 2] = o[2] + PAD_COORD;
         for (int k = 0; k < 5; ++k) geo[5 * i + k] = 0.0;
     }
     cols[i] = r;
 }
 
 // ---- vertex -> (sorted face, corner) adjacency, CSR, deterministic order ----------------------
-
-__global__ void corner_count(const int4* __restrict__ colv, int64_t nF, int64_t V,
-                             uint32_t* __restrict__ cnt) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nF) return;
-    int4 v = colv[i];
-    int vv[3] = {v.x, v.y, v.z};
-    for (int k = 0; k < 3; ++k)
-        if (vv[k] >= 0 && vv[k] < V) atomicAdd(&cnt[vv[k]], 1u);
-}
+// (per-vertex counts are accumulated by face_records)
 
 __global__ void corner_fill(const int4* __restrict__ colv, int64_t nF, int64_t V,
                             const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
@@ -241,23 +257,31 @@ __global__ void corner_sort(const uint32_t* __restrict__ off, int64_t V, uint32_
 }
 
 // Tile-pair exclusion map: bit (rb, t) set iff some row of row block rb shares a vertex with some
-// column of tile t.  Rows/columns are sorted positions.
-__global__ void touch_map(const int4* __restrict__ colv, int64_t nF, int64_t V,
-                          const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-                          int touch_words, uint32_t* __restrict__ touch) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nF) return;
-    int4 v = colv[i];
-    int vv[3] = {v.x, v.y, v.z};
-    const int64_t rb = i / ROWB;
-    for (int k = 0; k < 3; ++k) {
-        if (vv[k] < 0 || vv[k] >= V) continue;
-        for (uint32_t e = off[vv[k]]; e < off[vv[k] + 1]; ++e) {
-            uint32_t j = list[e] / 3;
-            uint32_t t = j / CTILE;
-            atomicOr(&touch[rb * touch_words + (t >> 5)], 1u << (t & 31));
+// column of tile t.  Rows/columns are sorted positions.  One work-group per row block builds its
+// row of the map in LDS (dynamic shared memory, touch_words words) and stores it: no global
+// atomics and no prior zeroing.
+__global__ __launch_bounds__(256) void touch_map(const int4* __restrict__ colv, int64_t nF, int64_t V,
+                                                  const uint32_t* __restrict__ off,
+                                                  const uint32_t* __restrict__ list, int touch_words,
+                                                  uint32_t* __restrict__ touch) {
+    extern __shared__ uint32_t bits[];
+    const int64_t rb = blockIdx.x;
+    for (int w = threadIdx.x; w < touch_words; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+    // ROWB rows x 3 corners, one (row, corner) per thread
+    for (int e = threadIdx.x; e < ROWB * 3; e += blockDim.x) {
+        const int64_t i = rb * ROWB + e / 3;
+        if (i >= nF) continue;
+        const int4 v = colv[i];
+        const int vk = (e % 3 == 0) ? v.x : (e % 3 == 1) ? v.y : v.z;
+        if (vk < 0 || vk >= V) continue;
+        for (uint32_t q = off[vk]; q < off[vk + 1]; ++q) {
+            const uint32_t t = (list[q] / 3) / CTILE;
+            atomicOr(&bits[t >> 5], 1u << (t & 31));
         }
     }
+    __syncthreads();
+    for (int w = threadIdx.x; w < touch_words; w += blockDim.x) touch[rb * touch_words + w] = bits[w];
 }
 
 // ---- host launchers ----------------------------------------------------------------------------
@@ -273,32 +297,37 @@ hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st) {
+    int g = (int)std::min<int64_t>(std::max<int64_t>(nblk(nzero, 256), 1), 2048);
+    hipLaunchKernelGGL(init_scratch, dim3(g), dim3(256), 0, st, zero, nzero, bbox, flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox,
                        uint32_t* flags, hipStream_t st) {
-    hipLaunchKernelGGL(face_bbox, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, flags);
+    int g = (int)std::min<int64_t>(nblk(nF, 256), 64);
+    hipLaunchKernelGGL(face_bbox, dim3(g), dim3(256), 0, st, X, V, F, nF, bbox, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
-                         uint32_t* keys, uint32_t* vals, hipStream_t st) {
-    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, keys, vals);
+                         int bits, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, bits, keys, vals);
     return hipGetLastError();
 }
 
+// cnt (V entries) must be zero on entry; face_records accumulates the per-vertex corner counts.
 hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp,
                           const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
-                          double* c64, double* geo, uint32_t* flags, hipStream_t st) {
-    int ntiles = (int)(Fp / CTILE);
-    hipLaunchKernelGGL(tile_origins, dim3(nblk(ntiles, 256)), dim3(256), 0, st, X, V, F, nF, perm, ntiles, bbox, org);
+                          double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st) {
     hipLaunchKernelGGL(face_records, dim3(nblk(Fp, 256)), dim3(256), 0, st, X, V, F, nF, Fp, perm, bbox, org, cols,
-                       colv, c64, geo, flags);
+                       colv, c64, geo, cnt, flags);
     return hipGetLastError();
 }
 
-// cnt and cursor must be zeroed by the caller (V entries each).
+// cnt holds the per-vertex corner counts; cursor must be zero (V entries).
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off,
                             uint32_t* cursor, uint32_t* list, hipStream_t st) {
-    hipLaunchKernelGGL(corner_count, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, cnt);
     hipError_t e = launch_exclusive_scan(cnt, V, off, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(corner_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, cursor, list);
@@ -307,9 +336,9 @@ hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* c
 }
 
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
-                        int touch_words, uint32_t* touch, hipStream_t st) {
-    hipLaunchKernelGGL(touch_map, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, list, touch_words,
-                       touch);
+                        int nrb, int touch_words, uint32_t* touch, hipStream_t st) {
+    hipLaunchKernelGGL(touch_map, dim3(nrb), dim3(256), touch_words * sizeof(uint32_t), st, colv, nF, V, off, list,
+                       touch_words, touch);
     return hipGetLastError();
 }
 

@@ -1,47 +1,54 @@
-// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits.
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 9- or 10-bit digits.
 //
-// Per pass: (1) every work-group counts the digits of its 4096-key tile in LDS and writes one
+// Per pass: (1) every work-group counts the digits of its 2048-key tile in LDS and writes one
 // column of a digit-major histogram; (2) one work-group scans the histogram; (3) every work-group
-// re-reads its tile in 16 rounds of 256 keys and writes each key to
+// re-reads its tile in 8 rounds of 256 keys and writes each key to
 // offset[digit][group] + (rank among equal digits before it).  The rank inside a wave comes from
-// eight ballots (one per digit bit), across the four waves from LDS counters, so the sort is
+// one ballot per digit bit, across the four waves from LDS counters, so the sort is
 // stable and deterministic.
 #include "common.hpp"
 
 namespace tpe {
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ROUNDS = 16;
+constexpr int RS_ROUNDS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
 
+template <int DB>
 __global__ __launch_bounds__(RS_THREADS) void rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                        int nblocks, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[256];
+    constexpr int ND = 1 << DB;
+    __shared__ uint32_t h[ND];
     const int tid = threadIdx.x;
-    h[tid] = 0;
+    for (int d = tid; d < ND; d += RS_THREADS) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ROUNDS; ++r) {
         int64_t i = base + r * RS_THREADS + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (ND - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
+    for (int d = tid; d < ND; d += RS_THREADS) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
 }
 
+template <int DB>
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin, int64_t n,
                                                           int shift, int nblocks,
                                                           const uint32_t* __restrict__ off,
                                                           uint32_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+    constexpr int ND = 1 << DB;
+    constexpr int NW = RS_THREADS / 64;
+    __shared__ uint32_t run[ND];
+    __shared__ uint32_t wcnt[NW][ND];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    run[tid] = off[(int64_t)tid * nblocks + blockIdx.x];
-    for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0;
+    for (int d = tid; d < ND; d += RS_THREADS) {
+        run[d] = off[(int64_t)d * nblocks + blockIdx.x];
+        for (int w = 0; w < NW; ++w) wcnt[w][d] = 0;
+    }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -50,9 +57,9 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restr
         const bool act = i < n;
         uint32_t k = act ? kin[i] : 0u;
         uint32_t v = act ? vin[i] : 0u;
-        uint32_t d = (k >> shift) & 255u;
+        uint32_t d = (k >> shift) & (ND - 1);
         uint64_t peers = __ballot(act);
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DB; ++b) {
             uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
@@ -66,9 +73,11 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restr
             vout[pos] = v;
         }
         __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < RS_THREADS / 64; ++w) { add += wcnt[w][tid]; wcnt[w][tid] = 0; }
-        run[tid] += add;
+        for (int dd = tid; dd < ND; dd += RS_THREADS) {
+            uint32_t add = 0;
+            for (int w = 0; w < NW; ++w) { add += wcnt[w][dd]; wcnt[w][dd] = 0; }
+            run[dd] += add;
+        }
         __syncthreads();
     }
 }
@@ -104,23 +113,32 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, h
 }
 
 
-// Sorts n pairs by the low `bits` bits of the key.  Uses (ktmp, vtmp) as ping-pong buffers and
-// `hist`/`off` of 256*ceil(n/4096) (+1) words.  The result always ends in (keys, vals): with an odd number of passes it is
-// copied back from the ping-pong buffers.
-int radix_passes(int bits) { return (bits + 7) / 8; }
+// Sorts n pairs by the low `bits` (<= 30) bits of the key: 2 passes of 9-bit digits up to 18 bits,
+// otherwise 3 passes of 10-bit digits.  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of
+// (1024 * ceil(n / RS_TILE) + 1) words.  The result always ends in (keys, vals).
+template <int DB>
+static hipError_t rs_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int64_t n, int shift,
+                          int nblocks, uint32_t* hist, uint32_t* off, hipStream_t st) {
+    hipLaunchKernelGGL((rs_hist<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, n, shift, nblocks, hist);
+    hipLaunchKernelGGL(exclusive_scan_1wg, dim3(1), dim3(1024), 0, st, hist, (int64_t)(1 << DB) * nblocks, off);
+    hipLaunchKernelGGL((rs_scatter<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, shift, nblocks, off, ko,
+                       vo);
+    return hipGetLastError();
+}
+
+int64_t radix_hist_words(int64_t n) { return (int64_t)1024 * ((n + RS_TILE - 1) / RS_TILE) + 1; }
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st) {
     if (n <= 1) return hipSuccess;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
-    const int passes = radix_passes(bits);
     uint32_t *ki = keys, *vi = vals, *ko = ktmp, *vo = vtmp;
+    const bool small = bits <= 18;
+    const int passes = small ? 2 : 3;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, ki, n, shift, nblocks, hist);
-        hipLaunchKernelGGL(exclusive_scan_1wg, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nblocks, off);
-        hipLaunchKernelGGL(rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, shift, nblocks, off,
-                           ko, vo);
+        hipError_t e = small ? rs_pass<9>(ki, vi, ko, vo, n, 9 * p, nblocks, hist, off, st)
+                             : rs_pass<10>(ki, vi, ko, vo, n, 10 * p, nblocks, hist, off, st);
+        if (e != hipSuccess) return e;
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
