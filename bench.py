@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -75,6 +77,13 @@ def main():
     E = torch.empty((), dtype=torch.float64, device=dev)
     ctx = T.context(dev)
     ctx.set_option(T.OPT_SYNC_CHECKS, 0)
+
+    if args.calib_copy_mb:
+        src = torch.empty(args.calib_copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         T.gradient(X, F, out=G, energy_out=E)

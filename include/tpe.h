@@ -32,6 +32,7 @@
  *   - A context is not thread-safe; use one per host thread or serialise calls.
  *   - Supported exponents: (q, p) = (6, 12) (the paper's alpha = 6).  Others return
  *     TPE_ERR_UNSUPPORTED.
+ *   - Sizes: nF <= 2^24, V <= 2^26.
  */
 #ifndef TPE_H
 #define TPE_H
@@ -43,6 +44,8 @@ extern "C" {
 #endif
 
 typedef struct tpe_ctx tpe_ctx;
+typedef struct tpe_tree tpe_tree;  /* cluster tree: a Morton ordering of the faces (see tpe_build_tree) */
+typedef struct tpe_mlp tpe_mlp;    /* learned far-field correction (see tpe_mlp_create) */
 
 typedef enum {
     TPE_OK = 0,
@@ -100,8 +103,42 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
 
+/* Build the cluster tree used by tpe_farfield (paper Sec. 3.3: the inner integrals are clustered
+ * with precomputed averages over patches of elements, Barnes-Hut style).  The tree is an implicit
+ * complete binary tree over leaves of `leaf_size` consecutive faces (1..4096; 32 in the
+ * paper-scale workloads); the faces are ordered top-down so that each node's faces are split
+ * along the longest axis of their centroid bounding box (k-d order), which keeps every cluster a
+ * compact patch.  Only
+ * the ordering is stored: the cluster moments are recomputed from the positions passed to each
+ * tpe_farfield call, so one tree serves a whole gradient flow as long as the faces stay put in
+ * the ordering sense (accuracy, not correctness, depends on it).  *out is owned by the caller
+ * (tpe_tree_destroy).  Synchronises the stream. */
+int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                   int32_t leaf_size, tpe_tree** out);
+
+/* Free a tree. */
+int tpe_tree_destroy(tpe_tree* tree);
+
+/* Barnes-Hut approximation of E and dE/dX on the tree (paper Sec. 3.3, clustering of the inner
+ * integrals of eq. (dTP_reordered)).  Every block of 64 consecutive faces in tree order is
+ * enclosed by a ball (C_T, r_T); a cluster B with area A_B, area-weighted centroid C_B, unit
+ * mean normal N_B and vertex-bounding radius r_B is far when 2 r_B < theta (|C_T - C_B| - r_T)
+ * and then acts on each face of the block as one pseudo-face (C_B, A_B, N_B); every other pair is
+ * evaluated exactly, with the shared-vertex exclusion.  theta = 0 reproduces tpe_gradient to
+ * rounding.  mlp: NULL for the plain monopole.  E_dev and/or G_dev (device) may be NULL but not
+ * both.  X, V, F, nF must describe the mesh the tree was built for (same size, same faces). */
+int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
+                 const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
+                 const tpe_mlp* mlp, double* E_dev, double* G_dev);
+
+/* Interaction counts of the last tpe_farfield call on this context, summed over target blocks of
+ * 64 faces (each count applies to every face of a block): out_host[0] = far clusters evaluated,
+ * [1] = near columns evaluated exactly, [2] = tree nodes visited, [3] = target blocks.  Host
+ * array of 4 int64.  Synchronises the stream. */
+int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
+
 /* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed
- * duration of the pair-kernel launches recorded since the last call and *count (host) <- their
+ * duration of the dominant-kernel launches (the exact pair kernel, or the far-field traversal) recorded since the last call and *count (host) <- their
  * number; the record is cleared. */
 int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count);
 

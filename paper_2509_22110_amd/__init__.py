@@ -18,7 +18,7 @@ import threading
 import torch
 
 __all__ = ["TPEError", "lib", "energy", "gradient", "pair_count", "TPEFunction", "tpe_energy",
-           "context", "LIB_PATH", "STATUS"]
+           "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtpe.so")
 
@@ -64,6 +64,10 @@ def lib():
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
             "tpe_kernel_time": ([P, ctypes.POINTER(D), ctypes.POINTER(I64)], I),
+            "tpe_build_tree": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
+            "tpe_tree_destroy": ([P], I),
+            "tpe_farfield": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
+            "tpe_farfield_stats": ([P, ctypes.POINTER(I64)], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -100,6 +104,12 @@ class _Ctx:
         ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
         self.check(lib().tpe_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def farfield_stats(self):
+        """(far clusters, near columns, visited nodes, target blocks) of the last far-field call."""
+        out = (ctypes.c_int64 * 4)()
+        self.check(lib().tpe_farfield_stats(self.h, out))
+        return tuple(int(v) for v in out)
 
     def sync_check(self):
         """Wait for the stream and raise on device-side errors (when sync checks are off)."""
@@ -161,6 +171,42 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
     return E, G
 
 
+class Tree:
+    """Cluster tree (Morton ordering of the faces, leaves of `leaf` faces); see tpe_build_tree."""
+
+    def __init__(self, X, F, leaf: int = 32):
+        X, F = _check_mesh(X, F)
+        c = context(X.device)
+        h = ctypes.c_void_p()
+        c.check(lib().tpe_build_tree(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], int(leaf),
+                                     ctypes.byref(h)))
+        self.h, self.nF, self.V, self.leaf, self.device = h, F.shape[0], X.shape[0], leaf, X.device
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.tpe_tree_destroy(self.h)
+        except Exception:
+            pass
+
+
+def build_tree(X, F, leaf: int = 32) -> Tree:
+    return Tree(X, F, leaf)
+
+
+def farfield(tree: Tree, X, F, theta=0.5, q=6.0, p=12.0, scale=1.0, mlp=None, out=None, energy_out=None,
+             want_grad=True):
+    """Barnes-Hut far-field approximation (E, G) on `tree` (G is None when want_grad is False)."""
+    X, F = _check_mesh(X, F)
+    G = (out if out is not None else torch.empty_like(X)) if want_grad else None
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_farfield(c.h, tree.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], float(q),
+                               float(p), float(scale), float(theta), mlp.h if mlp is not None else None,
+                               E.data_ptr(), G.data_ptr() if G is not None else None))
+    return E, G
+
+
 def pair_count(F, V: int) -> int:
     """Number of ordered face pairs sharing no vertex (pair interactions per evaluation)."""
     if F.device.type != "cuda" or F.dtype != torch.int32:
@@ -173,24 +219,32 @@ def pair_count(F, V: int) -> int:
 
 
 class TPEFunction(torch.autograd.Function):
-    """E = TPEFunction.apply(X, F, q, p, scale): forward runs the energy kernel; backward runs the
-    hand-written gradient (tpe_gradient) and scales it by the incoming gradient.  Only X and F are
-    saved; everything else is recomputed in backward."""
+    """E = TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp).
+
+    forward runs the energy (exact energy kernel, or the far field on `tree`); backward runs the
+    hand-written gradient of the same method (tpe_gradient, or tpe_farfield which recomputes the
+    cluster moments from X) and scales it by the incoming gradient.  Only X and F are saved."""
 
     @staticmethod
-    def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0):
+    def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None):
         ctx.save_for_backward(X, F)
-        ctx.params = (q, p, scale)
-        return energy(X.detach(), F, q, p, scale)
+        ctx.params = (q, p, scale, tree, theta, mlp)
+        if tree is None:
+            return energy(X.detach(), F, q, p, scale)
+        E, _ = farfield(tree, X.detach(), F, theta, q, p, scale, mlp, want_grad=False)
+        return E
 
     @staticmethod
     def backward(ctx, gE):
         X, F = ctx.saved_tensors
-        q, p, scale = ctx.params
-        _, G = gradient(X.detach(), F, q, p, scale)
-        return G * gE, None, None, None, None
+        q, p, scale, tree, theta, mlp = ctx.params
+        if tree is None:
+            _, G = gradient(X.detach(), F, q, p, scale)
+        else:
+            _, G = farfield(tree, X.detach(), F, theta, q, p, scale, mlp)
+        return G * gE, None, None, None, None, None, None, None
 
 
-def tpe_energy(X, F, q=6.0, p=12.0, scale=1.0):
+def tpe_energy(X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None):
     """Differentiable energy (autograd through TPEFunction)."""
-    return TPEFunction.apply(X, F, q, p, scale)
+    return TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp)

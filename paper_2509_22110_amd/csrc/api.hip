@@ -46,6 +46,19 @@ hipError_t launch_finalize(bool grad, int64_t Fp, int64_t nF, const double* acc6
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
                          hipStream_t st);
 int finalize_blocks(int64_t nF);
+int tree_height(int64_t nF, int leaf);
+hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, int H, float4* cen,
+                          uint32_t* nb, uint32_t* perm, uint32_t* keys, uint32_t* ktmp, uint32_t* vtmp,
+                          uint32_t* hist, uint32_t* off, hipStream_t st);
+size_t tree_node_bytes(int H);
+size_t tree_rec_bytes(int H);
+hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
+                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
+                               hipStream_t st);
+hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                           const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
+                           int64_t Fp, float theta, float4* balls, double* acc64, unsigned long long* stats,
+                           hipStream_t st);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -104,9 +117,17 @@ struct tpe_ctx {
     size_t arena_bytes = 0;
     uint32_t* dflags = nullptr;   // device error word
     uint32_t* hflags = nullptr;   // pinned host mirror
+    unsigned long long* dstats = nullptr;  // far-field interaction counters of the last call
     bool kernel_timing = false;
     std::vector<hipEvent_t> ev_pool;  // pairs (start, stop), reused
     size_t ev_used = 0;               // events recorded since the last tpe_kernel_time
+};
+
+struct tpe_tree {
+    int device = 0;
+    int64_t nF = 0, V = 0;
+    int leaf = 32, H = 0;
+    uint32_t* perm = nullptr;  // sorted position -> input face index (device, nF entries)
 };
 
 namespace {
@@ -167,6 +188,12 @@ struct Plan {
     int4* colv;
     float* part;
     unsigned long long* counter;
+    // far field
+    int treeH = -1;
+    void *nodes64 = nullptr, *recs = nullptr;
+    float4* balls = nullptr;
+    float4* cen4 = nullptr;
+    uint32_t* nbox = nullptr;
     size_t bytes;
 };
 
@@ -199,19 +226,28 @@ void layout(Plan& P, char* base, bool grad) {
     P.corner = c.take<double>(grad ? 9 * nF : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
+    if (P.treeH >= 0) {
+        P.nodes64 = c.take<char>(tree_node_bytes(P.treeH));
+        P.recs = c.take<char>(tree_rec_bytes(P.treeH));
+        P.balls = c.take<float4>(Fp / 64);
+        P.cen4 = c.take<float4>(nF);
+        P.nbox = c.take<uint32_t>((size_t)6 << std::max(P.treeH - 1, 0));
+    }
     P.bytes = c.off + 256;
 }
 
-void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad) {
+void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1) {
+    P.treeH = treeH;
     P.nF = nF;
     P.V = V;
     P.Fp = round_up(nF, std::max(ROWB, CTILE));
     P.ntiles = (int)(P.Fp / CTILE);
     P.nrb = (int)(P.Fp / ROWB);
-    P.touch_words = (P.ntiles + 31) / 32;
+    P.touch_words = (int)((P.Fp / CHUNK + 31) / 32);
     P.sc = make_sched(P.Fp, ctx->target_waves > 0 ? (int)ctx->target_waves : ctx->resident[grad ? 1 : 0]);
     P.sort_blocks = (int)ceil_div(nF, 4096);
     // Morton resolution: 6 bits per axis (2 radix passes of 9 bits) up to 2^18 faces, 10 above
+    // (3 passes of 10 bits)
     P.morton_bits = nF <= (int64_t)1 << 18 ? 6 : 10;
     P.fin_blocks = finalize_blocks(nF);
     layout(P, nullptr, grad);
@@ -240,8 +276,8 @@ int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!X || !F) return fail(ctx, TPE_ERR_INVALID_ARG, "null X or F");
     if (V < 1 || nF < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "V and nF must be >= 1");
-    if (nF > (int64_t)1 << 26 || V > (int64_t)1 << 28)
-        return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^26, V <= 2^28)");
+    if (nF > (int64_t)1 << 24 || V > (int64_t)1 << 26)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^24, V <= 2^26)");
     if (!(q >= 2.0) || !(p > q) || !std::isfinite(q) || !std::isfinite(p))
         return fail(ctx, TPE_ERR_INVALID_ARG, "exponents must satisfy 2 <= q < p");
     if (q != 6.0 || p != 12.0) return fail(ctx, TPE_ERR_UNSUPPORTED, "only (q, p) = (6, 12) is implemented");
@@ -333,6 +369,7 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return TPE_ERR_OOM;
     }
+    ctx->dstats = reinterpret_cast<unsigned long long*>(ctx->dflags) + 16;  // bytes 128..160 of the same block
     if (hipHostMalloc(&ctx->hflags, sizeof(uint32_t)) != hipSuccess) {
         (void)hipFree(ctx->dflags);
         delete ctx;
@@ -416,6 +453,111 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
     if (ctx && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
+}
+
+int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, int32_t leaf_size,
+                   tpe_tree** out) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    int rc = check_common(ctx, X, V, F, nF, 6.0, 12.0);
+    if (rc) return rc;
+    if (leaf_size < 1 || leaf_size > 4096) return fail(ctx, TPE_ERR_INVALID_ARG, "leaf_size must be in [1, 4096]");
+    DeviceGuard dg(ctx->device);
+    const int H = tree_height(nF, leaf_size);
+    Plan P;
+    plan(P, ctx, nF, V, false, H);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, false);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(build_kd_order(X, V, F, nF, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist, P.hoff,
+                          st));
+    tpe_tree* t = new tpe_tree();
+    t->device = ctx->device;
+    t->nF = nF;
+    t->V = V;
+    t->leaf = leaf_size;
+    t->H = tree_height(nF, leaf_size);
+    if (hipMalloc(&t->perm, nF * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete t;
+        return fail(ctx, TPE_ERR_OOM, "tree permutation allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(t->perm, P.vals, nF * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(t->perm);
+        delete t;
+        return hip_fail(ctx, e, "tree permutation copy");
+    }
+    if (ctx->sync_checks && (rc = report_flags(ctx))) {
+        (void)hipFree(t->perm);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return TPE_OK;
+}
+
+int tpe_tree_destroy(tpe_tree* t) {
+    if (!t) return TPE_ERR_INVALID_ARG;
+    DeviceGuard dg(t->device);
+    if (t->perm) (void)hipFree(t->perm);
+    delete t;
+    return TPE_OK;
+}
+
+int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                 double q, double p, double scale, double theta, const tpe_mlp* mlp, double* E_dev, double* G_dev) {
+    int rc = check_common(ctx, X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (!tree) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree");
+    if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
+    if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be >= 0");
+    if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
+    if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
+    if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    if (mlp) return fail(ctx, TPE_ERR_UNSUPPORTED, "learned far-field correction not available");
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    plan(P, ctx, nF, V, true, tree->H);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, true);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_records(X, V, F, nF, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                          ctx->dflags, st));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->kernel_timing) {
+        if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
+        HIPCHK(hipEventRecord(ev0, st));
+    }
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 8, st));
+    HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
+                           (float)theta, P.balls, P.acc64, ctx->dstats, st));
+    if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
+    HIPCHK(launch_finalize(true, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
+                           P.ticket, ctx->dflags, E_dev, st));
+    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
+int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!out_host) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    DeviceGuard dg(ctx->device);
+    unsigned long long h[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, ctx->dstats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < 4; ++i) out_host[i] = (int64_t)h[i];
+    return TPE_OK;
 }
 
 int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count) {

@@ -21,9 +21,10 @@
 // VALU instruction takes the column operand straight from an SGPR.  Columns come in tiles of 256
 // faces stored relative to an FP64 tile origin; each row re-expresses its centroid relative to
 // that origin once per tile, so nearby pairs see small, accurately rounded coordinates.  FP32 sums
-// run over CHUNK columns and are folded into Kahan-compensated (hi, lo) FP32 pairs.  Tile pairs in
-// which some row shares a vertex with some column (a few percent, faces being in Morton order)
-// take a masked variant that compares vertex indices; all other tiles run with no exclusion test.
+// run over CHUNK columns and are folded into Kahan-compensated (hi, lo) FP32 pairs.  (Row block,
+// chunk) pairs in which some row shares a vertex with some column (a few percent, faces being in
+// Morton order) take a masked variant that compares vertex indices; all others run with no
+// exclusion test.
 #include <algorithm>
 
 #include "common.hpp"
@@ -177,7 +178,6 @@ __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ c
         }
         const uint32_t* my_touch = touch + (size_t)rb * touch_words;
         int cur_t = -1;
-        bool masked = false;
         float rx[RPL], ry[RPL], rz[RPL];
         for (; u < uend; ++u) {
             const int cu = (int)(u - (int64_t)rb * sc.upr);
@@ -191,9 +191,9 @@ __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ c
                     ry[r] = (float)(cyd[r] - oy);
                     rz[r] = (float)(czd[r] - oz);
                 }
-                masked = (my_touch[t >> 5] >> (t & 31)) & 1u;
                 cur_t = t;
             }
+            const bool masked = (my_touch[cu >> 5] >> (cu & 31)) & 1u;
             const ColRec* tc = cols + (size_t)cu * CHUNK;
             const int4* tv = colv + (size_t)cu * CHUNK;
             if (masked)

@@ -256,8 +256,8 @@ __global__ void corner_sort(const uint32_t* __restrict__ off, int64_t V, uint32_
     }
 }
 
-// Tile-pair exclusion map: bit (rb, t) set iff some row of row block rb shares a vertex with some
-// column of tile t.  Rows/columns are sorted positions.  One work-group per row block builds its
+// Exclusion map: bit (rb, c) set iff some row of row block rb shares a vertex with some column of
+// the c-th chunk of CHUNK columns.  Rows/columns are sorted positions.  One work-group per row block builds its
 // row of the map in LDS (dynamic shared memory, touch_words words) and stores it: no global
 // atomics and no prior zeroing.
 __global__ __launch_bounds__(256) void touch_map(const int4* __restrict__ colv, int64_t nF, int64_t V,
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void touch_map(const int4* __restrict__ colv, 
         const int vk = (e % 3 == 0) ? v.x : (e % 3 == 1) ? v.y : v.z;
         if (vk < 0 || vk >= V) continue;
         for (uint32_t q = off[vk]; q < off[vk + 1]; ++q) {
-            const uint32_t t = (list[q] / 3) / CTILE;
+            const uint32_t t = (list[q] / 3) / CHUNK;
             atomicOr(&bits[t >> 5], 1u << (t & 31));
         }
     }

@@ -1,4 +1,4 @@
-// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 9- or 10-bit digits.
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, digits of 6 to 10 bits.
 //
 // Per pass: (1) every work-group counts the digits of its 2048-key tile in LDS and writes one
 // column of a digit-major histogram; (2) one work-group scans the histogram; (3) every work-group
@@ -113,8 +113,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, h
 }
 
 
-// Sorts n pairs by the low `bits` (<= 30) bits of the key: 2 passes of 9-bit digits up to 18 bits,
-// otherwise 3 passes of 10-bit digits.  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of
+// Sorts n pairs by the low `bits` (<= 32) bits of the key in ceil(bits / 10) passes of equal
+// digits (<= 10 bits).  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of
 // (1024 * ceil(n / RS_TILE) + 1) words.  The result always ends in (keys, vals).
 template <int DB>
 static hipError_t rs_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int64_t n, int shift,
@@ -130,14 +130,21 @@ int64_t radix_hist_words(int64_t n) { return (int64_t)1024 * ((n + RS_TILE - 1) 
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st) {
-    if (n <= 1) return hipSuccess;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    if (bits > 32) bits = 32;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int passes = (bits + 9) / 10;
+    const int db = (bits + passes - 1) / passes;
     uint32_t *ki = keys, *vi = vals, *ko = ktmp, *vo = vtmp;
-    const bool small = bits <= 18;
-    const int passes = small ? 2 : 3;
     for (int p = 0; p < passes; ++p) {
-        hipError_t e = small ? rs_pass<9>(ki, vi, ko, vo, n, 9 * p, nblocks, hist, off, st)
-                             : rs_pass<10>(ki, vi, ko, vo, n, 10 * p, nblocks, hist, off, st);
+        hipError_t e;
+        switch (db) {
+            case 10: e = rs_pass<10>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+            case 9: e = rs_pass<9>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+            case 8: e = rs_pass<8>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+            case 7: e = rs_pass<7>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+            default: e = rs_pass<6>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+        }
         if (e != hipSuccess) return e;
         std::swap(ki, ko);
         std::swap(vi, vo);

@@ -1,0 +1,502 @@
+// Cluster tree over Morton-ordered faces and the Barnes-Hut far field of the inner integrals.
+//
+// The paper clusters only the inner integrals f_K, f_nu, f of eq. (dTP_reordered) (Sec. 3.3): for
+// an outer point x, the contribution of a patch of faces far enough from x is replaced by one
+// evaluation with precomputed averages over the patch, and no derivative has to be propagated
+// back to the patch because the test function only appears in the outer integral.  Here:
+//   - the tree is an implicit complete binary tree over leaves of `leaf` consecutive faces in k-d
+//     order (node k has children 2k, 2k+1; leaves are nodes 2^H .. 2^H + nleaf - 1);
+//   - per node: area A_B = sum a, area-weighted centroid C_B, area-weighted normal sum N_B,
+//     second moments of (c - C_B) and of n weighted by area, and a radius r_B that bounds the
+//     distance from C_B to every vertex of every member face (exact at leaves, propagated up as
+//     max over children of |C_child - C_B| + r_child);
+//   - a target block of 64 consecutive faces (one wave) is enclosed by a ball (C_T, r_T) that
+//     bounds its faces' vertices; a cluster B is far when 2 r_B < theta (|C_T - C_B| - r_T);
+//   - a far cluster acts on every face S of the block as one pseudo-face (monopole): centroid C_B,
+//     area A_B, unit normal N_B/|N_B|, through exactly the same pair arithmetic as the exact
+//     kernel (forward term with n_S, reverse term with N_B/|N_B|);
+//   - a cluster that is not far is opened; a leaf that is not far is evaluated exactly, pair by
+//     pair, with the shared-vertex exclusion.  Because r_T and r_B bound vertices, a far cluster
+//     never contains a face sharing a vertex with a target face.
+// The output is the exact kernel's per-face row-sum layout, so the FP64 finalize and the vertex
+// gather are shared with the exact path.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace tpe {
+
+// FP64 node moments (combine pass) and the FP32 record the traversal reads with scalar loads.
+struct NodeF64 {
+    double A, cx, cy, cz, nx, ny, nz, r;
+    double m2c[6];  // sum a (c - C)(c - C)^T: xx, xy, xz, yy, yz, zz
+    double m2n[6];  // sum a n n^T
+};
+
+struct __align__(32) NodeRec {
+    float cx, cy, cz, r;  // centroid (normalised frame), radius bound
+    float a, nx, ny, nz;  // area, unit mean normal
+};
+
+__device__ __forceinline__ void sym_add_outer(double* m, double w, double x, double y, double z) {
+    m[0] += w * x * x; m[1] += w * x * y; m[2] += w * x * z;
+    m[3] += w * y * y; m[4] += w * y * z; m[5] += w * z * z;
+}
+
+__device__ __forceinline__ float round_up_f(double v) {
+    float f = (float)v;
+    return (double)f >= v ? f : nextafterf(f, INFINITY);
+}
+
+__device__ void write_rec(const NodeF64& n, NodeRec* rec) {
+    NodeRec r;
+    r.cx = (float)n.cx; r.cy = (float)n.cy; r.cz = (float)n.cz;
+    // the FP32 centroid moves by at most ~|C| 2^-24; fold that into the radius bound
+    const double slack = 1e-6 * (1.0 + fabs(n.cx) + fabs(n.cy) + fabs(n.cz));
+    r.r = n.A > 0.0 ? round_up_f(n.r + slack) : 0.f;
+    r.a = (float)n.A;
+    const double nn = sqrt(n.nx * n.nx + n.ny * n.ny + n.nz * n.nz);
+    r.nx = nn > 0.0 ? (float)(n.nx / nn) : 0.f;
+    r.ny = nn > 0.0 ? (float)(n.ny / nn) : 0.f;
+    r.nz = nn > 0.0 ? (float)(n.nz / nn) : 0.f;
+    *rec = r;
+}
+
+// One thread per leaf slot j in [0, 2^H): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order.
+__global__ void leaf_moments(const double* __restrict__ c64, const double* __restrict__ geo,
+                             const int4* __restrict__ colv, const double* __restrict__ X,
+                             const uint32_t* __restrict__ bbox, int64_t nF, int leaf, int H,
+                             NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nslot = (int64_t)1 << H;
+    if (j >= nslot) return;
+    const double s = norm_scale(bbox);
+    NodeF64 n = {};
+    const int64_t f0 = j * leaf, f1 = std::min<int64_t>(nF, f0 + leaf);
+    double sx = 0, sy = 0, sz = 0;
+    for (int64_t i = f0; i < f1; ++i) {
+        const double a = geo[5 * i];
+        n.A += a;
+        sx += a * c64[3 * i]; sy += a * c64[3 * i + 1]; sz += a * c64[3 * i + 2];
+        n.nx += a * geo[5 * i + 2]; n.ny += a * geo[5 * i + 3]; n.nz += a * geo[5 * i + 4];
+    }
+    if (n.A > 0.0) {
+        n.cx = sx / n.A; n.cy = sy / n.A; n.cz = sz / n.A;
+        for (int64_t i = f0; i < f1; ++i) {
+            const double a = geo[5 * i];
+            sym_add_outer(n.m2c, a, c64[3 * i] - n.cx, c64[3 * i + 1] - n.cy, c64[3 * i + 2] - n.cz);
+            sym_add_outer(n.m2n, a, geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]);
+            const int4 v = colv[i];
+            const int vv[3] = {v.x, v.y, v.z};
+            for (int k = 0; k < 3; ++k) {
+                if (vv[k] < 0) continue;
+                const double dx = s * X[3 * (int64_t)vv[k]] - n.cx, dy = s * X[3 * (int64_t)vv[k] + 1] - n.cy,
+                             dz = s * X[3 * (int64_t)vv[k] + 2] - n.cz;
+                n.r = fmax(n.r, sqrt(dx * dx + dy * dy + dz * dz));
+            }
+        }
+    }
+    nodes[nslot + j] = n;
+    write_rec(n, &recs[nslot + j]);
+}
+
+// Nodes of one level [2^l, 2^(l+1)) from their children.
+__global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t first = (int64_t)1 << level;
+    if (t >= first) return;
+    const int64_t k = first + t;
+    const NodeF64 a = nodes[2 * k], b = nodes[2 * k + 1];
+    NodeF64 n = {};
+    n.A = a.A + b.A;
+    if (n.A > 0.0) {
+        n.cx = (a.A * a.cx + b.A * b.cx) / n.A;
+        n.cy = (a.A * a.cy + b.A * b.cy) / n.A;
+        n.cz = (a.A * a.cz + b.A * b.cz) / n.A;
+        n.nx = a.nx + b.nx; n.ny = a.ny + b.ny; n.nz = a.nz + b.nz;
+        const NodeF64* ch[2] = {&a, &b};
+        for (int c = 0; c < 2; ++c) {
+            const NodeF64& q = *ch[c];
+            if (!(q.A > 0.0)) continue;
+            const double dx = q.cx - n.cx, dy = q.cy - n.cy, dz = q.cz - n.cz;
+            n.r = fmax(n.r, sqrt(dx * dx + dy * dy + dz * dz) + q.r);
+            for (int m = 0; m < 6; ++m) { n.m2c[m] += q.m2c[m]; n.m2n[m] += q.m2n[m]; }
+            sym_add_outer(n.m2c, q.A, dx, dy, dz);  // parallel-axis shift to the new centroid
+        }
+    }
+    nodes[k] = n;
+    write_rec(n, &recs[k]);
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+__device__ __forceinline__ double wave_max_d(double x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
+// Ball (C_T, r_T) of each target block of 64 sorted faces: C_T = mean of the centroids, r_T bounds
+// the distance to every vertex of the block's faces (plus FP32 rounding slack).  One wave each.
+__global__ __launch_bounds__(64) void target_balls(const double* __restrict__ c64, const int4* __restrict__ colv,
+                                                   const double* __restrict__ X, const uint32_t* __restrict__ bbox,
+                                                   int64_t nF, float4* __restrict__ balls) {
+    const int64_t b = blockIdx.x;
+    const int64_t i = b * 64 + threadIdx.x;
+    const bool act = i < nF;
+    const double s = norm_scale(bbox);
+    const double nact = wave_sum_d(act ? 1.0 : 0.0);
+    const double cx = wave_sum_d(act ? c64[3 * i] : 0.0) / fmax(nact, 1.0);
+    const double cy = wave_sum_d(act ? c64[3 * i + 1] : 0.0) / fmax(nact, 1.0);
+    const double cz = wave_sum_d(act ? c64[3 * i + 2] : 0.0) / fmax(nact, 1.0);
+    double r = 0.0;
+    if (act) {
+        const int4 v = colv[i];
+        const int vv[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3; ++k) {
+            if (vv[k] < 0) continue;
+            const double dx = s * X[3 * (int64_t)vv[k]] - cx, dy = s * X[3 * (int64_t)vv[k] + 1] - cy,
+                         dz = s * X[3 * (int64_t)vv[k] + 2] - cz;
+            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    }
+    r = wave_max_d(r);
+    if (threadIdx.x == 0) {
+        const double slack = 1e-6 * (1.0 + fabs(cx) + fabs(cy) + fabs(cz));
+        balls[b] = make_float4((float)cx, (float)cy, (float)cz, round_up_f(r + slack));
+    }
+}
+
+// pair arithmetic shared with the exact kernel
+template <int Q, bool GRAD, bool MASK>
+__device__ __forceinline__ void ff_pair(const ColRec& cr, int4 cv, float rx, float ry, float rz, float nx, float ny,
+                                        float nz, int v0, int v1, int v2, float* acc) {
+    float dx = rx - cr.cx, dy = ry - cr.cy, dz = rz - cr.cz;
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float w = __builtin_amdgcn_rcpf(r2);
+    if constexpr (MASK) {
+        bool ex = (v0 == cv.x) | (v0 == cv.y) | (v0 == cv.z) | (v1 == cv.x) | (v1 == cv.y) | (v1 == cv.z) |
+                  (v2 == cv.x) | (v2 == cv.y) | (v2 == cv.z);
+        w = ex ? 0.f : w;
+    }
+    float u = fmaf(nz, dz, fmaf(ny, dy, nx * dx));
+    float t = u * w;
+    float v = fmaf(cr.nz, dz, fmaf(cr.ny, dy, cr.nx * dx));
+    float tau = v * w;
+    float t2 = t * t, t4 = t2 * t2, t5 = t4 * t, t6 = t5 * t;
+    float s2 = tau * tau, s4 = s2 * s2, s5 = s4 * tau, s6 = s5 * tau;
+    float aw = cr.a * w;
+    float s = aw * t5;
+    float sp = aw * s5;
+    float e = t6 + s6;
+    float m = aw * e;
+    acc[0] = fmaf(cr.a, e, acc[0]);
+    acc[1] += s;
+    acc[2] = fmaf(s, dx, acc[2]);
+    acc[3] = fmaf(s, dy, acc[3]);
+    acc[4] = fmaf(s, dz, acc[4]);
+    acc[5] = fmaf(m, dx, acc[5]);
+    acc[6] = fmaf(m, dy, acc[6]);
+    acc[7] = fmaf(m, dz, acc[7]);
+    acc[8] = fmaf(sp, cr.nx, acc[8]);
+    acc[9] = fmaf(sp, cr.ny, acc[9]);
+    acc[10] = fmaf(sp, cr.nz, acc[10]);
+}
+
+__device__ __forceinline__ void ff_fold(float (&acc)[NACC], float (&hi)[NACC], float (&lo)[NACC]) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        float y = acc[k] - lo[k];
+        float t = hi[k] + y;
+        lo[k] = (t - hi[k]) - y;
+        hi[k] = t;
+        acc[k] = 0.f;
+    }
+}
+
+// Exact pairs of the block's rows with the faces [f0, f1) (a near node), with the shared-vertex
+// exclusion; columns are read with scalar loads, four at a time, rows re-expressed relative to
+// each 256-face tile's FP64 origin.
+__device__ __forceinline__ void ff_near_range(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
+                                              const double* __restrict__ org, int64_t f0, int64_t f1, double cxd,
+                                              double cyd, double czd, const ColRec& me, const int4& mv,
+                                              float (&acc)[NACC], float (&hi)[NACC], float (&lo)[NACC], int& cnt) {
+    int64_t f = f0;
+    while (f < f1) {
+        const int64_t t = f / CTILE;
+        const int64_t fend = std::min<int64_t>(f1, (t + 1) * CTILE);
+        const float rx = (float)(cxd - org[3 * t]), ry = (float)(cyd - org[3 * t + 1]), rz = (float)(czd - org[3 * t + 2]);
+        for (; f + 4 <= fend; f += 4) {
+            const ColRec c0 = cols[f], c1 = cols[f + 1], c2 = cols[f + 2], c3 = cols[f + 3];
+            const int4 v0 = colv[f], v1 = colv[f + 1], v2 = colv[f + 2], v3 = colv[f + 3];
+            ff_pair<6, true, true>(c0, v0, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, true>(c1, v1, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, true>(c2, v2, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, true>(c3, v3, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            cnt += 4;
+            if (cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        }
+        for (; f < fend; ++f) {
+            ff_pair<6, true, true>(cols[f], colv[f], rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        }
+    }
+}
+
+__device__ __forceinline__ float lane_f(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+constexpr int FF_STACK = 2048;  // LDS node stack per wave
+
+// One wave per target block of 64 consecutive (tree-ordered) faces.  Batched depth-first walk of
+// the implicit tree: up to 64 nodes are popped at once (one per lane), tested in parallel, and then
+//   - far clusters are applied to all 64 rows one after another (their records broadcast from the
+//     lane that loaded them),
+//   - near leaves are evaluated exactly,
+//   - other nodes push their two children;
+// if the stack could overflow, a node that would be opened is evaluated exactly instead (always
+// correct).  Writes the block's FP64 row sums acc64[k][i] (k < NACC).
+__global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
+                                                      const double* __restrict__ c64,
+                                                      const double* __restrict__ org,
+                                                      const NodeRec* __restrict__ nodes, int H, int leaf,
+                                                      int64_t nF, const float4* __restrict__ balls, float theta,
+                                                      int64_t Fp, double* __restrict__ acc64,
+                                                      unsigned long long* __restrict__ stats) {
+    __shared__ int stack[FF_STACK];
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t i = b * 64 + lane;
+    const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
+    const ColRec me = cols[i];
+    const int4 mv = colv[i];
+    const float ax = (float)cxd, ay = (float)cyd, az = (float)czd;
+    const float4 tb = balls[b];
+    float hi[NACC], lo[NACC], acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
+    int cnt = 0;
+    const int64_t leaf0 = (int64_t)1 << H;
+    const int4 nov = make_int4(0, 0, 0, 0);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t n_far = 0, n_near_cols = 0, n_visit = 0;
+    if (lane == 0) stack[0] = 1;
+    int sz = 1;
+    while (sz > 0) {
+        const int n = sz < 64 ? sz : 64;
+        sz -= n;
+        const bool act = lane < n;
+        const int k = act ? stack[sz + lane] : 0;
+        NodeRec nd = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (act) nd = nodes[k];
+        n_visit += n;
+        const float dx = tb.x - nd.cx, dy = tb.y - nd.cy, dz = tb.z - nd.cz;
+        const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+        const bool valid = act && nd.a > 0.f;
+        const bool far = valid && (2.f * nd.r < theta * (dist - tb.w));
+        const bool isleaf = (int64_t)k >= leaf0;
+        bool open = valid && !far && !isleaf;
+        const int nopen = __popcll(__ballot(open));
+        const bool overflow = sz + 2 * nopen > FF_STACK;
+        if (overflow) open = false;
+        const bool near = valid && !far && !open;
+        // push children of opened nodes (right child below left, so the left is popped first)
+        if (!overflow) {
+            const uint64_t om = __ballot(open);
+            if (open) {
+                const int pos = sz + 2 * (int)__popcll(om & lt);
+                stack[pos] = 2 * k + 1;
+                stack[pos + 1] = 2 * k;
+            }
+            sz += 2 * nopen;
+        }
+        // far clusters
+        uint64_t fm = __ballot(far);
+        n_far += (uint32_t)__popcll(fm);
+        while (fm) {
+            const int l = (int)__builtin_ctzll(fm);
+            fm &= fm - 1;
+            const ColRec cr = {lane_f(nd.cx, l), lane_f(nd.cy, l), lane_f(nd.cz, l), lane_f(nd.a, l),
+                               lane_f(nd.nx, l), lane_f(nd.ny, l), lane_f(nd.nz, l), 0.f};
+            ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        }
+        // near nodes (leaves, or nodes that could not be opened): exact pairs over their faces
+        uint64_t nm = __ballot(near);
+        while (nm) {
+            const int l = (int)__builtin_ctzll(nm);
+            nm &= nm - 1;
+            const int64_t kk = (int64_t)__builtin_amdgcn_readlane(k, l);
+            int lev = 63 - __builtin_clzll((unsigned long long)kk);
+            const int64_t span = (int64_t)1 << (H - lev);
+            const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
+            const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
+            if (f0 < f1) {
+                n_near_cols += (uint32_t)(f1 - f0);
+                ff_near_range(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+            }
+        }
+    }
+    ff_fold(acc, hi, lo);
+#pragma unroll
+    for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] = (double)hi[kk] - (double)lo[kk];
+    // interaction counts of this target block (per row): far clusters, near columns, visited nodes
+    if (lane == 0 && stats) {
+        atomicAdd(&stats[0], (unsigned long long)n_far);
+        atomicAdd(&stats[1], (unsigned long long)n_near_cols);
+        atomicAdd(&stats[2], (unsigned long long)n_visit);
+        atomicAdd(&stats[3], 1ull);
+    }
+}
+
+// ---- k-d ordering of the faces (tree build) -------------------------------------------------------
+// The faces are ordered so that every node of the implicit complete binary tree is a compact
+// piece of the surface: level by level, the faces of each node are sorted along the longest axis
+// of the node's centroid bounding box; the node's first child then takes the lower part (its leaf
+// capacity) and the second child the rest.  This is a balanced k-d (median-like) split on face
+// centroids, done with one stable radix sort per level on (node index, quantised coordinate).
+
+__global__ void kd_centroids(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F, int64_t nF,
+                             float4* __restrict__ cen, uint32_t* __restrict__ perm) {
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    const int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a >= 0 && a < V && b >= 0 && b < V && c >= 0 && c < V) {
+        const double x = (X[3 * (int64_t)a] + X[3 * (int64_t)b] + X[3 * (int64_t)c]) / 3.0;
+        const double y = (X[3 * (int64_t)a + 1] + X[3 * (int64_t)b + 1] + X[3 * (int64_t)c + 1]) / 3.0;
+        const double z = (X[3 * (int64_t)a + 2] + X[3 * (int64_t)b + 2] + X[3 * (int64_t)c + 2]) / 3.0;
+        if (isfinite(x + y + z)) r = make_float4((float)x, (float)y, (float)z, 0.f);
+    }
+    cen[f] = r;
+    perm[f] = (uint32_t)f;
+}
+
+__device__ __forceinline__ uint32_t f2o(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void kd_box_init(uint32_t* __restrict__ nb, int64_t nnodes) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < nnodes * 6) nb[t] = (t % 6) < 3 ? 0xffffffffu : 0u;
+}
+
+// Centroid bounding box of every node of `level` (min xyz, max xyz in the order-preserving encoding).
+__global__ void kd_node_bbox(const uint32_t* __restrict__ perm, const float4* __restrict__ cen, int64_t nF,
+                             int64_t node_faces, uint32_t* __restrict__ nb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool act = i < nF;
+    const int64_t j = act ? i / node_faces : -1;
+    float4 c = act ? cen[perm[i]] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t j0 = __shfl(j, __builtin_ctzll(__ballot(act) | (1ull << 63)));
+    const bool uniform = __ballot(act && j != j0) == 0ull;
+    if (uniform) {
+        float mn[3] = {act ? c.x : INFINITY, act ? c.y : INFINITY, act ? c.z : INFINITY};
+        float mx[3] = {act ? c.x : -INFINITY, act ? c.y : -INFINITY, act ? c.z : -INFINITY};
+        for (int d = 0; d < 3; ++d)
+            for (int off = 32; off > 0; off >>= 1) {
+                mn[d] = fminf(mn[d], __shfl_xor(mn[d], off));
+                mx[d] = fmaxf(mx[d], __shfl_xor(mx[d], off));
+            }
+        if ((threadIdx.x & 63) == 0 && j0 >= 0)
+            for (int d = 0; d < 3; ++d) {
+                atomicMin(&nb[6 * j0 + d], f2o(mn[d]));
+                atomicMax(&nb[6 * j0 + 3 + d], f2o(mx[d]));
+            }
+    } else if (act) {
+        const float v[3] = {c.x, c.y, c.z};
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&nb[6 * j + d], f2o(v[d]));
+            atomicMax(&nb[6 * j + 3 + d], f2o(v[d]));
+        }
+    }
+}
+
+// key = (node index << qbits) | coordinate along the node's longest axis quantised to qbits.
+__global__ void kd_keys(const uint32_t* __restrict__ perm, const float4* __restrict__ cen, int64_t nF,
+                        int64_t node_faces, const uint32_t* __restrict__ nb, int qbits, uint32_t* __restrict__ keys) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    const int64_t j = i / node_faces;
+    const float4 c = cen[perm[i]];
+    float lo[3], ext[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = ordered_to_float(nb[6 * j + d]);
+        ext[d] = ordered_to_float(nb[6 * j + 3 + d]) - lo[d];
+    }
+    int ax = 0;
+    if (ext[1] > ext[ax]) ax = 1;
+    if (ext[2] > ext[ax]) ax = 2;
+    const float v = ax == 0 ? c.x : (ax == 1 ? c.y : c.z);
+    const float maxq = (float)((1u << qbits) - 1u);
+    float s = ext[ax] > 0.f ? (v - lo[ax]) / ext[ax] * maxq : 0.f;
+    s = fminf(fmaxf(s, 0.f), maxq);
+    const uint32_t q = isfinite(s) ? (uint32_t)s : 0u;
+    keys[i] = ((uint32_t)j << qbits) | q;
+}
+
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
+                      uint32_t* hist, uint32_t* off, hipStream_t st);
+
+// perm (nF entries) <- k-d order of the faces for a tree of height H over leaves of `leaf` faces.
+// Scratch: cen (nF float4), nb (6 * 2^max(H-1,0) words), keys/ktmp/vtmp (nF words), hist/off.
+hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, int H, float4* cen,
+                          uint32_t* nb, uint32_t* perm, uint32_t* keys, uint32_t* ktmp, uint32_t* vtmp,
+                          uint32_t* hist, uint32_t* off, hipStream_t st) {
+    const unsigned g = (unsigned)((nF + 255) / 256);
+    hipLaunchKernelGGL(kd_centroids, dim3(g), dim3(256), 0, st, X, V, F, nF, cen, perm);
+    for (int level = 0; level < H; ++level) {
+        const int64_t nnodes = (int64_t)1 << level;
+        const int64_t node_faces = ((int64_t)1 << (H - level)) * leaf;
+        hipLaunchKernelGGL(kd_box_init, dim3((unsigned)((nnodes * 6 + 255) / 256)), dim3(256), 0, st, nb, nnodes);
+        hipLaunchKernelGGL(kd_node_bbox, dim3(g), dim3(256), 0, st, perm, cen, nF, node_faces, nb);
+        const int qbits = std::min(16, 32 - level);
+        hipLaunchKernelGGL(kd_keys, dim3(g), dim3(256), 0, st, perm, cen, nF, node_faces, nb, qbits, keys);
+        hipError_t e = radix_sort(keys, perm, ktmp, vtmp, nF, level + qbits, hist, off, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// ---- host side ----------------------------------------------------------------------------------
+
+int tree_height(int64_t nF, int leaf) {
+    const int64_t nleaf = (nF + leaf - 1) / leaf;
+    int H = 0;
+    while (((int64_t)1 << H) < nleaf) ++H;
+    return H;
+}
+
+size_t tree_node_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeF64); }
+size_t tree_rec_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeRec); }
+
+hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
+                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
+                               hipStream_t st) {
+    NodeF64* n = (NodeF64*)nodes64;
+    NodeRec* r = (NodeRec*)recs;
+    const int64_t nslot = (int64_t)1 << H;
+    hipLaunchKernelGGL(leaf_moments, dim3((unsigned)((nslot + 127) / 128)), dim3(128), 0, st, c64, geo, colv, X, bbox,
+                       nF, leaf, H, n, r);
+    for (int l = H - 1; l >= 0; --l) {
+        const int64_t cnt = (int64_t)1 << l;
+        hipLaunchKernelGGL(internal_moments, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, l, n, r);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                           const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
+                           int64_t Fp, float theta, float4* balls, double* acc64, unsigned long long* stats,
+                           hipStream_t st) {
+    const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
+    hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
+    hipLaunchKernelGGL(farfield_kernel, dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org,
+                       (const NodeRec*)recs, H, leaf, nF, balls, theta, Fp, acc64, stats);
+    return hipGetLastError();
+}
+
+}  // namespace tpe

@@ -1,0 +1,118 @@
+"""autograd.Function with the hand-written backward, and the explicit gradient flow."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+SCALE = 1e-4 / 6  # rho / alpha of the paper
+
+
+def test_autograd_backward_matches_oracle():
+    T = tpe()
+    c = M.make_config("C1")
+    Eo, Go = oracle.gradient(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    X = Xd.clone().requires_grad_(True)
+    E = T.tpe_energy(X, Fd)
+    (3.0 * E * E).backward()
+    G = X.grad.cpu().numpy() / (6.0 * float(E.detach().cpu()))
+    assert rel_energy(float(E.detach().cpu()), Eo) <= 1e-6
+    assert rel_grad_maxnorm(G, Go) <= 1e-5
+
+
+def test_autograd_directional_finite_differences():
+    """<dE/dX, v> against a central difference of the GPU energy along random directions."""
+    T = tpe()
+    import torch
+    X0, F = M.icosphere(2)
+    X0, _, _ = M.bump(X0, 0, 0.3, 0.2)
+    Xd, Fd = upload(X0, F)
+    X = Xd.clone().requires_grad_(True)
+    E = T.tpe_energy(X, Fd)
+    E.backward()
+    g = X.grad
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        v = torch.from_numpy(rng.normal(size=X0.shape)).cuda()
+        h = 1e-4
+        fd = (float(T.energy(Xd + h * v, Fd)) - float(T.energy(Xd - h * v, Fd))) / (2 * h)
+        an = float((g * v).sum())
+        log("directional", an, fd)
+        assert abs(fd - an) <= 2e-3 * abs(an) + 1e-9
+
+
+def test_autograd_farfield_recomputes_moments():
+    T = tpe()
+    c = M.make_config("C1")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    X = Xd.clone().requires_grad_(True)
+    E = T.tpe_energy(X, Fd, tree=tree, theta=0.0)
+    E.backward()
+    Eo, Go = oracle.gradient(c.X, c.F)
+    assert rel_grad_maxnorm(X.grad.cpu().numpy(), Go) <= 1e-5
+
+
+def _oracle_flow(X, F, steps, dt):
+    X = X.copy()
+    Es = []
+    for _ in range(steps):
+        E, G = oracle.gradient(X, F, scale=SCALE)
+        Es.append(E)
+        X -= dt * G
+    return X, Es
+
+
+def test_gradient_flow_trajectory_vs_oracle():
+    """20 explicit steps, dt = 1e-5, on a level-4 bump with a 0.02 gap: GPU vs oracle trajectory."""
+    from paper_2509_22110_amd.flow import gradient_flow
+    X0, F = M.icosphere(4)
+    X0, D, gap = M.bump(X0, 0, 0.3, 0.02)
+    Xo, Eo = _oracle_flow(X0, F, 20, 1e-5)
+    Xd, Fd = upload(X0, F)
+    rec = gradient_flow(Xd, Fd, 20, 1e-5, scale=SCALE)
+    Xg = Xd.cpu().numpy()
+    disp = np.abs(Xo - X0).max()
+    dev = np.abs(Xg - Xo).max()
+    log("flow: max displacement", disp, "gpu-oracle deviation", dev, "E0", Eo[0], "E19", Eo[-1])
+    assert disp > 1e-4  # the flow actually moves the surface
+    assert dev <= 1e-5 * disp
+    for a, b in zip(rec.energies, Eo):
+        assert rel_energy(a, b) <= 1e-6
+    assert all(b < a for a, b in zip(Eo, Eo[1:]))
+
+
+def test_gradient_flow_c3_sampled():
+    """Level-6 bump at gap 0.02 (the self-approaching workload): 20 GPU steps; energy decreases
+    monotonically and the end state matches the oracle's energy and sampled gradients."""
+    from paper_2509_22110_amd.flow import gradient_flow
+    T = tpe()
+    c = M.make_config("C3")
+    Xd, Fd = upload(c.X, c.F)
+    rec = gradient_flow(Xd, Fd, 20, 1e-5, scale=SCALE)
+    assert all(b < a for a, b in zip(rec.energies, rec.energies[1:]))
+    X = Xd.cpu().numpy()
+    E, G = T.gradient(Xd, Fd, scale=SCALE)
+    Eo = oracle.energy(X, c.F, scale=SCALE)
+    G = G.cpu().numpy()
+    verts = np.argsort(-np.abs(G).max(1))[:8].astype(np.int32)
+    Go = oracle.gradient_at(X, c.F, verts, scale=SCALE)
+    eG = float(np.abs(G[verts] - Go).max() / np.abs(Go).max())
+    log("C3 flow: E", rec.energies[0], "->", rec.energies[-1], "rel E end", rel_energy(float(E.cpu()), Eo), "rel G", eG)
+    assert rel_energy(float(E.cpu()), Eo) <= 1e-6
+    assert eG <= 1e-5
+
+
+def test_flow_with_farfield_judge():
+    from paper_2509_22110_amd.flow import gradient_flow
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    rec = gradient_flow(Xd, Fd, 10, 1e-3, scale=SCALE, tree=tree, theta=0.5, judge_every=5)
+    log("far-field flow judge", rec.judge)
+    assert len(rec.judge) == 2 and all(e < 0.5 for _, e in rec.judge)

@@ -1,0 +1,106 @@
+"""Far field (tpe_build_tree + tpe_farfield) against the exact path and the FP64 oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.mark.parametrize("leaf", [1, 7, 32])
+def test_theta_zero_is_exact(leaf):
+    """Nothing is admissible at theta = 0: every pair is evaluated exactly."""
+    T = tpe()
+    c = M.make_config("C1")
+    Eo, Go = oracle.gradient(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd, leaf=leaf)
+    E, G = T.farfield(tree, Xd, Fd, theta=0.0)
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("theta=0 leaf", leaf, "rel E", eE, "rel G", eG)
+    assert eE <= 1e-6 and eG <= 1e-5
+
+
+def test_error_decreases_with_theta():
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    E0, G0 = T.gradient(Xd, Fd)
+    E0 = float(E0.cpu()); G0 = G0.cpu().numpy()
+    tree = T.build_tree(Xd, Fd, leaf=32)
+    errs = []
+    for th in (0.5, 0.25, 0.1):
+        E, G = T.farfield(tree, Xd, Fd, theta=th)
+        errs.append((rel_energy(float(E.cpu()), E0), rel_grad_maxnorm(G.cpu().numpy(), G0)))
+        log("C2 theta", th, "rel E", errs[-1][0], "rel G", errs[-1][1])
+    assert errs[0][1] > errs[1][1] > errs[2][1]
+    assert errs[0][0] > errs[2][0]
+    assert errs[0][1] < 0.5  # monopole far field at theta = 0.5 is a rough but sane approximation
+
+
+def test_farfield_deterministic_and_tree_reuse():
+    T = tpe()
+    c = M.make_config("C1")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    E1, G1 = T.farfield(tree, Xd, Fd, theta=0.5)
+    E2, G2 = T.farfield(tree, Xd, Fd, theta=0.5)
+    assert float(E1.cpu()) == float(E2.cpu()) and np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+    # moments are refit from the positions passed in: a moved mesh with the old tree at theta=0
+    Xm = Xd * 1.5 + 0.25
+    E3, G3 = T.farfield(tree, Xm, Fd, theta=0.0)
+    E4, G4 = T.gradient(Xm, Fd)
+    assert rel_energy(float(E3.cpu()), float(E4.cpu())) <= 1e-6
+    assert rel_grad_maxnorm(G3.cpu().numpy(), G4.cpu().numpy()) <= 1e-5
+
+
+def test_farfield_errors():
+    T = tpe()
+    c = M.make_config("C1")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    X2, F2 = upload(*M.icosphere(2))
+    with pytest.raises(T.TPEError):
+        T.farfield(tree, X2, F2)  # tree built for another mesh
+    with pytest.raises(T.TPEError):
+        T.farfield(tree, Xd, Fd, theta=-1.0)
+    with pytest.raises(T.TPEError):
+        T.build_tree(Xd, Fd, leaf=0)
+
+
+def test_c4_far_field_vs_exact():
+    """Level-7 deformed sphere (327,680 faces): monopole far field at theta = 0.5 vs the exact GPU
+    path (itself checked against the oracle at sampled vertices).  Reports the speedup."""
+    T = tpe()
+    import torch
+    c = M.make_config("C4")
+    Xd, Fd = upload(c.X, c.F)
+    ctx = T.context(Xd.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E0, G0 = T.gradient(Xd, Fd)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    E0 = float(E0.cpu()); G0 = G0.cpu().numpy()
+    tree = T.build_tree(Xd, Fd, leaf=32)
+    T.farfield(tree, Xd, Fd, theta=0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, G = T.farfield(tree, Xd, Fd, theta=0.5)
+    torch.cuda.synchronize()
+    t_ff = time.perf_counter() - t0
+    eE, eG = rel_energy(float(E.cpu()), E0), rel_grad_maxnorm(G.cpu().numpy(), G0)
+    log(f"C4 exact {t_exact*1e3:.1f} ms, far field {t_ff*1e3:.2f} ms, speedup {t_exact/t_ff:.1f}x, "
+        f"rel E {eE:.3e}, rel G {eG:.3e}")
+    # the exact GPU gradient itself against the oracle at sampled vertices
+    verts = np.random.default_rng(1).choice(c.V, 6, replace=False).astype(np.int32)
+    Go = oracle.gradient_at(c.X, c.F, verts)
+    eS = float(np.abs(G0[verts] - Go).max() / np.abs(Go).max())
+    log("C4 exact vs oracle (sampled)", eS)
+    assert eS <= 1e-5
+    assert t_exact / t_ff > 5.0
+    assert eG < 0.5
