@@ -2,7 +2,7 @@
  * libtpe — discrete tangent-point energy and its vertex gradient on MI355X (gfx950).
  *
  * The energy follows the paper's definition of the tangent-point energy of a closed surface
- * (Sec. 2 "Self-avoidance", eq. (TP)): with the tangent-point radius
+ * (Sec. 2.2.2 "Self-avoidance", eq. (TP)): with the tangent-point radius
  * R(x,y) = |x-y|^2 / (2 |n(x).(x-y)|),  Phi = rho 2^-alpha / alpha  int_S int_S R^-alpha
  *       = rho / alpha  int_S int_S |n(x).(x-y)|^alpha / |x-y|^(2 alpha).
  * It is discretised on flat triangles with one quadrature point per face (the centroid), and
@@ -15,7 +15,7 @@
  * over ORDERED pairs (both orders, as the double integral counts them).  The paper's Phi is
  * q = alpha, p = 2 alpha, scale = rho / alpha (it uses alpha = 6, rho = 1e-4).  The gradient is
  * dE/dX, i.e. the deformation derivative of eq. (dTP) for the discrete surface, evaluated in the
- * reordered form eq. (dTP_reordered) (Sec. 3.3): each face collects its own inner integrals
+ * reordered form eq. (dTP_reordered) (Sec. 3.2): each face collects its own inner integrals
  * and no pair writes into another face.  The self-avoidance force is -dE/dX.
  *
  * Conventions for every call below:
@@ -103,7 +103,7 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
 
-/* Build the cluster tree used by tpe_farfield (paper Sec. 3.3: the inner integrals are clustered
+/* Build the cluster tree used by tpe_farfield (paper Sec. 3.2: the inner integrals are clustered
  * with precomputed averages over patches of elements, Barnes-Hut style).  The tree is an implicit
  * complete binary tree over leaves of `leaf_size` consecutive faces (1..4096; 32 in the
  * paper-scale workloads); the faces are ordered top-down so that each node's faces are split
@@ -119,7 +119,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
 /* Free a tree. */
 int tpe_tree_destroy(tpe_tree* tree);
 
-/* Barnes-Hut approximation of E and dE/dX on the tree (paper Sec. 3.3, clustering of the inner
+/* Barnes-Hut approximation of E and dE/dX on the tree (paper Sec. 3.2, clustering of the inner
  * integrals of eq. (dTP_reordered)).  Every block of 64 consecutive faces in tree order is
  * enclosed by a ball (C_T, r_T); a cluster B with area A_B, area-weighted centroid C_B, unit
  * mean normal N_B and vertex-bounding radius r_B is far when 2 r_B < theta (|C_T - C_B| - r_T)

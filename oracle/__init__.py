@@ -5,7 +5,7 @@ of ``bench.py``.  The library's product path never imports, links or calls anyth
 
 The arithmetic lives in ``tpe_oracle.c`` (plain C, FP64, OpenMP over rows); this module builds it with
 gcc and calls it through ctypes on NumPy arrays.  See ``tpe_oracle.c`` for the definition it follows
-(paper Sec. 2, eq. (TP), one-point centroid quadrature on flat triangles, ordered pairs of faces that
+(paper Sec. 2.2.2, eq. (TP), one-point centroid quadrature on flat triangles, ordered pairs of faces that
 share no vertex) and for the gradient's chain rule.
 
 Parity pins: closed forms (two-triangle example, sphere limit), exact identities (scaling law, Euler

@@ -6,7 +6,7 @@
  * can compare the HIP implementation against a plain, slow, obviously correct evaluation of
  * the definition.  It shares no code, header, table or helper with the HIP library.
  *
- * What it computes (paper, Sec. 2 "Self-avoidance", eq. (TP), with one-point centroid
+ * What it computes (paper, Sec. 2.2.2 "Self-avoidance", eq. (TP), with one-point centroid
  * quadrature on flat triangles):
  *
  *   For each face T = (i, j, k):  w_T = (x_j - x_i) x (x_k - x_i),  a_T = |w_T| / 2,

@@ -5,7 +5,7 @@
 // With the row sums of pair.hip (K, S0, Sd, Sdd, Sn) for face S and the kernel k = t^q with
 // p = 2q, the partial derivatives of E with respect to the face's own geometry are
 //     dE/da_S = K,   dE/dn_S = q a_S Sd,   dE/dc_S = a_S (q (n_S S0 + Sn) - p Sdd),
-// which are the paper's inner integrals f_K, f_nu and f (Sec. 3.3, eq. (dTP_reordered)) at the
+// which are the paper's inner integrals f_K, f_nu and f (Sec. 3.2, eq. (dTP_reordered)) at the
 // face's quadrature point.  They reach the vertices through w = (x_j - x_i) x (x_k - x_i):
 //     g_w = (dE/da) n / 2 + (I - n n^T) (dE/dn) / |w|,
 //     dE/dx_i = (dE/dc)/3 + (x_j - x_k) x g_w      (and cyclically for j, k).

@@ -1,9 +1,9 @@
 // Exact all-pairs triangle-pair kernel for the tangent-point energy and its per-face adjoint sums.
 //
-// Definition (paper Sec. 2, eq. (TP), one-point centroid quadrature on flat triangles): for an
+// Definition (paper Sec. 2.2.2, eq. (TP), one-point centroid quadrature on flat triangles): for an
 // ordered pair of faces (S, T) sharing no vertex, with d = c_S - c_T, w = 1/|d|^2,
 //     k(S,T) = |n_S . d|^q / |d|^p = t^q,   t = (n_S . d) w       (the fast path has p = 2q).
-// The reordered derivative (paper Sec. 3.3, eq. (dTP_reordered)) evaluates the inner integrals as
+// The reordered derivative (paper Sec. 3.2, eq. (dTP_reordered)) evaluates the inner integrals as
 // functions of the outer point only, so every row face S can collect everything its own gradient
 // needs from a loop over columns T, with no writes to other faces.  With tau = (n_T . d) w,
 // s = a_T t^(q-1) w,  s' = a_T tau^(q-1) w  the row sums are

@@ -1,7 +1,7 @@
 // Geometry preparation, spatial (Morton) ordering, vertex->corner adjacency and the tile-pair
 // exclusion map.
 //
-// Per face T = (i, j, k) (paper Sec. 3.3: positions, area elements and normals are cached per
+// Per face T = (i, j, k) (paper Sec. 3.2: positions, area elements and normals are cached per
 // quadrature point, contiguously, and iterated in memory order):
 //     w = (x_j - x_i) x (x_k - x_i),  a = |w|/2,  n = w/|w|,  c = (x_i + x_j + x_k)/3   (FP64)
 // Faces are reordered along a 30-bit Morton curve of their centroids so that a tile of 256

@@ -1,6 +1,6 @@
 // Cluster tree over Morton-ordered faces and the Barnes-Hut far field of the inner integrals.
 //
-// The paper clusters only the inner integrals f_K, f_nu, f of eq. (dTP_reordered) (Sec. 3.3): for
+// The paper clusters only the inner integrals f_K, f_nu, f of eq. (dTP_reordered) (Sec. 3.2): for
 // an outer point x, the contribution of a patch of faces far enough from x is replaced by one
 // evaluation with precomputed averages over the patch, and no derivative has to be propagated
 // back to the patch because the test function only appears in the outer integral.  Here:

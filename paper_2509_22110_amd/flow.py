@@ -1,6 +1,6 @@
 """Explicit gradient flow X <- X - dt dE/dX driven by the library's gradient.
 
-The paper treats the tangent-point force explicitly in time (Sec. 3.3: an implicit treatment
+The paper treats the tangent-point force explicitly in time (Sec. 3.2: an implicit treatment
 would need a dense system).  This harness takes plain explicit Euler steps of the energy's
 gradient flow, with the exact gradient or the far field, and can judge the far field every k
 steps against the exact gradient.  The update itself is one in-place device axpy.

@@ -1,7 +1,7 @@
 """Pins of the FP64 CPU oracle against what the definition and mathematics fix (no GPU).
 
 The oracle evaluates the one-point centroid quadrature of the paper's tangent-point energy
-(Sec. 2, eq. (TP)) over ordered face pairs sharing no vertex, and its exact vertex gradient.
+(Sec. 2.2.2, eq. (TP)) over ordered face pairs sharing no vertex, and its exact vertex gradient.
 Each test below checks it against something other than itself: closed forms, exact identities
 (homogeneity, rigid-motion invariance), brute-force counts and central finite differences.
 """
@@ -101,7 +101,7 @@ def test_flat_mesh_is_zero():
 
 
 def test_sphere_limit_convergence():
-    """On a sphere of radius R the tangent-point radius is R everywhere (paper Sec. 2), so the
+    """On a sphere of radius R the tangent-point radius is R everywhere (paper Sec. 2.2.2), so the
     continuum energy with (q,p) = (6,12) is (2R)^-6 (4 pi R^2)^2 = pi^2 / (4 R^2).  The centroid
     quadrature on refined icospheres must converge to it monotonically at second order."""
     errs = []
