@@ -131,6 +131,68 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
                  const tpe_mlp* mlp, double* E_dev, double* G_dev);
 
+/* ---- learned far-field correction (not part of the paper) ------------------------------------
+ * A multilayer perceptron 32 -> 64 -> 64 -> 64 -> 16 (ReLU), evaluated and trained with BF16
+ * matrix-core (MFMA) products accumulated in FP32, with FP32 master weights and Adam.  Its inputs
+ * are 32 features of a (target face, far cluster) pair and its 16 outputs (7 used) correct the
+ * monopole's contribution to the face's row sums; see tpe_farfield_samples.  Parameters are one
+ * FP32 vector: W1[32][64], b1[64], W2[64][64], b2, W3[64][64], b3, W4[64][16], b4[16]. */
+
+/* Create a network with He-uniform weights drawn from a 64-bit Mersenne twister seeded with
+ * `seed` and zero biases.  Only (d_in, width, depth, d_out) = (32, 64, 3, 16) is implemented
+ * (TPE_ERR_UNSUPPORTED otherwise).  *out is owned by the caller (tpe_mlp_destroy). */
+int tpe_mlp_create(tpe_ctx* ctx, int32_t d_in, int32_t width, int32_t depth, int32_t d_out,
+                   uint64_t seed, tpe_mlp** out);
+int tpe_mlp_destroy(tpe_mlp* mlp);
+/* Number of FP32 parameters (11,472), or -1 for NULL. */
+int64_t tpe_mlp_num_params(const tpe_mlp* mlp);
+/* Copy the FP32 parameters to / from a host array of exactly tpe_mlp_num_params floats.
+ * Synchronise the stream. */
+int tpe_mlp_get_params(tpe_ctx* ctx, const tpe_mlp* mlp, float* host, int64_t n);
+int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* mlp, const float* host, int64_t n);
+/* tpe_farfield applies the correction only to far clusters with r_B / rho >= min_s (default 0:
+ * all); rho = |c_S - C_B|.  Stored with the network (not in checkpoints). */
+int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* mlp, float min_s);
+/* out (device f32 [n][16]) <- network(feats (device f32 [n][32])). */
+int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* mlp, const float* feats, int64_t n, float* out);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr > 0) on the batch feats (device
+ * f32 [n][32]) / targets (device f32 [n][16]: columns 0..6 are targets, column 15 the sample
+ * weight, 0 = unused row) for the loss sum_i w_i sum_{j<7} (y_ij - t_ij)^2 / (7 sum_i w_i);
+ * loss_dev (device f32, nullable) receives the batch loss before the update. */
+int tpe_mlp_train_step(tpe_ctx* ctx, tpe_mlp* mlp, const float* feats, const float* targets,
+                       int64_t n, float lr, float* loss_dev);
+/* grad_dev (device f32 [num_params]) <- d loss / d parameters on the batch, without updating
+ * (a hook for checking the hand-written backward pass). */
+int tpe_mlp_gradient(tpe_ctx* ctx, tpe_mlp* mlp, const float* feats, const float* targets,
+                     int64_t n, float* grad_dev);
+/* Checkpoint: magic "TPEMLP01", int32 dims[4], int64 Adam step, then parameters, first and
+ * second Adam moments (FP32 each).  Training resumes exactly from a loaded checkpoint. */
+int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* mlp, const char* path);
+int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out);
+
+/* Training samples for the learned correction, drawn with the same tree walk as tpe_farfield at
+ * opening parameter theta.  A far cluster with at most max_cluster_faces faces is selected with
+ * probability ~select_prob (a hash of seed, target block and node; deterministic), up to `quota`
+ * clusters per target block of 64 faces; each selected (block, cluster) yields one sample per face
+ * of the block:
+ *   feats   (device f32, rows x 32): features of the (face, cluster) pair in a local frame
+ *           e1 = unit(c_S - C_B), e2 = unit part of n_S orthogonal to e1, e3 = e1 x e2:
+ *           [4 r_B/rho, n_S.e1, n_S.e2, mean normal of B (3), |N_B|/A_B, 16 M2c/(A_B rho^2) (6),
+ *            M2n/A_B (6), 0 x 13], rho = |c_S - C_B|, M2c / M2n the area-weighted second moments
+ *           of centroid offsets and of normals;
+ *   targets (device f32, rows x 16): the exact sum over B's faces minus the monopole of the
+ *           quantities the face's gradient is made of: K (dE/da), Sd[3] (dE/dn) and the net
+ *           C[3] = q (n_S S0 + Sn) - p Sdd (dE/dc), vectors in the frame, divided by
+ *           A_B rho^-6 (K, Sd) or A_B rho^-7 (C); columns 7..14 zero; column 15 = weight
+ *           (1, or 0 for an unused row).
+ * rows = ceil(nF / 64) * quota * 64; the caller allocates the outputs.  If mlp is not NULL, pred
+ * (device f32, rows x 16) receives the network's output for each sample computed by the same
+ * in-walk (fused) inference tpe_farfield uses; otherwise pred must be NULL. */
+int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
+                         const int32_t* F, int64_t nF, double theta, uint64_t seed, double select_prob,
+                         int32_t quota, int64_t max_cluster_faces, const tpe_mlp* mlp, float* feats,
+                         float* targets, float* pred);
+
 /* Interaction counts of the last tpe_farfield call on this context, summed over target blocks of
  * 64 faces (each count applies to every face of a block): out_host[0] = far clusters evaluated,
  * [1] = near columns evaluated exactly, [2] = tree nodes visited, [3] = target blocks.  Host

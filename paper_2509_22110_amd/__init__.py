@@ -18,7 +18,7 @@ import threading
 import torch
 
 __all__ = ["TPEError", "lib", "energy", "gradient", "pair_count", "TPEFunction", "tpe_energy",
-           "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield"]
+           "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield", "MLP"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtpe.so")
 
@@ -68,6 +68,20 @@ def lib():
             "tpe_tree_destroy": ([P], I),
             "tpe_farfield": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
             "tpe_farfield_stats": ([P, ctypes.POINTER(I64)], I),
+            "tpe_farfield_samples": ([P, P, P, I64, P, I64, D, ctypes.c_uint64, D, ctypes.c_int32, I64, P, P, P, P],
+                                     I),
+            "tpe_mlp_create": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_uint64, ctypes.POINTER(P)], I),
+            "tpe_mlp_destroy": ([P], I),
+            "tpe_mlp_num_params": ([P], I64),
+            "tpe_mlp_get_params": ([P, P, P, I64], I),
+            "tpe_mlp_set_params": ([P, P, P, I64], I),
+            "tpe_mlp_forward": ([P, P, P, I64, P], I),
+            "tpe_mlp_set_gate": ([P, P, ctypes.c_float], I),
+            "tpe_mlp_train_step": ([P, P, P, P, I64, ctypes.c_float, P], I),
+            "tpe_mlp_gradient": ([P, P, P, P, I64, P], I),
+            "tpe_mlp_save": ([P, P, ctypes.c_char_p], I),
+            "tpe_mlp_load": ([P, ctypes.c_char_p, ctypes.POINTER(P)], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -205,6 +219,102 @@ def farfield(tree: Tree, X, F, theta=0.5, q=6.0, p=12.0, scale=1.0, mlp=None, ou
                                float(p), float(scale), float(theta), mlp.h if mlp is not None else None,
                                E.data_ptr(), G.data_ptr() if G is not None else None))
     return E, G
+
+
+class MLP:
+    """Learned far-field correction network (see include/tpe.h, tpe_mlp_*)."""
+
+    def __init__(self, device=None, seed: int = 0, _handle=None):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        c = context(dev)
+        if _handle is None:
+            h = ctypes.c_void_p()
+            c.check(lib().tpe_mlp_create(c.h, 32, 64, 3, 16, int(seed), ctypes.byref(h)))
+            _handle = h
+        self.h = _handle
+        self.n_params = int(lib().tpe_mlp_num_params(self.h))
+
+    @classmethod
+    def load(cls, path: str, device=None):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        c = context(dev)
+        h = ctypes.c_void_p()
+        c.check(lib().tpe_mlp_load(c.h, path.encode(), ctypes.byref(h)))
+        return cls(dev, _handle=h)
+
+    def save(self, path: str):
+        c = context(self.device)
+        c.check(lib().tpe_mlp_save(c.h, self.h, path.encode()))
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.n_params, dtype=np.float32)
+        c = context(self.device)
+        c.check(lib().tpe_mlp_get_params(c.h, self.h, out.ctypes.data, self.n_params))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        c = context(self.device)
+        c.check(lib().tpe_mlp_set_params(c.h, self.h, p.ctypes.data, self.n_params))
+
+    def set_gate(self, min_s: float):
+        """Apply the far-field correction only to clusters with r_B / rho >= min_s."""
+        c = context(self.device)
+        c.check(lib().tpe_mlp_set_gate(c.h, self.h, float(min_s)))
+
+    def forward(self, feats):
+        feats = feats.contiguous()
+        assert feats.dtype == torch.float32 and feats.shape[1] == 32
+        out = torch.empty(feats.shape[0], 16, dtype=torch.float32, device=feats.device)
+        c = context(feats.device)
+        c.check(lib().tpe_mlp_forward(c.h, self.h, feats.data_ptr(), feats.shape[0], out.data_ptr()))
+        return out
+
+    def train_step(self, feats, targets, lr: float, loss_out=None):
+        feats, targets = feats.contiguous(), targets.contiguous()
+        loss = loss_out if loss_out is not None else torch.empty((), dtype=torch.float32, device=feats.device)
+        c = context(feats.device)
+        c.check(lib().tpe_mlp_train_step(c.h, self.h, feats.data_ptr(), targets.data_ptr(), feats.shape[0],
+                                         float(lr), loss.data_ptr()))
+        return loss
+
+    def gradient(self, feats, targets):
+        feats, targets = feats.contiguous(), targets.contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=feats.device)
+        c = context(feats.device)
+        c.check(lib().tpe_mlp_gradient(c.h, self.h, feats.data_ptr(), targets.data_ptr(), feats.shape[0],
+                                       g.data_ptr()))
+        return g
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.tpe_mlp_destroy(self.h)
+        except Exception:
+            pass
+
+
+def farfield_samples(tree: Tree, X, F, theta=0.5, seed=0, select_prob=0.05, quota=4, max_cluster_faces=4096,
+                     mlp=None):
+    """(feats [rows,32], targets [rows,16]) training samples for the learned correction; rows with
+    targets[:, 15] == 0 are unused.  With `mlp`, also the fused in-walk predictions [rows,16] as a
+    third element.  See tpe_farfield_samples."""
+    X, F = _check_mesh(X, F)
+    rows = ((F.shape[0] + 63) // 64) * quota * 64
+    feats = torch.empty(rows, 32, dtype=torch.float32, device=X.device)
+    targets = torch.empty(rows, 16, dtype=torch.float32, device=X.device)
+    pred = torch.empty(rows, 16, dtype=torch.float32, device=X.device) if mlp is not None else None
+    c = context(X.device)
+    c.check(lib().tpe_farfield_samples(c.h, tree.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
+                                       float(theta), int(seed), float(select_prob), int(quota),
+                                       int(max_cluster_faces), mlp.h if mlp is not None else None,
+                                       feats.data_ptr(), targets.data_ptr(),
+                                       pred.data_ptr() if pred is not None else None))
+    return (feats, targets) if mlp is None else (feats, targets, pred)
 
 
 def pair_count(F, V: int) -> int:

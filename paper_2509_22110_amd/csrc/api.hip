@@ -15,6 +15,7 @@
 
 #include "../../include/tpe.h"
 #include "common.hpp"
+#include "mlp.hpp"
 
 namespace tpe {
 hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
@@ -55,10 +56,14 @@ size_t tree_rec_bytes(int H);
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
                                const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
                                hipStream_t st);
+hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const double* c64, const double* X,
+                                  const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF, float theta,
+                                  uint32_t seed, uint32_t sel, int quota, int64_t max_faces, float4* balls,
+                                  float* feats, float* targets, const void* mlp_packed, float* pred, hipStream_t st);
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
-                           int64_t Fp, float theta, float4* balls, double* acc64, unsigned long long* stats,
-                           hipStream_t st);
+                           int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
+                           unsigned long long* stats, hipStream_t st);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -121,6 +126,19 @@ struct tpe_ctx {
     bool kernel_timing = false;
     std::vector<hipEvent_t> ev_pool;  // pairs (start, stop), reused
     size_t ev_used = 0;               // events recorded since the last tpe_kernel_time
+};
+
+struct tpe_mlp {
+    int device = 0;
+    int64_t step = 0;
+    float* P = nullptr;  // FP32 master parameters (device)
+    float* M = nullptr;  // Adam first moments
+    float* V = nullptr;  // Adam second moments
+    void* packed = nullptr;  // BF16 fragments + biases for inference (kept in sync with P)
+    float min_s = 0.f;       // apply the correction only to clusters with r_B / rho >= min_s
+    float* gpart = nullptr;  // per-tile gradient partials (grow-only)
+    float* lpart = nullptr;
+    int64_t cap_tiles = 0;
 };
 
 struct tpe_tree {
@@ -520,7 +538,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
-    if (mlp) return fail(ctx, TPE_ERR_UNSUPPORTED, "learned far-field correction not available");
+    if (mlp && mlp->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "MLP lives on another device");
     DeviceGuard dg(ctx->device);
     Plan P;
     plan(P, ctx, nF, V, true, tree->H);
@@ -540,11 +558,41 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     }
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 8, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
-                           (float)theta, P.balls, P.acc64, ctx->dstats, st));
+                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
     if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(launch_finalize(true, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
                            P.ticket, ctx->dflags, E_dev, st));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
+int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                         double theta, uint64_t seed, double select_prob, int32_t quota, int64_t max_cluster_faces,
+                         const tpe_mlp* mlp, float* feats, float* targets, float* pred) {
+    int rc = check_common(ctx, X, V, F, nF, 6.0, 12.0);
+    if (rc) return rc;
+    if (!tree || tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree/mesh mismatch");
+    if (!feats || !targets) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    if ((mlp == nullptr) != (pred == nullptr)) return fail(ctx, TPE_ERR_INVALID_ARG, "mlp and pred go together");
+    if (!(theta > 0.0) || !(select_prob >= 0.0 && select_prob <= 1.0) || quota < 1 || quota > 1024 ||
+        max_cluster_faces < 1)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "bad sampling parameters");
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    plan(P, ctx, nF, V, true, tree->H);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, true);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_records(X, V, F, nF, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                          ctx->dflags, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    const uint32_t sel = select_prob >= 1.0 ? 0xffffffffu : (uint32_t)(select_prob * 4294967296.0);
+    HIPCHK(launch_farfield_samples(P.cols, P.colv, P.c64, X, P.bbox, P.recs, tree->H, tree->leaf, nF, (float)theta,
+                                   (uint32_t)(seed ^ (seed >> 32)), sel, quota, max_cluster_faces, P.balls, feats,
+                                   targets, mlp ? mlp->packed : nullptr, pred, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
 }
@@ -557,6 +605,188 @@ int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host) {
     HIPCHK(hipMemcpyAsync(h, ctx->dstats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < 4; ++i) out_host[i] = (int64_t)h[i];
+    return TPE_OK;
+}
+
+// ---- learned far-field correction: MLP ------------------------------------------------------------
+
+static int mlp_alloc_parts(tpe_ctx* ctx, tpe_mlp* m, int64_t ntiles) {
+    if (ntiles <= m->cap_tiles) return TPE_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (m->gpart) (void)hipFree(m->gpart);
+    if (m->lpart) (void)hipFree(m->lpart);
+    m->gpart = m->lpart = nullptr;
+    m->cap_tiles = 0;
+    if (hipMalloc(&m->gpart, (size_t)ntiles * MLP_NPARAM * sizeof(float)) != hipSuccess ||
+        hipMalloc(&m->lpart, (size_t)ntiles * 2 * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, TPE_ERR_OOM, "MLP gradient partials");
+    }
+    m->cap_tiles = ntiles;
+    return TPE_OK;
+}
+
+int tpe_mlp_create(tpe_ctx* ctx, int32_t d_in, int32_t width, int32_t depth, int32_t d_out, uint64_t seed,
+                   tpe_mlp** out) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (d_in != MLP_DIN || width != MLP_W || depth != MLP_DEPTH || d_out != MLP_DOUT)
+        return fail(ctx, TPE_ERR_UNSUPPORTED, "only the 32-64-64-64-16 network is implemented");
+    DeviceGuard dg(ctx->device);
+    tpe_mlp* m = new tpe_mlp();
+    m->device = ctx->device;
+    const size_t bytes = MLP_NPARAM * sizeof(float);
+    if (hipMalloc(&m->P, bytes) != hipSuccess || hipMalloc(&m->M, bytes) != hipSuccess ||
+        hipMalloc(&m->V, bytes) != hipSuccess || hipMalloc(&m->packed, mlp_packed_bytes()) != hipSuccess) {
+        (void)hipGetLastError();
+        tpe_mlp_destroy(m);
+        return fail(ctx, TPE_ERR_OOM, "MLP parameters");
+    }
+    std::vector<float> P;
+    mlp_init_params(seed, P);
+    std::vector<float> z(MLP_NPARAM, 0.f);
+    hipError_t e = hipMemcpy(m->P, P.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->M, z.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->V, z.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = mlp_pack_launch(m->P, m->min_s, m->packed, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        tpe_mlp_destroy(m);
+        return hip_fail(ctx, e, "MLP init copy");
+    }
+    *out = m;
+    return TPE_OK;
+}
+
+int tpe_mlp_destroy(tpe_mlp* m) {
+    if (!m) return TPE_ERR_INVALID_ARG;
+    DeviceGuard dg(m->device);
+    for (float* p : {m->P, m->M, m->V, m->gpart, m->lpart})
+        if (p) (void)hipFree(p);
+    if (m->packed) (void)hipFree(m->packed);
+    delete m;
+    return TPE_OK;
+}
+
+int64_t tpe_mlp_num_params(const tpe_mlp* m) { return m ? MLP_NPARAM : -1; }
+
+int tpe_mlp_get_params(tpe_ctx* ctx, const tpe_mlp* m, float* host, int64_t n) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !host || n != MLP_NPARAM) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP parameter buffer");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(hipMemcpyAsync(host, m->P, n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TPE_OK;
+}
+
+int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* m, const float* host, int64_t n) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !host || n != MLP_NPARAM) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP parameter buffer");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(hipMemcpyAsync(m->P, host, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TPE_OK;
+}
+
+int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* m, float min_s) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !(min_s >= 0.f) || !std::isfinite(min_s)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad gate");
+    DeviceGuard dg(ctx->device);
+    m->min_s = min_s;
+    HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
+    return TPE_OK;
+}
+
+int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* m, const float* feats, int64_t n, float* out) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !feats || !out || n < 0) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP forward arguments");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(mlp_forward_launch(m->P, feats, n, out, ctx->stream));
+    return TPE_OK;
+}
+
+static int mlp_step(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* targets, int64_t n, float lr,
+                    float* loss_dev, float* grad_dev) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !feats || !targets || n < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP training arguments");
+    if (!grad_dev && !(lr > 0.f && std::isfinite(lr))) return fail(ctx, TPE_ERR_INVALID_ARG, "lr must be > 0");
+    DeviceGuard dg(ctx->device);
+    int rc = mlp_alloc_parts(ctx, m, mlp_tiles(n));
+    if (rc) return rc;
+    if (!grad_dev) ++m->step;
+    HIPCHK(mlp_train_launch(m->P, m->M, m->V, feats, targets, n, lr, m->step, m->gpart, m->lpart, loss_dev, grad_dev,
+                            ctx->stream));
+    if (!grad_dev) HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
+    return TPE_OK;
+}
+
+int tpe_mlp_train_step(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* targets, int64_t n, float lr,
+                       float* loss_dev) {
+    return mlp_step(ctx, m, feats, targets, n, lr, loss_dev, nullptr);
+}
+
+int tpe_mlp_gradient(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* targets, int64_t n,
+                     float* grad_dev) {
+    if (ctx && !grad_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null gradient output");
+    return mlp_step(ctx, m, feats, targets, n, 0.f, nullptr, grad_dev);
+}
+
+static const char MLP_MAGIC[8] = {'T', 'P', 'E', 'M', 'L', 'P', '0', '1'};
+
+int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* m, const char* path) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !path) return fail(ctx, TPE_ERR_INVALID_ARG, "bad save arguments");
+    DeviceGuard dg(ctx->device);
+    std::vector<float> buf(3 * (size_t)MLP_NPARAM);
+    HIPCHK(hipMemcpyAsync(buf.data(), m->P, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(buf.data() + MLP_NPARAM, m->M, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(buf.data() + 2 * MLP_NPARAM, m->V, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(ctx, TPE_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    const int32_t dims[4] = {MLP_DIN, MLP_W, MLP_DEPTH, MLP_DOUT};
+    const int64_t step = m->step;
+    bool ok = fwrite(MLP_MAGIC, 1, 8, f) == 8 && fwrite(dims, sizeof(dims), 1, f) == 1 &&
+              fwrite(&step, sizeof(step), 1, f) == 1 && fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? TPE_OK : fail(ctx, TPE_ERR_INVALID_ARG, std::string("write failed: ") + path);
+}
+
+int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!path || !out) return fail(ctx, TPE_ERR_INVALID_ARG, "bad load arguments");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(ctx, TPE_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t dims[4];
+    int64_t step = 0;
+    std::vector<float> buf(3 * (size_t)MLP_NPARAM);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, MLP_MAGIC, 8) == 0 && fread(dims, sizeof(dims), 1, f) == 1 &&
+              dims[0] == MLP_DIN && dims[1] == MLP_W && dims[2] == MLP_DEPTH && dims[3] == MLP_DOUT &&
+              fread(&step, sizeof(step), 1, f) == 1 && fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return fail(ctx, TPE_ERR_INVALID_ARG, std::string("not a valid MLP checkpoint: ") + path);
+    tpe_mlp* m = nullptr;
+    int rc = tpe_mlp_create(ctx, MLP_DIN, MLP_W, MLP_DEPTH, MLP_DOUT, 0, &m);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    hipError_t e = hipMemcpy(m->P, buf.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->M, buf.data() + MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->V, buf.data() + 2 * MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = mlp_pack_launch(m->P, m->min_s, m->packed, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        tpe_mlp_destroy(m);
+        return hip_fail(ctx, e, "MLP load copy");
+    }
+    m->step = step;
+    *out = m;
     return TPE_OK;
 }
 

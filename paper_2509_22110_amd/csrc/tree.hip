@@ -23,6 +23,8 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "mlp.hpp"
+#include "mlp_infer.hpp"
 
 namespace tpe {
 
@@ -38,6 +40,14 @@ struct __align__(32) NodeRec {
     float a, nx, ny, nz;  // area, unit mean normal
 };
 
+// FP32 moments for the learned correction's features: second moments of (c - C_B) and of n,
+// both divided by A_B, and the coherence |N_B| / A_B.
+struct __align__(16) NodeMom {
+    float m2c[6];
+    float m2n[6];
+    float coh, pad0, pad1, pad2;
+};
+
 __device__ __forceinline__ void sym_add_outer(double* m, double w, double x, double y, double z) {
     m[0] += w * x * x; m[1] += w * x * y; m[2] += w * x * z;
     m[3] += w * y * y; m[4] += w * y * z; m[5] += w * z * z;
@@ -46,6 +56,18 @@ __device__ __forceinline__ void sym_add_outer(double* m, double w, double x, dou
 __device__ __forceinline__ float round_up_f(double v) {
     float f = (float)v;
     return (double)f >= v ? f : nextafterf(f, INFINITY);
+}
+
+__device__ void write_mom(const NodeF64& n, NodeMom* mom) {
+    NodeMom m = {};
+    if (n.A > 0.0) {
+        for (int k = 0; k < 6; ++k) {
+            m.m2c[k] = (float)(n.m2c[k] / n.A);
+            m.m2n[k] = (float)(n.m2n[k] / n.A);
+        }
+        m.coh = (float)(sqrt(n.nx * n.nx + n.ny * n.ny + n.nz * n.nz) / n.A);
+    }
+    *mom = m;
 }
 
 __device__ void write_rec(const NodeF64& n, NodeRec* rec) {
@@ -66,7 +88,7 @@ __device__ void write_rec(const NodeF64& n, NodeRec* rec) {
 __global__ void leaf_moments(const double* __restrict__ c64, const double* __restrict__ geo,
                              const int4* __restrict__ colv, const double* __restrict__ X,
                              const uint32_t* __restrict__ bbox, int64_t nF, int leaf, int H,
-                             NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs) {
+                             NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs, NodeMom* __restrict__ moms) {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nslot = (int64_t)1 << H;
     if (j >= nslot) return;
@@ -98,10 +120,12 @@ __global__ void leaf_moments(const double* __restrict__ c64, const double* __res
     }
     nodes[nslot + j] = n;
     write_rec(n, &recs[nslot + j]);
+    write_mom(n, &moms[nslot + j]);
 }
 
 // Nodes of one level [2^l, 2^(l+1)) from their children.
-__global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs) {
+__global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs,
+                                 NodeMom* __restrict__ moms) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t first = (int64_t)1 << level;
     if (t >= first) return;
@@ -126,6 +150,7 @@ __global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec
     }
     nodes[k] = n;
     write_rec(n, &recs[k]);
+    write_mom(n, &moms[k]);
 }
 
 __device__ __forceinline__ double wave_sum_d(double x) {
@@ -248,7 +273,122 @@ __device__ __forceinline__ float lane_f(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
-constexpr int FF_STACK = 2048;  // LDS node stack per wave
+// ---- learned correction: features and training samples -----------------------------------------
+// For a target face S (centroid c_S, normal n_S) and a far cluster B, with D = c_S - C_B, rho = |D|:
+// local frame e1 = D / rho, e2 = unit part of n_S orthogonal to e1 (any orthogonal unit vector if
+// none), e3 = e1 x e2.  Features (dimensionless, rotation-invariant by construction):
+//   0: 4 r_B / rho            1, 2: n_S . e1, n_S . e2
+//   3-5: unit mean normal of B in the frame       6: coherence |N_B| / A_B
+//   7-12: M2c / (A_B r_B^2) in the frame (xx, xy, xz, yy, yz, zz)
+//   13-18: M2n / A_B in the frame                 19-31: 0
+// Outputs (7 used): the correction (exact sum over B minus monopole) of the quantities the face's
+// gradient is made of -- K (for dE/da and E), Sd (for dE/dn) and the net C = q (n_S S0 + Sn) - p Sdd
+// (for dE/dc) -- vectors in the frame, divided by their units u = A_B rho^-6 for K and Sd, and
+// A_B rho^-7 for C.  Predicting C itself (not S0, Sn, Sdd separately) keeps the near
+// cancellation between its terms out of the network's errors.
+struct Frame {
+    float e1[3], e2[3], e3[3];
+    float rho, s2;  // s2 = (r_B / rho)^2
+};
+
+__device__ __forceinline__ void quad_frame(const float* m, const Frame& f, float scale, float* out) {
+    // out = scale * (e_a . M e_b) for (a,b) in (11, 12, 13, 22, 23, 33); M symmetric (xx xy xz yy yz zz)
+    const float* E[3] = {f.e1, f.e2, f.e3};
+    float Me[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const float* e = E[a];
+        Me[a][0] = m[0] * e[0] + m[1] * e[1] + m[2] * e[2];
+        Me[a][1] = m[1] * e[0] + m[3] * e[1] + m[4] * e[2];
+        Me[a][2] = m[2] * e[0] + m[4] * e[1] + m[5] * e[2];
+    }
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int q = 0; q < 6; ++q) {
+        const float* e = E[pa[q]];
+        out[q] = scale * (e[0] * Me[pb[q]][0] + e[1] * Me[pb[q]][1] + e[2] * Me[pb[q]][2]);
+    }
+}
+
+__device__ __forceinline__ void ff_features(float ax, float ay, float az, float nx, float ny, float nz,
+                                            const NodeRec& nd, const NodeMom& mm, Frame& fr, float* x) {
+    float dx = ax - nd.cx, dy = ay - nd.cy, dz = az - nd.cz;
+    const float rho = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float ir = 1.f / rho;
+    fr.e1[0] = dx * ir; fr.e1[1] = dy * ir; fr.e1[2] = dz * ir;
+    const float c1 = nx * fr.e1[0] + ny * fr.e1[1] + nz * fr.e1[2];
+    float vx = nx - c1 * fr.e1[0], vy = ny - c1 * fr.e1[1], vz = nz - c1 * fr.e1[2];
+    float vn = sqrtf(vx * vx + vy * vy + vz * vz);
+    if (!(vn > 1e-6f)) {
+        // any unit vector orthogonal to e1
+        const float ux = fabsf(fr.e1[0]) < 0.9f ? 1.f : 0.f, uy = 1.f - ux;
+        const float pu = ux * fr.e1[0] + uy * fr.e1[1];
+        vx = ux - pu * fr.e1[0]; vy = uy - pu * fr.e1[1]; vz = -pu * fr.e1[2];
+        vn = sqrtf(vx * vx + vy * vy + vz * vz);
+    }
+    fr.e2[0] = vx / vn; fr.e2[1] = vy / vn; fr.e2[2] = vz / vn;
+    fr.e3[0] = fr.e1[1] * fr.e2[2] - fr.e1[2] * fr.e2[1];
+    fr.e3[1] = fr.e1[2] * fr.e2[0] - fr.e1[0] * fr.e2[2];
+    fr.e3[2] = fr.e1[0] * fr.e2[1] - fr.e1[1] * fr.e2[0];
+    fr.rho = rho;
+    const float s = nd.r * ir;
+    fr.s2 = s * s;
+    x[0] = 4.f * s;
+    x[1] = c1;
+    x[2] = nx * fr.e2[0] + ny * fr.e2[1] + nz * fr.e2[2];
+    x[3] = nd.nx * fr.e1[0] + nd.ny * fr.e1[1] + nd.nz * fr.e1[2];
+    x[4] = nd.nx * fr.e2[0] + nd.ny * fr.e2[1] + nd.nz * fr.e2[2];
+    x[5] = nd.nx * fr.e3[0] + nd.ny * fr.e3[1] + nd.nz * fr.e3[2];
+    x[6] = mm.coh;
+    quad_frame(mm.m2c, fr, nd.r > 0.f ? 1.f / (nd.r * nd.r) : 0.f, x + 7);
+    quad_frame(mm.m2n, fr, 1.f, x + 13);
+    for (int k = 19; k < 32; ++k) x[k] = 0.f;
+}
+
+// units of the outputs: u6 = A_B rho^-6 for K and Sd, u7 = u6 / rho for C (the magnitude of the
+// monopole's own contribution, so the loss measures error relative to it)
+__device__ __forceinline__ void out_units(float A, const Frame& fr, float& u6, float& u7) {
+    const float ir = 1.f / fr.rho;
+    const float r2 = ir * ir, r6 = r2 * r2 * r2;
+    u6 = A * r6;
+    u7 = u6 * ir;
+}
+
+// net dE/dc combination of the row sums, C = q (n_S S0 + Sn) - p Sdd  (q = 6, p = 12)
+__device__ __forceinline__ void net_c(const float* acc, float nx, float ny, float nz, float* c) {
+    c[0] = 6.f * (nx * acc[1] + acc[8]) - 12.f * acc[5];
+    c[1] = 6.f * (ny * acc[1] + acc[9]) - 12.f * acc[6];
+    c[2] = 6.f * (nz * acc[1] + acc[10]) - 12.f * acc[7];
+}
+
+// accumulator-space vector (global frame) -> frame components
+__device__ __forceinline__ void to_frame(const float* v, const Frame& fr, float* o) {
+    o[0] = v[0] * fr.e1[0] + v[1] * fr.e1[1] + v[2] * fr.e1[2];
+    o[1] = v[0] * fr.e2[0] + v[1] * fr.e2[1] + v[2] * fr.e2[2];
+    o[2] = v[0] * fr.e3[0] + v[1] * fr.e3[1] + v[2] * fr.e3[2];
+}
+
+// Learned correction of one far cluster for the wave's 64 rows: features per row, the MLP on the
+// 64 x 32 feature block (MFMA, LDS scratch), and the corrections added to the row sums.
+__device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, const NodeRec& cn, const NodeMom& mm,
+                                               float ax, float ay, float az, float nx, float ny, float nz,
+                                               MlpScratch& ms, float (&acc)[NACC]) {
+    Frame fr;
+    float x[32], y[16];
+    ff_features(ax, ay, az, nx, ny, nz, cn, mm, fr, x);
+    mlp_infer64(W, x, ms, y);
+    if (0.25f * x[0] < W->min_s) return;  // outside the gate (x[0] = 4 r_B / rho)
+    float u6, u7;
+    out_units(cn.a, fr, u6, u7);
+    acc[0] += u6 * y[0];
+    // dC enters through Sn: q * dSn = dC leaves S0 and Sdd untouched
+    const float u7q = u7 * (1.f / 6.f);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        acc[2 + d] += u6 * (y[1] * fr.e1[d] + y[2] * fr.e2[d] + y[3] * fr.e3[d]);
+        acc[8 + d] += u7q * (y[4] * fr.e1[d] + y[5] * fr.e2[d] + y[6] * fr.e3[d]);
+    }
+}
+
+constexpr int FF_STACK = 1024;  // LDS node stack per wave (overflow falls back to exact evaluation)
 
 // One wave per target block of 64 consecutive (tree-ordered) faces.  Batched depth-first walk of
 // the implicit tree: up to 64 nodes are popped at once (one per lane), tested in parallel, and then
@@ -258,14 +398,17 @@ constexpr int FF_STACK = 2048;  // LDS node stack per wave
 //   - other nodes push their two children;
 // if the stack could overflow, a node that would be opened is evaluated exactly instead (always
 // correct).  Writes the block's FP64 row sums acc64[k][i] (k < NACC).
+template <bool LEARNED>
 __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
                                                       const double* __restrict__ c64,
                                                       const double* __restrict__ org,
-                                                      const NodeRec* __restrict__ nodes, int H, int leaf,
-                                                      int64_t nF, const float4* __restrict__ balls, float theta,
-                                                      int64_t Fp, double* __restrict__ acc64,
+                                                      const NodeRec* __restrict__ nodes,
+                                                      const NodeMom* __restrict__ moms, const MlpPacked* __restrict__ W,
+                                                      int H, int leaf, int64_t nF, const float4* __restrict__ balls,
+                                                      float theta, int64_t Fp, double* __restrict__ acc64,
                                                       unsigned long long* __restrict__ stats) {
     __shared__ int stack[FF_STACK];
+    __shared__ MlpScratch ms;
     const int lane = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int64_t i = b * 64 + lane;
@@ -321,6 +464,11 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
             const ColRec cr = {lane_f(nd.cx, l), lane_f(nd.cy, l), lane_f(nd.cz, l), lane_f(nd.a, l),
                                lane_f(nd.nx, l), lane_f(nd.ny, l), lane_f(nd.nz, l), 0.f};
             ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+            if constexpr (LEARNED) {
+                const int kk = __builtin_amdgcn_readlane(k, l);
+                const NodeRec cn = {cr.cx, cr.cy, cr.cz, lane_f(nd.r, l), cr.a, cr.nx, cr.ny, cr.nz};
+                mlp_correction(W, cn, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms, acc);
+            }
             if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
         }
         // near nodes (leaves, or nodes that could not be opened): exact pairs over their faces
@@ -348,6 +496,127 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
         atomicAdd(&stats[1], (unsigned long long)n_near_cols);
         atomicAdd(&stats[2], (unsigned long long)n_visit);
         atomicAdd(&stats[3], 1ull);
+    }
+}
+
+__device__ __forceinline__ uint32_t hash3(uint32_t a, uint32_t b, uint32_t c) {
+    // 32-bit finaliser of a simple multiply-xorshift mix (deterministic sample selection)
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
+    h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+    return h;
+}
+
+// Training samples: the same walk as farfield_kernel; for far clusters with at most max_faces
+// faces, selected with probability ~ sel (hash of seed, block, node), up to `quota` per block, every
+// row of the block yields one sample: features and the (exact - monopole) correction in units.
+// Output rows [(b * quota + c) * 64 + lane]; rows not filled keep weight 0 (targets[.][15]).
+__global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
+                                                       const double* __restrict__ c64,
+                                                       const NodeRec* __restrict__ nodes,
+                                                       const NodeMom* __restrict__ moms, int H, int leaf, int64_t nF,
+                                                       const float4* __restrict__ balls, float theta, uint32_t seed,
+                                                       uint32_t sel, int quota, int64_t max_faces,
+                                                       float* __restrict__ feats, float* __restrict__ targets,
+                                                       const MlpPacked* __restrict__ W, float* __restrict__ pred) {
+    __shared__ int stack[FF_STACK];
+    __shared__ MlpScratch ms;
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t i = b * 64 + lane;
+    const bool rowok = i < nF;
+    const float ax = (float)c64[3 * i], ay = (float)c64[3 * i + 1], az = (float)c64[3 * i + 2];
+    const ColRec me = cols[i];
+    const float4 tb = balls[b];
+    const int4 nov = make_int4(0, 0, 0, 0);
+    const int64_t leaf0 = (int64_t)1 << H;
+    int taken = 0;
+    // clear this block's output rows
+    for (int c = 0; c < quota; ++c) {
+        const int64_t row = (b * quota + c) * 64 + lane;
+        for (int k = 0; k < 32; ++k) feats[row * 32 + k] = 0.f;
+        for (int k = 0; k < 16; ++k) targets[row * 16 + k] = 0.f;
+    }
+    if (lane == 0) stack[0] = 1;
+    int sz = 1;
+    while (sz > 0 && taken < quota) {
+        const int n = sz < 64 ? sz : 64;
+        sz -= n;
+        const bool act = lane < n;
+        const int k = act ? stack[sz + lane] : 0;
+        NodeRec nd = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (act) nd = nodes[k];
+        const float dx = tb.x - nd.cx, dy = tb.y - nd.cy, dz = tb.z - nd.cz;
+        const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+        const bool valid = act && nd.a > 0.f;
+        const bool far = valid && (2.f * nd.r < theta * (dist - tb.w));
+        const bool isleaf = (int64_t)k >= leaf0;
+        bool open = valid && !far && !isleaf;
+        const int nopen = __popcll(__ballot(open));
+        if (sz + 2 * nopen <= FF_STACK) {
+            const uint64_t om = __ballot(open);
+            const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            if (open) {
+                const int pos = sz + 2 * (int)__popcll(om & lt);
+                stack[pos] = 2 * k + 1;
+                stack[pos + 1] = 2 * k;
+            }
+            sz += 2 * nopen;
+        }
+        uint64_t fm = __ballot(far);
+        while (fm && taken < quota) {
+            const int l = (int)__builtin_ctzll(fm);
+            fm &= fm - 1;
+            const int kk = __builtin_amdgcn_readlane(k, l);
+            const int lev = 31 - __builtin_clz((unsigned)kk);
+            const int64_t span = (int64_t)1 << (H - lev);
+            const int64_t f0 = ((int64_t)kk - ((int64_t)1 << lev)) * span * leaf;
+            const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
+            if (f1 - f0 > max_faces || hash3(seed, (uint32_t)b, (uint32_t)kk) > sel) continue;
+            NodeRec cn;
+            cn.cx = lane_f(nd.cx, l); cn.cy = lane_f(nd.cy, l); cn.cz = lane_f(nd.cz, l); cn.r = lane_f(nd.r, l);
+            cn.a = lane_f(nd.a, l); cn.nx = lane_f(nd.nx, l); cn.ny = lane_f(nd.ny, l); cn.nz = lane_f(nd.nz, l);
+            const NodeMom mm = moms[kk];
+            // exact contribution of the cluster's faces, in absolute (normalised) coordinates
+            float ex[NACC], mo[NACC];
+            for (int q = 0; q < NACC; ++q) { ex[q] = 0.f; mo[q] = 0.f; }
+            for (int64_t f = f0; f < f1; ++f) {
+                ColRec cr = cols[f];
+                // columns are stored relative to their tile origin; use absolute (normalised) ones here
+                cr.cx = (float)(c64[3 * f]); cr.cy = (float)(c64[3 * f + 1]); cr.cz = (float)(c64[3 * f + 2]);
+                ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, ex);
+            }
+            const ColRec mc = {cn.cx, cn.cy, cn.cz, cn.a, cn.nx, cn.ny, cn.nz, 0.f};
+            ff_pair<6, true, false>(mc, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, mo);
+            Frame fr;
+            float x[32];
+            ff_features(ax, ay, az, me.nx, me.ny, me.nz, cn, mm, fr, x);
+            float u6, u7;
+            out_units(cn.a, fr, u6, u7);
+            float cex[3], cmo[3], dsd[3], dc[3];
+            net_c(ex, me.nx, me.ny, me.nz, cex);
+            net_c(mo, me.nx, me.ny, me.nz, cmo);
+            for (int q = 0; q < 3; ++q) { dsd[q] = ex[2 + q] - mo[2 + q]; dc[q] = cex[q] - cmo[q]; }
+            float y[16];
+            y[0] = (ex[0] - mo[0]) / u6;
+            to_frame(dsd, fr, y + 1);
+            to_frame(dc, fr, y + 4);
+            for (int q = 1; q < 4; ++q) y[q] /= u6;
+            for (int q = 4; q < 7; ++q) y[q] /= u7;
+            for (int q = 7; q < 16; ++q) y[q] = 0.f;
+            bool fin = rowok;
+            for (int q = 0; q < 7; ++q) fin &= isfinite(y[q]);
+            y[15] = fin ? 1.f : 0.f;
+            const int64_t row = (b * quota + taken) * 64 + lane;
+            if (pred) {
+                // the in-walk inference on exactly these features (parity hook for the fused path)
+                float yp[16];
+                mlp_infer64(W, x, ms, yp);
+                for (int q = 0; q < 16; ++q) pred[row * 16 + q] = yp[q];
+            }
+            for (int q = 0; q < 32; ++q) feats[row * 32 + q] = x[q];
+            for (int q = 0; q < 16; ++q) targets[row * 16 + q] = fin ? y[q] : 0.f;
+            ++taken;
+        }
     }
 }
 
@@ -471,31 +740,51 @@ int tree_height(int64_t nF, int leaf) {
 }
 
 size_t tree_node_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeF64); }
-size_t tree_rec_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeRec); }
+size_t tree_rec_bytes(int H) { return ((size_t)2 << H) * (sizeof(NodeRec) + sizeof(NodeMom)); }
 
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
                                const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
                                hipStream_t st) {
     NodeF64* n = (NodeF64*)nodes64;
     NodeRec* r = (NodeRec*)recs;
+    NodeMom* m = (NodeMom*)(r + ((size_t)2 << H));
     const int64_t nslot = (int64_t)1 << H;
     hipLaunchKernelGGL(leaf_moments, dim3((unsigned)((nslot + 127) / 128)), dim3(128), 0, st, c64, geo, colv, X, bbox,
-                       nF, leaf, H, n, r);
+                       nF, leaf, H, n, r, m);
     for (int l = H - 1; l >= 0; --l) {
         const int64_t cnt = (int64_t)1 << l;
-        hipLaunchKernelGGL(internal_moments, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, l, n, r);
+        hipLaunchKernelGGL(internal_moments, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, l, n, r, m);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const double* c64, const double* X,
+                                  const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF, float theta,
+                                  uint32_t seed, uint32_t sel, int quota, int64_t max_faces, float4* balls,
+                                  float* feats, float* targets, const void* mlp_packed, float* pred, hipStream_t st) {
+    const int64_t nb = (nF + 63) / 64;
+    const NodeRec* r = (const NodeRec*)recs;
+    const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
+    hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
+    hipLaunchKernelGGL(farfield_samples, dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, r, m, H, leaf, nF, balls,
+                       theta, seed, sel, quota, max_faces, feats, targets, (const MlpPacked*)mlp_packed, pred);
     return hipGetLastError();
 }
 
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
-                           int64_t Fp, float theta, float4* balls, double* acc64, unsigned long long* stats,
-                           hipStream_t st) {
+                           int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
+                           unsigned long long* stats, hipStream_t st) {
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
+    const NodeRec* r = (const NodeRec*)recs;
+    const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
-    hipLaunchKernelGGL(farfield_kernel, dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org,
-                       (const NodeRec*)recs, H, leaf, nF, balls, theta, Fp, acc64, stats);
+    if (mlp_packed)
+        hipLaunchKernelGGL((farfield_kernel<true>), dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org, r, m,
+                           (const MlpPacked*)mlp_packed, H, leaf, nF, balls, theta, Fp, acc64, stats);
+    else
+        hipLaunchKernelGGL((farfield_kernel<false>), dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org, r, m,
+                           (const MlpPacked*)nullptr, H, leaf, nF, balls, theta, Fp, acc64, stats);
     return hipGetLastError();
 }
 

@@ -1,0 +1,123 @@
+"""Learned far-field correction: training samples, fused BF16-MFMA inference in the tree walk,
+and the gain over the plain monopole (judged against the exact path)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A network trained in-test on seeded training shapes (seeds 1000..1029, disjoint from the
+    evaluation seed 0)."""
+    T = tpe()
+    from paper_2509_22110_amd import mlp_train as MT
+    t0 = time.time()
+    X, Y = MT.collect(range(1000, 1040))
+    Xv, Yv = MT.collect(range(1040, 1046))
+    m = T.MLP(seed=7)
+    MT.train(m, X, Y, epochs=4, batch=8192, lr=2e-3, log=log, Xv=Xv, Tv=Yv)
+    v, z = MT.evaluate(m, Xv, Yv), MT.zero_loss(Yv)
+    log(f"trained on {X.shape[0]} samples in {time.time() - t0:.1f} s; val loss {v:.4e} vs monopole {z:.4e}")
+    return m, v, z
+
+
+def test_samples_are_finite_and_deterministic():
+    import torch
+    T = tpe()
+    c = M.make_config("C2")  # the level-3 mesh is too coarse to have admissible clusters at theta 0.5
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    f1, t1 = T.farfield_samples(tree, Xd, Fd, seed=3, select_prob=0.05, quota=8)
+    f2, t2 = T.farfield_samples(tree, Xd, Fd, seed=3, select_prob=0.05, quota=8)
+    assert torch.equal(f1, f2) and torch.equal(t1, t2)
+    keep = t1[:, 15] > 0
+    assert int(keep.sum()) > 0
+    assert bool(torch.isfinite(f1[keep]).all()) and bool(torch.isfinite(t1[keep]).all())
+    # features are rotation-invariant by construction
+    R = M.random_rotation(4)
+    Xr, _ = upload(c.X @ R.T, c.F)
+    tree_r = T.build_tree(Xr, Fd)
+    f3, t3 = T.farfield_samples(tree_r, Xr, Fd, seed=3, select_prob=0.05, quota=8)
+    k3 = t3[:, 15] > 0
+    # same statistics (the k-d order can differ after rotation, so compare distributions)
+    a = f1[keep][:, :19].mean(0).cpu().numpy(); b = f3[k3][:, :19].mean(0).cpu().numpy()
+    log("feature means", a[:7], b[:7])
+    assert np.abs(a[:3] - b[:3]).max() < 0.05
+
+
+def test_fused_inference_matches_standalone(trained):
+    """The network evaluated inside the tree walk gives exactly what tpe_mlp_forward gives on
+    the same features."""
+    import torch
+    m, _, _ = trained
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    f, t, p = T.farfield_samples(tree, Xd, Fd, seed=9, select_prob=0.05, quota=8, mlp=m)
+    keep = t[:, 15] > 0
+    ps = m.forward(f[keep])
+    assert torch.equal(p[keep][:, :7], ps[:, :7])
+
+
+def test_learned_correction_gain(trained):
+    """What the trained network gains over the plain monopole, judged against the exact path.
+
+    Measured: on the level-5 workload the correction lowers the energy error several-fold and
+    the gradient error somewhat.  On the level-7 workload the per-sample fit is as good, but the
+    dE/da and dE/dn parts of the correction add face-to-face noise (BF16-quantised inputs) that does
+    not cancel at shared vertices the way the monopole's smooth error does, so the gradient error
+    there is not improved; the plain monopole (which meets the far-field target on its own) stays
+    the default and the judge."""
+    m, v, z = trained
+    assert v < 0.25 * z  # validation loss of the correction vs predicting zero (= plain monopole)
+    T = tpe()
+    res = {}
+    for name in ("C2", "C4"):
+        c = M.make_config(name)
+        Xd, Fd = upload(c.X, c.F)
+        E0, G0 = T.gradient(Xd, Fd)
+        E0 = float(E0.cpu()); G0 = G0.cpu().numpy()
+        tree = T.build_tree(Xd, Fd)
+        Em, Gm = T.farfield(tree, Xd, Fd, theta=0.5)
+        El, Gl = T.farfield(tree, Xd, Fd, theta=0.5, mlp=m)
+        em = (rel_energy(float(Em.cpu()), E0), rel_grad_maxnorm(Gm.cpu().numpy(), G0))
+        el = (rel_energy(float(El.cpu()), E0), rel_grad_maxnorm(Gl.cpu().numpy(), G0))
+        res[name] = (em, el)
+        log(f"{name}: monopole rel E {em[0]:.3e} rel G {em[1]:.3e} | learned rel E {el[0]:.3e} rel G {el[1]:.3e}")
+    (em, el) = res["C2"]
+    assert el[0] < 0.5 * em[0]      # energy: at least 2x closer to exact
+    assert el[1] < em[1]            # gradient: closer to exact
+    (em4, _) = res["C4"]
+    assert em4[1] <= 1e-3           # the monopole meets the level-7 far-field target by itself
+
+
+def test_farfield_speed_and_accuracy_at_c4(trained):
+    """Level-7 workload: monopole far field >= 10x faster than the exact kernel at <= 1e-3 gradient
+    error; the learned variant's time and error are reported."""
+    import torch
+    m, _, _ = trained
+    T = tpe()
+    c = M.make_config("C4")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    def timed(fn):
+        fn(); torch.cuda.synchronize()
+        t0 = time.perf_counter(); out = fn(); torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+    t_e, (E0, G0) = timed(lambda: T.gradient(Xd, Fd))
+    t_m, (Em, Gm) = timed(lambda: T.farfield(tree, Xd, Fd, theta=0.5))
+    t_l, (El, Gl) = timed(lambda: T.farfield(tree, Xd, Fd, theta=0.5, mlp=m))
+    G0 = G0.cpu().numpy()
+    eGm = rel_grad_maxnorm(Gm.cpu().numpy(), G0)
+    eGl = rel_grad_maxnorm(Gl.cpu().numpy(), G0)
+    log(f"C4: exact {t_e*1e3:.1f} ms | monopole {t_m*1e3:.2f} ms ({t_e/t_m:.1f}x, rel G {eGm:.3e}) | "
+        f"learned {t_l*1e3:.2f} ms ({t_e/t_l:.1f}x, rel G {eGl:.3e})")
+    assert t_e / t_m >= 10.0
+    assert eGm <= 1e-3
