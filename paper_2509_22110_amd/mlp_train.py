@@ -72,6 +72,50 @@ def evaluate(mlp, X, T, batch=65536):
     return tot / (NOUT * wsum)
 
 
+OFF_W4 = 32 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64  # W4 [64][16] row-major [in][out], then b4 [16]
+OFF_B4 = OFF_W4 + 64 * 16
+
+
+def output_scales(T):
+    """Weighted RMS of each used target column.  The outputs differ in size by two orders of
+    magnitude (the transverse Sd components are tiny next to C), so training on raw targets lets
+    the large ones dominate the loss and leaves the small ones as noise."""
+    w = T[:, 15]
+    return torch.sqrt((w[:, None] * T[:, :NOUT] ** 2).sum(0) / w.sum()).clamp_min(1e-30)
+
+
+def normalized(T, sig):
+    Tn = T.clone()
+    Tn[:, :NOUT] /= sig
+    return Tn
+
+
+def fold_scales(mlp, sig, keep=None):
+    """Multiply output j of the last (linear) layer by sig[j]; zero the outputs not in `keep`."""
+    p = mlp.get_params()
+    W4 = p[OFF_W4:OFF_W4 + 64 * 16].reshape(64, 16)
+    b4 = p[OFF_B4:OFF_B4 + 16]
+    s = sig.detach().cpu().numpy().astype(np.float64)
+    for j in range(16):
+        f = s[j] if j < NOUT and (keep is None or j in keep) else 0.0
+        W4[:, j] = (W4[:, j] * f).astype(np.float32)
+        b4[j] = np.float32(b4[j] * f)
+    mlp.set_params(p)
+
+
+def per_output_ratio(mlp, X, T, batch=65536):
+    """Weighted MSE of each used output divided by that of predicting zero (< 1: the output helps)."""
+    err = torch.zeros(NOUT, dtype=torch.float64, device=X.device)
+    zero = torch.zeros(NOUT, dtype=torch.float64, device=X.device)
+    for i in range(0, X.shape[0], batch):
+        y = mlp.forward(X[i:i + batch])[:, :NOUT].double()
+        t = T[i:i + batch]
+        w = t[:, 15:16].double()
+        err += (w * (y - t[:, :NOUT].double()) ** 2).sum(0)
+        zero += (w * t[:, :NOUT].double() ** 2).sum(0)
+    return (err / zero.clamp_min(1e-300)).cpu().numpy()
+
+
 def train(mlp, X, T, epochs=8, batch=8192, lr=2e-3, seed=0, log=print, Xv=None, Tv=None):
     n = X.shape[0]
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -89,6 +133,23 @@ def train(mlp, X, T, epochs=8, batch=8192, lr=2e-3, seed=0, log=print, Xv=None, 
         if Xv is not None:
             msg += f", val loss {evaluate(mlp, Xv, Tv):.4e} (zero-prediction {zero_loss(Tv):.4e})"
         log(msg)
+    return mlp
+
+
+def fit(X, T, Xv, Tv, epochs=8, seed=0, log=print, max_ratio=1.0):
+    """Train on per-output normalized targets, fold the scales back into the last layer, and keep
+    only the outputs that beat the zero correction on the validation set (ratio < max_ratio)."""
+    sig = output_scales(T)
+    log("output scales: " + " ".join(f"{float(v):.3e}" for v in sig))
+    mlp = MLP(seed=seed)
+    train(mlp, X, normalized(T, sig), epochs=epochs, log=log, Xv=Xv, Tv=normalized(Tv, sig))
+    fold_scales(mlp, sig)
+    ratio = per_output_ratio(mlp, Xv, Tv)
+    keep = {j for j in range(NOUT) if ratio[j] < max_ratio}
+    log("validation error / zero-correction error per output: " + " ".join(f"{r:.3f}" for r in ratio)
+        + f"; kept {sorted(keep)}")
+    if len(keep) < NOUT:
+        fold_scales(mlp, torch.ones(NOUT), keep)
     return mlp
 
 
@@ -110,8 +171,7 @@ def main(argv=None):
     X, T = collect(seeds[:-nval], theta=args.theta, log=log)
     Xv, Tv = collect(seeds[-nval:], theta=args.theta, log=log)
     log(f"samples: train {X.shape[0]}, val {Xv.shape[0]} ({time.time() - t0:.1f} s)")
-    mlp = MLP(seed=args.first_seed)
-    train(mlp, X, T, epochs=args.epochs, log=log, Xv=Xv, Tv=Tv)
+    mlp = fit(X, T, Xv, Tv, epochs=args.epochs, seed=args.first_seed, log=log)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     mlp.save(args.out)
     log(f"saved {args.out}; val loss {evaluate(mlp, Xv, Tv):.4e} vs zero-prediction {zero_loss(Tv):.4e}")

@@ -13,18 +13,18 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 @pytest.fixture(scope="module")
 def trained():
-    """A network trained in-test on seeded training shapes (seeds 1000..1029, disjoint from the
-    evaluation seed 0)."""
-    T = tpe()
+    """A network trained in-test on seeded training shapes (seeds 1000..1039, validation
+    1040..1045, all disjoint from the evaluation seed 0), on per-output normalized targets."""
+    tpe()
     from paper_2509_22110_amd import mlp_train as MT
     t0 = time.time()
     X, Y = MT.collect(range(1000, 1040))
     Xv, Yv = MT.collect(range(1040, 1046))
-    m = T.MLP(seed=7)
-    MT.train(m, X, Y, epochs=4, batch=8192, lr=2e-3, log=log, Xv=Xv, Tv=Yv)
-    v, z = MT.evaluate(m, Xv, Yv), MT.zero_loss(Yv)
-    log(f"trained on {X.shape[0]} samples in {time.time() - t0:.1f} s; val loss {v:.4e} vs monopole {z:.4e}")
-    return m, v, z
+    m = MT.fit(X, Y, Xv, Yv, epochs=8, seed=7, log=log)
+    ratio = MT.per_output_ratio(m, Xv, Yv)
+    log(f"trained on {X.shape[0]} samples in {time.time() - t0:.1f} s; validation error / zero-correction "
+        f"error per output {np.round(ratio, 3)}")
+    return m, ratio
 
 
 def test_samples_are_finite_and_deterministic():
@@ -55,7 +55,7 @@ def test_fused_inference_matches_standalone(trained):
     """The network evaluated inside the tree walk gives exactly what tpe_mlp_forward gives on
     the same features."""
     import torch
-    m, _, _ = trained
+    m, _ = trained
     T = tpe()
     c = M.make_config("C2")
     Xd, Fd = upload(c.X, c.F)
@@ -69,14 +69,14 @@ def test_fused_inference_matches_standalone(trained):
 def test_learned_correction_gain(trained):
     """What the trained network gains over the plain monopole, judged against the exact path.
 
-    Measured: on the level-5 workload the correction lowers the energy error several-fold and
-    the gradient error somewhat.  On the level-7 workload the per-sample fit is as good, but the
-    dE/da and dE/dn parts of the correction add face-to-face noise (BF16-quantised inputs) that does
-    not cancel at shared vertices the way the monopole's smooth error does, so the gradient error
-    there is not improved; the plain monopole (which meets the far-field target on its own) stays
-    the default and the judge."""
-    m, v, z = trained
-    assert v < 0.25 * z  # validation loss of the correction vs predicting zero (= plain monopole)
+    Measured: the correction lowers the energy error about 6x on the level-5 workload and 4x on
+    the level-7 one; the gradient's max-norm error drops on the level-5 workload and stays within
+    the 1e-3 target on the level-7 one (where it is at the monopole's level: the correction's errors
+    vary from face to face and do not cancel at shared vertices the way the monopole's smooth
+    error does)."""
+    m, ratio = trained
+    # every output of the correction beats predicting zero (= the plain monopole) per sample
+    assert ratio.max() < 0.5 and ratio.mean() < 0.25
     T = tpe()
     res = {}
     for name in ("C2", "C4"):
@@ -94,15 +94,16 @@ def test_learned_correction_gain(trained):
     (em, el) = res["C2"]
     assert el[0] < 0.5 * em[0]      # energy: at least 2x closer to exact
     assert el[1] < em[1]            # gradient: closer to exact
-    (em4, _) = res["C4"]
-    assert em4[1] <= 1e-3           # the monopole meets the level-7 far-field target by itself
+    (em4, el4) = res["C4"]
+    assert el4[0] < 0.5 * em4[0]    # level 7: energy at least 2x closer to exact
+    assert em4[1] <= 1e-3 and el4[1] <= 1e-3  # both meet the level-7 gradient target
 
 
 def test_farfield_speed_and_accuracy_at_c4(trained):
     """Level-7 workload: monopole far field >= 10x faster than the exact kernel at <= 1e-3 gradient
     error; the learned variant's time and error are reported."""
     import torch
-    m, _, _ = trained
+    m, _ = trained
     T = tpe()
     c = M.make_config("C4")
     Xd, Fd = upload(c.X, c.F)
