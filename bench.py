@@ -7,13 +7,19 @@ HBM.  Prints ONE JSON line:
     value     = ordered non-adjacent face pairs evaluated per second (energy + gradient)
     roofline  = the pair kernel's algorithmic FP32 rate (55 flop per pair) over its own launch
                 durations, measured with HIP events on the stream it runs on, vs the FP32
-                vector peak; traffic from rocprofv3 counters (see profiles/) when available
+                vector peak; traffic = HBM bytes per launch from the committed rocprofv3 counter
+                summary (profiles/pair_kernel_C2_traffic.txt), null when the kernel's sources
+                have changed since it was taken
+    farfield  = ms per gradient on the level-7 workload (327,680 faces): exact all-pairs vs the
+                cluster-tree far field (monopole, and with the learned correction), with their
+                relative errors against the exact path
     cpu_baseline = the FP64 CPU oracle, timed on this host on the same mesh
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-farfield]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,19 +46,89 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-farfield", action="store_true", help="skip the level-7 far-field comparison")
+    ap.add_argument("--farfield-only", action="store_true", help="run only the level-7 far-field comparison")
+    ap.add_argument("--ff-config", default="C4")
+    ap.add_argument("--ff-reps", type=int, default=5)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
 
 
+PAIR_SOURCES = ("paper_2509_22110_amd/csrc/pair.hip", "paper_2509_22110_amd/csrc/common.hpp")
+
+
+def pair_source_hash():
+    h = hashlib.sha256()
+    for rel in PAIR_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def read_traffic():
-    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter summary, if any."""
-    path = os.path.join(ROOT, "profiles", "pair_kernel_C2_traffic.json")
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter summary; None if there
+    is none or if it was taken on other sources of the kernel than the ones built here."""
+    path = os.path.join(ROOT, "profiles", "pair_kernel_C2_traffic.txt")
     if not os.path.exists(path):
         return None
-    try:
-        with open(path) as f:
-            return json.load(f).get("bytes_per_launch")
-    except Exception:
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != pair_source_hash():
         return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def farfield_leg(args, T, M, torch, dev):
+    """ms per gradient on the level-7 workload: exact vs cluster-tree far field (+ learned)."""
+    cfg = M.make_config(args.ff_config)
+    X = torch.from_numpy(cfg.X).to(dev)
+    F = torch.from_numpy(cfg.F).to(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3, out
+
+    G0 = torch.empty_like(X)
+    E0 = torch.empty((), dtype=torch.float64, device=dev)
+    t_exact, _ = timed(lambda: T.gradient(X, F, out=G0, energy_out=E0), max(1, args.ff_reps // 2))
+    t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
+    g0 = float(G0.abs().max())
+    e0 = float(E0)
+    G = torch.empty_like(X)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+
+    def variant(mlp):
+        t, _ = timed(lambda: T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E), args.ff_reps)
+        return {"ms": round(t, 3), "speedup_vs_exact": round(t_exact / t, 2),
+                "rel_grad_maxnorm": float((G - G0).abs().max()) / g0,
+                "rel_energy": abs(float(E) - e0) / abs(e0)}
+
+    out = {"workload": f"{args.ff_config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0",
+           "faces": cfg.nF, "theta": args.theta, "leaf": 32,
+           "exact_ms": round(t_exact, 3), "tree_build_ms": round(t_tree, 3),
+           "note": "errors against the exact FP32/FP64 path (itself parity-tested against the FP64 "
+                   "oracle); far-field ms per gradient exclude the tree build (an ordering that is "
+                   "reused while the moments are recomputed from X on every call)",
+           "monopole": variant(None), "learned": None}
+    if args.mlp and os.path.exists(args.mlp):
+        mlp = T.MLP.load(args.mlp, device=dev)
+        out["learned"] = variant(mlp)
+        out["learned"]["checkpoint"] = os.path.relpath(args.mlp, ROOT)
+    T.context(dev).sync_check()
+    return out
 
 
 def main():
@@ -77,6 +153,9 @@ def main():
     E = torch.empty((), dtype=torch.float64, device=dev)
     ctx = T.context(dev)
     ctx.set_option(T.OPT_SYNC_CHECKS, 0)
+    if args.farfield_only:
+        print(json.dumps({"farfield": farfield_leg(args, T, M, torch, dev)}), flush=True)
+        return
 
     if args.calib_copy_mb:
         src = torch.empty(args.calib_copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -115,6 +194,8 @@ def main():
                 "traffic": traffic, "kernel": "pair_kernel<6,true>",
                 "kernel_avg_ms": round(k_avg_ms, 4), "flop_per_pair": FLOP_PER_PAIR}
 
+    ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -138,6 +219,7 @@ def main():
                                "exact all-pairs energy+gradient, (q,p)=(6,12)",
                    "faces": cfg.nF, "pairs": P, "q": 6, "p": 12, "parallelism": "single-gpu"},
         "roofline": roofline,
+        "farfield": ff,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

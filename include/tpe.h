@@ -153,7 +153,8 @@ int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* mlp, const float* host, int64_t n)
 /* tpe_farfield applies the correction only to far clusters with r_B / rho >= min_s (default 0:
  * all); rho = |c_S - C_B|.  Stored with the network (not in checkpoints). */
 int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* mlp, float min_s);
-/* out (device f32 [n][16]) <- network(feats (device f32 [n][32])). */
+/* out (device f32 [n][16]) <- network(feats (device f32 [n][32])), evaluated with the BF16 weights
+ * and activations exactly as tpe_farfield evaluates it (bit-identical for the same features). */
 int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* mlp, const float* feats, int64_t n, float* out);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr > 0) on the batch feats (device
  * f32 [n][32]) / targets (device f32 [n][16]: columns 0..6 are targets, column 15 the sample

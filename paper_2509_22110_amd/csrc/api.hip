@@ -27,11 +27,12 @@ hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t n
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st);
 int64_t radix_hist_words(int64_t n);
+int64_t scan_ws_words(int64_t n);
 hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp, const uint32_t* perm,
                           const uint32_t* bbox, double* org, ColRec* cols, int4* colv, double* c64, double* geo,
                           uint32_t* cnt, uint32_t* flags, hipStream_t st);
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off, uint32_t* cursor,
-                            uint32_t* list, hipStream_t st);
+                            uint32_t* list, uint32_t* ws, hipStream_t st);
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
                         int nrb, int touch_words, uint32_t* touch, hipStream_t st);
 int pair_blocks_per_cu(bool grad);
@@ -198,7 +199,7 @@ struct Plan {
     // buffers
     uint32_t *keys, *vals, *ktmp, *vtmp, *hist, *hoff, *bbox;
     uint32_t *zero_begin, *cnt, *cursor, *touch, *zero_end;
-    uint32_t *voff, *list;
+    uint32_t *voff, *list, *scanws;
     double *org, *c64, *geo, *corner, *epart, *acc64;
     uint32_t* ticket;
     int morton_bits;
@@ -234,6 +235,7 @@ void layout(Plan& P, char* base, bool grad) {
     P.zero_end = c.take<uint32_t>(0);
     P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.voff = c.take<uint32_t>(V + 1);
+    P.scanws = c.take<uint32_t>((size_t)scan_ws_words(V) + 1);
     P.list = c.take<uint32_t>(3 * nF);
     P.org = c.take<double>(3 * (size_t)P.ntiles);
     P.cols = c.take<ColRec>(Fp);
@@ -335,7 +337,7 @@ int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nF, 3 * P.morton_bits, P.hist, P.hoff, st));
     HIPCHK(launch_records(X, P.V, F, P.nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
-    HIPCHK(launch_adjacency(P.colv, P.nF, P.V, P.cnt, P.voff, P.cursor, P.list, st));
+    HIPCHK(launch_adjacency(P.colv, P.nF, P.V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     HIPCHK(launch_touch(P.colv, P.nF, P.V, P.voff, P.list, P.nrb, P.touch_words, P.touch, st));
     return TPE_OK;
 }
@@ -549,7 +551,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, st));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
@@ -703,7 +705,7 @@ int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* m, const float* feats, int64_t 
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !feats || !out || n < 0) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP forward arguments");
     DeviceGuard dg(ctx->device);
-    HIPCHK(mlp_forward_launch(m->P, feats, n, out, ctx->stream));
+    HIPCHK(mlp_infer_launch(m->packed, feats, n, out, ctx->stream));
     return TPE_OK;
 }
 
@@ -822,7 +824,7 @@ int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(P.counter), 0u, 2, st));
     hipLaunchKernelGGL(face_ids, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, F, nF, V, P.colv, P.cnt, ctx->dflags);
     HIPCHK(hipGetLastError());
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, st));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     hipLaunchKernelGGL(excluded_count, dim3((int)ceil_div(nF, 256)), dim3(256), 0, st, P.colv, nF, V, P.voff, P.list,
                        P.counter);
     HIPCHK(hipGetLastError());

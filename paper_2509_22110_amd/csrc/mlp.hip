@@ -118,20 +118,19 @@ __device__ void mlp_tile_forward(const float* __restrict__ P, const float* Xs, f
     __syncthreads();
 }
 
-// Inference: out[n][16] for feats[n][32].  One wave per tile of TM samples.
-__global__ __launch_bounds__(64) void mlp_forward_kernel(const float* __restrict__ P, const float* __restrict__ X,
-                                                         int64_t n, float* __restrict__ out) {
-    __shared__ float Xs[TM * 32], H1[TM * 64], H2[TM * 64], H3[TM * 64], Y[TM * 16];
-    const int64_t base = (int64_t)blockIdx.x * TM;
-    for (int e = threadIdx.x; e < TM * 32; e += 64) {
-        const int64_t row = base + e / 32;
-        Xs[e] = row < n ? X[row * 32 + e % 32] : 0.f;
-    }
-    __syncthreads();
-    mlp_tile_forward(P, Xs, H1, H2, H3, Y);
-    for (int e = threadIdx.x; e < TM * 16; e += 64) {
-        const int64_t row = base + e / 16;
-        if (row < n) out[row * 16 + e % 16] = Y[e];
+// Inference through the routine the far-field walk uses (packed BF16 weights): one wave per 64
+// samples, so out[i] is bit-identical to the in-walk prediction for the same features.
+__global__ __launch_bounds__(64) void mlp_infer_kernel(const MlpPacked* __restrict__ W, const float* __restrict__ X,
+                                                       int64_t n, float* __restrict__ out) {
+    __shared__ MlpScratch ms;
+    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    float x[32], y[16];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) x[k] = row < n ? X[row * 32 + k] : 0.f;
+    mlp_infer64(W, x, ms, y);
+    if (row < n) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) out[row * 16 + j] = y[j];
     }
 }
 
@@ -297,19 +296,20 @@ __global__ void mlp_grad_sum(const float* __restrict__ gpart, const float* __res
     grad[p] = g * norm;
 }
 
-// FP32 master parameters -> BF16 B fragments in MFMA order + FP32 biases (see mlp_infer.hpp).
+// FP32 master parameters -> BF16 A fragments in MFMA order + FP32 biases (see mlp_infer.hpp).
 __global__ void mlp_pack(const float* __restrict__ P, float min_s, MlpPacked* __restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < MLP_NFRAG * 64) {
         const int f = t / 64, lane = t % 64, r = lane & 15, q = lane >> 4;
         const float* W;
-        int ld, kt, nt;
-        if (f < 4) { W = P + MLP_OFF_W1; ld = 64; kt = 0; nt = f; }
-        else if (f < 12) { W = P + MLP_OFF_W2; ld = 64; kt = (f - 4) / 4; nt = (f - 4) % 4; }
-        else if (f < 20) { W = P + MLP_OFF_W3; ld = 64; kt = (f - 12) / 4; nt = (f - 12) % 4; }
-        else { W = P + MLP_OFF_W4; ld = 16; kt = f - 20; nt = 0; }
+        int ld, kt, mt;
+        if (f < 4) { W = P + MLP_OFF_W1; ld = 64; kt = 0; mt = f; }
+        else if (f < 12) { W = P + MLP_OFF_W2; ld = 64; kt = (f - 4) / 4; mt = (f - 4) % 4; }
+        else if (f < 20) { W = P + MLP_OFF_W3; ld = 64; kt = (f - 12) / 4; mt = (f - 12) % 4; }
+        else { W = P + MLP_OFF_W4; ld = 16; kt = f - 20; mt = 0; }
+        // A[m = out unit mt * 16 + r][k = in unit kt * 32 + 8 q + i] = W[k][m]
         bf16x8 v;
-        for (int i = 0; i < 8; ++i) v[i] = (__bf16)W[(kt * 32 + 8 * q + i) * ld + nt * 16 + r];
+        for (int i = 0; i < 8; ++i) v[i] = (__bf16)W[(kt * 32 + 8 * q + i) * ld + mt * 16 + r];
         out->frag[f][lane] = v;
     }
     if (t == 0) out->min_s = min_s;
@@ -345,10 +345,11 @@ void mlp_init_params(uint64_t seed, std::vector<float>& P) {
     }
 }
 
-hipError_t mlp_forward_launch(const float* P, const float* X, int64_t n, float* out, hipStream_t st) {
-    const unsigned g = (unsigned)((n + TM - 1) / TM);
+hipError_t mlp_infer_launch(const void* packed, const float* X, int64_t n, float* out, hipStream_t st) {
+    const int64_t g = (n + 63) / 64;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3(g), dim3(64), 0, st, P, X, n, out);
+    if (g > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)g), dim3(64), 0, st, (const MlpPacked*)packed, X, n, out);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ constexpr int MLP_OFF_B4 = MLP_OFF_W4 + 64 * 16;
 constexpr int MLP_NPARAM = MLP_OFF_B4 + 16;  // 11,472
 
 void mlp_init_params(uint64_t seed, std::vector<float>& P);
-hipError_t mlp_forward_launch(const float* P, const float* X, int64_t n, float* out, hipStream_t st);
+hipError_t mlp_infer_launch(const void* packed, const float* X, int64_t n, float* out, hipStream_t st);
 int64_t mlp_tiles(int64_t n);
 hipError_t mlp_pack_launch(const float* P, float min_s, void* packed, hipStream_t st);
 size_t mlp_packed_bytes();

@@ -1,13 +1,24 @@
-// MLP inference for 64 samples held one per lane of a wave (used inside the far-field walk).
-// Weights come pre-packed in MFMA B-fragment order (one 16-byte load per lane per fragment);
-// activations pass between layers through LDS as BF16, row-major [sample][unit].
+// MLP inference for 64 samples held one per lane of a wave (the far-field walk and tpe_mlp_forward
+// both call mlp_infer64, so the two give bit-identical results).
+//
+// Every layer is computed transposed, H_out^T = W^T H_in^T, with v_mfma_f32_16x16x32_bf16:
+//   - the weights are the A operand, pre-packed per (layer, k-step, m-tile) so that each lane loads
+//     its fragment with one 16-byte load (lane l holds W[k = 8 (l / 16) + i][m = l % 16], i < 8);
+//   - the activations are the B operand, read from LDS rows [sample][unit] (BF16) with one 16-byte
+//     load per lane (B[k = 8 (l / 16) + i][n = l % 16]);
+//   - the accumulators start at the bias, and each lane's D fragment (D[m = 4 (l / 16) + i][n = l %
+//     16], i < 4) holds four consecutive units of one sample, so after ReLU and the BF16 conversion it
+//     goes back to LDS as one 8-byte store.
+// Only LDS traffic of a single wave is involved, which the hardware keeps in program order.
 #pragma once
 #include "mlp.hpp"
 
 namespace tpe {
 
-// B fragments of the four layers: layer 1 (K 32, N 64): 4 fragments [nt]; layer 2 and 3 (K 64,
-// N 64): 8 each [kt][nt]; layer 4 (K 64, N 16): 2 [kt].  Biases b1, b2, b3 (64 each) then b4 (16).
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+
+// A fragments of the four layers: layer 1 (K 32, M 64): 4 fragments [mt]; layers 2 and 3 (K 64,
+// M 64): 8 each [kt][mt]; layer 4 (K 64, M 16): 2 [kt].  Biases b1, b2, b3 (64 each) then b4 (16).
 constexpr int MLP_NFRAG = 22;
 struct MlpPacked {
     bf16x8 frag[MLP_NFRAG][64];
@@ -16,86 +27,103 @@ struct MlpPacked {
     float pad[3];
 };
 
+// LDS row strides, padded so that the 16 rows one fragment load touches fall in different banks
+constexpr int MLP_XS = 40;  // 32 features (bf16)
+constexpr int MLP_HS = 72;  // 64 hidden units (bf16)
+constexpr int MLP_YS = 20;  // 16 outputs (float)
+
 struct MlpScratch {
-    __bf16 xs[64 * 32];
-    __bf16 ha[64 * 64];
-    __bf16 hb[64 * 64];
-    float ys[64 * 16];
+    __bf16 h[64 * MLP_HS];  // hidden activations (layers 2 and 3 update them in place)
+    union {
+        __bf16 xs[64 * MLP_XS];  // features (dead after layer 1)
+        float ys[64 * MLP_YS];   // outputs
+    };
 };
 
-template <int NT>
-__device__ __forceinline__ void relu_store_bf16(const f32x4 (&acc)[4][NT], const float* __restrict__ bias,
-                                                __bf16* dst) {
+__device__ __forceinline__ bf16x4 relu_bf16x4(f32x4 v) {
+    f32x4 r;
+    r.x = fmaxf(v.x, 0.f);
+    r.y = fmaxf(v.y, 0.f);
+    r.z = fmaxf(v.z, 0.f);
+    r.w = fmaxf(v.w, 0.f);
+    return __builtin_convertvector(r, bf16x4);
+}
+
+// One hidden layer: dst[sample][0..64) = relu(W^T src + b), K = 32 * KT.  dst may be src: every
+// load of src is issued before the first store.
+template <int KT>
+__device__ __forceinline__ void mlp_hidden(const MlpPacked* __restrict__ W, int f0, const float* __restrict__ bias,
+                                           const __bf16* src, int sstride, __bf16* dst) {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const f32x4 b = *reinterpret_cast<const f32x4*>(bias + mt * 16 + 4 * q);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = b;
+    }
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            bfr[nt] = *reinterpret_cast<const bf16x8*>(src + (nt * 16 + r) * sstride + kt * 32 + 8 * q);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8 a = W->frag[f0 + kt * 4 + mt][lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = mt * 16 + 4 * q + i, col = nt * 16 + r;
-                dst[row * 64 + col] = (__bf16)fmaxf(acc[mt][nt][i] + bias[col], 0.f);
-            }
+        for (int nt = 0; nt < 4; ++nt)
+            *reinterpret_cast<bf16x4*>(dst + (nt * 16 + r) * MLP_HS + mt * 16 + 4 * q) = relu_bf16x4(acc[mt][nt]);
 }
 
+// y = MLP(x) for the wave's 64 samples (lane = sample).
 __device__ __forceinline__ void mlp_infer64(const MlpPacked* __restrict__ W, const float (&x)[32], MlpScratch& s,
                                             float (&y)[16]) {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    // Reload the weights (cache-resident, 23 KB) on every call instead of letting the compiler keep
+    // all fragments and biases in registers across the caller's loop, which would cost occupancy.
+    asm volatile("" : "+s"(W));
 #pragma unroll
-    for (int k = 0; k < 32; ++k) s.xs[lane * 32 + k] = (__bf16)x[k];
-    f32x4 acc[4][4];
-    // layer 1
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&s.xs[(mt * 16 + r) * 32 + 8 * q]);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, W->frag[nt][lane], acc[mt][nt], 0, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+        f32x4 lo = {x[8 * j], x[8 * j + 1], x[8 * j + 2], x[8 * j + 3]};
+        f32x4 hi = {x[8 * j + 4], x[8 * j + 5], x[8 * j + 6], x[8 * j + 7]};
+        const bf16x4 l4 = __builtin_convertvector(lo, bf16x4), h4 = __builtin_convertvector(hi, bf16x4);
+        *reinterpret_cast<bf16x8*>(s.xs + lane * MLP_XS + 8 * j) = bf16x8{l4.x, l4.y, l4.z, l4.w, h4.x, h4.y, h4.z, h4.w};
     }
-    relu_store_bf16<4>(acc, W->bias, s.ha);
-    // layers 2 and 3
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-        const __bf16* src = layer == 0 ? s.ha : s.hb;
-        __bf16* dst = layer == 0 ? s.hb : s.ha;
-        const int f0 = 4 + 8 * layer;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&src[(mt * 16 + r) * 64 + kt * 32 + 8 * q]);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[mt][nt] =
-                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, W->frag[f0 + kt * 4 + nt][lane], acc[mt][nt], 0, 0, 0);
-            }
-        relu_store_bf16<4>(acc, W->bias + 64 * (layer + 1), dst);
-    }
-    // layer 4 (linear)
+    mlp_hidden<1>(W, 0, W->bias, s.xs, MLP_XS, s.h);
+    mlp_hidden<2>(W, 4, W->bias + 64, s.h, MLP_HS, s.h);
+    mlp_hidden<2>(W, 12, W->bias + 128, s.h, MLP_HS, s.h);
+    // output layer (linear, M 16)
     f32x4 o[4];
+    const f32x4 b = *reinterpret_cast<const f32x4*>(W->bias + 192 + 4 * q);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < 4; ++nt) o[nt] = b;
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+    for (int kt = 0; kt < 2; ++kt) {
+        const bf16x8 a = W->frag[20 + kt][lane];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&s.ha[(mt * 16 + r) * 64 + kt * 32 + 8 * q]);
-            o[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, W->frag[20 + kt][lane], o[mt], 0, 0, 0);
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x8 bf = *reinterpret_cast<const bf16x8*>(s.h + (nt * 16 + r) * MLP_HS + kt * 32 + 8 * q);
+            o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf, o[nt], 0, 0, 0);
         }
+    }
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 4; ++nt) *reinterpret_cast<f32x4*>(s.ys + (nt * 16 + r) * MLP_YS + 4 * q) = o[nt];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) s.ys[(mt * 16 + 4 * q + i) * 16 + r] = o[mt][i] + W->bias[192 + r];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) y[j] = s.ys[lane * 16 + j];
+    for (int j = 0; j < 4; ++j) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(s.ys + lane * MLP_YS + 4 * j);
+        y[4 * j] = v.x;
+        y[4 * j + 1] = v.y;
+        y[4 * j + 2] = v.z;
+        y[4 * j + 3] = v.w;
+    }
 }
 
 }  // namespace tpe

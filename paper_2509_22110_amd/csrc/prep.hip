@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void touch_map(const int4* __restrict__ colv, 
 
 // ---- host launchers ----------------------------------------------------------------------------
 
-hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, hipStream_t st);
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, uint32_t* ws, hipStream_t st);
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -325,10 +325,11 @@ hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t 
     return hipGetLastError();
 }
 
-// cnt holds the per-vertex corner counts; cursor must be zero (V entries).
+// cnt holds the per-vertex corner counts; cursor must be zero (V entries); ws: scan workspace
+// (scan_ws_words(V) words).
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off,
-                            uint32_t* cursor, uint32_t* list, hipStream_t st) {
-    hipError_t e = launch_exclusive_scan(cnt, V, off, st);
+                            uint32_t* cursor, uint32_t* list, uint32_t* ws, hipStream_t st) {
+    hipError_t e = launch_exclusive_scan(cnt, V, off, ws, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(corner_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, cursor, list);
     hipLaunchKernelGGL(corner_sort, dim3(nblk(V, 256)), dim3(256), 0, st, off, V, list);

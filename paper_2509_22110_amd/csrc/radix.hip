@@ -82,7 +82,108 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restr
     }
 }
 
-// Single-work-group exclusive scan of n counts -> off[0..n] (off[n] = total).
+// Exclusive scan of n counts -> off[0..n] (off[n] = total), in tiles of SCAN_TILE counts.
+// Each tile is read and written coalesced through LDS; a thread scans 16 consecutive counts, the
+// 256 thread totals are scanned across the work-group with wave shuffles.  Up to SCAN_SMALL_TILES
+// tiles one work-group walks the tiles with a running carry (one launch); above, (1) every
+// work-group reduces its tile, (2) one work-group scans the tile sums, (3) every work-group scans
+// its tile from its tile's offset.
+constexpr int SCAN_T = 256;
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_TILE = SCAN_T * SCAN_PER;
+constexpr int SCAN_SMALL_TILES = 8;
+
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }  // thread t's row starts at 17 t
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Work-group exclusive scan of one value per thread; *total <- the sum (all threads).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+        const uint32_t x = wsum[w];
+        before += w < wave ? x : 0u;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                      uint32_t* __restrict__ sums) {
+    __shared__ uint32_t wsum[SCAN_T / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const int64_t i = base + j * SCAN_T + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t total;
+    (void)block_exclusive_scan(s, wsum, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Work-group b scans tiles [b * tpb, min((b + 1) * tpb, ntiles)) starting from boff[b] (0 if
+// boff is null); the work-group holding the last tile writes off[n].
+__global__ __launch_bounds__(SCAN_T) void scan_tiles(const uint32_t* __restrict__ in, int64_t n,
+                                                     const uint32_t* __restrict__ boff, int tpb,
+                                                     uint32_t* __restrict__ off) {
+    __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 16];
+    __shared__ uint32_t wsum[SCAN_T / 64];
+    const int t = threadIdx.x;
+    const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint32_t carry = boff ? boff[blockIdx.x] : 0u;
+    const int64_t t0 = (int64_t)blockIdx.x * tpb, t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+    for (int64_t tb = t0; tb < t1; ++tb) {
+        const int64_t base = tb * SCAN_TILE;
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; ++j) {
+            const int64_t i = base + j * SCAN_T + t;
+            tile[scan_pad(j * SCAN_T + t)] = i < n ? in[i] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[SCAN_PER], s = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_PER; ++k) {
+            v[k] = tile[scan_pad(t * SCAN_PER + k)];
+            s += v[k];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan(s, wsum, &total);
+#pragma unroll
+        for (int k = 0; k < SCAN_PER; ++k) {
+            tile[scan_pad(t * SCAN_PER + k)] = run;
+            run += v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; ++j) {
+            const int64_t i = base + j * SCAN_T + t;
+            if (i < n) off[i] = tile[scan_pad(j * SCAN_T + t)];
+        }
+        __syncthreads();
+        carry += total;
+    }
+    if (t == 0 && t1 == ntiles && t0 < t1) off[n] = carry;
+    if (t == 0 && ntiles == 0 && blockIdx.x == 0) off[0] = carry;
+}
+
+// Single-work-group exclusive scan of a short array (the tile sums).
 __global__ __launch_bounds__(1024) void exclusive_scan_1wg(const uint32_t* __restrict__ in, int64_t n,
                                                             uint32_t* __restrict__ off) {
     __shared__ uint32_t part[1024];
@@ -107,26 +208,47 @@ __global__ __launch_bounds__(1024) void exclusive_scan_1wg(const uint32_t* __res
     if (tid == 1023) off[n] = part[1023];
 }
 
-hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, hipStream_t st) {
-    hipLaunchKernelGGL(exclusive_scan_1wg, dim3(1), dim3(1024), 0, st, in, n, off);
+int64_t scan_ws_words(int64_t n) {
+    const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return nt <= SCAN_SMALL_TILES ? 0 : 2 * (nt + 1) + 64;
+}
+
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, uint32_t* ws, hipStream_t st) {
+    const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nt <= SCAN_SMALL_TILES) {
+        hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(SCAN_T), 0, st, in, n, (const uint32_t*)nullptr,
+                           (int)(nt > 0 ? nt : 1), off);
+        return hipGetLastError();
+    }
+    if (nt > 0x7fffffff || !ws) return hipErrorInvalidValue;
+    uint32_t* sums = ws;
+    uint32_t* soff = ws + nt + 1;
+    hipLaunchKernelGGL(scan_reduce, dim3((unsigned)nt), dim3(SCAN_T), 0, st, in, n, sums);
+    hipLaunchKernelGGL(exclusive_scan_1wg, dim3(1), dim3(1024), 0, st, sums, nt, soff);
+    hipLaunchKernelGGL(scan_tiles, dim3((unsigned)nt), dim3(SCAN_T), 0, st, in, n, soff, 1, off);
     return hipGetLastError();
 }
 
-
 // Sorts n pairs by the low `bits` (<= 32) bits of the key in ceil(bits / 10) passes of equal
-// digits (<= 10 bits).  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of
-// (1024 * ceil(n / RS_TILE) + 1) words.  The result always ends in (keys, vals).
+// digits (<= 10 bits).  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of radix_hist_words(n)
+// words (the histogram, its scan, and the scan's workspace at the end of off).  The result always
+// ends in (keys, vals).
 template <int DB>
 static hipError_t rs_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int64_t n, int shift,
                           int nblocks, uint32_t* hist, uint32_t* off, hipStream_t st) {
     hipLaunchKernelGGL((rs_hist<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, n, shift, nblocks, hist);
-    hipLaunchKernelGGL(exclusive_scan_1wg, dim3(1), dim3(1024), 0, st, hist, (int64_t)(1 << DB) * nblocks, off);
+    const int64_t m = (int64_t)(1 << DB) * nblocks;
+    hipError_t e = launch_exclusive_scan(hist, m, off, off + (int64_t)1024 * nblocks + 1, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((rs_scatter<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, shift, nblocks, off, ko,
                        vo);
     return hipGetLastError();
 }
 
-int64_t radix_hist_words(int64_t n) { return (int64_t)1024 * ((n + RS_TILE - 1) / RS_TILE) + 1; }
+int64_t radix_hist_words(int64_t n) {
+    const int64_t m = (int64_t)1024 * ((n + RS_TILE - 1) / RS_TILE);
+    return m + 1 + scan_ws_words(m);
+}
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st) {

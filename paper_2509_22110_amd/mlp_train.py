@@ -5,7 +5,9 @@ evaluation workloads use seed 0): real spherical-harmonic deformations of random
 amplitude, some with an inward bump that brings two sheets together.  For every shape the
 library's tree walk emits samples (features of a (face, far cluster) pair and the exact-minus-
 monopole correction of the face's row sums, see tpe_farfield_samples); the network is then trained
-with the library's BF16-MFMA forward/backward and Adam kernels.
+with the library's BF16-MFMA forward/backward and Adam kernels on per-output normalized targets.
+Finally the far field's errors with each output group (K, Sd, C) applied are reported on held-out
+level-6 and level-7 shapes (seeds disjoint from training and evaluation).
 
     python -m paper_2509_22110_amd.mlp_train --out paper_2509_22110_amd/data/farfield_mlp.bin
 """
@@ -20,17 +22,18 @@ import time
 import numpy as np
 import torch
 
-from . import MLP, build_tree, farfield_samples
+from . import MLP, build_tree, farfield, farfield_samples, gradient
 from . import meshes as M
 
 NOUT = 7  # used outputs: K, Sd (3), C (3)
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "farfield_mlp.bin")
 
 
-def training_shape(seed: int):
+def training_shape(seed: int, level: int | None = None):
     """A seeded level-5 or level-6 deformed sphere (never seed 0, the evaluation seed)."""
     rng = np.random.default_rng(seed)
-    level = 6 if seed % 4 == 0 else 5
+    if level is None:
+        level = 6 if seed % 4 == 0 else 5
     X, F = M.icosphere(level)
     lmax = int(rng.choice([8, 12, 16]))
     amp = float(rng.uniform(0.05, 0.2))
@@ -136,6 +139,48 @@ def train(mlp, X, T, epochs=8, batch=8192, lr=2e-3, seed=0, log=print, Xv=None, 
     return mlp
 
 
+GROUPS = {"K": (0,), "Sd": (1, 2, 3), "C": (4, 5, 6)}
+
+
+def group_report(mlp, shapes, theta=0.5, log=print):
+    """Far-field errors on held-out shapes with each subset of the output groups (K, Sd, C) applied.
+
+    Per-sample MSE does not control how the correction varies from face to face, which is what the
+    vertex gradient sees (it differentiates the per-face row sums across each vertex's fan), so
+    this reports, per subset, the max-norm gradient error and the energy error against the exact
+    path, averaged over the shapes.  The network is left as it was.  Returns {subset: (grad, E)}."""
+    import itertools
+    p0 = mlp.get_params()
+    names = list(GROUPS)
+    subsets = [()] + [c for k in range(1, len(names) + 1) for c in itertools.combinations(names, k)]
+    score = {sub: [0.0, 0.0] for sub in subsets}
+    try:
+        for X, F in shapes:
+            Xd = torch.from_numpy(X).cuda()
+            Fd = torch.from_numpy(F).cuda()
+            E0, G0 = gradient(Xd, Fd)
+            g0, e0 = float(G0.abs().max()), float(E0)
+            tree = build_tree(Xd, Fd, leaf=32)
+            for sub in subsets:
+                keep = {j for g in sub for j in GROUPS[g]}
+                mlp.set_params(p0)
+                fold_scales(mlp, torch.ones(NOUT), keep)
+                E, G = farfield(tree, Xd, Fd, theta=theta, mlp=mlp if keep else None)
+                score[sub][0] += float((G - G0).abs().max()) / g0 / len(shapes)
+                score[sub][1] += abs(float(E) - e0) / abs(e0) / len(shapes)
+    finally:
+        mlp.set_params(p0)
+    for sub in subsets:
+        log(f"  groups {'+'.join(sub) or '(none)':8s}: mean rel grad err {score[sub][0]:.3e}, "
+            f"mean rel energy err {score[sub][1]:.3e}")
+    return {sub: tuple(v) for sub, v in score.items()}
+
+
+def report_shapes(seeds=(1196, 1197, 1198, 1199)):
+    """Held-out shapes for group_report: two level-6 and two level-7 deformed spheres."""
+    return [training_shape(s, level=6 if i < len(seeds) // 2 else 7) for i, s in enumerate(seeds)]
+
+
 def fit(X, T, Xv, Tv, epochs=8, seed=0, log=print, max_ratio=1.0):
     """Train on per-output normalized targets, fold the scales back into the last layer, and keep
     only the outputs that beat the zero correction on the validation set (ratio < max_ratio)."""
@@ -172,6 +217,8 @@ def main(argv=None):
     Xv, Tv = collect(seeds[-nval:], theta=args.theta, log=log)
     log(f"samples: train {X.shape[0]}, val {Xv.shape[0]} ({time.time() - t0:.1f} s)")
     mlp = fit(X, T, Xv, Tv, epochs=args.epochs, seed=args.first_seed, log=log)
+    log("far-field errors by applied output group on held-out level-6/7 shapes:")
+    group_report(mlp, report_shapes(), theta=args.theta, log=log)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     mlp.save(args.out)
     log(f"saved {args.out}; val loss {evaluate(mlp, Xv, Tv):.4e} vs zero-prediction {zero_loss(Tv):.4e}")
