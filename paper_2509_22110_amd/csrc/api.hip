@@ -2,10 +2,10 @@
 //
 // Pipeline of one tpe_gradient call (all on the context's stream, no host synchronisation
 // unless sync checks are on):
-//   init_scratch -> face_bbox -> morton_keys -> radix sort (3 or 4 passes) -> face_records
-//   (+ per-vertex corner counts) -> vertex->corner CSR (scan, fill, per-vertex sort)
-//   -> tile-pair exclusion map -> pair_kernel (exact all-pairs row sums) -> merge_segments
-//   -> finalize (FP64 adjoint, energy) -> vertex_gather.
+//   init_scratch -> face_bbox -> morton_keys -> radix sort (2 or 3 passes) -> face_records
+//   (+ per-vertex corner counts) -> vertex->corner CSR (scan, fill)
+//   -> tile-pair exclusion map -> pair_kernel (exact all-pairs row sums, compensated segments)
+//   -> finalize (FP64 merge of the segments, adjoint, energy) -> vertex_gather (ascending order).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -40,11 +40,10 @@ Sched make_sched(int64_t Fp, int waves);
 int64_t pair_part_floats(const Sched& sc, bool grad);
 hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                        const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st);
-hipError_t launch_merge(bool grad, const float* part, const Sched& sc, int64_t Fp, double* acc, hipStream_t st);
-hipError_t launch_finalize(bool grad, int64_t Fp, int64_t nF, const double* acc64, const double* geo,
-                           const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
-                           double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
-                           hipStream_t st);
+hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
+                           const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
+                           double p, double scale, double* corner, double* epart, uint32_t* ticket, uint32_t* flags,
+                           double* E, hipStream_t st);
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
                          hipStream_t st);
 int finalize_blocks(int64_t nF);
@@ -362,8 +361,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     }
     HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
     if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
-    HIPCHK(launch_merge(grad, P.part, P.sc, P.Fp, P.acc64, st));
-    HIPCHK(launch_finalize(grad, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
+    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
                            P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -562,7 +560,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
     if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
-    HIPCHK(launch_finalize(true, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
+    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
                            P.ticket, ctx->dflags, E_dev, st));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
     if (ctx->sync_checks) return report_flags(ctx);

@@ -1,6 +1,7 @@
-// Finalize: turn the per-face row sums (merged in FP64 by merge_segments) into the
-// gradient contributions of the face's three corners, and reduce the energy; then the
-// scatter-free vertex gather.  No floating-point atomics anywhere: every sum has a fixed order.
+// Finalize: merge the per-face row sums in FP64 (the pair kernel's compensated partial segments,
+// or the far-field walk's FP64 sums), turn them into the gradient contributions of the face's
+// three corners, and reduce the energy; then the scatter-free vertex gather.  No floating-point
+// atomics anywhere: every sum has a fixed order.
 //
 // With the row sums of pair.hip (K, S0, Sd, Sdd, Sn) for face S and the kernel k = t^q with
 // p = 2q, the partial derivatives of E with respect to the face's own geometry are
@@ -20,11 +21,35 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
+// Row sums of face i: from the pair kernel's segments (part != null: the (hi, lo) FP32 pairs of
+// every wave whose range covers row i's block, added in FP64 in wave order), else acc64[k][i].
+// The covering waves are the same for the whole wave of threads (ROWB is a multiple of 64), so
+// the schedule's divisions run once per wave, on wave-uniform values.
+template <int NA>
+__device__ __forceinline__ void row_sums(const float* __restrict__ part, const Sched& sc,
+                                         const double* __restrict__ accs, int64_t Fp, int64_t i, double (&acc)[NA]) {
+    if (!part) {
+        for (int k = 0; k < NA; ++k) acc[k] = accs[(size_t)k * Fp + i];
+        return;
+    }
+    const int rr = (int)(i % ROWB);
+    const int rb = __builtin_amdgcn_readfirstlane((int)(i / ROWB));
+    const int w0 = __builtin_amdgcn_readfirstlane(sc.wave_of((int64_t)rb * sc.upr));
+    const int w1 = __builtin_amdgcn_readfirstlane(sc.wave_of((int64_t)(rb + 1) * sc.upr - 1));
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+    for (int w = w0; w <= w1; ++w) {
+        const int seg = __builtin_amdgcn_readfirstlane(rb - (int)(sc.begin(w) / sc.upr));
+        const float* ps = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB + rr;
+        for (int k = 0; k < NA; ++k) acc[k] += (double)ps[(size_t)k * ROWB] + (double)ps[(size_t)(NA + k) * ROWB];
+    }
+}
+
 // One thread per sorted face; every work-group writes one FP64 energy partial and the last
 // work-group to finish (ticket counter, zero on entry) adds the partials in index order, so the
 // energy is deterministic.
 template <bool GRAD>
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ accs, int64_t Fp, int64_t nF,
+__global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__ part, Sched sc,
+                                                       const double* __restrict__ accs, int64_t Fp, int64_t nF,
                                                        const double* __restrict__ geo,
                                                        const int4* __restrict__ colv,
                                                        const double* __restrict__ X,
@@ -44,7 +69,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     const double gs = scale * pow2i(kexp, p - q - 3.0);
     if (i < nF) {
         double acc[NA];
-        for (int k = 0; k < NA; ++k) acc[k] = accs[(size_t)k * Fp + i];
+        row_sums<NA>(part, sc, accs, Fp, i, acc);
         const double a = geo[5 * i + 0], wn = geo[5 * i + 1];
         const double n[3] = {geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]};
         bool finite = true;
@@ -103,15 +128,24 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     if (threadIdx.x == 0 && E) E[0] = scale * pow2i(kexp, p - q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
 }
 
-// G[v] = sum over the (sorted face, corner) slots incident to v, ascending slot order.
+// G[v] = sum over the (sorted face, corner) slots incident to v, in ascending slot order: the
+// list of v (filled in arbitrary order) is walked by repeatedly taking its smallest entry above
+// the last one taken (slots are distinct), so the sum is deterministic without sorting the list.
 __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list, int64_t V,
                               const double* __restrict__ corner, double* __restrict__ G) {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= V) return;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     const uint32_t b = off[v], e = off[v + 1];
-    for (uint32_t k = b; k < e; ++k) {
-        const double* c = corner + 3 * (size_t)list[k];
+    uint32_t last = 0;
+    for (uint32_t n = b; n < e; ++n) {
+        uint32_t m = 0xffffffffu;
+        for (uint32_t k = b; k < e; ++k) {
+            const uint32_t x = list[k];
+            if ((n == b || x > last) && x < m) m = x;
+        }
+        last = m;
+        const double* c = corner + 3 * (size_t)m;
         g0 += c[0];
         g1 += c[1];
         g2 += c[2];
@@ -123,18 +157,19 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 
-// acc64: NA x Fp merged row sums; ticket: one word, zero on entry.
-hipError_t launch_finalize(bool grad, int64_t Fp, int64_t nF, const double* acc64, const double* geo,
-                           const int4* colv, const double* X, const uint32_t* bbox, double q, double p, double scale,
-                           double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
-                           hipStream_t st) {
+// Row sums: the pair kernel's segments (part, sc) or, with part null, acc64 (NA x Fp FP64);
+// ticket: one word, zero on entry.
+hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
+                           const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
+                           double p, double scale, double* corner, double* epart, uint32_t* ticket, uint32_t* flags,
+                           double* E, hipStream_t st) {
     const int nb = finalize_blocks(nF);
     if (grad)
-        hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, acc64, Fp, nF, geo, colv, X, bbox, q, p,
-                           scale, corner, epart, ticket, E, flags);
+        hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
+                           bbox, q, p, scale, corner, epart, ticket, E, flags);
     else
-        hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, acc64, Fp, nF, geo, colv, X, bbox, q,
-                           p, scale, corner, epart, ticket, E, flags);
+        hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
+                           bbox, q, p, scale, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

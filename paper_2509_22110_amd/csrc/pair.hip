@@ -214,24 +214,6 @@ __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ c
     }
 }
 
-// acc[k][i] = sum, in wave order, of the segments covering row i's block: (hi + lo) in FP64.
-// One thread per (accumulator k = blockIdx.y, row i).
-__global__ __launch_bounds__(256) void merge_segments(const float* __restrict__ part, Sched sc, int NA, int64_t Fp,
-                                                      double* __restrict__ acc) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (i >= Fp) return;
-    const int rb = (int)(i / ROWB), rr = (int)(i % ROWB);
-    const int w0 = sc.wave_of((int64_t)rb * sc.upr), w1 = sc.wave_of((int64_t)(rb + 1) * sc.upr - 1);
-    double s = 0.0;
-    for (int w = w0; w <= w1; ++w) {
-        const int seg = rb - (int)(sc.begin(w) / sc.upr);
-        const float* ps = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB;
-        s += (double)ps[(size_t)k * ROWB + rr] + (double)ps[(size_t)(NA + k) * ROWB + rr];
-    }
-    acc[(size_t)k * Fp + i] = s;
-}
-
 int pair_blocks_per_cu(bool grad) {
     int nb = 0;
     hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, true>, WAVE, 0)
@@ -262,12 +244,6 @@ hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const do
     else
         hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE), 0, st, cols, colv, c64, org, touch,
                            touch_words, sc, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge(bool grad, const float* part, const Sched& sc, int64_t Fp, double* acc, hipStream_t st) {
-    const int NA = grad ? NACC : 1;
-    hipLaunchKernelGGL(merge_segments, dim3((unsigned)((Fp + 255) / 256), NA), dim3(256), 0, st, part, sc, NA, Fp, acc);
     return hipGetLastError();
 }
 

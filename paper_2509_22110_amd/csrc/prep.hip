@@ -243,19 +243,6 @@ __global__ void corner_fill(const int4* __restrict__ colv, int64_t nF, int64_t V
         }
 }
 
-// Sort each vertex's list ascending (insertion sort): makes the gather order deterministic.
-__global__ void corner_sort(const uint32_t* __restrict__ off, int64_t V, uint32_t* __restrict__ list) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    uint32_t b = off[v], e = off[v + 1];
-    for (uint32_t i = b + 1; i < e; ++i) {
-        uint32_t x = list[i];
-        uint32_t j = i;
-        while (j > b && list[j - 1] > x) { list[j] = list[j - 1]; --j; }
-        list[j] = x;
-    }
-}
-
 // Exclusion map: bit (rb, c) set iff some row of row block rb shares a vertex with some column of
 // the c-th chunk of CHUNK columns.  Rows/columns are sorted positions.  One work-group per row block builds its
 // row of the map in LDS (dynamic shared memory, touch_words words) and stores it: no global
@@ -332,7 +319,6 @@ hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* c
     hipError_t e = launch_exclusive_scan(cnt, V, off, ws, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(corner_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, colv, nF, V, off, cursor, list);
-    hipLaunchKernelGGL(corner_sort, dim3(nblk(V, 256)), dim3(256), 0, st, off, V, list);
     return hipGetLastError();
 }
 
