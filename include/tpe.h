@@ -61,8 +61,8 @@ typedef enum {
 typedef enum {
     TPE_OPT_SYNC_CHECKS = 1,  /* 1 (default): every call synchronises and reports device-side
                                  errors; 0: calls stay asynchronous, tpe_check() reports */
-    TPE_OPT_TARGET_WAVES = 2, /* waves (work-groups) of the persistent exact pair kernel; 0
-                                 (default) = as many as the device keeps resident at once.  The
+    TPE_OPT_TARGET_WAVES = 2, /* work-groups (of 4 waves) of the persistent exact pair kernel;
+                                 0 (default) = as many as the device keeps resident at once.  The
                                  work is split evenly over them; results agree to rounding */
     TPE_OPT_KERNEL_TIMING = 3 /* 1: record HIP events around every launch of the dominant
                                  kernel (the pair kernel) on the context's stream, read back

@@ -15,7 +15,8 @@ enum : uint32_t {
 // Geometry of the exact all-pairs kernel.
 constexpr int WAVE = 64;
 constexpr int RPL = 2;                  // rows (target faces) per lane
-constexpr int ROWB = WAVE * RPL;        // rows per wave (one wave per work-group)
+constexpr int ROWB = WAVE * RPL;        // rows of a row block (held by each wave of a work-group)
+constexpr int PAIR_NW = 4;              // waves per pair-kernel work-group (split a row block's columns)
 constexpr int CTILE = 256;              // columns per tile (one FP64 origin per tile)
 constexpr int CHUNK = 64;               // columns summed in plain FP32 before a compensated fold
 constexpr int NACC = 11;                // accumulators per row face (see pair.hip)
@@ -28,16 +29,17 @@ struct __align__(32) ColRec {
 
 // Balanced persistent schedule.  The work is U = nrb * upr units, a unit being one chunk of CHUNK
 // columns for one row block of ROWB rows (upr = Fp / CHUNK units per row block, in column order).
-// Wave w of W takes the contiguous units [floor(w U / W), floor((w+1) U / W)), so every wave does
-// the same work to within one unit and, with W equal to the number of resident waves, the launch
-// has no tail.  A wave's range may cover the end of one row block and the start of the next: it
-// writes one partial-sum segment per row block it touches (at most maxseg), and the merge pass
-// adds, for each row block, the segments of the waves that cover it, in wave order.
+// Work-group w of W takes the contiguous units [floor(w U / W), floor((w+1) U / W)), so every
+// work-group does the same work to within one unit and, with W equal to the number of resident
+// work-groups, the launch has no tail.  A range may cover the end of one row block and the start
+// of the next: the work-group writes one partial-sum segment per row block it touches (at most
+// maxseg), and the finalize pass adds, for each row block, the segments of the work-groups that
+// cover it, in work-group order.
 struct Sched {
     int64_t U;
     int W, upr, maxseg;
     __host__ __device__ int64_t begin(int w) const { return (int64_t)w * U / W; }
-    // the wave whose range contains unit x
+    // the work-group whose range contains unit x
     __host__ __device__ int wave_of(int64_t x) const { return (int)(((x + 1) * (int64_t)W - 1) / U); }
 };
 

@@ -14,11 +14,14 @@
 //     Sn  = sum s' n_T                       -> reverse d/dc_S, along n_T
 // (11 scalars).  The finalize pass turns them into corner gradients in FP64.
 //
-// MI355X mapping: one wave64 per work-group holds ROWB = 128 row faces (2 per lane) in VGPRs.
-// The launch is persistent and balanced (see Sched below).
+// MI355X mapping: every wave64 holds a row block of ROWB = 128 row faces (2 per lane) in VGPRs.
+// The launch is persistent and balanced (see Sched in common.hpp) over work-groups of PAIR_NW
+// waves: the waves of a work-group take contiguous quarters of the same row block's column range
+// and hand their compensated sums to wave 0 through LDS, which adds them in FP64 and writes one
+// partial-sum segment for the work-group (a quarter of the segment traffic of one-wave groups).
 // All lanes visit the same column at the same time, so column records are wave-uniform and are
-// fetched with scalar loads into SGPRs (one 32-byte record per column); no LDS is needed and every
-// VALU instruction takes the column operand straight from an SGPR.  Columns come in tiles of 256
+// fetched with scalar loads into SGPRs (one 32-byte record per column); every VALU instruction
+// takes the column operand straight from an SGPR.  Columns come in tiles of 256
 // faces stored relative to an FP64 tile origin; each row re-expresses its centroid relative to
 // that origin once per tile, so nearby pairs see small, accurately rounded coordinates.  FP32 sums
 // run over CHUNK columns and are folded into Kahan-compensated (hi, lo) FP32 pairs.  (Row block,
@@ -140,25 +143,32 @@ __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const 
         for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
 }
 
-// grid: W work-groups of one wave.  part layout: [W * maxseg segments][2 * NA][ROWB] FP32; the
-// first NA rows of a segment hold hi, the next NA the compensation to ADD (-c of Kahan's error).
+// grid: W work-groups of PAIR_NW waves.  part layout: [W * maxseg segments][2 * NA][ROWB] FP32;
+// the first NA rows of a segment hold hi, the next NA the compensation to add (the work-group's
+// waves' compensated sums folded into wave 0's).
 template <int Q, bool GRAD>
-__global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ cols,
-                                                    const int4* __restrict__ colv,
-                                                    const double* __restrict__ c64,
-                                                    const double* __restrict__ org,
-                                                    const uint32_t* __restrict__ touch, int touch_words,
-                                                    Sched sc, float* __restrict__ part) {
+__global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __restrict__ cols,
+                                                              const int4* __restrict__ colv,
+                                                              const double* __restrict__ c64,
+                                                              const double* __restrict__ org,
+                                                              const uint32_t* __restrict__ touch, int touch_words,
+                                                              Sched sc, float* __restrict__ part) {
     constexpr int NA = GRAD ? NACC : 1;
     constexpr int CPT = CTILE / CHUNK;  // chunks per tile
-    const int lane = threadIdx.x;
-    const int w = blockIdx.x;
-    int64_t u = sc.begin(w);
-    const int64_t u1 = sc.begin(w + 1);
+    // waves 1.. hand their (hi, -c) to wave 0: [PAIR_NW - 1][2 NA][ROWB] floats of dynamic LDS (static
+    // LDS of this size makes the compiler give up on occupancy and spend registers)
+    extern __shared__ float red_lds[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform (SGPR)
+    const int g = blockIdx.x;
+    int64_t u = sc.begin(g);
+    const int64_t u1 = sc.begin(g + 1);
     int seg = 0;
-    while (u < u1) {
+    while (u < u1) {  // uniform over the work-group
         const int rb = (int)(u / sc.upr);
         const int64_t uend = min(u1, (int64_t)(rb + 1) * sc.upr);
+        const int64_t len = uend - u;
+        const int64_t my0 = u + len * wave / PAIR_NW, my1 = u + len * (wave + 1) / PAIR_NW;
         double cxd[RPL], cyd[RPL], czd[RPL];
         float nx[RPL], ny[RPL], nz[RPL];
         int rv[RPL][3];
@@ -179,8 +189,8 @@ __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ c
         const uint32_t* my_touch = touch + (size_t)rb * touch_words;
         int cur_t = -1;
         float rx[RPL], ry[RPL], rz[RPL];
-        for (; u < uend; ++u) {
-            const int cu = (int)(u - (int64_t)rb * sc.upr);
+        for (int64_t x = my0; x < my1; ++x) {
+            const int cu = (int)(x - (int64_t)rb * sc.upr);
             const int t = cu / CPT;
             if (t != cur_t) {
                 // rows relative to this tile's FP64 origin (columns are stored relative to it)
@@ -201,23 +211,51 @@ __global__ __launch_bounds__(WAVE) void pair_kernel(const ColRec* __restrict__ c
             else
                 chunk_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
         }
-        float* out = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB;
+        if (wave > 0) {
+            float* mine = red_lds + (size_t)(wave - 1) * 2 * NA * ROWB + lane;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
+            for (int r = 0; r < RPL; ++r)
 #pragma unroll
-            for (int k = 0; k < NA; ++k) {
-                out[(size_t)k * ROWB + r * WAVE + lane] = hi[r][k];
-                out[(size_t)(NA + k) * ROWB + r * WAVE + lane] = -lo[r][k];
+                for (int k = 0; k < NA; ++k) {
+                    mine[k * ROWB + r * WAVE] = hi[r][k];
+                    mine[(NA + k) * ROWB + r * WAVE] = -lo[r][k];
+                }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // compensated FP32 sum of the four waves' (hi, -c) pairs, in wave order
+            const float* theirs = red_lds + lane;
+            float* out = part + ((size_t)g * sc.maxseg + seg) * 2 * NA * ROWB + lane;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+                for (int k = 0; k < NA; ++k) {
+#pragma unroll
+                    for (int j = 0; j < PAIR_NW - 1; ++j) {
+                        kahan_fold(theirs[(j * 2 * NA + k) * ROWB + r * WAVE], hi[r][k], lo[r][k]);
+                        kahan_fold(theirs[(j * 2 * NA + NA + k) * ROWB + r * WAVE], hi[r][k], lo[r][k]);
+                    }
+                    out[(size_t)k * ROWB + r * WAVE] = hi[r][k];
+                    out[(size_t)(NA + k) * ROWB + r * WAVE] = -lo[r][k];
+                }
+                // one row's LDS loads in flight at a time (keeps the register count at the loop's)
+                asm volatile("" ::: "memory");
             }
         }
+        __syncthreads();
+        u = uend;
         ++seg;
     }
 }
 
+static size_t pair_lds_bytes(bool grad) { return sizeof(float) * (PAIR_NW - 1) * 2 * (grad ? NACC : 1) * ROWB; }
+
 int pair_blocks_per_cu(bool grad) {
     int nb = 0;
-    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, true>, WAVE, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, false>, WAVE, 0);
+    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, true>, WAVE * PAIR_NW,
+                                                                       pair_lds_bytes(true))
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_kernel<6, false>, WAVE * PAIR_NW,
+                                                                       pair_lds_bytes(false));
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
@@ -239,11 +277,11 @@ int64_t pair_part_floats(const Sched& sc, bool grad) {
 hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                        const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st) {
     if (grad)
-        hipLaunchKernelGGL((pair_kernel<6, true>), dim3(sc.W), dim3(WAVE), 0, st, cols, colv, c64, org, touch,
-                           touch_words, sc, part);
+        hipLaunchKernelGGL((pair_kernel<6, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true), st, cols,
+                           colv, c64, org, touch, touch_words, sc, part);
     else
-        hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE), 0, st, cols, colv, c64, org, touch,
-                           touch_words, sc, part);
+        hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(false), st, cols,
+                           colv, c64, org, touch, touch_words, sc, part);
     return hipGetLastError();
 }
 

@@ -167,7 +167,7 @@ def test_split_independence(waves):
     try:
         E, G = T.gradient(Xd, Fd)
     finally:
-        ctx.set_option(T.OPT_TARGET_WAVES, 8192)
+        ctx.set_option(T.OPT_TARGET_WAVES, 0)
     assert rel_energy(float(E.cpu()), Eo) <= E_TOL
     assert rel_grad_maxnorm(G.cpu().numpy(), Go) <= G_TOL
 
