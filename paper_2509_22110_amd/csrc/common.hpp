@@ -17,7 +17,7 @@ constexpr int WAVE = 64;
 constexpr int RPL = 2;                  // rows (target faces) per lane
 constexpr int ROWB = WAVE * RPL;        // rows of a row block (held by each wave of a work-group)
 constexpr int PAIR_NW = 4;              // waves per pair-kernel work-group (split a row block's columns)
-constexpr int CTILE = 256;              // columns per tile (one FP64 origin per tile)
+constexpr int CTILE = 64;               // columns per tile (one FP64 origin per tile = per chunk)
 constexpr int CHUNK = 64;               // columns summed in plain FP32 before a compensated fold
 constexpr int NACC = 11;                // accumulators per row face (see pair.hip)
 

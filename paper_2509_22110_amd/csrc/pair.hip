@@ -17,13 +17,14 @@
 // MI355X mapping: every wave64 holds a row block of ROWB = 128 row faces (2 per lane) in VGPRs.
 // The launch is persistent and balanced (see Sched in common.hpp) over work-groups of PAIR_NW
 // waves: the waves of a work-group take contiguous quarters of the same row block's column range
-// and hand their compensated sums to wave 0 through LDS, which adds them in FP64 and writes one
-// partial-sum segment for the work-group (a quarter of the segment traffic of one-wave groups).
+// and hand their compensated sums to wave 0 through LDS, which folds them into its own and writes
+// one partial-sum segment for the work-group (a quarter of the segment traffic of one-wave groups).
 // All lanes visit the same column at the same time, so column records are wave-uniform and are
 // fetched with scalar loads into SGPRs (one 32-byte record per column); every VALU instruction
-// takes the column operand straight from an SGPR.  Columns come in tiles of 256
-// faces stored relative to an FP64 tile origin; each row re-expresses its centroid relative to
-// that origin once per tile, so nearby pairs see small, accurately rounded coordinates.  FP32 sums
+// takes the column operand straight from an SGPR.  Columns come in chunks of 64 faces stored
+// relative to an FP64 origin at the centre of the chunk's centroid box; each row re-expresses its
+// centroid relative to that origin once per chunk, so nearby pairs see small, accurately rounded
+// coordinates (what limits the accuracy of nearly touching pairs).  FP32 sums
 // run over CHUNK columns and are folded into Kahan-compensated (hi, lo) FP32 pairs.  (Row block,
 // chunk) pairs in which some row shares a vertex with some column (a few percent, faces being in
 // Morton order) take a masked variant that compares vertex indices; all others run with no

@@ -139,39 +139,36 @@ __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32
 //   c64[i]   : centroid (FP64)
 //   org[t]   : FP64 origin of tile t = centroid of its first face
 //   geo[i]   : FP64 {a, |w|, n.x, n.y, n.z} for the finalize pass
+__device__ __forceinline__ double wave_min(double x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off));
+    return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
+// One thread per sorted position i < Fp (whole waves: Fp is a multiple of 128).  A wave covers one
+// chunk of CTILE = 64 positions; the chunk's FP64 origin is the centre of its faces' centroid
+// bounding box, so the FP32 record coordinates relative to it are at most half the chunk's
+// extent (their rounding error sets the accuracy of the closest pairs).
 __global__ void face_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
                              int64_t nF, int64_t Fp, const uint32_t* __restrict__ perm,
                              const uint32_t* __restrict__ bbox, double* __restrict__ org,
                              ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
                              double* __restrict__ geo, uint32_t* __restrict__ cnt,
                              uint32_t* __restrict__ flags) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= Fp) return;
     const double s = norm_scale(bbox);
-    const int t = (int)(i / CTILE);
-    // tile origin = scaled centroid of the tile's first face (every thread of the tile derives
-    // the same value; the first thread stores it for the pair kernel)
-    double o[3] = {0.0, 0.0, 0.0};
-    {
-        const int64_t i0 = (int64_t)t * CTILE;
-        if (i0 < nF) {
-            const int64_t f0 = perm[i0];
-            const int32_t u0 = F[3 * f0], u1 = F[3 * f0 + 1], u2 = F[3 * f0 + 2];
-            if (u0 >= 0 && u0 < V && u1 >= 0 && u1 < V && u2 >= 0 && u2 < V)
-                for (int d = 0; d < 3; ++d) {
-                    const double od = s * (X[3 * (int64_t)u0 + d] + X[3 * (int64_t)u1 + d] +
-                                           X[3 * (int64_t)u2 + d]) / 3.0;
-                    o[d] = isfinite(od) ? od : 0.0;
-                }
-        }
-        if (i == i0)
-            for (int d = 0; d < 3; ++d) org[3 * t + d] = o[d];
-    }
-    ColRec r;
-    if (i < nF) {
-        int64_t f = perm[i];
-        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
-        bool ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
+    bool real = i < nF, ok = false;
+    int32_t v[3] = {-1, -1, -1};
+    double a = 0.0, wn = 1.0, n[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
+    uint32_t fl = 0;
+    if (real) {
+        const int64_t f = perm[i];
+        v[0] = F[3 * f]; v[1] = F[3 * f + 1]; v[2] = F[3 * f + 2];
+        ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
         double xi[3] = {0, 0, 0}, xj[3] = {1, 0, 0}, xk[3] = {0, 1, 0};
         if (ok)
             for (int d = 0; d < 3; ++d) {
@@ -182,24 +179,36 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         bool fin = true;
         for (int d = 0; d < 3; ++d) fin &= isfinite(xi[d]) && isfinite(xj[d]) && isfinite(xk[d]);
         if (!fin) {  // reported as non-finite input, not as a degenerate face
-            atomicOr(flags, (uint32_t)FLAG_NONFINITE);
+            fl |= FLAG_NONFINITE;
             for (int d = 0; d < 3; ++d) { xi[d] = 0.0; xj[d] = d == 0 ? 1.0 : 0.0; xk[d] = d == 1 ? 1.0 : 0.0; }
         }
-        double e1[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
-        double e2[3] = {xk[0] - xi[0], xk[1] - xi[1], xk[2] - xi[2]};
-        double w[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                       e1[0] * e2[1] - e1[1] * e2[0]};
-        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-        double a = 0.5 * wn;
-        uint32_t fl = 0;
+        const double e1[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        const double e2[3] = {xk[0] - xi[0], xk[1] - xi[1], xk[2] - xi[2]};
+        const double w[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        a = 0.5 * wn;
         if (!(a > 1e-300 * s * s)) { fl |= FLAG_DEGENERATE; wn = 1.0; a = 0.0; }
-        double n[3] = {w[0] / wn, w[1] / wn, w[2] / wn};
-        double c[3];
+        for (int d = 0; d < 3; ++d) n[d] = w[d] / wn;
         for (int d = 0; d < 3; ++d) c[d] = (xi[d] + xj[d] + xk[d]) / 3.0;
         if (!isfinite(c[0] + c[1] + c[2] + n[0] + n[1] + n[2])) {
             fl |= FLAG_NONFINITE;
             c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
         }
+    }
+    // chunk origin: centre of the bounding box of the chunk's real centroids (0 if none)
+    const bool inbox = real && ok && !(fl & FLAG_NONFINITE);
+    double o[3];
+    const bool any = __ballot(inbox) != 0ull;
+    for (int d = 0; d < 3; ++d) {
+        const double lo = wave_min(inbox ? c[d] : INFINITY);
+        const double hi = wave_max(inbox ? c[d] : -INFINITY);
+        o[d] = any ? 0.5 * (lo + hi) : 0.0;
+    }
+    if ((i % CTILE) == 0)
+        for (int d = 0; d < 3; ++d) org[3 * (i / CTILE) + d] = o[d];
+    ColRec r;
+    if (real) {
         if (fl) atomicOr(flags, fl);
         r.cx = (float)(c[0] - o[0]);
         r.cy = (float)(c[1] - o[1]);

@@ -21,6 +21,8 @@ ALPHA = 6.0
 class FlowRecord:
     energies: list = field(default_factory=list)
     judge: list = field(default_factory=list)  # (step, rel grad max-norm error of the far field)
+    dts: list = field(default_factory=list)    # accepted step sizes (backtracking flow)
+    rejected: int = 0                          # trial steps rejected by the backtracking flow
 
 
 def gradient_flow(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=None, theta: float = 0.5,
@@ -52,4 +54,55 @@ def gradient_flow(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=
         rec.energies.append(e)
         prev = e
         X.add_(G, alpha=-dt)
+    return rec
+
+
+def gradient_flow_backtracking(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=None,
+                               theta: float = 0.5, mlp=None, judge_every: int = 0, max_halvings: int = 40,
+                               grow: float = 1.0, record: FlowRecord | None = None):
+    """Explicit Euler steps with step rejection: a trial X - dt G whose energy is not below the
+    current one is discarded and dt halved (at most `max_halvings` times per step, then
+    FloatingPointError).  An accepted step's energy and gradient serve the next step, so each
+    accepted step costs one evaluation; dt is multiplied by `grow` after an accepted step.
+    `energies[k]` is the energy at the start of step k; with `tree` the far field supplies E and G,
+    and every `judge_every`-th step the exact gradient at the same state judges it."""
+    rec = record if record is not None else FlowRecord()
+    bufs = [torch.empty_like(X), torch.empty_like(X)]
+    ens = [torch.empty((), dtype=torch.float64, device=X.device) for _ in range(2)]
+    Xt = torch.empty_like(X)
+
+    def evaluate(Y, G, E):
+        if tree is None:
+            gradient(Y, F, scale=scale, out=G, energy_out=E)
+        else:
+            farfield(tree, Y, F, theta=theta, scale=scale, mlp=mlp, out=G, energy_out=E)
+        e = float(E)
+        return e if e == e and abs(e) != float("inf") else float("inf")
+
+    cur = 0
+    e = evaluate(X, bufs[cur], ens[cur])
+    if e == float("inf"):
+        raise FloatingPointError("non-finite energy at the start")
+    for k in range(steps):
+        G = bufs[cur]
+        if tree is not None and judge_every and k % judge_every == 0:
+            _, Ge = gradient(X, F, scale=scale)
+            rec.judge.append((k, float((G - Ge).abs().max() / Ge.abs().max())))
+        rec.energies.append(e)
+        for _ in range(max_halvings + 1):
+            torch.add(X, G, alpha=-dt, out=Xt)
+            try:
+                et = evaluate(Xt, bufs[1 - cur], ens[1 - cur])
+            except Exception:  # a trial state the library rejects (e.g. touching faces)
+                et = float("inf")
+            if et < e:
+                break
+            rec.rejected += 1
+            dt *= 0.5
+        else:
+            raise FloatingPointError(f"no decrease within {max_halvings} halvings at step {k}")
+        X.copy_(Xt)
+        rec.dts.append(dt)
+        cur, e = 1 - cur, et
+        dt *= grow
     return rec

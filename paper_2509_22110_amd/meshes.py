@@ -130,14 +130,25 @@ def real_sph_harm(lmax: int, U: np.ndarray) -> np.ndarray:
     return out
 
 
+_SH_CHUNK = 32768  # vertices per evaluation of the basis for large meshes (bounds its memory)
+
+
+def _sh_field(U: np.ndarray, lmin: int, lmax: int, a: np.ndarray) -> np.ndarray:
+    """f(u) = sum_{l=lmin..lmax, m} a_lm Y_lm(u); meshes above 200,000 vertices are evaluated in
+    chunks of vertices so that the (lmax+1)^2 x n basis never exists at once."""
+    rows = np.arange(lmin * lmin, (lmax + 1) ** 2)
+    if U.shape[0] <= 200_000:
+        return a @ real_sph_harm(lmax, U)[rows]
+    return np.concatenate([a @ real_sph_harm(lmax, U[i:i + _SH_CHUNK])[rows]
+                           for i in range(0, U.shape[0], _SH_CHUNK)])
+
+
 def sh_deform(X: np.ndarray, lmin: int, lmax: int, coeff_std: float, seed: int):
     """r(u) = 1 + sum_{l=lmin..lmax, m} a_lm Y_lm(u),  a_lm ~ N(0, coeff_std^2)  on the unit directions of X."""
     rng = np.random.Generator(np.random.PCG64(seed))
     U = X / np.linalg.norm(X, axis=1, keepdims=True)
-    Y = real_sph_harm(lmax, U)
-    rows = np.arange(lmin * lmin, (lmax + 1) ** 2)
-    a = rng.normal(0.0, coeff_std, size=rows.size)
-    r = 1.0 + a @ Y[rows]
+    a = rng.normal(0.0, coeff_std, size=(lmax + 1) ** 2 - lmin * lmin)
+    r = 1.0 + _sh_field(U, lmin, lmax, a)
     if r.min() <= 0.2:
         raise ValueError("deformation not star-shaped enough (min r <= 0.2)")
     return U * r[:, None], a
@@ -147,10 +158,8 @@ def sh_deform_amplitude(X: np.ndarray, lmin: int, lmax: int, amplitude: float, s
     """White N(0,1) coefficients for l = lmin..lmax, rescaled so that max_v |r_v - 1| = amplitude."""
     rng = np.random.Generator(np.random.PCG64(seed))
     U = X / np.linalg.norm(X, axis=1, keepdims=True)
-    Y = real_sph_harm(lmax, U)
-    rows = np.arange(lmin * lmin, (lmax + 1) ** 2)
-    a = rng.normal(0.0, 1.0, size=rows.size)
-    f = a @ Y[rows]
+    a = rng.normal(0.0, 1.0, size=(lmax + 1) ** 2 - lmin * lmin)
+    f = _sh_field(U, lmin, lmax, a)
     a = a * (amplitude / np.abs(f).max())
     r = 1.0 + f * (amplitude / np.abs(f).max())
     if r.min() <= 0.2:
@@ -158,11 +167,12 @@ def sh_deform_amplitude(X: np.ndarray, lmin: int, lmax: int, amplitude: float, s
     return U * r[:, None], a
 
 
-def _min_dist(A: np.ndarray, B: np.ndarray) -> float:
+def _min_dist(A: np.ndarray, B: np.ndarray, upper: float = np.inf) -> float:
+    """Smallest distance between the point sets A and B; inf when it exceeds `upper`."""
     from scipy.spatial import cKDTree
     if A.shape[0] == 0 or B.shape[0] == 0:
         return float("inf")
-    d, _ = cKDTree(B).query(A, k=1)
+    d, _ = cKDTree(B).query(A, k=1, distance_upper_bound=upper)
     return float(d.min())
 
 
@@ -180,14 +190,27 @@ def bump(X: np.ndarray, axis_vertex: int = 0, width: float = 0.3, gap: float = 0
     def apply(D):
         return X - (D * prof)[:, None] * a[None, :]
 
+    cap = np.flatnonzero(prof > 0.5)
+    sheet = np.flatnonzero(prof < 1e-3)
+    if depth is not None:
+        Y = apply(depth)
+        return Y, depth, _min_dist(Y[cap], Y[sheet])
+    # The bisection only compares distances with `gap`, and reports the final one (~ gap).  The
+    # displacement is along a, so distances perpendicular to a do not depend on D: a pair closer
+    # than 2 gap is closer than 2 gap laterally.  Keeping only the sheet vertices within 2 gap of
+    # some cap vertex laterally, and searching only up to 2 gap, leaves every comparison and the
+    # reported gap exactly as over the whole sheet.
+    bound = 2.0 * gap
+    if cap.size and sheet.size:
+        from scipy.spatial import cKDTree
+        lat = X - (X @ a)[:, None] * a[None, :]
+        d_lat, _ = cKDTree(lat[cap]).query(lat[sheet], k=1, distance_upper_bound=bound)
+        sheet = sheet[np.isfinite(d_lat)]
+
     def gap_of(D):
         Y = apply(D)
-        cap = prof > 0.5
-        sheet = prof < 1e-3
-        return _min_dist(Y[cap], Y[sheet])
+        return _min_dist(Y[cap], Y[sheet], bound)
 
-    if depth is not None:
-        return apply(depth), depth, gap_of(depth)
     lo, hi = 0.0, float(np.linalg.norm(X[axis_vertex]) + np.max(np.linalg.norm(X, axis=1)))
     # gap_of is decreasing in D until contact; bisect on gap_of(D) - gap
     for _ in range(iters):

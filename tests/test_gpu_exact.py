@@ -114,6 +114,36 @@ def test_c3_parity_sampled():
     assert eG <= G_TOL
 
 
+@pytest.mark.parametrize("name", ["C4", "C5"])
+def test_full_size_sampled_parity(name):
+    """The level-7 (327,680 faces) and level-8 (1,310,720 faces, gap 0.01, degree-32 wrinkles)
+    workloads in the launch configuration bench.py times: the oracle's gradient at sampled
+    vertices (the 8 with the largest gradient -- nearly touching pairs -- and 8 random ones), and
+    identities that hold at any size: zero net force and torque, and Euler's identity
+    sum (x_v - x0) . G_v = (4 + q - p) E about the largest-gradient vertex x0, each relative to the
+    sum of the magnitudes of its terms."""
+    T = tpe()
+    c = M.make_config(name)
+    Xd, Fd = upload(c.X, c.F)
+    log(name, "exact start", c.nF)
+    E, G = T.gradient(Xd, Fd)
+    G = G.cpu().numpy()
+    E = float(E.cpu())
+    gn = np.abs(G).max(1)
+    rng = np.random.default_rng(0)
+    verts = np.unique(np.concatenate([np.argsort(-gn)[:8], rng.choice(c.V, 8, replace=False)])).astype(np.int32)
+    Go = oracle.gradient_at(c.X, c.F, verts)
+    eG = float(np.abs(G[verts] - Go).max() / np.abs(G).max())
+    x0 = c.X[np.argmax(gn)]
+    terms = ((c.X - x0) * G).sum(1)
+    euler = abs(terms.sum() + 2.0 * E) / np.abs(terms).sum()
+    force = np.abs(G.sum(0)).max() / np.abs(G).sum()
+    torque = np.abs(np.cross(c.X - x0, G).sum(0)).max() / (np.abs(c.X - x0).max() * np.abs(G).sum())
+    log(name, "rel G(sampled)", eG, "euler", euler, "force", force, "torque", torque)
+    assert eG <= G_TOL
+    assert euler <= 1e-6 and force <= 1e-6 and torque <= 1e-6
+
+
 def test_scaling_and_euler_identity():
     """E(2X) = E(X)/4 and sum_v x_v . G_v = -2 E hold for any mesh (homogeneity of degree 4+q-p)."""
     T = tpe()

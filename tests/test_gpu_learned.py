@@ -123,3 +123,31 @@ def test_farfield_speed_and_accuracy_at_c4(trained):
         f"learned {t_l*1e3:.2f} ms ({t_e/t_l:.1f}x, rel G {eGl:.3e})")
     assert t_e / t_m >= 10.0
     assert eGm <= 1e-3
+
+
+def test_c5_learned_flow_judged():
+    """Level-8 workload (1,310,720 faces, gap 0.01): 100 explicit gradient-flow steps driven by
+    the learned far field (committed checkpoint) on a tree built once, with the exact path as the
+    judge every 10th step.  The degree-32 wrinkles hold pairs much closer than the gap, so the
+    explicit step is controlled by rejection: it starts at dt = 1e-3 / max|G| (no vertex moves
+    more than a tenth of the gap) and is halved until the energy decreases."""
+    import os
+    import torch
+    from paper_2509_22110_amd.flow import RHO, ALPHA, gradient_flow_backtracking
+    T = tpe()
+    ckpt = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2509_22110_amd", "data",
+                        "farfield_mlp.bin")
+    m = T.MLP.load(ckpt)
+    c = M.make_config("C5")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    _, G0 = T.farfield(tree, Xd, Fd, theta=0.5, scale=RHO / ALPHA, mlp=m)
+    dt = 1e-3 / float(G0.abs().max())
+    t0 = time.time()
+    rec = gradient_flow_backtracking(Xd, Fd, 100, dt, tree=tree, theta=0.5, mlp=m, judge_every=10, grow=1.25)
+    torch.cuda.synchronize()
+    log(f"C5 flow: dt {dt:.3e} -> {rec.dts[-1]:.3e} ({rec.rejected} rejected), {time.time() - t0:.1f} s, "
+        f"E {rec.energies[0]:.6e} -> {rec.energies[-1]:.6e}, judge {[(k, float(f'{e:.3e}')) for k, e in rec.judge]}")
+    assert len(rec.energies) == 100
+    assert all(b < a for a, b in zip(rec.energies, rec.energies[1:]))
+    assert len(rec.judge) == 10 and max(e for _, e in rec.judge) <= 1e-3
