@@ -196,8 +196,9 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
 
 /* Interaction counts of the last tpe_farfield call on this context, summed over target blocks of
  * 64 faces (each count applies to every face of a block): out_host[0] = far clusters evaluated,
- * [1] = near columns evaluated exactly, [2] = tree nodes visited, [3] = target blocks.  Host
- * array of 4 int64.  Synchronises the stream. */
+ * [1] = near columns evaluated exactly, [2] = tree nodes visited, [3] = target blocks; and the
+ * largest per block: [4] = near columns, [5] = far clusters.  Host array of 6 int64.
+ * Synchronises the stream. */
 int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
 
 /* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed

@@ -120,8 +120,9 @@ class _Ctx:
         return ms.value, n.value
 
     def farfield_stats(self):
-        """(far clusters, near columns, visited nodes, target blocks) of the last far-field call."""
-        out = (ctypes.c_int64 * 4)()
+        """(far clusters, near columns, visited nodes, target blocks, max near columns of a block,
+        max far clusters of a block) of the last far-field call."""
+        out = (ctypes.c_int64 * 6)()
         self.check(lib().tpe_farfield_stats(self.h, out))
         return tuple(int(v) for v in out)
 

@@ -387,7 +387,7 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return TPE_ERR_OOM;
     }
-    ctx->dstats = reinterpret_cast<unsigned long long*>(ctx->dflags) + 16;  // bytes 128..160 of the same block
+    ctx->dstats = reinterpret_cast<unsigned long long*>(ctx->dflags) + 16;  // bytes 128..176 of the same block
     if (hipHostMalloc(&ctx->hflags, sizeof(uint32_t)) != hipSuccess) {
         (void)hipFree(ctx->dflags);
         delete ctx;
@@ -556,7 +556,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
         HIPCHK(hipEventRecord(ev0, st));
     }
-    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 8, st));
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
     if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
@@ -601,10 +601,10 @@ int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!out_host) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
     DeviceGuard dg(ctx->device);
-    unsigned long long h[4] = {0, 0, 0, 0};
+    unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(h, ctx->dstats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int i = 0; i < 4; ++i) out_host[i] = (int64_t)h[i];
+    for (int i = 0; i < 6; ++i) out_host[i] = (int64_t)h[i];
     return TPE_OK;
 }
 

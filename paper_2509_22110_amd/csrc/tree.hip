@@ -241,12 +241,14 @@ __device__ __forceinline__ void ff_fold(float (&acc)[NACC], float (&hi)[NACC], f
 }
 
 // Exact pairs of the block's rows with the faces [f0, f1) (a near node), with the shared-vertex
-// exclusion; columns are read with scalar loads, four at a time, rows re-expressed relative to
-// each 256-face tile's FP64 origin.
+// exclusion when MASK (a node whose vertices cannot reach the block's needs none); columns are
+// read with scalar loads, four at a time, rows re-expressed relative to each chunk's FP64 origin.
+template <bool MASK>
 __device__ __forceinline__ void ff_near_range(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
                                               const double* __restrict__ org, int64_t f0, int64_t f1, double cxd,
                                               double cyd, double czd, const ColRec& me, const int4& mv,
                                               float (&acc)[NACC], float (&hi)[NACC], float (&lo)[NACC], int& cnt) {
+    const int4 nov = make_int4(0, 0, 0, 0);
     int64_t f = f0;
     while (f < f1) {
         const int64_t t = f / CTILE;
@@ -254,16 +256,18 @@ __device__ __forceinline__ void ff_near_range(const ColRec* __restrict__ cols, c
         const float rx = (float)(cxd - org[3 * t]), ry = (float)(cyd - org[3 * t + 1]), rz = (float)(czd - org[3 * t + 2]);
         for (; f + 4 <= fend; f += 4) {
             const ColRec c0 = cols[f], c1 = cols[f + 1], c2 = cols[f + 2], c3 = cols[f + 3];
-            const int4 v0 = colv[f], v1 = colv[f + 1], v2 = colv[f + 2], v3 = colv[f + 3];
-            ff_pair<6, true, true>(c0, v0, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
-            ff_pair<6, true, true>(c1, v1, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
-            ff_pair<6, true, true>(c2, v2, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
-            ff_pair<6, true, true>(c3, v3, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            int4 v0 = nov, v1 = nov, v2 = nov, v3 = nov;
+            if constexpr (MASK) { v0 = colv[f]; v1 = colv[f + 1]; v2 = colv[f + 2]; v3 = colv[f + 3]; }
+            ff_pair<6, true, MASK>(c0, v0, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, MASK>(c1, v1, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, MASK>(c2, v2, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, MASK>(c3, v3, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
             cnt += 4;
             if (cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
         }
         for (; f < fend; ++f) {
-            ff_pair<6, true, true>(cols[f], colv[f], rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+            ff_pair<6, true, MASK>(cols[f], MASK ? colv[f] : nov, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z,
+                                   acc);
             if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
         }
     }
@@ -389,27 +393,39 @@ __device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, 
 }
 
 constexpr int FF_STACK = 1024;  // LDS node stack per wave (overflow falls back to exact evaluation)
+constexpr int FF_NW = 4;          // waves per target block, monopole far field
+constexpr int FF_NW_LEARNED = 1;  // waves per target block with the learned correction (MLP scratch is LDS-bound)
 
-// One wave per target block of 64 consecutive (tree-ordered) faces.  Batched depth-first walk of
-// the implicit tree: up to 64 nodes are popped at once (one per lane), tested in parallel, and then
-//   - far clusters are applied to all 64 rows one after another (their records broadcast from the
-//     lane that loaded them),
-//   - near leaves are evaluated exactly,
+// One work-group of NW waves per target block of 64 consecutive (tree-ordered) faces.  Every wave
+// walks the implicit tree the same way (batched depth first: up to 64 nodes popped at once, one
+// per lane, and tested in parallel):
+//   - far clusters are applied to all 64 rows (their records broadcast from the lane that loaded
+//     them),
+//   - near nodes (leaves, or nodes that cannot be opened) are evaluated exactly, without the
+//     shared-vertex test when their vertex ball cannot meet the block's,
 //   - other nodes push their two children;
-// if the stack could overflow, a node that would be opened is evaluated exactly instead (always
-// correct).  Writes the block's FP64 row sums acc64[k][i] (k < NACC).
-template <bool LEARNED>
-__global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
-                                                      const double* __restrict__ c64,
-                                                      const double* __restrict__ org,
-                                                      const NodeRec* __restrict__ nodes,
-                                                      const NodeMom* __restrict__ moms, const MlpPacked* __restrict__ W,
-                                                      int H, int leaf, int64_t nF, const float4* __restrict__ balls,
-                                                      float theta, int64_t Fp, double* __restrict__ acc64,
-                                                      unsigned long long* __restrict__ stats) {
-    __shared__ int stack[FF_STACK];
-    __shared__ MlpScratch ms;
-    const int lane = threadIdx.x;
+// the far clusters and the near nodes met along the walk are dealt out round-robin over the NW
+// waves, which split the block's work (heavy blocks have several times the average near work)
+// and fold their compensated sums into wave 0's through LDS at the end.  If the stack could
+// overflow, a node that would be opened is evaluated exactly instead (always correct).  Writes
+// the block's FP64 row sums acc64[k][i] (k < NACC).
+template <bool LEARNED, int NW>
+__global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restrict__ cols,
+                                                           const int4* __restrict__ colv,
+                                                           const double* __restrict__ c64,
+                                                           const double* __restrict__ org,
+                                                           const NodeRec* __restrict__ nodes,
+                                                           const NodeMom* __restrict__ moms,
+                                                           const MlpPacked* __restrict__ W, int H, int leaf,
+                                                           int64_t nF, const float4* __restrict__ balls,
+                                                           float theta, int64_t Fp, double* __restrict__ acc64,
+                                                           unsigned long long* __restrict__ stats) {
+    __shared__ int stacks[NW][FF_STACK];
+    __shared__ float red[NW > 1 ? NW - 1 : 1][NW > 1 ? 2 * NACC : 1][64];
+    __shared__ MlpScratch ms[LEARNED ? NW : 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    int* stack = stacks[wave];
     const int64_t b = blockIdx.x;
     const int64_t i = b * 64 + lane;
     const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
@@ -425,6 +441,7 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
     const int4 nov = make_int4(0, 0, 0, 0);
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t n_far = 0, n_near_cols = 0, n_visit = 0;
+    uint32_t deal_far = 0, deal_near = 0;  // running indices of far clusters / near nodes (same in every wave)
     if (lane == 0) stack[0] = 1;
     int sz = 1;
     while (sz > 0) {
@@ -445,6 +462,9 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
         const bool overflow = sz + 2 * nopen > FF_STACK;
         if (overflow) open = false;
         const bool near = valid && !far && !open;
+        // a near node whose vertex ball is disjoint from the block's shares no vertex with it
+        // (conservative margin for the FP32 distance)
+        const bool disjoint = dist * (1.f - 1e-5f) > tb.w + nd.r;
         // push children of opened nodes (right child below left, so the left is popped first)
         if (!overflow) {
             const uint64_t om = __ballot(open);
@@ -461,18 +481,20 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
         while (fm) {
             const int l = (int)__builtin_ctzll(fm);
             fm &= fm - 1;
+            if ((deal_far++ % NW) != (uint32_t)wave) continue;
             const ColRec cr = {lane_f(nd.cx, l), lane_f(nd.cy, l), lane_f(nd.cz, l), lane_f(nd.a, l),
                                lane_f(nd.nx, l), lane_f(nd.ny, l), lane_f(nd.nz, l), 0.f};
             ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
             if constexpr (LEARNED) {
                 const int kk = __builtin_amdgcn_readlane(k, l);
                 const NodeRec cn = {cr.cx, cr.cy, cr.cz, lane_f(nd.r, l), cr.a, cr.nx, cr.ny, cr.nz};
-                mlp_correction(W, cn, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms, acc);
+                mlp_correction(W, cn, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
             }
             if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
         }
         // near nodes (leaves, or nodes that could not be opened): exact pairs over their faces
         uint64_t nm = __ballot(near);
+        const uint64_t dm = __ballot(disjoint);
         while (nm) {
             const int l = (int)__builtin_ctzll(nm);
             nm &= nm - 1;
@@ -483,19 +505,53 @@ __global__ __launch_bounds__(64) void farfield_kernel(const ColRec* __restrict__
             const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
             if (f0 < f1) {
                 n_near_cols += (uint32_t)(f1 - f0);
-                ff_near_range(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+                if ((deal_near++ % NW) != (uint32_t)wave) continue;
+                if ((dm >> l) & 1ull)
+                    ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+                else
+                    ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
             }
         }
     }
     ff_fold(acc, hi, lo);
+    if constexpr (NW > 1) {
+        if (wave > 0) {
 #pragma unroll
-    for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] = (double)hi[kk] - (double)lo[kk];
-    // interaction counts of this target block (per row): far clusters, near columns, visited nodes
-    if (lane == 0 && stats) {
-        atomicAdd(&stats[0], (unsigned long long)n_far);
-        atomicAdd(&stats[1], (unsigned long long)n_near_cols);
-        atomicAdd(&stats[2], (unsigned long long)n_visit);
-        atomicAdd(&stats[3], 1ull);
+            for (int kk = 0; kk < NACC; ++kk) {
+                red[wave - 1][kk][lane] = hi[kk];
+                red[wave - 1][NACC + kk][lane] = lo[kk];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // fold the other waves' compensated sums (hi - lo each) into wave 0's, in wave order
+#pragma unroll
+            for (int j = 0; j < NW - 1; ++j)
+#pragma unroll
+                for (int kk = 0; kk < NACC; ++kk) {
+                    float y = red[j][kk][lane] - lo[kk];
+                    float t = hi[kk] + y;
+                    lo[kk] = (t - hi[kk]) - y;
+                    hi[kk] = t;
+                    y = -red[j][NACC + kk][lane] - lo[kk];
+                    t = hi[kk] + y;
+                    lo[kk] = (t - hi[kk]) - y;
+                    hi[kk] = t;
+                }
+        }
+    }
+    if (wave == 0) {
+#pragma unroll
+        for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] = (double)hi[kk] - (double)lo[kk];
+        // interaction counts of this target block (per row): far clusters, near columns, visited nodes
+        if (lane == 0 && stats) {
+            atomicAdd(&stats[0], (unsigned long long)n_far);
+            atomicAdd(&stats[1], (unsigned long long)n_near_cols);
+            atomicAdd(&stats[2], (unsigned long long)n_visit);
+            atomicAdd(&stats[3], 1ull);
+            atomicMax(&stats[4], (unsigned long long)n_near_cols);
+            atomicMax(&stats[5], (unsigned long long)n_far);
+        }
     }
 }
 
@@ -780,11 +836,12 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
     if (mlp_packed)
-        hipLaunchKernelGGL((farfield_kernel<true>), dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org, r, m,
-                           (const MlpPacked*)mlp_packed, H, leaf, nF, balls, theta, Fp, acc64, stats);
+        hipLaunchKernelGGL((farfield_kernel<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st,
+                           cols, colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, balls, theta, Fp,
+                           acc64, stats);
     else
-        hipLaunchKernelGGL((farfield_kernel<false>), dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, org, r, m,
-                           (const MlpPacked*)nullptr, H, leaf, nF, balls, theta, Fp, acc64, stats);
+        hipLaunchKernelGGL((farfield_kernel<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv,
+                           c64, org, r, m, (const MlpPacked*)nullptr, H, leaf, nF, balls, theta, Fp, acc64, stats);
     return hipGetLastError();
 }
 
