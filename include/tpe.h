@@ -153,6 +153,13 @@ int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* mlp, const float* host, int64_t n)
 /* tpe_farfield applies the correction only to far clusters with r_B / rho >= min_s (default 0:
  * all); rho = |c_S - C_B|.  Stored with the network (not in checkpoints). */
 int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* mlp, float min_s);
+/* Weight lam >= 0 (default 0) of the training loss's difference term: for consecutive rows i, i+1
+ * of one 32-row tile of a training batch, lam w_i w_(i+1) sum_(j<7) ((y_(i+1),j - y_ij) -
+ * (t_(i+1),j - t_ij))^2 is added to the loss (same normalisation).  Rows of a tile of the
+ * samples tpe_farfield_samples writes are neighbouring faces seeing the same cluster, so the term
+ * asks the correction to vary from face to face as the exact one does.  Not stored in
+ * checkpoints.  (Not in the paper.) */
+int tpe_mlp_set_smoothness(tpe_ctx* ctx, tpe_mlp* mlp, float lam);
 /* out (device f32 [n][16]) <- network(feats (device f32 [n][32])), evaluated with the BF16 weights
  * and activations exactly as tpe_farfield evaluates it (bit-identical for the same features). */
 int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* mlp, const float* feats, int64_t n, float* out);

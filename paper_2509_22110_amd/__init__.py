@@ -78,6 +78,7 @@ def lib():
             "tpe_mlp_set_params": ([P, P, P, I64], I),
             "tpe_mlp_forward": ([P, P, P, I64, P], I),
             "tpe_mlp_set_gate": ([P, P, ctypes.c_float], I),
+            "tpe_mlp_set_smoothness": ([P, P, ctypes.c_float], I),
             "tpe_mlp_train_step": ([P, P, P, P, I64, ctypes.c_float, P], I),
             "tpe_mlp_gradient": ([P, P, P, P, I64, P], I),
             "tpe_mlp_save": ([P, P, ctypes.c_char_p], I),
@@ -261,6 +262,11 @@ class MLP:
         assert p.size == self.n_params
         c = context(self.device)
         c.check(lib().tpe_mlp_set_params(c.h, self.h, p.ctypes.data, self.n_params))
+
+    def set_smoothness(self, lam: float):
+        """Weight of the training loss's neighbouring-row difference term (see tpe_mlp_set_smoothness)."""
+        c = context(self.device)
+        c.check(lib().tpe_mlp_set_smoothness(c.h, self.h, float(lam)))
 
     def set_gate(self, min_s: float):
         """Apply the far-field correction only to clusters with r_B / rho >= min_s."""

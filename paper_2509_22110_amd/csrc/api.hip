@@ -136,6 +136,7 @@ struct tpe_mlp {
     float* V = nullptr;  // Adam second moments
     void* packed = nullptr;  // BF16 fragments + biases for inference (kept in sync with P)
     float min_s = 0.f;       // apply the correction only to clusters with r_B / rho >= min_s
+    float lam = 0.f;         // weight of the neighbouring-row difference term of the training loss
     float* gpart = nullptr;  // per-tile gradient partials (grow-only)
     float* lpart = nullptr;
     int64_t cap_tiles = 0;
@@ -690,6 +691,13 @@ int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* m, const float* host, int64_t n) {
     return TPE_OK;
 }
 
+int tpe_mlp_set_smoothness(tpe_ctx* ctx, tpe_mlp* m, float lam) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !(lam >= 0.f) || !std::isfinite(lam)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad smoothness weight");
+    m->lam = lam;
+    return TPE_OK;
+}
+
 int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* m, float min_s) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !(min_s >= 0.f) || !std::isfinite(min_s)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad gate");
@@ -716,8 +724,8 @@ static int mlp_step(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* t
     int rc = mlp_alloc_parts(ctx, m, mlp_tiles(n));
     if (rc) return rc;
     if (!grad_dev) ++m->step;
-    HIPCHK(mlp_train_launch(m->P, m->M, m->V, feats, targets, n, lr, m->step, m->gpart, m->lpart, loss_dev, grad_dev,
-                            ctx->stream));
+    HIPCHK(mlp_train_launch(m->P, m->M, m->V, feats, targets, n, lr, m->lam, m->step, m->gpart, m->lpart, loss_dev,
+                            grad_dev, ctx->stream));
     if (!grad_dev) HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
     return TPE_OK;
 }

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64) void mlp_infer_kernel(const MlpPacked* __restri
 // w * d(sum_j (y - t)^2)) to gpart[tile][MLP_NPARAM] and (sum w (y-t)^2, sum w) to lpart[tile][2].
 __global__ __launch_bounds__(64) void mlp_train_tile(const float* __restrict__ P, const float* __restrict__ X,
                                                      const float* __restrict__ T, int64_t n,
-                                                     float* __restrict__ gpart, float* __restrict__ lpart) {
+                                                     float* __restrict__ gpart, float* __restrict__ lpart, float lam) {
     __shared__ float Xs[TM * 32], H1[TM * 64], H2[TM * 64], H3[TM * 64], D1[TM * 64], D2[TM * 64], Y[TM * 16];
     __shared__ float red[64];
     const int lane = threadIdx.x;
@@ -149,10 +149,13 @@ __global__ __launch_bounds__(64) void mlp_train_tile(const float* __restrict__ P
     }
     __syncthreads();
     mlp_tile_forward(P, Xs, H1, H2, H3, Y);
-    // dL/dY (up to the global normalisation, applied in the Adam pass) into Y; loss partials
+    // dL/dY (up to the global normalisation, applied in the Adam pass) into Y; loss partials.
+    // With lam > 0 the loss also compares the differences of neighbouring rows of the tile:
+    // lam sum_m w_m w_(m+1) |(y_(m+1) - y_m) - (t_(m+1) - t_m)|^2.
     float ls = 0.f, ws = 0.f;
     for (int e = lane; e < TM * 16; e += 64) {
-        const int64_t row = base + e / 16;
+        const int m = e / 16;
+        const int64_t row = base + m;
         const int j = e % 16;
         float g = 0.f;
         if (row < n && j < MLP_NOUT_USED) {
@@ -161,9 +164,24 @@ __global__ __launch_bounds__(64) void mlp_train_tile(const float* __restrict__ P
             ls += w * d * d;
             g = 2.f * w * d;
             if (j == 0) ws += w;
+            if (lam > 0.f) {
+                if (m + 1 < TM && row + 1 < n) {
+                    const float v = w * T[(row + 1) * 16 + 15];
+                    const float D = (Y[e + 16] - T[(row + 1) * 16 + j]) - d;
+                    ls += lam * v * D * D;
+                    g -= 2.f * lam * v * D;
+                }
+                if (m > 0) {
+                    const float v = T[(row - 1) * 16 + 15] * w;
+                    const float D = d - (Y[e - 16] - T[(row - 1) * 16 + j]);
+                    g += 2.f * lam * v * D;
+                }
+            }
         }
-        Y[e] = g;
+        D1[e] = g;
     }
+    __syncthreads();
+    for (int e = lane; e < TM * 16; e += 64) Y[e] = D1[e];
     for (int off = 32; off > 0; off >>= 1) {
         ls += __shfl_xor(ls, off);
         ws += __shfl_xor(ws, off);
@@ -356,9 +374,10 @@ hipError_t mlp_infer_launch(const void* packed, const float* X, int64_t n, float
 int64_t mlp_tiles(int64_t n) { return (n + TM - 1) / TM; }
 
 hipError_t mlp_train_launch(float* P, float* Mm, float* Vv, const float* X, const float* T, int64_t n, float lr,
-                            int64_t step, float* gpart, float* lpart, float* loss, float* grad_out, hipStream_t st) {
+                            float lam, int64_t step, float* gpart, float* lpart, float* loss, float* grad_out,
+                            hipStream_t st) {
     const int ntiles = (int)mlp_tiles(n);
-    hipLaunchKernelGGL(mlp_train_tile, dim3(ntiles), dim3(64), 0, st, P, X, T, n, gpart, lpart);
+    hipLaunchKernelGGL(mlp_train_tile, dim3(ntiles), dim3(64), 0, st, P, X, T, n, gpart, lpart, lam);
     if (grad_out) {
         hipLaunchKernelGGL(mlp_grad_sum, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, gpart, lpart, ntiles,
                            grad_out);

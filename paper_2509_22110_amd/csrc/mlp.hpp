@@ -29,6 +29,7 @@ int64_t mlp_tiles(int64_t n);
 hipError_t mlp_pack_launch(const float* P, float min_s, void* packed, hipStream_t st);
 size_t mlp_packed_bytes();
 hipError_t mlp_train_launch(float* P, float* Mm, float* Vv, const float* X, const float* T, int64_t n, float lr,
-                            int64_t step, float* gpart, float* lpart, float* loss, float* grad_out, hipStream_t st);
+                            float lam, int64_t step, float* gpart, float* lpart, float* loss, float* grad_out,
+                            hipStream_t st);
 
 }  // namespace tpe

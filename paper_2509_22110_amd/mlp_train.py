@@ -44,7 +44,12 @@ def training_shape(seed: int, level: int | None = None):
     return X, F
 
 
+GROUP = 32  # rows per training tile; sample rows come in runs of 64 faces of one (block, cluster)
+
+
 def collect(seeds, theta=0.5, select_prob=0.02, quota=16, max_cluster_faces=1 << 20, device="cuda", log=print):
+    """Samples of the given training shapes, kept in aligned groups of GROUP rows (consecutive
+    faces of one target block seeing one far cluster); groups without a used row are dropped."""
     feats, targs = [], []
     for s in seeds:
         X, F = training_shape(s)
@@ -53,9 +58,9 @@ def collect(seeds, theta=0.5, select_prob=0.02, quota=16, max_cluster_faces=1 <<
         tree = build_tree(Xd, Fd, leaf=32)
         f, t = farfield_samples(tree, Xd, Fd, theta=theta, seed=s, select_prob=select_prob, quota=quota,
                                 max_cluster_faces=max_cluster_faces)
-        keep = t[:, 15] > 0
-        feats.append(f[keep])
-        targs.append(t[keep])
+        keep = (t[:, 15].view(-1, GROUP) > 0).any(1)
+        feats.append(f.view(-1, GROUP, 32)[keep].reshape(-1, 32))
+        targs.append(t.view(-1, GROUP, 16)[keep].reshape(-1, 16))
     return torch.cat(feats), torch.cat(targs)
 
 
@@ -119,14 +124,19 @@ def per_output_ratio(mlp, X, T, batch=65536):
     return (err / zero.clamp_min(1e-300)).cpu().numpy()
 
 
-def train(mlp, X, T, epochs=8, batch=8192, lr=2e-3, seed=0, log=print, Xv=None, Tv=None):
+def train(mlp, X, T, epochs=8, batch=8192, lr=2e-3, seed=0, log=print, Xv=None, Tv=None, lam=0.0):
+    """Adam with cosine decay over shuffled batches of whole GROUP-row groups (so every training
+    tile holds neighbouring faces, which the difference term of weight `lam` compares)."""
     n = X.shape[0]
+    assert n % GROUP == 0 and batch % GROUP == 0
+    mlp.set_smoothness(lam)
     g = torch.Generator(device="cpu").manual_seed(seed)
     steps = epochs * max(1, n // batch)
     step = 0
     loss = torch.empty((), dtype=torch.float32, device=X.device)
+    within = torch.arange(GROUP)
     for ep in range(epochs):
-        perm = torch.randperm(n, generator=g).to(X.device)
+        perm = (torch.randperm(n // GROUP, generator=g)[:, None] * GROUP + within).reshape(-1).to(X.device)
         for i in range(0, n - batch + 1, batch):
             idx = perm[i:i + batch]
             cur = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))
@@ -181,13 +191,13 @@ def report_shapes(seeds=(1196, 1197, 1198, 1199)):
     return [training_shape(s, level=6 if i < len(seeds) // 2 else 7) for i, s in enumerate(seeds)]
 
 
-def fit(X, T, Xv, Tv, epochs=8, seed=0, log=print, max_ratio=1.0):
+def fit(X, T, Xv, Tv, epochs=8, seed=0, log=print, max_ratio=1.0, lam=0.0):
     """Train on per-output normalized targets, fold the scales back into the last layer, and keep
     only the outputs that beat the zero correction on the validation set (ratio < max_ratio)."""
     sig = output_scales(T)
     log("output scales: " + " ".join(f"{float(v):.3e}" for v in sig))
     mlp = MLP(seed=seed)
-    train(mlp, X, normalized(T, sig), epochs=epochs, log=log, Xv=Xv, Tv=normalized(Tv, sig))
+    train(mlp, X, normalized(T, sig), epochs=epochs, log=log, Xv=Xv, Tv=normalized(Tv, sig), lam=lam)
     fold_scales(mlp, sig)
     ratio = per_output_ratio(mlp, Xv, Tv)
     keep = {j for j in range(NOUT) if ratio[j] < max_ratio}
@@ -205,6 +215,7 @@ def main(argv=None):
     ap.add_argument("--first-seed", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--smooth", type=float, default=1.0, help="weight of the neighbouring-face difference term")
     args = ap.parse_args(argv)
 
     def log(*a):
@@ -216,7 +227,7 @@ def main(argv=None):
     X, T = collect(seeds[:-nval], theta=args.theta, log=log)
     Xv, Tv = collect(seeds[-nval:], theta=args.theta, log=log)
     log(f"samples: train {X.shape[0]}, val {Xv.shape[0]} ({time.time() - t0:.1f} s)")
-    mlp = fit(X, T, Xv, Tv, epochs=args.epochs, seed=args.first_seed, log=log)
+    mlp = fit(X, T, Xv, Tv, epochs=args.epochs, seed=args.first_seed, log=log, lam=args.smooth)
     log("far-field errors by applied output group on held-out level-6/7 shapes:")
     group_report(mlp, report_shapes(), theta=args.theta, log=log)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

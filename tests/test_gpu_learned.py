@@ -14,13 +14,14 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 @pytest.fixture(scope="module")
 def trained():
     """A network trained in-test on seeded training shapes (seeds 1000..1039, validation
-    1040..1045, all disjoint from the evaluation seed 0), on per-output normalized targets."""
+    1040..1045, all disjoint from the evaluation seed 0), on per-output normalized targets, with
+    the neighbouring-face difference term at weight 1."""
     tpe()
     from paper_2509_22110_amd import mlp_train as MT
     t0 = time.time()
     X, Y = MT.collect(range(1000, 1040))
     Xv, Yv = MT.collect(range(1040, 1046))
-    m = MT.fit(X, Y, Xv, Yv, epochs=8, seed=7, log=log)
+    m = MT.fit(X, Y, Xv, Yv, epochs=8, seed=7, log=log, lam=1.0)
     ratio = MT.per_output_ratio(m, Xv, Yv)
     log(f"trained on {X.shape[0]} samples in {time.time() - t0:.1f} s; validation error / zero-correction "
         f"error per output {np.round(ratio, 3)}")

@@ -35,14 +35,16 @@ def test_forward_matches_fp64_reference():
         assert err < 2e-2
 
 
-def test_backward_matches_fp64_reference():
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_backward_matches_fp64_reference(lam):
     import torch
     T_ = tpe()
     m = T_.MLP(seed=5)
+    m.set_smoothness(lam)  # difference term over consecutive rows of each 32-row tile
     p = m.get_params()
     X, T = batch(777, 1)
     g = m.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()).cpu().numpy()
-    gr = mlp_ref.gradient(p, X.astype(np.float64), T.astype(np.float64))
+    gr = mlp_ref.gradient(p, X.astype(np.float64), T.astype(np.float64), lam=lam, tile=32)
     # Tolerance: every product takes BF16 operands (unit roundoff 2^-9) and the input-layer
     # gradient passes through three chained products that sum 16..777 terms with cancellation,
     # so max-norm errors of a few percent are expected; an indexing or transposition mistake
