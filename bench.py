@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 55
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
 HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per face of the finalize + gather passes: finalize reads one segment of
+# row sums (11 x (hi, lo) FP32 = 88 B), {a, |w|, n} (40 B), vertex ids (16 B) and its three vertices
+# (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices (12 B) and
+# the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
+FINALIZE_GATHER_BYTES_PER_FACE = 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
 
 
 def parse():
@@ -104,6 +109,19 @@ def farfield_leg(args, T, M, torch, dev):
     G0 = torch.empty_like(X)
     E0 = torch.empty((), dtype=torch.float64, device=dev)
     t_exact, _ = timed(lambda: T.gradient(X, F, out=G0, energy_out=E0), max(1, args.ff_reps // 2))
+    # the HBM-bound passes of the exact path (finalize + vertex gather), timed with HIP events
+    ctx = T.context(dev)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 2)
+    ctx.kernel_time()
+    for _ in range(2):
+        T.gradient(X, F, out=G0, energy_out=E0)
+    fg_ms, fg_n = ctx.kernel_time()
+    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+    fg_ms /= max(fg_n, 1)
+    fg_bytes = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF
+    fg = {"kernels": "finalize_kernel<true> + vertex_gather", "bound": "hbm", "ms": round(fg_ms, 4),
+          "algorithmic_bytes": fg_bytes, "achieved": round(fg_bytes / (fg_ms * 1e-3) / 1e9, 1),
+          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fg_bytes / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
     g0 = float(G0.abs().max())
     e0 = float(E0)
@@ -118,7 +136,7 @@ def farfield_leg(args, T, M, torch, dev):
 
     out = {"workload": f"{args.ff_config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0",
            "faces": cfg.nF, "theta": args.theta, "leaf": 32,
-           "exact_ms": round(t_exact, 3), "tree_build_ms": round(t_tree, 3),
+           "exact_ms": round(t_exact, 3), "tree_build_ms": round(t_tree, 3), "finalize_gather": fg,
            "note": "errors against the exact FP32/FP64 path (itself parity-tested against the FP64 "
                    "oracle); far-field ms per gradient exclude the tree build (an ordering that is "
                    "reused while the moments are recomputed from X on every call)",

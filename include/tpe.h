@@ -65,8 +65,9 @@ typedef enum {
                                  0 (default) = as many as the device keeps resident at once.  The
                                  work is split evenly over them; results agree to rounding */
     TPE_OPT_KERNEL_TIMING = 3 /* 1: record HIP events around every launch of the dominant
-                                 kernel (the pair kernel) on the context's stream, read back
-                                 with tpe_kernel_time(); 0 (default): off */
+                                 kernel (the pair kernel, or the far-field walk) on the context's
+                                 stream; 2: around the finalize + vertex-gather launches; read
+                                 back with tpe_kernel_time(); 0 (default): off */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */

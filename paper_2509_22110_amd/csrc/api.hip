@@ -123,7 +123,7 @@ struct tpe_ctx {
     uint32_t* dflags = nullptr;   // device error word
     uint32_t* hflags = nullptr;   // pinned host mirror
     unsigned long long* dstats = nullptr;  // far-field interaction counters of the last call
-    bool kernel_timing = false;
+    int kernel_timing = 0;        // 1: the dominant kernel, 2: finalize + vertex gather
     std::vector<hipEvent_t> ev_pool;  // pairs (start, stop), reused
     size_t ev_used = 0;               // events recorded since the last tpe_kernel_time
 };
@@ -358,13 +358,15 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
-        HIPCHK(hipEventRecord(ev0, st));
     }
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
-    if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
                            P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
 }
@@ -443,8 +445,8 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
             ctx->target_waves = value;
             return TPE_OK;
         case TPE_OPT_KERNEL_TIMING:
-            if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0 or 1");
-            ctx->kernel_timing = value != 0;
+            if (value < 0 || value > 2) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0, 1 or 2");
+            ctx->kernel_timing = (int)value;
             return TPE_OK;
         default:
             return fail(ctx, TPE_ERR_INVALID_ARG, "unknown option");
@@ -555,15 +557,17 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
-        HIPCHK(hipEventRecord(ev0, st));
     }
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
-    if (ctx->kernel_timing) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
                            P.ticket, ctx->dflags, E_dev, st));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
 }
