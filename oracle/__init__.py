@@ -8,9 +8,13 @@ gcc and calls it through ctypes on NumPy arrays.  See ``tpe_oracle.c`` for the d
 (paper Sec. 2.2.2, eq. (TP), one-point centroid quadrature on flat triangles, ordered pairs of faces that
 share no vertex) and for the gradient's chain rule.
 
-Parity pins: closed forms (two-triangle example, sphere limit), exact identities (scaling law, Euler
-identity, zero net force and torque, rigid-motion, orientation and permutation invariance), brute-force
-pair counts and central finite differences -- see tests/test_oracle.py.
+Also the confinement energy (paper Sec. 2.2.3, eq. (TPConf)) of a moving surface against a fixed one
+(``conf_energy``, ``conf_gradient``; see ``tpe_oracle.c``).
+
+Parity pins: closed forms (two-triangle example, sphere limit, concentric-sphere limit of the
+confinement energy), exact identities (scaling law, Euler identity, zero net force and torque,
+rigid-motion, orientation and permutation invariance), brute-force pair counts and central finite
+differences -- see tests/test_oracle.py and tests/test_oracle_conf.py.
 """
 from __future__ import annotations
 
@@ -56,6 +60,10 @@ def _load():
         lib.tpeo_energy_rows.argtypes = [P, I64, P, I64, D, D, D, I64, I64, I32, P]
         lib.tpeo_gradient.argtypes = [P, I64, P, I64, D, D, D, I32, P, P]
         lib.tpeo_gradient_at.argtypes = [P, I64, P, I64, D, D, D, P, I64, I32, P]
+        lib.tpeo_conf_energy.argtypes = [P, I64, P, I64, P, I64, P, I64, D, D, D, I32, P]
+        lib.tpeo_conf_gradient.argtypes = [P, I64, P, I64, P, I64, P, I64, D, D, D, I32, P, P]
+        lib.tpeo_conf_energy.restype = I32
+        lib.tpeo_conf_gradient.restype = I32
         lib.tpeo_pair_count.argtypes = [P, I64]
         lib.tpeo_pair_count.restype = I64
         lib.tpeo_num_threads.argtypes = [I32]
@@ -124,3 +132,30 @@ def gradient_at(X, F, verts, q=6.0, p=12.0, scale=1.0, nthreads=0):
 def pair_count(F) -> int:
     F = np.ascontiguousarray(F, dtype=np.int32)
     return int(_load().tpeo_pair_count(F.ctypes.data, F.shape[0]))
+
+
+def conf_energy(X, F, Y, FY, q=6.0, p=12.0, scale=1.0, nthreads=0) -> float:
+    """Confinement energy of the moving surface (X, F) against the fixed surface (Y, FY)."""
+    X, F = _prep(X, F)
+    Y, FY = _prep(Y, FY)
+    E = np.zeros(1)
+    rc = _load().tpeo_conf_energy(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], Y.ctypes.data, Y.shape[0],
+                                  FY.ctypes.data, FY.shape[0], q, p, scale, nthreads, E.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0])
+
+
+def conf_gradient(X, F, Y, FY, q=6.0, p=12.0, scale=1.0, nthreads=0):
+    """(E_conf, dE_conf/dX [V, 3]); the confining surface is fixed."""
+    X, F = _prep(X, F)
+    Y, FY = _prep(Y, FY)
+    E = np.zeros(1)
+    G = np.zeros_like(X)
+    rc = _load().tpeo_conf_gradient(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], Y.ctypes.data,
+                                    Y.shape[0], FY.ctypes.data, FY.shape[0], q, p, scale, nthreads, E.ctypes.data,
+                                    G.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G
+

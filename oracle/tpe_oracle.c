@@ -343,3 +343,94 @@ int tpeo_gradient_at(const double* X, int64_t V, const int32_t* F, int64_t nF, d
     free(G);
     return err;
 }
+
+/*
+ * Confinement energy (paper Sec. 2.2.3, eq. (TPConf)): the moving surface (X, F) against a fixed
+ * confining surface (Y, FY), with the tangent-point kernel built from the moving surface's normal
+ * only, one-point centroid quadrature on both:
+ *
+ *   E_conf(X) = scale * sum_{S in F} sum_{T in FY}  a_S a_T |n_S . (c_S - c_T)|^q / |c_S - c_T|^p
+ *
+ * (every pair counts once: S always plays x and T always y; no pair is excluded, the meshes being
+ * different surfaces).  The gradient is with respect to X only, by the same chain rule as above
+ * applied to S alone: dE/dc_S = scale a_S a_T dk/dd, dE/dn_S = scale a_S a_T dk/dn,
+ * dE/da_S = scale a_T k.  The paper's prefactor is rho_conf / alpha with rho_conf = 1e-4.
+ */
+static int conf_common(const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y, int64_t VY,
+                       const int32_t* FY, int64_t nFY, double q, double p, face_t** GS, face_t** GT) {
+    int rc = check_inputs(X, V, F, nF, q, p);
+    if (rc) return rc;
+    rc = check_inputs(Y, VY, FY, nFY, q, p);
+    if (rc) return rc;
+    *GS = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
+    *GT = (face_t*)malloc(sizeof(face_t) * (size_t)nFY);
+    if (!*GS || !*GT) return EINVAL_;
+    rc = all_faces(X, F, nF, *GS);
+    if (!rc) rc = all_faces(Y, FY, nFY, *GT);
+    return rc;
+}
+
+int tpeo_conf_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y, int64_t VY,
+                       const int32_t* FY, int64_t nFY, double q, double p, double scale, int nthreads,
+                       double* E_out, double* G_out) {
+    face_t *GS = NULL, *GT = NULL;
+    int rc = conf_common(X, V, F, nF, Y, VY, FY, nFY, q, p, &GS, &GT);
+    if (rc) { free(GS); free(GT); return rc; }
+    int nt = nthreads_of(nthreads);
+    nsum* GV = G_out ? (nsum*)calloc((size_t)nt * (size_t)V * 3, sizeof(nsum)) : NULL;
+    nsum* part = (nsum*)calloc((size_t)nt, sizeof(nsum));
+    if ((G_out && !GV) || !part) { free(GS); free(GT); free(GV); free(part); return EINVAL_; }
+    int err = OK;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        nsum* myG = GV ? GV + (size_t)tid * (size_t)V * 3 : NULL;
+        nsum acc = {0.0, 0.0};
+        int lerr = OK;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < nF; ++s) {
+            for (int64_t t = 0; t < nFY; ++t) {
+                pairval pv;
+                if (pair_eval(&GS[s], &GT[t], q, p, myG != NULL, &pv)) { lerr = ENONFIN; continue; }
+                double aa = GS[s].a * GT[t].a;
+                nadd(&acc, aa * pv.k);
+                if (myG) {
+                    double dcS[3], dnS[3];
+                    for (int i = 0; i < 3; ++i) {
+                        dcS[i] = scale * aa * pv.dkdd[i];
+                        dnS[i] = scale * aa * pv.dkdn[i];
+                    }
+                    face_vjp(X, F, s, &GS[s], dcS, dnS, scale * GT[t].a * pv.k, myG);
+                }
+            }
+        }
+        part[tid] = acc;
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    nsum tot = {0.0, 0.0};
+    for (int i = 0; i < nt; ++i) { nadd(&tot, part[i].s); nadd(&tot, part[i].c); }
+    if (E_out) *E_out = err ? INFINITY : scale * nval(&tot);
+    if (G_out)
+        for (int64_t i = 0; i < V * 3; ++i) {
+            nsum g = {0.0, 0.0};
+            for (int th = 0; th < nt; ++th) {
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].s);
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].c);
+            }
+            G_out[i] = nval(&g);
+        }
+    free(GV); free(part); free(GS); free(GT);
+    return err;
+}
+
+int tpeo_conf_energy(const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y, int64_t VY,
+                     const int32_t* FY, int64_t nFY, double q, double p, double scale, int nthreads, double* E_out) {
+    return tpeo_conf_gradient(X, V, F, nF, Y, VY, FY, nFY, q, p, scale, nthreads, E_out, NULL);
+}
+
