@@ -104,6 +104,23 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
 
+/* Confinement energy (paper Sec. 2.2.3, eq. (TPConf)) of the moving surface (X, F) against a fixed
+ * confining surface (Y, FY), with the same one-point centroid quadrature:
+ *     E_conf = scale * sum_{S in F} sum_{T in FY} a_S a_T |n_S . (c_S - c_T)|^q / |c_S - c_T|^p.
+ * Only the moving surface's normal enters (the confinement may be non-smooth), every pair counts
+ * once and none is excluded.  The paper's prefactor is scale = rho_conf / alpha, rho_conf = 1e-4.
+ * X, Y: device f64 [V][3] / [VY][3]; F, FY: device i32 [nF][3] / [nFY][3]; the confining surface
+ * is only read.  E_dev (device, one double) <- E_conf.  Errors as for tpe_energy, for either
+ * surface; coincident centroids across the surfaces give TPE_ERR_NONFINITE. */
+int tpe_conf_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y,
+                    int64_t VY, const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E_dev);
+
+/* G_dev (device f64 [V][3]) <- dE_conf/dX (the confining surface is fixed) and, if E_dev != NULL,
+ * E_dev <- E_conf.  G_dev must alias neither X nor Y. */
+int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y,
+                      int64_t VY, const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E_dev,
+                      double* G_dev);
+
 /* Build the cluster tree used by tpe_farfield (paper Sec. 3.2: the inner integrals are clustered
  * with precomputed averages over patches of elements, Barnes-Hut style).  The tree is an implicit
  * complete binary tree over leaves of `leaf_size` consecutive faces (1..4096; 32 in the

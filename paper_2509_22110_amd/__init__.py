@@ -17,7 +17,8 @@ import threading
 
 import torch
 
-__all__ = ["TPEError", "lib", "energy", "gradient", "pair_count", "TPEFunction", "tpe_energy",
+__all__ = ["TPEError", "lib", "energy", "gradient", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
+           "tpe_energy",
            "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield", "MLP"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtpe.so")
@@ -62,6 +63,8 @@ def lib():
             "tpe_check": ([P], I),
             "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
+            "tpe_conf_energy": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P], I),
+            "tpe_conf_gradient": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
             "tpe_kernel_time": ([P, ctypes.POINTER(D), ctypes.POINTER(I64)], I),
             "tpe_build_tree": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
@@ -184,6 +187,37 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
     c = context(X.device)
     c.check(lib().tpe_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
                                float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
+    return E, G
+
+
+def _check_pair(X, F, Y, FY):
+    X, F = _check_mesh(X, F)
+    Y, FY = _check_mesh(Y, FY)
+    if Y.device != X.device:
+        raise ValueError("both surfaces must be on the same device")
+    return X, F, Y, FY
+
+
+def conf_energy(X, F, Y, FY, q=6.0, p=12.0, scale=1.0, out=None) -> torch.Tensor:
+    """Confinement energy of the moving surface (X, F) against the fixed surface (Y, FY) (paper
+    eq. (TPConf) discretised), as a 0-dim float64 device tensor."""
+    X, F, Y, FY = _check_pair(X, F, Y, FY)
+    E = out if out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_conf_energy(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], Y.data_ptr(), Y.shape[0],
+                                  FY.data_ptr(), FY.shape[0], float(q), float(p), float(scale), E.data_ptr()))
+    return E
+
+
+def conf_gradient(X, F, Y, FY, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
+    """(E_conf, dE_conf/dX float64 [V, 3]); the confining surface (Y, FY) is fixed."""
+    X, F, Y, FY = _check_pair(X, F, Y, FY)
+    G = out if out is not None else torch.empty_like(X)
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_conf_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], Y.data_ptr(),
+                                    Y.shape[0], FY.data_ptr(), FY.shape[0], float(q), float(p), float(scale),
+                                    E.data_ptr(), G.data_ptr()))
     return E, G
 
 

@@ -36,14 +36,17 @@ hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* c
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
                         int nrb, int touch_words, uint32_t* touch, hipStream_t st);
 int pair_blocks_per_cu(bool grad);
-Sched make_sched(int64_t Fp, int waves);
+Sched make_sched(int64_t rows_p, int64_t cols_p, int waves);
 int64_t pair_part_floats(const Sched& sc, bool grad);
 hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                        const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st);
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
-                           double p, double scale, double* corner, double* epart, uint32_t* ticket, uint32_t* flags,
-                           double* E, hipStream_t st);
+                           double p, double scale, double efac, double* corner, double* epart, uint32_t* ticket,
+                           uint32_t* flags, double* E, hipStream_t st);
+hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
+                            const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
+                            hipStream_t st);
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
                          hipStream_t st);
 int finalize_blocks(int64_t nF);
@@ -207,6 +210,12 @@ struct Plan {
     int4* colv;
     float* part;
     unsigned long long* counter;
+    // confinement: the fixed confining surface (columns)
+    int64_t nFY = 0, VY = 0, FpY = 0;
+    int morton_bits_y = 0;
+    ColRec* colsY = nullptr;
+    int4* colvY = nullptr;
+    double *c64Y = nullptr, *geoY = nullptr, *orgY = nullptr;
     // far field
     int treeH = -1;
     void *nodes64 = nullptr, *recs = nullptr;
@@ -219,12 +228,13 @@ struct Plan {
 void layout(Plan& P, char* base, bool grad) {
     Carve c(base);
     const int64_t nF = P.nF, V = P.V, Fp = P.Fp;
-    P.keys = c.take<uint32_t>(nF);
-    P.vals = c.take<uint32_t>(nF);
-    P.ktmp = c.take<uint32_t>(nF);
-    P.vtmp = c.take<uint32_t>(nF);
-    P.hist = c.take<uint32_t>((size_t)radix_hist_words(nF));
-    P.hoff = c.take<uint32_t>((size_t)radix_hist_words(nF));
+    const int64_t ns = std::max(nF, P.nFY);  // the sort buffers serve both surfaces in turn
+    P.keys = c.take<uint32_t>(ns);
+    P.vals = c.take<uint32_t>(ns);
+    P.ktmp = c.take<uint32_t>(ns);
+    P.vtmp = c.take<uint32_t>(ns);
+    P.hist = c.take<uint32_t>((size_t)radix_hist_words(ns));
+    P.hoff = c.take<uint32_t>((size_t)radix_hist_words(ns));
     P.bbox = c.take<uint32_t>(8);
     P.counter = c.take<unsigned long long>(1);
     // one contiguous zero-initialised region
@@ -246,6 +256,13 @@ void layout(Plan& P, char* base, bool grad) {
     P.corner = c.take<double>(grad ? 9 * nF : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
+    if (P.FpY > 0) {
+        P.colsY = c.take<ColRec>(P.FpY);
+        P.colvY = c.take<int4>(P.FpY);
+        P.c64Y = c.take<double>(3 * P.FpY);
+        P.geoY = c.take<double>(5 * P.FpY);
+        P.orgY = c.take<double>(3 * (P.FpY / CTILE));
+    }
     if (P.treeH >= 0) {
         P.nodes64 = c.take<char>(tree_node_bytes(P.treeH));
         P.recs = c.take<char>(tree_rec_bytes(P.treeH));
@@ -256,15 +273,21 @@ void layout(Plan& P, char* base, bool grad) {
     P.bytes = c.off + 256;
 }
 
-void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1) {
+void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1, int64_t nFY = 0,
+          int64_t VY = 0) {
     P.treeH = treeH;
+    P.nFY = nFY;
+    P.VY = VY;
+    P.FpY = nFY > 0 ? round_up(nFY, std::max(ROWB, CTILE)) : 0;
+    P.morton_bits_y = nFY <= (int64_t)1 << 18 ? 6 : 10;
     P.nF = nF;
     P.V = V;
     P.Fp = round_up(nF, std::max(ROWB, CTILE));
     P.ntiles = (int)(P.Fp / CTILE);
     P.nrb = (int)(P.Fp / ROWB);
     P.touch_words = (int)((P.Fp / CHUNK + 31) / 32);
-    P.sc = make_sched(P.Fp, ctx->target_waves > 0 ? (int)ctx->target_waves : ctx->resident[grad ? 1 : 0]);
+    P.sc = make_sched(P.Fp, P.FpY > 0 ? P.FpY : P.Fp,
+                      ctx->target_waves > 0 ? (int)ctx->target_waves : ctx->resident[grad ? 1 : 0]);
     P.sort_blocks = (int)ceil_div(nF, 4096);
     // Morton resolution: 6 bits per axis (2 radix passes of 9 bits) up to 2^18 faces, 10 above
     // (3 passes of 10 bits)
@@ -363,8 +386,54 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
-                           P.ticket, ctx->dflags, E, st));
+    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.corner,
+                           P.epart, P.ticket, ctx->dflags, E, st));
+    if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
+// Confinement energy / gradient: rows = the moving surface (X, F) in Morton order with its CSR for
+// the gather; columns = the confining surface (Y, FY) in Morton order, records only.  Both are
+// normalised by one power of two from their common bounding box.
+int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y, int64_t VY,
+             const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E, double* G) {
+    int rc = check_common(ctx, X, V, F, nF, q, p);
+    if (rc) return rc;
+    if ((rc = check_common(ctx, Y, VY, FY, nFY, q, p))) return rc;
+    if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
+    const bool grad = G != nullptr;
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    plan(P, ctx, nF, V, grad, -1, nFY, VY);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, grad);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(Y, VY, FY, nFY, P.bbox, ctx->dflags, st));
+    // confining surface: records in Morton order (the sort buffers are reused for the rows below)
+    HIPCHK(launch_morton(Y, VY, FY, nFY, P.bbox, P.morton_bits_y, P.keys, P.vals, st));
+    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nFY, 3 * P.morton_bits_y, P.hist, P.hoff, st));
+    HIPCHK(launch_records(Y, VY, FY, nFY, P.FpY, P.vals, P.bbox, P.orgY, P.colsY, P.colvY, P.c64Y, P.geoY, nullptr,
+                          ctx->dflags, st));
+    // moving surface: records, corner counts and CSR (no exclusion between different surfaces)
+    HIPCHK(launch_morton(X, V, F, nF, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nF, 3 * P.morton_bits, P.hist, P.hoff, st));
+    HIPCHK(launch_records(X, V, F, nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt, ctx->dflags,
+                          st));
+    if (grad) HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->kernel_timing) {
+        if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
+    }
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_pair_conf(grad, P.cols, P.c64, P.colv, P.colsY, P.colvY, P.orgY, P.sc, P.part, st));
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 1.0, P.corner,
+                           P.epart, P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -476,6 +545,21 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
 }
 
+int tpe_conf_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y,
+                    int64_t VY, const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E_dev) {
+    if (ctx && !E_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null E_dev");
+    return run_conf(ctx, X, V, F, nF, Y, VY, FY, nFY, q, p, scale, E_dev, nullptr);
+}
+
+int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y,
+                      int64_t VY, const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E_dev,
+                      double* G_dev) {
+    if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
+    if (ctx && ((const void*)G_dev == (const void*)X || (const void*)G_dev == (const void*)Y))
+        return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases an input");
+    return run_conf(ctx, X, V, F, nF, Y, VY, FY, nFY, q, p, scale, E_dev, G_dev);
+}
+
 int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, int32_t leaf_size,
                    tpe_tree** out) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
@@ -564,8 +648,8 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, P.corner, P.epart,
-                           P.ticket, ctx->dflags, E_dev, st));
+    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.corner,
+                           P.epart, P.ticket, ctx->dflags, E_dev, st));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
                                                        const int4* __restrict__ colv,
                                                        const double* __restrict__ X,
                                                        const uint32_t* __restrict__ bbox, double q, double p,
-                                                       double scale, double* __restrict__ corner,
+                                                       double scale, double efac, double* __restrict__ corner,
                                                        double* __restrict__ epart, uint32_t* __restrict__ ticket,
                                                        double* __restrict__ E, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
         if (!GRAD) {
             e = a * acc[0];
         } else {
-            e = 0.5 * a * acc[0];
+            e = efac * a * acc[0];
             const double Ga = gs * acc[0];
             double Gn[3], Gc[3];
             for (int d = 0; d < 3; ++d) {
@@ -158,18 +158,19 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 
 // Row sums: the pair kernel's segments (part, sc) or, with part null, acc64 (NA x Fp FP64);
-// ticket: one word, zero on entry.
+// ticket: one word, zero on entry.  efac: E = efac sum_S a_S K_S with the gradient's row sums
+// (1/2 for the self energy, whose K holds both orders of every pair; 1 for the confinement).
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
-                           double p, double scale, double* corner, double* epart, uint32_t* ticket, uint32_t* flags,
-                           double* E, hipStream_t st) {
+                           double p, double scale, double efac, double* corner, double* epart, uint32_t* ticket,
+                           uint32_t* flags, double* E, hipStream_t st) {
     const int nb = finalize_blocks(nF);
     if (grad)
         hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, corner, epart, ticket, E, flags);
+                           bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
     else
         hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, corner, epart, ticket, E, flags);
+                           bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

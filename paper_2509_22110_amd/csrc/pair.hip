@@ -72,7 +72,10 @@ __device__ __forceinline__ void kahan_fold(float x, float& hi, float& c) {
     hi = t;
 }
 
-template <int Q, bool GRAD, bool MASK>
+// CONF: the column is a face of a fixed confining surface (paper Sec. 2.2.3, eq. (TPConf)): only
+// the row's normal enters and the pair counts once, so only the forward terms are summed (K, S0,
+// Sd, and Sdd with t^q alone; Sn stays 0).
+template <int Q, bool GRAD, bool MASK, bool CONF = false>
 __device__ __forceinline__ void pair_update(const ColRec& cr, int4 cv, float rx, float ry, float rz,
                                             float nx, float ny, float nz, int v0, int v1, int v2,
                                             float* acc) {
@@ -88,6 +91,20 @@ __device__ __forceinline__ void pair_update(const ColRec& cr, int4 cv, float rx,
     float t = u * w;
     if constexpr (!GRAD) {
         acc[0] = fmaf(cr.a, powq_only<Q>(t), acc[0]);
+    } else if constexpr (CONF) {
+        float t5, t6;
+        powq<Q>(t, t5, t6);
+        float aw = cr.a * w;
+        float s = aw * t5;
+        float m = aw * t6;
+        acc[0] = fmaf(cr.a, t6, acc[0]);
+        acc[1] += s;
+        acc[2] = fmaf(s, dx, acc[2]);
+        acc[3] = fmaf(s, dy, acc[3]);
+        acc[4] = fmaf(s, dz, acc[4]);
+        acc[5] = fmaf(m, dx, acc[5]);
+        acc[6] = fmaf(m, dy, acc[6]);
+        acc[7] = fmaf(m, dz, acc[7]);
     } else {
         float v = fmaf(cr.nz, dz, fmaf(cr.ny, dy, cr.nx * dx));
         float tau = v * w;
@@ -115,7 +132,7 @@ __device__ __forceinline__ void pair_update(const ColRec& cr, int4 cv, float rx,
 
 // One chunk of CHUNK columns for the wave's RPL x 64 rows: plain FP32 sums over the chunk, then a
 // Kahan fold into the rows' (hi, lo) accumulators.
-template <int Q, bool GRAD, bool MASK>
+template <int Q, bool GRAD, bool MASK, bool CONF = false>
 __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const int4* __restrict__ tv,
                                            const float (&rx)[RPL], const float (&ry)[RPL],
                                            const float (&rz)[RPL], const float (&nx)[RPL],
@@ -135,8 +152,8 @@ __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const 
         if constexpr (MASK) cv = tv[j];
 #pragma unroll
         for (int r = 0; r < RPL; ++r)
-            pair_update<Q, GRAD, MASK>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0], rv[r][1],
-                                       rv[r][2], acc[r]);
+            pair_update<Q, GRAD, MASK, CONF>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0], rv[r][1],
+                                             rv[r][2], acc[r]);
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
@@ -147,11 +164,15 @@ __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const 
 // grid: W work-groups of PAIR_NW waves.  part layout: [W * maxseg segments][2 * NA][ROWB] FP32;
 // the first NA rows of a segment hold hi, the next NA the compensation to add (the work-group's
 // waves' compensated sums folded into wave 0's).
-template <int Q, bool GRAD>
-__global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __restrict__ cols,
-                                                              const int4* __restrict__ colv,
-                                                              const double* __restrict__ c64,
-                                                              const double* __restrict__ org,
+// Rows come from (rcols, rc64, rcolv), columns from (ccols, ccolv, corg): the same arrays for the
+// self energy, the confining surface's for CONF (no exclusion map then).
+template <int Q, bool GRAD, bool CONF = false>
+__global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __restrict__ rcols,
+                                                              const double* __restrict__ rc64,
+                                                              const int4* __restrict__ rcolv,
+                                                              const ColRec* __restrict__ ccols,
+                                                              const int4* __restrict__ ccolv,
+                                                              const double* __restrict__ corg,
                                                               const uint32_t* __restrict__ touch, int touch_words,
                                                               Sched sc, float* __restrict__ part) {
     constexpr int NA = GRAD ? NACC : 1;
@@ -177,17 +198,17 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = rb * ROWB + r * WAVE + lane;
-            cxd[r] = c64[3 * (size_t)i + 0];
-            cyd[r] = c64[3 * (size_t)i + 1];
-            czd[r] = c64[3 * (size_t)i + 2];
-            const ColRec me = cols[i];
+            cxd[r] = rc64[3 * (size_t)i + 0];
+            cyd[r] = rc64[3 * (size_t)i + 1];
+            czd[r] = rc64[3 * (size_t)i + 2];
+            const ColRec me = rcols[i];
             nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz;
-            const int4 v = colv[i];
+            const int4 v = rcolv[i];
             rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
 #pragma unroll
             for (int k = 0; k < NACC; ++k) { hi[r][k] = 0.f; lo[r][k] = 0.f; }
         }
-        const uint32_t* my_touch = touch + (size_t)rb * touch_words;
+        const uint32_t* my_touch = CONF ? nullptr : touch + (size_t)rb * touch_words;
         int cur_t = -1;
         float rx[RPL], ry[RPL], rz[RPL];
         for (int64_t x = my0; x < my1; ++x) {
@@ -195,7 +216,7 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
             const int t = cu / CPT;
             if (t != cur_t) {
                 // rows relative to this tile's FP64 origin (columns are stored relative to it)
-                const double ox = org[3 * t + 0], oy = org[3 * t + 1], oz = org[3 * t + 2];
+                const double ox = corg[3 * t + 0], oy = corg[3 * t + 1], oz = corg[3 * t + 2];
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) {
                     rx[r] = (float)(cxd[r] - ox);
@@ -204,13 +225,17 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
                 }
                 cur_t = t;
             }
-            const bool masked = (my_touch[cu >> 5] >> (cu & 31)) & 1u;
-            const ColRec* tc = cols + (size_t)cu * CHUNK;
-            const int4* tv = colv + (size_t)cu * CHUNK;
-            if (masked)
-                chunk_pass<Q, GRAD, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
-            else
-                chunk_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+            const ColRec* tc = ccols + (size_t)cu * CHUNK;
+            const int4* tv = ccolv + (size_t)cu * CHUNK;
+            if constexpr (CONF) {
+                chunk_pass<Q, GRAD, false, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+            } else {
+                const bool masked = (my_touch[cu >> 5] >> (cu & 31)) & 1u;
+                if (masked)
+                    chunk_pass<Q, GRAD, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                else
+                    chunk_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+            }
         }
         if (wave > 0) {
             float* mine = red_lds + (size_t)(wave - 1) * 2 * NA * ROWB + lane;
@@ -260,10 +285,11 @@ int pair_blocks_per_cu(bool grad) {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-Sched make_sched(int64_t Fp, int waves) {
+// rows_p padded rows (multiple of ROWB) against cols_p padded columns (multiple of CHUNK)
+Sched make_sched(int64_t rows_p, int64_t cols_p, int waves) {
     Sched sc;
-    const int nrb = (int)(Fp / ROWB);
-    sc.upr = (int)(Fp / CHUNK);
+    const int nrb = (int)(rows_p / ROWB);
+    sc.upr = (int)(cols_p / CHUNK);
     sc.U = (int64_t)nrb * sc.upr;
     sc.W = (int)std::max<int64_t>(1, std::min<int64_t>(waves, sc.U));
     const int64_t per = (sc.U + sc.W - 1) / sc.W;
@@ -279,10 +305,24 @@ hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const do
                        const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st) {
     if (grad)
         hipLaunchKernelGGL((pair_kernel<6, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true), st, cols,
-                           colv, c64, org, touch, touch_words, sc, part);
+                           c64, colv, cols, colv, org, touch, touch_words, sc, part);
     else
         hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(false), st, cols,
-                           colv, c64, org, touch, touch_words, sc, part);
+                           c64, colv, cols, colv, org, touch, touch_words, sc, part);
+    return hipGetLastError();
+}
+
+// Confinement: rows (moving surface) against the confining surface's columns; the energy-only
+// kernel is the self kernel's (forward term only) without exclusion.
+hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
+                            const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
+                            hipStream_t st) {
+    if (grad)
+        hipLaunchKernelGGL((pair_kernel<6, true, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true), st,
+                           rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part);
+    else
+        hipLaunchKernelGGL((pair_kernel<6, false, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(false),
+                           st, rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part);
     return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         r.cx = (float)(c[0] - o[0]);
         r.cy = (float)(c[1] - o[1]);
         r.cz = (float)(c[2] - o[2]);
-        if (ok)
+        if (ok && cnt)
             for (int k = 0; k < 3; ++k) atomicAdd(&cnt[v[k]], 1u);
         r.a = (float)a;
         r.nx = (float)n[0]; r.ny = (float)n[1]; r.nz = (float)n[2];

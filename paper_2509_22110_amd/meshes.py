@@ -302,3 +302,16 @@ def make_config(name: str, seed: int = 0, **kw) -> ConfigMesh:
     C5: level-8 (1,310,720 faces), SH l=2..32 at max|r-1| = 0.2 plus a bump at gap 0.01.
     """
     return CONFIGS[name](seed, **kw)
+
+
+def confinement_config(level: int = 5, conf_level: int = 5, radius: float = 1.1, flatten: float = 0.02,
+                       seed: int = 0) -> tuple:
+    """Sphere inside a spherical confinement (the paper's Sec. 4.2 setting): the unit icosphere of
+    `level`, slightly flattened on one side (an inward Gaussian dent of depth `flatten` and width 0.3
+    at vertex 0), and the concentric icosphere of `conf_level` scaled to `radius`, both turned by
+    the same seeded rotation.  Returns (X, F, Y, FY)."""
+    X, F = icosphere(level)
+    X, _, _ = bump(X, 0, 0.3, depth=flatten)
+    Y, FY = icosphere(conf_level)
+    R = random_rotation(seed)
+    return X @ R.T, F, (radius * Y) @ R.T, FY
