@@ -10,6 +10,8 @@ HBM.  Prints ONE JSON line:
                 vector peak; traffic = HBM bytes per launch from the committed rocprofv3 counter
                 summary (profiles/pair_kernel_C2_traffic.txt), null when the kernel's sources
                 have changed since it was taken
+    confinement = the confinement energy + gradient of a flattened sphere in a radius-1.1 sphere
+                (20,480 x 20,480 faces): pairs/s and the kernel's algorithmic FP32 rate
     farfield  = ms per gradient on the level-7 workload (327,680 faces): exact all-pairs vs the
                 cluster-tree far field (monopole, and with the learned correction), with their
                 relative errors against the exact path
@@ -56,6 +58,7 @@ def parse():
     ap.add_argument("--ff-config", default="C4")
     ap.add_argument("--ff-reps", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--no-conf", action="store_true", help="skip the confinement-energy timing")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
 
@@ -149,6 +152,43 @@ def farfield_leg(args, T, M, torch, dev):
     return out
 
 
+# algorithmic FP32 work of one (moving face, confining face) pair of the confinement gradient:
+# d 3, |d|^2 5, 1/|d|^2 1, n_S.d 5, t 1, t^5 t^6 4, a w / s / m 3, K 2, S0 1, Sd 6, Sdd 6
+FLOP_PER_CONF_PAIR = 37
+
+
+def conf_leg(args, T, M, torch, dev):
+    """Confinement energy + gradient (the sphere-inversion setting: the slightly flattened unit
+    sphere inside the concentric sphere of radius 1.1, both level 5, 20,480 x 20,480 faces)."""
+    X, F, Y, FY = M.confinement_config(5, 5)
+    Xd, Fd = torch.from_numpy(X).to(dev), torch.from_numpy(F).to(dev)
+    Yd, FYd = torch.from_numpy(Y).to(dev), torch.from_numpy(FY).to(dev)
+    G = torch.empty_like(Xd)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    pairs = F.shape[0] * FY.shape[0]
+    for _ in range(3):
+        T.conf_gradient(Xd, Fd, Yd, FYd, out=G, energy_out=E)
+    ctx = T.context(dev)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+    ctx.kernel_time()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        T.conf_gradient(Xd, Fd, Yd, FYd, out=G, energy_out=E)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    k_ms, k_n = ctx.kernel_time()
+    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+    ctx.sync_check()
+    k_ms /= max(k_n, 1)
+    return {"workload": "flattened unit sphere (level 5, 20,480 faces) in the concentric radius-1.1 sphere "
+                        "(level 5, 20,480 faces)", "pairs": pairs, "ms_per_call": round(dt * 1e3, 4),
+            "pairs_per_s": pairs / dt, "kernel": "pair_kernel<6,true,CONF>", "kernel_avg_ms": round(k_ms, 4),
+            "kernel_tflops": round(FLOP_PER_CONF_PAIR * pairs / (k_ms * 1e-3) / 1e12, 2),
+            "flop_per_pair": FLOP_PER_CONF_PAIR}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -213,6 +253,7 @@ def main():
                 "kernel_avg_ms": round(k_avg_ms, 4), "flop_per_pair": FLOP_PER_PAIR}
 
     ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
+    conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -238,6 +279,7 @@ def main():
                    "faces": cfg.nF, "pairs": P, "q": 6, "p": 12, "parallelism": "single-gpu"},
         "roofline": roofline,
         "farfield": ff,
+        "confinement": conf,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
