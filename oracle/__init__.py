@@ -64,6 +64,10 @@ def _load():
         lib.tpeo_conf_gradient.argtypes = [P, I64, P, I64, P, I64, P, I64, D, D, D, I32, P, P]
         lib.tpeo_conf_energy.restype = I32
         lib.tpeo_conf_gradient.restype = I32
+        lib.tpeo_gradient_quad.argtypes = [P, I64, P, I64, D, D, D, I32, I32, P, P]
+        lib.tpeo_gradient_quad.restype = I32
+        lib.tpeo_quad_rule.argtypes = [I32, P, P]
+        lib.tpeo_quad_rule.restype = I32
         lib.tpeo_pair_count.argtypes = [P, I64]
         lib.tpeo_pair_count.restype = I64
         lib.tpeo_num_threads.argtypes = [I32]
@@ -155,6 +159,28 @@ def conf_gradient(X, F, Y, FY, q=6.0, p=12.0, scale=1.0, nthreads=0):
     rc = _load().tpeo_conf_gradient(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], Y.ctypes.data,
                                     Y.shape[0], FY.ctypes.data, FY.shape[0], q, p, scale, nthreads, E.ctypes.data,
                                     G.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G
+
+
+def quad_rule(rule):
+    """(barycentric points [Q, 3], weights [Q]) of the oracle's triangle rule (1, 3 or 6 points)."""
+    b = np.zeros((6, 3))
+    w = np.zeros(6)
+    n = _load().tpeo_quad_rule(int(rule), b.ctypes.data, w.ctypes.data)
+    if n == 0:
+        raise OracleError(-1)
+    return b[:n].copy(), w[:n].copy()
+
+
+def gradient_quad(X, F, rule, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=True):
+    """(E_Q, dE_Q/dX) with `rule`-point quadrature on every face (G is None if not want_grad)."""
+    X, F = _prep(X, F)
+    E = np.zeros(1)
+    G = np.zeros_like(X) if want_grad else None
+    rc = _load().tpeo_gradient_quad(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale, int(rule),
+                                    nthreads, E.ctypes.data, G.ctypes.data if want_grad else None)
     if rc:
         raise OracleError(rc)
     return float(E[0]), G

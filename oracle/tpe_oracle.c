@@ -434,3 +434,159 @@ int tpeo_conf_energy(const double* X, int64_t V, const int32_t* F, int64_t nF, c
     return tpeo_conf_gradient(X, V, F, nF, Y, VY, FY, nFY, q, p, scale, nthreads, E_out, NULL);
 }
 
+/*
+ * Multi-point quadrature on each flat triangle (the paper integrates both integrals of eq. (TP)
+ * with higher-order rules, Sec. 3.2): face f carries points x_fp = sum_i beta_pi x_(v_i) with weights
+ * W_p (sum_p W_p = 1), and
+ *
+ *   E_Q(X) = scale * sum_S sum_{T : S,T share no vertex} sum_p sum_r W_p W_r a_S a_T
+ *                    |n_S . (x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p .
+ *
+ * Rules (barycentric points, weights), written out here from their published values:
+ *   1: the centroid, weight 1 (the one-point quadrature above);
+ *   3: (2/3, 1/6, 1/6) and its permutations, weights 1/3 (exact for degree 2; Strang and Fix);
+ *   6: (1 - 2a, a, a) and permutations for a = 0.445948490915965 (weight 0.223381589678011) and
+ *      a = 0.091576213509771 (weight 0.109951743655322) (exact for degree 4; Dunavant 1985).
+ * The gradient follows the chain rule through the points (dx_fp/dx_(v_i) = beta_pi I), the
+ * normal and the area, pushed straight to the vertices as above.
+ */
+static int quad_rule(int rule, double (*b)[3], double* w) {
+    if (rule == 1) {
+        b[0][0] = b[0][1] = b[0][2] = 1.0 / 3.0; w[0] = 1.0;
+        return 1;
+    }
+    if (rule == 3) {
+        for (int p = 0; p < 3; ++p) {
+            for (int i = 0; i < 3; ++i) b[p][i] = (i == p) ? 2.0 / 3.0 : 1.0 / 6.0;
+            w[p] = 1.0 / 3.0;
+        }
+        return 3;
+    }
+    if (rule == 6) {
+        const double a[2] = {0.445948490915965, 0.091576213509771};
+        const double wt[2] = {0.223381589678011, 0.109951743655322};
+        for (int g = 0; g < 2; ++g)
+            for (int p = 0; p < 3; ++p) {
+                for (int i = 0; i < 3; ++i) b[3 * g + p][i] = (i == p) ? 1.0 - 2.0 * a[g] : a[g];
+                w[3 * g + p] = wt[g];
+            }
+        return 6;
+    }
+    return 0;
+}
+
+int tpeo_quad_rule(int rule, double* bary_out, double* w_out) {
+    double b[6][3], w[6];
+    int n = quad_rule(rule, b, w);
+    for (int p = 0; p < n; ++p) {
+        for (int i = 0; i < 3; ++i) bary_out[3 * p + i] = b[p][i];
+        w_out[p] = w[p];
+    }
+    return n;
+}
+
+/* face_vjp with the point's barycentric weights instead of 1/3 for the position term */
+static void face_vjp_b(const double* X, const int32_t* F, int64_t f, const face_t* g, const double* dx,
+                       const double* beta, const double* dn, double da, nsum* GV) {
+    int32_t v[3] = {F[3*f+0], F[3*f+1], F[3*f+2]};
+    double gw[3];
+    double ndn = dn ? dot3(g->n, dn) : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        gw[d] = 0.5 * da * g->n[d];
+        if (dn) gw[d] += (dn[d] - ndn * g->n[d]) / g->wn;
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double* xj = X + 3 * (int64_t)v[(c + 1) % 3];
+        const double* xk = X + 3 * (int64_t)v[(c + 2) % 3];
+        double e[3], cr[3];
+        sub3(xj, xk, e);
+        cross3(e, gw, cr);
+        for (int d = 0; d < 3; ++d) nadd(&GV[3 * (int64_t)v[c] + d], beta[c] * dx[d] + cr[d]);
+    }
+}
+
+int tpeo_gradient_quad(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                       double scale, int rule, int nthreads, double* E_out, double* G_out) {
+    double b[6][3], w[6];
+    const int nq = quad_rule(rule, b, w);
+    if (!nq) return EINVAL_;
+    int rc = check_inputs(X, V, F, nF, q, p);
+    if (rc) return rc;
+    face_t* G = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
+    double* P = (double*)malloc(sizeof(double) * 3 * (size_t)nF * nq);  /* points [f][p][3] */
+    if (!G || !P) { free(G); free(P); return EINVAL_; }
+    rc = all_faces(X, F, nF, G);
+    if (rc) { free(G); free(P); return rc; }
+    for (int64_t f = 0; f < nF; ++f)
+        for (int k = 0; k < nq; ++k)
+            for (int d = 0; d < 3; ++d) {
+                double x = 0.0;
+                for (int i = 0; i < 3; ++i) x += b[k][i] * X[3 * (int64_t)F[3 * f + i] + d];
+                P[(f * nq + k) * 3 + d] = x;
+            }
+    int nt = nthreads_of(nthreads);
+    nsum* GV = G_out ? (nsum*)calloc((size_t)nt * (size_t)V * 3, sizeof(nsum)) : NULL;
+    nsum* part = (nsum*)calloc((size_t)nt, sizeof(nsum));
+    if ((G_out && !GV) || !part) { free(G); free(P); free(GV); free(part); return EINVAL_; }
+    int err = OK;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        nsum* myG = GV ? GV + (size_t)tid * (size_t)V * 3 : NULL;
+        nsum acc = {0.0, 0.0};
+        int lerr = OK;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < nF; ++s) {
+            for (int64_t t = 0; t < nF; ++t) {
+                if (share_vertex(F, s, t)) continue;
+                for (int ks = 0; ks < nq; ++ks)
+                    for (int kt = 0; kt < nq; ++kt) {
+                        /* a face record located at the quadrature point, with the face's normal */
+                        face_t S = G[s], T = G[t];
+                        for (int d = 0; d < 3; ++d) {
+                            S.c[d] = P[(s * nq + ks) * 3 + d];
+                            T.c[d] = P[(t * nq + kt) * 3 + d];
+                        }
+                        pairval pv;
+                        if (pair_eval(&S, &T, q, p, myG != NULL, &pv)) { lerr = ENONFIN; continue; }
+                        const double ww = w[ks] * w[kt];
+                        const double aa = ww * G[s].a * G[t].a;
+                        nadd(&acc, aa * pv.k);
+                        if (myG) {
+                            double dxS[3], dxT[3], dnS[3];
+                            for (int i = 0; i < 3; ++i) {
+                                dxS[i] = scale * aa * pv.dkdd[i];
+                                dxT[i] = -dxS[i];
+                                dnS[i] = scale * aa * pv.dkdn[i];
+                            }
+                            face_vjp_b(X, F, s, &G[s], dxS, b[ks], dnS, scale * ww * G[t].a * pv.k, myG);
+                            face_vjp_b(X, F, t, &G[t], dxT, b[kt], NULL, scale * ww * G[s].a * pv.k, myG);
+                        }
+                    }
+            }
+        }
+        part[tid] = acc;
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    nsum tot = {0.0, 0.0};
+    for (int i = 0; i < nt; ++i) { nadd(&tot, part[i].s); nadd(&tot, part[i].c); }
+    if (E_out) *E_out = err ? INFINITY : scale * nval(&tot);
+    if (G_out)
+        for (int64_t i = 0; i < V * 3; ++i) {
+            nsum g = {0.0, 0.0};
+            for (int th = 0; th < nt; ++th) {
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].s);
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].c);
+            }
+            G_out[i] = nval(&g);
+        }
+    free(GV); free(part); free(G); free(P);
+    return err;
+}
+
