@@ -64,10 +64,17 @@ typedef enum {
     TPE_OPT_TARGET_WAVES = 2, /* work-groups (of 4 waves) of the persistent exact pair kernel;
                                  0 (default) = as many as the device keeps resident at once.  The
                                  work is split evenly over them; results agree to rounding */
-    TPE_OPT_KERNEL_TIMING = 3 /* 1: record HIP events around every launch of the dominant
+    TPE_OPT_KERNEL_TIMING = 3, /* 1: record HIP events around every launch of the dominant
                                  kernel (the pair kernel, or the far-field walk) on the context's
                                  stream; 2: around the finalize + vertex-gather launches; read
                                  back with tpe_kernel_time(); 0 (default): off */
+    TPE_OPT_QUADRATURE = 4    /* quadrature points per face of tpe_energy / tpe_gradient: 1
+                                 (default, the centroid), 3 (degree 2) or 6 (degree 4); the paper
+                                 integrates both integrals with higher-order rules (Sec. 3.2).  Each
+                                 point pair of two faces sharing no vertex contributes
+                                 W_p W_r a_S a_T |n_S.(x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p.  The far
+                                 field and the confinement energy take 1 only (else
+                                 TPE_ERR_UNSUPPORTED); at most 2^26 points in all. */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */

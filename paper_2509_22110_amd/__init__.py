@@ -29,6 +29,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "degenerate face", -3: "non-finit
 OPT_SYNC_CHECKS = 1
 OPT_TARGET_WAVES = 2
 OPT_KERNEL_TIMING = 3
+OPT_QUADRATURE = 4
 
 
 class TPEError(RuntimeError):

@@ -22,15 +22,15 @@ hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st);
 hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox, uint32_t* flags,
                        hipStream_t st);
-hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, const uint32_t* bbox,
                          int bits, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st);
 int64_t radix_hist_words(int64_t n);
 int64_t scan_ws_words(int64_t n);
-hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp, const uint32_t* perm,
-                          const uint32_t* bbox, double* org, ColRec* cols, int4* colv, double* c64, double* geo,
-                          uint32_t* cnt, uint32_t* flags, hipStream_t st);
+hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, int64_t Fp,
+                          const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
+                          double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st);
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off, uint32_t* cursor,
                             uint32_t* list, uint32_t* ws, hipStream_t st);
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
@@ -42,8 +42,8 @@ hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const do
                        const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st);
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
-                           double p, double scale, double efac, double* corner, double* epart, uint32_t* ticket,
-                           uint32_t* flags, double* E, hipStream_t st);
+                           double p, double scale, double efac, int Q, double* corner, double* epart,
+                           uint32_t* ticket, uint32_t* flags, double* E, hipStream_t st);
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
@@ -120,6 +120,7 @@ struct tpe_ctx {
     std::string err;
     bool sync_checks = true;
     int64_t target_waves = 0;     // 0: resident-wave capacity of the pair kernel
+    int quad = 1;                 // quadrature points per face of the exact path (1, 3 or 6)
     int resident[2] = {0, 0};     // pair-kernel waves resident on the device (energy, gradient)
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -197,6 +198,8 @@ struct Carve {
 
 struct Plan {
     int64_t nF, V, Fp;
+    int Q = 1;        // quadrature points per face (records per face)
+    int64_t nR = 0;   // records = Q nF
     int ntiles, nrb, touch_words, sort_blocks, fin_blocks;
     Sched sc;
     // buffers
@@ -228,7 +231,8 @@ struct Plan {
 void layout(Plan& P, char* base, bool grad) {
     Carve c(base);
     const int64_t nF = P.nF, V = P.V, Fp = P.Fp;
-    const int64_t ns = std::max(nF, P.nFY);  // the sort buffers serve both surfaces in turn
+    const int64_t nR = P.nR;
+    const int64_t ns = std::max(nR, P.nFY);  // the sort buffers serve both surfaces in turn
     P.keys = c.take<uint32_t>(ns);
     P.vals = c.take<uint32_t>(ns);
     P.ktmp = c.take<uint32_t>(ns);
@@ -246,14 +250,14 @@ void layout(Plan& P, char* base, bool grad) {
     P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.voff = c.take<uint32_t>(V + 1);
     P.scanws = c.take<uint32_t>((size_t)scan_ws_words(V) + 1);
-    P.list = c.take<uint32_t>(3 * nF);
+    P.list = c.take<uint32_t>(3 * nR);
     P.org = c.take<double>(3 * (size_t)P.ntiles);
     P.cols = c.take<ColRec>(Fp);
     P.colv = c.take<int4>(Fp);
     P.c64 = c.take<double>(3 * Fp);
     P.geo = c.take<double>(5 * Fp);
     P.part = c.take<float>((size_t)pair_part_floats(P.sc, grad));
-    P.corner = c.take<double>(grad ? 9 * nF : 1);
+    P.corner = c.take<double>(grad ? 9 * nR : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
     if (P.FpY > 0) {
@@ -274,25 +278,27 @@ void layout(Plan& P, char* base, bool grad) {
 }
 
 void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1, int64_t nFY = 0,
-          int64_t VY = 0) {
+          int64_t VY = 0, int Q = 1) {
     P.treeH = treeH;
+    P.Q = Q;
+    P.nR = nF * Q;
     P.nFY = nFY;
     P.VY = VY;
     P.FpY = nFY > 0 ? round_up(nFY, std::max(ROWB, CTILE)) : 0;
     P.morton_bits_y = nFY <= (int64_t)1 << 18 ? 6 : 10;
     P.nF = nF;
     P.V = V;
-    P.Fp = round_up(nF, std::max(ROWB, CTILE));
+    P.Fp = round_up(P.nR, std::max(ROWB, CTILE));
     P.ntiles = (int)(P.Fp / CTILE);
     P.nrb = (int)(P.Fp / ROWB);
     P.touch_words = (int)((P.Fp / CHUNK + 31) / 32);
     P.sc = make_sched(P.Fp, P.FpY > 0 ? P.FpY : P.Fp,
                       ctx->target_waves > 0 ? (int)ctx->target_waves : ctx->resident[grad ? 1 : 0]);
-    P.sort_blocks = (int)ceil_div(nF, 4096);
+    P.sort_blocks = (int)ceil_div(P.nR, 4096);
     // Morton resolution: 6 bits per axis (2 radix passes of 9 bits) up to 2^18 faces, 10 above
     // (3 passes of 10 bits)
     P.morton_bits = nF <= (int64_t)1 << 18 ? 6 : 10;
-    P.fin_blocks = finalize_blocks(nF);
+    P.fin_blocks = finalize_blocks(P.nR);
     layout(P, nullptr, grad);
 }
 
@@ -356,12 +362,12 @@ int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
     HIPCHK(launch_bbox(X, P.V, F, P.nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_morton(X, P.V, F, P.nF, P.bbox, P.morton_bits, P.keys, P.vals, st));
-    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nF, 3 * P.morton_bits, P.hist, P.hoff, st));
-    HIPCHK(launch_records(X, P.V, F, P.nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    HIPCHK(launch_morton(X, P.V, F, P.nF, P.Q, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nR, 3 * P.morton_bits, P.hist, P.hoff, st));
+    HIPCHK(launch_records(X, P.V, F, P.nF, P.Q, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
-    HIPCHK(launch_adjacency(P.colv, P.nF, P.V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
-    HIPCHK(launch_touch(P.colv, P.nF, P.V, P.voff, P.list, P.nrb, P.touch_words, P.touch, st));
+    HIPCHK(launch_adjacency(P.colv, P.nR, P.V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
+    HIPCHK(launch_touch(P.colv, P.nR, P.V, P.voff, P.list, P.nrb, P.touch_words, P.touch, st));
     return TPE_OK;
 }
 
@@ -371,9 +377,10 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (rc) return rc;
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     const bool grad = G != nullptr;
+    if (nF * ctx->quad > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
     DeviceGuard dg(ctx->device);
     Plan P;
-    plan(P, ctx, nF, V, grad);
+    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
@@ -386,8 +393,8 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.corner,
-                           P.epart, P.ticket, ctx->dflags, E, st));
+    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, P.nR, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.Q,
+                           P.corner, P.epart, P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -401,6 +408,7 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
              const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E, double* G) {
     int rc = check_common(ctx, X, V, F, nF, q, p);
     if (rc) return rc;
+    if (ctx->quad != 1) return fail(ctx, TPE_ERR_UNSUPPORTED, "the confinement energy uses one point per face");
     if ((rc = check_common(ctx, Y, VY, FY, nFY, q, p))) return rc;
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     const bool grad = G != nullptr;
@@ -414,14 +422,14 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_bbox(Y, VY, FY, nFY, P.bbox, ctx->dflags, st));
     // confining surface: records in Morton order (the sort buffers are reused for the rows below)
-    HIPCHK(launch_morton(Y, VY, FY, nFY, P.bbox, P.morton_bits_y, P.keys, P.vals, st));
+    HIPCHK(launch_morton(Y, VY, FY, nFY, 1, P.bbox, P.morton_bits_y, P.keys, P.vals, st));
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nFY, 3 * P.morton_bits_y, P.hist, P.hoff, st));
-    HIPCHK(launch_records(Y, VY, FY, nFY, P.FpY, P.vals, P.bbox, P.orgY, P.colsY, P.colvY, P.c64Y, P.geoY, nullptr,
+    HIPCHK(launch_records(Y, VY, FY, nFY, 1, P.FpY, P.vals, P.bbox, P.orgY, P.colsY, P.colvY, P.c64Y, P.geoY, nullptr,
                           ctx->dflags, st));
     // moving surface: records, corner counts and CSR (no exclusion between different surfaces)
-    HIPCHK(launch_morton(X, V, F, nF, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(launch_morton(X, V, F, nF, 1, P.bbox, P.morton_bits, P.keys, P.vals, st));
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nF, 3 * P.morton_bits, P.hist, P.hoff, st));
-    HIPCHK(launch_records(X, V, F, nF, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt, ctx->dflags,
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt, ctx->dflags,
                           st));
     if (grad) HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -432,8 +440,8 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     HIPCHK(launch_pair_conf(grad, P.cols, P.c64, P.colv, P.colsY, P.colvY, P.orgY, P.sc, P.part, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 1.0, P.corner,
-                           P.epart, P.ticket, ctx->dflags, E, st));
+    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 1.0, 1,
+                           P.corner, P.epart, P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -512,6 +520,11 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
         case TPE_OPT_TARGET_WAVES:
             if (value < 0 || value > (int64_t)1 << 24) return fail(ctx, TPE_ERR_INVALID_ARG, "target waves");
             ctx->target_waves = value;
+            return TPE_OK;
+        case TPE_OPT_QUADRATURE:
+            if (!quad_rule_ok((int)value) || value != (int)value)
+                return fail(ctx, TPE_ERR_INVALID_ARG, "quadrature: 1, 3 or 6 points per face");
+            ctx->quad = (int)value;
             return TPE_OK;
         case TPE_OPT_KERNEL_TIMING:
             if (value < 0 || value > 2) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0, 1 or 2");
@@ -626,6 +639,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
     if (mlp && mlp->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "MLP lives on another device");
+    if (ctx->quad != 1) return fail(ctx, TPE_ERR_UNSUPPORTED, "the far field uses one point per face");
     DeviceGuard dg(ctx->device);
     Plan P;
     plan(P, ctx, nF, V, true, tree->H);
@@ -634,7 +648,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
     HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_records(X, V, F, nF, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
     HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
@@ -648,8 +662,8 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.corner,
-                           P.epart, P.ticket, ctx->dflags, E_dev, st));
+    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
+                           P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -675,7 +689,7 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
     HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_records(X, V, F, nF, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
     const uint32_t sel = select_prob >= 1.0 ? 0xffffffffu : (uint32_t)(select_prob * 4294967296.0);

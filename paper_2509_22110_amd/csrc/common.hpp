@@ -21,6 +21,28 @@ constexpr int CTILE = 64;               // columns per tile (one FP64 origin per
 constexpr int CHUNK = 64;               // columns summed in plain FP32 before a compensated fold
 constexpr int NACC = 11;                // accumulators per row face (see pair.hip)
 
+// Triangle quadrature rules: point p of the Q-point rule as barycentric weights b on the face's
+// vertices (in the order of F) and its weight w (the weights sum to 1).
+//   Q = 1: the centroid.
+//   Q = 3: (2/3, 1/6, 1/6) and its permutations, weights 1/3 (exact for degree 2; Strang and Fix).
+//   Q = 6: (1 - 2a, a, a) and its permutations for a = 0.445948490915965, weight 0.223381589678011,
+//          and for a = 0.091576213509771, weight 0.109951743655322 (exact for degree 4; Dunavant).
+__host__ __device__ inline bool quad_rule_ok(int Q) { return Q == 1 || Q == 3 || Q == 6; }
+__host__ __device__ inline void quad_point(int Q, int p, double* b, double& w) {
+    if (Q == 3) {
+        for (int i = 0; i < 3; ++i) b[i] = i == p ? 2.0 / 3.0 : 1.0 / 6.0;
+        w = 1.0 / 3.0;
+    } else if (Q == 6) {
+        const int g = p / 3, k = p % 3;
+        const double a = g == 0 ? 0.445948490915965 : 0.091576213509771;
+        for (int i = 0; i < 3; ++i) b[i] = i == k ? 1.0 - 2.0 * a : a;
+        w = g == 0 ? 0.223381589678011 : 0.109951743655322;
+    } else {
+        b[0] = b[1] = b[2] = 1.0 / 3.0;
+        w = 1.0;
+    }
+}
+
 // Column record read with scalar loads: centroid relative to its tile origin, area, normal.
 struct __align__(32) ColRec {
     float cx, cy, cz, a;

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
                                                        const int4* __restrict__ colv,
                                                        const double* __restrict__ X,
                                                        const uint32_t* __restrict__ bbox, double q, double p,
-                                                       double scale, double efac, double* __restrict__ corner,
+                                                       double scale, double efac, int Q,
+                                                       double* __restrict__ corner,
                                                        double* __restrict__ epart, uint32_t* __restrict__ ticket,
                                                        double* __restrict__ E, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
@@ -78,7 +79,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
             e = a * acc[0];
         } else {
             e = efac * a * acc[0];
-            const double Ga = gs * acc[0];
+            // the record is quadrature point v.w of its face, with weight wq (Q = 1: the centroid)
+            const int4 v = colv[i];
+            double bq[3], wq;
+            quad_point(Q, v.w, bq, wq);
+            const double Ga = gs * wq * acc[0];
             double Gn[3], Gc[3];
             for (int d = 0; d < 3; ++d) {
                 Gn[d] = gs * q * a * acc[2 + d];
@@ -87,7 +92,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
             const double nGn = n[0] * Gn[0] + n[1] * Gn[1] + n[2] * Gn[2];
             double gw[3];
             for (int d = 0; d < 3; ++d) gw[d] = 0.5 * Ga * n[d] + (Gn[d] - nGn * n[d]) / wn;
-            const int4 v = colv[i];
             const int vv[3] = {v.x, v.y, v.z};
             double x[3][3];
             for (int c = 0; c < 3; ++c)
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
                 const double cr[3] = {ed[1] * gw[2] - ed[2] * gw[1], ed[2] * gw[0] - ed[0] * gw[2],
                                       ed[0] * gw[1] - ed[1] * gw[0]};
                 for (int d = 0; d < 3; ++d) {
-                    const double g = Gc[d] / 3.0 + cr[d];
+                    const double g = (Q == 1 ? Gc[d] / 3.0 : bq[c] * Gc[d]) + cr[d];
                     finite &= isfinite(g);
                     corner[9 * i + 3 * c + d] = g;
                 }
@@ -162,15 +166,15 @@ int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 // (1/2 for the self energy, whose K holds both orders of every pair; 1 for the confinement).
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
-                           double p, double scale, double efac, double* corner, double* epart, uint32_t* ticket,
-                           uint32_t* flags, double* E, hipStream_t st) {
+                           double p, double scale, double efac, int Q, double* corner, double* epart,
+                           uint32_t* ticket, uint32_t* flags, double* E, hipStream_t st) {
     const int nb = finalize_blocks(nF);
     if (grad)
         hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+                           bbox, q, p, scale, efac, Q, corner, epart, ticket, E, flags);
     else
         hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+                           bbox, q, p, scale, efac, Q, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

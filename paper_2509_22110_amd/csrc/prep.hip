@@ -100,11 +100,14 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 
 // 3*bits-bit Morton key (bits <= 10 per axis) of each face centroid inside the centroid bounding
 // box; value = face id.
+// One key per record r < Q nF (the Q quadrature points of face r / Q share the face centroid's key,
+// so a stable sort keeps a face's records together, in point order).
 __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
-                            int64_t nF, const uint32_t* __restrict__ bbox, int bits,
+                            int64_t nF, int Q, const uint32_t* __restrict__ bbox, int bits,
                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (f >= nF) return;
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nF * Q) return;
+    const int64_t f = r / Q;
     float lo[3], ext[3];
     for (int d = 0; d < 3; ++d) {
         lo[d] = ordered_to_float(bbox[d]);
@@ -125,8 +128,8 @@ __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32
             q[d] = isfinite(s) ? (uint32_t)s : 0u;
         }
     }
-    keys[f] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-    vals[f] = (uint32_t)f;
+    keys[r] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    vals[r] = (uint32_t)r;
 }
 
 // Sorted face records.  For sorted position i < nF: face f = perm[i].  Positions in [nF, Fp) are
@@ -148,12 +151,14 @@ __device__ __forceinline__ double wave_max(double x) {
     return x;
 }
 
-// One thread per sorted position i < Fp (whole waves: Fp is a multiple of 128).  A wave covers one
-// chunk of CTILE = 64 positions; the chunk's FP64 origin is the centre of its faces' centroid
-// bounding box, so the FP32 record coordinates relative to it are at most half the chunk's
-// extent (their rounding error sets the accuracy of the closest pairs).
+// One thread per sorted position i < Fp (whole waves: Fp is a multiple of 128).  Record perm[i] = r
+// is quadrature point r % Q of face r / Q (Q = 1: the centroid): position sum_k b_k x_(v_k),
+// weight w a, the face's normal, vertex ids and the point index (colv.w).  A wave covers one
+// chunk of CTILE = 64 positions; the chunk's FP64 origin is the centre of its points' bounding
+// box, so the FP32 record coordinates relative to it are at most half the chunk's extent (their
+// rounding error sets the accuracy of the closest pairs).
 __global__ void face_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
-                             int64_t nF, int64_t Fp, const uint32_t* __restrict__ perm,
+                             int64_t nF, int Q, int64_t Fp, const uint32_t* __restrict__ perm,
                              const uint32_t* __restrict__ bbox, double* __restrict__ org,
                              ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
                              double* __restrict__ geo, uint32_t* __restrict__ cnt,
@@ -161,12 +166,15 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= Fp) return;
     const double s = norm_scale(bbox);
-    bool real = i < nF, ok = false;
+    bool real = i < nF * Q, ok = false;
     int32_t v[3] = {-1, -1, -1};
+    int pt = 0;
     double a = 0.0, wn = 1.0, n[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
     uint32_t fl = 0;
     if (real) {
-        const int64_t f = perm[i];
+        const int64_t rec = perm[i];
+        const int64_t f = rec / Q;
+        pt = (int)(rec % Q);
         v[0] = F[3 * f]; v[1] = F[3 * f + 1]; v[2] = F[3 * f + 2];
         ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
         double xi[3] = {0, 0, 0}, xj[3] = {1, 0, 0}, xk[3] = {0, 1, 0};
@@ -190,7 +198,14 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         a = 0.5 * wn;
         if (!(a > 1e-300 * s * s)) { fl |= FLAG_DEGENERATE; wn = 1.0; a = 0.0; }
         for (int d = 0; d < 3; ++d) n[d] = w[d] / wn;
-        for (int d = 0; d < 3; ++d) c[d] = (xi[d] + xj[d] + xk[d]) / 3.0;
+        if (Q == 1) {
+            for (int d = 0; d < 3; ++d) c[d] = (xi[d] + xj[d] + xk[d]) / 3.0;
+        } else {
+            double b[3], wq;
+            quad_point(Q, pt, b, wq);
+            for (int d = 0; d < 3; ++d) c[d] = b[0] * xi[d] + b[1] * xj[d] + b[2] * xk[d];
+            a *= wq;  // the record's weight in place of the face's area
+        }
         if (!isfinite(c[0] + c[1] + c[2] + n[0] + n[1] + n[2])) {
             fl |= FLAG_NONFINITE;
             c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
@@ -218,7 +233,7 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         r.a = (float)a;
         r.nx = (float)n[0]; r.ny = (float)n[1]; r.nz = (float)n[2];
         r.pad = 0.f;
-        colv[i] = ok ? make_int4(v[0], v[1], v[2], 0) : make_int4(-3, -3, -3, 0);
+        colv[i] = ok ? make_int4(v[0], v[1], v[2], pt) : make_int4(-3, -3, -3, 0);
         c64[3 * i + 0] = c[0]; c64[3 * i + 1] = c[1]; c64[3 * i + 2] = c[2];
         geo[5 * i + 0] = a; geo[5 * i + 1] = wn;
         geo[5 * i + 2] = n[0]; geo[5 * i + 3] = n[1]; geo[5 * i + 4] = n[2];
@@ -306,18 +321,19 @@ hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF,
     return hipGetLastError();
 }
 
-hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* bbox,
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, const uint32_t* bbox,
                          int bits, uint32_t* keys, uint32_t* vals, hipStream_t st) {
-    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF, 256)), dim3(256), 0, st, X, V, F, nF, bbox, bits, keys, vals);
+    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF * Q, 256)), dim3(256), 0, st, X, V, F, nF, Q, bbox, bits, keys,
+                       vals);
     return hipGetLastError();
 }
 
 // cnt (V entries) must be zero on entry; face_records accumulates the per-vertex corner counts.
-hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int64_t Fp,
+hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, int64_t Fp,
                           const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
                           double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st) {
-    hipLaunchKernelGGL(face_records, dim3(nblk(Fp, 256)), dim3(256), 0, st, X, V, F, nF, Fp, perm, bbox, org, cols,
-                       colv, c64, geo, cnt, flags);
+    hipLaunchKernelGGL(face_records, dim3(nblk(Fp, 256)), dim3(256), 0, st, X, V, F, nF, Q, Fp, perm, bbox, org,
+                       cols, colv, c64, geo, cnt, flags);
     return hipGetLastError();
 }
 
