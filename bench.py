@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--ff-config", default="C4")
     ap.add_argument("--ff-reps", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--no-conf", action="store_true", help="skip the confinement-energy timing")
+    ap.add_argument("--no-conf", action="store_true", help="skip the confinement and 6-point-quadrature timings")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
 
@@ -189,6 +189,31 @@ def conf_leg(args, T, M, torch, dev):
             "flop_per_pair": FLOP_PER_CONF_PAIR}
 
 
+def quad_leg(args, T, M, torch, dev, cfg, X, F):
+    """The exact gradient with the 6-point (degree-4) rule on both integrals: 36 point pairs per
+    face pair of the same workload."""
+    ctx = T.context(dev)
+    G = torch.empty_like(X)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    ctx.set_option(T.OPT_QUADRATURE, 6)
+    try:
+        for _ in range(2):
+            T.gradient(X, F, out=G, energy_out=E)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T.gradient(X, F, out=G, energy_out=E)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        ctx.set_option(T.OPT_QUADRATURE, 1)
+    ctx.sync_check()
+    pp = 36 * T.pair_count(F, cfg.V)
+    return {"workload": f"{args.config} with 6 quadrature points per face", "point_pairs": pp,
+            "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +279,7 @@ def main():
 
     ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
     conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)
+    quad = None if args.no_conf else quad_leg(args, T, M, torch, dev, cfg, X, F)
 
     cpu = None
     if not args.no_cpu:
@@ -280,6 +306,7 @@ def main():
         "roofline": roofline,
         "farfield": ff,
         "confinement": conf,
+        "quadrature6": quad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
