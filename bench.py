@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--ff-config", default="C4")
     ap.add_argument("--ff-reps", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--no-conf", action="store_true", help="skip the confinement and 6-point-quadrature timings")
+    ap.add_argument("--no-conf", action="store_true", help="skip the confinement, 6-point-quadrature and other-exponent timings")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
 
@@ -214,6 +214,36 @@ def quad_leg(args, T, M, torch, dev, cfg, X, F):
             "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
 
 
+def exponents_leg(args, T, torch, dev, cfg, X, F, P):
+    """The exact gradient with other exponents (the generic pair kernel, -m extra multiplications
+    by |d|^2 per pair) on the same workload."""
+    ctx = T.context(dev)
+    G = torch.empty_like(X)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    out = {}
+    for q, p in ((4, 8), (8, 14)):
+        for _ in range(2):
+            T.gradient(X, F, q=float(q), p=float(p), out=G, energy_out=E)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T.gradient(X, F, q=float(q), p=float(p), out=G, energy_out=E)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+        ctx.kernel_time()
+        for _ in range(reps):
+            T.gradient(X, F, q=float(q), p=float(p), out=G, energy_out=E)
+        k_ms, k_n = ctx.kernel_time()
+        ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+        ctx.sync_check()
+        out[f"q{q}_p{p}"] = {"ms_per_call": round(dt * 1e3, 4), "pairs_per_s": P / dt,
+                             "kernel": f"pair_kernel<{q},true,false,true>",
+                             "kernel_avg_ms": round(k_ms / max(k_n, 1), 4)}
+    return {"workload": f"{args.config} ({cfg.nF} faces), exact energy+gradient", "pairs": P, **out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -280,6 +310,7 @@ def main():
     ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
     conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)
     quad = None if args.no_conf else quad_leg(args, T, M, torch, dev, cfg, X, F)
+    expo = None if args.no_conf else exponents_leg(args, T, torch, dev, cfg, X, F, P)
 
     cpu = None
     if not args.no_cpu:
@@ -307,6 +338,7 @@ def main():
         "farfield": ff,
         "confinement": conf,
         "quadrature6": quad,
+        "other_exponents": expo,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -30,8 +30,11 @@
  *     bounds; with the sync-checks option on (default) the call waits for the stream and
  *     returns the corresponding status, with it off the status is collected by tpe_check().
  *   - A context is not thread-safe; use one per host thread or serialise calls.
- *   - Supported exponents: (q, p) = (6, 12) (the paper's alpha = 6).  Others return
- *     TPE_ERR_UNSUPPORTED.
+ *   - Supported exponents: (q, p) = (6, 12) (the paper's alpha = 6) everywhere.  tpe_energy and
+ *     tpe_gradient (with any quadrature rule) also take even q in {2, 4, 6, 8} with even p,
+ *     q < p <= 2q (the tangent-point family of Sec. 2.2.2 whose kernel stays in FP32 range on
+ *     meshes of unit size); the far field, the learned correction and the confinement energy do
+ *     not.  Others return TPE_ERR_UNSUPPORTED.
  *   - Sizes: nF <= 2^24, V <= 2^26.
  */
 #ifndef TPE_H

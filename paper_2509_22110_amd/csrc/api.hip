@@ -38,8 +38,10 @@ hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t*
 int pair_blocks_per_cu(bool grad);
 Sched make_sched(int64_t rows_p, int64_t cols_p, int waves);
 int64_t pair_part_floats(const Sched& sc, bool grad);
-hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
-                       const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st);
+hipError_t launch_pair(bool grad, int q, int p, const ColRec* cols, const int4* colv, const double* c64,
+                       const double* org, const uint32_t* touch, int touch_words, const Sched& sc, float* part,
+                       hipStream_t st);
+bool pair_exponents_ok(int q, int p);
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
                            double p, double scale, double efac, int Q, double* corner, double* epart,
@@ -321,7 +323,10 @@ int ensure_arena(tpe_ctx* ctx, size_t bytes) {
     return TPE_OK;
 }
 
-int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p) {
+// generic: the exact energy / gradient also take the other exponents of pair_exponents_ok;
+// everything else (far field, learned correction, confinement) is (6, 12) only.
+int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                 bool generic = false) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!X || !F) return fail(ctx, TPE_ERR_INVALID_ARG, "null X or F");
     if (V < 1 || nF < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "V and nF must be >= 1");
@@ -329,7 +334,12 @@ int check_common(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
         return fail(ctx, TPE_ERR_INVALID_ARG, "mesh too large (nF <= 2^24, V <= 2^26)");
     if (!(q >= 2.0) || !(p > q) || !std::isfinite(q) || !std::isfinite(p))
         return fail(ctx, TPE_ERR_INVALID_ARG, "exponents must satisfy 2 <= q < p");
-    if (q != 6.0 || p != 12.0) return fail(ctx, TPE_ERR_UNSUPPORTED, "only (q, p) = (6, 12) is implemented");
+    const bool fast = q == 6.0 && p == 12.0;
+    const bool other = generic && q == (int)q && p == (int)p && pair_exponents_ok((int)q, (int)p);
+    if (!fast && !other)
+        return fail(ctx, TPE_ERR_UNSUPPORTED,
+                    generic ? "exponents: (6, 12), or even q in {2, 4, 6, 8} with even p, q < p <= 2q"
+                            : "only (q, p) = (6, 12) is implemented here");
     return TPE_OK;
 }
 
@@ -373,7 +383,7 @@ int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
 
 int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
               double scale, double* E, double* G) {
-    int rc = check_common(ctx, X, V, F, nF, q, p);
+    int rc = check_common(ctx, X, V, F, nF, q, p, true);
     if (rc) return rc;
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     const bool grad = G != nullptr;
@@ -390,7 +400,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_pair(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
+    HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, P.nR, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.Q,

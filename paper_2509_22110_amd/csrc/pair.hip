@@ -130,10 +130,57 @@ __device__ __forceinline__ void pair_update(const ColRec& cr, int4 cv, float rx,
     }
 }
 
+// Other exponents (the generic path): even q = Q and even p with q < p <= 2q.  With t = u w and
+// m = p/2 - q <= 0 the kernel is k = t^q w^m and s = a t^(q-1) w^(m+1): the fast path's sums with
+// w^m = (|d|^2)^(-m) folded in (mneg = -m multiplications per pair).
+template <int Q, bool GRAD, bool MASK>
+__device__ __forceinline__ void pair_update_gen(const ColRec& cr, int4 cv, float rx, float ry, float rz, float nx,
+                                                float ny, float nz, int v0, int v1, int v2, int mneg, float* acc) {
+    float dx = rx - cr.cx, dy = ry - cr.cy, dz = rz - cr.cz;
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float w = __builtin_amdgcn_rcpf(r2);
+    if constexpr (MASK) {
+        bool ex = (v0 == cv.x) | (v0 == cv.y) | (v0 == cv.z) | (v1 == cv.x) | (v1 == cv.y) |
+                  (v1 == cv.z) | (v2 == cv.x) | (v2 == cv.y) | (v2 == cv.z);
+        w = ex ? 0.f : w;
+    }
+    float wm = 1.f;
+    for (int j = 0; j < mneg; ++j) wm *= r2;
+    if constexpr (MASK) wm = w == 0.f ? 0.f : wm;
+    float u = fmaf(nz, dz, fmaf(ny, dy, nx * dx));
+    float t = u * w;
+    float tq1, tq;
+    powq<Q>(t, tq1, tq);
+    if constexpr (!GRAD) {
+        acc[0] = fmaf(cr.a, tq * wm, acc[0]);
+    } else {
+        float v = fmaf(cr.nz, dz, fmaf(cr.ny, dy, cr.nx * dx));
+        float tau = v * w;
+        float sq1, sq;
+        powq<Q>(tau, sq1, sq);
+        float aw = cr.a * w * wm;
+        float s = aw * tq1;
+        float sp = aw * sq1;
+        float e = tq + sq;
+        float m = aw * e;
+        acc[0] = fmaf(cr.a * wm, e, acc[0]);
+        acc[1] += s;
+        acc[2] = fmaf(s, dx, acc[2]);
+        acc[3] = fmaf(s, dy, acc[3]);
+        acc[4] = fmaf(s, dz, acc[4]);
+        acc[5] = fmaf(m, dx, acc[5]);
+        acc[6] = fmaf(m, dy, acc[6]);
+        acc[7] = fmaf(m, dz, acc[7]);
+        acc[8] = fmaf(sp, cr.nx, acc[8]);
+        acc[9] = fmaf(sp, cr.ny, acc[9]);
+        acc[10] = fmaf(sp, cr.nz, acc[10]);
+    }
+}
+
 // One chunk of CHUNK columns for the wave's RPL x 64 rows: plain FP32 sums over the chunk, then a
 // Kahan fold into the rows' (hi, lo) accumulators.
-template <int Q, bool GRAD, bool MASK, bool CONF = false>
-__device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const int4* __restrict__ tv,
+template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false>
+__device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ tc, const int4* __restrict__ tv,
                                            const float (&rx)[RPL], const float (&ry)[RPL],
                                            const float (&rz)[RPL], const float (&nx)[RPL],
                                            const float (&ny)[RPL], const float (&nz)[RPL],
@@ -152,8 +199,12 @@ __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const 
         if constexpr (MASK) cv = tv[j];
 #pragma unroll
         for (int r = 0; r < RPL; ++r)
-            pair_update<Q, GRAD, MASK, CONF>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0], rv[r][1],
-                                             rv[r][2], acc[r]);
+            if constexpr (GEN)
+                pair_update_gen<Q, GRAD, MASK>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0], rv[r][1],
+                                               rv[r][2], mneg, acc[r]);
+            else
+                pair_update<Q, GRAD, MASK, CONF>(cr, cv, rx[r], ry[r], rz[r], nx[r], ny[r], nz[r], rv[r][0],
+                                                 rv[r][1], rv[r][2], acc[r]);
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
@@ -166,7 +217,7 @@ __device__ __forceinline__ void chunk_pass(const ColRec* __restrict__ tc, const 
 // waves' compensated sums folded into wave 0's).
 // Rows come from (rcols, rc64, rcolv), columns from (ccols, ccolv, corg): the same arrays for the
 // self energy, the confining surface's for CONF (no exclusion map then).
-template <int Q, bool GRAD, bool CONF = false>
+template <int Q, bool GRAD, bool CONF = false, bool GEN = false>
 __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __restrict__ rcols,
                                                               const double* __restrict__ rc64,
                                                               const int4* __restrict__ rcolv,
@@ -174,7 +225,7 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
                                                               const int4* __restrict__ ccolv,
                                                               const double* __restrict__ corg,
                                                               const uint32_t* __restrict__ touch, int touch_words,
-                                                              Sched sc, float* __restrict__ part) {
+                                                              Sched sc, float* __restrict__ part, int mneg) {
     constexpr int NA = GRAD ? NACC : 1;
     constexpr int CPT = CTILE / CHUNK;  // chunks per tile
     // waves 1.. hand their (hi, -c) to wave 0: [PAIR_NW - 1][2 NA][ROWB] floats of dynamic LDS (static
@@ -228,13 +279,13 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
             const ColRec* tc = ccols + (size_t)cu * CHUNK;
             const int4* tv = ccolv + (size_t)cu * CHUNK;
             if constexpr (CONF) {
-                chunk_pass<Q, GRAD, false, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                chunk_pass<Q, GRAD, false, true>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
             } else {
                 const bool masked = (my_touch[cu >> 5] >> (cu & 31)) & 1u;
                 if (masked)
-                    chunk_pass<Q, GRAD, true>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                    chunk_pass<Q, GRAD, true, false, GEN>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
                 else
-                    chunk_pass<Q, GRAD, false>(tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                    chunk_pass<Q, GRAD, false, false, GEN>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
             }
         }
         if (wave > 0) {
@@ -301,14 +352,33 @@ int64_t pair_part_floats(const Sched& sc, bool grad) {
     return (int64_t)sc.W * sc.maxseg * 2 * (grad ? NACC : 1) * ROWB;
 }
 
-hipError_t launch_pair(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
-                       const uint32_t* touch, int touch_words, const Sched& sc, float* part, hipStream_t st) {
+template <int Q, bool GEN>
+static void launch_pair_q(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                          const uint32_t* touch, int touch_words, const Sched& sc, float* part, int mneg,
+                          hipStream_t st) {
     if (grad)
-        hipLaunchKernelGGL((pair_kernel<6, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true), st, cols,
-                           c64, colv, cols, colv, org, touch, touch_words, sc, part);
+        hipLaunchKernelGGL((pair_kernel<Q, true, false, GEN>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true),
+                           st, cols, c64, colv, cols, colv, org, touch, touch_words, sc, part, mneg);
     else
-        hipLaunchKernelGGL((pair_kernel<6, false>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(false), st, cols,
-                           c64, colv, cols, colv, org, touch, touch_words, sc, part);
+        hipLaunchKernelGGL((pair_kernel<Q, false, false, GEN>), dim3(sc.W), dim3(WAVE * PAIR_NW),
+                           pair_lds_bytes(false), st, cols, c64, colv, cols, colv, org, touch, touch_words, sc, part,
+                           mneg);
+}
+
+// (q, p) = (6, 12) runs the fast kernel; other supported exponents (see pair_exponents_ok) the
+// generic one.
+bool pair_exponents_ok(int q, int p) { return (q == 2 || q == 4 || q == 6 || q == 8) && p % 2 == 0 && p > q && p <= 2 * q; }
+
+hipError_t launch_pair(bool grad, int q, int p, const ColRec* cols, const int4* colv, const double* c64,
+                       const double* org, const uint32_t* touch, int touch_words, const Sched& sc, float* part,
+                       hipStream_t st) {
+    const int mneg = q - p / 2;
+    if (q == 6 && p == 12) launch_pair_q<6, false>(grad, cols, colv, c64, org, touch, touch_words, sc, part, 0, st);
+    else if (q == 2) launch_pair_q<2, true>(grad, cols, colv, c64, org, touch, touch_words, sc, part, mneg, st);
+    else if (q == 4) launch_pair_q<4, true>(grad, cols, colv, c64, org, touch, touch_words, sc, part, mneg, st);
+    else if (q == 6) launch_pair_q<6, true>(grad, cols, colv, c64, org, touch, touch_words, sc, part, mneg, st);
+    else if (q == 8) launch_pair_q<8, true>(grad, cols, colv, c64, org, touch, touch_words, sc, part, mneg, st);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -319,10 +389,10 @@ hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, 
                             hipStream_t st) {
     if (grad)
         hipLaunchKernelGGL((pair_kernel<6, true, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(true), st,
-                           rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part);
+                           rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part, 0);
     else
         hipLaunchKernelGGL((pair_kernel<6, false, true>), dim3(sc.W), dim3(WAVE * PAIR_NW), pair_lds_bytes(false),
-                           st, rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part);
+                           st, rcols, rc64, rcolv, ccols, ccolv, corg, nullptr, 0, sc, part, 0);
     return hipGetLastError();
 }
 

@@ -1,0 +1,88 @@
+"""Exact path with exponents other than (q, p) = (6, 12) (paper Sec. 2.2.2: the tangent-point
+kernel for a pair of exponents q < p) against the oracle, which takes any (q, p).
+
+The HIP path takes even q in {2, 4, 6, 8} with even p, q < p <= 2q; other pairs, and the far
+field / learned correction / confinement entry points with anything but (6, 12), raise
+TPE_ERR_UNSUPPORTED.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+E_TOL, G_TOL = 1e-6, 1e-5
+
+EXPONENTS = [(2, 4), (4, 6), (4, 8), (6, 8), (6, 10), (8, 10), (8, 14), (8, 16)]
+
+
+def meshes():
+    X, F = M.icosphere(1)
+    yield "L1-jitter", M.radial_jitter(X, 0.02, 1), F
+    X, F = M.icosphere(3)
+    Xb, _, _ = M.bump(X, 0, 0.3, 0.1)
+    yield "L3-bump", Xb, F
+    c = M.make_config("C1")
+    yield "C1", c.X, c.F
+
+
+@pytest.mark.parametrize("q,p", EXPONENTS, ids=lambda v: str(v))
+@pytest.mark.parametrize("name,X,F", list(meshes()), ids=lambda v: v if isinstance(v, str) else "")
+def test_parity(q, p, name, X, F):
+    T = tpe()
+    Xd, Fd = upload(X, F)
+    E, G = T.gradient(Xd, Fd, q=float(q), p=float(p))
+    Ee = T.energy(Xd, Fd, q=float(q), p=float(p))
+    Eo, Go = oracle.gradient(X, F, float(q), float(p))
+    eE, eEe = rel_energy(float(E.cpu()), Eo), rel_energy(float(Ee.cpu()), Eo)
+    eG = rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log(name, "q", q, "p", p, "rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
+    assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
+
+
+def test_two_triangles_closed_form():
+    """Two parallel unit right triangles at offset (1, 0, 1): d = (-1, 0, -1) between centroids, so
+    n.d = -1 for both and each ordered pair contributes a^2 / |d|^p = 1 / (4 * 2^(p/2))."""
+    T = tpe()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 0, 1], [2, 0, 1], [1, 1, 1]], dtype=np.float64)
+    F = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    Xd, Fd = upload(X, F)
+    for q, p in EXPONENTS:
+        E = float(T.energy(Xd, Fd, q=float(q), p=float(p)).cpu())
+        assert E == pytest.approx(2.0 / (4.0 * 2.0 ** (p / 2)), rel=1e-6), (q, p)
+
+
+def test_quadrature_with_other_exponents():
+    T = tpe()
+    X, F = M.icosphere(2)
+    X = M.radial_jitter(X, 0.02, 2)
+    Xd, Fd = upload(X, F)
+    ctx = T.context(Xd.device)
+    ctx.set_option(T.OPT_QUADRATURE, 3)
+    try:
+        E, G = T.gradient(Xd, Fd, q=4.0, p=8.0)
+    finally:
+        ctx.set_option(T.OPT_QUADRATURE, 1)
+    Eo, Go = oracle.gradient_quad(X, F, 3, 4.0, 8.0)
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("L2 Q 3 (4, 8) rel E", eE, "rel G", eG)
+    assert eE <= E_TOL and eG <= G_TOL
+
+
+def test_unsupported_exponents():
+    T = tpe()
+    X, F = M.icosphere(1)
+    Xd, Fd = upload(X, F)
+    for q, p in [(5.0, 10.0), (4.0, 10.0), (6.0, 11.0), (10.0, 20.0), (6.5, 12.0)]:
+        with pytest.raises(T.TPEError) as e:
+            T.energy(Xd, Fd, q=q, p=p)
+        assert e.value.code == -6, (q, p)
+    tree = T.build_tree(Xd, Fd)
+    with pytest.raises(T.TPEError) as e:
+        T.farfield(tree, Xd, Fd, q=4.0, p=8.0)
+    assert e.value.code == -6
+    with pytest.raises(T.TPEError) as e:
+        T.conf_energy(Xd, Fd, Xd * 1.5, Fd, q=4.0, p=8.0)
+    assert e.value.code == -6

@@ -116,6 +116,21 @@ def test_sphere_limit_convergence():
     assert oracle.energy(2 * X, F) == pytest.approx(oracle.energy(X, F) / 4, rel=1e-13)
 
 
+@pytest.mark.parametrize("q", [2.0, 4.0, 8.0])
+def test_sphere_limit_other_exponents(q):
+    """With p = 2q the kernel on a sphere of radius R is the constant (2R)^-q (the tangent-point
+    radius is R everywhere), so the continuum energy of the unit sphere is (4 pi)^2 / 2^q.  The
+    centroid quadrature must converge to it at second order."""
+    ref = (4 * np.pi) ** 2 / 2 ** q
+    errs = []
+    for level in (1, 2, 3, 4):
+        X, F = M.icosphere(level)
+        errs.append(abs(oracle.energy(X, F, q, 2 * q) - ref) / ref)
+    for a, b in zip(errs, errs[1:]):
+        assert b < a and a / b > 3.0
+    assert errs[-1] < 5e-3
+
+
 @pytest.mark.parametrize("qp", [(6.0, 12.0), (4.0, 10.0), (8.0, 14.0)])
 def test_scaling_law_and_euler(qp):
     q, p = qp
@@ -209,6 +224,20 @@ def test_gradient_finite_differences(name, X, F):
     Gfd = _fd_gradient(X, F, h)
     err = np.abs(G - Gfd).max() / np.abs(G).max()
     assert err < 1e-8, (name, err)
+
+
+@pytest.mark.parametrize("qp", [(2.0, 4.0), (4.0, 8.0), (8.0, 10.0)])
+def test_gradient_finite_differences_other_exponents(qp):
+    """The exact path also runs other exponents; their oracle gradient is pinned the same way."""
+    q, p = qp
+    X, F = M.icosphere(1)
+    X = M.radial_jitter(X, 0.03, 4)
+    E, G = oracle.gradient(X, F, q, p)
+    assert E > 0
+    h = 1e-4 * np.abs(X).max()
+    Gfd = _fd_gradient(X, F, h, q=q, p=p)
+    err = np.abs(G - Gfd).max() / np.abs(G).max()
+    assert err < 1e-8, (qp, err)
 
 
 def test_gradient_at_matches_full():
