@@ -5,11 +5,14 @@ kernel, FP64 finalize, vertex gather) on the level-5 deformed sphere (20,480 fac
 spherical-harmonic deformation, a_lm ~ N(0, 0.05^2), seed 0), with the mesh already resident in
 HBM.  Prints ONE JSON line:
     value     = ordered non-adjacent face pairs evaluated per second (energy + gradient)
-    roofline  = the pair kernel's algorithmic FP32 rate (55 flop per pair) over its own launch
-                durations, measured with HIP events on the stream it runs on, vs the FP32
-                vector peak; traffic = HBM bytes per launch from the committed rocprofv3 counter
-                summary (profiles/pair_kernel_C2_traffic.txt), null when the kernel's sources
-                have changed since it was taken
+    roofline  = the pair kernel's algorithmic FP32 rate (55 flop per ordered pair, the row
+                formulation) over its own launch durations, measured with HIP events on the
+                stream it runs on, vs the FP32 vector peak; the symmetric kernel that runs by
+                default evaluates each unordered pair once and executes 40.5 flop per ordered pair
+                (executed_tflops); traffic = HBM bytes per launch from the committed rocprofv3
+                counter summary (profiles/pair_kernel_C2_traffic.txt), null when the kernel's
+                sources have changed since it was taken; row_only = the same step with the row-only
+                pair kernel (TPE_OPT_SYMMETRIC = 0), for comparison
     confinement = the confinement energy + gradient of a flattened sphere in a radius-1.1 sphere
                 (20,480 x 20,480 faces): pairs/s and the kernel's algorithmic FP32 rate
     farfield  = ms per gradient on the level-7 workload (327,680 faces): exact all-pairs vs the
@@ -34,6 +37,11 @@ sys.path.insert(0, ROOT)
 # d 3, |d|^2 5, 1/|d|^2 1, n_S.d 5, n_T.d 5, t and tau 2, powers 8, a w / s / s' 3,
 # t^6+tau^6 and m 2, K 2, S0 1, Sd 6, Sdd 6, Sn 6
 FLOP_PER_PAIR = 55
+# FP32 work the symmetric kernel executes per unordered pair (FMA = 2, rcp = 1), credited to both
+# faces: shared d 3, |d|^2 5, rcp 1, n_S.d 5, n_T.d 5, t and tau 2, powers 6, T1 and U1 2,
+# t^6+tau^6 3, w e 1 (33); the row face's 11 sums 24; the column face's 11 sums 24 (contributions of
+# two rows per lane combined, then added to the rotating column sums); 81 = 40.5 per ordered pair
+EXEC_FLOP_PER_PAIR_SYM = 40.5
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per face of the finalize + gather passes: finalize reads one segment of
@@ -41,6 +49,19 @@ HBM_PEAK_GBS = 8000.0
 # (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices (12 B) and
 # the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
 FINALIZE_GATHER_BYTES_PER_FACE = 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
+SYM_MAX_COLPART_BYTES = 6 << 30
+
+
+def sym_colpart_bytes(nF, na=11):
+    """Bytes of the symmetric pair kernel's column partial sums, which the finalize reads once: one
+    FP32 sum per (symmetric unit, column, accumulator); super blocks of 512 faces, units of 64
+    columns, the 8 chunks of a super block's own faces excluded.  0 when the library takes the
+    row-only kernel (above its 6 GiB cap)."""
+    fp = -(-nF // 512) * 512
+    nsb, nch = fp // 512, fp // 64
+    units = nsb * (nch - 8) - 8 * nsb * (nsb - 1) // 2
+    b = units * na * 64 * 4
+    return b if b <= SYM_MAX_COLPART_BYTES else 0
 
 
 def parse():
@@ -121,9 +142,10 @@ def farfield_leg(args, T, M, torch, dev):
     fg_ms, fg_n = ctx.kernel_time()
     ctx.set_option(T.OPT_KERNEL_TIMING, 0)
     fg_ms /= max(fg_n, 1)
-    fg_bytes = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF
+    cp_bytes = sym_colpart_bytes(cfg.nF)
+    fg_bytes = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF + cp_bytes
     fg = {"kernels": "finalize_kernel<true> + vertex_gather", "bound": "hbm", "ms": round(fg_ms, 4),
-          "algorithmic_bytes": fg_bytes, "achieved": round(fg_bytes / (fg_ms * 1e-3) / 1e9, 1),
+          "algorithmic_bytes": fg_bytes, "column_partial_bytes": cp_bytes, "achieved": round(fg_bytes / (fg_ms * 1e-3) / 1e9, 1),
           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fg_bytes / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
     g0 = float(G0.abs().max())
@@ -302,10 +324,33 @@ def main():
     k_avg_ms = k_ms / max(k_n, 1)
     achieved = FLOP_PER_PAIR * P / (k_avg_ms * 1e-3) / 1e12
     traffic = read_traffic()
+    # the row-only kernel on the same step, for comparison
+    ctx.set_option(T.OPT_SYMMETRIC, 0)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+    for _ in range(2):
+        T.gradient(X, F, out=G, energy_out=E)
+    ctx.kernel_time()
+    reps = max(5, min(args.steps, 20))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        T.gradient(X, F, out=G, energy_out=E)
+    torch.cuda.synchronize()
+    ro_ms = (time.perf_counter() - t0) / reps * 1e3
+    r_ms, r_n = ctx.kernel_time()
+    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+    ctx.set_option(T.OPT_SYMMETRIC, 1)
+    ctx.sync_check()
+    r_avg_ms = r_ms / max(r_n, 1)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": "pair_kernel<6,true>",
-                "kernel_avg_ms": round(k_avg_ms, 4), "flop_per_pair": FLOP_PER_PAIR}
+                "traffic": traffic, "kernel": "pair_sym_kernel<true>",
+                "kernel_avg_ms": round(k_avg_ms, 4), "flop_per_pair": FLOP_PER_PAIR,
+                "executed_flop_per_pair": EXEC_FLOP_PER_PAIR_SYM,
+                "executed_tflops": round(EXEC_FLOP_PER_PAIR_SYM * P / (k_avg_ms * 1e-3) / 1e12, 3),
+                "row_only": {"kernel": "pair_kernel<6,true>", "kernel_avg_ms": round(r_avg_ms, 4),
+                             "ms_per_step": round(ro_ms, 4),
+                             "tflops": round(FLOP_PER_PAIR * P / (r_avg_ms * 1e-3) / 1e12, 3)}}
 
     ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
     conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)

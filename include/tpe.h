@@ -71,13 +71,19 @@ typedef enum {
                                  kernel (the pair kernel, or the far-field walk) on the context's
                                  stream; 2: around the finalize + vertex-gather launches; read
                                  back with tpe_kernel_time(); 0 (default): off */
-    TPE_OPT_QUADRATURE = 4    /* quadrature points per face of tpe_energy / tpe_gradient: 1
+    TPE_OPT_QUADRATURE = 4,   /* quadrature points per face of tpe_energy / tpe_gradient: 1
                                  (default, the centroid), 3 (degree 2) or 6 (degree 4); the paper
                                  integrates both integrals with higher-order rules (Sec. 3.2).  Each
                                  point pair of two faces sharing no vertex contributes
                                  W_p W_r a_S a_T |n_S.(x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p.  The far
                                  field and the confinement energy take 1 only (else
                                  TPE_ERR_UNSUPPORTED); at most 2^26 points in all. */
+    TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
+                                 every unordered pair of faces once and credit both faces (the
+                                 symmetric pair kernel), while its column partial sums fit in 6 GiB
+                                 of the context's scratch (about 380,000 faces with the gradient);
+                                 0, or beyond that size: every ordered pair from its row face (the
+                                 row-only kernel).  Results agree to rounding */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */

@@ -30,6 +30,7 @@ OPT_SYNC_CHECKS = 1
 OPT_TARGET_WAVES = 2
 OPT_KERNEL_TIMING = 3
 OPT_QUADRATURE = 4
+OPT_SYMMETRIC = 5
 
 
 class TPEError(RuntimeError):

@@ -46,6 +46,17 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
                            double p, double scale, double efac, int Q, double* corner, double* epart,
                            uint32_t* ticket, uint32_t* flags, double* E, hipStream_t st);
+hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
+                            const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st);
+int pair_sym_blocks_per_cu(bool grad);
+SymSched make_sym_sched(int64_t Fp, int W);
+int64_t sym_part_floats(const SymSched& sc, bool grad);
+int64_t sym_colpart_floats(const SymSched& sc, bool grad);
+hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                           const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
+                           int* first, hipStream_t st);
+// the symmetric kernel is used while its column partials fit in this many bytes
+constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)6 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
@@ -123,7 +134,9 @@ struct tpe_ctx {
     bool sync_checks = true;
     int64_t target_waves = 0;     // 0: resident-wave capacity of the pair kernel
     int quad = 1;                 // quadrature points per face of the exact path (1, 3 or 6)
-    int resident[2] = {0, 0};     // pair-kernel waves resident on the device (energy, gradient)
+    int resident[2] = {0, 0};     // pair-kernel work-groups resident on the device (energy, gradient)
+    int resident_sym[2] = {0, 0}; // the same for the symmetric pair kernel
+    bool symmetric = true;        // exact self energy (6, 12): symmetric pair kernel where it fits
     char* arena = nullptr;
     size_t arena_bytes = 0;
     uint32_t* dflags = nullptr;   // device error word
@@ -204,6 +217,11 @@ struct Plan {
     int64_t nR = 0;   // records = Q nF
     int ntiles, nrb, touch_words, sort_blocks, fin_blocks;
     Sched sc;
+    // symmetric pair kernel (exact self energy)
+    bool sym = false;
+    SymSched ssc{};
+    float* colpart = nullptr;
+    int* first = nullptr;
     // buffers
     uint32_t *keys, *vals, *ktmp, *vtmp, *hist, *hoff, *bbox;
     uint32_t *zero_begin, *cnt, *cursor, *touch, *zero_end;
@@ -258,7 +276,11 @@ void layout(Plan& P, char* base, bool grad) {
     P.colv = c.take<int4>(Fp);
     P.c64 = c.take<double>(3 * Fp);
     P.geo = c.take<double>(5 * Fp);
-    P.part = c.take<float>((size_t)pair_part_floats(P.sc, grad));
+    P.part = c.take<float>((size_t)(P.sym ? sym_part_floats(P.ssc, grad) : pair_part_floats(P.sc, grad)));
+    if (P.sym) {
+        P.colpart = c.take<float>((size_t)sym_colpart_floats(P.ssc, grad));
+        P.first = c.take<int>((size_t)P.ssc.W);
+    }
     P.corner = c.take<double>(grad ? 9 * nR : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
@@ -279,8 +301,9 @@ void layout(Plan& P, char* base, bool grad) {
     P.bytes = c.off + 256;
 }
 
+// sym: the exact self energy asks for the symmetric kernel (taken if its buffers fit)
 void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1, int64_t nFY = 0,
-          int64_t VY = 0, int Q = 1) {
+          int64_t VY = 0, int Q = 1, bool sym = false) {
     P.treeH = treeH;
     P.Q = Q;
     P.nR = nF * Q;
@@ -291,6 +314,25 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
     P.nF = nF;
     P.V = V;
     P.Fp = round_up(P.nR, std::max(ROWB, CTILE));
+    P.sym = false;
+    if (sym) {
+        const int64_t Fs = round_up(P.nR, SB);
+        // work-groups: the resident count, times up to 4 when there are enough units (the
+        // hardware then refills the slots of early finishers, which evens out the finish times)
+        int W = ctx->resident_sym[grad ? 1 : 0];
+        if (ctx->target_waves > 0) {
+            W = (int)ctx->target_waves;
+        } else {
+            const int64_t units = make_sym_sched(Fs, 1).U;
+            W *= (int)std::max<int64_t>(1, std::min<int64_t>(4, units / ((int64_t)W * 32)));
+        }
+        const SymSched t = make_sym_sched(Fs, W);
+        if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_MAX_COLPART_BYTES) {
+            P.sym = true;
+            P.ssc = t;
+            P.Fp = Fs;
+        }
+    }
     P.ntiles = (int)(P.Fp / CTILE);
     P.nrb = (int)(P.Fp / ROWB);
     P.touch_words = (int)((P.Fp / CHUNK + 31) / 32);
@@ -390,7 +432,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (nF * ctx->quad > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
     DeviceGuard dg(ctx->device);
     Plan P;
-    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad);
+    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
@@ -400,11 +442,18 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part, st));
+    if (P.sym) {
+        HIPCHK(launch_pair_sym(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.ssc, P.part, P.colpart,
+                               P.first, st));
+    } else {
+        HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part,
+                           st));
+    }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, P.nR, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, P.Q,
-                           P.corner, P.epart, P.ticket, ctx->dflags, E, st));
+    if (P.sym) HIPCHK(launch_sym_merge(grad, P.part, P.colpart, P.first, P.ssc, P.nR, P.Fp, P.acc64, st));
+    HIPCHK(launch_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, P.nR, P.sym ? P.acc64 : nullptr, P.geo,
+                           P.colv, X, P.bbox, q, p, scale, 0.5, P.Q, P.corner, P.epart, P.ticket, ctx->dflags, E, st));
     if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -490,6 +539,8 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
             ncu = 1;
         ctx->resident[0] = ncu * pair_blocks_per_cu(false);
         ctx->resident[1] = ncu * pair_blocks_per_cu(true);
+        ctx->resident_sym[0] = ncu * pair_sym_blocks_per_cu(false);
+        ctx->resident_sym[1] = ncu * pair_sym_blocks_per_cu(true);
     }
     if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -535,6 +586,10 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
             if (!quad_rule_ok((int)value) || value != (int)value)
                 return fail(ctx, TPE_ERR_INVALID_ARG, "quadrature: 1, 3 or 6 points per face");
             ctx->quad = (int)value;
+            return TPE_OK;
+        case TPE_OPT_SYMMETRIC:
+            if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric: 0 or 1");
+            ctx->symmetric = value != 0;
             return TPE_OK;
         case TPE_OPT_KERNEL_TIMING:
             if (value < 0 || value > 2) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0, 1 or 2");

@@ -65,6 +65,72 @@ struct Sched {
     __host__ __device__ int wave_of(int64_t x) const { return (int)(((x + 1) * (int64_t)W - 1) / U); }
 };
 
+// Symmetric schedule of the self energy's pair kernel.  A work-group of SYM_NW waves holds a super
+// block of SB = SYM_NW * ROWB rows (one row block per wave).  Super block I owns first its SBC
+// diagonal units, the CHUNK-column chunks J = SBC I, ..., SBC I + SBC - 1 of its own faces (pairs
+// inside the super block, evaluated from both sides as ordered pairs), then its symmetric units,
+// the SYM_COLS-column slices of all later chunks (every unordered pair once, credited to both
+// faces; the columns' share goes to one column partial per symmetric unit).  Units are numbered
+// super block by super block; work-group w takes the contiguous range [begin(w), begin(w+1)) of
+// equal cost, a diagonal unit costing DIAG_COST and a symmetric one SYM_COST.
+constexpr int SYM_NW = 4;
+constexpr int SB = SYM_NW * ROWB;
+constexpr int SBC = SB / CHUNK;           // chunks per super block
+constexpr int SYM_COLS = 64;              // columns of a symmetric unit (64: the wave; 16: a row of lanes)
+constexpr int SUB = CHUNK / SYM_COLS;     // symmetric units per chunk
+// relative costs, measured: a diagonal unit (the row-only pass over CHUNK columns, nearly always
+// with vertex comparisons, and the first unit of a super block with its row loads) takes about
+// 1.7 times a symmetric unit of 64 columns, which itself takes about 122 VALU instructions per
+// column and lane
+constexpr int SYM_COST = 12 * SYM_COLS / 64, DIAG_COST = 20;
+
+struct SymSched {
+    int64_t U, C;  // units, total cost
+    int W, nsb, nch;
+    // units of super block I: SBC + SUB (nch - SBC (I + 1)) = A - D I
+    __host__ __device__ int64_t ua() const { return SBC + (int64_t)SUB * (nch - SBC); }
+    static constexpr int64_t UD = (int64_t)SUB * SBC;
+    // first unit of super block I
+    __host__ __device__ int64_t base(int64_t I) const { return I * ua() - UD * I * (I - 1) / 2; }
+    // symmetric units of the super blocks before I
+    __host__ __device__ int64_t base_sym(int64_t I) const {
+        return (int64_t)SUB * (I * (nch - SBC) - (int64_t)SBC * I * (I - 1) / 2);
+    }
+    // super block of unit u (0 <= u < U): the root of base(I) = u, then corrected to be exact
+    __host__ __device__ int block_of(int64_t u) const {
+        const double h = 0.5 * UD, b = (double)ua() + h;
+        const double disc = b * b - 4.0 * h * (double)u;
+        int I = (int)((b - sqrt(disc > 0.0 ? disc : 0.0)) / (2.0 * h));
+        I = I < 0 ? 0 : (I > nsb - 1 ? nsb - 1 : I);
+        while (I > 0 && base(I) > u) --I;
+        while (I < nsb - 1 && base(I + 1) <= u) ++I;
+        return I;
+    }
+    // cost of the units [0, u)
+    __host__ __device__ int64_t cost(int64_t u) const {
+        if (u >= U) return C;
+        const int I = block_of(u);
+        const int64_t k = u - base(I);
+        const int64_t ndiag = (int64_t)SBC * I + (k < SBC ? k : SBC);
+        return SYM_COST * u + (int64_t)(DIAG_COST - SYM_COST) * ndiag;
+    }
+    // first unit of work-group w: the smallest u with cost(u) W >= w C
+    __host__ __device__ int64_t begin(int w) const {
+        if (w <= 0) return 0;
+        if (w >= W) return U;
+        const int64_t target = (int64_t)w * C;
+        int64_t lo = 0, hi = U;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (cost(mid) * W >= target) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    }
+    // the work-group whose range contains unit x
+    __host__ __device__ int wave_of(int64_t x) const { return (int)(cost(x) * W / C); }
+};
+
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 

@@ -161,6 +161,51 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 
+// Row sums of the symmetric pair kernel, one thread per (face i, sum k): acc64[k][i] <- the
+// segments of the work-groups that cover i's super block (work-group order), then the column
+// partials of the symmetric units (I', i's columns) of the earlier super blocks I' (ascending), all
+// added in FP64.  Each wave's 64 faces lie in one row block, so the covering work-groups are
+// wave-uniform.
+template <int NA>
+__global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict__ part,
+                                                        const float* __restrict__ colpart,
+                                                        const int* __restrict__ first, SymSched sc, int64_t nR,
+                                                        int64_t Fp, double* __restrict__ acc64) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= nR) return;
+    const int rr = (int)(i % ROWB);
+    const int rb = __builtin_amdgcn_readfirstlane((int)(i / ROWB));
+    const int I = rb / SYM_NW, wv = rb % SYM_NW;
+    const int w0 = __builtin_amdgcn_readfirstlane(sc.wave_of(sc.base(I)));
+    const int w1 = __builtin_amdgcn_readfirstlane(sc.wave_of(sc.base(I + 1) - 1));
+    // The loops are unrolled so that the loads of several terms are in flight together; the adds
+    // stay in order.  Slot w + I of an empty work-group is in bounds but unrelated: its value is
+    // dropped.
+    double acc = 0.0;
+#pragma unroll 8
+    for (int w = w0; w <= w1; ++w) {
+        const int f = first[w];
+        const float v = part[(((size_t)(w + I) * SYM_NW + wv) * NA + k) * ROWB + rr];
+        acc += f <= I ? (double)v : 0.0;
+    }
+    const int J = (int)(i / SYM_COLS), jj = (int)(i % SYM_COLS);
+#pragma unroll 8
+    for (int Ip = 0; Ip < I; ++Ip)
+        acc += (double)colpart[((size_t)(sc.base_sym(Ip) + J - SUB * SBC * (Ip + 1)) * NA + k) * SYM_COLS + jj];
+    acc64[(size_t)k * Fp + i] = acc;
+}
+
+hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
+                            const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st) {
+    const dim3 grid((unsigned)((nR + 255) / 256), grad ? NACC : 1);
+    if (grad)
+        hipLaunchKernelGGL((sym_merge_kernel<NACC>), grid, dim3(256), 0, st, part, colpart, first, sc, nR, Fp, acc64);
+    else
+        hipLaunchKernelGGL((sym_merge_kernel<1>), grid, dim3(256), 0, st, part, colpart, first, sc, nR, Fp, acc64);
+    return hipGetLastError();
+}
+
 // Row sums: the pair kernel's segments (part, sc) or, with part null, acc64 (NA x Fp FP64);
 // ticket: one word, zero on entry.  efac: E = efac sum_S a_S K_S with the gradient's row sums
 // (1/2 for the self energy, whose K holds both orders of every pair; 1 for the confinement).

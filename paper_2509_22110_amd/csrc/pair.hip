@@ -325,6 +325,397 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Symmetric kernel (self energy, (q, p) = (6, 12)): every unordered pair {S, T} of faces in
+// different super blocks is evaluated once, by the wave that holds S as a row, and credited to both
+// faces.  The reversed ordered pair (T, S) has d -> -d and t <-> -tau, so with
+//     T1 = w t^(q-1),  U1 = w tau^(q-1),  e = t^q + tau^q   (q - 1 odd)
+// the row face S collects, with weight a_T,
+//     K += a_T e, S0 += a_T T1, Sd += a_T T1 d, Sdd += a_T w e d, Sn += a_T U1 n_T,
+// and the column face T, with weight a_S,
+//     K += a_S e, S0 -= a_S U1, Sd += a_S U1 d, Sdd -= a_S w e d, Sn -= a_S T1 n_S,
+// i.e. exactly what T's own row pass over S would add.  The energy-only kernel credits a_T t^q to
+// S and a_S tau^q to T (each ordered pair's forward kernel, as the row-only energy kernel sums).
+// The shared part of a pair (d, w, t, tau and their powers) is computed once instead of twice.
+//
+// Layout of a symmetric unit on one wave: the 128 rows stay in the lanes (2 per lane) as in the
+// row-only kernel; the unit's SYM_COLS columns are held one per lane too (SYM_COLS = 64: one per
+// lane of the wave; 16: one per lane of each row of 16 lanes), lane l taking column
+// (l + j) mod SYM_COLS at step j from LDS.  A column's sums travel with it: after every step they
+// move one lane down (a DPP wave or row rotation fused into the add of the step's contributions), so
+// after the SYM_COLS steps every lane holds the sums of one column over the rows of its group of
+// lanes, and the work-group adds the (64 / SYM_COLS) x SYM_NW partial sums of each column in LDS,
+// without any cross-lane reduction.
+
+// Shared part of the pair (row face, column face) for the symmetric kernel.  Energy only: e = t^q
+// (the row face's kernel) and we = tau^q (the column face's), since the energy-only row sums hold
+// the forward kernel alone.
+struct SymPair {
+    float dx, dy, dz, e, we, T1, U1;
+};
+
+template <bool GRAD, bool MASK>
+__device__ __forceinline__ SymPair sym_pair(const ColRec& cr, int4 cv, float rx, float ry, float rz, float nx,
+                                            float ny, float nz, int v0, int v1, int v2) {
+    SymPair P;
+    P.dx = rx - cr.cx; P.dy = ry - cr.cy; P.dz = rz - cr.cz;
+    float r2 = fmaf(P.dz, P.dz, fmaf(P.dy, P.dy, P.dx * P.dx));
+    float w = __builtin_amdgcn_rcpf(r2);
+    if constexpr (MASK) {
+        bool ex = (v0 == cv.x) | (v0 == cv.y) | (v0 == cv.z) | (v1 == cv.x) | (v1 == cv.y) |
+                  (v1 == cv.z) | (v2 == cv.x) | (v2 == cv.y) | (v2 == cv.z);
+        w = ex ? 0.f : w;
+    }
+    float u = fmaf(nz, P.dz, fmaf(ny, P.dy, nx * P.dx));
+    float v = fmaf(cr.nz, P.dz, fmaf(cr.ny, P.dy, cr.nx * P.dx));
+    float t = u * w, tau = v * w;
+    if constexpr (!GRAD) {
+        float t3 = t * t * t, s3 = tau * tau * tau;
+        P.e = t3 * t3;
+        P.we = s3 * s3;
+    } else {
+        float t2 = t * t, t4 = t2 * t2, t5 = t4 * t;
+        float s2 = tau * tau, s4 = s2 * s2, s5 = s4 * tau;
+        P.T1 = w * t5;
+        P.U1 = w * s5;
+        P.e = fmaf(t5, t, s5 * tau);
+        P.we = w * P.e;
+    }
+    return P;
+}
+
+// the row face's share, weight a_T = cr.a
+template <bool GRAD>
+__device__ __forceinline__ void sym_row(const ColRec& cr, const SymPair& P, float* acc) {
+    acc[0] = fmaf(cr.a, P.e, acc[0]);
+    if constexpr (GRAD) {
+        float s = cr.a * P.T1;
+        acc[1] += s;
+        acc[2] = fmaf(s, P.dx, acc[2]);
+        acc[3] = fmaf(s, P.dy, acc[3]);
+        acc[4] = fmaf(s, P.dz, acc[4]);
+        float m = cr.a * P.we;
+        acc[5] = fmaf(m, P.dx, acc[5]);
+        acc[6] = fmaf(m, P.dy, acc[6]);
+        acc[7] = fmaf(m, P.dz, acc[7]);
+        float sp = cr.a * P.U1;
+        acc[8] = fmaf(sp, cr.nx, acc[8]);
+        acc[9] = fmaf(sp, cr.ny, acc[9]);
+        acc[10] = fmaf(sp, cr.nz, acc[10]);
+    }
+}
+
+// x moved down by one lane within each group of SYM_COLS lanes, the group's last lane taking its
+// first lane's value (DPP wave_rol:1 for 64, row_ror:15 for 16), plus y
+__device__ __forceinline__ float rot_add(float x, float y) {
+    static_assert(SYM_COLS == 64 || SYM_COLS == 16, "rotation over the wave or over rows of 16 lanes");
+    constexpr int ctrl = SYM_COLS == 64 ? 0x134 : 0x12F;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false)) + y;
+}
+
+// The column face's share of the step's two pairs (rows 0 and 1 of the lane, weights a_S), added
+// to the column sums after moving them one lane down (ROT; the first step has nothing to move).
+template <bool GRAD, bool ROT>
+__device__ __forceinline__ void sym_col(const SymPair& P0, const SymPair& P1, float aS0, float aS1, float nx0,
+                                        float ny0, float nz0, float nx1, float ny1, float nz1, float* ca) {
+    float c[GRAD ? NACC : 1];
+    if constexpr (!GRAD) {
+        c[0] = fmaf(aS1, P1.we, aS0 * P0.we);
+    } else {
+        c[0] = fmaf(aS1, P1.e, aS0 * P0.e);
+        const float y0 = aS0 * P0.U1, y1 = aS1 * P1.U1;
+        const float z0 = aS0 * P0.we, z1 = aS1 * P1.we;
+        const float x0 = aS0 * P0.T1, x1 = aS1 * P1.T1;
+        c[1] = -y0 - y1;
+        c[2] = fmaf(y1, P1.dx, y0 * P0.dx);
+        c[3] = fmaf(y1, P1.dy, y0 * P0.dy);
+        c[4] = fmaf(y1, P1.dz, y0 * P0.dz);
+        c[5] = fmaf(-z1, P1.dx, -z0 * P0.dx);
+        c[6] = fmaf(-z1, P1.dy, -z0 * P0.dy);
+        c[7] = fmaf(-z1, P1.dz, -z0 * P0.dz);
+        c[8] = fmaf(-x1, nx1, -x0 * nx0);
+        c[9] = fmaf(-x1, ny1, -x0 * ny0);
+        c[10] = fmaf(-x1, nz1, -x0 * nz0);
+    }
+#pragma unroll
+    for (int k = 0; k < (GRAD ? NACC : 1); ++k) ca[k] = ROT ? rot_add(ca[k], c[k]) : c[k];
+}
+
+template <bool GRAD, bool MASK, bool ROT>
+__device__ __forceinline__ void sym_step(const ColRec& cr, int4 cv, const float (&rx)[RPL], const float (&ry)[RPL],
+                                         const float (&rz)[RPL], const float (&nx)[RPL], const float (&ny)[RPL],
+                                         const float (&nz)[RPL], const float (&aS)[RPL], const int (&rv)[RPL][3],
+                                         float (&acc)[RPL][GRAD ? NACC : 1], float* ca) {
+    static_assert(RPL == 2, "the column share is written for two rows per lane");
+    const SymPair P0 = sym_pair<GRAD, MASK>(cr, cv, rx[0], ry[0], rz[0], nx[0], ny[0], nz[0], rv[0][0], rv[0][1],
+                                            rv[0][2]);
+    const SymPair P1 = sym_pair<GRAD, MASK>(cr, cv, rx[1], ry[1], rz[1], nx[1], ny[1], nz[1], rv[1][0], rv[1][1],
+                                            rv[1][2]);
+    sym_row<GRAD>(cr, P0, acc[0]);
+    sym_row<GRAD>(cr, P1, acc[1]);
+    sym_col<GRAD, ROT>(P0, P1, aS[0], aS[1], nx[0], ny[0], nz[0], nx[1], ny[1], nz[1], ca);
+}
+
+// One symmetric unit for the wave: its rows against the SYM_COLS columns staged in LDS (lcol, lv).
+// Row sums are folded into (hi, lo) as in chunk_pass; on return lane l holds in ca the sums of
+// column (l + SYM_COLS - 1) mod SYM_COLS over the rows of its group of SYM_COLS lanes.
+template <bool GRAD, bool MASK>
+__device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* lv, const float (&rx)[RPL],
+                                               const float (&ry)[RPL], const float (&rz)[RPL],
+                                               const float (&nx)[RPL], const float (&ny)[RPL],
+                                               const float (&nz)[RPL], const float (&aS)[RPL],
+                                               const int (&rv)[RPL][3], float (&hi)[RPL][NACC],
+                                               float (&lo)[RPL][NACC], float* ca) {
+    constexpr int NA = GRAD ? NACC : 1;
+    const int sl = threadIdx.x & (SYM_COLS - 1);
+    float acc[RPL][NA];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[r][k] = 0.f;
+    {
+        const ColRec cr = lcol[sl];
+        const int4 cv = MASK ? lv[sl] : make_int4(0, 0, 0, 0);
+        sym_step<GRAD, MASK, false>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+    }
+    // steps 1 .. SYM_COLS - 1, two per iteration (SYM_COLS - 1 is odd: the last one after the loop)
+#pragma unroll 1
+    for (int j = 1; j < SYM_COLS - 1; j += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int col = (sl + j + h) & (SYM_COLS - 1);
+            const ColRec cr = lcol[col];
+            const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
+            sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+        }
+    }
+    {
+        const int col = (sl + SYM_COLS - 1) & (SYM_COLS - 1);
+        const ColRec cr = lcol[col];
+        const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
+        sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
+}
+
+// LDS of the symmetric kernel's work-group: two column buffers (records, vertex ids) and two column
+// reduction buffers [SYM_NW][WAVE / SYM_COLS][SYM_COLS][CS] (CS = 12 with the gradient: 11 sums,
+// padded).
+template <bool GRAD>
+constexpr int sym_cs() { return GRAD ? 12 : 1; }
+template <bool GRAD>
+constexpr size_t sym_lds_floats() {
+    return 2 * (size_t)SYM_COLS * (8 + 4) + 2 * (size_t)SYM_NW * WAVE * sym_cs<GRAD>();
+}
+
+// grid: W work-groups of SYM_NW waves (see SymSched).  part: [W + nsb][SYM_NW][NA][ROWB] FP32, one
+// segment per (work-group g, super block I it touches) at slot g + I (the slots of consecutive
+// work-groups do not overlap: each super block after a work-group's first adds one slot), each wave
+// writing its own row block's compensated sums rounded to FP32 (hi minus the compensation).  colpart:
+// [symmetric unit][NA][SYM_COLS] FP32, the sums of the unit's SB rows for each of its columns, added
+// over the waves and rows of lanes in a fixed order.
+// first[w]: the first super block of work-group w (INT32_MAX if its range is empty).
+template <bool GRAD>
+__global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* __restrict__ cols,
+                                                                 const double* __restrict__ c64,
+                                                                 const int4* __restrict__ colv,
+                                                                 const double* __restrict__ corg,
+                                                                 const uint32_t* __restrict__ touch, int touch_words,
+                                                                 SymSched sc, float* __restrict__ part,
+                                                                 float* __restrict__ colpart, int* __restrict__ first) {
+    constexpr int NA = GRAD ? NACC : 1;
+    constexpr int CS = sym_cs<GRAD>();
+    extern __shared__ float lds[];
+    ColRec* lcol = reinterpret_cast<ColRec*>(lds);                 // [2][SYM_COLS]
+    int4* lvid = reinterpret_cast<int4*>(lds + 2 * SYM_COLS * 8);  // [2][SYM_COLS]
+    float* red = lds + 2 * SYM_COLS * 12;                          // [2][SYM_NW][WAVE][CS]
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int g = blockIdx.x;
+    int64_t u = sc.begin(g);
+    const int64_t u1 = sc.begin(g + 1);
+    if (u >= u1) {  // uniform over the work-group; an empty range (more work-groups than units)
+        if (threadIdx.x == 0) first[g] = INT32_MAX;
+        return;
+    }
+    int I = sc.block_of(u);
+    if (threadIdx.x == 0) first[g] = I;
+    int64_t k = u - sc.base(I);
+    // staging of a unit's columns: SYM_COLS columns x 12 dwords (record, vertex ids); thread t
+    // moves SPT consecutive dwords of column t / TPC (TPC threads per column)
+    constexpr int NT = WAVE * SYM_NW;
+    constexpr int TPC = NT / SYM_COLS < 12 ? NT / SYM_COLS : 12;
+    constexpr int SPT = 12 / TPC;
+    static_assert(TPC * SPT == 12 && SYM_COLS * TPC <= NT, "staging layout");
+    const bool stager = threadIdx.x < SYM_COLS * TPC;
+    const int sc_col = threadIdx.x / TPC, sc_d0 = SPT * (threadIdx.x % TPC);
+    auto stage_load = [&](int slice, float (&reg)[SPT]) {
+        if (!stager) return;
+        const size_t c = (size_t)slice * SYM_COLS + sc_col;
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int d = sc_d0 + q;
+            reg[q] = d < 8 ? reinterpret_cast<const float*>(cols + c)[d]
+                           : reinterpret_cast<const float*>(colv + c)[d - 8];
+        }
+    };
+    auto stage_store = [&](int b, const float (&reg)[SPT]) {
+        if (!stager) return;
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int d = sc_d0 + q;
+            if (d < 8) reinterpret_cast<float*>(lcol + b * SYM_COLS + sc_col)[d] = reg[q];
+            else reinterpret_cast<float*>(lvid + b * SYM_COLS + sc_col)[d - 8] = reg[q];
+        }
+    };
+    int nsym = 0;  // symmetric units done by this work-group
+    float pre[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) pre[q] = 0.f;
+    // the SYM_COLS-column slice of symmetric unit k >= SBC of super block I
+    auto slice_of = [&](int I_, int64_t k_) { return SUB * SBC * (I_ + 1) + (int)(k_ - SBC); };
+    if (k >= SBC) {  // the range starts on a symmetric unit: stage it now
+        stage_load(slice_of(I, k), pre);
+        stage_store(0, pre);
+        __syncthreads();
+    }
+    while (u < u1) {  // uniform over the work-group
+        const int rb = I * SYM_NW + wave;
+        double cxd[RPL], cyd[RPL], czd[RPL];
+        float nx[RPL], ny[RPL], nz[RPL], aS[RPL];
+        int rv[RPL][3];
+        float hi[RPL][NACC], lo[RPL][NACC];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = rb * ROWB + r * WAVE + lane;
+            cxd[r] = c64[3 * (size_t)i + 0];
+            cyd[r] = c64[3 * (size_t)i + 1];
+            czd[r] = c64[3 * (size_t)i + 2];
+            const ColRec me = cols[i];
+            nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz; aS[r] = me.a;
+            const int4 v = colv[i];
+            rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
+#pragma unroll
+            for (int a = 0; a < NACC; ++a) { hi[r][a] = 0.f; lo[r][a] = 0.f; }
+        }
+        const uint32_t* my_touch = touch + (size_t)rb * touch_words;
+        const int64_t kn = sc.ua() - SymSched::UD * I;  // units of super block I
+        const int64_t kend = min(kn, k + (u1 - u));
+        for (; k < kend; ++k, ++u) {
+            // chunk of the unit (diagonal: the unit's columns; symmetric: the chunk of its slice)
+            const int J = k < SBC ? SBC * I + (int)k : slice_of(I, k) / SUB;
+            // the next unit of the range, if symmetric (a super block starts with diagonal units)
+            const bool next_sym = u + 1 < u1 && k + 1 < kn && k + 1 >= SBC;
+            if (next_sym) stage_load(slice_of(I, k + 1), pre);
+            // rows relative to the chunk's FP64 origin (its columns are stored relative to it)
+            const double ox = corg[3 * J + 0], oy = corg[3 * J + 1], oz = corg[3 * J + 2];
+            float rx[RPL], ry[RPL], rz[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                rx[r] = (float)(cxd[r] - ox);
+                ry[r] = (float)(cyd[r] - oy);
+                rz[r] = (float)(czd[r] - oz);
+            }
+            const bool masked = (my_touch[J >> 5] >> (J & 31)) & 1u;
+            if (k < SBC) {
+                const ColRec* tc = cols + (size_t)J * CHUNK;
+                const int4* tv = colv + (size_t)J * CHUNK;
+                if (masked) chunk_pass<6, GRAD, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                else chunk_pass<6, GRAD, false>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                if (next_sym) {
+                    stage_store(nsym & 1, pre);
+                    __syncthreads();
+                }
+            } else {
+                const int b = nsym & 1;
+                float ca[NA];
+                if (masked)
+                    sym_chunk_pass<GRAD, true>(lcol + b * SYM_COLS, lvid + b * SYM_COLS, rx, ry, rz, nx, ny, nz, aS,
+                                               rv, hi, lo, ca);
+                else
+                    sym_chunk_pass<GRAD, false>(lcol + b * SYM_COLS, lvid + b * SYM_COLS, rx, ry, rz, nx, ny, nz,
+                                                aS, rv, hi, lo, ca);
+                // lane l holds column (l + SYM_COLS - 1) mod SYM_COLS of its group of lanes l / SYM_COLS
+                const int mycol = (lane + SYM_COLS - 1) & (SYM_COLS - 1);
+                float* mine = red + (((size_t)(b * SYM_NW + wave) * (WAVE / SYM_COLS) + lane / SYM_COLS) * SYM_COLS +
+                                     mycol) * CS;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) mine[a] = ca[a];
+                if (next_sym) stage_store(b ^ 1, pre);
+                // Buffers: unit s reads chunk buffer s & 1 and writes reduction buffer s & 1; the
+                // next symmetric unit's chunk goes to the other buffer, whose last reader (unit s - 1)
+                // finished before the previous barrier, and reduction buffer s & 1 is written again
+                // by unit s + 2 only after the barrier of unit s + 1, which every wave reaches after
+                // its reads below.
+                __syncthreads();
+                const float* rbuf = red + (size_t)b * SYM_NW * WAVE * CS;
+                float* out = colpart + (size_t)(sc.base_sym(I) + k - SBC) * NA * SYM_COLS;
+                for (int e = threadIdx.x; e < NA * SYM_COLS; e += NT) {
+                    const int a = e / SYM_COLS, j = e % SYM_COLS;
+                    float sum = 0.f;
+#pragma unroll
+                    for (int w = 0; w < SYM_NW * (WAVE / SYM_COLS); ++w) sum += rbuf[(w * SYM_COLS + j) * CS + a];
+                    out[e] = sum;
+                }
+                ++nsym;
+            }
+        }
+        float* o = part + ((size_t)(g + I) * SYM_NW + wave) * NA * ROWB + lane;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) o[(size_t)a * ROWB + r * WAVE] = hi[r][a] - lo[r][a];
+        ++I;
+        k = 0;
+    }
+}
+
+static size_t pair_sym_lds_bytes(bool grad) {
+    return sizeof(float) * (grad ? sym_lds_floats<true>() : sym_lds_floats<false>());
+}
+
+int pair_sym_blocks_per_cu(bool grad) {
+    int nb = 0;
+    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<true>, WAVE * SYM_NW,
+                                                                       pair_sym_lds_bytes(true))
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<false>, WAVE * SYM_NW,
+                                                                       pair_sym_lds_bytes(false));
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+// Fp padded faces (a multiple of SB), W work-groups at most
+SymSched make_sym_sched(int64_t Fp, int W) {
+    SymSched sc;
+    sc.nsb = (int)(Fp / SB);
+    sc.nch = (int)(Fp / CHUNK);
+    sc.U = sc.base(sc.nsb);
+    sc.C = (int64_t)SYM_COST * sc.U + (int64_t)(DIAG_COST - SYM_COST) * SBC * sc.nsb;
+    sc.W = (int)std::max<int64_t>(1, std::min<int64_t>(W, sc.U));
+    return sc;
+}
+
+int64_t sym_part_floats(const SymSched& sc, bool grad) {
+    return ((int64_t)sc.W + sc.nsb) * SYM_NW * (grad ? NACC : 1) * ROWB;
+}
+int64_t sym_colpart_floats(const SymSched& sc, bool grad) {
+    return sc.base_sym(sc.nsb) * (grad ? NACC : 1) * SYM_COLS;
+}
+
+hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                           const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
+                           int* first, hipStream_t st) {
+    if (grad)
+        hipLaunchKernelGGL((pair_sym_kernel<true>), dim3(sc.W), dim3(WAVE * SYM_NW), pair_sym_lds_bytes(true), st,
+                           cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
+    else
+        hipLaunchKernelGGL((pair_sym_kernel<false>), dim3(sc.W), dim3(WAVE * SYM_NW), pair_sym_lds_bytes(false), st,
+                           cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
+    return hipGetLastError();
+}
+
 static size_t pair_lds_bytes(bool grad) { return sizeof(float) * (PAIR_NW - 1) * 2 * (grad ? NACC : 1) * ROWB; }
 
 int pair_blocks_per_cu(bool grad) {

@@ -202,6 +202,44 @@ def test_split_independence(waves):
     assert rel_grad_maxnorm(G.cpu().numpy(), Go) <= G_TOL
 
 
+def _sym_cases():
+    X, F = M.icosphere(0)
+    yield "L0 (20 faces, one super block)", M.radial_jitter(X, 0.02, 1), F
+    X, F = M.icosphere(2)
+    yield "L2 (320 faces)", M.radial_jitter(X, 0.02, 2), F
+    X, F = M.icosphere(3)
+    Xb, _, _ = M.bump(X, 0, 0.3, 0.1)
+    yield "L3-bump (1,280 faces, ragged)", Xb, F
+    X, F = M.icosphere(4)
+    yield "L4-patch (2,001 faces, ragged)", *_patch(M.sh_deform(X, 2, 6, 0.05, 3)[0], F, X[7], 2001)
+
+
+@pytest.mark.parametrize("name,X,F", list(_sym_cases()), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("waves", [0, 1, 7, 100000])
+def test_symmetric_kernel(name, X, F, waves):
+    """The symmetric pair kernel (default for (6, 12)) and the row-only kernel against the oracle,
+    for several work-group counts (uneven ranges, empty ranges, one work-group for everything)."""
+    T = tpe()
+    Eo, Go = oracle.gradient(X, F)
+    Xd, Fd = upload(X, F)
+    ctx = T.context(Xd.device)
+    ctx.set_option(T.OPT_TARGET_WAVES, waves)
+    out = {}
+    try:
+        for sym in (1, 0):
+            ctx.set_option(T.OPT_SYMMETRIC, sym)
+            E, G = T.gradient(Xd, Fd)
+            Ee = T.energy(Xd, Fd)
+            out[sym] = (float(E.cpu()), G.cpu().numpy(), float(Ee.cpu()))
+    finally:
+        ctx.set_option(T.OPT_SYMMETRIC, 1)
+        ctx.set_option(T.OPT_TARGET_WAVES, 0)
+    for sym, (E, G, Ee) in out.items():
+        eE, eEe, eG = rel_energy(E, Eo), rel_energy(Ee, Eo), rel_grad_maxnorm(G, Go)
+        log(name, "waves", waves, "symmetric", sym, "rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
+        assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
+
+
 def test_pair_count():
     T = tpe()
     for level in (1, 3, 5):
