@@ -185,8 +185,11 @@ int64_t tpe_mlp_num_params(const tpe_mlp* mlp);
 int tpe_mlp_get_params(tpe_ctx* ctx, const tpe_mlp* mlp, float* host, int64_t n);
 int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* mlp, const float* host, int64_t n);
 /* tpe_farfield applies the correction only to far clusters with r_B / rho >= min_s (default 0:
- * all); rho = |c_S - C_B|.  Stored with the network (not in checkpoints). */
+ * all); rho = |c_S - C_B|.  A wave skips the network for a cluster when none of its 64 faces is
+ * inside the gate.  Stored with the network and in checkpoints. */
 int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* mlp, float min_s);
+/* *min_s (host) <- the gate of mlp. */
+int tpe_mlp_get_gate(tpe_ctx* ctx, const tpe_mlp* mlp, float* min_s);
 /* Weight lam >= 0 (default 0) of the training loss's difference term: for consecutive rows i, i+1
  * of one 32-row tile of a training batch, lam w_i w_(i+1) sum_(j<7) ((y_(i+1),j - y_ij) -
  * (t_(i+1),j - t_ij))^2 is added to the loss (same normalisation).  Rows of a tile of the
@@ -207,8 +210,9 @@ int tpe_mlp_train_step(tpe_ctx* ctx, tpe_mlp* mlp, const float* feats, const flo
  * (a hook for checking the hand-written backward pass). */
 int tpe_mlp_gradient(tpe_ctx* ctx, tpe_mlp* mlp, const float* feats, const float* targets,
                      int64_t n, float* grad_dev);
-/* Checkpoint: magic "TPEMLP01", int32 dims[4], int64 Adam step, then parameters, first and
- * second Adam moments (FP32 each).  Training resumes exactly from a loaded checkpoint. */
+/* Checkpoint: magic "TPEMLP02", int32 dims[4], int64 Adam step, float32 gate min_s and 4 bytes of
+ * padding, then parameters, first and second Adam moments (FP32 each).  Training resumes exactly
+ * from a loaded checkpoint.  Files with magic "TPEMLP01" (no gate field) load with min_s = 0. */
 int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* mlp, const char* path);
 int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out);
 

@@ -83,6 +83,7 @@ def lib():
             "tpe_mlp_set_params": ([P, P, P, I64], I),
             "tpe_mlp_forward": ([P, P, P, I64, P], I),
             "tpe_mlp_set_gate": ([P, P, ctypes.c_float], I),
+            "tpe_mlp_get_gate": ([P, P, ctypes.POINTER(ctypes.c_float)], I),
             "tpe_mlp_set_smoothness": ([P, P, ctypes.c_float], I),
             "tpe_mlp_train_step": ([P, P, P, P, I64, ctypes.c_float, P], I),
             "tpe_mlp_gradient": ([P, P, P, P, I64, P], I),
@@ -308,6 +309,12 @@ class MLP:
         """Apply the far-field correction only to clusters with r_B / rho >= min_s."""
         c = context(self.device)
         c.check(lib().tpe_mlp_set_gate(c.h, self.h, float(min_s)))
+
+    def gate(self) -> float:
+        c = context(self.device)
+        v = ctypes.c_float()
+        c.check(lib().tpe_mlp_get_gate(c.h, self.h, ctypes.byref(v)))
+        return float(v.value)
 
     def forward(self, feats):
         feats = feats.contiguous()

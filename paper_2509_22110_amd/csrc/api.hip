@@ -865,6 +865,13 @@ int tpe_mlp_set_smoothness(tpe_ctx* ctx, tpe_mlp* m, float lam) {
     return TPE_OK;
 }
 
+int tpe_mlp_get_gate(tpe_ctx* ctx, const tpe_mlp* m, float* min_s) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!m || !min_s) return fail(ctx, TPE_ERR_INVALID_ARG, "bad gate arguments");
+    *min_s = m->min_s;
+    return TPE_OK;
+}
+
 int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* m, float min_s) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !(min_s >= 0.f) || !std::isfinite(min_s)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad gate");
@@ -908,7 +915,8 @@ int tpe_mlp_gradient(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* 
     return mlp_step(ctx, m, feats, targets, n, 0.f, nullptr, grad_dev);
 }
 
-static const char MLP_MAGIC[8] = {'T', 'P', 'E', 'M', 'L', 'P', '0', '1'};
+static const char MLP_MAGIC[8] = {'T', 'P', 'E', 'M', 'L', 'P', '0', '2'};
+static const char MLP_MAGIC_V1[8] = {'T', 'P', 'E', 'M', 'L', 'P', '0', '1'};  // no gate (read as 0)
 
 int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* m, const char* path) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
@@ -925,8 +933,10 @@ int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* m, const char* path) {
     if (!f) return fail(ctx, TPE_ERR_INVALID_ARG, std::string("cannot open ") + path);
     const int32_t dims[4] = {MLP_DIN, MLP_W, MLP_DEPTH, MLP_DOUT};
     const int64_t step = m->step;
+    const float gate[2] = {m->min_s, 0.f};
     bool ok = fwrite(MLP_MAGIC, 1, 8, f) == 8 && fwrite(dims, sizeof(dims), 1, f) == 1 &&
-              fwrite(&step, sizeof(step), 1, f) == 1 && fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+              fwrite(&step, sizeof(step), 1, f) == 1 && fwrite(gate, sizeof(gate), 1, f) == 1 &&
+              fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
     ok = (fclose(f) == 0) && ok;
     return ok ? TPE_OK : fail(ctx, TPE_ERR_INVALID_ARG, std::string("write failed: ") + path);
 }
@@ -941,14 +951,19 @@ int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out) {
     int32_t dims[4];
     int64_t step = 0;
     std::vector<float> buf(3 * (size_t)MLP_NPARAM);
-    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, MLP_MAGIC, 8) == 0 && fread(dims, sizeof(dims), 1, f) == 1 &&
-              dims[0] == MLP_DIN && dims[1] == MLP_W && dims[2] == MLP_DEPTH && dims[3] == MLP_DOUT &&
-              fread(&step, sizeof(step), 1, f) == 1 && fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    float gate[2] = {0.f, 0.f};
+    bool ok = fread(magic, 1, 8, f) == 8;
+    const bool v2 = ok && memcmp(magic, MLP_MAGIC, 8) == 0;
+    ok = ok && (v2 || memcmp(magic, MLP_MAGIC_V1, 8) == 0) && fread(dims, sizeof(dims), 1, f) == 1 &&
+         dims[0] == MLP_DIN && dims[1] == MLP_W && dims[2] == MLP_DEPTH && dims[3] == MLP_DOUT &&
+         fread(&step, sizeof(step), 1, f) == 1 && (!v2 || fread(gate, sizeof(gate), 1, f) == 1) &&
+         fread(buf.data(), sizeof(float), buf.size(), f) == buf.size() && gate[0] >= 0.f && std::isfinite(gate[0]);
     fclose(f);
     if (!ok) return fail(ctx, TPE_ERR_INVALID_ARG, std::string("not a valid MLP checkpoint: ") + path);
     tpe_mlp* m = nullptr;
     int rc = tpe_mlp_create(ctx, MLP_DIN, MLP_W, MLP_DEPTH, MLP_DOUT, 0, &m);
     if (rc) return rc;
+    m->min_s = gate[0];
     DeviceGuard dg(ctx->device);
     hipError_t e = hipMemcpy(m->P, buf.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->M, buf.data() + MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);

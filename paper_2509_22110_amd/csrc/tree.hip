@@ -375,11 +375,16 @@ __device__ __forceinline__ void to_frame(const float* v, const Frame& fr, float*
 __device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, const NodeRec& cn, const NodeMom& mm,
                                                float ax, float ay, float az, float nx, float ny, float nz,
                                                MlpScratch& ms, float (&acc)[NACC]) {
+    // the gate (r_B / rho >= min_s), checked before the features: the wave skips the network when
+    // no row needs it
+    const float gx = ax - cn.cx, gy = ay - cn.cy, gz = az - cn.cz;
+    const bool gate = cn.r * cn.r >= W->min_s * W->min_s * (gx * gx + gy * gy + gz * gz);
+    if (!__any(gate)) return;
     Frame fr;
     float x[32], y[16];
     ff_features(ax, ay, az, nx, ny, nz, cn, mm, fr, x);
     mlp_infer64(W, x, ms, y);
-    if (0.25f * x[0] < W->min_s) return;  // outside the gate (x[0] = 4 r_B / rho)
+    if (!gate) return;
     float u6, u7;
     out_units(cn.a, fr, u6, u7);
     acc[0] += u6 * y[0];
@@ -445,6 +450,8 @@ __global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restr
     if (lane == 0) stack[0] = 1;
     int sz = 1;
     while (sz > 0) {
+        // the pops below read entries other lanes pushed: keep them after those stores
+        lds_phase();
         const int n = sz < 64 ? sz : 64;
         sz -= n;
         const bool act = lane < n;
@@ -595,6 +602,7 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
     if (lane == 0) stack[0] = 1;
     int sz = 1;
     while (sz > 0 && taken < quota) {
+        lds_phase();  // the pops below read entries other lanes pushed
         const int n = sz < 64 ? sz : 64;
         sz -= n;
         const bool act = lane < n;

@@ -191,6 +191,33 @@ def report_shapes(seeds=(1196, 1197, 1198, 1199)):
     return [training_shape(s, level=6 if i < len(seeds) // 2 else 7) for i, s in enumerate(seeds)]
 
 
+GATES = (0.0, 0.1, 0.15, 0.18, 0.2, 0.22)
+
+
+def select_gate(mlp, shapes, gates=GATES, theta=0.5, log=print):
+    """Choose the gate min_s (the correction applies to far clusters with r_B / rho >= min_s) on
+    held-out shapes: the far-field gradient's max-norm error against the exact path, averaged over
+    the shapes, is evaluated for every candidate; the smallest mean wins, a larger gate (less
+    network work) among those within 1% of it.  Sets the gate on mlp and returns it."""
+    errs = np.zeros(len(gates))
+    for X, F in shapes:
+        Xd = torch.from_numpy(X).cuda()
+        Fd = torch.from_numpy(F).cuda()
+        E0, G0 = gradient(Xd, Fd)
+        g0 = float(G0.abs().max())
+        tree = build_tree(Xd, Fd)
+        for i, g in enumerate(gates):
+            mlp.set_gate(g)
+            _, G = farfield(tree, Xd, Fd, theta=theta, mlp=mlp)
+            errs[i] += float((G - G0).abs().max()) / g0 / len(shapes)
+    best = float(errs.min())
+    pick = max(i for i in range(len(gates)) if errs[i] <= 1.01 * best)
+    log("gate selection (mean gradient max-norm error on held-out shapes): "
+        + " ".join(f"{g}: {e:.4e}" for g, e in zip(gates, errs)) + f"; chose {gates[pick]}")
+    mlp.set_gate(gates[pick])
+    return gates[pick]
+
+
 def fit(X, T, Xv, Tv, epochs=8, seed=0, log=print, max_ratio=1.0, lam=0.0):
     """Train on per-output normalized targets, fold the scales back into the last layer, and keep
     only the outputs that beat the zero correction on the validation set (ratio < max_ratio)."""
@@ -216,10 +243,19 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--smooth", type=float, default=1.0, help="weight of the neighbouring-face difference term")
+    ap.add_argument("--select-gate-only", metavar="CHECKPOINT", default=None,
+                    help="load CHECKPOINT, choose its gate on the held-out shapes, save it to --out")
     args = ap.parse_args(argv)
 
     def log(*a):
         print(f"[{time.strftime('%H:%M:%S')}]", *a, flush=True)
+
+    if args.select_gate_only:
+        mlp = MLP.load(args.select_gate_only)
+        select_gate(mlp, report_shapes(), theta=args.theta, log=log)
+        mlp.save(args.out)
+        log(f"saved {args.out}")
+        return 0
 
     seeds = list(range(args.first_seed, args.first_seed + args.shapes))
     nval = max(1, args.shapes // 10)
@@ -229,7 +265,9 @@ def main(argv=None):
     log(f"samples: train {X.shape[0]}, val {Xv.shape[0]} ({time.time() - t0:.1f} s)")
     mlp = fit(X, T, Xv, Tv, epochs=args.epochs, seed=args.first_seed, log=log, lam=args.smooth)
     log("far-field errors by applied output group on held-out level-6/7 shapes:")
-    group_report(mlp, report_shapes(), theta=args.theta, log=log)
+    shapes = report_shapes()
+    group_report(mlp, shapes, theta=args.theta, log=log)
+    select_gate(mlp, shapes, theta=args.theta, log=log)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     mlp.save(args.out)
     log(f"saved {args.out}; val loss {evaluate(mlp, Xv, Tv):.4e} vs zero-prediction {zero_loss(Tv):.4e}")

@@ -126,6 +126,41 @@ def test_farfield_speed_and_accuracy_at_c4(trained):
     assert eGm <= 1e-3
 
 
+def test_committed_checkpoint_at_c4():
+    """The committed checkpoint on the level-7 workload (327,680 faces, theta 0.5): its gate was
+    chosen on held-out training-family shapes (mlp_train.select_gate), not on this workload.  The
+    learned far field must be >= 10x faster than the exact kernel at <= 1e-3 gradient max-norm
+    error, and no farther from the exact gradient than the plain monopole."""
+    import os
+    import torch
+    T = tpe()
+    ckpt = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2509_22110_amd", "data",
+                        "farfield_mlp.bin")
+    m = T.MLP.load(ckpt)
+    c = M.make_config("C4")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+
+    def timed(fn, reps=3):
+        fn(); torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+    t_e, (E0, G0) = timed(lambda: T.gradient(Xd, Fd), reps=2)
+    _, (Em, Gm) = timed(lambda: T.farfield(tree, Xd, Fd, theta=0.5))
+    t_l, (El, Gl) = timed(lambda: T.farfield(tree, Xd, Fd, theta=0.5, mlp=m))
+    G0 = G0.cpu().numpy()
+    eGm = rel_grad_maxnorm(Gm.cpu().numpy(), G0)
+    eGl = rel_grad_maxnorm(Gl.cpu().numpy(), G0)
+    eEl = rel_energy(float(El.cpu()), float(E0.cpu()))
+    log(f"C4 committed checkpoint (gate {m.gate():.3f}): exact {t_e*1e3:.1f} ms, learned {t_l*1e3:.2f} ms "
+        f"({t_e/t_l:.1f}x), rel G {eGl:.3e} (monopole {eGm:.3e}), rel E {eEl:.3e}")
+    assert t_e / t_l >= 10.0
+    assert eGl <= 1e-3 and eGl <= eGm
+
+
 def test_c5_learned_flow_judged():
     """Level-8 workload (1,310,720 faces, gap 0.01): 100 explicit gradient-flow steps driven by
     the learned far field (committed checkpoint) on a tree built once, with the exact path as the

@@ -80,9 +80,21 @@ def test_training_reduces_loss_and_checkpoint_roundtrip(tmp_path):
     assert losses[-1] < 0.2 * losses[0]
     # the reported loss is the reference loss of the parameters before the step
     path = str(tmp_path / "mlp.bin")
+    m.set_gate(0.17)
     m.save(path)
     m2 = T_.MLP.load(path)
     assert np.array_equal(m.get_params(), m2.get_params())
+    assert m2.gate() == np.float32(0.17)
+    # a checkpoint of the first format (no gate field) loads with gate 0
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"TPEMLP02"
+    v1 = str(tmp_path / "mlp_v1.bin")
+    with open(v1, "wb") as f:
+        f.write(b"TPEMLP01" + raw[8:32] + raw[40:])
+    m3 = T_.MLP.load(v1)
+    assert m3.gate() == 0.0 and np.array_equal(m.get_params(), m3.get_params())
+    m.set_gate(0.0)
+    m2.set_gate(0.0)
     l1 = [float(m.train_step(Xd, Td, 3e-3)) for _ in range(5)]
     l2 = [float(m2.train_step(Xd, Td, 3e-3)) for _ in range(5)]
     assert l1 == l2  # resumed Adam state is exact and the kernels are deterministic
