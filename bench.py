@@ -170,6 +170,14 @@ def farfield_leg(args, T, M, torch, dev):
         mlp = T.MLP.load(args.mlp, device=dev)
         out["learned"] = variant(mlp)
         out["learned"]["checkpoint"] = os.path.relpath(args.mlp, ROOT)
+        out["learned"]["gate"] = round(mlp.gate(), 4)
+    # dual tree (both integrals clustered) on the same tree
+    t, _ = timed(lambda: T.farfield_dual(tree, X, F, theta=args.theta, out=G, energy_out=E), args.ff_reps)
+    st = T.context(dev).farfield_stats()
+    out["dual_tree"] = {"ms": round(t, 3), "speedup_vs_exact": round(t_exact / t, 2),
+                        "rel_grad_maxnorm": float((G - G0).abs().max()) / g0,
+                        "rel_energy": abs(float(E) - e0) / abs(e0),
+                        "far_cluster_pairs": st[0], "exact_face_pairs": st[1]}
     T.context(dev).sync_check()
     return out
 

@@ -165,6 +165,22 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
                  const tpe_mlp* mlp, double* E_dev, double* G_dev);
 
+/* Dual-tree (cluster-cluster) approximation of E and dE/dX on the tree: both integrals clustered,
+ * the scheme the paper compares against in Sec. 3.2 (its own clusters only the inner integrals),
+ * with the derivatives carried back from the clusters to the faces.  A pair of same-level clusters
+ * (A, B) (area, area-weighted centroid, unit mean normal, vertex-bounding radius each) is far when
+ * 2 max(r_A, r_B) < theta |C_A - C_B| and then counts as one pair of pseudo-faces for all its face
+ * pairs; the interaction lists are built level by level (the children of a node's parent's near
+ * clusters are its candidates), and the near pairs of the dual leaves (the nodes of 64 faces)
+ * are evaluated exactly, with the shared-vertex exclusion.  E is this approximate energy and G
+ * its exact gradient (every cluster's derivative passed down to its faces).  theta in [0, 1];
+ * theta = 0 reproduces tpe_gradient to rounding (at quadratic cost).  The tree's leaf size must
+ * divide 64.  TPE_ERR_OOM if the lists outgrow their scratch (384 entries per node on average;
+ * only for theta far below 0.5).  E_dev and/or G_dev may be NULL but not both.  (Not in the
+ * paper's own method.) */
+int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F,
+                      int64_t nF, double q, double p, double scale, double theta, double* E_dev, double* G_dev);
+
 /* ---- learned far-field correction (not part of the paper) ------------------------------------
  * A multilayer perceptron 32 -> 64 -> 64 -> 64 -> 16 (ReLU), evaluated and trained with BF16
  * matrix-core (MFMA) products accumulated in FP32, with FP32 master weights and Adam.  Its inputs
@@ -242,7 +258,8 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
 /* Interaction counts of the last tpe_farfield call on this context, summed over target blocks of
  * 64 faces (each count applies to every face of a block): out_host[0] = far clusters evaluated,
  * [1] = near columns evaluated exactly, [2] = tree nodes visited, [3] = target blocks; and the
- * largest per block: [4] = near columns, [5] = far clusters.  Host array of 6 int64.
+ * largest per block: [4] = near columns, [5] = far clusters.  After tpe_farfield_dual: [0] =
+ * far cluster pairs, [1] = exactly evaluated face pairs, the rest 0.  Host array of 6 int64.
  * Synchronises the stream. */
 int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
 

@@ -72,6 +72,7 @@ def lib():
             "tpe_build_tree": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
             "tpe_tree_destroy": ([P], I),
             "tpe_farfield": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
+            "tpe_farfield_dual": ([P, P, P, I64, P, I64, D, D, D, D, P, P], I),
             "tpe_farfield_stats": ([P, ctypes.POINTER(I64)], I),
             "tpe_farfield_samples": ([P, P, P, I64, P, I64, D, ctypes.c_uint64, D, ctypes.c_int32, I64, P, P, P, P],
                                      I),
@@ -257,6 +258,20 @@ def farfield(tree: Tree, X, F, theta=0.5, q=6.0, p=12.0, scale=1.0, mlp=None, ou
     c.check(lib().tpe_farfield(c.h, tree.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], float(q),
                                float(p), float(scale), float(theta), mlp.h if mlp is not None else None,
                                E.data_ptr(), G.data_ptr() if G is not None else None))
+    return E, G
+
+
+def farfield_dual(tree: Tree, X, F, theta=0.5, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None,
+                  want_grad=True):
+    """Dual-tree (cluster-cluster) approximation (E, G) on `tree`: G is the exact gradient of the
+    approximate energy E (see tpe_farfield_dual)."""
+    X, F = _check_mesh(X, F)
+    G = (out if out is not None else torch.empty_like(X)) if want_grad else None
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_farfield_dual(c.h, tree.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], float(q),
+                                    float(p), float(scale), float(theta), E.data_ptr(),
+                                    G.data_ptr() if G is not None else None))
     return E, G
 
 

@@ -55,6 +55,13 @@ int64_t sym_colpart_floats(const SymSched& sc, bool grad);
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
                            int* first, hipStream_t st);
+int dual_level(int H, int leaf);
+int64_t dual_entry_cap(int H, int leaf);
+hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const int4* colv, const double* c64,
+                       const double* geo, const double* org, const void* nodes64, const void* recs_, int64_t nF,
+                       int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
+                       uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, double* acc64, uint32_t* flags,
+                       unsigned long long* stats, hipStream_t st);
 // the symmetric kernel is used while its column partials fit in this many bytes
 constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)6 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
@@ -245,6 +252,11 @@ struct Plan {
     float4* balls = nullptr;
     float4* cen4 = nullptr;
     uint32_t* nbox = nullptr;
+    // dual-tree far field (leaf size of the tree; -1: not used)
+    int dual_leaf = -1;
+    uint32_t *doff = nullptr, *dnear = nullptr, *dfar = nullptr, *dcnt = nullptr, *drel = nullptr;
+    uint32_t *dent = nullptr, *dscan = nullptr;
+    double* dadj = nullptr;
     size_t bytes;
 };
 
@@ -297,6 +309,18 @@ void layout(Plan& P, char* base, bool grad) {
         P.balls = c.take<float4>(Fp / 64);
         P.cen4 = c.take<float4>(nF);
         P.nbox = c.take<uint32_t>((size_t)6 << std::max(P.treeH - 1, 0));
+        if (P.dual_leaf > 0) {
+            const int Hd = dual_level(P.treeH, P.dual_leaf);
+            const size_t nn = (size_t)2 << Hd, nl = (size_t)1 << Hd;
+            P.doff = c.take<uint32_t>(nn);
+            P.dnear = c.take<uint32_t>(nn);
+            P.dfar = c.take<uint32_t>(nn);
+            P.dcnt = c.take<uint32_t>(nl);
+            P.drel = c.take<uint32_t>(nl);
+            P.dscan = c.take<uint32_t>((size_t)scan_ws_words((int64_t)nl) + 1);
+            P.dent = c.take<uint32_t>((size_t)dual_entry_cap(P.treeH, P.dual_leaf));
+            P.dadj = c.take<double>(8 * nn);
+        }
     }
     P.bytes = c.off + 256;
 }
@@ -393,6 +417,8 @@ int report_flags(tpe_ctx* ctx) {
     if (f & FLAG_NONFINITE)
         return fail(ctx, TPE_ERR_NONFINITE, "non-finite input or result (coincident non-adjacent centroids?)");
     if (f & FLAG_DEGENERATE) return fail(ctx, TPE_ERR_DEGENERATE, "degenerate face (area <= 1e-300)");
+    if (f & FLAG_LISTS)
+        return fail(ctx, TPE_ERR_OOM, "dual-tree interaction lists exceed their scratch (theta too small for this mesh)");
     return TPE_OK;
 }
 
@@ -725,6 +751,52 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                            (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
+                           P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
+    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
+int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                      double q, double p, double scale, double theta, double* E_dev, double* G_dev) {
+    int rc = check_common(ctx, X, V, F, nF, q, p);
+    if (rc) return rc;
+    if (!tree) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree");
+    if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
+    if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
+    if (tree->leaf > 64 || (64 % tree->leaf) != 0)
+        return fail(ctx, TPE_ERR_UNSUPPORTED, "the dual-tree far field needs a leaf size dividing 64");
+    if (!(theta >= 0.0 && theta <= 1.0)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be in [0, 1]");
+    if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
+    if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
+    if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    if (ctx->quad != 1) return fail(ctx, TPE_ERR_UNSUPPORTED, "the far field uses one point per face");
+    DeviceGuard dg(ctx->device);
+    Plan P;
+    P.dual_leaf = tree->leaf;
+    plan(P, ctx, nF, V, true, tree->H);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, true);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                          ctx->dflags, st));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->kernel_timing) {
+        if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
+    }
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
+    HIPCHK(launch_dual(tree->H, tree->leaf, (float)theta, P.cols, P.colv, P.c64, P.geo, P.org, P.nodes64, P.recs, nF,
+                       P.Fp, q, p, P.doff, P.dnear, P.dfar, P.dcnt, P.drel, P.dent, P.dscan, P.dadj, P.acc64,
+                       ctx->dflags, ctx->dstats, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,

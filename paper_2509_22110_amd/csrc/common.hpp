@@ -10,6 +10,7 @@ enum : uint32_t {
     FLAG_BAD_INDEX = 1u,   // a face refers to a vertex outside [0, V)
     FLAG_DEGENERATE = 2u,  // a face with area <= 1e-300
     FLAG_NONFINITE = 4u,   // non-finite coordinate, or a non-finite accumulated result
+    FLAG_LISTS = 8u,       // the dual-tree interaction lists outgrew their scratch
 };
 
 // Geometry of the exact all-pairs kernel.
