@@ -81,7 +81,7 @@ typedef enum {
     TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
                                  every unordered pair of faces once and credit both faces (the
                                  symmetric pair kernel), while its column partial sums fit in 6 GiB
-                                 of the context's scratch (about 380,000 faces with the gradient);
+                                 of the context's scratch (about 450,000 faces with the gradient);
                                  0, or beyond that size: every ordered pair from its row face (the
                                  row-only kernel).  Results agree to rounding */
 } tpe_option;

@@ -44,10 +44,12 @@ __host__ __device__ inline void quad_point(int Q, int p, double* b, double& w) {
     }
 }
 
-// Column record read with scalar loads: centroid relative to its tile origin, area, normal.
+// Column record read with scalar loads: centroid relative to its tile origin, area, normal, and
+// wv = -2 a, the weight of a column's Sdd term in the symmetric kernel's combined sum
+// V = Sn - (p/q) Sdd for (q, p) = (6, 12).
 struct __align__(32) ColRec {
     float cx, cy, cz, a;
-    float nx, ny, nz, pad;
+    float nx, ny, nz, wv;
 };
 
 // Balanced persistent schedule.  The work is U = nrb * upr units, a unit being one chunk of CHUNK
@@ -74,6 +76,8 @@ struct Sched {
 // faces; the columns' share goes to one column partial per symmetric unit).  Units are numbered
 // super block by super block; work-group w takes the contiguous range [begin(w), begin(w+1)) of
 // equal cost, a diagonal unit costing DIAG_COST and a symmetric one SYM_COST.
+// sums per face in the symmetric kernel: K, S0, Sd (3), V = Sn - 2 Sdd (3)
+constexpr int NSYM = 8;
 constexpr int SYM_NW = 4;
 constexpr int SB = SYM_NW * ROWB;
 constexpr int SBC = SB / CHUNK;           // chunks per super block

@@ -165,7 +165,8 @@ int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
 // segments of the work-groups that cover i's super block (work-group order), then the column
 // partials of the symmetric units (I', i's columns) of the earlier super blocks I' (ascending), all
 // added in FP64.  Each wave's 64 faces lie in one row block, so the covering work-groups are
-// wave-uniform.
+// wave-uniform.  With the gradient the kernel's 8 sums K, S0, Sd, V = Sn - 2 Sdd become the 11 of
+// the finalize as Sn = V and Sdd = 0 (the finalize uses Sn and Sdd only as q Sn - p Sdd, p = 2q).
 template <int NA>
 __global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict__ part,
                                                         const float* __restrict__ colpart,
@@ -174,6 +175,14 @@ __global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict_
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (i >= nR) return;
+    int ks = k;  // the kernel's sum that feeds finalize sum k
+    if constexpr (NA == NSYM) {
+        if (k >= 5 && k < 8) {
+            acc64[(size_t)k * Fp + i] = 0.0;
+            return;
+        }
+        ks = k < 5 ? k : k - 3;
+    }
     const int rr = (int)(i % ROWB);
     const int rb = __builtin_amdgcn_readfirstlane((int)(i / ROWB));
     const int I = rb / SYM_NW, wv = rb % SYM_NW;
@@ -186,13 +195,13 @@ __global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict_
 #pragma unroll 8
     for (int w = w0; w <= w1; ++w) {
         const int f = first[w];
-        const float v = part[(((size_t)(w + I) * SYM_NW + wv) * NA + k) * ROWB + rr];
+        const float v = part[(((size_t)(w + I) * SYM_NW + wv) * NA + ks) * ROWB + rr];
         acc += f <= I ? (double)v : 0.0;
     }
     const int J = (int)(i / SYM_COLS), jj = (int)(i % SYM_COLS);
 #pragma unroll 8
     for (int Ip = 0; Ip < I; ++Ip)
-        acc += (double)colpart[((size_t)(sc.base_sym(Ip) + J - SUB * SBC * (Ip + 1)) * NA + k) * SYM_COLS + jj];
+        acc += (double)colpart[((size_t)(sc.base_sym(Ip) + J - SUB * SBC * (Ip + 1)) * NA + ks) * SYM_COLS + jj];
     acc64[(size_t)k * Fp + i] = acc;
 }
 
@@ -200,7 +209,7 @@ hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, 
                             const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st) {
     const dim3 grid((unsigned)((nR + 255) / 256), grad ? NACC : 1);
     if (grad)
-        hipLaunchKernelGGL((sym_merge_kernel<NACC>), grid, dim3(256), 0, st, part, colpart, first, sc, nR, Fp, acc64);
+        hipLaunchKernelGGL((sym_merge_kernel<NSYM>), grid, dim3(256), 0, st, part, colpart, first, sc, nR, Fp, acc64);
     else
         hipLaunchKernelGGL((sym_merge_kernel<1>), grid, dim3(256), 0, st, part, colpart, first, sc, nR, Fp, acc64);
     return hipGetLastError();

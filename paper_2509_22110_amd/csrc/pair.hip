@@ -179,13 +179,16 @@ __device__ __forceinline__ void pair_update_gen(const ColRec& cr, int4 cv, float
 
 // One chunk of CHUNK columns for the wave's RPL x 64 rows: plain FP32 sums over the chunk, then a
 // Kahan fold into the rows' (hi, lo) accumulators.
-template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false>
+// FOLDV (gradient only): fold the chunk's sums into the symmetric kernel's 8-sum layout K, S0,
+// Sd, V = Sn - 2 Sdd (see pair_sym_kernel) instead of the 11 row sums.
+template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false, bool FOLDV = false, int NH>
 __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ tc, const int4* __restrict__ tv,
                                            const float (&rx)[RPL], const float (&ry)[RPL],
                                            const float (&rz)[RPL], const float (&nx)[RPL],
                                            const float (&ny)[RPL], const float (&nz)[RPL],
-                                           const int (&rv)[RPL][3], float (&hi)[RPL][NACC],
-                                           float (&lo)[RPL][NACC]) {
+                                           const int (&rv)[RPL][3], float (&hi)[RPL][NH],
+                                           float (&lo)[RPL][NH]) {
+    static_assert(NH == ((FOLDV && GRAD) ? 8 : NACC) || !GRAD, "row sum layout");
     constexpr int NA = GRAD ? NACC : 1;
     float acc[RPL][NA];
 #pragma unroll
@@ -207,9 +210,17 @@ __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ 
                                                  rv[r][1], rv[r][2], acc[r]);
     }
 #pragma unroll
-    for (int r = 0; r < RPL; ++r)
+    for (int r = 0; r < RPL; ++r) {
+        if constexpr (FOLDV && GRAD) {
 #pragma unroll
-        for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
+            for (int k = 0; k < 5; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) kahan_fold(fmaf(-2.f, acc[r][5 + d], acc[r][8 + d]), hi[r][5 + d], lo[r][5 + d]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
+        }
+    }
 }
 
 // grid: W work-groups of PAIR_NW waves.  part layout: [W * maxseg segments][2 * NA][ROWB] FP32;
@@ -337,6 +348,9 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __re
 // i.e. exactly what T's own row pass over S would add.  The energy-only kernel credits a_T t^q to
 // S and a_S tau^q to T (each ordered pair's forward kernel, as the row-only energy kernel sums).
 // The shared part of a pair (d, w, t, tau and their powers) is computed once instead of twice.
+// Sn and Sdd only reach the gradient through dE/dc = a (q (n S0 + Sn) - p Sdd), so each face keeps
+// 8 sums, K, S0, Sd and V = Sn - (p/q) Sdd = Sn - 2 Sdd, and the merge hands the finalize
+// Sn = V, Sdd = 0: three fewer column sums to carry through the wave per step.
 //
 // Layout of a symmetric unit on one wave: the 128 rows stay in the lanes (2 per lane) as in the
 // row-only kernel; the unit's SYM_COLS columns are held one per lane too (SYM_COLS = 64: one per
@@ -384,7 +398,7 @@ __device__ __forceinline__ SymPair sym_pair(const ColRec& cr, int4 cv, float rx,
     return P;
 }
 
-// the row face's share, weight a_T = cr.a
+// the row face's share, weight a_T = cr.a (cr.wv = -2 a_T for the Sdd part of V)
 template <bool GRAD>
 __device__ __forceinline__ void sym_row(const ColRec& cr, const SymPair& P, float* acc) {
     acc[0] = fmaf(cr.a, P.e, acc[0]);
@@ -394,14 +408,11 @@ __device__ __forceinline__ void sym_row(const ColRec& cr, const SymPair& P, floa
         acc[2] = fmaf(s, P.dx, acc[2]);
         acc[3] = fmaf(s, P.dy, acc[3]);
         acc[4] = fmaf(s, P.dz, acc[4]);
-        float m = cr.a * P.we;
-        acc[5] = fmaf(m, P.dx, acc[5]);
-        acc[6] = fmaf(m, P.dy, acc[6]);
-        acc[7] = fmaf(m, P.dz, acc[7]);
+        float m2 = cr.wv * P.we;
         float sp = cr.a * P.U1;
-        acc[8] = fmaf(sp, cr.nx, acc[8]);
-        acc[9] = fmaf(sp, cr.ny, acc[9]);
-        acc[10] = fmaf(sp, cr.nz, acc[10]);
+        acc[5] = fmaf(sp, cr.nx, fmaf(m2, P.dx, acc[5]));
+        acc[6] = fmaf(sp, cr.ny, fmaf(m2, P.dy, acc[6]));
+        acc[7] = fmaf(sp, cr.nz, fmaf(m2, P.dz, acc[7]));
     }
 }
 
@@ -413,39 +424,39 @@ __device__ __forceinline__ float rot_add(float x, float y) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false)) + y;
 }
 
-// The column face's share of the step's two pairs (rows 0 and 1 of the lane, weights a_S), added
-// to the column sums after moving them one lane down (ROT; the first step has nothing to move).
+// The column face's share of the step's two pairs (rows 0 and 1 of the lane, weights a_S; aS2 =
+// 2 a_S), added to the column sums after moving them one lane down (ROT; the first step has
+// nothing to move).  For the column, Sn -= a_S T1 n_S and Sdd -= a_S w e d, so V gains
+// -a_S T1 n_S + 2 a_S w e d.
 template <bool GRAD, bool ROT>
-__device__ __forceinline__ void sym_col(const SymPair& P0, const SymPair& P1, float aS0, float aS1, float nx0,
-                                        float ny0, float nz0, float nx1, float ny1, float nz1, float* ca) {
-    float c[GRAD ? NACC : 1];
+__device__ __forceinline__ void sym_col(const SymPair& P0, const SymPair& P1, float aS0, float aS1, float aS20,
+                                        float aS21, float nx0, float ny0, float nz0, float nx1, float ny1, float nz1,
+                                        float* ca) {
+    float c[GRAD ? NSYM : 1];
     if constexpr (!GRAD) {
         c[0] = fmaf(aS1, P1.we, aS0 * P0.we);
     } else {
         c[0] = fmaf(aS1, P1.e, aS0 * P0.e);
         const float y0 = aS0 * P0.U1, y1 = aS1 * P1.U1;
-        const float z0 = aS0 * P0.we, z1 = aS1 * P1.we;
+        const float z0 = aS20 * P0.we, z1 = aS21 * P1.we;
         const float x0 = aS0 * P0.T1, x1 = aS1 * P1.T1;
         c[1] = -y0 - y1;
         c[2] = fmaf(y1, P1.dx, y0 * P0.dx);
         c[3] = fmaf(y1, P1.dy, y0 * P0.dy);
         c[4] = fmaf(y1, P1.dz, y0 * P0.dz);
-        c[5] = fmaf(-z1, P1.dx, -z0 * P0.dx);
-        c[6] = fmaf(-z1, P1.dy, -z0 * P0.dy);
-        c[7] = fmaf(-z1, P1.dz, -z0 * P0.dz);
-        c[8] = fmaf(-x1, nx1, -x0 * nx0);
-        c[9] = fmaf(-x1, ny1, -x0 * ny0);
-        c[10] = fmaf(-x1, nz1, -x0 * nz0);
+        c[5] = fmaf(-x1, nx1, fmaf(z1, P1.dx, fmaf(-x0, nx0, z0 * P0.dx)));
+        c[6] = fmaf(-x1, ny1, fmaf(z1, P1.dy, fmaf(-x0, ny0, z0 * P0.dy)));
+        c[7] = fmaf(-x1, nz1, fmaf(z1, P1.dz, fmaf(-x0, nz0, z0 * P0.dz)));
     }
 #pragma unroll
-    for (int k = 0; k < (GRAD ? NACC : 1); ++k) ca[k] = ROT ? rot_add(ca[k], c[k]) : c[k];
+    for (int k = 0; k < (GRAD ? NSYM : 1); ++k) ca[k] = ROT ? rot_add(ca[k], c[k]) : c[k];
 }
 
 template <bool GRAD, bool MASK, bool ROT>
 __device__ __forceinline__ void sym_step(const ColRec& cr, int4 cv, const float (&rx)[RPL], const float (&ry)[RPL],
                                          const float (&rz)[RPL], const float (&nx)[RPL], const float (&ny)[RPL],
-                                         const float (&nz)[RPL], const float (&aS)[RPL], const int (&rv)[RPL][3],
-                                         float (&acc)[RPL][GRAD ? NACC : 1], float* ca) {
+                                         const float (&nz)[RPL], const float (&aS)[RPL], const float (&aS2)[RPL],
+                                         const int (&rv)[RPL][3], float (&acc)[RPL][GRAD ? NSYM : 1], float* ca) {
     static_assert(RPL == 2, "the column share is written for two rows per lane");
     const SymPair P0 = sym_pair<GRAD, MASK>(cr, cv, rx[0], ry[0], rz[0], nx[0], ny[0], nz[0], rv[0][0], rv[0][1],
                                             rv[0][2]);
@@ -453,7 +464,7 @@ __device__ __forceinline__ void sym_step(const ColRec& cr, int4 cv, const float 
                                             rv[1][2]);
     sym_row<GRAD>(cr, P0, acc[0]);
     sym_row<GRAD>(cr, P1, acc[1]);
-    sym_col<GRAD, ROT>(P0, P1, aS[0], aS[1], nx[0], ny[0], nz[0], nx[1], ny[1], nz[1], ca);
+    sym_col<GRAD, ROT>(P0, P1, aS[0], aS[1], aS2[0], aS2[1], nx[0], ny[0], nz[0], nx[1], ny[1], nz[1], ca);
 }
 
 // One symmetric unit for the wave: its rows against the SYM_COLS columns staged in LDS (lcol, lv).
@@ -464,9 +475,9 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
                                                const float (&ry)[RPL], const float (&rz)[RPL],
                                                const float (&nx)[RPL], const float (&ny)[RPL],
                                                const float (&nz)[RPL], const float (&aS)[RPL],
-                                               const int (&rv)[RPL][3], float (&hi)[RPL][NACC],
-                                               float (&lo)[RPL][NACC], float* ca) {
-    constexpr int NA = GRAD ? NACC : 1;
+                                               const float (&aS2)[RPL], const int (&rv)[RPL][3],
+                                               float (&hi)[RPL][NSYM], float (&lo)[RPL][NSYM], float* ca) {
+    constexpr int NA = GRAD ? NSYM : 1;
     const int sl = threadIdx.x & (SYM_COLS - 1);
     float acc[RPL][NA];
 #pragma unroll
@@ -476,7 +487,7 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
     {
         const ColRec cr = lcol[sl];
         const int4 cv = MASK ? lv[sl] : make_int4(0, 0, 0, 0);
-        sym_step<GRAD, MASK, false>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+        sym_step<GRAD, MASK, false>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
     }
     // steps 1 .. SYM_COLS - 1, two per iteration (SYM_COLS - 1 is odd: the last one after the loop)
 #pragma unroll 1
@@ -486,14 +497,14 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
             const int col = (sl + j + h) & (SYM_COLS - 1);
             const ColRec cr = lcol[col];
             const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
-            sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+            sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
         }
     }
     {
         const int col = (sl + SYM_COLS - 1) & (SYM_COLS - 1);
         const ColRec cr = lcol[col];
         const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
-        sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, rv, acc, ca);
+        sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
@@ -502,10 +513,9 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
 }
 
 // LDS of the symmetric kernel's work-group: two column buffers (records, vertex ids) and two column
-// reduction buffers [SYM_NW][WAVE / SYM_COLS][SYM_COLS][CS] (CS = 12 with the gradient: 11 sums,
-// padded).
+// reduction buffers [SYM_NW][WAVE / SYM_COLS][SYM_COLS][CS] (CS = NSYM with the gradient).
 template <bool GRAD>
-constexpr int sym_cs() { return GRAD ? 12 : 1; }
+constexpr int sym_cs() { return GRAD ? NSYM : 1; }
 template <bool GRAD>
 constexpr size_t sym_lds_floats() {
     return 2 * (size_t)SYM_COLS * (8 + 4) + 2 * (size_t)SYM_NW * WAVE * sym_cs<GRAD>();
@@ -526,7 +536,7 @@ __global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* _
                                                                  const uint32_t* __restrict__ touch, int touch_words,
                                                                  SymSched sc, float* __restrict__ part,
                                                                  float* __restrict__ colpart, int* __restrict__ first) {
-    constexpr int NA = GRAD ? NACC : 1;
+    constexpr int NA = GRAD ? NSYM : 1;
     constexpr int CS = sym_cs<GRAD>();
     extern __shared__ float lds[];
     ColRec* lcol = reinterpret_cast<ColRec*>(lds);                 // [2][SYM_COLS]
@@ -585,9 +595,9 @@ __global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* _
     while (u < u1) {  // uniform over the work-group
         const int rb = I * SYM_NW + wave;
         double cxd[RPL], cyd[RPL], czd[RPL];
-        float nx[RPL], ny[RPL], nz[RPL], aS[RPL];
+        float nx[RPL], ny[RPL], nz[RPL], aS[RPL], aS2[RPL];
         int rv[RPL][3];
-        float hi[RPL][NACC], lo[RPL][NACC];
+        float hi[RPL][NSYM], lo[RPL][NSYM];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = rb * ROWB + r * WAVE + lane;
@@ -595,11 +605,11 @@ __global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* _
             cyd[r] = c64[3 * (size_t)i + 1];
             czd[r] = c64[3 * (size_t)i + 2];
             const ColRec me = cols[i];
-            nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz; aS[r] = me.a;
+            nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz; aS[r] = me.a; aS2[r] = -me.wv;
             const int4 v = colv[i];
             rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
 #pragma unroll
-            for (int a = 0; a < NACC; ++a) { hi[r][a] = 0.f; lo[r][a] = 0.f; }
+            for (int a = 0; a < NSYM; ++a) { hi[r][a] = 0.f; lo[r][a] = 0.f; }
         }
         const uint32_t* my_touch = touch + (size_t)rb * touch_words;
         const int64_t kn = sc.ua() - SymSched::UD * I;  // units of super block I
@@ -623,8 +633,8 @@ __global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* _
             if (k < SBC) {
                 const ColRec* tc = cols + (size_t)J * CHUNK;
                 const int4* tv = colv + (size_t)J * CHUNK;
-                if (masked) chunk_pass<6, GRAD, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
-                else chunk_pass<6, GRAD, false>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                if (masked) chunk_pass<6, GRAD, true, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                else chunk_pass<6, GRAD, false, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
                 if (next_sym) {
                     stage_store(nsym & 1, pre);
                     __syncthreads();
@@ -634,10 +644,10 @@ __global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* _
                 float ca[NA];
                 if (masked)
                     sym_chunk_pass<GRAD, true>(lcol + b * SYM_COLS, lvid + b * SYM_COLS, rx, ry, rz, nx, ny, nz, aS,
-                                               rv, hi, lo, ca);
+                                               aS2, rv, hi, lo, ca);
                 else
                     sym_chunk_pass<GRAD, false>(lcol + b * SYM_COLS, lvid + b * SYM_COLS, rx, ry, rz, nx, ny, nz,
-                                                aS, rv, hi, lo, ca);
+                                                aS, aS2, rv, hi, lo, ca);
                 // lane l holds column (l + SYM_COLS - 1) mod SYM_COLS of its group of lanes l / SYM_COLS
                 const int mycol = (lane + SYM_COLS - 1) & (SYM_COLS - 1);
                 float* mine = red + (((size_t)(b * SYM_NW + wave) * (WAVE / SYM_COLS) + lane / SYM_COLS) * SYM_COLS +
@@ -698,10 +708,10 @@ SymSched make_sym_sched(int64_t Fp, int W) {
 }
 
 int64_t sym_part_floats(const SymSched& sc, bool grad) {
-    return ((int64_t)sc.W + sc.nsb) * SYM_NW * (grad ? NACC : 1) * ROWB;
+    return ((int64_t)sc.W + sc.nsb) * SYM_NW * (grad ? NSYM : 1) * ROWB;
 }
 int64_t sym_colpart_floats(const SymSched& sc, bool grad) {
-    return sc.base_sym(sc.nsb) * (grad ? NACC : 1) * SYM_COLS;
+    return sc.base_sym(sc.nsb) * (grad ? NSYM : 1) * SYM_COLS;
 }
 
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,

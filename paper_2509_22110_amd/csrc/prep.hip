@@ -232,7 +232,7 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
             for (int k = 0; k < 3; ++k) atomicAdd(&cnt[v[k]], 1u);
         r.a = (float)a;
         r.nx = (float)n[0]; r.ny = (float)n[1]; r.nz = (float)n[2];
-        r.pad = 0.f;
+        r.wv = -2.f * r.a;
         colv[i] = ok ? make_int4(v[0], v[1], v[2], pt) : make_int4(-3, -3, -3, 0);
         c64[3 * i + 0] = c[0]; c64[3 * i + 1] = c[1]; c64[3 * i + 2] = c[2];
         geo[5 * i + 0] = a; geo[5 * i + 1] = wn;
@@ -240,7 +240,7 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
     } else {
         // padding: far from everything, zero area; row padding ids differ from column ids
         r.cx = PAD_COORD; r.cy = PAD_COORD; r.cz = PAD_COORD; r.a = 0.f;
-        r.nx = 0.f; r.ny = 0.f; r.nz = 0.f; r.pad = 0.f;
+        r.nx = 0.f; r.ny = 0.f; r.nz = 0.f; r.wv = 0.f;
         colv[i] = make_int4(-1, -1, -1, 0);
         c64[3 * i + 0] = o[0] + PAD_COORD;
         c64[3 * i + 1] = o[1] + PAD_COORD;
