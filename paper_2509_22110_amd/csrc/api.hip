@@ -341,14 +341,15 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
     P.sym = false;
     if (sym) {
         const int64_t Fs = round_up(P.nR, SB);
-        // work-groups: the resident count, times up to 4 when there are enough units (the
-        // hardware then refills the slots of early finishers, which evens out the finish times)
+        // work-groups: 2 to 8 times the resident count, one step per 16 units a resident slot
+        // would get (the hardware refills the slots of early finishers, which evens out the
+        // finish times; more work-groups add row segments for the merge to read)
         int W = ctx->resident_sym[grad ? 1 : 0];
         if (ctx->target_waves > 0) {
             W = (int)ctx->target_waves;
         } else {
             const int64_t units = make_sym_sched(Fs, 1).U;
-            W *= (int)std::max<int64_t>(1, std::min<int64_t>(4, units / ((int64_t)W * 32)));
+            W *= (int)std::max<int64_t>(2, std::min<int64_t>(8, units / ((int64_t)W * 16)));
         }
         const SymSched t = make_sym_sched(Fs, W);
         if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_MAX_COLPART_BYTES) {

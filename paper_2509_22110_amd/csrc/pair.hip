@@ -229,7 +229,9 @@ __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ 
 // Rows come from (rcols, rc64, rcolv), columns from (ccols, ccolv, corg): the same arrays for the
 // self energy, the confining surface's for CONF (no exclusion map then).
 template <int Q, bool GRAD, bool CONF = false, bool GEN = false>
-__global__ __launch_bounds__(WAVE * PAIR_NW) void pair_kernel(const ColRec* __restrict__ rcols,
+// at least 4 waves per SIMD (128 VGPRs): the few values the generic kernel then keeps in scratch are
+// touched once per chunk, outside the column loop
+__global__ __launch_bounds__(WAVE * PAIR_NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel(const ColRec* __restrict__ rcols,
                                                               const double* __restrict__ rc64,
                                                               const int4* __restrict__ rcolv,
                                                               const ColRec* __restrict__ ccols,
@@ -529,7 +531,10 @@ constexpr size_t sym_lds_floats() {
 // over the waves and rows of lanes in a fixed order.
 // first[w]: the first super block of work-group w (INT32_MAX if its range is empty).
 template <bool GRAD>
-__global__ __launch_bounds__(WAVE * SYM_NW) void pair_sym_kernel(const ColRec* __restrict__ cols,
+// At least 4 waves per SIMD (128 VGPRs, against 165 unconstrained): the compiler then keeps a few
+// long-lived values (FP64 row centroids, vertex ids) in scratch, reloaded once per super block,
+// and the column loop is unchanged.
+__global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_kernel(const ColRec* __restrict__ cols,
                                                                  const double* __restrict__ c64,
                                                                  const int4* __restrict__ colv,
                                                                  const double* __restrict__ corg,
