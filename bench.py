@@ -44,15 +44,16 @@ FLOP_PER_PAIR = 55
 EXEC_FLOP_PER_PAIR_SYM = 40.5
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per face of the finalize + gather passes: finalize reads one segment of
-# row sums (11 x (hi, lo) FP32 = 88 B), {a, |w|, n} (40 B), vertex ids (16 B) and its three vertices
-# (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices (12 B) and
-# the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
-FINALIZE_GATHER_BYTES_PER_FACE = 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
+# algorithmic HBM bytes per face of the passes after the symmetric pair kernel: the merge reads one
+# row segment (8 FP32 sums = 32 B) plus the column partials (counted apart) and writes the 11 FP64
+# row sums (88 B); the finalize reads them (88 B), {a, |w|, n} (40 B), vertex ids (16 B) and its
+# three vertices (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices
+# (12 B) and the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
+MERGE_FINALIZE_GATHER_BYTES_PER_FACE = 32 + 88 + 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
 SYM_MAX_COLPART_BYTES = 6 << 30
 
 
-def sym_colpart_bytes(nF, na=11):
+def sym_colpart_bytes(nF, na=8):
     """Bytes of the symmetric pair kernel's column partial sums, which the finalize reads once: one
     FP32 sum per (symmetric unit, column, accumulator); super blocks of 512 faces, units of 64
     columns, the 8 chunks of a super block's own faces excluded.  0 when the library takes the
@@ -143,8 +144,8 @@ def farfield_leg(args, T, M, torch, dev):
     ctx.set_option(T.OPT_KERNEL_TIMING, 0)
     fg_ms /= max(fg_n, 1)
     cp_bytes = sym_colpart_bytes(cfg.nF)
-    fg_bytes = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF + cp_bytes
-    fg = {"kernels": "finalize_kernel<true> + vertex_gather", "bound": "hbm", "ms": round(fg_ms, 4),
+    fg_bytes = MERGE_FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF + cp_bytes
+    fg = {"kernels": "sym_merge_kernel + finalize_kernel<true> + vertex_gather", "bound": "hbm", "ms": round(fg_ms, 4),
           "algorithmic_bytes": fg_bytes, "column_partial_bytes": cp_bytes, "achieved": round(fg_bytes / (fg_ms * 1e-3) / 1e9, 1),
           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fg_bytes / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
