@@ -68,6 +68,10 @@ def _load():
         lib.tpeo_gradient_quad.restype = I32
         lib.tpeo_quad_rule.argtypes = [I32, P, P]
         lib.tpeo_quad_rule.restype = I32
+        lib.tpeo_gradient_p3.argtypes = [P, I64, P, I64, D, D, D, I32, I32, P, P]
+        lib.tpeo_gradient_p3.restype = I32
+        lib.tpeo_p3_map.argtypes = [P, D, D, P, P, P]
+        lib.tpeo_p3_map.restype = I32
         lib.tpeo_pair_count.argtypes = [P, I64]
         lib.tpeo_pair_count.restype = I64
         lib.tpeo_num_threads.argtypes = [I32]
@@ -185,3 +189,31 @@ def gradient_quad(X, F, rule, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=Tr
         raise OracleError(rc)
     return float(E[0]), G
 
+
+def _prep10(X, F10):
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    F10 = np.ascontiguousarray(np.asarray(F10, dtype=np.int32))
+    if X.ndim != 2 or X.shape[1] != 3 or F10.ndim != 2 or F10.shape[1] != 10:
+        raise ValueError("expected X [V, 3] and F10 [nF, 10]")
+    return X, F10
+
+
+def p3_map(P, s, t):
+    """(x, x_s, x_t) of the cubic element with nodes P [10, 3] at reference point (s, t)."""
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(10, 3))
+    x, xs, xt = np.zeros(3), np.zeros(3), np.zeros(3)
+    _load().tpeo_p3_map(P.ctypes.data, float(s), float(t), x.ctypes.data, xs.ctypes.data, xt.ctypes.data)
+    return x, xs, xt
+
+
+def gradient_p3(X, F10, rule, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=True):
+    """(E, dE/dX) on curved cubic elements (X: all nodes [V, 3]; F10: [nF, 10] node ids, corners
+    first) with the `rule`-point quadrature on both integrals (G is None if not want_grad)."""
+    X, F10 = _prep10(X, F10)
+    E = np.zeros(1)
+    G = np.zeros_like(X) if want_grad else None
+    rc = _load().tpeo_gradient_p3(X.ctypes.data, X.shape[0], F10.ctypes.data, F10.shape[0], q, p, scale, int(rule),
+                                  nthreads, E.ctypes.data, G.ctypes.data if want_grad else None)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G

@@ -590,3 +590,197 @@ int tpeo_gradient_quad(const double* X, int64_t V, const int32_t* F, int64_t nF,
     return err;
 }
 
+
+/*
+ * Curved cubic (P3) triangles (the paper's surface S_h^3, Sec. 3.1; its full integration scheme
+ * evaluates positions, area elements and normals at the quadrature points of the curved elements,
+ * Sec. 3.2).  Element f has 10 nodes F10[10 f + 0..9] at the barycentric lattice points
+ *     0: (1,0,0)      1: (0,1,0)      2: (0,0,1)                      (corners)
+ *     3: (2/3,1/3,0)  4: (1/3,2/3,0)                                   (edge 0-1)
+ *     5: (0,2/3,1/3)  6: (0,1/3,2/3)                                   (edge 1-2)
+ *     7: (1/3,0,2/3)  8: (2/3,0,1/3)                                   (edge 2-0)
+ *     9: (1/3,1/3,1/3)                                                 (centre)
+ * and the cubic Lagrange basis on barycentric coordinates (l0, l1, l2):
+ *     corner i:                   phi = l_i (3 l_i - 1)(3 l_i - 2) / 2
+ *     edge node (2/3 on i, 1/3 on j): phi = 9/2 l_i l_j (3 l_i - 1)
+ *     centre:                     phi = 27 l0 l1 l2.
+ * With reference coordinates (s, t) = (l1, l2), l0 = 1 - s - t, the element maps
+ *     x(s, t) = sum_k phi_k X_k,   J = x_s x x_t,   n = J / |J|,
+ * and quadrature point p of a rule (barycentric b_p, weight W_p, sum W_p = 1) is a record at
+ * x(b_p) with normal n(b_p) and weight alpha_p = W_p |J(b_p)| / 2 (for straight elements:
+ * W_p times the area).  The energy is that of the flat multi-point scheme over these records:
+ *
+ *   E(X) = scale * sum_S sum_{T : S, T share no corner node} sum_p sum_r alpha_Sp alpha_Tr
+ *                  |n_Sp . (x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p .
+ *
+ * The gradient follows the chain rule through the record: with g = dE/dalpha, gn = dE/dn and
+ * gx = dE/dx of a record, gJ = g (W_p / 2) n + (I - n n^T) gn / |J|, and node k receives
+ *     phi_k gx + (d phi_k / ds) (x_t x gJ) + (d phi_k / dt) (gJ x x_s).
+ */
+
+/* basis values and derivatives with respect to (s, t) at barycentric (l0, l1, l2) */
+static void p3_basis(const double* l, double* phi, double* ds, double* dt) {
+    static const int EI[6] = {0, 1, 1, 2, 2, 0}, EJ[6] = {1, 0, 2, 1, 0, 2};
+    double dl[10][3];
+    for (int i = 0; i < 3; ++i) {
+        phi[i] = 0.5 * l[i] * (3.0 * l[i] - 1.0) * (3.0 * l[i] - 2.0);
+        for (int m = 0; m < 3; ++m) dl[i][m] = 0.0;
+        dl[i][i] = 0.5 * (27.0 * l[i] * l[i] - 18.0 * l[i] + 2.0);
+    }
+    for (int e = 0; e < 6; ++e) {
+        const int i = EI[e], j = EJ[e], k = 3 + e;
+        phi[k] = 4.5 * l[i] * l[j] * (3.0 * l[i] - 1.0);
+        for (int m = 0; m < 3; ++m) dl[k][m] = 0.0;
+        dl[k][i] = 4.5 * l[j] * (6.0 * l[i] - 1.0);
+        dl[k][j] = 4.5 * l[i] * (3.0 * l[i] - 1.0);
+    }
+    phi[9] = 27.0 * l[0] * l[1] * l[2];
+    dl[9][0] = 27.0 * l[1] * l[2];
+    dl[9][1] = 27.0 * l[0] * l[2];
+    dl[9][2] = 27.0 * l[0] * l[1];
+    /* l0 = 1 - s - t, l1 = s, l2 = t */
+    for (int k = 0; k < 10; ++k) {
+        ds[k] = dl[k][1] - dl[k][0];
+        dt[k] = dl[k][2] - dl[k][0];
+    }
+}
+
+/* x, x_s, x_t of the element with nodes P (10 x 3) at barycentric l */
+static void p3_eval(const double* P, const double* l, double* x, double* xs, double* xt) {
+    double phi[10], ds[10], dt[10];
+    p3_basis(l, phi, ds, dt);
+    for (int d = 0; d < 3; ++d) {
+        x[d] = xs[d] = xt[d] = 0.0;
+        for (int k = 0; k < 10; ++k) {
+            x[d] += phi[k] * P[3 * k + d];
+            xs[d] += ds[k] * P[3 * k + d];
+            xt[d] += dt[k] * P[3 * k + d];
+        }
+    }
+}
+
+int tpeo_p3_map(const double* P, double s, double t, double* x, double* xs, double* xt) {
+    const double l[3] = {1.0 - s - t, s, t};
+    p3_eval(P, l, x, xs, xt);
+    return OK;
+}
+
+static int share_corner10(const int32_t* F, int64_t s, int64_t t) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (F[10 * s + i] == F[10 * t + j]) return 1;
+    return 0;
+}
+
+typedef struct { double x[3], xs[3], xt[3], n[3], Jn, alpha, W; const double* l; } p3rec;
+
+int tpeo_gradient_p3(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p, double scale,
+                     int rule, int nthreads, double* E_out, double* G_out) {
+    double b[6][3], w[6];
+    const int nq = quad_rule(rule, b, w);
+    if (!nq) return EINVAL_;
+    if (!X || !F || V <= 0 || nF <= 0 || !(q >= 2.0) || !(p > q)) return EINVAL_;
+    for (int64_t i = 0; i < 10 * nF; ++i)
+        if (F[i] < 0 || F[i] >= V) return EINVAL_;
+    for (int64_t i = 0; i < 3 * V; ++i)
+        if (!isfinite(X[i])) return ENONFIN;
+    p3rec* R = (p3rec*)malloc(sizeof(p3rec) * (size_t)nF * nq);
+    if (!R) return EINVAL_;
+    for (int64_t f = 0; f < nF; ++f) {
+        double P[30];
+        for (int k = 0; k < 10; ++k)
+            for (int d = 0; d < 3; ++d) P[3 * k + d] = X[3 * (int64_t)F[10 * f + k] + d];
+        for (int k = 0; k < nq; ++k) {
+            p3rec* r = &R[f * nq + k];
+            p3_eval(P, b[k], r->x, r->xs, r->xt);
+            double J[3];
+            cross3(r->xs, r->xt, J);
+            r->Jn = sqrt(dot3(J, J));
+            if (!(r->Jn > 1e-300)) { free(R); return EDEGEN; }
+            for (int d = 0; d < 3; ++d) r->n[d] = J[d] / r->Jn;
+            r->W = w[k];
+            r->alpha = 0.5 * w[k] * r->Jn;
+            r->l = b[k];
+        }
+    }
+    int nt = nthreads_of(nthreads);
+    nsum* GV = G_out ? (nsum*)calloc((size_t)nt * (size_t)V * 3, sizeof(nsum)) : NULL;
+    nsum* part = (nsum*)calloc((size_t)nt, sizeof(nsum));
+    if ((G_out && !GV) || !part) { free(R); free(GV); free(part); return EINVAL_; }
+    int err = OK;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        nsum* myG = GV ? GV + (size_t)tid * (size_t)V * 3 : NULL;
+        nsum acc = {0.0, 0.0};
+        int lerr = OK;
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < nF; ++s) {
+            for (int64_t t = 0; t < nF; ++t) {
+                if (share_corner10(F, s, t)) continue;
+                for (int ks = 0; ks < nq; ++ks)
+                    for (int kt = 0; kt < nq; ++kt) {
+                        const p3rec* rs = &R[s * nq + ks];
+                        const p3rec* rt = &R[t * nq + kt];
+                        face_t S, T;
+                        memset(&S, 0, sizeof S);
+                        memset(&T, 0, sizeof T);
+                        for (int d = 0; d < 3; ++d) {
+                            S.c[d] = rs->x[d]; S.n[d] = rs->n[d];
+                            T.c[d] = rt->x[d]; T.n[d] = rt->n[d];
+                        }
+                        pairval pv;
+                        if (pair_eval(&S, &T, q, p, myG != NULL, &pv)) { lerr = ENONFIN; continue; }
+                        const double aa = rs->alpha * rt->alpha;
+                        nadd(&acc, aa * pv.k);
+                        if (!myG) continue;
+                        /* dE/dx, dE/dn, dE/dalpha of both records, then to their nodes */
+                        for (int side = 0; side < 2; ++side) {
+                            const p3rec* r = side ? rt : rs;
+                            const int64_t f = side ? t : s;
+                            double gx[3], gn[3], gJ[3];
+                            const double g = scale * (side ? rs->alpha : rt->alpha) * pv.k;
+                            for (int i = 0; i < 3; ++i) {
+                                gx[i] = (side ? -1.0 : 1.0) * scale * aa * pv.dkdd[i];
+                                gn[i] = side ? 0.0 : scale * aa * pv.dkdn[i];
+                            }
+                            const double ngn = dot3(r->n, gn);
+                            for (int i = 0; i < 3; ++i)
+                                gJ[i] = g * 0.5 * r->W * r->n[i] + (gn[i] - ngn * r->n[i]) / r->Jn;
+                            double phi[10], ds[10], dt[10], cs[3], ct[3];
+                            p3_basis(r->l, phi, ds, dt);
+                            cross3(r->xt, gJ, cs);   /* x_t x gJ: the d/dx_s direction */
+                            cross3(gJ, r->xs, ct);   /* gJ x x_s: the d/dx_t direction */
+                            for (int k = 0; k < 10; ++k) {
+                                const int64_t v = F[10 * f + k];
+                                for (int d = 0; d < 3; ++d)
+                                    nadd(&myG[3 * v + d], phi[k] * gx[d] + ds[k] * cs[d] + dt[k] * ct[d]);
+                            }
+                        }
+                    }
+            }
+        }
+        part[tid] = acc;
+        if (lerr) {
+#pragma omp critical
+            err = lerr;
+        }
+    }
+    nsum tot = {0.0, 0.0};
+    for (int i = 0; i < nt; ++i) { nadd(&tot, part[i].s); nadd(&tot, part[i].c); }
+    if (E_out) *E_out = err ? INFINITY : scale * nval(&tot);
+    if (G_out)
+        for (int64_t i = 0; i < V * 3; ++i) {
+            nsum g = {0.0, 0.0};
+            for (int th = 0; th < nt; ++th) {
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].s);
+                nadd(&g, GV[(size_t)th * (size_t)V * 3 + (size_t)i].c);
+            }
+            G_out[i] = nval(&g);
+        }
+    free(GV); free(part); free(R);
+    return err;
+}

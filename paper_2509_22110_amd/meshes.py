@@ -20,6 +20,7 @@ import numpy as np
 __all__ = [
     "icosphere", "radial_jitter", "real_sph_harm", "sh_deform", "sh_deform_amplitude",
     "bump", "random_rotation", "make_config", "CONFIGS", "ConfigMesh", "n_faces", "n_vertices",
+    "P3_LATTICE", "p3_lattice", "p3_sphere",
 ]
 
 
@@ -290,6 +291,65 @@ def _c5(seed, level=8):
 
 
 CONFIGS = {"C1": _c1, "C2": _c2, "C3": _c3, "C4": _c4, "C5": _c5}
+
+
+# ---- curved cubic (P3) elements -----------------------------------------------------------------
+# An element has 10 nodes at the barycentric lattice points of its flat parent (v0, v1, v2):
+#   0, 1, 2: the corners; 3, 4: (2/3, 1/3, 0), (1/3, 2/3, 0); 5, 6: (0, 2/3, 1/3), (0, 1/3, 2/3);
+#   7, 8: (1/3, 0, 2/3), (2/3, 0, 1/3); 9: (1/3, 1/3, 1/3).
+# Neighbouring elements share their corner and edge nodes.
+
+P3_LATTICE = np.array([[3, 0, 0], [0, 3, 0], [0, 0, 3],
+                       [2, 1, 0], [1, 2, 0], [0, 2, 1], [0, 1, 2], [1, 0, 2], [2, 0, 1],
+                       [1, 1, 1]], dtype=np.float64) / 3.0
+
+
+def p3_lattice(X: np.ndarray, F: np.ndarray):
+    """(X10, F10): the flat mesh (X, F) as straight cubic elements.  The first V nodes are the
+    vertices of X (same indices), then two nodes per undirected edge, then one per face; every
+    node sits at its lattice point, so the cubic map of each element is the flat triangle."""
+    X = np.asarray(X, dtype=np.float64)
+    F = np.asarray(F, dtype=np.int64)
+    V, nF = X.shape[0], F.shape[0]
+    # directed face edges (i -> j) for the three sides 0-1, 1-2, 2-0
+    I = F[:, [0, 1, 2]].reshape(-1)
+    J = F[:, [1, 2, 0]].reshape(-1)
+    lo, hi = np.minimum(I, J), np.maximum(I, J)
+    key = lo * V + hi
+    uk, inv = np.unique(key, return_inverse=True)
+    ne = uk.shape[0]
+    ulo, uhi = uk // V, uk % V
+    # global edge nodes: V + 2 e (2/3 at lo), V + 2 e + 1 (2/3 at hi)
+    near_lo = V + 2 * inv
+    near_hi = near_lo + 1
+    first = np.where(I == lo, near_lo, near_hi)    # the node 2/3 of the way at i
+    second = np.where(I == lo, near_hi, near_lo)   # the node 2/3 of the way at j
+    first, second = first.reshape(nF, 3), second.reshape(nF, 3)
+    F10 = np.empty((nF, 10), dtype=np.int32)
+    F10[:, 0:3] = F
+    F10[:, 3], F10[:, 4] = first[:, 0], second[:, 0]
+    F10[:, 5], F10[:, 6] = first[:, 1], second[:, 1]
+    F10[:, 7], F10[:, 8] = first[:, 2], second[:, 2]
+    F10[:, 9] = V + 2 * ne + np.arange(nF)
+    X10 = np.empty((V + 2 * ne + nF, 3))
+    X10[:V] = X
+    X10[V:V + 2 * ne:2] = (2.0 * X[ulo] + X[uhi]) / 3.0
+    X10[V + 1:V + 2 * ne:2] = (X[ulo] + 2.0 * X[uhi]) / 3.0
+    X10[V + 2 * ne:] = X[F].mean(axis=1)
+    return X10, F10
+
+
+def p3_sphere(level: int, lmin: int = 2, lmax: int = 8, coeff_std: float = 0.05, seed: int = 0):
+    """Curved cubic elements on the deformed sphere r(u) = 1 + sum a_lm Y_lm(u): the lattice nodes
+    of the level-`level` icosphere are moved radially onto that surface (the corners land where
+    ``sh_deform`` puts the vertices of the flat mesh with the same seed).  coeff_std = 0: the
+    unit sphere."""
+    X, F = icosphere(level)
+    X10, F10 = p3_lattice(X, F)
+    if coeff_std == 0.0:
+        return X10 / np.linalg.norm(X10, axis=1, keepdims=True), F10
+    X10, _ = sh_deform(X10, lmin, lmax, coeff_std, seed)
+    return X10, F10
 
 
 def make_config(name: str, seed: int = 0, **kw) -> ConfigMesh:
