@@ -245,6 +245,37 @@ def quad_leg(args, T, M, torch, dev, cfg, X, F):
             "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
 
 
+def p3_leg(args, T, M, torch, dev, cfg, F):
+    """The exact gradient on curved cubic elements of the same sphere (the level-5 icosphere's
+    lattice nodes moved onto the same deformed surface; corners where the flat workload's vertices
+    are), with the 6-point rule on both integrals: records, pair kernel, 10-node finalize and
+    node gather."""
+    X10, F10 = M.p3_sphere(5, 2, 8, 0.05, 0)
+    Xd = torch.from_numpy(X10).to(dev)
+    Fd = torch.from_numpy(F10).to(dev)
+    ctx = T.context(dev)
+    G = torch.empty_like(Xd)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    ctx.set_option(T.OPT_QUADRATURE, 6)
+    try:
+        for _ in range(2):
+            T.gradient_p3(Xd, Fd, out=G, energy_out=E)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T.gradient_p3(Xd, Fd, out=G, energy_out=E)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        ctx.set_option(T.OPT_QUADRATURE, 1)
+    ctx.sync_check()
+    pp = 36 * T.pair_count(F, cfg.V)  # the elements' corners are the flat workload's faces
+    return {"workload": f"{args.config}'s sphere as {F10.shape[0]} curved cubic elements ({X10.shape[0]} nodes), "
+                        "6 quadrature points per element", "point_pairs": pp,
+            "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
+
+
 def exponents_leg(args, T, torch, dev, cfg, X, F, P):
     """The exact gradient with other exponents (the generic pair kernel, -m extra multiplications
     by |d|^2 per pair) on the same workload."""
@@ -365,6 +396,7 @@ def main():
     conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)
     quad = None if args.no_conf else quad_leg(args, T, M, torch, dev, cfg, X, F)
     expo = None if args.no_conf else exponents_leg(args, T, torch, dev, cfg, X, F, P)
+    p3 = None if args.no_conf or args.config != "C2" else p3_leg(args, T, M, torch, dev, cfg, F)
 
     cpu = None
     if not args.no_cpu:
@@ -393,6 +425,7 @@ def main():
         "confinement": conf,
         "quadrature6": quad,
         "other_exponents": expo,
+        "p3_elements": p3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

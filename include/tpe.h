@@ -120,6 +120,30 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
 
+/* The same energy and gradient on curved cubic (P3) elements, the paper's surface S_h^3 (Sec. 3.1)
+ * with its quadrature at the points of the curved elements (Sec. 3.2).
+ * X: device f64 [V][3], all nodes; F10: device i32 [nF][10], the nodes of each element at the
+ * barycentric lattice points m / 3 in the order
+ *     (3,0,0) (0,3,0) (0,0,3) | (2,1,0) (1,2,0) | (0,2,1) (0,1,2) | (1,0,2) (2,0,1) | (1,1,1)
+ * (corners, the two nodes of edges 0-1, 1-2 and 2-0 from the edge's first corner, centre);
+ * neighbouring elements share corner and edge nodes.  The element maps reference point (s, t) to
+ * x(s, t) = sum_k phi_k(1 - s - t, s, t) X_k with the cubic Lagrange basis phi_k.  Quadrature
+ * point b (barycentric) of the rule chosen by TPE_OPT_QUADRATURE (1, 3 or 6 points, on both
+ * integrals) becomes a record at x(b) with normal J / |J| and weight w_b |J| / 2,
+ * J = x_s x x_t, and
+ *     E = scale * sum_S sum_{T : S, T share no corner node} sum_{b, c} weight_Sb weight_Tc
+ *                 |n_Sb . (x_Sb - x_Tc)|^q / |x_Sb - x_Tc|^p.
+ * The gradient is its exact derivative with respect to every node (nodes in no element: zero).
+ * Exponents, options (symmetric kernel, work-group count) and errors as for tpe_energy /
+ * tpe_gradient; a node index outside [0, V) is TPE_ERR_INVALID_ARG, an element whose |J| vanishes
+ * at a quadrature point TPE_ERR_DEGENERATE.  With every node at its lattice point of the flat
+ * triangle of the corners the results are those of tpe_energy / tpe_gradient with the same rule
+ * (the flat gradient being the pull-back through the node positions). */
+int tpe_energy_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
+                  double q, double p, double scale, double* E_dev);
+int tpe_gradient_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
+                    double q, double p, double scale, double* E_dev, double* G_dev);
+
 /* Confinement energy (paper Sec. 2.2.3, eq. (TPConf)) of the moving surface (X, F) against a fixed
  * confining surface (Y, FY), with the same one-point centroid quadrature:
  *     E_conf = scale * sum_{S in F} sum_{T in FY} a_S a_T |n_S . (c_S - c_T)|^q / |c_S - c_T|^p.

@@ -17,7 +17,7 @@ import threading
 
 import torch
 
-__all__ = ["TPEError", "lib", "energy", "gradient", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
+__all__ = ["TPEError", "lib", "energy", "gradient", "energy_p3", "gradient_p3", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
            "tpe_energy",
            "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield", "MLP"]
 
@@ -65,6 +65,8 @@ def lib():
             "tpe_check": ([P], I),
             "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
+            "tpe_energy_p3": ([P, P, I64, P, I64, D, D, D, P], I),
+            "tpe_gradient_p3": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_conf_energy": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P], I),
             "tpe_conf_gradient": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
@@ -161,15 +163,15 @@ def context(device=None) -> _Ctx:
     return c.bind(torch.device("cuda", idx))
 
 
-def _check_mesh(X: torch.Tensor, F: torch.Tensor):
+def _check_mesh(X: torch.Tensor, F: torch.Tensor, nodes: int = 3):
     if not (isinstance(X, torch.Tensor) and isinstance(F, torch.Tensor)):
         raise TypeError("X and F must be tensors")
     if X.device.type != "cuda" or F.device != X.device:
         raise ValueError("X and F must be on the same CUDA/HIP device")
     if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != 3:
         raise ValueError("X must be float64 [V, 3]")
-    if F.dtype != torch.int32 or F.dim() != 2 or F.shape[1] != 3:
-        raise ValueError("F must be int32 [nF, 3]")
+    if F.dtype != torch.int32 or F.dim() != 2 or F.shape[1] != nodes:
+        raise ValueError(f"F must be int32 [nF, {nodes}]")
     return X.contiguous(), F.contiguous()
 
 
@@ -191,6 +193,28 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
     c = context(X.device)
     c.check(lib().tpe_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
                                float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
+    return E, G
+
+
+def energy_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None) -> torch.Tensor:
+    """E on curved cubic elements (X: all nodes float64 [V, 3]; F10: int32 [nF, 10], corners first),
+    with the context's quadrature rule on both integrals."""
+    X, F10 = _check_mesh(X, F10, 10)
+    E = out if out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_energy_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
+                                float(q), float(p), float(scale), E.data_ptr()))
+    return E
+
+
+def gradient_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
+    """(E, dE/dX) on curved cubic elements (see energy_p3)."""
+    X, F10 = _check_mesh(X, F10, 10)
+    G = out if out is not None else torch.empty_like(X)
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_gradient_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
+                                  float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
     return E, G
 
 

@@ -20,9 +20,9 @@
 namespace tpe {
 hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st);
-hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox, uint32_t* flags,
+hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox, uint32_t* flags,
                        hipStream_t st);
-hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, const uint32_t* bbox,
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, int Q, const uint32_t* bbox,
                          int bits, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st);
@@ -33,6 +33,16 @@ hipError_t launch_records(const double* X, int64_t V, const int32_t* F, int64_t 
                           double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st);
 hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* cnt, uint32_t* off, uint32_t* cursor,
                             uint32_t* list, uint32_t* ws, hipStream_t st);
+hipError_t launch_p3_records(const double* X, int64_t V, const int32_t* F10, int64_t nF, int Q, int64_t Fp,
+                             const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
+                             double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st);
+hipError_t launch_p3_nodes(const int32_t* F10, int64_t nF, int Q, int64_t V, const uint32_t* perm, uint32_t* cnt,
+                           uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws, hipStream_t st);
+hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, int Q,
+                              const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
+                              const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
+                              double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                              hipStream_t st);
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
                         int nrb, int touch_words, uint32_t* touch, hipStream_t st);
 int pair_blocks_per_cu(bool grad);
@@ -221,6 +231,9 @@ struct Carve {
 struct Plan {
     int64_t nF, V, Fp;
     int Q = 1;        // quadrature points per face (records per face)
+    bool p3 = false;  // curved cubic elements: F holds 10 node ids per element, V counts all nodes
+    int fs = 3;       // ints per face in F
+    uint32_t *ncnt = nullptr, *ncursor = nullptr, *noff = nullptr, *nlist = nullptr;  // node CSR (p3)
     int64_t nR = 0;   // records = Q nF
     int ntiles, nrb, touch_words, sort_blocks, fin_blocks;
     Sched sc;
@@ -278,7 +291,15 @@ void layout(Plan& P, char* base, bool grad) {
     P.ticket = c.take<uint32_t>(64);
     P.cnt = c.take<uint32_t>(V);
     P.cursor = c.take<uint32_t>(V);
+    if (P.p3 && grad) {
+        P.ncnt = c.take<uint32_t>(V);
+        P.ncursor = c.take<uint32_t>(V);
+    }
     P.zero_end = c.take<uint32_t>(0);
+    if (P.p3 && grad) {
+        P.noff = c.take<uint32_t>(V + 1);
+        P.nlist = c.take<uint32_t>((size_t)P3_NODES * nF);
+    }
     P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.voff = c.take<uint32_t>(V + 1);
     P.scanws = c.take<uint32_t>((size_t)scan_ws_words(V) + 1);
@@ -293,7 +314,7 @@ void layout(Plan& P, char* base, bool grad) {
         P.colpart = c.take<float>((size_t)sym_colpart_floats(P.ssc, grad));
         P.first = c.take<int>((size_t)P.ssc.W);
     }
-    P.corner = c.take<double>(grad ? 9 * nR : 1);
+    P.corner = c.take<double>(grad ? std::max<int64_t>(9 * nR, P.p3 ? 3 * P3_NODES * nF : 0) : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
     if (P.FpY > 0) {
@@ -327,8 +348,10 @@ void layout(Plan& P, char* base, bool grad) {
 
 // sym: the exact self energy asks for the symmetric kernel (taken if its buffers fit)
 void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int treeH = -1, int64_t nFY = 0,
-          int64_t VY = 0, int Q = 1, bool sym = false) {
+          int64_t VY = 0, int Q = 1, bool sym = false, bool p3 = false) {
     P.treeH = treeH;
+    P.p3 = p3;
+    P.fs = p3 ? P3_NODES : 3;
     P.Q = Q;
     P.nR = nF * Q;
     P.nFY = nFY;
@@ -440,18 +463,23 @@ int timing_events(tpe_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
 int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, P.V, F, P.nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_morton(X, P.V, F, P.nF, P.Q, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(launch_bbox(X, P.V, F, P.fs, P.nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_morton(X, P.V, F, P.fs, P.nF, P.Q, P.bbox, P.morton_bits, P.keys, P.vals, st));
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, P.nR, 3 * P.morton_bits, P.hist, P.hoff, st));
-    HIPCHK(launch_records(X, P.V, F, P.nF, P.Q, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
-                          ctx->dflags, st));
+    if (P.p3)
+        HIPCHK(launch_p3_records(X, P.V, F, P.nF, P.Q, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo,
+                                 P.cnt, ctx->dflags, st));
+    else
+        HIPCHK(launch_records(X, P.V, F, P.nF, P.Q, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                              ctx->dflags, st));
     HIPCHK(launch_adjacency(P.colv, P.nR, P.V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     HIPCHK(launch_touch(P.colv, P.nR, P.V, P.voff, P.list, P.nrb, P.touch_words, P.touch, st));
     return TPE_OK;
 }
 
+// p3: curved cubic elements (F: 10 node ids per element, corners first; V: all nodes)
 int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
-              double scale, double* E, double* G) {
+              double scale, double* E, double* G, bool p3 = false) {
     int rc = check_common(ctx, X, V, F, nF, q, p, true);
     if (rc) return rc;
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
@@ -459,11 +487,13 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (nF * ctx->quad > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
     DeviceGuard dg(ctx->device);
     Plan P;
-    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0);
+    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
     if ((rc = prepare(ctx, P, X, F))) return rc;
+    if (p3 && grad)
+        HIPCHK(launch_p3_nodes(F, nF, P.Q, V, P.vals, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -479,9 +509,17 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) HIPCHK(launch_sym_merge(grad, P.part, P.colpart, P.first, P.ssc, P.nR, P.Fp, P.acc64, st));
-    HIPCHK(launch_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, P.nR, P.sym ? P.acc64 : nullptr, P.geo,
-                           P.colv, X, P.bbox, q, p, scale, 0.5, P.Q, P.corner, P.epart, P.ticket, ctx->dflags, E, st));
-    if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+    if (p3) {
+        HIPCHK(launch_p3_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, nF, P.Q, P.sym ? P.acc64 : nullptr,
+                                  P.vals, F, V, X, P.bbox, q, p, scale, 0.5, P.corner, P.epart, P.ticket, ctx->dflags,
+                                  E, st));
+        if (grad) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G, st));
+    } else {
+        HIPCHK(launch_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, P.nR, P.sym ? P.acc64 : nullptr, P.geo,
+                               P.colv, X, P.bbox, q, p, scale, 0.5, P.Q, P.corner, P.epart, P.ticket, ctx->dflags, E,
+                               st));
+        if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+    }
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -505,15 +543,15 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_bbox(Y, VY, FY, nFY, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(Y, VY, FY, 3, nFY, P.bbox, ctx->dflags, st));
     // confining surface: records in Morton order (the sort buffers are reused for the rows below)
-    HIPCHK(launch_morton(Y, VY, FY, nFY, 1, P.bbox, P.morton_bits_y, P.keys, P.vals, st));
+    HIPCHK(launch_morton(Y, VY, FY, 3, nFY, 1, P.bbox, P.morton_bits_y, P.keys, P.vals, st));
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nFY, 3 * P.morton_bits_y, P.hist, P.hoff, st));
     HIPCHK(launch_records(Y, VY, FY, nFY, 1, P.FpY, P.vals, P.bbox, P.orgY, P.colsY, P.colvY, P.c64Y, P.geoY, nullptr,
                           ctx->dflags, st));
     // moving surface: records, corner counts and CSR (no exclusion between different surfaces)
-    HIPCHK(launch_morton(X, V, F, nF, 1, P.bbox, P.morton_bits, P.keys, P.vals, st));
+    HIPCHK(launch_morton(X, V, F, 3, nF, 1, P.bbox, P.morton_bits, P.keys, P.vals, st));
     HIPCHK(radix_sort(P.keys, P.vals, P.ktmp, P.vtmp, nF, 3 * P.morton_bits, P.hist, P.hoff, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt, ctx->dflags,
                           st));
@@ -650,6 +688,19 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
 }
 
+int tpe_energy_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, double q, double p,
+                  double scale, double* E_dev) {
+    if (ctx && !E_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null E_dev");
+    return run_exact(ctx, X, V, F10, nF, q, p, scale, E_dev, nullptr, true);
+}
+
+int tpe_gradient_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, double q, double p,
+                    double scale, double* E_dev, double* G_dev) {
+    if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
+    if (ctx && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    return run_exact(ctx, X, V, F10, nF, q, p, scale, E_dev, G_dev, true);
+}
+
 int tpe_conf_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, const double* Y,
                     int64_t VY, const int32_t* FY, int64_t nFY, double q, double p, double scale, double* E_dev) {
     if (ctx && !E_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null E_dev");
@@ -681,7 +732,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     layout(P, ctx->arena, false);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(build_kd_order(X, V, F, nF, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist, P.hoff,
                           st));
     tpe_tree* t = new tpe_tree();
@@ -739,7 +790,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
     HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
@@ -784,7 +835,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
     HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
@@ -826,7 +877,7 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));

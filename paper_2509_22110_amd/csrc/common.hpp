@@ -44,6 +44,43 @@ __host__ __device__ inline void quad_point(int Q, int p, double* b, double& w) {
     }
 }
 
+// Curved cubic element (the paper's S_h^3): 10 nodes at the barycentric lattice points
+// m / 3, m = (m0, m1, m2) with m0 + m1 + m2 = 3, in the order of P3_M below (corners, the two
+// nodes of edges 0-1, 1-2, 2-0 starting at the edge's first corner, centre).  The Lagrange basis
+// function of node m is the product over the three barycentric coordinates of
+//     L_k(x) = prod_{j<k} (3x - j) / (j + 1)      (k = m_c, x = l_c),
+// which is 1 at its own node and 0 at the other nine.  With reference coordinates (s, t) =
+// (l1, l2), d/ds = d/dl1 - d/dl0 and d/dt = d/dl2 - d/dl0.
+constexpr int P3_NODES = 10;
+__host__ __device__ constexpr int p3_m(int node, int c) {
+    // m_c of each node, three base-4 digits per node: corners, edges 0-1, 1-2, 2-0, centre
+    constexpr int M[P3_NODES] = {0x300, 0x030, 0x003, 0x210, 0x120, 0x021, 0x012, 0x102, 0x201, 0x111};
+    return (M[node] >> (4 * (2 - c))) & 0xf;
+}
+
+__device__ __forceinline__ void p3_lk(int k, double x, double& v, double& dv) {
+    // L_k and its derivative for k = 0..3
+    const double y = 3.0 * x;
+    if (k == 0) { v = 1.0; dv = 0.0; }
+    else if (k == 1) { v = y; dv = 3.0; }
+    else if (k == 2) { v = 0.5 * y * (y - 1.0); dv = 1.5 * (2.0 * y - 1.0); }
+    else { v = y * (y - 1.0) * (y - 2.0) / 6.0; dv = 0.5 * (3.0 * y * y - 6.0 * y + 2.0); }
+}
+
+// basis values and (s, t) derivatives at barycentric l
+__device__ __forceinline__ void p3_shape(const double* l, double* phi, double* ds, double* dt) {
+#pragma unroll
+    for (int k = 0; k < P3_NODES; ++k) {
+        double v[3], dv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p3_lk(p3_m(k, c), l[c], v[c], dv[c]);
+        phi[k] = v[0] * v[1] * v[2];
+        const double d0 = dv[0] * v[1] * v[2], d1 = v[0] * dv[1] * v[2], d2 = v[0] * v[1] * dv[2];
+        ds[k] = d1 - d0;
+        dt[k] = d2 - d0;
+    }
+}
+
 // Column record read with scalar loads: centroid relative to its tile origin, area, normal, and
 // wv = -2 a, the weight of a column's Sdd term in the symmetric kernel's combined sum
 // V = Sn - (p/q) Sdd for (q, p) = (6, 12).

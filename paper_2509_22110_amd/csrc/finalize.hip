@@ -23,30 +23,57 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 // Row sums of face i: from the pair kernel's segments (part != null: the (hi, lo) FP32 pairs of
 // every wave whose range covers row i's block, added in FP64 in wave order), else acc64[k][i].
-// The covering waves are the same for the whole wave of threads (ROWB is a multiple of 64), so
-// the schedule's divisions run once per wave, on wave-uniform values.
-template <int NA>
+// UNIFORM: the covering waves are the same for the whole wave of threads (consecutive rows, ROWB a
+// multiple of 64), so the schedule's divisions run once per wave, on wave-uniform values.
+template <int NA, bool UNIFORM = true>
 __device__ __forceinline__ void row_sums(const float* __restrict__ part, const Sched& sc,
                                          const double* __restrict__ accs, int64_t Fp, int64_t i, double (&acc)[NA]) {
     if (!part) {
         for (int k = 0; k < NA; ++k) acc[k] = accs[(size_t)k * Fp + i];
         return;
     }
+    auto uni = [](int x) { return UNIFORM ? __builtin_amdgcn_readfirstlane(x) : x; };
     const int rr = (int)(i % ROWB);
-    const int rb = __builtin_amdgcn_readfirstlane((int)(i / ROWB));
-    const int w0 = __builtin_amdgcn_readfirstlane(sc.wave_of((int64_t)rb * sc.upr));
-    const int w1 = __builtin_amdgcn_readfirstlane(sc.wave_of((int64_t)(rb + 1) * sc.upr - 1));
+    const int rb = uni((int)(i / ROWB));
+    const int w0 = uni(sc.wave_of((int64_t)rb * sc.upr));
+    const int w1 = uni(sc.wave_of((int64_t)(rb + 1) * sc.upr - 1));
     for (int k = 0; k < NA; ++k) acc[k] = 0.0;
     for (int w = w0; w <= w1; ++w) {
-        const int seg = __builtin_amdgcn_readfirstlane(rb - (int)(sc.begin(w) / sc.upr));
+        const int seg = uni(rb - (int)(sc.begin(w) / sc.upr));
         const float* ps = part + ((size_t)w * sc.maxseg + seg) * 2 * NA * ROWB + rr;
         for (int k = 0; k < NA; ++k) acc[k] += (double)ps[(size_t)k * ROWB] + (double)ps[(size_t)(NA + k) * ROWB];
     }
 }
 
-// One thread per sorted face; every work-group writes one FP64 energy partial and the last
-// work-group to finish (ticket counter, zero on entry) adds the partials in index order, so the
-// energy is deterministic.
+// Energy of a 256-thread work-group's threads (e per thread): every work-group writes one FP64
+// partial and the last one to finish (ticket counter, zero on entry) adds the partials in index
+// order and writes E[0] = fac * total, so the energy is deterministic.
+__device__ void energy_tail(double e, double* __restrict__ epart, uint32_t* __restrict__ ticket,
+                            double* __restrict__ E, double fac) {
+    __shared__ double ws[4];
+    __shared__ bool last;
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
+        t += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = wave_sum(t);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0 && E) E[0] = fac * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+}
+
+// One thread per sorted face; the energy as in energy_tail.
 template <bool GRAD>
 __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__ part, Sched sc,
                                                        const double* __restrict__ accs, int64_t Fp, int64_t nF,
@@ -59,8 +86,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
                                                        double* __restrict__ epart, uint32_t* __restrict__ ticket,
                                                        double* __restrict__ E, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
-    __shared__ double ws[4];
-    __shared__ bool last;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double e = 0.0;
     // the row sums were taken on positions multiplied by s = 2^k: G(X) = s^(p-q-3) G(sX) and
@@ -111,25 +136,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
         }
         if (!finite) atomicOr(flags, (uint32_t)FLAG_NONFINITE);
     }
-    e = wave_sum(e);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double t = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
-        t += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    t = wave_sum(t);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0 && E) E[0] = scale * pow2i(kexp, p - q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+    energy_tail(e, epart, ticket, E, scale * pow2i(kexp, p - q - 4.0));
 }
 
 // G[v] = sum over the (sorted face, corner) slots incident to v, in ascending slot order: the
@@ -157,6 +164,93 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
     G[3 * v + 0] = g0;
     G[3 * v + 1] = g1;
     G[3 * v + 2] = g2;
+}
+
+// Curved cubic elements: one thread per sorted element e < nF (records e Q .. e Q + Q - 1, in point
+// order; the element is perm[e Q] / Q).  Each record's row sums give dE/dweight, dE/dn and dE/dx of
+// its point as in finalize_kernel; with the element's map recomputed at the point,
+//     g_J = (dE/dweight) (w / 2) n + (I - n n^T) (dE/dn) / |J|,
+//     node k += phi_k dE/dx + (d phi_k / ds) (x_t x g_J) + (d phi_k / dt) (g_J x x_s),
+// summed over the element's points in order and written to corner[e][k] (10 x 3 FP64): the
+// gather's slot 10 e + k.
+template <bool GRAD>
+__global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restrict__ part, Sched sc,
+                                                          const double* __restrict__ accs, int64_t Fp, int64_t nF,
+                                                          int Q, const uint32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ F10, int64_t V,
+                                                          const double* __restrict__ X,
+                                                          const uint32_t* __restrict__ bbox, double q, double p,
+                                                          double scale, double efac, double* __restrict__ corner,
+                                                          double* __restrict__ epart, uint32_t* __restrict__ ticket,
+                                                          double* __restrict__ E, uint32_t* __restrict__ flags) {
+    constexpr int NA = GRAD ? NACC : 1;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double en = 0.0;
+    const int kexp = norm_exp(bbox);
+    const double s = ldexp(1.0, kexp);
+    const double gs = scale * pow2i(kexp, p - q - 3.0);
+    if (e < nF) {
+        const int64_t f = perm[e * Q] / Q;
+        int32_t id[P3_NODES];
+        bool ok = true;
+        for (int k = 0; k < P3_NODES; ++k) {
+            id[k] = F10[P3_NODES * f + k];
+            ok &= id[k] >= 0 && id[k] < V;  // (bad ids were reported by the record kernel)
+        }
+        double g[P3_NODES][3];
+        for (int k = 0; k < P3_NODES; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0;
+        bool finite = true;
+        for (int pt = 0; pt < Q; ++pt) {
+            const int64_t i = e * Q + pt;
+            double acc[NA];
+            row_sums<NA, false>(part, sc, accs, Fp, i, acc);
+            double b[3], wq;
+            quad_point(Q, pt, b, wq);
+            double phi[P3_NODES], ds[P3_NODES], dt[P3_NODES];
+            p3_shape(b, phi, ds, dt);
+            double xs[3] = {0.0, 0.0, 0.0}, xt[3] = {0.0, 0.0, 0.0};
+            if (ok)
+                for (int k = 0; k < P3_NODES; ++k)
+                    for (int d = 0; d < 3; ++d) {
+                        const double x = s * X[3 * (int64_t)id[k] + d];
+                        xs[d] += ds[k] * x;
+                        xt[d] += dt[k] * x;
+                    }
+            const double J[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
+                                 xs[0] * xt[1] - xs[1] * xt[0]};
+            double wn = sqrt(J[0] * J[0] + J[1] * J[1] + J[2] * J[2]);
+            if (!(wn > 0.0)) wn = 1.0;  // degenerate: reported by the record kernel
+            const double n[3] = {J[0] / wn, J[1] / wn, J[2] / wn};
+            const double a = 0.5 * wq * wn;
+            for (int k = 0; k < NA; ++k) finite &= isfinite(acc[k]);
+            en += (GRAD ? efac : 1.0) * a * acc[0];  // the energy-only row sums hold each pair once
+            if (GRAD) {
+                const double Ga = gs * wq * acc[0];
+                double Gn[3], Gc[3];
+                for (int d = 0; d < 3; ++d) {
+                    Gn[d] = gs * q * a * acc[2 + d];
+                    Gc[d] = gs * a * (q * (n[d] * acc[1] + acc[8 + d]) - p * acc[5 + d]);
+                }
+                const double nGn = n[0] * Gn[0] + n[1] * Gn[1] + n[2] * Gn[2];
+                double gJ[3];
+                for (int d = 0; d < 3; ++d) gJ[d] = 0.5 * Ga * n[d] + (Gn[d] - nGn * n[d]) / wn;
+                const double cs[3] = {xt[1] * gJ[2] - xt[2] * gJ[1], xt[2] * gJ[0] - xt[0] * gJ[2],
+                                      xt[0] * gJ[1] - xt[1] * gJ[0]};
+                const double ct[3] = {gJ[1] * xs[2] - gJ[2] * xs[1], gJ[2] * xs[0] - gJ[0] * xs[2],
+                                      gJ[0] * xs[1] - gJ[1] * xs[0]};
+                for (int k = 0; k < P3_NODES; ++k)
+                    for (int d = 0; d < 3; ++d) g[k][d] += phi[k] * Gc[d] + ds[k] * cs[d] + dt[k] * ct[d];
+            }
+        }
+        if (GRAD)
+            for (int k = 0; k < P3_NODES; ++k)
+                for (int d = 0; d < 3; ++d) {
+                    finite &= isfinite(g[k][d]);
+                    corner[(size_t)P3_NODES * 3 * e + 3 * k + d] = g[k][d];
+                }
+        if (!finite) atomicOr(flags, (uint32_t)FLAG_NONFINITE);
+    }
+    energy_tail(en, epart, ticket, E, scale * pow2i(kexp, p - q - 4.0));
 }
 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
@@ -229,6 +323,21 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
     else
         hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
                            bbox, q, p, scale, efac, Q, corner, epart, ticket, E, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, int Q,
+                              const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
+                              const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
+                              double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                              hipStream_t st) {
+    const int nb = finalize_blocks(nF);
+    if (grad)
+        hipLaunchKernelGGL((p3_finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, Q, perm,
+                           F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+    else
+        hipLaunchKernelGGL((p3_finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, Q, perm,
+                           F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

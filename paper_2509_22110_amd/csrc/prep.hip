@@ -33,16 +33,18 @@ __global__ void init_scratch(uint32_t* __restrict__ zero, int64_t nzero, uint32_
 
 // bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids (FP32); must start at
 // (0xffffffff x3, 0 x3).  Also validates indices / coordinates and flags errors.  Grid-stride
-// loop, reduction over the work-group, then six atomics per work-group.
+// loop, reduction over the work-group, then six atomics per work-group.  Face f's corners are
+// F[fs f + 0..2] (fs = 3 for triangles, 10 for curved cubic elements, whose centroid here is that
+// of their corners).
 __global__ __launch_bounds__(256) void face_bbox(const double* __restrict__ X, int64_t V,
-                                                  const int32_t* __restrict__ F, int64_t nF,
+                                                  const int32_t* __restrict__ F, int fs, int64_t nF,
                                                   uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags) {
     __shared__ float smn[4][3], smx[4][3];
     __shared__ uint32_t sfl[4];
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     uint32_t fl = 0;
     for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nF; f += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+        int32_t v[3] = {F[fs * f], F[fs * f + 1], F[fs * f + 2]};
         double c[3] = {0, 0, 0};
         bool ok = true;
         for (int k = 0; k < 3; ++k) {
@@ -102,7 +104,7 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 // box; value = face id.
 // One key per record r < Q nF (the Q quadrature points of face r / Q share the face centroid's key,
 // so a stable sort keeps a face's records together, in point order).
-__global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
+__global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F, int fs,
                             int64_t nF, int Q, const uint32_t* __restrict__ bbox, int bits,
                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -117,7 +119,7 @@ __global__ void morton_keys(const double* __restrict__ X, int64_t V, const int32
         if (!isfinite(lo[d])) lo[d] = 0.f;
     }
     uint32_t q[3] = {0, 0, 0};
-    int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+    int32_t v[3] = {F[fs * f], F[fs * f + 1], F[fs * f + 2]};
     bool ok = v[0] >= 0 && v[0] < V && v[1] >= 0 && v[1] < V && v[2] >= 0 && v[2] < V;
     if (ok) {
         for (int d = 0; d < 3; ++d) {
@@ -157,6 +159,11 @@ __device__ __forceinline__ double wave_max(double x) {
 // chunk of CTILE = 64 positions; the chunk's FP64 origin is the centre of its points' bounding
 // box, so the FP32 record coordinates relative to it are at most half the chunk's extent (their
 // rounding error sets the accuracy of the closest pairs).
+__device__ void store_record(int64_t i, bool real, bool ok, uint32_t fl, const double* c, const double* n,
+                             double a, double wn, const int32_t* v, int pt, double* __restrict__ org,
+                             ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
+                             double* __restrict__ geo, uint32_t* __restrict__ cnt, uint32_t* __restrict__ flags);
+
 __global__ void face_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F,
                              int64_t nF, int Q, int64_t Fp, const uint32_t* __restrict__ perm,
                              const uint32_t* __restrict__ bbox, double* __restrict__ org,
@@ -211,6 +218,16 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
             c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
         }
     }
+    store_record(i, real, ok, fl, c, n, a, wn, v, pt, org, cols, colv, c64, geo, cnt, flags);
+}
+
+// The common tail of the record kernels (all lanes of the wave take part): the chunk origin, the
+// FP32 record, vertex ids and point index, the FP64 position and {a, |w|, n}, the corner counts of
+// the vertex CSR, and the error flags.
+__device__ void store_record(int64_t i, bool real, bool ok, uint32_t fl, const double* c, const double* n,
+                             double a, double wn, const int32_t* v, int pt, double* __restrict__ org,
+                             ColRec* __restrict__ cols, int4* __restrict__ colv, double* __restrict__ c64,
+                             double* __restrict__ geo, uint32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
     // chunk origin: centre of the bounding box of the chunk's real centroids (0 if none)
     const bool inbox = real && ok && !(fl & FLAG_NONFINITE);
     double o[3];
@@ -248,6 +265,100 @@ __global__ void face_records(const double* __restrict__ X, int64_t V, const int3
         for (int k = 0; k < 5; ++k) geo[5 * i + k] = 0.0;
     }
     cols[i] = r;
+}
+
+// Curved cubic elements: one thread per sorted position i < Fp.  Record perm[i] = r is quadrature
+// point r % Q of element r / Q, whose nodes are F10[10 (r / Q) + 0..9] (corners first): with the
+// element's cubic map x(s, t), the record sits at x(b) for the rule's barycentric point b, with
+// normal J / |J| and weight w |J| / 2, J = x_s x x_t (for a straight element: w times the area,
+// the flat record).  The vertex ids of the record are the element's corner nodes, so records of
+// elements sharing a corner are excluded from each other, as for flat faces.  geo holds
+// {weight, |J|, n}.
+__global__ void p3_records(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F10, int64_t nF,
+                           int Q, int64_t Fp, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ bbox,
+                           double* __restrict__ org, ColRec* __restrict__ cols, int4* __restrict__ colv,
+                           double* __restrict__ c64, double* __restrict__ geo, uint32_t* __restrict__ cnt,
+                           uint32_t* __restrict__ flags) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= Fp) return;
+    const double s = norm_scale(bbox);
+    bool real = i < nF * Q, ok = false;
+    int32_t v[3] = {-1, -1, -1};
+    int pt = 0;
+    double a = 0.0, wn = 1.0, n[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
+    uint32_t fl = 0;
+    if (real) {
+        const int64_t rec = perm[i];
+        const int64_t f = rec / Q;
+        pt = (int)(rec % Q);
+        int32_t id[P3_NODES];
+        ok = true;
+        for (int k = 0; k < P3_NODES; ++k) {
+            id[k] = F10[P3_NODES * f + k];
+            ok &= id[k] >= 0 && id[k] < V;
+        }
+        if (!ok) fl |= FLAG_BAD_INDEX;
+        for (int k = 0; k < 3; ++k) v[k] = id[k];
+        double b[3], wq;
+        quad_point(Q, pt, b, wq);
+        double phi[P3_NODES], ds[P3_NODES], dt[P3_NODES];
+        p3_shape(b, phi, ds, dt);
+        double xs[3] = {0.0, 0.0, 0.0}, xt[3] = {0.0, 0.0, 0.0};
+        bool fin = true;
+        if (ok)
+            for (int k = 0; k < P3_NODES; ++k)
+                for (int d = 0; d < 3; ++d) {
+                    const double x = s * X[3 * (int64_t)id[k] + d];
+                    fin &= isfinite(x);
+                    c[d] += phi[k] * x;
+                    xs[d] += ds[k] * x;
+                    xt[d] += dt[k] * x;
+                }
+        if (!fin) fl |= FLAG_NONFINITE;
+        const double J[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
+                             xs[0] * xt[1] - xs[1] * xt[0]};
+        wn = sqrt(J[0] * J[0] + J[1] * J[1] + J[2] * J[2]);
+        a = 0.5 * wq * wn;
+        if (ok && fin && !(wn > 1e-300 * s * s)) fl |= FLAG_DEGENERATE;
+        if (!(wn > 1e-300 * s * s) || !ok || !fin) { wn = 1.0; a = 0.0; }
+        for (int d = 0; d < 3; ++d) n[d] = J[d] / wn;
+        if (!isfinite(c[0] + c[1] + c[2] + n[0] + n[1] + n[2])) {
+            fl |= FLAG_NONFINITE;
+            c[0] = c[1] = c[2] = 0.0; n[0] = n[1] = n[2] = 0.0; a = 0.0;
+        }
+    }
+    store_record(i, real, ok, fl, c, n, a, wn, v, pt, org, cols, colv, c64, geo, cnt, flags);
+}
+
+// node -> (sorted element, node slot) adjacency of curved cubic elements, for the vertex gather:
+// element e of the sorted order (records e Q .. e Q + Q - 1) is element perm[e Q] / Q; slot
+// 10 e + k is its node k.  p3_node_count adds the per-node counts (cnt zero on entry);
+// p3_node_fill writes the lists (cursor zero on entry; order within a list arbitrary, the gather
+// orders it).
+__global__ void p3_node_count(const int32_t* __restrict__ F10, int64_t nF, int Q, int64_t V,
+                              const uint32_t* __restrict__ perm, uint32_t* __restrict__ cnt) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nF) return;
+    const int64_t f = perm[e * Q] / Q;
+    for (int k = 0; k < P3_NODES; ++k) {
+        const int32_t v = F10[P3_NODES * f + k];
+        if (v >= 0 && v < V) atomicAdd(&cnt[v], 1u);
+    }
+}
+
+__global__ void p3_node_fill(const int32_t* __restrict__ F10, int64_t nF, int Q, int64_t V,
+                             const uint32_t* __restrict__ perm, const uint32_t* __restrict__ off,
+                             uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nF) return;
+    const int64_t f = perm[e * Q] / Q;
+    for (int k = 0; k < P3_NODES; ++k) {
+        const int32_t v = F10[P3_NODES * f + k];
+        if (v >= 0 && v < V) {
+            const uint32_t pos = atomicAdd(&cursor[v], 1u);
+            list[off[v] + pos] = (uint32_t)(P3_NODES * e + k);
+        }
+    }
 }
 
 // ---- vertex -> (sorted face, corner) adjacency, CSR, deterministic order ----------------------
@@ -314,17 +425,37 @@ hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int64_t nF, uint32_t* bbox,
+// fs: ints per face in F (3 for triangles; 10 for curved cubic elements, corners first)
+hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox,
                        uint32_t* flags, hipStream_t st) {
     int g = (int)std::min<int64_t>(nblk(nF, 256), 64);
-    hipLaunchKernelGGL(face_bbox, dim3(g), dim3(256), 0, st, X, V, F, nF, bbox, flags);
+    hipLaunchKernelGGL(face_bbox, dim3(g), dim3(256), 0, st, X, V, F, fs, nF, bbox, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, const uint32_t* bbox,
-                         int bits, uint32_t* keys, uint32_t* vals, hipStream_t st) {
-    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF * Q, 256)), dim3(256), 0, st, X, V, F, nF, Q, bbox, bits, keys,
+hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, int Q,
+                         const uint32_t* bbox, int bits, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    hipLaunchKernelGGL(morton_keys, dim3(nblk(nF * Q, 256)), dim3(256), 0, st, X, V, F, fs, nF, Q, bbox, bits, keys,
                        vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_p3_records(const double* X, int64_t V, const int32_t* F10, int64_t nF, int Q, int64_t Fp,
+                             const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
+                             double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(p3_records, dim3(nblk(Fp, 256)), dim3(256), 0, st, X, V, F10, nF, Q, Fp, perm, bbox, org,
+                       cols, colv, c64, geo, cnt, flags);
+    return hipGetLastError();
+}
+
+// node CSR of the gather: cnt and cursor (V entries each) zero on entry; ws: scan workspace
+// (scan_ws_words(V) words)
+hipError_t launch_p3_nodes(const int32_t* F10, int64_t nF, int Q, int64_t V, const uint32_t* perm, uint32_t* cnt,
+                           uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws, hipStream_t st) {
+    hipLaunchKernelGGL(p3_node_count, dim3(nblk(nF, 256)), dim3(256), 0, st, F10, nF, Q, V, perm, cnt);
+    hipError_t e = launch_exclusive_scan(cnt, V, off, ws, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(p3_node_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, F10, nF, Q, V, perm, off, cursor, list);
     return hipGetLastError();
 }
 

@@ -1,0 +1,127 @@
+"""Curved cubic (P3) elements on the GPU (tpe_energy_p3 / tpe_gradient_p3) against the oracle's
+P3 scheme, and straight elements against the flat multi-point path at the level-5 size."""
+import contextlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+E_TOL, G_TOL = 1e-6, 1e-5
+
+
+@contextlib.contextmanager
+def options(T, dev, **kw):
+    ctx = T.context(dev)
+    names = {"Q": T.OPT_QUADRATURE, "sym": T.OPT_SYMMETRIC, "waves": T.OPT_TARGET_WAVES}
+    defaults = {"Q": 1, "sym": 1, "waves": 0}
+    for k, v in kw.items():
+        ctx.set_option(names[k], v)
+    try:
+        yield ctx
+    finally:
+        for k in kw:
+            ctx.set_option(names[k], defaults[k])
+
+
+def meshes():
+    X, F = M.icosphere(1)
+    yield ("L1-straight",) + M.p3_lattice(M.radial_jitter(X, 0.03, 2), F)
+    yield ("L2-curved",) + M.p3_sphere(2, 2, 8, 0.05, 1)
+    X10, F10 = M.p3_sphere(1, 2, 4, 0.05, 4)
+    rng = np.random.default_rng(4)
+    yield "L1-curved-jitter", X10 + rng.normal(0.0, 0.004, X10.shape), F10
+
+
+MESHES = list(meshes())
+
+
+def check(T, name, X10, F10, Q, q=6.0, p=12.0, **opt):
+    Xd, Fd = upload(X10, F10)
+    with options(T, Xd.device, Q=Q, **opt):
+        E, G = T.gradient_p3(Xd, Fd, q, p)
+        Ee = T.energy_p3(Xd, Fd, q, p)
+    Eo, Go = oracle.gradient_p3(X10, F10, Q, q, p)
+    eE, eEe = rel_energy(float(E.cpu()), Eo), rel_energy(float(Ee.cpu()), Eo)
+    eG = rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log(name, "Q", Q, "q,p", q, p, opt, "rel E", eE, "rel E(energy only)", eEe, "rel G", eG)
+    assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
+
+
+@pytest.mark.parametrize("Q", [1, 3, 6])
+@pytest.mark.parametrize("name,X10,F10", MESHES, ids=[m[0] for m in MESHES])
+def test_parity(Q, name, X10, F10):
+    check(tpe(), name, X10, F10, Q)
+
+
+@pytest.mark.parametrize("sym,waves", [(0, 0), (1, 1), (1, 7), (0, 5)])
+def test_kernel_variants(sym, waves):
+    name, X10, F10 = MESHES[1]
+    check(tpe(), name, X10, F10, 6, sym=sym, waves=waves)
+
+
+@pytest.mark.parametrize("qp", [(4.0, 8.0), (8.0, 14.0)])
+def test_other_exponents(qp):
+    name, X10, F10 = MESHES[2]
+    check(tpe(), name, X10, F10, 3, *qp)
+
+
+def test_level3_six_points():
+    """1,280 curved elements x 36 point pairs per element pair."""
+    X10, F10 = M.p3_sphere(3, 2, 8, 0.05, 2)
+    check(tpe(), "L3-curved", X10, F10, 6)
+
+
+def _pull_back(X, F, X10, F10, G3):
+    """Gradient with respect to the corners of straight elements: every node is the fixed affine
+    combination of its element's corners given by its lattice point."""
+    nodes, first = np.unique(F10.reshape(-1), return_index=True)
+    f, k = first // 10, first % 10
+    G = np.zeros_like(X)
+    for c in range(3):
+        np.add.at(G, F[f, c], M.P3_LATTICE[k, c][:, None] * G3[nodes])
+    return G
+
+
+def test_straight_level5_matches_flat_path():
+    """At the level-5 size (20,480 elements, 3 points): straight cubic elements give the flat
+    path's energy and, pulled back to the corners, its gradient."""
+    T = tpe()
+    c = M.make_config("C2")
+    X10, F10 = M.p3_lattice(c.X, c.F)
+    Xd, Fd = upload(c.X, c.F)
+    X10d, F10d = upload(X10, F10)
+    with options(T, Xd.device, Q=3):
+        Ef, Gf = T.gradient(Xd, Fd)
+        E3, G3 = T.gradient_p3(X10d, F10d)
+    Gp = _pull_back(c.X, c.F, X10, F10, G3.cpu().numpy())
+    eE = rel_energy(float(E3.cpu()), float(Ef.cpu()))
+    eG = rel_grad_maxnorm(Gp, Gf.cpu().numpy())
+    log("C2 straight P3 vs flat, Q 3: rel E", eE, "rel G", eG)
+    assert eE <= E_TOL and eG <= G_TOL
+
+
+def test_deterministic():
+    T = tpe()
+    name, X10, F10 = MESHES[1]
+    Xd, Fd = upload(X10, F10)
+    with options(T, Xd.device, Q=6):
+        E1, G1 = T.gradient_p3(Xd, Fd)
+        E2, G2 = T.gradient_p3(Xd, Fd)
+    assert float(E1.cpu()) == float(E2.cpu()) and np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+
+
+def test_errors():
+    T = tpe()
+    name, X10, F10 = MESHES[1]
+    bad = F10.copy()
+    bad[3, 7] = X10.shape[0] + 5
+    Xd, Fd = upload(X10, bad)
+    with pytest.raises(T.TPEError):
+        T.gradient_p3(Xd, Fd)
+    Xd, Fd = upload(X10, F10[:, :3])
+    with pytest.raises(ValueError):
+        T.energy_p3(Xd, Fd)
