@@ -144,6 +144,13 @@ int tpe_energy_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, 
 int tpe_gradient_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
                     double q, double p, double scale, double* E_dev, double* G_dev);
 
+/* Stable LSD radix sort of n (key, value) pairs in place by the low `bits` bits of the keys (the
+ * sort that orders faces along the Morton curve and the tree's k-d order, exposed for testing and
+ * reuse).  keys, vals: device u32 [n], caller-owned, sorted in place (pairs with equal low bits
+ * keep their input order; the keys' other bits travel with them).  1 <= bits <= 32,
+ * 0 <= n <= 2^30; uses the context's scratch arena. */
+int tpe_sort_pairs(tpe_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits);
+
 /* Confinement energy (paper Sec. 2.2.3, eq. (TPConf)) of the moving surface (X, F) against a fixed
  * confining surface (Y, FY), with the same one-point centroid quadrature:
  *     E_conf = scale * sum_{S in F} sum_{T in FY} a_S a_T |n_S . (c_S - c_T)|^q / |c_S - c_T|^p.

@@ -17,7 +17,7 @@ import threading
 
 import torch
 
-__all__ = ["TPEError", "lib", "energy", "gradient", "energy_p3", "gradient_p3", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
+__all__ = ["TPEError", "lib", "energy", "gradient", "energy_p3", "gradient_p3", "sort_pairs", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
            "tpe_energy",
            "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield", "MLP"]
 
@@ -66,6 +66,7 @@ def lib():
             "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_energy_p3": ([P, P, I64, P, I64, D, D, D, P], I),
+            "tpe_sort_pairs": ([P, P, P, I64, I], I),
             "tpe_gradient_p3": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_conf_energy": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P], I),
             "tpe_conf_gradient": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P, P], I),
@@ -194,6 +195,19 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
     c.check(lib().tpe_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
                                float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
     return E, G
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int = 32):
+    """Stable in-place sort of device int32 (keys, vals) by the low `bits` bits of the keys (read
+    as unsigned 32-bit integers)."""
+    for t in (keys, vals):
+        if t.device.type != "cuda" or t.dtype != torch.int32 or t.dim() != 1 or not t.is_contiguous():
+            raise ValueError("keys and vals must be contiguous 1-D int32 device tensors")
+    if keys.shape != vals.shape or keys.device != vals.device:
+        raise ValueError("keys and vals must have the same shape and device")
+    c = context(keys.device)
+    c.check(lib().tpe_sort_pairs(c.h, keys.data_ptr(), vals.data_ptr(), keys.shape[0], int(bits)))
+    return keys, vals
 
 
 def energy_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None) -> torch.Tensor:

@@ -688,6 +688,30 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
 }
 
+int tpe_sort_pairs(tpe_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (n < 0 || n > ((int64_t)1 << 30) || (n > 0 && (!keys || !vals)))
+        return fail(ctx, TPE_ERR_INVALID_ARG, "keys/vals null or n outside [0, 2^30]");
+    if (bits < 1 || bits > 32) return fail(ctx, TPE_ERR_INVALID_ARG, "bits must be in [1, 32]");
+    if (n <= 1) return TPE_OK;
+    DeviceGuard dg(ctx->device);
+    Carve plan_c(nullptr);
+    plan_c.take<uint32_t>(n);
+    plan_c.take<uint32_t>(n);
+    plan_c.take<uint32_t>((size_t)radix_hist_words(n));
+    plan_c.take<uint32_t>((size_t)radix_hist_words(n));
+    int rc = ensure_arena(ctx, plan_c.off + 256);
+    if (rc) return rc;
+    Carve c(ctx->arena);
+    uint32_t* ktmp = c.take<uint32_t>(n);
+    uint32_t* vtmp = c.take<uint32_t>(n);
+    uint32_t* hist = c.take<uint32_t>((size_t)radix_hist_words(n));
+    uint32_t* hoff = c.take<uint32_t>((size_t)radix_hist_words(n));
+    HIPCHK(radix_sort(keys, vals, ktmp, vtmp, n, bits, hist, hoff, ctx->stream));
+    if (ctx->sync_checks) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TPE_OK;
+}
+
 int tpe_energy_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, double q, double p,
                   double scale, double* E_dev) {
     if (ctx && !E_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null E_dev");

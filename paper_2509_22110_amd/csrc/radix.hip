@@ -2,10 +2,10 @@
 //
 // Per pass: (1) every work-group counts the digits of its 2048-key tile in LDS and writes one
 // column of a digit-major histogram; (2) one work-group scans the histogram; (3) every work-group
-// re-reads its tile in 8 rounds of 256 keys and writes each key to
-// offset[digit][group] + (rank among equal digits before it).  The rank inside a wave comes from
-// one ballot per digit bit, across the four waves from LDS counters, so the sort is
-// stable and deterministic.
+// re-reads its tile, each wave a contiguous quarter in 8 rounds of 64 keys, and writes each key to
+// offset[digit][group] + (equal digits of lower waves) + (rank among equal digits before it in
+// the wave).  The rank inside a round comes from one ballot per digit bit, so the sort is stable
+// and deterministic.
 #include "common.hpp"
 
 namespace tpe {
@@ -15,70 +15,135 @@ constexpr int RS_ROUNDS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
 
 template <int DB>
-__global__ __launch_bounds__(RS_THREADS) void rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                       int nblocks, uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(RS_THREADS) void rs_hist(const uint32_t* __restrict__ keys, int64_t n, uint32_t kmask,
+                                                       int shift, int nblocks, uint32_t* __restrict__ hist) {
     constexpr int ND = 1 << DB;
     __shared__ uint32_t h[ND];
     const int tid = threadIdx.x;
     for (int d = tid; d < ND; d += RS_THREADS) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    uint32_t kr[RS_ROUNDS];
+#pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = base + r * RS_THREADS + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (ND - 1)], 1u);
+        const int64_t i = base + r * RS_THREADS + tid;
+        kr[r] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t i = base + r * RS_THREADS + tid;
+        if (i < n) atomicAdd(&h[((kr[r] & kmask) >> shift) & (ND - 1)], 1u);
     }
     __syncthreads();
     for (int d = tid; d < ND; d += RS_THREADS) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
 }
 
-template <int DB>
+// Up to RS_FUSE_BLOCKS tiles the scatter work-groups compute their offsets from the histogram
+// themselves (no scan launch): the offset of (digit d, tile b) is the count of all smaller digits
+// plus the count of digit d in tiles before b.
+constexpr int RS_FUSE_BLOCKS = 64;
+
+__device__ __forceinline__ uint32_t rs_wave_inclusive_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Wave w of the work-group owns the WR rounds of 64 consecutive keys starting at tile offset
+// w * WR * 64; equal digits keep their input order: wave, then round, then lane.  FUSED: `off`
+// is the histogram itself (digit-major, nblocks <= RS_FUSE_BLOCKS), else its exclusive scan.
+template <int DB, bool FUSED>
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin, int64_t n,
-                                                          int shift, int nblocks,
+                                                          uint32_t kmask, int shift, int nblocks,
                                                           const uint32_t* __restrict__ off,
                                                           uint32_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout) {
     constexpr int ND = 1 << DB;
     constexpr int NW = RS_THREADS / 64;
-    __shared__ uint32_t run[ND];
-    __shared__ uint32_t wcnt[NW][ND];
+    constexpr int WR = RS_TILE / RS_THREADS;  // rounds per wave
+    __shared__ uint32_t pos[NW][ND];          // (wave, digit): count, then running position
+    __shared__ uint32_t boff[FUSED ? ND : 1];  // FUSED: this tile's offset of each digit
+    __shared__ uint32_t wsum[NW];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    if constexpr (FUSED) {
+        // thread t takes digits [t DPT, (t + 1) DPT): their totals and this tile's prefix
+        constexpr int DPT = (ND + RS_THREADS - 1) / RS_THREADS;
+        uint32_t tot[DPT], pre[DPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            tot[j] = pre[j] = 0;
+            if (d < ND)
+                for (int b = 0; b < nblocks; ++b) {
+                    const uint32_t c = off[(int64_t)d * nblocks + b];
+                    tot[j] += c;
+                    pre[j] += b < (int)blockIdx.x ? c : 0u;
+                }
+            sum += tot[j];
+        }
+        const uint32_t inc = rs_wave_inclusive_scan(sum);
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - sum;
+        for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            if (d < ND) boff[d] = run + pre[j];
+            run += tot[j];
+        }
+    }
+    for (int e = tid; e < NW * ND; e += RS_THREADS) pos[e / ND][e % ND] = 0;
+    __syncthreads();
+    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * WR * 64;
+    uint32_t kr[WR], vr[WR];
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        kr[r] = i < n ? kin[i] : 0u;
+        vr[r] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < WR; ++r)
+        if (wbase + r * 64 + lane < n) atomicAdd(&pos[wave][((kr[r] & kmask) >> shift) & (ND - 1)], 1u);
+    __syncthreads();
     for (int d = tid; d < ND; d += RS_THREADS) {
-        run[d] = off[(int64_t)d * nblocks + blockIdx.x];
-        for (int w = 0; w < NW; ++w) wcnt[w][d] = 0;
+        uint32_t run = FUSED ? boff[d] : off[(int64_t)d * nblocks + blockIdx.x];
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = pos[w][d];
+            pos[w][d] = run;
+            run += c;
+        }
     }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        const int64_t i = base + r * RS_THREADS + tid;
-        const bool act = i < n;
-        uint32_t k = act ? kin[i] : 0u;
-        uint32_t v = act ? vin[i] : 0u;
-        uint32_t d = (k >> shift) & (ND - 1);
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+        const bool act = wbase + r * 64 + lane < n;
+        const uint32_t d = ((kr[r] & kmask) >> shift) & (ND - 1);
         uint64_t peers = __ballot(act);
+#pragma unroll
         for (int b = 0; b < DB; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+            const uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
         const uint32_t below = (uint32_t)__popcll(peers & lt);
-        if (act && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
+        uint32_t* slot = &pos[wave][d];
+        const uint32_t p = *slot + below;
         if (act) {
-            uint32_t pos = run[d] + below;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = k;
-            vout[pos] = v;
+            kout[p] = kr[r];
+            vout[p] = vr[r];
         }
-        __syncthreads();
-        for (int dd = tid; dd < ND; dd += RS_THREADS) {
-            uint32_t add = 0;
-            for (int w = 0; w < NW; ++w) { add += wcnt[w][dd]; wcnt[w][dd] = 0; }
-            run[dd] += add;
-        }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // every lane has read its position before it moves
+        if (act && below == 0) *slot += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -229,19 +294,24 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* off, u
     return hipGetLastError();
 }
 
-// Sorts n pairs by the low `bits` (<= 32) bits of the key in ceil(bits / 10) passes of equal
-// digits (<= 10 bits).  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of radix_hist_words(n)
-// words (the histogram, its scan, and the scan's workspace at the end of off).  The result always
-// ends in (keys, vals).
+// Stable sort of n pairs by the low `bits` (<= 32) bits of the key in ceil(bits / 10) passes of
+// equal digits (<= 10 bits), three launches each (two up to RS_FUSE_BLOCKS tiles).  Uses (ktmp, vtmp) as ping-pong buffers and hist/off of
+// radix_hist_words(n) words (the histogram, its scan, and the scan's workspace at the end of off).
+// The result always ends in (keys, vals).
 template <int DB>
-static hipError_t rs_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int64_t n, int shift,
-                          int nblocks, uint32_t* hist, uint32_t* off, hipStream_t st) {
-    hipLaunchKernelGGL((rs_hist<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, n, shift, nblocks, hist);
+static hipError_t rs_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int64_t n,
+                          uint32_t kmask, int shift, int nblocks, uint32_t* hist, uint32_t* off, hipStream_t st) {
+    hipLaunchKernelGGL((rs_hist<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, n, kmask, shift, nblocks, hist);
+    if (nblocks <= RS_FUSE_BLOCKS) {
+        hipLaunchKernelGGL((rs_scatter<DB, true>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, kmask, shift,
+                           nblocks, hist, ko, vo);
+        return hipGetLastError();
+    }
     const int64_t m = (int64_t)(1 << DB) * nblocks;
     hipError_t e = launch_exclusive_scan(hist, m, off, off + (int64_t)1024 * nblocks + 1, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rs_scatter<DB>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, shift, nblocks, off, ko,
-                       vo);
+    hipLaunchKernelGGL((rs_scatter<DB, false>), dim3(nblocks), dim3(RS_THREADS), 0, st, ki, vi, n, kmask, shift,
+                       nblocks, off, ko, vo);
     return hipGetLastError();
 }
 
@@ -254,6 +324,8 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* 
                       uint32_t* hist, uint32_t* off, hipStream_t st) {
     if (n <= 1 || bits <= 0) return hipSuccess;
     if (bits > 32) bits = 32;
+    // digits are taken from the low `bits` bits only (a pass's digit may reach above them)
+    const uint32_t kmask = bits >= 32 ? 0xffffffffu : (1u << bits) - 1u;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
     const int passes = (bits + 9) / 10;
     const int db = (bits + passes - 1) / passes;
@@ -261,11 +333,11 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* 
     for (int p = 0; p < passes; ++p) {
         hipError_t e;
         switch (db) {
-            case 10: e = rs_pass<10>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
-            case 9: e = rs_pass<9>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
-            case 8: e = rs_pass<8>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
-            case 7: e = rs_pass<7>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
-            default: e = rs_pass<6>(ki, vi, ko, vo, n, db * p, nblocks, hist, off, st); break;
+            case 10: e = rs_pass<10>(ki, vi, ko, vo, n, kmask, db * p, nblocks, hist, off, st); break;
+            case 9: e = rs_pass<9>(ki, vi, ko, vo, n, kmask, db * p, nblocks, hist, off, st); break;
+            case 8: e = rs_pass<8>(ki, vi, ko, vo, n, kmask, db * p, nblocks, hist, off, st); break;
+            case 7: e = rs_pass<7>(ki, vi, ko, vo, n, kmask, db * p, nblocks, hist, off, st); break;
+            default: e = rs_pass<6>(ki, vi, ko, vo, n, kmask, db * p, nblocks, hist, off, st); break;
         }
         if (e != hipSuccess) return e;
         std::swap(ki, ko);
