@@ -295,8 +295,9 @@ __device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, 
 }
 
 constexpr int FF_STACK = 1024;  // LDS node stack per wave (overflow falls back to exact evaluation)
+constexpr int FF_STACK_LEARNED = 512;  // the same with the learned correction, whose MLP scratch shares the LDS
 constexpr int FF_NW = 4;          // waves per target block, monopole far field
-constexpr int FF_NW_LEARNED = 1;  // waves per target block with the learned correction (MLP scratch is LDS-bound)
+constexpr int FF_NW_LEARNED = 4;  // waves per target block with the learned correction
 
 // One work-group of NW waves per target block of 64 consecutive (tree-ordered) faces.  Every wave
 // walks the implicit tree the same way (batched depth first: up to 64 nodes popped at once, one
@@ -322,9 +323,16 @@ __global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restr
                                                            int64_t nF, const float4* __restrict__ balls,
                                                            float theta, int64_t Fp, double* __restrict__ acc64,
                                                            unsigned long long* __restrict__ stats) {
-    __shared__ int stacks[NW][FF_STACK];
-    __shared__ float red[NW > 1 ? NW - 1 : 1][NW > 1 ? 2 * NACC : 1][64];
+    constexpr int STK = LEARNED ? FF_STACK_LEARNED : FF_STACK;
+    constexpr int NRED = NW > 1 ? NW - 1 : 1;
+    __shared__ int stacks[NW][STK];
     __shared__ MlpScratch ms[LEARNED ? NW : 1];
+    // the waves' final sums for the fold into wave 0; with the correction they reuse the MLP scratch,
+    // which is dead by then (every wave has passed the barrier before the fold)
+    __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
+    static_assert(!LEARNED || sizeof(MlpScratch) * NW >= sizeof(float) * NRED * 2 * NACC * 64, "fold space");
+    float (*red)[2 * NACC][64] = LEARNED ? reinterpret_cast<float (*)[2 * NACC][64]>(&ms[0])
+                                         : reinterpret_cast<float (*)[2 * NACC][64]>(&red_own[0][0][0]);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     int* stack = stacks[wave];
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restr
         const bool isleaf = (int64_t)k >= leaf0;
         bool open = valid && !far && !isleaf;
         const int nopen = __popcll(__ballot(open));
-        const bool overflow = sz + 2 * nopen > FF_STACK;
+        const bool overflow = sz + 2 * nopen > STK;
         if (overflow) open = false;
         const bool near = valid && !far && !open;
         // a near node whose vertex ball is disjoint from the block's shares no vertex with it
@@ -419,6 +427,7 @@ __global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restr
     }
     ff_fold(acc, hi, lo);
     if constexpr (NW > 1) {
+        if constexpr (LEARNED) __syncthreads();  // the MLP scratch is reused below
         if (wave > 0) {
 #pragma unroll
             for (int kk = 0; kk < NACC; ++kk) {
