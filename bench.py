@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # three vertices (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices
 # (12 B) and the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
 MERGE_FINALIZE_GATHER_BYTES_PER_FACE = 32 + 88 + 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
-SYM_MAX_COLPART_BYTES = 6 << 30
+SYM_MAX_COLPART_BYTES = 64 << 30
 
 
 def sym_colpart_bytes(nF, na=8):

@@ -80,10 +80,12 @@ typedef enum {
                                  TPE_ERR_UNSUPPORTED); at most 2^26 points in all. */
     TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
                                  every unordered pair of faces once and credit both faces (the
-                                 symmetric pair kernel), while its column partial sums fit in 6 GiB
-                                 of the context's scratch (about 450,000 faces with the gradient);
-                                 0, or beyond that size: every ordered pair from its row face (the
-                                 row-only kernel).  Results agree to rounding */
+                                 symmetric pair kernel), while its column partial sums fit in 64 GiB
+                                 of the context's scratch (about 1,430,000 faces with the gradient)
+                                 and that scratch can be allocated; 0, or beyond that: every
+                                 ordered pair from its row face (the row-only kernel).  Results
+                                 agree to rounding.  The scratch stays allocated with the context
+                                 (tpe_destroy frees it) */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */

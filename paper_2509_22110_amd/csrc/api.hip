@@ -72,8 +72,10 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
                        uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, double* acc64, uint32_t* flags,
                        unsigned long long* stats, hipStream_t st);
-// the symmetric kernel is used while its column partials fit in this many bytes
-constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)6 << 30;
+// the symmetric kernel is used while its column partials (32 B per face and earlier super block of
+// 512 faces) fit in this many bytes: about 1,430,000 faces, of the GPU's 288 GB of HBM; if the
+// allocation fails the call runs the row-only kernel instead
+constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
@@ -488,7 +490,14 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     DeviceGuard dg(ctx->device);
     Plan P;
     plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
-    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    rc = ensure_arena(ctx, P.bytes);
+    if (rc == TPE_ERR_OOM && P.sym) {  // no room for the column partials: the row-only kernel
+        P = Plan();
+        plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, false, p3);
+        ctx->err.clear();
+        rc = ensure_arena(ctx, P.bytes);
+    }
+    if (rc) return rc;
     layout(P, ctx->arena, grad);
     hipStream_t st = ctx->stream;
     if ((rc = prepare(ctx, P, X, F))) return rc;
