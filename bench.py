@@ -276,6 +276,51 @@ def p3_leg(args, T, M, torch, dev, cfg, F):
             "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
 
 
+def p3_farfield_leg(args, T, M, torch, dev):
+    """The far field on curved cubic elements: the level-6 sphere (81,920 elements, the level-5
+    workload's deformation) with 3 points per element, monopole and learned, against the exact
+    path with the same points."""
+    X10, F10 = M.p3_sphere(6, 2, 8, 0.05, 0)
+    Xd = torch.from_numpy(X10).to(dev)
+    Fd = torch.from_numpy(F10).to(dev)
+    ctx = T.context(dev)
+    ctx.set_option(T.OPT_QUADRATURE, 3)
+    try:
+        E0, G0 = T.gradient_p3(Xd, Fd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E0, G0 = T.gradient_p3(Xd, Fd)
+        torch.cuda.synchronize()
+        t_exact = time.perf_counter() - t0
+    finally:
+        ctx.set_option(T.OPT_QUADRATURE, 1)
+    t0 = time.perf_counter()
+    tree = T.build_tree_p3(Xd, Fd, leaf=32, points=3)
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
+    mlp = T.MLP.load(args.mlp, dev) if os.path.exists(args.mlp) else None
+    out = {"workload": f"level-6 sphere as {F10.shape[0]} curved cubic elements ({X10.shape[0]} nodes), "
+                       f"3 points per element, theta {args.theta}, leaf 32",
+           "exact_ms": round(t_exact * 1e3, 3), "tree_build_ms": round(t_tree * 1e3, 3)}
+    for name, m in (("monopole", None), ("learned", mlp)):
+        if name == "learned" and m is None:
+            continue
+        for _ in range(2):
+            E, G = T.farfield_p3(tree, Xd, Fd, theta=args.theta, mlp=m)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E, G = T.farfield_p3(tree, Xd, Fd, theta=args.theta, mlp=m)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": round(dt * 1e3, 3), "speedup_vs_exact": round(t_exact / dt, 2),
+                     "rel_grad_maxnorm": float((G - G0).abs().max() / G0.abs().max()),
+                     "rel_energy": abs(float(E) - float(E0)) / abs(float(E0))}
+    ctx.sync_check()
+    return out
+
+
 def exponents_leg(args, T, torch, dev, cfg, X, F, P):
     """The exact gradient with other exponents (the generic pair kernel, -m extra multiplications
     by |d|^2 per pair) on the same workload."""
@@ -397,6 +442,7 @@ def main():
     quad = None if args.no_conf else quad_leg(args, T, M, torch, dev, cfg, X, F)
     expo = None if args.no_conf else exponents_leg(args, T, torch, dev, cfg, X, F, P)
     p3 = None if args.no_conf or args.config != "C2" else p3_leg(args, T, M, torch, dev, cfg, F)
+    p3ff = None if args.no_farfield else p3_farfield_leg(args, T, M, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -426,6 +472,7 @@ def main():
         "quadrature6": quad,
         "other_exponents": expo,
         "p3_elements": p3,
+        "p3_farfield": p3ff,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

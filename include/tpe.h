@@ -198,6 +198,19 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
                  const tpe_mlp* mlp, double* E_dev, double* G_dev);
 
+/* The same far field on curved cubic elements (F10 and V as for tpe_energy_p3).  The tree
+ * (tpe_build_tree_p3) is built over the quadrature points of the elements, with the rule chosen by
+ * TPE_OPT_QUADRATURE at build time (1, 3 or 6 points); its items are those point records, so
+ * clusters gather points, a cluster acts on each point of a target block as one pseudo-record,
+ * and near pairs of points are summed exactly with the exclusion of element pairs sharing a
+ * corner node.  theta = 0 reproduces tpe_gradient_p3 with the same rule to rounding.  The ordering
+ * is kept; positions, weights, normals and moments are recomputed from X on every call. */
+int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
+                      int32_t leaf_size, tpe_tree** out);
+int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F10,
+                    int64_t nF, double q, double p, double scale, double theta, const tpe_mlp* mlp,
+                    double* E_dev, double* G_dev);
+
 /* Dual-tree (cluster-cluster) approximation of E and dE/dX on the tree: both integrals clustered,
  * the scheme the paper compares against in Sec. 3.2 (its own clusters only the inner integrals),
  * with the derivatives carried back from the clusters to the faces.  A pair of same-level clusters

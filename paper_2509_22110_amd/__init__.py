@@ -17,7 +17,7 @@ import threading
 
 import torch
 
-__all__ = ["TPEError", "lib", "energy", "gradient", "energy_p3", "gradient_p3", "sort_pairs", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
+__all__ = ["TPEError", "lib", "energy", "gradient", "energy_p3", "gradient_p3", "sort_pairs", "build_tree_p3", "farfield_p3", "conf_energy", "conf_gradient", "pair_count", "TPEFunction",
            "tpe_energy",
            "context", "LIB_PATH", "STATUS", "Tree", "build_tree", "farfield", "MLP"]
 
@@ -76,6 +76,8 @@ def lib():
             "tpe_tree_destroy": ([P], I),
             "tpe_farfield": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
             "tpe_farfield_dual": ([P, P, P, I64, P, I64, D, D, D, D, P, P], I),
+            "tpe_build_tree_p3": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
+            "tpe_farfield_p3": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
             "tpe_farfield_stats": ([P, ctypes.POINTER(I64)], I),
             "tpe_farfield_samples": ([P, P, P, I64, P, I64, D, ctypes.c_uint64, D, ctypes.c_int32, I64, P, P, P, P],
                                      I),
@@ -284,6 +286,40 @@ class Tree:
 
 def build_tree(X, F, leaf: int = 32) -> Tree:
     return Tree(X, F, leaf)
+
+
+class TreeP3(Tree):
+    """Cluster tree over the quadrature points of curved cubic elements; see tpe_build_tree_p3."""
+
+    def __init__(self, X, F10, leaf: int = 32, points: int = 3):
+        X, F10 = _check_mesh(X, F10, 10)
+        c = context(X.device)
+        h = ctypes.c_void_p()
+        c.set_option(OPT_QUADRATURE, int(points))
+        try:
+            c.check(lib().tpe_build_tree_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0], int(leaf),
+                                            ctypes.byref(h)))
+        finally:
+            c.set_option(OPT_QUADRATURE, 1)
+        self.h, self.nF, self.V, self.leaf, self.device = h, F10.shape[0], X.shape[0], leaf, X.device
+        self.points = int(points)
+
+
+def build_tree_p3(X, F10, leaf: int = 32, points: int = 3) -> TreeP3:
+    return TreeP3(X, F10, leaf, points)
+
+
+def farfield_p3(tree: TreeP3, X, F10, theta=0.5, q=6.0, p=12.0, scale=1.0, mlp=None, out=None, energy_out=None,
+                want_grad=True):
+    """Barnes-Hut far field (E, G) on curved cubic elements, with the tree's quadrature points."""
+    X, F10 = _check_mesh(X, F10, 10)
+    G = (out if out is not None else torch.empty_like(X)) if want_grad else None
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_farfield_p3(c.h, tree.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0], float(q),
+                                  float(p), float(scale), float(theta), mlp.h if mlp is not None else None,
+                                  E.data_ptr(), G.data_ptr() if G is not None else None))
+    return E, G
 
 
 def farfield(tree: Tree, X, F, theta=0.5, q=6.0, p=12.0, scale=1.0, mlp=None, out=None, energy_out=None,

@@ -36,9 +36,10 @@ hipError_t launch_adjacency(const int4* colv, int64_t nF, int64_t V, uint32_t* c
 hipError_t launch_p3_records(const double* X, int64_t V, const int32_t* F10, int64_t nF, int Q, int64_t Fp,
                              const uint32_t* perm, const uint32_t* bbox, double* org, ColRec* cols, int4* colv,
                              double* c64, double* geo, uint32_t* cnt, uint32_t* flags, hipStream_t st);
-hipError_t launch_p3_nodes(const int32_t* F10, int64_t nF, int Q, int64_t V, const uint32_t* perm, uint32_t* cnt,
-                           uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws, hipStream_t st);
-hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, int Q,
+hipError_t launch_p3_nodes(const int32_t* F10, int64_t n, int step, int Q, int64_t V, const uint32_t* perm,
+                           uint32_t* cnt, uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws,
+                           hipStream_t st);
+hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t n, int step, int Q,
                               const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
                               const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
                               double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
@@ -83,7 +84,7 @@ hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, c
                          hipStream_t st);
 int finalize_blocks(int64_t nF);
 int tree_height(int64_t nF, int leaf);
-hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, int H, float4* cen,
+hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, int leaf, int H, float4* cen,
                           uint32_t* nb, uint32_t* perm, uint32_t* keys, uint32_t* ktmp, uint32_t* vtmp,
                           uint32_t* hist, uint32_t* off, hipStream_t st);
 size_t tree_node_bytes(int H);
@@ -184,7 +185,9 @@ struct tpe_tree {
     int device = 0;
     int64_t nF = 0, V = 0;
     int leaf = 32, H = 0;
-    uint32_t* perm = nullptr;  // sorted position -> input face index (device, nF entries)
+    int Q = 0;                 // 0: a tree over faces; >= 1: over the Q quadrature points of each curved element
+    int64_t n = 0;             // items: nF faces, or nF Q points
+    uint32_t* perm = nullptr;  // sorted position -> input item (face f, or point r = Q f + point) (device, n entries)
 };
 
 namespace {
@@ -298,9 +301,11 @@ void layout(Plan& P, char* base, bool grad) {
         P.ncursor = c.take<uint32_t>(V);
     }
     P.zero_end = c.take<uint32_t>(0);
+    // the exact path's P3 finalize works per element, the far field's per point record
+    const int64_t p3_items = P.treeH >= 0 ? nR : nF;
     if (P.p3 && grad) {
         P.noff = c.take<uint32_t>(V + 1);
-        P.nlist = c.take<uint32_t>((size_t)P3_NODES * nF);
+        P.nlist = c.take<uint32_t>((size_t)P3_NODES * p3_items);
     }
     P.touch = c.take<uint32_t>((size_t)P.nrb * P.touch_words);
     P.voff = c.take<uint32_t>(V + 1);
@@ -316,7 +321,7 @@ void layout(Plan& P, char* base, bool grad) {
         P.colpart = c.take<float>((size_t)sym_colpart_floats(P.ssc, grad));
         P.first = c.take<int>((size_t)P.ssc.W);
     }
-    P.corner = c.take<double>(grad ? std::max<int64_t>(9 * nR, P.p3 ? 3 * P3_NODES * nF : 0) : 1);
+    P.corner = c.take<double>(grad ? std::max<int64_t>(9 * nR, P.p3 ? 3 * P3_NODES * p3_items : 0) : 1);
     P.acc64 = c.take<double>((size_t)(grad ? NACC : 1) * Fp);
     P.epart = c.take<double>(P.fin_blocks);
     if (P.FpY > 0) {
@@ -330,7 +335,7 @@ void layout(Plan& P, char* base, bool grad) {
         P.nodes64 = c.take<char>(tree_node_bytes(P.treeH));
         P.recs = c.take<char>(tree_rec_bytes(P.treeH));
         P.balls = c.take<float4>(Fp / 64);
-        P.cen4 = c.take<float4>(nF);
+        P.cen4 = c.take<float4>(nR);
         P.nbox = c.take<uint32_t>((size_t)6 << std::max(P.treeH - 1, 0));
         if (P.dual_leaf > 0) {
             const int Hd = dual_level(P.treeH, P.dual_leaf);
@@ -502,7 +507,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     hipStream_t st = ctx->stream;
     if ((rc = prepare(ctx, P, X, F))) return rc;
     if (p3 && grad)
-        HIPCHK(launch_p3_nodes(F, nF, P.Q, V, P.vals, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
+        HIPCHK(launch_p3_nodes(F, nF, P.Q, P.Q, V, P.vals, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -519,7 +524,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) HIPCHK(launch_sym_merge(grad, P.part, P.colpart, P.first, P.ssc, P.nR, P.Fp, P.acc64, st));
     if (p3) {
-        HIPCHK(launch_p3_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, nF, P.Q, P.sym ? P.acc64 : nullptr,
+        HIPCHK(launch_p3_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, nF, P.Q, P.Q, P.sym ? P.acc64 : nullptr,
                                   P.vals, F, V, X, P.bbox, q, p, scale, 0.5, P.corner, P.epart, P.ticket, ctx->dflags,
                                   E, st));
         if (grad) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G, st));
@@ -766,14 +771,15 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
     HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(build_kd_order(X, V, F, nF, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist, P.hoff,
-                          st));
+    HIPCHK(build_kd_order(X, V, F, nF, 0, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist,
+                          P.hoff, st));
     tpe_tree* t = new tpe_tree();
     t->device = ctx->device;
     t->nF = nF;
     t->V = V;
     t->leaf = leaf_size;
     t->H = tree_height(nF, leaf_size);
+    t->n = nF;
     if (hipMalloc(&t->perm, nF * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         delete t;
@@ -795,6 +801,107 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     return TPE_OK;
 }
 
+int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, int32_t leaf_size,
+                      tpe_tree** out) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    int rc = check_common(ctx, X, V, F10, nF, 6.0, 12.0);
+    if (rc) return rc;
+    if (leaf_size < 1 || leaf_size > 4096) return fail(ctx, TPE_ERR_INVALID_ARG, "leaf_size must be in [1, 4096]");
+    const int Q = ctx->quad;
+    const int64_t n = nF * Q;
+    if (n > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
+    DeviceGuard dg(ctx->device);
+    const int H = tree_height(n, leaf_size);
+    Plan P;
+    plan(P, ctx, nF, V, false, H, 0, 0, Q, false, true);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, false);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F10, P3_NODES, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(build_kd_order(X, V, F10, nF, Q, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist,
+                          P.hoff, st));
+    tpe_tree* t = new tpe_tree();
+    t->device = ctx->device;
+    t->nF = nF;
+    t->V = V;
+    t->leaf = leaf_size;
+    t->H = H;
+    t->Q = Q;
+    t->n = n;
+    if (hipMalloc(&t->perm, n * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete t;
+        return fail(ctx, TPE_ERR_OOM, "tree permutation allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(t->perm, P.vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(t->perm);
+        delete t;
+        return hip_fail(ctx, e, "tree permutation copy");
+    }
+    if (ctx->sync_checks && (rc = report_flags(ctx))) {
+        (void)hipFree(t->perm);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return TPE_OK;
+}
+
+// The far field on curved cubic elements: the tree's items are the quadrature points, so the
+// walk, the moments and the near ranges run on point records exactly as on faces, the records'
+// vertex ids being the elements' corners; the finalize takes one record per item.
+int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F10, int64_t nF,
+                    double q, double p, double scale, double theta, const tpe_mlp* mlp, double* E_dev,
+                    double* G_dev) {
+    int rc = check_common(ctx, X, V, F10, nF, q, p);
+    if (rc) return rc;
+    if (!tree) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree");
+    if (tree->Q < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built over flat faces (tpe_build_tree)");
+    if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
+    if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be >= 0");
+    if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
+    if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
+    if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    if (mlp && mlp->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "MLP lives on another device");
+    DeviceGuard dg(ctx->device);
+    const int Q = tree->Q;
+    const int64_t n = tree->n;
+    Plan P;
+    plan(P, ctx, nF, V, true, tree->H, 0, 0, Q, false, true);
+    if ((rc = ensure_arena(ctx, P.bytes))) return rc;
+    layout(P, ctx->arena, true);
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
+    HIPCHK(launch_bbox(X, V, F10, P3_NODES, nF, P.bbox, ctx->dflags, st));
+    HIPCHK(launch_p3_records(X, V, F10, nF, Q, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                             ctx->dflags, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, n, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    if (G_dev)
+        HIPCHK(launch_p3_nodes(F10, n, 1, Q, V, tree->perm, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx->kernel_timing) {
+        if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
+    }
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
+    HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
+                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
+    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_p3_finalize(true, nullptr, P.sc, P.Fp, n, 1, Q, P.acc64, tree->perm, F10, V, X, P.bbox, q, p, scale,
+                              0.5, P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
+    if (G_dev) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G_dev, st));
+    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
+    if (ctx->sync_checks) return report_flags(ctx);
+    return TPE_OK;
+}
+
 int tpe_tree_destroy(tpe_tree* t) {
     if (!t) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(t->device);
@@ -809,6 +916,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (rc) return rc;
     if (!tree) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree");
     if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
+    if (tree->Q != 0) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built over curved elements");
     if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
     if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be >= 0");
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
@@ -852,6 +960,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     if (rc) return rc;
     if (!tree) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree");
     if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
+    if (tree->Q != 0) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built over curved elements");
     if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
     if (tree->leaf > 64 || (64 % tree->leaf) != 0)
         return fail(ctx, TPE_ERR_UNSUPPORTED, "the dual-tree far field needs a leaf size dividing 64");
@@ -897,7 +1006,8 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
                          const tpe_mlp* mlp, float* feats, float* targets, float* pred) {
     int rc = check_common(ctx, X, V, F, nF, 6.0, 12.0);
     if (rc) return rc;
-    if (!tree || tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree/mesh mismatch");
+    if (!tree || tree->nF != nF || tree->V != V || tree->Q != 0)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "tree/mesh mismatch");
     if (!feats || !targets) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
     if ((mlp == nullptr) != (pred == nullptr)) return fail(ctx, TPE_ERR_INVALID_ARG, "mlp and pred go together");
     if (!(theta > 0.0) || !(select_prob >= 0.0 && select_prob <= 1.0) || quota < 1 || quota > 1024 ||

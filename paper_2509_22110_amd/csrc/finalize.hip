@@ -166,17 +166,19 @@ __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* 
     G[3 * v + 2] = g2;
 }
 
-// Curved cubic elements: one thread per sorted element e < nF (records e Q .. e Q + Q - 1, in point
-// order; the element is perm[e Q] / Q).  Each record's row sums give dE/dweight, dE/dn and dE/dx of
+// Curved cubic elements: one thread per item e < n of `step` consecutive records, all points of one
+// element (record i is point perm[i] % Q of element perm[i] / Q): the Q records of an element in
+// the exact path (step = Q, records in point order), one record in the far field (step = 1, the
+// tree orders points, not elements).  Each record's row sums give dE/dweight, dE/dn and dE/dx of
 // its point as in finalize_kernel; with the element's map recomputed at the point,
 //     g_J = (dE/dweight) (w / 2) n + (I - n n^T) (dE/dn) / |J|,
 //     node k += phi_k dE/dx + (d phi_k / ds) (x_t x g_J) + (d phi_k / dt) (g_J x x_s),
-// summed over the element's points in order and written to corner[e][k] (10 x 3 FP64): the
-// gather's slot 10 e + k.
+// summed over the item's records in order and written to corner[e][k] (10 x 3 FP64): the gather's
+// slot 10 e + k.
 template <bool GRAD>
 __global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restrict__ part, Sched sc,
-                                                          const double* __restrict__ accs, int64_t Fp, int64_t nF,
-                                                          int Q, const uint32_t* __restrict__ perm,
+                                                          const double* __restrict__ accs, int64_t Fp, int64_t n,
+                                                          int step, int Q, const uint32_t* __restrict__ perm,
                                                           const int32_t* __restrict__ F10, int64_t V,
                                                           const double* __restrict__ X,
                                                           const uint32_t* __restrict__ bbox, double q, double p,
@@ -189,8 +191,8 @@ __global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restric
     const int kexp = norm_exp(bbox);
     const double s = ldexp(1.0, kexp);
     const double gs = scale * pow2i(kexp, p - q - 3.0);
-    if (e < nF) {
-        const int64_t f = perm[e * Q] / Q;
+    if (e < n) {
+        const int64_t f = perm[e * step] / Q;
         int32_t id[P3_NODES];
         bool ok = true;
         for (int k = 0; k < P3_NODES; ++k) {
@@ -200,8 +202,9 @@ __global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restric
         double g[P3_NODES][3];
         for (int k = 0; k < P3_NODES; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0;
         bool finite = true;
-        for (int pt = 0; pt < Q; ++pt) {
-            const int64_t i = e * Q + pt;
+        for (int j = 0; j < step; ++j) {
+            const int64_t i = e * step + j;
+            const int pt = (int)(perm[i] % Q);
             double acc[NA];
             row_sums<NA, false>(part, sc, accs, Fp, i, acc);
             double b[3], wq;
@@ -326,18 +329,19 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, int Q,
+// n items of `step` records (see p3_finalize_kernel)
+hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t n, int step, int Q,
                               const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
                               const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
                               double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
                               hipStream_t st) {
-    const int nb = finalize_blocks(nF);
+    const int nb = finalize_blocks(n);
     if (grad)
-        hipLaunchKernelGGL((p3_finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, Q, perm,
-                           F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+        hipLaunchKernelGGL((p3_finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, n, step, Q,
+                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
     else
-        hipLaunchKernelGGL((p3_finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, Q, perm,
-                           F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+        hipLaunchKernelGGL((p3_finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, n, step, Q,
+                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
     return hipGetLastError();
 }
 

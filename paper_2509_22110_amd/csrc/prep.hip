@@ -330,28 +330,28 @@ __global__ void p3_records(const double* __restrict__ X, int64_t V, const int32_
     store_record(i, real, ok, fl, c, n, a, wn, v, pt, org, cols, colv, c64, geo, cnt, flags);
 }
 
-// node -> (sorted element, node slot) adjacency of curved cubic elements, for the vertex gather:
-// element e of the sorted order (records e Q .. e Q + Q - 1) is element perm[e Q] / Q; slot
-// 10 e + k is its node k.  p3_node_count adds the per-node counts (cnt zero on entry);
-// p3_node_fill writes the lists (cursor zero on entry; order within a list arbitrary, the gather
-// orders it).
-__global__ void p3_node_count(const int32_t* __restrict__ F10, int64_t nF, int Q, int64_t V,
+// node -> (item, node slot) adjacency of curved cubic elements, for the vertex gather: item e of
+// `step` records (records e step .. e step + step - 1, see p3_finalize_kernel) belongs to element
+// perm[e step] / Q; slot 10 e + k is that element's node k.  p3_node_count adds the per-node
+// counts (cnt zero on entry); p3_node_fill writes the lists (cursor zero on entry; order within a
+// list arbitrary, the gather orders it).
+__global__ void p3_node_count(const int32_t* __restrict__ F10, int64_t n, int step, int Q, int64_t V,
                               const uint32_t* __restrict__ perm, uint32_t* __restrict__ cnt) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= nF) return;
-    const int64_t f = perm[e * Q] / Q;
+    if (e >= n) return;
+    const int64_t f = perm[e * step] / Q;
     for (int k = 0; k < P3_NODES; ++k) {
         const int32_t v = F10[P3_NODES * f + k];
         if (v >= 0 && v < V) atomicAdd(&cnt[v], 1u);
     }
 }
 
-__global__ void p3_node_fill(const int32_t* __restrict__ F10, int64_t nF, int Q, int64_t V,
+__global__ void p3_node_fill(const int32_t* __restrict__ F10, int64_t n, int step, int Q, int64_t V,
                              const uint32_t* __restrict__ perm, const uint32_t* __restrict__ off,
                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ list) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= nF) return;
-    const int64_t f = perm[e * Q] / Q;
+    if (e >= n) return;
+    const int64_t f = perm[e * step] / Q;
     for (int k = 0; k < P3_NODES; ++k) {
         const int32_t v = F10[P3_NODES * f + k];
         if (v >= 0 && v < V) {
@@ -448,14 +448,16 @@ hipError_t launch_p3_records(const double* X, int64_t V, const int32_t* F10, int
     return hipGetLastError();
 }
 
-// node CSR of the gather: cnt and cursor (V entries each) zero on entry; ws: scan workspace
-// (scan_ws_words(V) words)
-hipError_t launch_p3_nodes(const int32_t* F10, int64_t nF, int Q, int64_t V, const uint32_t* perm, uint32_t* cnt,
-                           uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws, hipStream_t st) {
-    hipLaunchKernelGGL(p3_node_count, dim3(nblk(nF, 256)), dim3(256), 0, st, F10, nF, Q, V, perm, cnt);
+// node CSR of the gather over n items of `step` records: cnt and cursor (V entries each) zero on
+// entry; ws: scan workspace (scan_ws_words(V) words); list: 10 n entries
+hipError_t launch_p3_nodes(const int32_t* F10, int64_t n, int step, int Q, int64_t V, const uint32_t* perm,
+                           uint32_t* cnt, uint32_t* off, uint32_t* cursor, uint32_t* list, uint32_t* ws,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(p3_node_count, dim3(nblk(n, 256)), dim3(256), 0, st, F10, n, step, Q, V, perm, cnt);
     hipError_t e = launch_exclusive_scan(cnt, V, off, ws, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(p3_node_fill, dim3(nblk(nF, 256)), dim3(256), 0, st, F10, nF, Q, V, perm, off, cursor, list);
+    hipLaunchKernelGGL(p3_node_fill, dim3(nblk(n, 256)), dim3(256), 0, st, F10, n, step, Q, V, perm, off, cursor,
+                       list);
     return hipGetLastError();
 }
 

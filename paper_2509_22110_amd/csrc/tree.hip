@@ -613,6 +613,30 @@ __global__ void kd_centroids(const double* __restrict__ X, int64_t V, const int3
     perm[f] = (uint32_t)f;
 }
 
+// Curved cubic elements: item r = quadrature point r % Q of element r / Q (nodes F10[10 (r / Q) ..]),
+// at x(b) of the element's cubic map; the tree is built over these points.
+__global__ void kd_centroids_p3(const double* __restrict__ X, int64_t V, const int32_t* __restrict__ F10, int64_t nF,
+                                int Q, float4* __restrict__ cen, uint32_t* __restrict__ perm) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nF * Q) return;
+    const int64_t f = r / Q;
+    double b[3], wq;
+    quad_point(Q, (int)(r % Q), b, wq);
+    double phi[P3_NODES], ds[P3_NODES], dt[P3_NODES];
+    p3_shape(b, phi, ds, dt);
+    double x[3] = {0.0, 0.0, 0.0};
+    bool ok = true;
+    for (int k = 0; k < P3_NODES; ++k) {
+        const int32_t v = F10[P3_NODES * f + k];
+        if (v < 0 || v >= V) { ok = false; break; }
+        for (int d = 0; d < 3; ++d) x[d] += phi[k] * X[3 * (int64_t)v + d];
+    }
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok && isfinite(x[0] + x[1] + x[2])) c = make_float4((float)x[0], (float)x[1], (float)x[2], 0.f);
+    cen[r] = c;
+    perm[r] = (uint32_t)r;
+}
+
 __device__ __forceinline__ uint32_t f2o(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -680,13 +704,21 @@ __global__ void kd_keys(const uint32_t* __restrict__ perm, const float4* __restr
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
                       uint32_t* hist, uint32_t* off, hipStream_t st);
 
-// perm (nF entries) <- k-d order of the faces for a tree of height H over leaves of `leaf` faces.
-// Scratch: cen (nF float4), nb (6 * 2^max(H-1,0) words), keys/ktmp/vtmp (nF words), hist/off.
-hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, int H, float4* cen,
-                          uint32_t* nb, uint32_t* perm, uint32_t* keys, uint32_t* ktmp, uint32_t* vtmp,
+// perm (n entries) <- k-d order of the items for a tree of height H over leaves of `leaf` items.
+// Items: the nF faces (Q = 0: F holds 3 vertex ids per face), or the Q quadrature points of each
+// of the nF curved cubic elements (Q >= 1: F holds 10 node ids per element), n = nF Q.
+// Scratch: cen (n float4), nb (6 * 2^max(H-1,0) words), keys/ktmp/vtmp (n words), hist/off.
+hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, int leaf, int H,
+                          float4* cen, uint32_t* nb, uint32_t* perm, uint32_t* keys, uint32_t* ktmp, uint32_t* vtmp,
                           uint32_t* hist, uint32_t* off, hipStream_t st) {
+    if (Q > 0) {
+        hipLaunchKernelGGL(kd_centroids_p3, dim3((unsigned)((nF * Q + 255) / 256)), dim3(256), 0, st, X, V, F, nF, Q,
+                           cen, perm);
+        nF *= Q;
+    } else {
+        hipLaunchKernelGGL(kd_centroids, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, st, X, V, F, nF, cen, perm);
+    }
     const unsigned g = (unsigned)((nF + 255) / 256);
-    hipLaunchKernelGGL(kd_centroids, dim3(g), dim3(256), 0, st, X, V, F, nF, cen, perm);
     for (int level = 0; level < H; ++level) {
         const int64_t nnodes = (int64_t)1 << level;
         const int64_t node_faces = ((int64_t)1 << (H - level)) * leaf;

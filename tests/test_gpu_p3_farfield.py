@@ -1,0 +1,86 @@
+"""The far field on curved cubic elements (tpe_build_tree_p3 / tpe_farfield_p3): theta = 0 is the
+exact P3 scheme (GPU path and oracle), the error falls with theta, the learned correction applies,
+results are deterministic, and trees of the other kind are refused."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+from tests.gpu_util import log, needs_gpu, rel_energy, rel_grad_maxnorm, tpe, upload
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+E_TOL, G_TOL = 1e-6, 1e-5
+CKPT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2509_22110_amd", "data",
+                    "farfield_mlp.bin")
+
+
+def exact_p3(T, Xd, Fd, Q):
+    ctx = T.context(Xd.device)
+    ctx.set_option(T.OPT_QUADRATURE, Q)
+    try:
+        return T.gradient_p3(Xd, Fd)
+    finally:
+        ctx.set_option(T.OPT_QUADRATURE, 1)
+
+
+@pytest.mark.parametrize("Q,leaf", [(1, 32), (3, 32), (6, 7)])
+def test_theta_zero_is_exact(Q, leaf):
+    T = tpe()
+    X10, F10 = M.p3_sphere(2, 2, 8, 0.05, 1)
+    Xd, Fd = upload(X10, F10)
+    tree = T.build_tree_p3(Xd, Fd, leaf=leaf, points=Q)
+    E, G = T.farfield_p3(tree, Xd, Fd, theta=0.0)
+    Eo, Go = oracle.gradient_p3(X10, F10, Q)
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("P3 far field theta 0, Q", Q, "leaf", leaf, "rel E", eE, "rel G", eG)
+    assert eE <= E_TOL and eG <= G_TOL
+
+
+def test_error_decreases_with_theta_and_learned():
+    T = tpe()
+    X10, F10 = M.p3_sphere(4, 2, 8, 0.05, 3)
+    Xd, Fd = upload(X10, F10)
+    E0, G0 = exact_p3(T, Xd, Fd, 3)
+    E0, G0 = float(E0.cpu()), G0.cpu().numpy()
+    tree = T.build_tree_p3(Xd, Fd, leaf=32, points=3)
+    errs = []
+    for th in (0.25, 0.5, 0.75):
+        E, G = T.farfield_p3(tree, Xd, Fd, theta=th)
+        errs.append(rel_grad_maxnorm(G.cpu().numpy(), G0))
+        log("P3 L4 Q3 theta", th, "rel E", rel_energy(float(E.cpu()), E0), "rel G", errs[-1])
+    assert errs[0] < errs[1] < errs[2] and errs[1] < 5e-3
+    mlp = T.MLP.load(CKPT, Xd.device)
+    E, G = T.farfield_p3(tree, Xd, Fd, theta=0.5, mlp=mlp)
+    eL = rel_grad_maxnorm(G.cpu().numpy(), G0)
+    log("P3 L4 Q3 theta 0.5 learned: rel E", rel_energy(float(E.cpu()), E0), "rel G", eL)
+    assert np.isfinite(float(E.cpu())) and eL < 2 * errs[1]
+
+
+def test_deterministic_tree_reuse_and_errors():
+    T = tpe()
+    X10, F10 = M.p3_sphere(3, 2, 8, 0.05, 2)
+    Xd, Fd = upload(X10, F10)
+    tree = T.build_tree_p3(Xd, Fd, leaf=32, points=3)
+    E1, G1 = T.farfield_p3(tree, Xd, Fd, theta=0.5)
+    E2, G2 = T.farfield_p3(tree, Xd, Fd, theta=0.5)
+    assert float(E1.cpu()) == float(E2.cpu()) and np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+    # the ordering serves moved positions: theta 0 is still the exact scheme there
+    Xm = Xd - 1e-3 * G1 / G1.abs().max()
+    E, G = T.farfield_p3(tree, Xm, Fd, theta=0.0)
+    E0, G0 = exact_p3(T, Xm, Fd, 3)
+    assert rel_energy(float(E.cpu()), float(E0.cpu())) <= E_TOL
+    assert rel_grad_maxnorm(G.cpu().numpy(), G0.cpu().numpy()) <= G_TOL
+    # trees of the other kind, other sizes
+    c = M.make_config("C1")
+    Xf, Ff = upload(c.X, c.F)
+    flat = T.build_tree(Xf, Ff)
+    with pytest.raises(T.TPEError):
+        T.farfield_p3(flat, Xd, Fd)
+    with pytest.raises(T.TPEError):
+        T.farfield(tree, Xf, Ff)
+    X2, F2 = M.p3_sphere(2)
+    X2d, F2d = upload(X2, F2)
+    with pytest.raises(T.TPEError):
+        T.farfield_p3(tree, X2d, F2d)
