@@ -212,25 +212,43 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int = 32):
     return keys, vals
 
 
-def energy_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None) -> torch.Tensor:
+class _Points:
+    """Sets the context's quadrature rule for one call (None: leave it as it is)."""
+
+    def __init__(self, c, points):
+        self.c, self.points = c, points
+
+    def __enter__(self):
+        if self.points is not None:
+            self.c.set_option(OPT_QUADRATURE, int(self.points))
+
+    def __exit__(self, *exc):
+        if self.points is not None:
+            self.c.set_option(OPT_QUADRATURE, 1)
+
+
+def energy_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None, points=None) -> torch.Tensor:
     """E on curved cubic elements (X: all nodes float64 [V, 3]; F10: int32 [nF, 10], corners first),
-    with the context's quadrature rule on both integrals."""
+    with `points` (1, 3 or 6) quadrature points per element on both integrals (None: the
+    context's TPE_OPT_QUADRATURE)."""
     X, F10 = _check_mesh(X, F10, 10)
     E = out if out is not None else torch.empty((), dtype=torch.float64, device=X.device)
     c = context(X.device)
-    c.check(lib().tpe_energy_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
-                                float(q), float(p), float(scale), E.data_ptr()))
+    with _Points(c, points):
+        c.check(lib().tpe_energy_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
+                                    float(q), float(p), float(scale), E.data_ptr()))
     return E
 
 
-def gradient_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
+def gradient_p3(X, F10, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None, points=None):
     """(E, dE/dX) on curved cubic elements (see energy_p3)."""
     X, F10 = _check_mesh(X, F10, 10)
     G = out if out is not None else torch.empty_like(X)
     E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
     c = context(X.device)
-    c.check(lib().tpe_gradient_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
-                                  float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
+    with _Points(c, points):
+        c.check(lib().tpe_gradient_p3(c.h, X.data_ptr(), X.shape[0], F10.data_ptr(), F10.shape[0],
+                                      float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
     return E, G
 
 
@@ -467,33 +485,51 @@ def pair_count(F, V: int) -> int:
     return int(n.value)
 
 
+def _energy_of(X, F, q, p, scale, tree, theta, mlp, points):
+    """E of the surface (F: 3 vertex ids per face, or 10 node ids per curved element)."""
+    if F.shape[1] == 10:
+        if tree is None:
+            return energy_p3(X, F, q, p, scale, points=points)
+        return farfield_p3(tree, X, F, theta, q, p, scale, mlp, want_grad=False)[0]
+    if tree is None:
+        return energy(X, F, q, p, scale)
+    return farfield(tree, X, F, theta, q, p, scale, mlp, want_grad=False)[0]
+
+
+def _gradient_of(X, F, q, p, scale, tree, theta, mlp, points, out=None, energy_out=None):
+    """(E, dE/dX) of the surface, flat faces or curved elements (see _energy_of)."""
+    if F.shape[1] == 10:
+        if tree is None:
+            return gradient_p3(X, F, q, p, scale, out=out, energy_out=energy_out, points=points)
+        return farfield_p3(tree, X, F, theta, q, p, scale, mlp, out=out, energy_out=energy_out)
+    if tree is None:
+        return gradient(X, F, q, p, scale, out=out, energy_out=energy_out)
+    return farfield(tree, X, F, theta, q, p, scale, mlp, out=out, energy_out=energy_out)
+
+
 class TPEFunction(torch.autograd.Function):
-    """E = TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp).
+    """E = TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp, points).
 
     forward runs the energy (exact energy kernel, or the far field on `tree`); backward runs the
     hand-written gradient of the same method (tpe_gradient, or tpe_farfield which recomputes the
-    cluster moments from X) and scales it by the incoming gradient.  Only X and F are saved."""
+    cluster moments from X) and scales it by the incoming gradient.  Only X and F are saved.
+    F with 10 ints per row: curved cubic elements (tpe_gradient_p3 / tpe_farfield_p3, `points`
+    quadrature points per element for the exact path)."""
 
     @staticmethod
-    def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None):
+    def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None, points=None):
         ctx.save_for_backward(X, F)
-        ctx.params = (q, p, scale, tree, theta, mlp)
-        if tree is None:
-            return energy(X.detach(), F, q, p, scale)
-        E, _ = farfield(tree, X.detach(), F, theta, q, p, scale, mlp, want_grad=False)
-        return E
+        ctx.params = (q, p, scale, tree, theta, mlp, points)
+        return _energy_of(X.detach(), F, q, p, scale, tree, theta, mlp, points)
 
     @staticmethod
     def backward(ctx, gE):
         X, F = ctx.saved_tensors
-        q, p, scale, tree, theta, mlp = ctx.params
-        if tree is None:
-            _, G = gradient(X.detach(), F, q, p, scale)
-        else:
-            _, G = farfield(tree, X.detach(), F, theta, q, p, scale, mlp)
-        return G * gE, None, None, None, None, None, None, None
+        q, p, scale, tree, theta, mlp, points = ctx.params
+        _, G = _gradient_of(X.detach(), F, q, p, scale, tree, theta, mlp, points)
+        return G * gE, None, None, None, None, None, None, None, None
 
 
-def tpe_energy(X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None):
+def tpe_energy(X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None, points=None):
     """Differentiable energy (autograd through TPEFunction)."""
-    return TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp)
+    return TPEFunction.apply(X, F, q, p, scale, tree, theta, mlp, points)

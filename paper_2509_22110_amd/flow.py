@@ -3,7 +3,9 @@
 The paper treats the tangent-point force explicitly in time (Sec. 3.2: an implicit treatment
 would need a dense system).  This harness takes plain explicit Euler steps of the energy's
 gradient flow, with the exact gradient or the far field, and can judge the far field every k
-steps against the exact gradient.  The update itself is one in-place device axpy.
+steps against the exact gradient.  The update itself is one in-place device axpy.  F with 10 ints
+per row is a mesh of curved cubic elements (all nodes move; `points` quadrature points per
+element for the exact path, the tree's points for the far field).
 """
 from __future__ import annotations
 
@@ -11,7 +13,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import farfield, gradient
+from . import _gradient_of
 
 RHO = 1e-4
 ALPHA = 6.0
@@ -26,7 +28,8 @@ class FlowRecord:
 
 
 def gradient_flow(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=None, theta: float = 0.5,
-                  mlp=None, judge_every: int = 0, stop_on_increase: bool = True, record: FlowRecord | None = None):
+                  mlp=None, judge_every: int = 0, stop_on_increase: bool = True, record: FlowRecord | None = None,
+                  points=None):
     """Run `steps` explicit Euler steps in place on X (float64 cuda [V,3]); returns the record.
 
     With `tree` the far field (optionally with `mlp`) supplies the gradient, and every
@@ -37,13 +40,12 @@ def gradient_flow(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=
     G = torch.empty_like(X)
     E = torch.empty((), dtype=torch.float64, device=X.device)
     prev = None
+    pts = getattr(tree, "points", None) if tree is not None else points
     for k in range(steps):
-        if tree is None:
-            gradient(X, F, scale=scale, out=G, energy_out=E)
-        else:
-            farfield(tree, X, F, theta=theta, scale=scale, mlp=mlp, out=G, energy_out=E)
+        _gradient_of(X, F, 6.0, 12.0, scale, tree, theta, mlp, points, out=G, energy_out=E)
+        if tree is not None:
             if judge_every and k % judge_every == 0:
-                Ee, Ge = gradient(X, F, scale=scale)
+                Ee, Ge = _gradient_of(X, F, 6.0, 12.0, scale, None, theta, None, pts)
                 err = float((G - Ge).abs().max() / Ge.abs().max())
                 rec.judge.append((k, err))
         e = float(E)
@@ -59,7 +61,7 @@ def gradient_flow(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=
 
 def gradient_flow_backtracking(X, F, steps: int, dt: float, scale: float = RHO / ALPHA, tree=None,
                                theta: float = 0.5, mlp=None, judge_every: int = 0, max_halvings: int = 40,
-                               grow: float = 1.0, record: FlowRecord | None = None):
+                               grow: float = 1.0, record: FlowRecord | None = None, points=None):
     """Explicit Euler steps with step rejection: a trial X - dt G whose energy is not below the
     current one is discarded and dt halved (at most `max_halvings` times per step, then
     FloatingPointError).  An accepted step's energy and gradient serve the next step, so each
@@ -71,11 +73,10 @@ def gradient_flow_backtracking(X, F, steps: int, dt: float, scale: float = RHO /
     ens = [torch.empty((), dtype=torch.float64, device=X.device) for _ in range(2)]
     Xt = torch.empty_like(X)
 
+    pts = getattr(tree, "points", None) if tree is not None else points
+
     def evaluate(Y, G, E):
-        if tree is None:
-            gradient(Y, F, scale=scale, out=G, energy_out=E)
-        else:
-            farfield(tree, Y, F, theta=theta, scale=scale, mlp=mlp, out=G, energy_out=E)
+        _gradient_of(Y, F, 6.0, 12.0, scale, tree, theta, mlp, points, out=G, energy_out=E)
         e = float(E)
         return e if e == e and abs(e) != float("inf") else float("inf")
 
@@ -86,7 +87,7 @@ def gradient_flow_backtracking(X, F, steps: int, dt: float, scale: float = RHO /
     for k in range(steps):
         G = bufs[cur]
         if tree is not None and judge_every and k % judge_every == 0:
-            _, Ge = gradient(X, F, scale=scale)
+            _, Ge = _gradient_of(X, F, 6.0, 12.0, scale, None, theta, None, pts)
             rec.judge.append((k, float((G - Ge).abs().max() / Ge.abs().max())))
         rec.energies.append(e)
         for _ in range(max_halvings + 1):

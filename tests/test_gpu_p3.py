@@ -125,3 +125,32 @@ def test_errors():
     Xd, Fd = upload(X10, F10[:, :3])
     with pytest.raises(ValueError):
         T.energy_p3(Xd, Fd)
+
+
+def test_autograd_and_flows():
+    """The autograd function and the gradient flows on curved elements: backward is
+    tpe_gradient_p3's gradient, the flows lower the energy, the far-field flow is judged by the
+    exact path."""
+    import torch
+    from paper_2509_22110_amd.flow import gradient_flow, gradient_flow_backtracking
+    T = tpe()
+    X10, F10 = M.p3_sphere(3, 2, 8, 0.05, 5)
+    Xd, Fd = upload(X10, F10)
+    Xr = Xd.clone().requires_grad_(True)
+    E = T.tpe_energy(Xr, Fd, scale=2.0, points=3)
+    E.backward()
+    E0, G0 = T.gradient_p3(Xd, Fd, scale=2.0, points=3)
+    # forward runs the energy-only kernel, the reference the gradient kernel: equal to rounding
+    assert abs(float(E) - float(E0)) <= E_TOL * abs(float(E0))
+    assert torch.equal(Xr.grad, G0)
+    # explicit steps that move a node by at most 2e-3 at first
+    dt = 2e-3 / float(G0.abs().max()) * 2.0
+    X1 = Xd.clone()
+    rec = gradient_flow(X1, Fd, 4, dt, scale=1.0, points=3)
+    assert all(b < a for a, b in zip(rec.energies, rec.energies[1:]))
+    tree = T.build_tree_p3(Xd, Fd, leaf=32, points=3)
+    X2 = Xd.clone()
+    rec = gradient_flow_backtracking(X2, Fd, 4, dt, scale=1.0, tree=tree, judge_every=2)
+    log("P3 flows: exact", rec.energies, "far-field judge", rec.judge)
+    assert all(b < a for a, b in zip(rec.energies, rec.energies[1:]))
+    assert len(rec.judge) == 2 and max(e for _, e in rec.judge) < 1e-3
