@@ -5,7 +5,8 @@
  * (Sec. 2.2.2 "Self-avoidance", eq. (TP)): with the tangent-point radius
  * R(x,y) = |x-y|^2 / (2 |n(x).(x-y)|),  Phi = rho 2^-alpha / alpha  int_S int_S R^-alpha
  *       = rho / alpha  int_S int_S |n(x).(x-y)|^alpha / |x-y|^(2 alpha).
- * It is discretised on flat triangles with one quadrature point per face (the centroid), and
+ * It is discretised on flat triangles with one quadrature point per face (the centroid) or a
+ * multi-point rule (TPE_OPT_QUADRATURE), or on curved cubic elements (the *_p3 calls), and
  * pairs of faces that share a vertex index are left out (the continuous integrand has no
  * exclusion; on a mesh those pairs sit on the diagonal of the double integral).  For faces
  * S, T with area a, unit normal n and centroid c:
@@ -31,7 +32,8 @@
  *     returns the corresponding status, with it off the status is collected by tpe_check().
  *   - A context is not thread-safe; use one per host thread or serialise calls.
  *   - Supported exponents: (q, p) = (6, 12) (the paper's alpha = 6) everywhere.  tpe_energy and
- *     tpe_gradient (with any quadrature rule) also take even q in {2, 4, 6, 8} with even p,
+ *     tpe_gradient (with any quadrature rule) and tpe_energy_p3 / tpe_gradient_p3 also take
+ *     even q in {2, 4, 6, 8} with even p,
  *     q < p <= 2q (the tangent-point family of Sec. 2.2.2 whose kernel stays in FP32 range on
  *     meshes of unit size); the far field, the learned correction and the confinement energy do
  *     not.  Others return TPE_ERR_UNSUPPORTED.
@@ -47,13 +49,15 @@ extern "C" {
 #endif
 
 typedef struct tpe_ctx tpe_ctx;
-typedef struct tpe_tree tpe_tree;  /* cluster tree: a Morton ordering of the faces (see tpe_build_tree) */
+typedef struct tpe_tree tpe_tree;  /* cluster tree: a k-d ordering of the faces (tpe_build_tree) or of the
+                                      quadrature points of curved elements (tpe_build_tree_p3) */
 typedef struct tpe_mlp tpe_mlp;    /* learned far-field correction (see tpe_mlp_create) */
 
 typedef enum {
     TPE_OK = 0,
     TPE_ERR_INVALID_ARG = -1, /* null pointer, bad size, vertex index out of range, bad exponents */
-    TPE_ERR_DEGENERATE = -2,  /* a face with area <= 1e-300 */
+    TPE_ERR_DEGENERATE = -2,  /* a face with area <= 1e-300 (curved elements: |J| <= 1e-300 at a
+                                 quadrature point) */
     TPE_ERR_NONFINITE = -3,   /* non-finite coordinate, or coincident centroids of a non-adjacent
                                  pair (the energy is infinite for such a non-embedded surface) */
     TPE_ERR_OOM = -4,         /* device allocation of the scratch arena failed */
@@ -71,12 +75,13 @@ typedef enum {
                                  kernel (the pair kernel, or the far-field walk) on the context's
                                  stream; 2: around the finalize + vertex-gather launches; read
                                  back with tpe_kernel_time(); 0 (default): off */
-    TPE_OPT_QUADRATURE = 4,   /* quadrature points per face of tpe_energy / tpe_gradient: 1
-                                 (default, the centroid), 3 (degree 2) or 6 (degree 4); the paper
-                                 integrates both integrals with higher-order rules (Sec. 3.2).  Each
-                                 point pair of two faces sharing no vertex contributes
-                                 W_p W_r a_S a_T |n_S.(x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p.  The far
-                                 field and the confinement energy take 1 only (else
+    TPE_OPT_QUADRATURE = 4,   /* quadrature points per face of tpe_energy / tpe_gradient and per
+                                 element of tpe_energy_p3 / tpe_gradient_p3 / tpe_build_tree_p3:
+                                 1 (default, the centroid), 3 (degree 2) or 6 (degree 4); the
+                                 paper integrates both integrals with higher-order rules (Sec.
+                                 3.2).  Each point pair of two faces sharing no vertex contributes
+                                 W_p W_r a_S a_T |n_S.(x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p.  The flat
+                                 far field and the confinement energy take 1 only (else
                                  TPE_ERR_UNSUPPORTED); at most 2^26 points in all. */
     TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
                                  every unordered pair of faces once and credit both faces (the
