@@ -35,12 +35,13 @@ constexpr int MLP_XS = 40;  // 32 features (bf16)
 constexpr int MLP_HS = 72;  // 64 hidden units (bf16)
 constexpr int MLP_YS = 20;  // 16 outputs (float)
 
-struct MlpScratch {
-    __bf16 h[64 * MLP_HS];  // hidden activations (layers 2 and 3 update them in place)
-    union {
-        __bf16 xs[64 * MLP_XS];  // features (dead after layer 1)
-        float ys[64 * MLP_YS];   // outputs
-    };
+// One region for the features, the hidden activations and the outputs: every layer issues all
+// its loads before its first store (and a wave's LDS accesses run in order), so each layer may
+// overwrite its own input, as layers 2 and 3 do in place.
+union MlpScratch {
+    __bf16 h[64 * MLP_HS];   // hidden activations
+    __bf16 xs[64 * MLP_XS];  // features (layer 1's input)
+    float ys[64 * MLP_YS];   // outputs (layer 4's)
 };
 
 // BF16 conversion, then the ReLU as a packed 16-bit integer max on the bit patterns (a negative
@@ -59,6 +60,9 @@ __device__ __forceinline__ uint2 relu_bf16x4(f32x4 v) { return make_uint2(relu_p
 // the packed weights, read through an explicitly global pointer (global_load, not flat)
 typedef const __attribute__((address_space(1))) MlpPacked GlobalMlp;
 typedef const __attribute__((address_space(1))) f32x4 GlobalF32x4;
+
+// compiler memory barrier between the LDS phases of a wave (see the top of this file)
+__device__ __forceinline__ void lds_phase() { asm volatile("" ::: "memory"); }
 
 // One hidden layer: dst[sample][0..64) = relu(W^T src + b), K = 32 * KT.  dst may be src: every
 // load of src is issued before the first store.  The bias is the C operand of the first k-step.
@@ -83,6 +87,7 @@ __device__ __forceinline__ void mlp_hidden(GlobalMlp* __restrict__ W, int f0, in
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], kt == 0 ? b : acc[mt][nt], 0, 0, 0);
         }
     }
+    lds_phase();  // no store moves above a load of src (dst overlaps it)
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -90,9 +95,8 @@ __device__ __forceinline__ void mlp_hidden(GlobalMlp* __restrict__ W, int f0, in
             *reinterpret_cast<uint2*>(dst + (nt * 16 + r) * MLP_HS + mt * 16 + 4 * q) = relu_bf16x4(acc[mt][nt]);
 }
 
-// y = MLP(x) for the wave's 64 samples (lane = sample).
-__device__ __forceinline__ void lds_phase() { asm volatile("" ::: "memory"); }
 
+// y = MLP(x) for the wave's 64 samples (lane = sample).
 __device__ __forceinline__ void mlp_infer64(const MlpPacked* __restrict__ W, const float (&x)[32], MlpScratch& s,
                                             float (&y)[16]) {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
@@ -127,6 +131,8 @@ __device__ __forceinline__ void mlp_infer64(const MlpPacked* __restrict__ W, con
             o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf, kt == 0 ? b : o[nt], 0, 0, 0);
         }
     }
+    lds_phase();  // the outputs overlap the activations: every load first (float and bf16 stores
+                  // would otherwise count as unrelated to the bf16 loads)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) *reinterpret_cast<f32x4*>(s.ys + (nt * 16 + r) * MLP_YS + 4 * q) = o[nt];
     lds_phase();

@@ -312,8 +312,10 @@ constexpr int FF_NW_LEARNED = 4;  // waves per target block with the learned cor
 // and fold their compensated sums into wave 0's through LDS at the end.  If the stack could
 // overflow, a node that would be opened is evaluated exactly instead (always correct).  Writes
 // the block's FP64 row sums acc64[k][i] (k < NACC).
+// At least 3 waves per SIMD (168 VGPRs): the learned variant needs 199 unconstrained and then spills a
+// few values; with its 9 KB of MLP scratch per wave, 3 work-groups fit a CU's LDS.
 template <bool LEARNED, int NW>
-__global__ __launch_bounds__(64 * NW) void farfield_kernel(const ColRec* __restrict__ cols,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void farfield_kernel(const ColRec* __restrict__ cols,
                                                            const int4* __restrict__ colv,
                                                            const double* __restrict__ c64,
                                                            const double* __restrict__ org,
