@@ -68,11 +68,12 @@ hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, cons
                            int* first, hipStream_t st);
 int dual_level(int H, int leaf);
 int64_t dual_entry_cap(int H, int leaf);
+int64_t dual_part_floats(int H, int leaf);
 hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const int4* colv, const double* c64,
                        const double* geo, const double* org, const void* nodes64, const void* recs_, int64_t nF,
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
-                       uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, double* acc64, uint32_t* flags,
-                       unsigned long long* stats, hipStream_t st);
+                       uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
+                       uint32_t* flags, unsigned long long* stats, hipStream_t st);
 // the symmetric kernel is used while its column partials (32 B per face and earlier super block of
 // 512 faces) fit in this many bytes: about 1,430,000 faces, of the GPU's 288 GB of HBM; if the
 // allocation fails the call runs the row-only kernel instead
@@ -275,6 +276,7 @@ struct Plan {
     uint32_t *doff = nullptr, *dnear = nullptr, *dfar = nullptr, *dcnt = nullptr, *drel = nullptr;
     uint32_t *dent = nullptr, *dscan = nullptr;
     double* dadj = nullptr;
+    float* dpart = nullptr;
     size_t bytes;
 };
 
@@ -348,6 +350,7 @@ void layout(Plan& P, char* base, bool grad) {
             P.dscan = c.take<uint32_t>((size_t)scan_ws_words((int64_t)nl) + 1);
             P.dent = c.take<uint32_t>((size_t)dual_entry_cap(P.treeH, P.dual_leaf));
             P.dadj = c.take<double>(8 * nn);
+            P.dpart = c.take<float>((size_t)dual_part_floats(P.treeH, P.dual_leaf));
         }
     }
     P.bytes = c.off + 256;
@@ -989,7 +992,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_dual(tree->H, tree->leaf, (float)theta, P.cols, P.colv, P.c64, P.geo, P.org, P.nodes64, P.recs, nF,
-                       P.Fp, q, p, P.doff, P.dnear, P.dfar, P.dcnt, P.drel, P.dent, P.dscan, P.dadj, P.acc64,
+                       P.Fp, q, p, P.doff, P.dnear, P.dfar, P.dcnt, P.drel, P.dent, P.dscan, P.dadj, P.dpart, P.acc64,
                        ctx->dflags, ctx->dstats, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));

@@ -174,17 +174,22 @@ __global__ __launch_bounds__(256) void dual_far_eval(int Hd, const NodeRec* __re
     }
 }
 
-// One work-group of DN waves per dual leaf (DUAL_SPAN faces, one per lane): the exact pairs with
-// the faces of the leaf's near list (dealt round-robin over the waves, folded through LDS in wave
-// order), written as FP64 row sums acc64[k][i].
+// DUAL_SPLIT work-groups of DUAL_NW waves per dual leaf (its faces one per lane): the exact pairs
+// with the faces of the leaf's near list.  Near lists are heavy-tailed (a few leaves have tens of
+// times the mean), so each leaf's entries are dealt round-robin over the DUAL_SPLIT x DUAL_NW waves
+// of its work-groups; a work-group folds its waves through LDS in wave order and writes one FP32
+// partial per (row, sum), and dual_near_merge adds a leaf's partials in work-group order.
 constexpr int DUAL_NW = 4;
+constexpr int DUAL_SPLIT = 8;
 
 __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
     int Hd, int64_t span, const ColRec* __restrict__ cols, const int4* __restrict__ colv,
     const double* __restrict__ c64, const double* __restrict__ org, const NodeRec* __restrict__ recs,
     const uint32_t* __restrict__ off, const uint32_t* __restrict__ nnear, const uint32_t* __restrict__ ent,
-    uint32_t cap, int64_t nF, int64_t Fp, double* __restrict__ acc64, unsigned long long* __restrict__ stats) {
+    uint32_t cap, int64_t nF, int64_t Fp, float* __restrict__ part, unsigned long long* __restrict__ stats) {
     __shared__ float red[DUAL_NW - 1][2 * NACC][64];
+    __shared__ unsigned long long wpairs[DUAL_NW];
+    const int split = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int64_t A = ((int64_t)1 << Hd) + blockIdx.x;
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
     const uint32_t o = off[A];
     const uint32_t nn = a.a > 0.f && (uint64_t)o + nnear[A] <= cap ? nnear[A] : 0u;
     uint64_t pairs = 0;
-    for (uint32_t e = wave; e < nn; e += DUAL_NW) {
+    for (uint32_t e = (uint32_t)(split * DUAL_NW + wave); e < nn; e += DUAL_SPLIT * DUAL_NW) {
         const int64_t B = ent[o + e];
         const int64_t f0 = (B - ((int64_t)1 << Hd)) * span, f1 = std::min<int64_t>(nF, f0 + span);
         if (f0 >= f1) continue;
@@ -224,6 +229,7 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
             red[wave - 1][NACC + k][lane] = lo[k];
         }
     }
+    if (lane == 0) wpairs[wave] = pairs;
     __syncthreads();
     if (wave == 0) {
 #pragma unroll
@@ -239,12 +245,31 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
                 lo[k] = (t - hi[k]) - y;
                 hi[k] = t;
             }
-        if (row) {
+        float* o = part + ((size_t)blockIdx.x * DUAL_SPLIT + split) * NACC * 64 + lane;
 #pragma unroll
-            for (int k = 0; k < NACC; ++k) acc64[(size_t)k * Fp + i] = (double)hi[k] - (double)lo[k];
-        }
+        for (int k = 0; k < NACC; ++k) o[(size_t)k * 64] = hi[k] - lo[k];
     }
-    if (stats && lane == 0) atomicAdd(&stats[1], (unsigned long long)pairs * (unsigned long long)std::min<int64_t>(span, nF - i0));
+    // one counter update per work-group (the same word for all of them)
+    if (stats && threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < DUAL_NW; ++w) t += wpairs[w];
+        if (t) atomicAdd(&stats[1], t * (unsigned long long)std::min<int64_t>(span, nF - i0));
+    }
+}
+
+// acc64[k][i] <- the partials of face i's leaf, added in FP64 in work-group order (one thread per
+// (face, sum)).
+__global__ void dual_near_merge(int64_t span, const float* __restrict__ part, int64_t nF, int64_t Fp,
+                                double* __restrict__ acc64) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= nF) return;
+    const int64_t leaf = i / span;
+    const float* pp = part + ((size_t)leaf * DUAL_SPLIT * NACC + k) * 64 + (i - leaf * span);
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < DUAL_SPLIT; ++w) s += (double)pp[(size_t)w * NACC * 64];
+    acc64[(size_t)k * Fp + i] = s;
 }
 
 // One thread per face i: the far-field adjoints of the clusters that contain it (levels 1 .. Hd),
@@ -290,6 +315,8 @@ int dual_level(int H, int leaf) {
     return l;
 }
 int64_t dual_span(int H, int leaf) { return (int64_t)leaf << (H - dual_level(H, leaf)); }
+// FP32 floats of the near partials: DUAL_SPLIT x NACC x 64 per dual leaf
+int64_t dual_part_floats(int H, int leaf) { return ((int64_t)1 << dual_level(H, leaf)) * DUAL_SPLIT * NACC * 64; }
 // entry capacity of the lists (near + far over all levels); an overflow sets FLAG_LISTS, which the
 // caller reports as an error (no list entry beyond the capacity is ever read)
 int64_t dual_entry_cap(int H, int leaf) {
@@ -305,8 +332,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, u
 hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const int4* colv, const double* c64,
                        const double* geo, const double* org, const void* nodes64, const void* recs_, int64_t nF,
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
-                       uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, double* acc64, uint32_t* flags,
-                       unsigned long long* stats, hipStream_t st) {
+                       uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
+                       uint32_t* flags, unsigned long long* stats, hipStream_t st) {
     const NodeF64* nodes = (const NodeF64*)nodes64;
     const NodeRec* recs = (const NodeRec*)recs_;
     const int Hd = dual_level(H, leaf);
@@ -327,8 +354,10 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
     if (nn > 0)
         hipLaunchKernelGGL(dual_far_eval, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, st, Hd, recs, nodes, off,
                            nnear, nfar, ent, cap, q, p, adj, stats);
-    hipLaunchKernelGGL(dual_near_eval, dim3((unsigned)((int64_t)1 << Hd)), dim3(64 * DUAL_NW), 0, st, Hd, span, cols,
-                       colv, c64, org, recs, off, nnear, ent, cap, nF, Fp, acc64, stats);
+    hipLaunchKernelGGL(dual_near_eval, dim3((unsigned)((int64_t)1 << Hd), DUAL_SPLIT), dim3(64 * DUAL_NW), 0, st, Hd,
+                       span, cols, colv, c64, org, recs, off, nnear, ent, cap, nF, Fp, part, stats);
+    hipLaunchKernelGGL(dual_near_merge, dim3((unsigned)((nF + 255) / 256), NACC), dim3(256), 0, st, span, part, nF, Fp,
+                       acc64);
     hipLaunchKernelGGL(dual_down, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, st, Hd, span, nodes, adj, c64, geo,
                        nF, Fp, q, acc64);
     return hipGetLastError();
