@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void dual_far_eval(int Hd, const NodeRec* __re
         const double ng = nu[0] * gnu[0] + nu[1] * gnu[1] + nu[2] * gnu[2];
         for (int d = 0; d < 3; ++d) o[4 + d] = Nn > 0.0 ? (gnu[d] - ng * nu[d]) / Nn : 0.0;
         o[7] = 0.0;
-        if (stats) atomicAdd(&stats[0], (unsigned long long)nf);
+        if (stats && nf) atomicAdd(&stats[0], (unsigned long long)nf);  // same word for every node
     }
 }
 
