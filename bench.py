@@ -134,8 +134,20 @@ def farfield_leg(args, T, M, torch, dev):
     G0 = torch.empty_like(X)
     E0 = torch.empty((), dtype=torch.float64, device=dev)
     t_exact, _ = timed(lambda: T.gradient(X, F, out=G0, energy_out=E0), max(1, args.ff_reps // 2))
-    # the HBM-bound passes of the exact path (finalize + vertex gather), timed with HIP events
     ctx = T.context(dev)
+    # the exact pair kernel at this size, timed with HIP events (the same roofline as the main line)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+    ctx.kernel_time()
+    T.gradient(X, F, out=G0, energy_out=E0)
+    k_ms, k_n = ctx.kernel_time()
+    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+    k_ms /= max(k_n, 1)
+    pairs = T.pair_count(F, cfg.V)
+    k_tflops = FLOP_PER_PAIR * pairs / (k_ms * 1e-3) / 1e12
+    exact_kernel = {"kernel": "pair_sym_kernel<true>", "kernel_avg_ms": round(k_ms, 3), "pairs": pairs,
+                    "achieved": round(k_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(k_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    # the HBM-bound passes of the exact path (finalize + vertex gather), timed with HIP events
     ctx.set_option(T.OPT_KERNEL_TIMING, 2)
     ctx.kernel_time()
     for _ in range(2):
@@ -162,7 +174,8 @@ def farfield_leg(args, T, M, torch, dev):
 
     out = {"workload": f"{args.ff_config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0",
            "faces": cfg.nF, "theta": args.theta, "leaf": 32,
-           "exact_ms": round(t_exact, 3), "tree_build_ms": round(t_tree, 3), "finalize_gather": fg,
+           "exact_ms": round(t_exact, 3), "exact_kernel": exact_kernel, "tree_build_ms": round(t_tree, 3),
+           "finalize_gather": fg,
            "note": "errors against the exact FP32/FP64 path (itself parity-tested against the FP64 "
                    "oracle); far-field ms per gradient exclude the tree build (an ordering that is "
                    "reused while the moments are recomputed from X on every call)",
