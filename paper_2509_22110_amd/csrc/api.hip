@@ -60,7 +60,7 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
 hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
                             const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st);
 int pair_sym_blocks_per_cu(bool grad);
-SymSched make_sym_sched(int64_t Fp, int W);
+SymSched make_sym_sched(int64_t Fp, int W, int tail);
 int64_t sym_part_floats(const SymSched& sc, bool grad);
 int64_t sym_colpart_floats(const SymSched& sc, bool grad);
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
@@ -374,17 +374,20 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
     P.sym = false;
     if (sym) {
         const int64_t Fs = round_up(P.nR, SB);
-        // work-groups: 2 to 8 times the resident count, one step per 16 units a resident slot
+        // work-groups: 1 to 8 times the resident count, one step per 16 units a resident slot
         // would get (the hardware refills the slots of early finishers, which evens out the
-        // finish times; more work-groups add row segments for the merge to read)
-        int W = ctx->resident_sym[grad ? 1 : 0];
+        // finish times; more work-groups add row segments for the merge to read), then one
+        // single-unit work-group per resident slot for the end of the launch
+        const int resident = ctx->resident_sym[grad ? 1 : 0];
+        int W = resident, tail = 0;
         if (ctx->target_waves > 0) {
             W = (int)ctx->target_waves;
         } else {
-            const int64_t units = make_sym_sched(Fs, 1).U;
-            W *= (int)std::max<int64_t>(2, std::min<int64_t>(8, units / ((int64_t)W * 16)));
+            const int64_t units = make_sym_sched(Fs, 1, 0).U;
+            W *= (int)std::max<int64_t>(1, std::min<int64_t>(8, units / ((int64_t)W * 16)));
+            tail = resident;
         }
-        const SymSched t = make_sym_sched(Fs, W);
+        const SymSched t = make_sym_sched(Fs, W, tail);
         if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_MAX_COLPART_BYTES) {
             P.sym = true;
             P.ssc = t;

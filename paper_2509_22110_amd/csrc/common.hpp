@@ -111,8 +111,11 @@ struct Sched {
 // inside the super block, evaluated from both sides as ordered pairs), then its symmetric units,
 // the SYM_COLS-column slices of all later chunks (every unordered pair once, credited to both
 // faces; the columns' share goes to one column partial per symmetric unit).  Units are numbered
-// super block by super block; work-group w takes the contiguous range [begin(w), begin(w+1)) of
-// equal cost, a diagonal unit costing DIAG_COST and a symmetric one SYM_COST.
+// super block by super block; work-group w takes the contiguous range [begin(w), begin(w+1)), a
+// diagonal unit costing DIAG_COST and a symmetric one SYM_COST.  The first W1 work-groups share
+// the cost C1 in equal parts; the other W - W1 share the rest, about one unit each, so that the
+// end of the launch is made of short ranges the hardware hands to whichever slots free up first
+// (W1 = W: equal parts for all).
 // sums per face in the symmetric kernel: K, S0, Sd (3), V = Sn - 2 Sdd (3)
 constexpr int NSYM = 8;
 constexpr int SYM_NW = 4;
@@ -129,6 +132,8 @@ constexpr int SYM_COST = 12 * SYM_COLS / 64, DIAG_COST = 20;
 struct SymSched {
     int64_t U, C;  // units, total cost
     int W, nsb, nch;
+    int W1;        // work-groups sharing the cost C1 (the rest share C - C1)
+    int64_t C1;
     // units of super block I: SBC + SUB (nch - SBC (I + 1)) = A - D I
     __host__ __device__ int64_t ua() const { return SBC + (int64_t)SUB * (nch - SBC); }
     static constexpr int64_t UD = (int64_t)SUB * SBC;
@@ -156,21 +161,32 @@ struct SymSched {
         const int64_t ndiag = (int64_t)SBC * I + (k < SBC ? k : SBC);
         return SYM_COST * u + (int64_t)(DIAG_COST - SYM_COST) * ndiag;
     }
-    // first unit of work-group w: the smallest u with cost(u) W >= w C
+    // does the range of work-group w start at or before a unit whose preceding cost is c?
+    __host__ __device__ bool reached(int64_t c, int w) const {
+        if (w <= W1) return c * W1 >= (int64_t)w * C1;
+        return c >= C1 && (c - C1) * (W - W1) >= (int64_t)(w - W1) * (C - C1);
+    }
+    // first unit of work-group w: the smallest u with reached(cost(u), w)
     __host__ __device__ int64_t begin(int w) const {
         if (w <= 0) return 0;
         if (w >= W) return U;
-        const int64_t target = (int64_t)w * C;
         int64_t lo = 0, hi = U;
         while (lo < hi) {
             const int64_t mid = (lo + hi) / 2;
-            if (cost(mid) * W >= target) hi = mid;
+            if (reached(cost(mid), w)) hi = mid;
             else lo = mid + 1;
         }
         return lo;
     }
-    // the work-group whose range contains unit x
-    __host__ __device__ int wave_of(int64_t x) const { return (int)(cost(x) * W / C); }
+    // the work-group whose range contains unit x (the largest w with reached(cost(x), w))
+    __host__ __device__ int wave_of(int64_t x) const {
+        const int64_t c = cost(x);
+        int w;
+        if (c < C1) w = (int)(c * W1 / C1);
+        else if (W == W1) w = W - 1;
+        else w = W1 + (int)((c - C1) * (W - W1) / (C - C1));
+        return w < W - 1 ? w : W - 1;
+    }
 };
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

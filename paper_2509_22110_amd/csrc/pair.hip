@@ -701,14 +701,24 @@ int pair_sym_blocks_per_cu(bool grad) {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// Fp padded faces (a multiple of SB), W work-groups at most
-SymSched make_sym_sched(int64_t Fp, int W) {
+// Fp padded faces (a multiple of SB); W work-groups in equal parts, plus `tail` work-groups of
+// about one unit each at the end (dropped when that would be more than half the cost)
+SymSched make_sym_sched(int64_t Fp, int W, int tail) {
     SymSched sc;
     sc.nsb = (int)(Fp / SB);
     sc.nch = (int)(Fp / CHUNK);
     sc.U = sc.base(sc.nsb);
     sc.C = (int64_t)SYM_COST * sc.U + (int64_t)(DIAG_COST - SYM_COST) * SBC * sc.nsb;
-    sc.W = (int)std::max<int64_t>(1, std::min<int64_t>(W, sc.U));
+    const int64_t Ct = (int64_t)SYM_COST * std::max(tail, 0);
+    if (tail > 0 && 2 * Ct <= sc.C && (int64_t)W + tail <= sc.U) {
+        sc.W1 = std::max(W, 1);
+        sc.W = sc.W1 + tail;
+        sc.C1 = sc.C - Ct;
+    } else {
+        sc.W = (int)std::max<int64_t>(1, std::min<int64_t>(W, sc.U));
+        sc.W1 = sc.W;
+        sc.C1 = sc.C;
+    }
     return sc;
 }
 
