@@ -139,27 +139,58 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
     energy_tail(e, epart, ticket, E, scale * pow2i(kexp, p - q - 4.0));
 }
 
-// G[v] = sum over the (sorted face, corner) slots incident to v, in ascending slot order: the
-// list of v (filled in arbitrary order) is walked by repeatedly taking its smallest entry above
-// the last one taken (slots are distinct), so the sum is deterministic without sorting the list.
+// G[v] = sum over the (sorted face, corner) slots incident to v, in ascending slot order, so the
+// sum is deterministic although the list of v is filled in arbitrary order.  Up to GATHER_REG
+// slots (every vertex of a regular mesh): the list is read at once, sorted in registers by an
+// odd-even transposition network and the corner loads are issued together, one memory round trip
+// instead of one per slot.  Longer lists are walked by repeatedly taking the smallest entry above
+// the last one taken (slots are distinct).
+constexpr int GATHER_REG = 16;
+
 __global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list, int64_t V,
                               const double* __restrict__ corner, double* __restrict__ G) {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= V) return;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     const uint32_t b = off[v], e = off[v + 1];
-    uint32_t last = 0;
-    for (uint32_t n = b; n < e; ++n) {
-        uint32_t m = 0xffffffffu;
-        for (uint32_t k = b; k < e; ++k) {
-            const uint32_t x = list[k];
-            if ((n == b || x > last) && x < m) m = x;
+    if (e - b <= (uint32_t)GATHER_REG) {
+        const int deg = (int)(e - b);
+        uint32_t L[GATHER_REG];
+#pragma unroll
+        for (int k = 0; k < GATHER_REG; ++k) L[k] = k < deg ? list[b + k] : 0xffffffffu;
+#pragma unroll
+        for (int r = 0; r < GATHER_REG; ++r)
+#pragma unroll
+            for (int k = r & 1; k + 1 < GATHER_REG; k += 2) {
+                const uint32_t lo = min(L[k], L[k + 1]), hi = max(L[k], L[k + 1]);
+                L[k] = lo;
+                L[k + 1] = hi;
+            }
+        double c[GATHER_REG][3];
+#pragma unroll
+        for (int k = 0; k < GATHER_REG; ++k)
+            for (int d = 0; d < 3; ++d) c[k][d] = k < deg ? corner[3 * (size_t)L[k] + d] : 0.0;
+#pragma unroll
+        for (int k = 0; k < GATHER_REG; ++k)
+            if (k < deg) {
+                g0 += c[k][0];
+                g1 += c[k][1];
+                g2 += c[k][2];
+            }
+    } else {
+        uint32_t last = 0;
+        for (uint32_t n = b; n < e; ++n) {
+            uint32_t m = 0xffffffffu;
+            for (uint32_t k = b; k < e; ++k) {
+                const uint32_t x = list[k];
+                if ((n == b || x > last) && x < m) m = x;
+            }
+            last = m;
+            const double* c = corner + 3 * (size_t)m;
+            g0 += c[0];
+            g1 += c[1];
+            g2 += c[2];
         }
-        last = m;
-        const double* c = corner + 3 * (size_t)m;
-        g0 += c[0];
-        g1 += c[1];
-        g2 += c[2];
     }
     G[3 * v + 0] = g0;
     G[3 * v + 1] = g1;
