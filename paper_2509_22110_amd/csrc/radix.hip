@@ -148,17 +148,18 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(const uint32_t* __restr
 }
 
 // Exclusive scan of n counts -> off[0..n] (off[n] = total), in tiles of SCAN_TILE counts.
-// Each tile is read and written coalesced through LDS; a thread scans 8 consecutive counts, the
+// Each tile is read and written coalesced through LDS; a thread scans 16 consecutive counts, the
 // 1024 thread totals are scanned across the work-group with wave shuffles.  Up to SCAN_SMALL_TILES
 // tiles one work-group walks the tiles with a running carry (one launch); above, (1) every
 // work-group reduces its tile, (2) one work-group scans the tile sums, (3) every work-group scans
 // its tile from its tile's offset.
 constexpr int SCAN_T = 1024;
-constexpr int SCAN_PER = 8;
+constexpr int SCAN_PER = 16;
 constexpr int SCAN_TILE = SCAN_T * SCAN_PER;
 constexpr int SCAN_SMALL_TILES = 2;
 
-__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 3); }  // thread t's row starts at 9 t
+// thread t's row starts at (SCAN_PER + 1) t: an odd stride, free of bank conflicts
+__device__ __forceinline__ int scan_pad(int i) { return i + i / SCAN_PER; }
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(SCAN_T) void scan_reduce(const uint32_t* __restrict
 __global__ __launch_bounds__(SCAN_T) void scan_tiles(const uint32_t* __restrict__ in, int64_t n,
                                                      const uint32_t* __restrict__ boff, int tpb,
                                                      uint32_t* __restrict__ off) {
-    __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 8];
+    __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / SCAN_PER];
     __shared__ uint32_t wsum[SCAN_T / 64];
     const int t = threadIdx.x;
     const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
