@@ -183,8 +183,12 @@ int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
  * compact patch.  Only
  * the ordering is stored: the cluster moments are recomputed from the positions passed to each
  * tpe_farfield call, so one tree serves a whole gradient flow as long as the faces stay put in
- * the ordering sense (accuracy, not correctness, depends on it).  *out is owned by the caller
- * (tpe_tree_destroy).  Synchronises the stream. */
+ * the ordering sense (accuracy, not correctness, depends on it).  The tree also keeps, on the
+ * device, the work each target block of 64 faces took in the last tpe_farfield call on it; the
+ * next monopole call (mlp NULL) launches the heaviest blocks first.  That changes only when blocks run, never what
+ * they compute (results are the same bits in any order); calls that share one tree on several
+ * streams at once are still correct.  *out is owned by the caller (tpe_tree_destroy).
+ * Synchronises the stream. */
 int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                    int32_t leaf_size, tpe_tree** out);
 
@@ -209,7 +213,8 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
  * clusters gather points, a cluster acts on each point of a target block as one pseudo-record,
  * and near pairs of points are summed exactly with the exclusion of element pairs sharing a
  * corner node.  theta = 0 reproduces tpe_gradient_p3 with the same rule to rounding.  The ordering
- * is kept; positions, weights, normals and moments are recomputed from X on every call. */
+ * and the per-block work record (as for tpe_build_tree, blocks of 64 points) are kept; positions,
+ * weights, normals and moments are recomputed from X on every call. */
 int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
                       int32_t leaf_size, tpe_tree** out);
 int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V, const int32_t* F10,

@@ -100,7 +100,9 @@ hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const d
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
-                           unsigned long long* stats, hipStream_t st);
+                           unsigned long long* stats, const uint32_t* order, uint32_t* work, hipStream_t st);
+hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
+                           uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -189,6 +191,7 @@ struct tpe_tree {
     int Q = 0;                 // 0: a tree over faces; >= 1: over the Q quadrature points of each curved element
     int64_t n = 0;             // items: nF faces, or nF Q points
     uint32_t* perm = nullptr;  // sorted position -> input item (face f, or point r = Q f + point) (device, n entries)
+    uint32_t* work = nullptr;  // work of each 64-item target block in the last far-field walk (device, (n + 63) / 64)
 };
 
 namespace {
@@ -592,6 +595,33 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     return TPE_OK;
 }
 
+// Device arrays of a new tree: the permutation (copied from the build's sort) and the per-block
+// work record of the far-field walk (zero: the first walk runs in tree order).  Frees the tree on
+// failure.
+int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out) {
+    hipStream_t st = ctx->stream;
+    const int64_t nb = (t->n + 63) / 64;
+    auto drop = [&](int code) {
+        if (t->perm) (void)hipFree(t->perm);
+        if (t->work) (void)hipFree(t->work);
+        delete t;
+        return code;
+    };
+    if (hipMalloc(&t->perm, t->n * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&t->work, nb * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return drop(fail(ctx, TPE_ERR_OOM, "tree allocation failed"));
+    }
+    hipError_t e = hipMemcpyAsync(t->perm, perm, t->n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_fill(t->work, 0u, nb, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return drop(hip_fail(ctx, e, "tree set-up"));
+    int rc;
+    if (ctx->sync_checks && (rc = report_flags(ctx))) return drop(rc);
+    *out = t;
+    return TPE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -786,25 +816,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     t->leaf = leaf_size;
     t->H = tree_height(nF, leaf_size);
     t->n = nF;
-    if (hipMalloc(&t->perm, nF * sizeof(uint32_t)) != hipSuccess) {
-        (void)hipGetLastError();
-        delete t;
-        return fail(ctx, TPE_ERR_OOM, "tree permutation allocation failed");
-    }
-    hipError_t e = hipMemcpyAsync(t->perm, P.vals, nF * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        (void)hipFree(t->perm);
-        delete t;
-        return hip_fail(ctx, e, "tree permutation copy");
-    }
-    if (ctx->sync_checks && (rc = report_flags(ctx))) {
-        (void)hipFree(t->perm);
-        delete t;
-        return rc;
-    }
-    *out = t;
-    return TPE_OK;
+    return finish_tree(ctx, t, P.vals, out);
 }
 
 int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, int32_t leaf_size,
@@ -837,25 +849,7 @@ int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
     t->H = H;
     t->Q = Q;
     t->n = n;
-    if (hipMalloc(&t->perm, n * sizeof(uint32_t)) != hipSuccess) {
-        (void)hipGetLastError();
-        delete t;
-        return fail(ctx, TPE_ERR_OOM, "tree permutation allocation failed");
-    }
-    hipError_t e = hipMemcpyAsync(t->perm, P.vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        (void)hipFree(t->perm);
-        delete t;
-        return hip_fail(ctx, e, "tree permutation copy");
-    }
-    if (ctx->sync_checks && (rc = report_flags(ctx))) {
-        (void)hipFree(t->perm);
-        delete t;
-        return rc;
-    }
-    *out = t;
-    return TPE_OK;
+    return finish_tree(ctx, t, P.vals, out);
 }
 
 // The far field on curved cubic elements: the tree's items are the quadrature points, so the
@@ -895,9 +889,13 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    // monopole walks run their blocks heaviest first (the work recorded by the last walk on the tree)
+    if (!mlp)
+        HIPCHK(launch_ff_order(tree->work, (n + 63) / 64, P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
-                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
+                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats,
+                           mlp ? nullptr : P.vals, tree->work, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_p3_finalize(true, nullptr, P.sc, P.Fp, n, 1, Q, P.acc64, tree->perm, F10, V, X, P.bbox, q, p, scale,
@@ -912,6 +910,7 @@ int tpe_tree_destroy(tpe_tree* t) {
     if (!t) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(t->device);
     if (t->perm) (void)hipFree(t->perm);
+    if (t->work) (void)hipFree(t->work);
     delete t;
     return TPE_OK;
 }
@@ -947,9 +946,13 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    // monopole walks run their blocks heaviest first (the work recorded by the last walk on the tree)
+    if (!mlp)
+        HIPCHK(launch_ff_order(tree->work, (nF + 63) / 64, P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
     HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
-                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, st));
+                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats,
+                           mlp ? nullptr : P.vals, tree->work, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,

@@ -42,14 +42,22 @@ def test_error_decreases_with_theta():
     assert errs[0][1] < 0.5  # monopole far field at theta = 0.5 is a rough but sane approximation
 
 
-def test_farfield_deterministic_and_tree_reuse():
+@pytest.mark.parametrize("cfg", ["C1", "C2"])
+def test_farfield_deterministic_and_tree_reuse(cfg):
+    """The first call on a new tree runs its target blocks in tree order, later monopole calls
+    heaviest first (by the work the tree recorded): the same bits either way."""
     T = tpe()
-    c = M.make_config("C1")
+    c = M.make_config(cfg)
     Xd, Fd = upload(c.X, c.F)
     tree = T.build_tree(Xd, Fd)
     E1, G1 = T.farfield(tree, Xd, Fd, theta=0.5)
     E2, G2 = T.farfield(tree, Xd, Fd, theta=0.5)
     assert float(E1.cpu()) == float(E2.cpu()) and np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+    E2, G2 = T.farfield(tree, Xd, Fd, theta=0.25)  # another work record, another order
+    E2, G2 = T.farfield(tree, Xd, Fd, theta=0.5)
+    assert float(E1.cpu()) == float(E2.cpu()) and np.array_equal(G1.cpu().numpy(), G2.cpu().numpy())
+    if cfg != "C1":
+        return
     # moments are refit from the positions passed in: a moved mesh with the old tree at theta=0
     Xm = Xd * 1.5 + 0.25
     E3, G3 = T.farfield(tree, Xm, Fd, theta=0.0)
