@@ -65,53 +65,76 @@ __device__ void write_rec(const NodeF64& n, NodeRec* rec) {
     *rec = r;
 }
 
-// One thread per leaf slot j in [0, 2^H): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order.
-__global__ void leaf_moments(const double* __restrict__ c64, const double* __restrict__ geo,
-                             const int4* __restrict__ colv, const double* __restrict__ X,
-                             const uint32_t* __restrict__ bbox, int64_t nF, int leaf, int H,
-                             NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs, NodeMom* __restrict__ moms) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ double wave_sum_d(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+__device__ __forceinline__ double wave_max_d(double x) {
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
+// One wave per leaf slot j in [0, 2^H): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order, the
+// lanes striding over them; the FP64 sums are reduced across the wave in a fixed order (every
+// lane ends with the same bits: each butterfly step adds the same two values).
+constexpr int MOM_LEAF_WAVES = 4;
+
+__global__ __launch_bounds__(64 * MOM_LEAF_WAVES) void leaf_moments(const double* __restrict__ c64,
+                                                                    const double* __restrict__ geo,
+                                                                    const int4* __restrict__ colv,
+                                                                    const double* __restrict__ X,
+                                                                    const uint32_t* __restrict__ bbox, int64_t nF,
+                                                                    int leaf, int H, NodeF64* __restrict__ nodes,
+                                                                    NodeRec* __restrict__ recs,
+                                                                    NodeMom* __restrict__ moms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = blockIdx.x * (int64_t)MOM_LEAF_WAVES + (threadIdx.x >> 6);
     const int64_t nslot = (int64_t)1 << H;
     if (j >= nslot) return;
     const double s = norm_scale(bbox);
     NodeF64 n = {};
     const int64_t f0 = j * leaf, f1 = std::min<int64_t>(nF, f0 + leaf);
-    double sx = 0, sy = 0, sz = 0;
-    for (int64_t i = f0; i < f1; ++i) {
+    double A = 0, sx = 0, sy = 0, sz = 0, nx = 0, ny = 0, nz = 0;
+    for (int64_t i = f0 + lane; i < f1; i += 64) {
         const double a = geo[5 * i];
-        n.A += a;
+        A += a;
         sx += a * c64[3 * i]; sy += a * c64[3 * i + 1]; sz += a * c64[3 * i + 2];
-        n.nx += a * geo[5 * i + 2]; n.ny += a * geo[5 * i + 3]; n.nz += a * geo[5 * i + 4];
+        nx += a * geo[5 * i + 2]; ny += a * geo[5 * i + 3]; nz += a * geo[5 * i + 4];
     }
+    n.A = wave_sum_d(A);
+    sx = wave_sum_d(sx); sy = wave_sum_d(sy); sz = wave_sum_d(sz);
+    n.nx = wave_sum_d(nx); n.ny = wave_sum_d(ny); n.nz = wave_sum_d(nz);
     if (n.A > 0.0) {
         n.cx = sx / n.A; n.cy = sy / n.A; n.cz = sz / n.A;
-        for (int64_t i = f0; i < f1; ++i) {
+        double m2c[6] = {0, 0, 0, 0, 0, 0}, m2n[6] = {0, 0, 0, 0, 0, 0}, r = 0.0;
+        for (int64_t i = f0 + lane; i < f1; i += 64) {
             const double a = geo[5 * i];
-            sym_add_outer(n.m2c, a, c64[3 * i] - n.cx, c64[3 * i + 1] - n.cy, c64[3 * i + 2] - n.cz);
-            sym_add_outer(n.m2n, a, geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]);
+            sym_add_outer(m2c, a, c64[3 * i] - n.cx, c64[3 * i + 1] - n.cy, c64[3 * i + 2] - n.cz);
+            sym_add_outer(m2n, a, geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]);
             const int4 v = colv[i];
             const int vv[3] = {v.x, v.y, v.z};
             for (int k = 0; k < 3; ++k) {
                 if (vv[k] < 0) continue;
                 const double dx = s * X[3 * (int64_t)vv[k]] - n.cx, dy = s * X[3 * (int64_t)vv[k] + 1] - n.cy,
                              dz = s * X[3 * (int64_t)vv[k] + 2] - n.cz;
-                n.r = fmax(n.r, sqrt(dx * dx + dy * dy + dz * dz));
+                r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
             }
         }
+        for (int k = 0; k < 6; ++k) {
+            n.m2c[k] = wave_sum_d(m2c[k]);
+            n.m2n[k] = wave_sum_d(m2n[k]);
+        }
+        n.r = wave_max_d(r);
     }
-    nodes[nslot + j] = n;
-    write_rec(n, &recs[nslot + j]);
-    write_mom(n, &moms[nslot + j]);
+    if (lane == 0) {
+        nodes[nslot + j] = n;
+        write_rec(n, &recs[nslot + j]);
+        write_mom(n, &moms[nslot + j]);
+    }
 }
 
-// Nodes of one level [2^l, 2^(l+1)) from their children.
-__global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec* __restrict__ recs,
-                                 NodeMom* __restrict__ moms) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t first = (int64_t)1 << level;
-    if (t >= first) return;
-    const int64_t k = first + t;
-    const NodeF64 a = nodes[2 * k], b = nodes[2 * k + 1];
+// A node from its two children.
+__device__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
     NodeF64 n = {};
     n.A = a.A + b.A;
     if (n.A > 0.0) {
@@ -129,18 +152,37 @@ __global__ void internal_moments(int level, NodeF64* __restrict__ nodes, NodeRec
             sym_add_outer(n.m2c, q.A, dx, dy, dz);  // parallel-axis shift to the new centroid
         }
     }
-    nodes[k] = n;
-    write_rec(n, &recs[k]);
-    write_mom(n, &moms[k]);
+    return n;
 }
 
-__device__ __forceinline__ double wave_sum_d(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
-}
-__device__ __forceinline__ double wave_max_d(double x) {
-    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
-    return x;
+// Levels L - 1, ..., L - nl from the nodes of level L, in one launch: work-group g loads the
+// 2^nl nodes [2^L + g 2^nl, 2^L + (g + 1) 2^nl) of level L into LDS (blockDim.x = 2^nl) and
+// combines them level by level up to their common ancestor at level L - nl, writing every node.
+// The tree's internal levels take ceil(H / MOM_SUB) launches instead of H.
+constexpr int MOM_SUB = 8;
+
+__global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, NodeF64* __restrict__ nodes,
+                                                                NodeRec* __restrict__ recs,
+                                                                NodeMom* __restrict__ moms) {
+    __shared__ NodeF64 buf[1 << MOM_SUB];
+    const int t = threadIdx.x, cnt = 1 << nl;
+    const int64_t g = blockIdx.x;
+    buf[t] = nodes[((int64_t)1 << L) + g * cnt + t];
+    __syncthreads();
+    for (int st = 1; st <= nl; ++st) {
+        const int m = cnt >> st;
+        NodeF64 par = {};
+        if (t < m) par = combine_nodes(buf[2 * t], buf[2 * t + 1]);
+        __syncthreads();
+        if (t < m) {
+            buf[t] = par;
+            const int64_t k = ((int64_t)1 << (L - st)) + g * m + t;
+            nodes[k] = par;
+            write_rec(par, &recs[k]);
+            write_mom(par, &moms[k]);
+        }
+        __syncthreads();
+    }
 }
 
 // Ball (C_T, r_T) of each target block of 64 sorted faces: C_T = mean of the centroids, r_T bounds
@@ -757,11 +799,13 @@ hipError_t launch_tree_moments(const double* c64, const double* geo, const int4*
     NodeRec* r = (NodeRec*)recs;
     NodeMom* m = (NodeMom*)(r + ((size_t)2 << H));
     const int64_t nslot = (int64_t)1 << H;
-    hipLaunchKernelGGL(leaf_moments, dim3((unsigned)((nslot + 127) / 128)), dim3(128), 0, st, c64, geo, colv, X, bbox,
-                       nF, leaf, H, n, r, m);
-    for (int l = H - 1; l >= 0; --l) {
-        const int64_t cnt = (int64_t)1 << l;
-        hipLaunchKernelGGL(internal_moments, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, st, l, n, r, m);
+    hipLaunchKernelGGL(leaf_moments, dim3((unsigned)((nslot + MOM_LEAF_WAVES - 1) / MOM_LEAF_WAVES)),
+                       dim3(64 * MOM_LEAF_WAVES), 0, st, c64, geo, colv, X, bbox, nF, leaf, H, n, r, m);
+    for (int L = H; L > 0;) {
+        const int nl = std::min(L, MOM_SUB);
+        hipLaunchKernelGGL(subtree_moments, dim3((unsigned)(((int64_t)1 << L) >> nl)), dim3(1 << nl), 0, st, L, nl,
+                           n, r, m);
+        L -= nl;
     }
     return hipGetLastError();
 }
