@@ -42,7 +42,7 @@ hipError_t launch_p3_nodes(const int32_t* F10, int64_t n, int step, int Q, int64
 hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t n, int step, int Q,
                               const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
                               const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
-                              double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                              double* corner, double* epart, uint32_t* flags, double* E, EnergyOut* in_gather,
                               hipStream_t st);
 hipError_t launch_touch(const int4* colv, int64_t nF, int64_t V, const uint32_t* off, const uint32_t* list,
                         int nrb, int touch_words, uint32_t* touch, hipStream_t st);
@@ -56,7 +56,7 @@ bool pair_exponents_ok(int q, int p);
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
                            double p, double scale, double efac, int Q, double* corner, double* epart,
-                           uint32_t* ticket, uint32_t* flags, double* E, hipStream_t st);
+                           uint32_t* flags, double* E, EnergyOut* in_gather, hipStream_t st);
 hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
                             const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st);
 int pair_sym_blocks_per_cu(bool grad);
@@ -82,7 +82,7 @@ hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, 
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
-                         hipStream_t st);
+                         const EnergyOut& en, hipStream_t st);
 int finalize_blocks(int64_t nF);
 int tree_height(int64_t nF, int leaf);
 hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int Q, int leaf, int H, float4* cen,
@@ -256,7 +256,6 @@ struct Plan {
     uint32_t *zero_begin, *cnt, *cursor, *touch, *zero_end;
     uint32_t *voff, *list, *scanws;
     double *org, *c64, *geo, *corner, *epart, *acc64;
-    uint32_t* ticket;
     int morton_bits;
     ColRec* cols;
     int4* colv;
@@ -298,7 +297,6 @@ void layout(Plan& P, char* base, bool grad) {
     P.counter = c.take<unsigned long long>(1);
     // one contiguous zero-initialised region
     P.zero_begin = c.take<uint32_t>(0);
-    P.ticket = c.take<uint32_t>(64);
     P.cnt = c.take<uint32_t>(V);
     P.cursor = c.take<uint32_t>(V);
     if (P.p3 && grad) {
@@ -532,16 +530,17 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) HIPCHK(launch_sym_merge(grad, P.part, P.colpart, P.first, P.ssc, P.nR, P.Fp, P.acc64, st));
+    EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     if (p3) {
         HIPCHK(launch_p3_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, nF, P.Q, P.Q, P.sym ? P.acc64 : nullptr,
-                                  P.vals, F, V, X, P.bbox, q, p, scale, 0.5, P.corner, P.epart, P.ticket, ctx->dflags,
-                                  E, st));
-        if (grad) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G, st));
+                                  P.vals, F, V, X, P.bbox, q, p, scale, 0.5, P.corner, P.epart, ctx->dflags,
+                                  E, grad ? &en : nullptr, st));
+        if (grad) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G, en, st));
     } else {
         HIPCHK(launch_finalize(grad, P.sym ? nullptr : P.part, P.sc, P.Fp, P.nR, P.sym ? P.acc64 : nullptr, P.geo,
-                               P.colv, X, P.bbox, q, p, scale, 0.5, P.Q, P.corner, P.epart, P.ticket, ctx->dflags, E,
-                               st));
-        if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+                               P.colv, X, P.bbox, q, p, scale, 0.5, P.Q, P.corner, P.epart, ctx->dflags, E,
+                               grad ? &en : nullptr, st));
+        if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, en, st));
     }
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -587,9 +586,10 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     HIPCHK(launch_pair_conf(grad, P.cols, P.c64, P.colv, P.colsY, P.colvY, P.orgY, P.sc, P.part, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(grad, P.part, P.sc, P.Fp, nF, nullptr, P.geo, P.colv, X, P.bbox, q, p, scale, 1.0, 1,
-                           P.corner, P.epart, P.ticket, ctx->dflags, E, st));
-    if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, st));
+                           P.corner, P.epart, ctx->dflags, E, grad ? &en : nullptr, st));
+    if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -898,9 +898,10 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
                            mlp ? nullptr : P.vals, tree->work, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_p3_finalize(true, nullptr, P.sc, P.Fp, n, 1, Q, P.acc64, tree->perm, F10, V, X, P.bbox, q, p, scale,
-                              0.5, P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
-    if (G_dev) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G_dev, st));
+                              0.5, P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
+    if (G_dev) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -955,9 +956,10 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                            mlp ? nullptr : P.vals, tree->work, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
-                           P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
-    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+                           P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
+    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -1002,9 +1004,10 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
                        ctx->dflags, ctx->dstats, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
-                           P.corner, P.epart, P.ticket, ctx->dflags, E_dev, st));
-    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, st));
+                           P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
+    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;

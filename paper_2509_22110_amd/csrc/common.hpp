@@ -189,6 +189,16 @@ struct SymSched {
     }
 };
 
+// The energy of a finalize: E[0] = scale 2^(kexp (p - q - 4)) (sum of the nb FP64 work-group
+// partials epart), kexp from the bounding box; E null: no energy.
+struct EnergyOut {
+    const double* epart;
+    int nb;
+    const uint32_t* bbox;
+    double q, p, scale;
+    double* E;
+};
+
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 

@@ -46,34 +46,36 @@ __device__ __forceinline__ void row_sums(const float* __restrict__ part, const S
 }
 
 // Energy of a 256-thread work-group's threads (e per thread): every work-group writes one FP64
-// partial and the last one to finish (ticket counter, zero on entry) adds the partials in index
-// order and writes E[0] = fac * total, so the energy is deterministic.
-__device__ void energy_tail(double e, double* __restrict__ epart, uint32_t* __restrict__ ticket,
-                            double* __restrict__ E, double fac) {
+// partial, and energy_sum adds the partials in index order after the kernel (the launch boundary
+// orders the writes), so the energy is deterministic.  No last-work-group ticket: that needs a
+// device-scope release fence in every work-group, which on this chip writes back the L2 (the
+// finalize at 327,680 faces took 89 us with it, 26 us without).
+__device__ void energy_part(double e, double* __restrict__ epart) {
     __shared__ double ws[4];
-    __shared__ bool last;
     e = wave_sum(e);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double t = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
-        t += __hip_atomic_load(&epart[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    t = wave_sum(t);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0 && E) E[0] = fac * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+    if (threadIdx.x == 0) epart[blockIdx.x] = ((ws[0] + ws[1]) + (ws[2] + ws[3]));
 }
 
-// One thread per sorted face; the energy as in energy_tail.
+// E[0] = scale 2^(kexp (p - q - 4)) * (sum of the nb partials), by one work-group of 256 threads:
+// thread t adds partials t, t + 256, ... in order, then the waves, then the 4 wave sums.  The row
+// sums were taken on positions multiplied by s = 2^kexp, and E(X) = s^(p-q-4) E(sX) exactly.  Runs
+// as the extra last work-group of the vertex gather when there is one, else alone (energy_sum).
+__device__ void energy_total(const EnergyOut& en) {
+    __shared__ double ws[4];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < en.nb; b += 256) t += en.epart[b];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        en.E[0] = en.scale * pow2i(norm_exp(en.bbox), en.p - en.q - 4.0) * ((ws[0] + ws[1]) + (ws[2] + ws[3]));
+}
+
+__global__ __launch_bounds__(256) void energy_sum(EnergyOut en) { energy_total(en); }
+
+// One thread per sorted face; the energy partials as in energy_part.
 template <bool GRAD>
 __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__ part, Sched sc,
                                                        const double* __restrict__ accs, int64_t Fp, int64_t nF,
@@ -83,8 +85,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
                                                        const uint32_t* __restrict__ bbox, double q, double p,
                                                        double scale, double efac, int Q,
                                                        double* __restrict__ corner,
-                                                       double* __restrict__ epart, uint32_t* __restrict__ ticket,
-                                                       double* __restrict__ E, uint32_t* __restrict__ flags) {
+                                                       double* __restrict__ epart, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double e = 0.0;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
         }
         if (!finite) atomicOr(flags, (uint32_t)FLAG_NONFINITE);
     }
-    energy_tail(e, epart, ticket, E, scale * pow2i(kexp, p - q - 4.0));
+    energy_part(e, epart);
 }
 
 // G[v] = sum over the (sorted face, corner) slots incident to v, in ascending slot order, so the
@@ -147,8 +148,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(const float* __restrict__
 // the last one taken (slots are distinct).
 constexpr int GATHER_REG = 16;
 
-__global__ void vertex_gather(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list, int64_t V,
-                              const double* __restrict__ corner, double* __restrict__ G) {
+__global__ __launch_bounds__(256) void vertex_gather(const uint32_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ list, int64_t V,
+                                                     const double* __restrict__ corner, double* __restrict__ G,
+                                                     EnergyOut en) {
+    if (en.E && blockIdx.x == gridDim.x - 1) {  // the extra work-group: the energy
+        energy_total(en);
+        return;
+    }
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= V) return;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -214,8 +221,7 @@ __global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restric
                                                           const double* __restrict__ X,
                                                           const uint32_t* __restrict__ bbox, double q, double p,
                                                           double scale, double efac, double* __restrict__ corner,
-                                                          double* __restrict__ epart, uint32_t* __restrict__ ticket,
-                                                          double* __restrict__ E, uint32_t* __restrict__ flags) {
+                                                          double* __restrict__ epart, uint32_t* __restrict__ flags) {
     constexpr int NA = GRAD ? NACC : 1;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double en = 0.0;
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(256) void p3_finalize_kernel(const float* __restric
                 }
         if (!finite) atomicOr(flags, (uint32_t)FLAG_NONFINITE);
     }
-    energy_tail(en, epart, ticket, E, scale * pow2i(kexp, p - q - 4.0));
+    energy_part(en, epart);
 }
 
 int finalize_blocks(int64_t nF) { return (int)((nF + 255) / 256); }
@@ -343,42 +349,57 @@ hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, 
     return hipGetLastError();
 }
 
+// The energy of a finalize (nothing when E is null): summed by its own one-work-group launch, or
+// left to the vertex gather that follows (in_gather; the caller passes the same EnergyOut there).
+static hipError_t finish_energy(const double* epart, int nb, const uint32_t* bbox, double q, double p, double scale,
+                                double* E, EnergyOut* in_gather, hipStream_t st) {
+    const EnergyOut en = {epart, nb, bbox, q, p, scale, E};
+    if (in_gather) *in_gather = en;
+    else if (E) hipLaunchKernelGGL(energy_sum, dim3(1), dim3(256), 0, st, en);
+    return hipGetLastError();
+}
+
 // Row sums: the pair kernel's segments (part, sc) or, with part null, acc64 (NA x Fp FP64);
-// ticket: one word, zero on entry.  efac: E = efac sum_S a_S K_S with the gradient's row sums
-// (1/2 for the self energy, whose K holds both orders of every pair; 1 for the confinement).
+// efac: E = efac sum_S a_S K_S with the gradient's row sums (1/2 for the self energy, whose K
+// holds both orders of every pair; 1 for the confinement).  epart: finalize_blocks(nF) FP64.
+// in_gather: see finish_energy.
 hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t nF, const double* acc64,
                            const double* geo, const int4* colv, const double* X, const uint32_t* bbox, double q,
                            double p, double scale, double efac, int Q, double* corner, double* epart,
-                           uint32_t* ticket, uint32_t* flags, double* E, hipStream_t st) {
+                           uint32_t* flags, double* E, EnergyOut* in_gather, hipStream_t st) {
     const int nb = finalize_blocks(nF);
     if (grad)
         hipLaunchKernelGGL((finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, efac, Q, corner, epart, ticket, E, flags);
+                           bbox, q, p, scale, efac, Q, corner, epart, flags);
     else
         hipLaunchKernelGGL((finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, nF, geo, colv, X,
-                           bbox, q, p, scale, efac, Q, corner, epart, ticket, E, flags);
-    return hipGetLastError();
+                           bbox, q, p, scale, efac, Q, corner, epart, flags);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : finish_energy(epart, nb, bbox, q, p, scale, E, in_gather, st);
 }
 
 // n items of `step` records (see p3_finalize_kernel)
 hipError_t launch_p3_finalize(bool grad, const float* part, const Sched& sc, int64_t Fp, int64_t n, int step, int Q,
                               const double* acc64, const uint32_t* perm, const int32_t* F10, int64_t V,
                               const double* X, const uint32_t* bbox, double q, double p, double scale, double efac,
-                              double* corner, double* epart, uint32_t* ticket, uint32_t* flags, double* E,
+                              double* corner, double* epart, uint32_t* flags, double* E, EnergyOut* in_gather,
                               hipStream_t st) {
     const int nb = finalize_blocks(n);
     if (grad)
         hipLaunchKernelGGL((p3_finalize_kernel<true>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, n, step, Q,
-                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
+                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, flags);
     else
         hipLaunchKernelGGL((p3_finalize_kernel<false>), dim3(nb), dim3(256), 0, st, part, sc, acc64, Fp, n, step, Q,
-                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, ticket, E, flags);
-    return hipGetLastError();
+                           perm, F10, V, X, bbox, q, p, scale, efac, corner, epart, flags);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : finish_energy(epart, nb, bbox, q, p, scale, E, in_gather, st);
 }
 
+// en: the energy left to the gather by the finalize (E null: none)
 hipError_t launch_gather(const uint32_t* off, const uint32_t* list, int64_t V, const double* corner, double* G,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(vertex_gather, dim3((int)((V + 255) / 256)), dim3(256), 0, st, off, list, V, corner, G);
+                         const EnergyOut& en, hipStream_t st) {
+    const int nb = (int)((V + 255) / 256) + (en.E ? 1 : 0);
+    hipLaunchKernelGGL(vertex_gather, dim3(nb), dim3(256), 0, st, off, list, V, corner, G, en);
     return hipGetLastError();
 }
 
