@@ -97,7 +97,10 @@ typedef enum {
 int tpe_version(void);
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t; NULL = the
- * null stream).  *out receives the context; ownership passes to the caller (tpe_destroy). */
+ * null stream).  The context also owns a second stream of default priority: the far-field calls
+ * fork their vertex CSR onto it (only the final gather reads it) and join it back into
+ * `hip_stream` before that gather, so every call stays ordered on `hip_stream` as a whole.
+ * *out receives the context; ownership passes to the caller (tpe_destroy). */
 int tpe_create(tpe_ctx** out, int device, void* hip_stream);
 
 /* Destroy a context and free its scratch arena.  Waits for the context's stream first. */

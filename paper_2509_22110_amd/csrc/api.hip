@@ -168,6 +168,10 @@ struct tpe_ctx {
     int kernel_timing = 0;        // 1: the dominant kernel, 2: finalize + vertex gather
     std::vector<hipEvent_t> ev_pool;  // pairs (start, stop), reused
     size_t ev_used = 0;               // events recorded since the last tpe_kernel_time
+    // second stream (default priority) for the far field's vertex CSR, which only the final gather
+    // reads: it runs beside the moments and the walk, forked from and joined back into `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct tpe_mlp {
@@ -412,6 +416,7 @@ int ensure_arena(tpe_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->arena_bytes) return TPE_OK;
     if (ctx->arena) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->side);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
         (void)hipFree(ctx->arena);
         ctx->arena = nullptr;
@@ -658,7 +663,14 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         ctx->resident_sym[1] = ncu * pair_sym_blocks_per_cu(true);
     }
     if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        hipStreamSynchronize(ctx->stream) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->join) (void)hipEventDestroy(ctx->join);
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+        if (ctx->side) (void)hipStreamDestroy(ctx->side);
         (void)hipFree(ctx->dflags);
         (void)hipHostFree(ctx->hflags);
         delete ctx;
@@ -672,10 +684,14 @@ int tpe_destroy(tpe_ctx* ctx) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->side);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->dflags) (void)hipFree(ctx->dflags);
     if (ctx->hflags) (void)hipHostFree(ctx->hflags);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(ctx->fork);
+    (void)hipEventDestroy(ctx->join);
+    (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return TPE_OK;
 }
@@ -882,8 +898,13 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     HIPCHK(launch_p3_records(X, V, F10, nF, Q, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                              ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, n, tree->leaf, tree->H, P.nodes64, P.recs, st));
-    if (G_dev)
-        HIPCHK(launch_p3_nodes(F10, n, 1, Q, V, tree->perm, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
+    if (G_dev) {  // the node CSR only serves the gather: built on the side stream during the walk
+        HIPCHK(hipEventRecord(ctx->fork, st));
+        HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        HIPCHK(launch_p3_nodes(F10, n, 1, Q, V, tree->perm, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws,
+                               ctx->side));
+        HIPCHK(hipEventRecord(ctx->join, ctx->side));
+    }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -901,7 +922,10 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_p3_finalize(true, nullptr, P.sc, P.Fp, n, 1, Q, P.acc64, tree->perm, F10, V, X, P.bbox, q, p, scale,
                               0.5, P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
-    if (G_dev) HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G_dev, en, st));
+    if (G_dev) {
+        HIPCHK(hipStreamWaitEvent(st, ctx->join, 0));
+        HIPCHK(launch_gather(P.noff, P.nlist, V, P.corner, G_dev, en, st));
+    }
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -940,7 +964,11 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
+    // the vertex CSR only serves the gather: it is built on the side stream during the walk
+    HIPCHK(hipEventRecord(ctx->fork, st));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, ctx->side));
+    HIPCHK(hipEventRecord(ctx->join, ctx->side));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
@@ -959,6 +987,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
                            P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
+    HIPCHK(hipStreamWaitEvent(st, ctx->join, 0));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
@@ -991,7 +1020,11 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                           ctx->dflags, st));
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
+    // the vertex CSR only serves the gather: it is built on the side stream during the walk
+    HIPCHK(hipEventRecord(ctx->fork, st));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, ctx->side));
+    HIPCHK(hipEventRecord(ctx->join, ctx->side));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
@@ -1007,6 +1040,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
                            P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
+    HIPCHK(hipStreamWaitEvent(st, ctx->join, 0));
     if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
