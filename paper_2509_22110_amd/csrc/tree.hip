@@ -726,6 +726,69 @@ __global__ void kd_node_bbox(const uint32_t* __restrict__ perm, const float4* __
     }
 }
 
+// The same boxes at the levels whose nodes hold at least KD_BIG faces: a work-group covers KD_BIG
+// consecutive sorted faces (KD_PER per thread), which meet at most two nodes (A, the node of the
+// first face, and A + 1); the two boxes are reduced over the work-group and each gets one set of
+// atomics per work-group.  With one thread per face, every wave of the launch sent its atomics to
+// the same six words at the top level (350 us at 327,680 faces).  Min and max are exact, so the
+// boxes are the same bits either way.
+constexpr int KD_PER = 8;
+constexpr int KD_BIG = 256 * KD_PER;
+
+__global__ __launch_bounds__(256) void kd_node_bbox_big(const uint32_t* __restrict__ perm,
+                                                        const float4* __restrict__ cen, int64_t nF,
+                                                        int64_t node_faces, uint32_t* __restrict__ nb) {
+    __shared__ float red[4][12];
+    const int64_t base = blockIdx.x * (int64_t)KD_BIG;
+    const int64_t jA = base / node_faces, bound = (jA + 1) * node_faces;
+    // [0..2] min, [3..5] max of node A; [6..11] the same for node A + 1
+    float r[12];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        r[d] = r[6 + d] = INFINITY;
+        r[3 + d] = r[9 + d] = -INFINITY;
+    }
+#pragma unroll
+    for (int k = 0; k < KD_PER; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < nF) {
+            const float4 c = cen[perm[i]];
+            const float v[3] = {c.x, c.y, c.z};
+            const bool a = i < bound;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                r[d] = a ? fminf(r[d], v[d]) : r[d];
+                r[3 + d] = a ? fmaxf(r[3 + d], v[d]) : r[3 + d];
+                r[6 + d] = a ? r[6 + d] : fminf(r[6 + d], v[d]);
+                r[9 + d] = a ? r[9 + d] : fmaxf(r[9 + d], v[d]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+        for (int off = 32; off > 0; off >>= 1) {
+            const float o = __shfl_xor(r[q], off);
+            r[q] = (q % 6) < 3 ? fminf(r[q], o) : fmaxf(r[q], o);
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 12; ++q) red[threadIdx.x >> 6][q] = r[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 12; ++q)
+            for (int w = 1; w < 4; ++w) r[q] = (q % 6) < 3 ? fminf(r[q], red[w][q]) : fmaxf(r[q], red[w][q]);
+        for (int h = 0; h < 2; ++h) {
+            const float* b = r + 6 * h;
+            if (!(b[0] <= b[3])) continue;  // no face of this node here
+            const int64_t j = jA + h;
+            for (int d = 0; d < 3; ++d) {
+                atomicMin(&nb[6 * j + d], f2o(b[d]));
+                atomicMax(&nb[6 * j + 3 + d], f2o(b[3 + d]));
+            }
+        }
+    }
+}
+
 // key = (node index << qbits) | coordinate along the node's longest axis quantised to qbits.
 __global__ void kd_keys(const uint32_t* __restrict__ perm, const float4* __restrict__ cen, int64_t nF,
                         int64_t node_faces, const uint32_t* __restrict__ nb, int qbits, uint32_t* __restrict__ keys) {
@@ -771,7 +834,11 @@ hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t 
         const int64_t nnodes = (int64_t)1 << level;
         const int64_t node_faces = ((int64_t)1 << (H - level)) * leaf;
         hipLaunchKernelGGL(kd_box_init, dim3((unsigned)((nnodes * 6 + 255) / 256)), dim3(256), 0, st, nb, nnodes);
-        hipLaunchKernelGGL(kd_node_bbox, dim3(g), dim3(256), 0, st, perm, cen, nF, node_faces, nb);
+        if (node_faces >= KD_BIG)
+            hipLaunchKernelGGL(kd_node_bbox_big, dim3((unsigned)((nF + KD_BIG - 1) / KD_BIG)), dim3(256), 0, st, perm,
+                               cen, nF, node_faces, nb);
+        else
+            hipLaunchKernelGGL(kd_node_bbox, dim3(g), dim3(256), 0, st, perm, cen, nF, node_faces, nb);
         const int qbits = std::min(16, 32 - level);
         hipLaunchKernelGGL(kd_keys, dim3(g), dim3(256), 0, st, perm, cen, nF, node_faces, nb, qbits, keys);
         hipError_t e = radix_sort(keys, perm, ktmp, vtmp, nF, level + qbits, hist, off, st);
