@@ -19,7 +19,7 @@ needs_gpu = pytest.mark.skipif(not HAVE_GPU, reason="needs a GPU")
 
 
 def tpe():
-    """The HIP binding; fails loudly (no fallback) when the library is missing on a GPU machine."""
+    """The HIP binding; fails loudly (no fallback) when the library is missing on a machine with a GPU."""
     if not os.path.exists(LIB):
         raise RuntimeError("libtpe.so is not built; run python -m paper_2509_22110_amd.build")
     import paper_2509_22110_amd as m
