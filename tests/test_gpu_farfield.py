@@ -112,3 +112,38 @@ def test_c4_far_field_vs_exact():
     assert eS <= 1e-5
     assert t_exact / t_ff > 5.0
     assert eG < 0.5
+
+
+def test_farfield_calls_on_a_user_stream():
+    """Far-field calls build their CSR on the context's second stream and join it back into the
+    caller's stream before the gather: on a non-default stream, work enqueued after the call sees
+    the finished gradient, and the results equal those of calls on the default stream (flat faces,
+    dual tree, curved elements)."""
+    import torch
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    X10, F10 = M.p3_sphere(3, 2, 8, 0.05, 2)
+    X10d, F10d = upload(X10, F10)
+    tree = T.build_tree(Xd, Fd)
+    tree3 = T.build_tree_p3(X10d, F10d, leaf=32, points=3)
+    ref = [T.farfield(tree, Xd, Fd, theta=0.5), T.farfield_dual(tree, Xd, Fd, theta=0.5),
+           T.farfield_p3(tree3, X10d, F10d, theta=0.5)]
+    ref = [(float(E.cpu()), G.cpu().numpy()) for E, G in ref]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream(device=Xd.device)
+    with torch.cuda.stream(s):
+        out = []
+        for _ in range(2):
+            for call in (lambda: T.farfield(tree, Xd, Fd, theta=0.5), lambda: T.farfield_dual(tree, Xd, Fd, theta=0.5),
+                         lambda: T.farfield_p3(tree3, X10d, F10d, theta=0.5)):
+                E, G = call()
+                out.append((E, G, (G * 2.0).sum()))  # consumers enqueued on the same stream
+    s.synchronize()
+    for k, (E, G, S) in enumerate(out):
+        Er, Gr = ref[k % 3]
+        assert float(E.cpu()) == Er and np.array_equal(G.cpu().numpy(), Gr)
+        # another summation order, so not bitwise; the sum nearly cancels (translation invariance),
+        # so the bound is relative to the sum of magnitudes
+        Gt = torch.from_numpy(Gr) * 2.0
+        assert abs(float(S.cpu()) - float(Gt.sum())) <= 1e-12 * float(Gt.abs().sum())
