@@ -73,7 +73,7 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
                        const double* geo, const double* org, const void* nodes64, const void* recs_, int64_t nF,
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
                        uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
-                       uint32_t* flags, unsigned long long* stats, hipStream_t st);
+                       uint32_t* flags, unsigned long long* stats, uint32_t* const sort[6], hipStream_t st);
 // the symmetric kernel is used while its column partials (32 B per face and earlier super block of
 // 512 faces) fit in this many bytes: about 1,430,000 faces, of the GPU's 288 GB of HBM; if the
 // allocation fails the call runs the row-only kernel instead
@@ -1032,9 +1032,10 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
+    uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
     HIPCHK(launch_dual(tree->H, tree->leaf, (float)theta, P.cols, P.colv, P.c64, P.geo, P.org, P.nodes64, P.recs, nF,
                        P.Fp, q, p, P.doff, P.dnear, P.dfar, P.dcnt, P.drel, P.dent, P.dscan, P.dadj, P.dpart, P.acc64,
-                       ctx->dflags, ctx->dstats, st));
+                       ctx->dflags, ctx->dstats, sortbuf, st));
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group

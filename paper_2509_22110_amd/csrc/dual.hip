@@ -186,14 +186,16 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
     int Hd, int64_t span, const ColRec* __restrict__ cols, const int4* __restrict__ colv,
     const double* __restrict__ c64, const double* __restrict__ org, const NodeRec* __restrict__ recs,
     const uint32_t* __restrict__ off, const uint32_t* __restrict__ nnear, const uint32_t* __restrict__ ent,
-    uint32_t cap, int64_t nF, int64_t Fp, float* __restrict__ part, unsigned long long* __restrict__ stats) {
+    uint32_t cap, int64_t nF, int64_t Fp, float* __restrict__ part, unsigned long long* __restrict__ stats,
+    const uint32_t* __restrict__ order) {
     __shared__ float red[DUAL_NW - 1][2 * NACC][64];
     __shared__ unsigned long long wpairs[DUAL_NW];
     const int split = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const int64_t A = ((int64_t)1 << Hd) + blockIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.x * span;
+    const int64_t x = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;  // the leaf
+    const int64_t A = ((int64_t)1 << Hd) + x;
+    const int64_t i0 = x * span;
     const bool row = lane < span && i0 + lane < Fp;
     const int64_t i = row ? i0 + lane : 0;  // lanes without a row read row 0 and write nothing
     const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
                 lo[k] = (t - hi[k]) - y;
                 hi[k] = t;
             }
-        float* o = part + ((size_t)blockIdx.x * DUAL_SPLIT + split) * NACC * 64 + lane;
+        float* o = part + ((size_t)x * DUAL_SPLIT + split) * NACC * 64 + lane;
 #pragma unroll
         for (int k = 0; k < NACC; ++k) o[(size_t)k * 64] = hi[k] - lo[k];
     }
@@ -326,6 +328,8 @@ int64_t dual_entry_cap(int H, int leaf) {
 
 int64_t scan_ws_words(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* ws, hipStream_t st);
+hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
+                           uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st);
 
 // The whole dual-tree evaluation after the records and tree moments: lists, far clusters, near
 // leaves, downward pass; leaves FP64 row sums in acc64 for the finalize.
@@ -333,7 +337,7 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
                        const double* geo, const double* org, const void* nodes64, const void* recs_, int64_t nF,
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
                        uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
-                       uint32_t* flags, unsigned long long* stats, hipStream_t st) {
+                       uint32_t* flags, unsigned long long* stats, uint32_t* const sort[6], hipStream_t st) {
     const NodeF64* nodes = (const NodeF64*)nodes64;
     const NodeRec* recs = (const NodeRec*)recs_;
     const int Hd = dual_level(H, leaf);
@@ -354,8 +358,13 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
     if (nn > 0)
         hipLaunchKernelGGL(dual_far_eval, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, st, Hd, recs, nodes, off,
                            nnear, nfar, ent, cap, q, p, adj, stats);
-    hipLaunchKernelGGL(dual_near_eval, dim3((unsigned)((int64_t)1 << Hd), DUAL_SPLIT), dim3(64 * DUAL_NW), 0, st, Hd,
-                       span, cols, colv, c64, org, recs, off, nnear, ent, cap, nF, Fp, part, stats);
+    // leaves with the longest near lists first (work-groups start in launch order); sort: keys, vals,
+    // ktmp, vtmp, hist, hoff of a radix sort of 2^Hd entries
+    const int64_t nleaf = (int64_t)1 << Hd;
+    hipError_t e = launch_ff_order(nnear + nleaf, nleaf, sort[0], sort[1], sort[2], sort[3], sort[4], sort[5], st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dual_near_eval, dim3((unsigned)nleaf, DUAL_SPLIT), dim3(64 * DUAL_NW), 0, st, Hd, span, cols,
+                       colv, c64, org, recs, off, nnear, ent, cap, nF, Fp, part, stats, (const uint32_t*)sort[1]);
     hipLaunchKernelGGL(dual_near_merge, dim3((unsigned)((nF + 255) / 256), NACC), dim3(256), 0, st, span, part, nF, Fp,
                        acc64);
     hipLaunchKernelGGL(dual_down, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, st, Hd, span, nodes, adj, c64, geo,
