@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpe_oracle.c")
+_SRC_FF = os.path.join(_HERE, "tpe_oracle_ff.c")
 _LIB = os.path.join(_HERE, "libtpe_oracle.so")
 _lib = None
 
@@ -40,11 +41,12 @@ class OracleError(RuntimeError):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_FF))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-            "-fno-fast-math", _SRC, "-o", tmp, "-lm",
+            "-fno-fast-math", _SRC, _SRC_FF, "-o", tmp, "-lm",
         ])
         os.replace(tmp, _LIB)
     return _LIB
@@ -75,6 +77,18 @@ def _load():
         lib.tpeo_pair_count.argtypes = [P, I64]
         lib.tpeo_pair_count.restype = I64
         lib.tpeo_num_threads.argtypes = [I32]
+        lib.tpeo_kd_order.argtypes = [P, I64, P, I64, I32, P]
+        lib.tpeo_kd_order.restype = I32
+        lib.tpeo_farfield.argtypes = [P, I64, P, I64, P, I32, D, D, D, D, I32, P, P, P]
+        lib.tpeo_farfield.restype = I32
+        lib.tpeo_farfield_coverage.argtypes = [P, I64, P, I64, P, I32, D, P]
+        lib.tpeo_farfield_coverage.restype = I32
+        lib.tpeo_sample_hash.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        lib.tpeo_sample_hash.restype = ctypes.c_uint32
+        lib.tpeo_farfield_samples.argtypes = [P, I64, P, I64, P, I32, D, ctypes.c_uint64, D, I64, I64, P, P, P, P]
+        lib.tpeo_farfield_samples.restype = I64
+        lib.tpeo_farfield_dual.argtypes = [P, I64, P, I64, P, I32, D, D, D, D, P, I64, I32, P, P, P]
+        lib.tpeo_farfield_dual.restype = I32
         for f in (lib.tpeo_energy, lib.tpeo_energy_rows, lib.tpeo_gradient, lib.tpeo_gradient_at):
             f.restype = I32
         _lib = lib
@@ -217,3 +231,103 @@ def gradient_p3(X, F10, rule, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=Tr
     if rc:
         raise OracleError(rc)
     return float(E[0]), G
+
+
+# ---- cluster approximations (tpe_oracle_ff.c; paper Sec. 3.2) -----------------------------------------
+
+
+def kd_order(X, F, leaf=32):
+    """Tree order of the faces (position -> face id, uint32 [nF]): the k-d ordering of the cluster
+    tree with leaves of `leaf` faces (see tpe_oracle_ff.c)."""
+    X, F = _prep(X, F)
+    perm = np.zeros(F.shape[0], dtype=np.uint32)
+    rc = _load().tpeo_kd_order(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], int(leaf), perm.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return perm
+
+
+def _perm(X, F, perm, leaf):
+    if perm is None:
+        perm = kd_order(X, F, leaf)
+    return np.ascontiguousarray(perm, dtype=np.uint32)
+
+
+def farfield(X, F, theta, leaf=32, perm=None, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=True):
+    """(E, G, stats) of the Barnes-Hut clustering of the inner integrals of eq. (dTP_reordered) on
+    the tree `perm` (default: kd_order(X, F, leaf)); stats = (far clusters, near columns, visited
+    nodes, target blocks, max near columns of a block, max far clusters of a block)."""
+    X, F = _prep(X, F)
+    perm = _perm(X, F, perm, leaf)
+    E = np.zeros(1)
+    G = np.zeros_like(X) if want_grad else None
+    st = np.zeros(6, dtype=np.int64)
+    rc = _load().tpeo_farfield(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], perm.ctypes.data, int(leaf),
+                               float(theta), q, p, scale, nthreads, E.ctypes.data,
+                               G.ctypes.data if want_grad else None, st.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G, tuple(int(v) for v in st)
+
+
+def farfield_coverage(X, F, theta, leaf=32, perm=None):
+    """Invariants of the walk: (blocks whose faces do not see every face exactly once, far clusters
+    holding a face that shares a vertex with a face of the target block)."""
+    X, F = _prep(X, F)
+    perm = _perm(X, F, perm, leaf)
+    out = np.zeros(2, dtype=np.int64)
+    rc = _load().tpeo_farfield_coverage(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], perm.ctypes.data,
+                                        int(leaf), float(theta), out.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return int(out[0]), int(out[1])
+
+
+def sample_hash(seed, block, node):
+    return int(_load().tpeo_sample_hash(int(seed) & (2**64 - 1), int(block), int(node)))
+
+
+def farfield_samples(X, F, theta, seed, select_prob, max_faces, leaf=32, perm=None, cap=None):
+    """Learned-correction samples of the walk: dict with 'block', 'node' [n], 'feats' [n, 64, 19] and
+    'targets' [n, 64, 8] (7 targets and the row weight) for every selected (block, far cluster)."""
+    X, F = _prep(X, F)
+    perm = _perm(X, F, perm, leaf)
+    lib = _load()
+    args = (X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], perm.ctypes.data, int(leaf), float(theta),
+            int(seed) & (2**64 - 1), float(select_prob), int(max_faces))
+    if cap is None:
+        n = lib.tpeo_farfield_samples(*args, 0, None, None, None, None)
+        if n < 0:
+            raise OracleError(int(n))
+        cap = int(n)
+    blk = np.zeros(max(cap, 1), dtype=np.int32)
+    node = np.zeros(max(cap, 1), dtype=np.int32)
+    feats = np.zeros((max(cap, 1), 64, 19))
+    targ = np.zeros((max(cap, 1), 64, 8))
+    n = lib.tpeo_farfield_samples(*args, cap, blk.ctypes.data, node.ctypes.data, feats.ctypes.data,
+                                  targ.ctypes.data)
+    if n < 0:
+        raise OracleError(int(n))
+    n = min(int(n), cap)
+    return {"block": blk[:n], "node": node[:n], "feats": feats[:n], "targets": targ[:n]}
+
+
+def farfield_dual(X, F, theta, leaf=32, perm=None, verts=None, q=6.0, p=12.0, scale=1.0, nthreads=0,
+                  want_grad=True):
+    """(E, G, stats) of the dual-tree clustering: E its approximate energy, G [V or len(verts), 3] the
+    exact derivative of E (complex step, lists fixed), stats = (far cluster pairs, face pairs of near
+    dual leaves)."""
+    X, F = _prep(X, F)
+    perm = _perm(X, F, perm, leaf)
+    vv = None if verts is None else np.ascontiguousarray(verts, dtype=np.int32)
+    nv = X.shape[0] if vv is None else vv.size
+    E = np.zeros(1)
+    G = np.zeros((nv, 3)) if want_grad else None
+    st = np.zeros(2, dtype=np.int64)
+    rc = _load().tpeo_farfield_dual(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], perm.ctypes.data,
+                                    int(leaf), float(theta), q, p, scale, None if vv is None else vv.ctypes.data,
+                                    nv, nthreads, E.ctypes.data, G.ctypes.data if want_grad else None,
+                                    st.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G, tuple(int(v) for v in st)

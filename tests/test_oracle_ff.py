@@ -1,0 +1,265 @@
+"""Pins of the FP64 oracle for the cluster approximations (oracle/tpe_oracle_ff.c; paper Sec. 3.2).
+
+The oracle follows eq. (dTP_reordered) face by face (inner integrals f_K, f_nu, f, clustered
+per target block) and the dual-tree energy with a complex-step derivative.  What fixes it:
+- theta = 0: nothing is admissible and both schemes must give tpeo_gradient's exact energy and
+  gradient (an independent organisation: pair derivatives pushed to six vertices there, per-face
+  inner integrals and their chain rule here);
+- the walk's invariants: from every target block each face is reached exactly once, and no far
+  cluster holds a face that shares a vertex with the block (the radii bound vertices);
+- a cluster of one face is its own monopole: the samples' targets (exact minus monopole) vanish;
+- the k-d order is a permutation, every node is split along its longest axis at the quantised
+  median position, and it keeps leaves compact;
+- the dual tree's complex-step gradient agrees with central differences of its own energy;
+- the scaling law E(2X) = E(X)/4 and G(2X) = G(X)/8 holds exactly for (q, p) = (6, 12), since a
+  power of two leaves every FP32 decision unchanged;
+- the approximation error falls with theta.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_22110_amd import meshes as M
+
+
+def _l3():
+    X, F = M.icosphere(3)
+    return M.radial_jitter(X, 0.01, 0), F
+
+
+def _l4():
+    X, F = M.icosphere(4)
+    return M.sh_deform(X, 2, 8, 0.05, 0)[0], F
+
+
+def _rel(G, G0):
+    return float(np.abs(G - G0).max() / np.abs(G0).max())
+
+
+@pytest.mark.parametrize("leaf", [1, 7, 32])
+def test_theta_zero_is_the_exact_gradient(leaf):
+    X, F = _l3()
+    E0, G0 = oracle.gradient(X, F)
+    E, G, st = oracle.farfield(X, F, 0.0, leaf=leaf)
+    assert abs(E - E0) <= 1e-13 * abs(E0) and _rel(G, G0) <= 1e-13
+    assert st[0] == 0 and st[1] == 20 * F.shape[0] and st[3] == 20  # every block saw every face
+    Ed, Gd, sd = oracle.farfield_dual(X, F, 0.0, leaf=leaf if 64 % leaf == 0 else 32)
+    assert abs(Ed - E0) <= 1e-13 * abs(E0) and _rel(Gd, G0) <= 1e-12
+    assert sd[0] == 0 and sd[1] == F.shape[0] ** 2
+
+
+def test_theta_zero_bumped_and_open_patch():
+    """The same on a bumped level-2 sphere (sheets 0.1 apart) and on an open patch cut from it."""
+    X, F = M.icosphere(2)
+    X, _, _ = M.bump(X, 0, 0.3, 0.1)
+    keep = np.where(X[F].mean(1)[:, 2] > -0.2)[0][:150]
+    for (Xs, Fs) in ((X, F), (X, F[keep])):
+        E0, G0 = oracle.gradient(Xs, Fs)
+        E, G, _ = oracle.farfield(Xs, Fs, 0.0, leaf=4)
+        assert abs(E - E0) <= 1e-13 * abs(E0) and _rel(G, G0) <= 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.25, 0.5, 1.0])
+def test_walk_covers_every_face_once_and_keeps_neighbours_near(theta):
+    for X, F in (_l3(), _l4()):
+        for leaf in (1, 32):
+            assert oracle.farfield_coverage(X, F, theta, leaf=leaf) == (0, 0)
+    # theta beyond 2 would let neighbours into far clusters; the bound argument needs the vertex radii
+    X, F = _l4()
+    assert oracle.farfield_coverage(X, F, 4.0, leaf=1)[1] > 0
+
+
+def test_single_face_clusters_are_exact():
+    X, F = _l4()
+    s = oracle.farfield_samples(X, F, 0.5, seed=3, select_prob=1.0, max_faces=1, leaf=1)
+    assert s["node"].size > 50
+    w = s["targets"][:, :, 7]
+    assert w.sum() > 0
+    assert np.abs(s["targets"][:, :, :7] * w[..., None]).max() <= 1e-9
+    # features: a single face's normal is coherent (|N| / A = 1) and has no second moment of offsets
+    assert np.abs(s["feats"][:, :, 6][w > 0] - 1.0).max() <= 1e-12
+    assert np.abs(s["feats"][:, :, 7:13][w > 0]).max() <= 1e-12
+
+
+def test_samples_selection_is_the_published_hash():
+    """MurmurHash3 fmix32 of known inputs, and the selection rule applied to every far cluster."""
+    # fmix32 pins: fmix32(0) = 0 and fmix32 is a bijection on a sample of inputs
+    assert oracle.sample_hash(0, 0, 0) == 0
+    hs = {oracle.sample_hash(7, b, 5) for b in range(4096)}
+    assert len(hs) == 4096
+    X, F = _l4()
+    a = oracle.farfield_samples(X, F, 0.5, seed=11, select_prob=1.0, max_faces=1 << 20)
+    b = oracle.farfield_samples(X, F, 0.5, seed=11, select_prob=0.1, max_faces=1 << 20)
+    thr = np.floor(0.1 * 2.0 ** 32)
+    want = {(int(bb), int(nn)) for bb, nn in zip(a["block"], a["node"])
+            if oracle.sample_hash(11, int(bb), int(nn)) <= thr}
+    got = {(int(bb), int(nn)) for bb, nn in zip(b["block"], b["node"])}
+    assert got == want and 0 < len(got) < len(a["node"])
+
+
+def test_kd_order_splits_nodes_along_their_longest_axis():
+    for leaf in (1, 5, 32):
+        X, F = _l4()
+        nF = F.shape[0]
+        perm = oracle.kd_order(X, F, leaf)
+        assert np.array_equal(np.sort(perm), np.arange(nF))
+        c = (X[F[:, 0]] + X[F[:, 1]] + X[F[:, 2]]) / 3.0
+        cf = c.astype(np.float32)[perm]
+        H = int(np.ceil(np.log2(-(-nF // leaf))))
+        for level in range(H):
+            cap = (1 << (H - level)) * leaf
+            for j0 in range(0, nF, cap):
+                node = cf[j0:min(j0 + cap, nF)]
+                half = cap // 2
+                if node.shape[0] <= half:
+                    continue
+                ext = node.max(0) - node.min(0)
+                ax = int(np.argmax(ext))
+                # the first child holds the lower part along the axis, up to the quantisation step
+                step = float(ext[ax]) / 65535.0 * 2.0
+                assert node[:half, ax].max() <= node[half:, ax].min() + step
+        # compact leaves: mean leaf radius far below that of the input order
+        def mean_radius(order):
+            r = []
+            for j0 in range(0, nF, leaf):
+                p = c[order[j0:j0 + leaf]]
+                r.append(np.linalg.norm(p - p.mean(0), axis=1).max())
+            return float(np.mean(r))
+        if leaf == 32:
+            assert mean_radius(perm) < 0.5 * mean_radius(np.random.default_rng(0).permutation(nF))
+
+
+def test_dual_complex_step_matches_finite_differences():
+    X, F = _l4()
+    verts = np.array([3, 100, 777, 2000])
+    E, G, st = oracle.farfield_dual(X, F, 0.5, verts=verts)
+    assert st[0] > 0  # far cluster pairs exist
+    h = 1e-6
+    for k, v in enumerate(verts):
+        for d in range(3):
+            Xp = X.copy(); Xp[v, d] += h
+            Xm = X.copy(); Xm[v, d] -= h
+            Ep, _, sp = oracle.farfield_dual(Xp, F, 0.5, want_grad=False)
+            Em, _, sm = oracle.farfield_dual(Xm, F, 0.5, want_grad=False)
+            assert sp == st and sm == st  # the same lists on both sides
+            fd = (Ep - Em) / (2 * h)
+            assert abs(fd - G[k, d]) <= 1e-6 * np.abs(G).max() + 1e-7 * abs(fd)
+
+
+def test_scaling_by_a_power_of_two_is_exact():
+    X, F = _l4()
+    E1, G1, s1 = oracle.farfield(X, F, 0.5)
+    E2, G2, s2 = oracle.farfield(2.0 * X, F, 0.5)
+    assert s1 == s2
+    assert abs(E2 - E1 / 4.0) <= 1e-14 * abs(E1) and _rel(G2, G1 / 8.0) <= 1e-14
+    Ed1, _, d1 = oracle.farfield_dual(X, F, 0.5, want_grad=False)
+    Ed2, _, d2 = oracle.farfield_dual(2.0 * X, F, 0.5, want_grad=False)
+    assert d1 == d2 and abs(Ed2 - Ed1 / 4.0) <= 1e-14 * abs(Ed1)
+
+
+def test_error_falls_with_theta():
+    X, F = M.make_config("C2").X, M.make_config("C2").F
+    E0, G0 = oracle.gradient(X, F)
+    prev = None
+    for th in (1.0, 0.5, 0.25):
+        E, G, st = oracle.farfield(X, F, th)
+        err = (abs(E - E0) / E0, _rel(G, G0))
+        assert st[0] > 0
+        if prev is not None:
+            assert err[0] < prev[0] and err[1] < prev[1]
+        prev = err
+    assert prev[0] < 1e-4 and prev[1] < 1e-6
+
+
+def _stacks(normals, centres, m=64, seed=0):
+    """Clusters of m triangles sharing one centroid and one normal: fans about a common vertex v
+    whose other two corners a_k, b_k keep a_k + b_k fixed (so the faces of a fan exclude one another
+    and have one centroid), with different areas.  The monopole of such a cluster is exact,
+    whatever its weights, for the forward and the reverse terms alike."""
+    rng = np.random.default_rng(seed)
+    Xs, Fs, nv = [], [], 0
+    for n, c in zip(normals, centres):
+        n = np.asarray(n, float) / np.linalg.norm(n)
+        c = np.asarray(c, float)
+        u = np.cross(n, [0.3, 0.5, 0.7]); u /= np.linalg.norm(u)
+        w = np.cross(n, u)  # (u, w, n) right-handed: u x w = n
+        r0 = 0.04
+        v = c + r0 * u
+        mid = c - 0.5 * r0 * u
+        Xs.append(v[None])
+        vi = nv
+        nv += 1
+        for k in range(m):
+            phi = 0.3 + 2.5 * k / m
+            t = 0.03 * (0.4 + rng.random()) * (np.cos(phi) * u + np.sin(phi) * w)
+            Xs.append(np.stack([mid + t, mid - t]))
+            Fs.append([vi, nv, nv + 1])
+            nv += 2
+    return np.concatenate(Xs), np.array(Fs, dtype=np.int32)
+
+
+def test_coincident_stacks_make_the_monopole_exact():
+    # a regular tetrahedron of stacks: a cluster of two stacks is never admissible, so every far
+    # cluster is one stack
+    normals = [(0, 0, 1), (1, 0.2, 0.1), (0.3, 1, -0.2), (-0.5, 0.4, 1)]
+    centres = [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]
+    X, F = _stacks(normals, centres)
+    E0, G0 = oracle.gradient(X, F)
+    for theta in (0.5, 1.0):
+        E, G, st = oracle.farfield(X, F, theta, leaf=32)
+        assert st[0] > 0, st  # the stacks are far from one another
+        assert abs(E - E0) <= 1e-12 * abs(E0) and _rel(G, G0) <= 1e-11
+        Ed, Gd, sd = oracle.farfield_dual(X, F, theta, leaf=32)
+        assert sd[0] > 0, sd
+        assert abs(Ed - E0) <= 1e-12 * abs(E0) and _rel(Gd, G0) <= 1e-11
+
+
+def test_sample_features_follow_their_definitions():
+    """Frame invariants, and the node moments recomputed directly from the cluster's faces (the
+    oracle builds them bottom-up with the parallel-axis shift)."""
+    X, F = _l4()
+    perm = oracle.kd_order(X, F, 32)
+    s = oracle.farfield_samples(X, F, 0.5, seed=5, select_prob=0.05, max_faces=1 << 20, perm=perm)
+    w = s["targets"][:, :, 7] > 0
+    x = s["feats"]
+    assert np.abs(x[..., 1] ** 2 + x[..., 2] ** 2 - 1.0)[w].max() <= 1e-12   # n_S in span(e1, e2)
+    assert np.abs((x[..., 3:6] ** 2).sum(-1) - 1.0)[w].max() <= 1e-12       # unit mean normal
+    assert np.abs(x[..., 13] + x[..., 16] + x[..., 18] - 1.0)[w].max() <= 1e-12  # tr(M2n) / A = 1
+    nF = F.shape[0]
+    H = int(np.ceil(np.log2(-(-nF // 32))))
+    a_all = 0.5 * np.linalg.norm(np.cross(X[F[:, 1]] - X[F[:, 0]], X[F[:, 2]] - X[F[:, 0]]), axis=1)
+    n_all = np.cross(X[F[:, 1]] - X[F[:, 0]], X[F[:, 2]] - X[F[:, 0]]) / (2 * a_all[:, None])
+    c_all = X[F].mean(1)
+    rng = np.random.default_rng(0)
+    internal = np.where(s["node"] < (1 << H))[0]
+    leaves = np.where(s["node"] >= (1 << H))[0]
+    assert internal.size >= 8 and leaves.size >= 4
+    for k in np.concatenate([rng.choice(internal, 8, replace=False), rng.choice(leaves, 4, replace=False)]):
+        b, node = int(s["block"][k]), int(s["node"][k])
+        lev = int(np.floor(np.log2(node)))
+        span = (1 << (H - lev)) * 32
+        p0 = (node - (1 << lev)) * span
+        faces = perm[p0:min(p0 + span, nF)]
+        a, c, n = a_all[faces], c_all[faces], n_all[faces]
+        A = a.sum(); C = (a[:, None] * c).sum(0) / A; N = (a[:, None] * n).sum(0)
+        M2c = np.einsum("i,ij,ik->jk", a, c - C, c - C) / A
+        M2n = np.einsum("i,ij,ik->jk", a, n, n) / A
+        for lane in range(64):
+            if not w[k, lane]:
+                continue
+            S = perm[b * 64 + lane]
+            D = c_all[S] - C
+            rho = np.linalg.norm(D)
+            e1 = D / rho
+            v = n_all[S] - (n_all[S] @ e1) * e1
+            e2 = v / np.linalg.norm(v)
+            E = np.stack([e1, e2, np.cross(e1, e2)])
+            rB = x[k, lane, 0] * rho / 4.0
+            iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+            mc = np.array([E[i] @ M2c @ E[j] for i, j in iu]) / rB ** 2
+            mn = np.array([E[i] @ M2n @ E[j] for i, j in iu])
+            want = np.concatenate([[n_all[S] @ e1, n_all[S] @ e2], E @ (N / np.linalg.norm(N)),
+                                   [np.linalg.norm(N) / A], mc, mn])
+            assert np.abs(x[k, lane, 1:19] - want).max() <= 1e-10
+            # the radius bounds every vertex of the cluster
+            assert rB * (1 + 1e-6) >= np.linalg.norm(X[F[faces]].reshape(-1, 3) - C, axis=1).max()
