@@ -198,13 +198,33 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
 /* Free a tree. */
 int tpe_tree_destroy(tpe_tree* tree);
 
+/* perm_dev (device u32 [n], caller-owned) <- the tree's order: perm_dev[i] is the item (face, or
+ * point record Q f + point for a tpe_build_tree_p3 tree) at tree position i; node k of the implicit
+ * tree (root 1, children 2k and 2k + 1, leaves 2^H .. 2^H + ceil(n / leaf) - 1) holds the positions
+ * [(k - 2^l) leaf 2^(H - l), (k - 2^l + 1) leaf 2^(H - l)) clipped to n, l = floor(log2 k).  The
+ * order is the k-d order of tpe_build_tree: level by level, the items of every node are sorted
+ * stably by key = (node << b) | quantised coordinate, the coordinate being the FP32 centroid's
+ * along the longest axis of the node's FP32 centroid box, quantised to b = min(16, 32 - level)
+ * bits as (uint32) min(max((x - lo) / extent * (2^b - 1), 0), 2^b - 1) in FP32 (0 for a box of
+ * zero extent); the FP32 centroid is the FP64 mean of the three corners, rounded (paper Sec. 3.2
+ * leaves the tree open).  n must be the tree's item count (nF, or nF Q). */
+int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64_t n);
+
 /* Barnes-Hut approximation of E and dE/dX on the tree (paper Sec. 3.2, clustering of the inner
  * integrals of eq. (dTP_reordered)).  Every block of 64 consecutive faces in tree order is
  * enclosed by a ball (C_T, r_T); a cluster B with area A_B, area-weighted centroid C_B, unit
  * mean normal N_B and vertex-bounding radius r_B is far when 2 r_B < theta (|C_T - C_B| - r_T)
  * and then acts on each face of the block as one pseudo-face (C_B, A_B, N_B); every other pair is
- * evaluated exactly, with the shared-vertex exclusion.  theta = 0 reproduces tpe_gradient to
- * rounding.  mlp: NULL for the plain monopole.  E_dev and/or G_dev (device) may be NULL but not
+ * evaluated exactly, with the shared-vertex exclusion.  r_B is the largest distance from C_B to a
+ * vertex of a leaf's faces, and max over the children of |C_child - C_B| + r_child above; r_T the
+ * largest distance from C_T (the mean of the block's centroids) to a vertex of the block.  The test
+ * is taken in FP32 on the mesh scaled by the power of two 2^k that brings the largest extent of the
+ * FP32 centroid box into [0.5, 1): centres rounded to FP32, radii r + 1e-6 (1 + |C|_1) rounded up,
+ * |C_T - C_B| = sqrt(fma(dz, dz, fma(dy, dy, dx dx))).  theta in [0, 1] (theta <= 2 keeps faces that
+ * share a vertex with the block out of far clusters; else TPE_ERR_INVALID_ARG); theta = 0
+ * reproduces tpe_gradient to rounding.  G is the clustered form of eq. (dTP_reordered) (each
+ * face's inner integrals with far patches replaced by their averages), not the derivative of E:
+ * the paper propagates nothing back to the patches.  mlp: NULL for the plain monopole.  E_dev and/or G_dev (device) may be NULL but not
  * both.  X, V, F, nF must describe the mesh the tree was built for (same size, same faces). */
 int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
@@ -215,7 +235,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
  * TPE_OPT_QUADRATURE at build time (1, 3 or 6 points); its items are those point records, so
  * clusters gather points, a cluster acts on each point of a target block as one pseudo-record,
  * and near pairs of points are summed exactly with the exclusion of element pairs sharing a
- * corner node.  theta = 0 reproduces tpe_gradient_p3 with the same rule to rounding.  The ordering
+ * corner node.  theta in [0, 1]; theta = 0 reproduces tpe_gradient_p3 with the same rule to rounding.  The ordering
  * and the per-block work record (as for tpe_build_tree, blocks of 64 points) are kept; positions,
  * weights, normals and moments are recomputed from X on every call. */
 int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF,
@@ -294,18 +314,22 @@ int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out);
 /* Training samples for the learned correction, drawn with the same tree walk as tpe_farfield at
  * opening parameter theta.  A far cluster with at most max_cluster_faces faces is selected with
  * probability ~select_prob (a hash of seed, target block and node; deterministic), up to `quota`
- * clusters per target block of 64 faces; each selected (block, cluster) yields one sample per face
- * of the block:
+ * clusters per target block of 64 faces (in walk order); cluster B of block b is selected when
+ * u = fmix32(fmix32(fmix32(s) ^ b) ^ B) <= floor(select_prob 2^32) (every cluster for select_prob =
+ * 1), s = low 32 bits of seed ^ (seed >> 32), fmix32 the 32-bit finaliser of MurmurHash3.  theta in
+ * (0, 1].  Each selected (block, cluster) yields one sample per face of the block:
  *   feats   (device f32, rows x 32): features of the (face, cluster) pair in a local frame
  *           e1 = unit(c_S - C_B), e2 = unit part of n_S orthogonal to e1, e3 = e1 x e2:
- *           [4 r_B/rho, n_S.e1, n_S.e2, mean normal of B (3), |N_B|/A_B, 16 M2c/(A_B rho^2) (6),
- *            M2n/A_B (6), 0 x 13], rho = |c_S - C_B|, M2c / M2n the area-weighted second moments
- *           of centroid offsets and of normals;
+ *           [4 r_B/rho, n_S.e1, n_S.e2, mean normal of B (3), |N_B|/A_B, M2c/(A_B r_B^2) (6),
+ *            M2n/A_B (6), 0 x 13] (the symmetric forms e_a . M e_b in the order 11 12 13 22 23 33),
+ *           rho = |c_S - C_B|, r_B the FP32 radius of the admissibility test, M2c / M2n the
+ *           area-weighted second moments of centroid offsets (about C_B) and of normals;
  *   targets (device f32, rows x 16): the exact sum over B's faces minus the monopole of the
  *           quantities the face's gradient is made of: K (dE/da), Sd[3] (dE/dn) and the net
  *           C[3] = q (n_S S0 + Sn) - p Sdd (dE/dc), vectors in the frame, divided by
- *           A_B rho^-6 (K, Sd) or A_B rho^-7 (C); columns 7..14 zero; column 15 = weight
- *           (1, or 0 for an unused row).
+ *           A_B rho^-6 (K, Sd) or A_B rho^-7 (C); columns 7..13 zero; column 14 = the
+ *           cluster's node index (as a float); column 15 = weight (1, or 0 for an unused row,
+ *           whose other columns are 0).
  * rows = ceil(nF / 64) * quota * 64; the caller allocates the outputs.  If mlp is not NULL, pred
  * (device f32, rows x 16) receives the network's output for each sample computed by the same
  * in-walk (fused) inference tpe_farfield uses; otherwise pred must be NULL. */

@@ -74,6 +74,7 @@ def lib():
             "tpe_kernel_time": ([P, ctypes.POINTER(D), ctypes.POINTER(I64)], I),
             "tpe_build_tree": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
             "tpe_tree_destroy": ([P], I),
+            "tpe_tree_order": ([P, P, P, I64], I),
             "tpe_farfield": ([P, P, P, I64, P, I64, D, D, D, D, P, P, P], I),
             "tpe_farfield_dual": ([P, P, P, I64, P, I64, D, D, D, D, P, P], I),
             "tpe_build_tree_p3": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
@@ -293,6 +294,15 @@ class Tree:
         c.check(lib().tpe_build_tree(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0], int(leaf),
                                      ctypes.byref(h)))
         self.h, self.nF, self.V, self.leaf, self.device = h, F.shape[0], X.shape[0], leaf, X.device
+
+    def order(self) -> torch.Tensor:
+        """The tree order: item at each tree position, int32 [n] on the tree's device (the bits of
+        the u32 permutation; see tpe_tree_order)."""
+        n = self.nF * getattr(self, "points", 1)
+        out = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = context(self.device)
+        c.check(lib().tpe_tree_order(c.h, self.h, out.data_ptr(), n))
+        return out
 
     def __del__(self):
         try:

@@ -880,7 +880,9 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     if (tree->Q < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built over flat faces (tpe_build_tree)");
     if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
     if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
-    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be >= 0");
+    // theta <= 2 keeps every face sharing a vertex with the block out of the far clusters (the radii
+    // bound vertices: a shared vertex means |C_T - C_B| - r_T <= r_B); [0, 1] as for the dual tree
+    if (!(theta >= 0.0 && theta <= 1.0)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be in [0, 1]");
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
@@ -931,6 +933,17 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     return TPE_OK;
 }
 
+int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64_t n) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!tree || !perm_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null tree or output");
+    if (n != tree->n) return fail(ctx, TPE_ERR_INVALID_ARG, "n must be the tree's item count");
+    if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(hipMemcpyAsync(perm_dev, tree->perm, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    if (ctx->sync_checks) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return TPE_OK;
+}
+
 int tpe_tree_destroy(tpe_tree* t) {
     if (!t) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(t->device);
@@ -948,7 +961,9 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (tree->nF != nF || tree->V != V) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built for another mesh size");
     if (tree->Q != 0) return fail(ctx, TPE_ERR_INVALID_ARG, "tree was built over curved elements");
     if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
-    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be >= 0");
+    // theta <= 2 keeps every face sharing a vertex with the block out of the far clusters (the radii
+    // bound vertices: a shared vertex means |C_T - C_B| - r_T <= r_B); [0, 1] as for the dual tree
+    if (!(theta >= 0.0 && theta <= 1.0)) return fail(ctx, TPE_ERR_INVALID_ARG, "theta must be in [0, 1]");
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     if (!E_dev && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "nothing to compute");
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
@@ -1057,7 +1072,7 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
         return fail(ctx, TPE_ERR_INVALID_ARG, "tree/mesh mismatch");
     if (!feats || !targets) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
     if ((mlp == nullptr) != (pred == nullptr)) return fail(ctx, TPE_ERR_INVALID_ARG, "mlp and pred go together");
-    if (!(theta > 0.0) || !(select_prob >= 0.0 && select_prob <= 1.0) || quota < 1 || quota > 1024 ||
+    if (!(theta > 0.0 && theta <= 1.0) || !(select_prob >= 0.0 && select_prob <= 1.0) || quota < 1 || quota > 1024 ||
         max_cluster_faces < 1)
         return fail(ctx, TPE_ERR_INVALID_ARG, "bad sampling parameters");
     DeviceGuard dg(ctx->device);

@@ -35,7 +35,7 @@ constexpr int DUAL_SPAN = 64;
 
 __device__ __forceinline__ bool dual_far(const NodeRec& a, const NodeRec& b, float theta) {
     const float dx = a.cx - b.cx, dy = a.cy - b.cy, dz = a.cz - b.cz;
-    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float d = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));  // fixed order: an exact FP32 decision
     // FP32 slack on the distance; theta <= 1 makes the vertex balls disjoint
     return 2.f * fmaxf(a.r, b.r) < theta * d * (1.f - 1e-5f);
 }

@@ -336,6 +336,13 @@ __device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, 
     }
 }
 
+// |C_T - C_B| for the admissibility test, with the products in a fixed order (the decision is an
+// integer outcome of FP32 arithmetic, reproduced exactly by an independent evaluation).
+__device__ __forceinline__ float ball_dist(const float4& tb, const NodeRec& nd) {
+    const float dx = tb.x - nd.cx, dy = tb.y - nd.cy, dz = tb.z - nd.cz;
+    return sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+}
+
 constexpr int FF_STACK = 1024;  // LDS node stack per wave (overflow falls back to exact evaluation)
 constexpr int FF_STACK_LEARNED = 512;  // the same with the learned correction, whose MLP scratch shares the LDS
 constexpr int FF_NW = 4;          // waves per target block, monopole far field
@@ -410,9 +417,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         NodeRec nd = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (act) nd = nodes[k];
         n_visit += n;
-        const float dx = tb.x - nd.cx, dy = tb.y - nd.cy, dz = tb.z - nd.cz;
-        const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
         const bool valid = act && nd.a > 0.f;
+        const float dist = ball_dist(tb, nd);
         const bool far = valid && (2.f * nd.r < theta * (dist - tb.w));
         const bool isleaf = (int64_t)k >= leaf0;
         bool open = valid && !far && !isleaf;
@@ -516,11 +522,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     }
 }
 
-__device__ __forceinline__ uint32_t hash3(uint32_t a, uint32_t b, uint32_t c) {
-    // 32-bit finaliser of a simple multiply-xorshift mix (deterministic sample selection)
-    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
-    h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+// MurmurHash3's 32-bit finaliser (Appleby): a bijective avalanche mix.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
     return h;
+}
+
+// Deterministic sample selection: u(seed, block, node) = fmix32(fmix32(fmix32(seed) ^ block) ^ node).
+__device__ __forceinline__ uint32_t sample_hash(uint32_t seed, uint32_t block, uint32_t node) {
+    return fmix32(fmix32(fmix32(seed) ^ block) ^ node);
 }
 
 // Training samples: the same walk as farfield_kernel; for far clusters with at most max_faces
@@ -563,9 +577,8 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
         const int k = act ? stack[sz + lane] : 0;
         NodeRec nd = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (act) nd = nodes[k];
-        const float dx = tb.x - nd.cx, dy = tb.y - nd.cy, dz = tb.z - nd.cz;
-        const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
         const bool valid = act && nd.a > 0.f;
+        const float dist = ball_dist(tb, nd);
         const bool far = valid && (2.f * nd.r < theta * (dist - tb.w));
         const bool isleaf = (int64_t)k >= leaf0;
         bool open = valid && !far && !isleaf;
@@ -589,7 +602,7 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
             const int64_t span = (int64_t)1 << (H - lev);
             const int64_t f0 = ((int64_t)kk - ((int64_t)1 << lev)) * span * leaf;
             const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-            if (f1 - f0 > max_faces || hash3(seed, (uint32_t)b, (uint32_t)kk) > sel) continue;
+            if (f1 - f0 > max_faces || sample_hash(seed, (uint32_t)b, (uint32_t)kk) > sel) continue;
             NodeRec cn;
             cn.cx = lane_f(nd.cx, l); cn.cy = lane_f(nd.cy, l); cn.cz = lane_f(nd.cz, l); cn.r = lane_f(nd.r, l);
             cn.a = lane_f(nd.a, l); cn.nx = lane_f(nd.nx, l); cn.ny = lane_f(nd.ny, l); cn.nz = lane_f(nd.nz, l);
@@ -621,6 +634,7 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
             for (int q = 1; q < 4; ++q) y[q] /= u6;
             for (int q = 4; q < 7; ++q) y[q] /= u7;
             for (int q = 7; q < 16; ++q) y[q] = 0.f;
+            y[14] = (float)kk;  // the cluster's node (exact below 2^24): which cluster the sample is of
             bool fin = rowok;
             for (int q = 0; q < 7; ++q) fin &= isfinite(y[q]);
             y[15] = fin ? 1.f : 0.f;

@@ -39,7 +39,9 @@ def test_error_decreases_with_theta():
         log("C2 theta", th, "rel E", errs[-1][0], "rel G", errs[-1][1])
     assert errs[0][1] > errs[1][1] > errs[2][1]
     assert errs[0][0] > errs[2][0]
-    assert errs[0][1] < 0.5  # monopole far field at theta = 0.5 is a rough but sane approximation
+    # element-wise parity with the oracle of the scheme is tests/test_gpu_ff_parity.py; here the
+    # size of the approximation error the oracle gives at theta = 0.5 (5.8e-6), with margin
+    assert errs[0][1] < 2e-5
 
 
 @pytest.mark.parametrize("cfg", ["C1", "C2"])
@@ -77,6 +79,8 @@ def test_farfield_errors():
     with pytest.raises(T.TPEError):
         T.farfield(tree, Xd, Fd, theta=-1.0)
     with pytest.raises(T.TPEError):
+        T.farfield(tree, Xd, Fd, theta=1.5)  # beyond 2 neighbours could enter far clusters; [0, 1] taken
+    with pytest.raises(T.TPEError):
         T.build_tree(Xd, Fd, leaf=0)
 
 
@@ -110,8 +114,8 @@ def test_c4_far_field_vs_exact():
     eS = float(np.abs(G0[verts] - Go).max() / np.abs(Go).max())
     log("C4 exact vs oracle (sampled)", eS)
     assert eS <= 1e-5
-    assert t_exact / t_ff > 5.0
-    assert eG < 0.5
+    assert t_exact / t_ff > 10.0
+    assert eG <= 1e-3  # the far-field target against the exact gradient
 
 
 def test_farfield_calls_on_a_user_stream():
