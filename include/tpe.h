@@ -24,7 +24,9 @@
  *     argument says "host".  X is row-major float64 [V][3]; F is row-major int32 [nF][3], 0-based
  *     vertex indices; face orientation does not matter for the exact path (|.| in the kernel).
  *   - Work is enqueued on the context's stream and is asynchronous.  Outputs are valid once the
- *     stream reaches them.  The library owns only opaque objects (context, scratch arena).
+ *     stream reaches them.  Calls of one context are ordered among themselves even when the
+ *     stream changes between them (tpe_set_stream).  The library owns only opaque objects
+ *     (context, scratch arena).
  *   - Return value: TPE_OK or a negative tpe_status; tpe_last_error() gives a message.  Inputs
  *     that can only be checked on the device (vertex indices in range, finite coordinates,
  *     non-degenerate faces, finite result) are checked by the kernels, which never read out of
@@ -106,7 +108,11 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream);
 /* Destroy a context and free its scratch arena.  Waits for the context's stream first. */
 int tpe_destroy(tpe_ctx* ctx);
 
-/* Rebind the stream work is enqueued on (e.g. PyTorch's current stream). */
+/* Rebind the stream work is enqueued on (e.g. PyTorch's current stream).  The context's calls stay
+ * ordered across streams: every call records an event on its stream when it returns, and a call on
+ * another stream than the previous call's first makes its stream wait for that event (on the
+ * device; no host synchronisation).  Work the caller enqueues itself is ordered by the caller's
+ * streams as usual: results of a call on stream A are complete for later work on A. */
 int tpe_set_stream(tpe_ctx* ctx, void* hip_stream);
 
 /* Set an option (tpe_option).  Returns TPE_ERR_INVALID_ARG for unknown options or values. */

@@ -172,6 +172,11 @@ struct tpe_ctx {
     // reads: it runs beside the moments and the walk, forked from and joined back into `stream`
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // end of the last call that enqueued work: recorded on that call's stream, waited for by the
+    // next call when it runs on another stream (see Ordered)
+    hipEvent_t done = nullptr;
+    hipStream_t done_stream = nullptr;
+    bool done_valid = false;
 };
 
 struct tpe_mlp {
@@ -226,6 +231,37 @@ int hip_fail(tpe_ctx* c, hipError_t e, const char* where) {
         hipError_t e_ = (expr);                                   \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);    \
     } while (0)
+
+// Stream order of the calls of one context.  Every call enqueues on ctx->stream; if the previous
+// call ran on another stream (tpe_set_stream in between, as the Python binding does for torch's
+// current stream), the new stream first waits for the event recorded at the end of that call.  On
+// leaving, the call records the event on its own stream.  So calls never overlap on the context's
+// scratch arena, flags or counters whatever streams they run on, and a stream the caller has
+// switched away from may be destroyed afterwards (the event was recorded on it already).
+struct Ordered {
+    tpe_ctx* ctx;
+    int rc = TPE_OK;
+    explicit Ordered(tpe_ctx* c) : ctx(c) {
+        if (ctx->done_valid && ctx->done_stream != ctx->stream) {
+            const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->done, 0);
+            if (e != hipSuccess) rc = hip_fail(ctx, e, "hipStreamWaitEvent");
+        }
+    }
+    ~Ordered() {
+        if (hipEventRecord(ctx->done, ctx->stream) == hipSuccess) {
+            ctx->done_stream = ctx->stream;
+            ctx->done_valid = true;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    Ordered(const Ordered&) = delete;
+    Ordered& operator=(const Ordered&) = delete;
+};
+
+#define ORDERED(ctx)                    \
+    Ordered ordered_call_(ctx);         \
+    if (ordered_call_.rc) return ordered_call_.rc
 
 // Bump allocator over the arena; 256-byte aligned slices.
 struct Carve {
@@ -415,7 +451,10 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
 int ensure_arena(tpe_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->arena_bytes) return TPE_OK;
     if (ctx->arena) {
-        hipError_t e = hipStreamSynchronize(ctx->stream);
+        // every earlier user of the arena: the calls before this one (ended by ctx->done, on
+        // whichever stream), the side stream, and what this call has enqueued so far
+        hipError_t e = ctx->done_valid ? hipEventSynchronize(ctx->done) : hipSuccess;
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->side);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
         (void)hipFree(ctx->arena);
@@ -505,6 +544,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     const bool grad = G != nullptr;
     if (nF * ctx->quad > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
     rc = ensure_arena(ctx, P.bytes);
@@ -515,16 +555,18 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
         rc = ensure_arena(ctx, P.bytes);
     }
     if (rc) return rc;
-    layout(P, ctx->arena, grad);
+    char* base = ctx->arena;
+    layout(P, base, grad);
     hipStream_t st = ctx->stream;
     if ((rc = prepare(ctx, P, X, F))) return rc;
     if (p3 && grad)
         HIPCHK(launch_p3_nodes(F, nF, P.Q, P.Q, V, P.vals, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx->kernel_timing) {
+    const int timing = ctx->kernel_timing;
+    if (timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
+    if (timing == 1) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) {
         HIPCHK(launch_pair_sym(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.ssc, P.part, P.colpart,
                                P.first, st));
@@ -532,8 +574,8 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
         HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part,
                            st));
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
-    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
+    if (timing == 1) HIPCHK(hipEventRecord(ev1, st));
+    if (timing == 2) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) HIPCHK(launch_sym_merge(grad, P.part, P.colpart, P.first, P.ssc, P.nR, P.Fp, P.acc64, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     if (p3) {
@@ -547,7 +589,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
                                grad ? &en : nullptr, st));
         if (grad) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G, en, st));
     }
-    if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
+    if (timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
 }
@@ -564,6 +606,7 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
     const bool grad = G != nullptr;
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     plan(P, ctx, nF, V, grad, -1, nFY, VY);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
@@ -666,8 +709,10 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         hipStreamSynchronize(ctx->stream) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
+        if (ctx->done) (void)hipEventDestroy(ctx->done);
         if (ctx->join) (void)hipEventDestroy(ctx->join);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
         if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -683,6 +728,7 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
 int tpe_destroy(tpe_ctx* ctx) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(ctx->device);
+    if (ctx->done_valid) (void)hipEventSynchronize(ctx->done);
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamSynchronize(ctx->side);
     if (ctx->arena) (void)hipFree(ctx->arena);
@@ -691,6 +737,7 @@ int tpe_destroy(tpe_ctx* ctx) {
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     (void)hipEventDestroy(ctx->fork);
     (void)hipEventDestroy(ctx->join);
+    (void)hipEventDestroy(ctx->done);
     (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return TPE_OK;
@@ -736,6 +783,7 @@ const char* tpe_last_error(const tpe_ctx* ctx) { return ctx ? ctx->err.c_str() :
 int tpe_check(tpe_ctx* ctx) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     int rc = report_flags(ctx);
     if (launch_fill(ctx->dflags, 0u, 1, ctx->stream) != hipSuccess) return hip_fail(ctx, hipGetLastError(), "fill");
     return rc;
@@ -761,6 +809,7 @@ int tpe_sort_pairs(tpe_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int 
     if (bits < 1 || bits > 32) return fail(ctx, TPE_ERR_INVALID_ARG, "bits must be in [1, 32]");
     if (n <= 1) return TPE_OK;
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Carve plan_c(nullptr);
     plan_c.take<uint32_t>(n);
     plan_c.take<uint32_t>(n);
@@ -815,6 +864,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     if (rc) return rc;
     if (leaf_size < 1 || leaf_size > 4096) return fail(ctx, TPE_ERR_INVALID_ARG, "leaf_size must be in [1, 4096]");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     const int H = tree_height(nF, leaf_size);
     Plan P;
     plan(P, ctx, nF, V, false, H);
@@ -847,6 +897,7 @@ int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
     const int64_t n = nF * Q;
     if (n > (int64_t)1 << 26) return fail(ctx, TPE_ERR_INVALID_ARG, "too many quadrature points (> 2^26)");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     const int H = tree_height(n, leaf_size);
     Plan P;
     plan(P, ctx, nF, V, false, H, 0, 0, Q, false, true);
@@ -888,6 +939,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
     if (mlp && mlp->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "MLP lives on another device");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     const int Q = tree->Q;
     const int64_t n = tree->n;
     Plan P;
@@ -939,6 +991,7 @@ int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64
     if (n != tree->n) return fail(ctx, TPE_ERR_INVALID_ARG, "n must be the tree's item count");
     if (tree->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "tree lives on another device");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     HIPCHK(hipMemcpyAsync(perm_dev, tree->perm, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
     if (ctx->sync_checks) HIPCHK(hipStreamSynchronize(ctx->stream));
     return TPE_OK;
@@ -970,6 +1023,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (mlp && mlp->device != ctx->device) return fail(ctx, TPE_ERR_INVALID_ARG, "MLP lives on another device");
     if (ctx->quad != 1) return fail(ctx, TPE_ERR_UNSUPPORTED, "the far field uses one point per face");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     plan(P, ctx, nF, V, true, tree->H);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
@@ -1025,6 +1079,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     if (G_dev && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
     if (ctx->quad != 1) return fail(ctx, TPE_ERR_UNSUPPORTED, "the far field uses one point per face");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     P.dual_leaf = tree->leaf;
     plan(P, ctx, nF, V, true, tree->H);
@@ -1076,6 +1131,7 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
         max_cluster_faces < 1)
         return fail(ctx, TPE_ERR_INVALID_ARG, "bad sampling parameters");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     plan(P, ctx, nF, V, true, tree->H);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
@@ -1098,6 +1154,7 @@ int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!out_host) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(h, ctx->dstats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1172,6 +1229,7 @@ int tpe_mlp_get_params(tpe_ctx* ctx, const tpe_mlp* m, float* host, int64_t n) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !host || n != MLP_NPARAM) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP parameter buffer");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     HIPCHK(hipMemcpyAsync(host, m->P, n * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return TPE_OK;
@@ -1181,6 +1239,7 @@ int tpe_mlp_set_params(tpe_ctx* ctx, tpe_mlp* m, const float* host, int64_t n) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !host || n != MLP_NPARAM) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP parameter buffer");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     HIPCHK(hipMemcpyAsync(m->P, host, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1205,6 +1264,7 @@ int tpe_mlp_set_gate(tpe_ctx* ctx, tpe_mlp* m, float min_s) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !(min_s >= 0.f) || !std::isfinite(min_s)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad gate");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     m->min_s = min_s;
     HIPCHK(mlp_pack_launch(m->P, m->min_s, m->packed, ctx->stream));
     return TPE_OK;
@@ -1214,6 +1274,7 @@ int tpe_mlp_forward(tpe_ctx* ctx, const tpe_mlp* m, const float* feats, int64_t 
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !feats || !out || n < 0) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP forward arguments");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     HIPCHK(mlp_infer_launch(m->packed, feats, n, out, ctx->stream));
     return TPE_OK;
 }
@@ -1224,6 +1285,7 @@ static int mlp_step(tpe_ctx* ctx, tpe_mlp* m, const float* feats, const float* t
     if (!m || !feats || !targets || n < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "bad MLP training arguments");
     if (!grad_dev && !(lr > 0.f && std::isfinite(lr))) return fail(ctx, TPE_ERR_INVALID_ARG, "lr must be > 0");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     int rc = mlp_alloc_parts(ctx, m, mlp_tiles(n));
     if (rc) return rc;
     if (!grad_dev) ++m->step;
@@ -1251,6 +1313,7 @@ int tpe_mlp_save(tpe_ctx* ctx, const tpe_mlp* m, const char* path) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!m || !path) return fail(ctx, TPE_ERR_INVALID_ARG, "bad save arguments");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     std::vector<float> buf(3 * (size_t)MLP_NPARAM);
     HIPCHK(hipMemcpyAsync(buf.data(), m->P, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(buf.data() + MLP_NPARAM, m->M, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost,
@@ -1313,6 +1376,7 @@ int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!total_ms || !count) return fail(ctx, TPE_ERR_INVALID_ARG, "null output");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     double tot = 0.0;
     for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
@@ -1330,6 +1394,7 @@ int tpe_pair_count(tpe_ctx* ctx, const int32_t* F, int64_t nF, int64_t V, int64_
     if (!ctx) return TPE_ERR_INVALID_ARG;
     if (!F || !out_host || nF < 1 || V < 1) return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
     DeviceGuard dg(ctx->device);
+    ORDERED(ctx);
     Plan P;
     plan(P, ctx, nF, V, false);
     int rc = ensure_arena(ctx, P.bytes);
