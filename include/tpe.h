@@ -136,6 +136,20 @@ int tpe_energy(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64
 int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                  double q, double p, double scale, double* E_dev, double* G_dev);
 
+/* tpe_gradient for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same energy and gradient, computed with the
+ * row-only pair kernel (as tpe_gradient with TPE_OPT_SYMMETRIC = 0, to the same bits) in a scratch
+ * array of 64 MiB that the library holds on every device it runs on until the process ends, instead
+ * of the context's arena.  Makes no device or host allocation (no hipMalloc, no event creation;
+ * TPE_OPT_KERNEL_TIMING is ignored).  Meshes whose scratch exceeds 64 MiB (about 147,000 faces
+ * with one quadrature point: 456 bytes per face at 327,680) return TPE_ERR_INVALID_ARG with the
+ * size in the message.  All calls on one device share that array, which keeps the last call's
+ * contents: calls that overlap on one device (other contexts, or other host threads) race and must
+ * be serialised by the caller; calls of one context are ordered as usual.  Arguments and errors as
+ * for tpe_gradient; flat faces only. */
+int tpe_gradient_noalloc(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
+                         double q, double p, double scale, double* E_dev, double* G_dev);
+
 /* The same energy and gradient on curved cubic (P3) elements, the paper's surface S_h^3 (Sec. 3.1)
  * with its quadrature at the points of the curved elements (Sec. 3.2).
  * X: device f64 [V][3], all nodes; F10: device i32 [nF][10], the nodes of each element at the

@@ -65,6 +65,7 @@ def lib():
             "tpe_check": ([P], I),
             "tpe_energy": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_gradient": ([P, P, I64, P, I64, D, D, D, P, P], I),
+            "tpe_gradient_noalloc": ([P, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_energy_p3": ([P, P, I64, P, I64, D, D, D, P], I),
             "tpe_sort_pairs": ([P, P, P, I64, I], I),
             "tpe_gradient_p3": ([P, P, I64, P, I64, D, D, D, P, P], I),
@@ -197,6 +198,18 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
     c = context(X.device)
     c.check(lib().tpe_gradient(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
                                float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
+    return E, G
+
+
+def gradient_noalloc(X, F, q=6.0, p=12.0, scale=1.0, out=None, energy_out=None):
+    """gradient() without any device allocation inside the library (tpe_gradient_noalloc): pass
+    `out` and `energy_out` to allocate nothing at all."""
+    X, F = _check_mesh(X, F)
+    G = out if out is not None else torch.empty_like(X)
+    E = energy_out if energy_out is not None else torch.empty((), dtype=torch.float64, device=X.device)
+    c = context(X.device)
+    c.check(lib().tpe_gradient_noalloc(c.h, X.data_ptr(), X.shape[0], F.data_ptr(), F.shape[0],
+                                       float(q), float(p), float(scale), E.data_ptr(), G.data_ptr()))
     return E, G
 
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,6 +150,36 @@ __global__ void face_ids(const int32_t* __restrict__ F, int64_t nF, int64_t V, i
 }  // namespace tpe
 
 using namespace tpe;
+
+// ---- scratch of the entry point that allocates nothing (tpe_gradient_noalloc) -------------------
+// One file-scope device array, which every GPU the library runs on holds for the process's life.
+// In host code `noalloc_scratch` names a host-side stand-in, not device memory: its device address
+// is looked up once per device (tpe_create, with the device current) and only that address is
+// handed to kernels.  Every tpe_gradient_noalloc call on a device uses that device's copy.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char noalloc_scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::vector<void*> g_noalloc_ptr;  // device address of noalloc_scratch per device (null: not looked up)
+
+// With `device` current: look up its copy of the array, once.
+void noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if ((int)g_noalloc_ptr.size() <= device) g_noalloc_ptr.resize((size_t)device + 1, nullptr);
+    if (g_noalloc_ptr[device]) return;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)) == hipSuccess && ptr)
+        g_noalloc_ptr[device] = ptr;
+    else
+        (void)hipGetLastError();  // tpe_gradient_noalloc then reports TPE_ERR_HIP
+}
+
+void* noalloc_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return device >= 0 && device < (int)g_noalloc_ptr.size() ? g_noalloc_ptr[device] : nullptr;
+}
+}  // namespace
 
 struct tpe_ctx {
     int device = 0;
@@ -536,8 +567,10 @@ int prepare(tpe_ctx* ctx, Plan& P, const double* X, const int32_t* F) {
 }
 
 // p3: curved cubic elements (F: 10 node ids per element, corners first; V: all nodes)
+// noalloc: carve the scratch from the device's static array instead of the context's arena (no
+// allocation of any kind; the row-only pair kernel, whose scratch is linear in the faces)
 int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
-              double scale, double* E, double* G, bool p3 = false) {
+              double scale, double* E, double* G, bool p3 = false, bool noalloc = false) {
     int rc = check_common(ctx, X, V, F, nF, q, p, true);
     if (rc) return rc;
     if (!std::isfinite(scale)) return fail(ctx, TPE_ERR_INVALID_ARG, "scale must be finite");
@@ -546,23 +579,34 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     DeviceGuard dg(ctx->device);
     ORDERED(ctx);
     Plan P;
-    plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
-    rc = ensure_arena(ctx, P.bytes);
-    if (rc == TPE_ERR_OOM && P.sym) {  // no room for the column partials: the row-only kernel
-        P = Plan();
+    char* base = nullptr;
+    if (noalloc) {
         plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, false, p3);
-        ctx->err.clear();
+        base = static_cast<char*>(noalloc_ptr(ctx->device));
+        if (!base) return fail(ctx, TPE_ERR_HIP, "the no-allocation scratch has no device address");
+        if (P.bytes > NOALLOC_SCRATCH_BYTES)
+            return fail(ctx, TPE_ERR_INVALID_ARG,
+                        "mesh too large for the no-allocation scratch: " + std::to_string(P.bytes) +
+                            " bytes needed, " + std::to_string(NOALLOC_SCRATCH_BYTES) + " available");
+    } else {
+        plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
         rc = ensure_arena(ctx, P.bytes);
+        if (rc == TPE_ERR_OOM && P.sym) {  // no room for the column partials: the row-only kernel
+            P = Plan();
+            plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, false, p3);
+            ctx->err.clear();
+            rc = ensure_arena(ctx, P.bytes);
+        }
+        if (rc) return rc;
+        base = ctx->arena;
     }
-    if (rc) return rc;
-    char* base = ctx->arena;
     layout(P, base, grad);
     hipStream_t st = ctx->stream;
     if ((rc = prepare(ctx, P, X, F))) return rc;
     if (p3 && grad)
         HIPCHK(launch_p3_nodes(F, nF, P.Q, P.Q, V, P.vals, P.ncnt, P.noff, P.ncursor, P.nlist, P.scanws, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    const int timing = ctx->kernel_timing;
+    const int timing = noalloc ? 0 : ctx->kernel_timing;  // timing events are created on demand: not here
     if (timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
@@ -696,6 +740,7 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         return TPE_ERR_OOM;
     }
     *ctx->hflags = 0;
+    noalloc_setup(device);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 1)
@@ -800,6 +845,13 @@ int tpe_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int
     if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
     if (ctx && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
     return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev);
+}
+
+int tpe_gradient_noalloc(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF, double q,
+                         double p, double scale, double* E_dev, double* G_dev) {
+    if (ctx && !G_dev) return fail(ctx, TPE_ERR_INVALID_ARG, "null G_dev");
+    if (ctx && (const void*)G_dev == (const void*)X) return fail(ctx, TPE_ERR_INVALID_ARG, "G_dev aliases X");
+    return run_exact(ctx, X, V, F, nF, q, p, scale, E_dev, G_dev, false, true);
 }
 
 int tpe_sort_pairs(tpe_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int bits) {
