@@ -239,7 +239,8 @@ int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64
  * vertex of a leaf's faces, and max over the children of |C_child - C_B| + r_child above; r_T the
  * largest distance from C_T (the mean of the block's centroids) to a vertex of the block.  The test
  * is taken in FP32 on the mesh scaled by the power of two 2^k that brings the largest extent of the
- * FP32 centroid box into [0.5, 1): centres rounded to FP32, radii r + 1e-6 (1 + |C|_1) rounded up,
+ * FP32 centroid box into [0.5, 1): centres relative to that box's centre, rounded to FP32, radii
+ * r + 1e-6 (1 + |C|_1) rounded up,
  * |C_T - C_B| = sqrt(fma(dz, dz, fma(dy, dy, dx dx))).  theta in [0, 1] (theta <= 2 keeps faces that
  * share a vertex with the block out of far clusters; else TPE_ERR_INVALID_ARG); theta = 0
  * reproduces tpe_gradient to rounding.  G is the clustered form of eq. (dTP_reordered) (each

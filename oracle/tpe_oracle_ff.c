@@ -41,7 +41,8 @@
  *     block.  Not far: a leaf is summed exactly, face by face; other nodes are opened.
  *   - The test is an integer decision taken in the kernels' precision: in FP32, on the mesh scaled
  *     by the power of two 2^k that brings the largest extent of the FP32 centroid box into
- *     [0.5, 1), with centres rounded to FP32 and radii r + 1e-6 (1 + |C|_1) rounded up to FP32
+ *     [0.5, 1), with centres taken relative to the centre of that box (in the scaled frame) and
+ *     rounded to FP32, and radii r + 1e-6 (1 + |C|_1) (C relative) rounded up to FP32
  *     (the slack covers the FP32 rounding of the centres, so the radii stay bounds), and
  *     dist = sqrt(fma(dz, dz, fma(dy, dy, dx dx))).  The pair sums themselves are FP64.
  *
@@ -193,8 +194,9 @@ static int centroid_f32(const double* X, int64_t V, const int32_t* F, int64_t f,
     return 1;
 }
 
-/* s = 2^k with (largest extent of the FP32 centroid box) * s in [0.5, 1); 1 for an empty box. */
-static double frame_scale(const double* X, int64_t V, const int32_t* F, int64_t nF) {
+/* s = 2^k with (largest extent of the FP32 centroid box) * s in [0.5, 1) (1 for an empty box), and
+ * the box's centre in the scaled frame (the origin of the decisions' FP32 centres). */
+static double frame_scale(const double* X, int64_t V, const int32_t* F, int64_t nF, double* origin) {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t f = 0; f < nF; ++f) {
         float c[3];
@@ -209,10 +211,15 @@ static double frame_scale(const double* X, int64_t V, const int32_t* F, int64_t 
         const double e = (double)hi[d] - (double)lo[d];
         if (e > ext && isfinite(e)) ext = e;
     }
-    if (!(ext > 0.0) || !isfinite(ext)) return 1.0;
-    int ex;
-    (void)frexp(ext, &ex);
-    return ldexp(1.0, -ex);
+    double s = 1.0;
+    if (ext > 0.0 && isfinite(ext)) {
+        int ex;
+        (void)frexp(ext, &ex);
+        s = ldexp(1.0, -ex);
+    }
+    for (int d = 0; d < 3; ++d)
+        origin[d] = lo[d] <= hi[d] ? s * (0.5 * ((double)lo[d] + (double)hi[d])) : 0.0;
+    return s;
 }
 
 static float round_up_f32(double v) {
@@ -220,9 +227,10 @@ static float round_up_f32(double v) {
     return (double)f >= v ? f : nextafterf(f, INFINITY);
 }
 
-/* FP32 ball (centre, bounding radius) of a centre C and radius r given in the original frame. */
-static void ball_f32(const double* C, double r, double s, float* out) {
-    const double sc[3] = {s * C[0], s * C[1], s * C[2]};
+/* FP32 ball (centre relative to the origin o, bounding radius) in the scaled frame, of a centre C and
+ * radius r given in the original frame. */
+static void ball_f32(const double* C, double r, double s, const double* o, float* out) {
+    const double sc[3] = {s * C[0] - o[0], s * C[1] - o[1], s * C[2] - o[2]};
     const double slack = 1e-6 * (1.0 + fabs(sc[0]) + fabs(sc[1]) + fabs(sc[2]));
     for (int d = 0; d < 3; ++d) out[d] = (float)sc[d];
     out[3] = round_up_f32(s * r + slack);
@@ -309,7 +317,7 @@ typedef struct {
 typedef struct {
     int64_t nF, V;
     int leaf, H;
-    double s;
+    double s, o[3]; /* scale and origin of the FP32 decision frame */
     const double* X;
     const int32_t* F;
     const uint32_t* perm; /* tree position -> face */
@@ -322,9 +330,9 @@ static void outer_add(double* m, double w, const double* v) {
     m[3] += w * v[1] * v[1]; m[4] += w * v[1] * v[2]; m[5] += w * v[2] * v[2];
 }
 
-static void node_decision(fnode* n, double s) {
+static void node_decision(fnode* n, double s, const double* o) {
     if (n->A > 0.0) {
-        ball_f32(n->C, n->r, s, n->rec);
+        ball_f32(n->C, n->r, s, o, n->rec);
         n->af = (float)(s * s * n->A);
     } else {
         n->rec[0] = n->rec[1] = n->rec[2] = n->rec[3] = 0.f;
@@ -350,7 +358,7 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
     if (!perm || leaf < 1) return FF_EINVAL;
     t->nF = nF; t->V = V; t->leaf = leaf; t->X = X; t->F = F; t->perm = perm;
     t->H = height_of(nF, leaf);
-    t->s = frame_scale(X, V, F, nF);
+    t->s = frame_scale(X, V, F, nF, t->o);
     t->g = malloc(sizeof(fface) * (size_t)nF);
     t->nodes = calloc((size_t)2 << t->H, sizeof(fnode));
     if (!t->g || !t->nodes) return FF_EINVAL;
@@ -387,7 +395,7 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
                 }
             }
         }
-        node_decision(n, t->s);
+        node_decision(n, t->s, t->o);
     }
     for (int64_t k = nslot - 1; k >= 1; --k) {
         fnode* n = &t->nodes[k];
@@ -407,7 +415,7 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
                 outer_add(n->m2c, ch[c]->A, dc); /* parallel-axis shift */
             }
         }
-        node_decision(n, t->s);
+        node_decision(n, t->s, t->o);
     }
     return FF_OK;
 }
@@ -431,7 +439,7 @@ static void block_ball(const ftree* t, int64_t b, float* out) {
             const double rr = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
             if (rr > r) r = rr;
         }
-    ball_f32(C, r, t->s, out);
+    ball_f32(C, r, t->s, t->o, out);
 }
 
 static int is_far(const float* tb, const fnode* n, float theta) {

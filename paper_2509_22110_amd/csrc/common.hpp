@@ -222,6 +222,17 @@ __device__ __forceinline__ int norm_exp(const uint32_t* bbox) {
 }
 __device__ __forceinline__ double norm_scale(const uint32_t* bbox) { return ldexp(1.0, norm_exp(bbox)); }
 
+// Centre of the centroid bounding box in the normalised frame (0 for an empty box): the origin of
+// the far field's FP32 cluster records and rows, so that their coordinates stay small wherever the
+// mesh sits (FP32 positions of a mesh translated by 1e4 would carry errors of 1e-3).
+__device__ __forceinline__ void norm_origin(const uint32_t* bbox, double* o) {
+    const double s = norm_scale(bbox);
+    for (int d = 0; d < 3; ++d) {
+        const double lo = (double)ordered_to_float(bbox[d]), hi = (double)ordered_to_float(bbox[3 + d]);
+        o[d] = lo <= hi && isfinite(lo) && isfinite(hi) ? s * (0.5 * (lo + hi)) : 0.0;
+    }
+}
+
 // s^m for s = 2^k and an integer-valued m, exactly.
 __device__ __forceinline__ double pow2i(int k, double m) { return ldexp(1.0, (int)llrint(k * m)); }
 

@@ -51,11 +51,13 @@ __device__ void write_mom(const NodeF64& n, NodeMom* mom) {
     *mom = m;
 }
 
-__device__ void write_rec(const NodeF64& n, NodeRec* rec) {
+// FP32 record of a node: centre relative to the origin o (norm_origin), radius rounded up.
+__device__ void write_rec(const NodeF64& n, const double* o, NodeRec* rec) {
     NodeRec r;
-    r.cx = (float)n.cx; r.cy = (float)n.cy; r.cz = (float)n.cz;
+    const double cx = n.cx - o[0], cy = n.cy - o[1], cz = n.cz - o[2];
+    r.cx = (float)cx; r.cy = (float)cy; r.cz = (float)cz;
     // the FP32 centroid moves by at most ~|C| 2^-24; fold that into the radius bound
-    const double slack = 1e-6 * (1.0 + fabs(n.cx) + fabs(n.cy) + fabs(n.cz));
+    const double slack = 1e-6 * (1.0 + fabs(cx) + fabs(cy) + fabs(cz));
     r.r = n.A > 0.0 ? round_up_f(n.r + slack) : 0.f;
     r.a = (float)n.A;
     const double nn = sqrt(n.nx * n.nx + n.ny * n.ny + n.nz * n.nz);
@@ -127,8 +129,10 @@ __global__ __launch_bounds__(64 * MOM_LEAF_WAVES) void leaf_moments(const double
         n.r = wave_max_d(r);
     }
     if (lane == 0) {
+        double o[3];
+        norm_origin(bbox, o);
         nodes[nslot + j] = n;
-        write_rec(n, &recs[nslot + j]);
+        write_rec(n, o, &recs[nslot + j]);
         write_mom(n, &moms[nslot + j]);
     }
 }
@@ -161,7 +165,8 @@ __device__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
 // The tree's internal levels take ceil(H / MOM_SUB) launches instead of H.
 constexpr int MOM_SUB = 8;
 
-__global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, NodeF64* __restrict__ nodes,
+__global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, const uint32_t* __restrict__ bbox,
+                                                                NodeF64* __restrict__ nodes,
                                                                 NodeRec* __restrict__ recs,
                                                                 NodeMom* __restrict__ moms) {
     __shared__ NodeF64 buf[1 << MOM_SUB];
@@ -178,7 +183,9 @@ __global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, N
             buf[t] = par;
             const int64_t k = ((int64_t)1 << (L - st)) + g * m + t;
             nodes[k] = par;
-            write_rec(par, &recs[k]);
+            double o[3];
+            norm_origin(bbox, o);
+            write_rec(par, o, &recs[k]);
             write_mom(par, &moms[k]);
         }
         __syncthreads();
@@ -211,8 +218,11 @@ __global__ __launch_bounds__(64) void target_balls(const double* __restrict__ c6
     }
     r = wave_max_d(r);
     if (threadIdx.x == 0) {
-        const double slack = 1e-6 * (1.0 + fabs(cx) + fabs(cy) + fabs(cz));
-        balls[b] = make_float4((float)cx, (float)cy, (float)cz, round_up_f(r + slack));
+        double o[3];
+        norm_origin(bbox, o);
+        const double rx = cx - o[0], ry = cy - o[1], rz = cz - o[2];  // relative to the records' origin
+        const double slack = 1e-6 * (1.0 + fabs(rx) + fabs(ry) + fabs(rz));
+        balls[b] = make_float4((float)rx, (float)ry, (float)rz, round_up_f(r + slack));
     }
 }
 
@@ -371,7 +381,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
                                                            const NodeRec* __restrict__ nodes,
                                                            const NodeMom* __restrict__ moms,
                                                            const MlpPacked* __restrict__ W, int H, int leaf,
-                                                           int64_t nF, const float4* __restrict__ balls,
+                                                           int64_t nF, const uint32_t* __restrict__ bbox,
+                                                           const float4* __restrict__ balls,
                                                            float theta, int64_t Fp, double* __restrict__ acc64,
                                                            unsigned long long* __restrict__ stats,
                                                            const uint32_t* __restrict__ order,
@@ -394,7 +405,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
     const ColRec me = cols[i];
     const int4 mv = colv[i];
-    const float ax = (float)cxd, ay = (float)cyd, az = (float)czd;
+    double o[3];
+    norm_origin(bbox, o);
+    // the row's centroid relative to the cluster records' origin (far clusters and the learned
+    // correction's features); near leaves re-express it relative to each chunk's origin
+    const float ax = (float)(cxd - o[0]), ay = (float)(cyd - o[1]), az = (float)(czd - o[2]);
     const float4 tb = balls[b];
     float hi[NACC], lo[NACC], acc[NACC];
 #pragma unroll
@@ -545,6 +560,7 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
                                                        const double* __restrict__ c64,
                                                        const NodeRec* __restrict__ nodes,
                                                        const NodeMom* __restrict__ moms, int H, int leaf, int64_t nF,
+                                                       const uint32_t* __restrict__ bbox,
                                                        const float4* __restrict__ balls, float theta, uint32_t seed,
                                                        uint32_t sel, int quota, int64_t max_faces,
                                                        float* __restrict__ feats, float* __restrict__ targets,
@@ -555,7 +571,9 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
     const int64_t b = blockIdx.x;
     const int64_t i = b * 64 + lane;
     const bool rowok = i < nF;
-    const float ax = (float)c64[3 * i], ay = (float)c64[3 * i + 1], az = (float)c64[3 * i + 2];
+    double o[3];
+    norm_origin(bbox, o);
+    const float ax = (float)(c64[3 * i] - o[0]), ay = (float)(c64[3 * i + 1] - o[1]), az = (float)(c64[3 * i + 2] - o[2]);
     const ColRec me = cols[i];
     const float4 tb = balls[b];
     const int4 nov = make_int4(0, 0, 0, 0);
@@ -613,7 +631,9 @@ __global__ __launch_bounds__(64) void farfield_samples(const ColRec* __restrict_
             for (int64_t f = f0; f < f1; ++f) {
                 ColRec cr = cols[f];
                 // columns are stored relative to their tile origin; use absolute (normalised) ones here
-                cr.cx = (float)(c64[3 * f]); cr.cy = (float)(c64[3 * f + 1]); cr.cz = (float)(c64[3 * f + 2]);
+                cr.cx = (float)(c64[3 * f] - o[0]);
+                cr.cy = (float)(c64[3 * f + 1] - o[1]);
+                cr.cz = (float)(c64[3 * f + 2] - o[2]);
                 ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, ex);
             }
             const ColRec mc = {cn.cx, cn.cy, cn.cz, cn.a, cn.nx, cn.ny, cn.nz, 0.f};
@@ -884,7 +904,7 @@ hipError_t launch_tree_moments(const double* c64, const double* geo, const int4*
                        dim3(64 * MOM_LEAF_WAVES), 0, st, c64, geo, colv, X, bbox, nF, leaf, H, n, r, m);
     for (int L = H; L > 0;) {
         const int nl = std::min(L, MOM_SUB);
-        hipLaunchKernelGGL(subtree_moments, dim3((unsigned)(((int64_t)1 << L) >> nl)), dim3(1 << nl), 0, st, L, nl,
+        hipLaunchKernelGGL(subtree_moments, dim3((unsigned)(((int64_t)1 << L) >> nl)), dim3(1 << nl), 0, st, L, nl, bbox,
                            n, r, m);
         L -= nl;
     }
@@ -899,7 +919,7 @@ hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const d
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
-    hipLaunchKernelGGL(farfield_samples, dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, r, m, H, leaf, nF, balls,
+    hipLaunchKernelGGL(farfield_samples, dim3((unsigned)nb), dim3(64), 0, st, cols, colv, c64, r, m, H, leaf, nF, bbox, balls,
                        theta, seed, sel, quota, max_faces, feats, targets, (const MlpPacked*)mlp_packed, pred);
     return hipGetLastError();
 }
@@ -945,11 +965,11 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
     if (mlp_packed)
         hipLaunchKernelGGL((farfield_kernel<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st,
-                           cols, colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, balls, theta, Fp,
+                           cols, colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, theta, Fp,
                            acc64, stats, order, work);
     else
         hipLaunchKernelGGL((farfield_kernel<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv,
-                           c64, org, r, m, (const MlpPacked*)nullptr, H, leaf, nF, balls, theta, Fp, acc64, stats,
+                           c64, org, r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, theta, Fp, acc64, stats,
                            order, work);
     return hipGetLastError();
 }
