@@ -292,9 +292,11 @@ __global__ __launch_bounds__(256) void mlp_adam(float* __restrict__ P, float* __
     float g = 0.f;
     for (int t = 0; t < ntiles; ++t) g += gpart[(size_t)t * MLP_NPARAM + p];
     g *= norm;
+    // 1 - beta in FP64 before the rounding to FP32 (1.f - 0.999f is 0.00099998713: 1.3e-5 off)
     const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
-    const float m = beta1 * M[p] + (1.f - beta1) * g;
-    const float v = beta2 * Vv[p] + (1.f - beta2) * g * g;
+    const float omb1 = (float)(1.0 - 0.9), omb2 = (float)(1.0 - 0.999);
+    const float m = beta1 * M[p] + omb1 * g;
+    const float v = beta2 * Vv[p] + omb2 * g * g;
     M[p] = m;
     Vv[p] = v;
     const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);

@@ -59,3 +59,52 @@ def test_reference_loss_ignores_unused_rows_and_columns():
     assert mlp_ref.loss(p, X, T2) == L
     X3 = np.concatenate([X, rng.normal(size=(5, 32))]); T3 = np.concatenate([T, np.zeros((5, 16))])
     assert abs(mlp_ref.loss(p, X3, T3) - L) <= 1e-13 * L
+
+
+def test_bf16_rounding():
+    """Round to nearest, ties to even, on the 7 stored mantissa bits of BF16."""
+    one = 1.0
+    assert mlp_ref.bf16(one) == 1.0
+    assert mlp_ref.bf16(1 + 2.0 ** -8) == 1.0                   # tie -> even mantissa (0)
+    assert mlp_ref.bf16(1 + 3 * 2.0 ** -8) == 1 + 2.0 ** -6     # tie -> even mantissa (2)
+    assert mlp_ref.bf16(1 + 2.0 ** -8 + 2.0 ** -20) == 1 + 2.0 ** -7
+    assert mlp_ref.bf16(-3.0) == -3.0 and mlp_ref.bf16(0.0) == 0.0
+    x = np.random.default_rng(0).normal(size=10000) * 10.0 ** np.random.default_rng(1).integers(-20, 20, 10000)
+    r = mlp_ref.bf16(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-12))
+    assert np.array_equal(mlp_ref.bf16(r), r)
+    assert np.all(np.sign(r) == np.sign(x))
+
+
+def test_low_precision_mode_reduces_to_the_exact_network():
+    """With the rounding steps replaced by the identity the kernel-rounding mode is the FP64 network
+    (so the two modes differ only where the kernels round), and with them it stays close to it."""
+    rng = np.random.default_rng(4)
+    n = sum(int(np.prod(s)) for s in mlp_ref.SHAPES)
+    p = rng.normal(0, 0.2, n)
+    X = rng.normal(size=(64, 32))
+    T = np.concatenate([rng.normal(size=(64, 15)), rng.uniform(0.5, 1.5, (64, 1))], 1)
+    ident = lambda a: np.asarray(a, dtype=np.float64)
+    Y0, _ = mlp_ref.forward(p, X)
+    Y1, _ = mlp_ref.forward(p, X, low=True, rnd=ident, store=ident)
+    assert np.abs(Y1 - Y0).max() <= 1e-13 * np.abs(Y0).max()
+    g0 = mlp_ref.gradient(p, X, T, lam=0.3, tile=16)
+    g1 = mlp_ref.gradient(p, X, T, lam=0.3, tile=16, low=True, rnd=ident, store=ident)
+    assert np.abs(g1 - g0).max() <= 1e-12 * np.abs(g0).max()
+    Yb, _ = mlp_ref.forward(p, X, low=True)
+    gb = mlp_ref.gradient(p, X, T, lam=0.3, tile=16, low=True)
+    assert 0 < np.abs(Yb - Y0).max() <= 5e-2 * np.abs(Y0).max()
+    assert float(gb @ g0 / (np.linalg.norm(gb) * np.linalg.norm(g0))) > 0.999
+
+
+def test_adam_first_step_is_a_signed_step():
+    """With zero moments, the bias-corrected first Adam step is lr g / (|g| + eps)."""
+    rng = np.random.default_rng(5)
+    p = rng.normal(size=100)
+    g = rng.normal(size=100)
+    p1, m1, v1 = mlp_ref.adam(p, np.zeros(100), np.zeros(100), g, 1, 1e-3)
+    assert np.allclose(p1, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+    # a second step with the same gradient: m = 0.19 g, v = 0.001999 g^2, corrections 0.19 and 0.001999
+    p2, _, _ = mlp_ref.adam(p1, m1, v1, g, 2, 1e-3)
+    assert np.allclose(p2, p1 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
