@@ -1,25 +1,23 @@
-"""Benchmark of the exact tangent-point energy + gradient hot path on one MI355X.
+"""Benchmark of the tangent-point energy + gradient hot path on one MI355X.
 
-One step = one tpe_gradient call (face prep, Morton sort, exclusion map, exact all-pairs pair
-kernel, FP64 finalize, vertex gather) on the level-5 deformed sphere (20,480 faces, l = 2..8
-spherical-harmonic deformation, a_lm ~ N(0, 0.05^2), seed 0), with the mesh already resident in
-HBM.  Prints ONE JSON line:
-    value     = ordered non-adjacent face pairs evaluated per second (energy + gradient)
-    roofline  = the pair kernel's algorithmic FP32 rate (55 flop per ordered pair, the row
-                formulation) over its own launch durations, measured with HIP events on the
-                stream it runs on, vs the FP32 vector peak; the symmetric kernel that runs by
-                default evaluates each unordered pair once and executes 40.5 flop per ordered pair
-                (executed_tflops); traffic = HBM bytes per launch from the committed rocprofv3
-                counter summary (profiles/pair_kernel_C2_traffic.txt), null when the kernel's
-                sources have changed since it was taken; row_only = the same step with the row-only
-                pair kernel (TPE_OPT_SYMMETRIC = 0), for comparison
-    confinement = the confinement energy + gradient of a flattened sphere in a radius-1.1 sphere
-                (20,480 x 20,480 faces): pairs/s and the kernel's algorithmic FP32 rate
-    farfield  = ms per gradient on the level-7 workload (327,680 faces): exact all-pairs vs the
-                cluster-tree far field (monopole, and with the learned correction), with their
-                relative errors against the exact path
-    cpu_baseline = the FP64 CPU oracle, timed on this host on the same mesh
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-farfield]
+One step = one exact energy + gradient call (tpe_gradient: face prep, sort, exclusion map, exact
+all-pairs symmetric pair kernel, FP64 merge / finalize, vertex gather) on the level-7 workload the
+metric is quoted on: the icosphere of 327,680 faces deformed by spherical harmonics of degree 2..16
+at amplitude 0.15 (seed 0), with the mesh already resident in HBM.  Prints ONE JSON line:
+    value     = ordered non-adjacent face pairs per second of the exact energy + gradient
+    roofline  = the pair kernel: 64 flop per ordered pair (the algorithmic count of the energy +
+                gradient, FMA = 2) over its own launch durations, measured with HIP events on its
+                stream inside the timed region, against the FP32 vector peak; executed flop per
+                pair from the committed rocprofv3 counter summary (profiles/pair_kernel_C4_flops.txt)
+                and HBM bytes per launch (profiles/pair_kernel_C4_traffic.txt), both null when the
+                kernel's sources have changed since they were taken
+    farfield  = ms per gradient on the same workload: exact all-pairs vs the cluster-tree far field
+                (monopole, learned correction, dual tree) with their errors against the exact path,
+                and the HBM-bound passes (merge, finalize, vertex gather) against their algorithmic
+                bytes (374 per face) with the symmetric kernel's column partials as an overhead
+    c2        = the same exact step on the level-5 workload (20,480 faces)
+    cpu_baseline = the FP64 CPU oracle on a bounded row sample of the same workload
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-farfield] [--no-extra]
 """
 from __future__ import annotations
 
@@ -33,31 +31,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic FP32 work of one ordered pair in the energy + gradient form (FMA = 2, rcp = 1):
-# d 3, |d|^2 5, 1/|d|^2 1, n_S.d 5, n_T.d 5, t and tau 2, powers 8, a w / s / s' 3,
-# t^6+tau^6 and m 2, K 2, S0 1, Sd 6, Sdd 6, Sn 6
-FLOP_PER_PAIR = 55
-# FP32 work the symmetric kernel executes per unordered pair (FMA = 2, rcp = 1), credited to both
-# faces: shared d 3, |d|^2 5, rcp 1, n_S.d 5, n_T.d 5, t and tau 2, powers 6, T1 and U1 2,
-# t^6+tau^6 3, w e 1 (33); the row face's 11 sums 24; the column face's 11 sums 24 (contributions of
-# two rows per lane combined, then added to the rotating column sums); 81 = 40.5 per ordered pair
-EXEC_FLOP_PER_PAIR_SYM = 40.5
+# algorithmic FP32 work of one ordered pair of the energy + gradient (FMA = 2), the count of the
+# scatter-free form: shared terms 9 (d 3, |d|^2 5, 1/|d|^2 counted as 1), forward (x = S) 28,
+# reverse (y = S) 27
+FLOP_PER_PAIR = 64
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per face of the passes after the symmetric pair kernel: the merge reads one
-# row segment (8 FP32 sums = 32 B) plus the column partials (counted apart) and writes the 11 FP64
-# row sums (88 B); the finalize reads them (88 B), {a, |w|, n} (40 B), vertex ids (16 B) and its
-# three vertices (72 B) and writes three corner gradients (72 B); the gather reads 3 corner indices
-# (12 B) and the corners (72 B) and per vertex (V ~ F/2) an offset (4 B) and writes G (24 B)
-MERGE_FINALIZE_GATHER_BYTES_PER_FACE = 32 + 88 + 88 + 40 + 16 + 72 + 72 + 12 + 72 + (4 + 24) // 2
+# algorithmic HBM bytes per face of the passes after the pair kernel: finalize ~276 (row sums,
+# geometry, vertex ids, corner positions in; three FP64 corner gradients out) + gather ~98 (corner
+# gradients and indices in, vertex gradient out)
+FINALIZE_GATHER_BYTES_PER_FACE = 276 + 98
 SYM_MAX_COLPART_BYTES = 64 << 30
 
 
 def sym_colpart_bytes(nF, na=8):
-    """Bytes of the symmetric pair kernel's column partial sums, which the finalize reads once: one
+    """Bytes of the symmetric pair kernel's column partial sums, which the merge reads once: one
     FP32 sum per (symmetric unit, column, accumulator); super blocks of 512 faces, units of 64
     columns, the 8 chunks of a super block's own faces excluded.  0 when the library takes the
-    row-only kernel (above its 6 GiB cap)."""
+    row-only kernel (above its 64 GiB cap)."""
     fp = -(-nF // 512) * 512
     nsb, nch = fp // 512, fp // 64
     units = nsb * (nch - 8) - 8 * nsb * (nsb - 1) // 2
@@ -68,38 +59,44 @@ def sym_colpart_bytes(nF, na=8):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C4")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--no-farfield", action="store_true", help="skip the level-7 far-field comparison")
-    ap.add_argument("--farfield-only", action="store_true", help="run only the level-7 far-field comparison")
-    ap.add_argument("--ff-config", default="C4")
+    ap.add_argument("--no-farfield", action="store_true", help="skip the far-field comparison")
+    ap.add_argument("--no-c2", action="store_true", help="skip the level-5 exact step")
+    ap.add_argument("--no-row-only", action="store_true", help="skip the row-only kernel comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the confinement, quadrature, exponent and curved-element timings")
     ap.add_argument("--ff-reps", type=int, default=5)
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--no-conf", action="store_true", help="skip the confinement, 6-point-quadrature and other-exponent timings")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
 
 
-PAIR_SOURCES = ("paper_2509_22110_amd/csrc/pair.hip", "paper_2509_22110_amd/csrc/common.hpp")
+SOURCES = {
+    "pair": ("paper_2509_22110_amd/csrc/pair.hip", "paper_2509_22110_amd/csrc/common.hpp"),
+    "farfield": ("paper_2509_22110_amd/csrc/tree.hip", "paper_2509_22110_amd/csrc/farfield_common.hpp",
+                 "paper_2509_22110_amd/csrc/common.hpp", "paper_2509_22110_amd/csrc/mlp_infer.hpp"),
+    "finalize": ("paper_2509_22110_amd/csrc/finalize.hip", "paper_2509_22110_amd/csrc/common.hpp"),
+}
 
 
-def pair_source_hash():
+def source_hash(kind):
     h = hashlib.sha256()
-    for rel in PAIR_SOURCES:
+    for rel in SOURCES[kind]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def read_traffic():
-    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter summary; None if there
-    is none or if it was taken on other sources of the kernel than the ones built here."""
-    path = os.path.join(ROOT, "profiles", "pair_kernel_C2_traffic.txt")
+def read_summary(name, kind):
+    """key = value pairs of a committed rocprofv3 summary under profiles/; None if there is none or if
+    it was taken on other sources of the kernel than the ones built here (source_sha256)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -108,19 +105,78 @@ def read_traffic():
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != pair_source_hash():
+    if kv.get("source_sha256") != source_hash(kind):
         return None
+    return kv
+
+
+def summary_float(kv, key):
     try:
-        return float(kv["bytes_per_launch"])
+        return float(kv[key]) if kv else None
     except (KeyError, ValueError):
         return None
 
 
-def farfield_leg(args, T, M, torch, dev):
-    """ms per gradient on the level-7 workload: exact vs cluster-tree far field (+ learned)."""
-    cfg = M.make_config(args.ff_config)
+def exact_leg(T, M, torch, dev, name, steps, warmup):
+    """`steps` timed exact energy + gradient calls after `warmup`, with the pair kernel's launches
+    timed by HIP events on the context's stream inside the timed region."""
+    cfg = M.make_config(name)
     X = torch.from_numpy(cfg.X).to(dev)
     F = torch.from_numpy(cfg.F).to(dev)
+    P = T.pair_count(F, cfg.V)
+    G = torch.empty_like(X)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    ctx = T.context(dev)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+    for _ in range(warmup):
+        T.gradient(X, F, out=G, energy_out=E)
+    ctx.sync_check()
+    ctx.kernel_time()  # clears the record (the event pool now exists)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        T.gradient(X, F, out=G, energy_out=E)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_n = ctx.kernel_time()
+    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+    ctx.sync_check()
+    k_avg = k_ms / max(k_n, 1)
+    tflops = FLOP_PER_PAIR * P / (k_avg * 1e-3) / 1e12
+    return {"cfg": cfg, "X": X, "F": F, "P": P, "G": G, "E": E, "ms_per_step": dt / steps * 1e3,
+            "value": P * steps / dt, "kernel_avg_ms": k_avg, "kernel_launches": k_n, "tflops": tflops}
+
+
+def row_only_leg(T, torch, dev, X, F, P, reps):
+    """The same step with the row-only pair kernel (TPE_OPT_SYMMETRIC = 0), for comparison."""
+    ctx = T.context(dev)
+    G = torch.empty_like(X)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+    ctx.set_option(T.OPT_SYMMETRIC, 0)
+    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+    try:
+        T.gradient(X, F, out=G, energy_out=E)
+        ctx.kernel_time()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            T.gradient(X, F, out=G, energy_out=E)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        r_ms, r_n = ctx.kernel_time()
+    finally:
+        ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+        ctx.set_option(T.OPT_SYMMETRIC, 1)
+    ctx.sync_check()
+    k = r_ms / max(r_n, 1)
+    return {"kernel": "pair_kernel<6,true>", "kernel_avg_ms": round(k, 4), "ms_per_step": round(ms, 4),
+            "tflops": round(FLOP_PER_PAIR * P / (k * 1e-3) / 1e12, 3)}
+
+
+def farfield_leg(args, T, torch, dev, ex):
+    """ms per gradient on the headline workload: exact vs cluster-tree far field (+ learned, dual
+    tree), and the HBM-bound passes of the exact path."""
+    cfg, X, F, G0, E0 = ex["cfg"], ex["X"], ex["F"], ex["G"], ex["E"]
 
     def timed(fn, reps):
         fn()
@@ -131,35 +187,28 @@ def farfield_leg(args, T, M, torch, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps * 1e3, out
 
-    G0 = torch.empty_like(X)
-    E0 = torch.empty((), dtype=torch.float64, device=dev)
-    t_exact, _ = timed(lambda: T.gradient(X, F, out=G0, energy_out=E0), max(1, args.ff_reps // 2))
+    t_exact = ex["ms_per_step"]
     ctx = T.context(dev)
-    # the exact pair kernel at this size, timed with HIP events (the same roofline as the main line)
-    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
-    ctx.kernel_time()
-    T.gradient(X, F, out=G0, energy_out=E0)
-    k_ms, k_n = ctx.kernel_time()
-    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
-    k_ms /= max(k_n, 1)
-    pairs = T.pair_count(F, cfg.V)
-    k_tflops = FLOP_PER_PAIR * pairs / (k_ms * 1e-3) / 1e12
-    exact_kernel = {"kernel": "pair_sym_kernel<true>", "kernel_avg_ms": round(k_ms, 3), "pairs": pairs,
-                    "achieved": round(k_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(k_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
-    # the HBM-bound passes of the exact path (finalize + vertex gather), timed with HIP events
+    # merge + finalize + vertex gather of the exact path, timed with HIP events
+    Gs = torch.empty_like(X)
+    Es = torch.empty((), dtype=torch.float64, device=dev)
     ctx.set_option(T.OPT_KERNEL_TIMING, 2)
     ctx.kernel_time()
-    for _ in range(2):
-        T.gradient(X, F, out=G0, energy_out=E0)
+    for _ in range(3):
+        T.gradient(X, F, out=Gs, energy_out=Es)
     fg_ms, fg_n = ctx.kernel_time()
     ctx.set_option(T.OPT_KERNEL_TIMING, 0)
     fg_ms /= max(fg_n, 1)
-    cp_bytes = sym_colpart_bytes(cfg.nF)
-    fg_bytes = MERGE_FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF + cp_bytes
-    fg = {"kernels": "sym_merge_kernel + finalize_kernel<true> + vertex_gather", "bound": "hbm", "ms": round(fg_ms, 4),
-          "algorithmic_bytes": fg_bytes, "column_partial_bytes": cp_bytes, "achieved": round(fg_bytes / (fg_ms * 1e-3) / 1e9, 1),
-          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fg_bytes / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    alg = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF
+    cp = sym_colpart_bytes(cfg.nF)
+    tr = read_summary(f"gather_passes_{args.config}_traffic.txt", "finalize")
+    fg = {"kernels": "sym_merge_kernel + finalize_kernel<true> + vertex_gather", "bound": "hbm",
+          "ms": round(fg_ms, 4), "algorithmic_bytes": alg, "bytes_per_face": FINALIZE_GATHER_BYTES_PER_FACE,
+          "achieved": round(alg / (fg_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(alg / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+          "overhead": {"what": "the symmetric pair kernel's column partial sums, read once by the merge",
+                       "bytes": cp, "with_overhead_gbs": round((alg + cp) / (fg_ms * 1e-3) / 1e9, 1)},
+          "traffic": summary_float(tr, "bytes_per_call")}
     t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
     g0 = float(G0.abs().max())
     e0 = float(E0)
@@ -167,17 +216,26 @@ def farfield_leg(args, T, M, torch, dev):
     E = torch.empty((), dtype=torch.float64, device=dev)
 
     def variant(mlp):
+        ctx.set_option(T.OPT_KERNEL_TIMING, 1)
+        T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E)
+        ctx.kernel_time()
         t, _ = timed(lambda: T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E), args.ff_reps)
+        k_ms, k_n = ctx.kernel_time()
+        ctx.set_option(T.OPT_KERNEL_TIMING, 0)
+        st = ctx.farfield_stats()
         return {"ms": round(t, 3), "speedup_vs_exact": round(t_exact / t, 2),
                 "rel_grad_maxnorm": float((G - G0).abs().max()) / g0,
-                "rel_energy": abs(float(E) - e0) / abs(e0)}
+                "rel_energy": abs(float(E) - e0) / abs(e0),
+                "walk_kernel_avg_ms": round(k_ms / max(k_n, 1), 4),
+                "far_clusters": st[0], "near_pairs": st[1] * 64 if st[3] else 0}
 
-    out = {"workload": f"{args.ff_config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0",
+    out = {"workload": f"{args.config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0",
            "faces": cfg.nF, "theta": args.theta, "leaf": 32,
-           "exact_ms": round(t_exact, 3), "exact_kernel": exact_kernel, "tree_build_ms": round(t_tree, 3),
+           "exact_ms": round(t_exact, 3), "tree_build_ms": round(t_tree, 3),
            "finalize_gather": fg,
-           "note": "errors against the exact FP32/FP64 path (itself parity-tested against the FP64 "
-                   "oracle); far-field ms per gradient exclude the tree build (an ordering that is "
+           "note": "errors against the exact GPU path, itself within 1e-5 of the FP64 oracle (the far "
+                   "field is also checked against the FP64 oracle at its 16 worst vertices in the "
+                   "tests); far-field ms per gradient exclude the tree build (an ordering that is "
                    "reused while the moments are recomputed from X on every call)",
            "monopole": variant(None), "learned": None}
     if args.mlp and os.path.exists(args.mlp):
@@ -185,15 +243,43 @@ def farfield_leg(args, T, M, torch, dev):
         out["learned"] = variant(mlp)
         out["learned"]["checkpoint"] = os.path.relpath(args.mlp, ROOT)
         out["learned"]["gate"] = round(mlp.gate(), 4)
-    # dual tree (both integrals clustered) on the same tree
     t, _ = timed(lambda: T.farfield_dual(tree, X, F, theta=args.theta, out=G, energy_out=E), args.ff_reps)
-    st = T.context(dev).farfield_stats()
+    st = ctx.farfield_stats()
     out["dual_tree"] = {"ms": round(t, 3), "speedup_vs_exact": round(t_exact / t, 2),
                         "rel_grad_maxnorm": float((G - G0).abs().max()) / g0,
                         "rel_energy": abs(float(E) - e0) / abs(e0),
                         "far_cluster_pairs": st[0], "exact_face_pairs": st[1]}
-    T.context(dev).sync_check()
+    ctx.sync_check()
     return out
+
+
+def cpu_leg(args, cfg, P):
+    """The FP64 oracle (energy + gradient, all host threads) on a bounded sample of the workload:
+    consecutive blocks of rows (each row face against every column), until cpu_seconds have passed."""
+    import numpy as np
+
+    import oracle
+    nth = oracle.num_threads()
+    F = cfg.F
+    nF = F.shape[0]
+    # ordered pairs of a row: nF minus the faces sharing a vertex with it (itself included)
+    v2f = [[] for _ in range(cfg.V)]
+    for f, tri in enumerate(F):
+        for v in tri:
+            v2f[int(v)].append(f)
+    rows, pairs, t = 0, 0, 0.0
+    block = 1024
+    while t < args.cpu_seconds and rows < nF:
+        r1 = min(nF, rows + block)
+        c0 = time.perf_counter()
+        oracle.gradient_rows(cfg.X, F, rows, r1, nthreads=nth)
+        t += time.perf_counter() - c0
+        for f in range(rows, r1):
+            pairs += nF - len(set(v2f[int(F[f, 0])]) | set(v2f[int(F[f, 1])]) | set(v2f[int(F[f, 2])]))
+        rows = r1
+    return {"value": pairs / t, "unit": "pairs/s", "cores": nth, "kind": "oracle",
+            "sample": f"FP64 oracle energy+gradient on rows [0, {rows}) of {args.config} ({cfg.name}, "
+                      f"{nF} faces): {pairs} ordered pairs of the workload's {P}, {t:.1f} s on {nth} threads"}
 
 
 # algorithmic FP32 work of one (moving face, confining face) pair of the confinement gradient:
@@ -254,7 +340,7 @@ def quad_leg(args, T, M, torch, dev, cfg, X, F):
         ctx.set_option(T.OPT_QUADRATURE, 1)
     ctx.sync_check()
     pp = 36 * T.pair_count(F, cfg.V)
-    return {"workload": f"{args.config} with 6 quadrature points per face", "point_pairs": pp,
+    return {"workload": f"{cfg.name} ({cfg.nF} faces) with 6 quadrature points per face", "point_pairs": pp,
             "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
 
 
@@ -284,7 +370,7 @@ def p3_leg(args, T, M, torch, dev, cfg, F):
         ctx.set_option(T.OPT_QUADRATURE, 1)
     ctx.sync_check()
     pp = 36 * T.pair_count(F, cfg.V)  # the elements' corners are the flat workload's faces
-    return {"workload": f"{args.config}'s sphere as {F10.shape[0]} curved cubic elements ({X10.shape[0]} nodes), "
+    return {"workload": f"{cfg.name}'s sphere as {F10.shape[0]} curved cubic elements ({X10.shape[0]} nodes), "
                         "6 quadrature points per element", "point_pairs": pp,
             "ms_per_call": round(dt * 1e3, 3), "point_pairs_per_s": pp / dt}
 
@@ -361,7 +447,7 @@ def exponents_leg(args, T, torch, dev, cfg, X, F, P):
         out[f"q{q}_p{p}"] = {"ms_per_call": round(dt * 1e3, 4), "pairs_per_s": P / dt,
                              "kernel": f"pair_kernel<{q},true,false,true>",
                              "kernel_avg_ms": round(k_ms / max(k_n, 1), 4)}
-    return {"workload": f"{args.config} ({cfg.nF} faces), exact energy+gradient", "pairs": P, **out}
+    return {"workload": f"{cfg.name} ({cfg.nF} faces), exact energy+gradient", "pairs": P, **out}
 
 
 def main():
@@ -370,7 +456,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               f"multi-GPU path.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2509_22110_amd as T
@@ -378,18 +463,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    cfg = M.make_config(args.config)
-    X = torch.from_numpy(cfg.X).to(dev)
-    F = torch.from_numpy(cfg.F).to(dev)
-    P = T.pair_count(F, cfg.V)
-    G = torch.empty_like(X)
-    E = torch.empty((), dtype=torch.float64, device=dev)
     ctx = T.context(dev)
     ctx.set_option(T.OPT_SYNC_CHECKS, 0)
-    if args.farfield_only:
-        print(json.dumps({"farfield": farfield_leg(args, T, M, torch, dev)}), flush=True)
-        return
-
     if args.calib_copy_mb:
         src = torch.empty(args.calib_copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -397,97 +472,52 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        T.gradient(X, F, out=G, energy_out=E)
-    ctx.sync_check()
+    ex = exact_leg(T, M, torch, dev, args.config, args.steps, args.warmup)
+    cfg, P = ex["cfg"], ex["P"]
+    fl = read_summary(f"pair_kernel_{args.config}_flops.txt", "pair")
+    tr = read_summary(f"pair_kernel_{args.config}_traffic.txt", "pair")
+    exec_flop = summary_float(fl, "flop_per_launch")
+    roofline = {"bound": "alu", "achieved": round(ex["tflops"], 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ex["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": summary_float(tr, "bytes_per_launch"), "kernel": "pair_sym_kernel<true>",
+                "kernel_avg_ms": round(ex["kernel_avg_ms"], 4), "kernel_launches": ex["kernel_launches"],
+                "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": P,
+                "executed_flop_per_pair": round(exec_flop / P, 2) if exec_flop else None,
+                "executed_tflops": round(exec_flop / (ex["kernel_avg_ms"] * 1e-3) / 1e12, 3) if exec_flop else None}
+    if not args.no_row_only:
+        roofline["row_only"] = row_only_leg(T, torch, dev, ex["X"], ex["F"], P, 3)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        T.gradient(X, F, out=G, energy_out=E)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.sync_check()
-    ms_per_step = dt / args.steps * 1e3
-    value = P * args.steps / dt
-
-    # dominant kernel: the pair kernel, timed with HIP events on its own stream
-    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
-    ctx.kernel_time()
-    for _ in range(args.steps):
-        T.gradient(X, F, out=G, energy_out=E)
-    k_ms, k_n = ctx.kernel_time()
-    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
-    ctx.sync_check()
-    k_avg_ms = k_ms / max(k_n, 1)
-    achieved = FLOP_PER_PAIR * P / (k_avg_ms * 1e-3) / 1e12
-    traffic = read_traffic()
-    # the row-only kernel on the same step, for comparison
-    ctx.set_option(T.OPT_SYMMETRIC, 0)
-    ctx.set_option(T.OPT_KERNEL_TIMING, 1)
-    for _ in range(2):
-        T.gradient(X, F, out=G, energy_out=E)
-    ctx.kernel_time()
-    reps = max(5, min(args.steps, 20))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        T.gradient(X, F, out=G, energy_out=E)
-    torch.cuda.synchronize()
-    ro_ms = (time.perf_counter() - t0) / reps * 1e3
-    r_ms, r_n = ctx.kernel_time()
-    ctx.set_option(T.OPT_KERNEL_TIMING, 0)
-    ctx.set_option(T.OPT_SYMMETRIC, 1)
-    ctx.sync_check()
-    r_avg_ms = r_ms / max(r_n, 1)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": "pair_sym_kernel<true>",
-                "kernel_avg_ms": round(k_avg_ms, 4), "flop_per_pair": FLOP_PER_PAIR,
-                "executed_flop_per_pair": EXEC_FLOP_PER_PAIR_SYM,
-                "executed_tflops": round(EXEC_FLOP_PER_PAIR_SYM * P / (k_avg_ms * 1e-3) / 1e12, 3),
-                "row_only": {"kernel": "pair_kernel<6,true>", "kernel_avg_ms": round(r_avg_ms, 4),
-                             "ms_per_step": round(ro_ms, 4),
-                             "tflops": round(FLOP_PER_PAIR * P / (r_avg_ms * 1e-3) / 1e12, 3)}}
-
-    ff = None if args.no_farfield else farfield_leg(args, T, M, torch, dev)
-    conf = None if args.no_conf else conf_leg(args, T, M, torch, dev)
-    quad = None if args.no_conf else quad_leg(args, T, M, torch, dev, cfg, X, F)
-    expo = None if args.no_conf else exponents_leg(args, T, torch, dev, cfg, X, F, P)
-    p3 = None if args.no_conf or args.config != "C2" else p3_leg(args, T, M, torch, dev, cfg, F)
-    p3ff = None if args.no_farfield else p3_farfield_leg(args, T, M, torch, dev)
-
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        nth = oracle.num_threads()
-        reps, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds or reps == 0:
-            c0 = time.perf_counter()
-            oracle.gradient(cfg.X, cfg.F, nthreads=nth)
-            t_cpu += time.perf_counter() - c0
-            reps += 1
-        cpu = {"value": P * reps / t_cpu, "unit": "pairs/s", "cores": nth, "kind": "oracle",
-               "sample": f"FP64 oracle energy+gradient, full {args.config} mesh ({cfg.nF} faces, "
-                         f"{P} pairs) x {reps}, {t_cpu:.1f} s on {nth} threads"}
-
+    ff = None if args.no_farfield else farfield_leg(args, T, torch, dev, ex)
+    cpu = None if args.no_cpu else cpu_leg(args, cfg, P)
     out = {
         "metric": "TP pair interactions/s (energy+grad); ms/gradient at 327k tris vs exact FP64",
-        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "value": ex["value"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ex["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.config}: {cfg.name} ({cfg.nF} faces, {cfg.V} vertices), seed 0, "
                                "exact all-pairs energy+gradient, (q,p)=(6,12)",
                    "faces": cfg.nF, "pairs": P, "q": 6, "p": 12, "parallelism": "single-gpu"},
         "roofline": roofline,
         "farfield": ff,
-        "confinement": conf,
-        "quadrature6": quad,
-        "other_exponents": expo,
-        "p3_elements": p3,
-        "p3_farfield": p3ff,
         "cpu_baseline": cpu,
     }
+    del ex
+    if not args.no_c2 and args.config != "C2":
+        c2 = exact_leg(T, M, torch, dev, "C2", 50, 5)
+        out["c2"] = {"workload": f"C2: {c2['cfg'].name} ({c2['cfg'].nF} faces), exact energy+gradient",
+                     "pairs": c2["P"], "ms_per_step": round(c2["ms_per_step"], 4), "pairs_per_s": c2["value"],
+                     "kernel": "pair_sym_kernel<true>", "kernel_avg_ms": round(c2["kernel_avg_ms"], 4),
+                     "achieved": round(c2["tflops"], 3),
+                     "frac": round(c2["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4)}
+        if not args.no_row_only:
+            out["c2"]["row_only"] = row_only_leg(T, torch, dev, c2["X"], c2["F"], c2["P"], 10)
+        if not args.no_extra:
+            out["confinement"] = conf_leg(args, T, M, torch, dev)
+            out["quadrature6"] = quad_leg(args, T, M, torch, dev, c2["cfg"], c2["X"], c2["F"])
+            out["other_exponents"] = exponents_leg(args, T, torch, dev, c2["cfg"], c2["X"], c2["F"], c2["P"])
+            out["p3_elements"] = p3_leg(args, T, M, torch, dev, c2["cfg"], c2["F"])
+    if not args.no_extra and not args.no_farfield:
+        out["p3_farfield"] = p3_farfield_leg(args, T, M, torch, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -62,6 +62,8 @@ def _load():
         lib.tpeo_energy_rows.argtypes = [P, I64, P, I64, D, D, D, I64, I64, I32, P]
         lib.tpeo_gradient.argtypes = [P, I64, P, I64, D, D, D, I32, P, P]
         lib.tpeo_gradient_at.argtypes = [P, I64, P, I64, D, D, D, P, I64, I32, P]
+        lib.tpeo_gradient_rows.argtypes = [P, I64, P, I64, D, D, D, I64, I64, I32, P, P]
+        lib.tpeo_gradient_rows.restype = I32
         lib.tpeo_conf_energy.argtypes = [P, I64, P, I64, P, I64, P, I64, D, D, D, I32, P]
         lib.tpeo_conf_gradient.argtypes = [P, I64, P, I64, P, I64, P, I64, D, D, D, I32, P, P]
         lib.tpeo_conf_energy.restype = I32
@@ -134,6 +136,19 @@ def gradient(X, F, q=6.0, p=12.0, scale=1.0, nthreads=0):
     G = np.zeros_like(X)
     rc = _load().tpeo_gradient(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
                                nthreads, E.ctypes.data, G.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G
+
+
+def gradient_rows(X, F, r0, r1, q=6.0, p=12.0, scale=1.0, nthreads=0):
+    """(E_rows, G_rows): the contributions of the ordered pairs whose first face lies in [r0, r1)
+    to the energy and to dE/dX (the full ones for [0, nF))."""
+    X, F = _prep(X, F)
+    E = np.zeros(1)
+    G = np.zeros_like(X)
+    rc = _load().tpeo_gradient_rows(X.ctypes.data, X.shape[0], F.ctypes.data, F.shape[0], q, p, scale,
+                                    int(r0), int(r1), nthreads, E.ctypes.data, G.ctypes.data)
     if rc:
         raise OracleError(rc)
     return float(E[0]), G

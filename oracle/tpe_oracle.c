@@ -231,12 +231,13 @@ int tpeo_energy(const double* X, int64_t V, const int32_t* F, int64_t nF, double
     return tpeo_energy_rows(X, V, F, nF, q, p, scale, 0, nF, nthreads, E_out);
 }
 
-/* Full energy and gradient G[V*3] = dE/dX (row-major like X). */
-int tpeo_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
-                  double scale, int nthreads, double* E_out, double* G_out) {
+/* The contributions of the ordered pairs (S, T) with row S in [r0, r1) to the energy and to
+ * G[V*3] = dE/dX (row-major like X); rows [0, nF) give the full energy and gradient. */
+int tpeo_gradient_rows(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                       double scale, int64_t r0, int64_t r1, int nthreads, double* E_out, double* G_out) {
     int rc = check_inputs(X, V, F, nF, q, p);
     if (rc) return rc;
-    if (!G_out) return EINVAL_;
+    if (!G_out || r0 < 0 || r1 > nF || r0 > r1) return EINVAL_;
     face_t* G = (face_t*)malloc(sizeof(face_t) * (size_t)nF);
     if (!G) return EINVAL_;
     rc = all_faces(X, F, nF, G);
@@ -256,7 +257,7 @@ int tpeo_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, doub
         nsum acc = {0.0, 0.0};
         int lerr = OK;
 #pragma omp for schedule(static)
-        for (int64_t s = 0; s < nF; ++s) {
+        for (int64_t s = r0; s < r1; ++s) {
             for (int64_t t = 0; t < nF; ++t) {
                 if (share_vertex(F, s, t)) continue;
                 pairval pv;
@@ -292,6 +293,12 @@ int tpeo_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, doub
     }
     free(GV); free(part); free(G);
     return err;
+}
+
+/* Full energy and gradient G[V*3] = dE/dX (row-major like X). */
+int tpeo_gradient(const double* X, int64_t V, const int32_t* F, int64_t nF, double q, double p,
+                  double scale, int nthreads, double* E_out, double* G_out) {
+    return tpeo_gradient_rows(X, V, F, nF, q, p, scale, 0, nF, nthreads, E_out, G_out);
 }
 
 /* Exact gradient at selected vertices only: G_out[nv*3] = dE/dx_v for v = verts[i].

@@ -277,3 +277,14 @@ def test_error_paths():
     assert e.value.code == -3
     with pytest.raises(oracle.OracleError):
         oracle.energy(X, F, q=6.0, p=5.0)
+
+
+def test_row_ranges_add_up_to_the_whole():
+    """The row-range form (the CPU baseline's bounded sample) splits the energy and gradient exactly
+    along rows: the pieces add up to the full evaluation."""
+    c = M.make_config("C1")
+    E, G = oracle.gradient(c.X, c.F)
+    parts = [oracle.gradient_rows(c.X, c.F, a, b) for a, b in ((0, 1), (1, 700), (700, 1280))]
+    assert abs(sum(p[0] for p in parts) - E) <= 1e-13 * abs(E)
+    assert np.abs(sum(p[1] for p in parts) - G).max() <= 1e-13 * np.abs(G).max()
+    assert abs(oracle.energy_rows(c.X, c.F, 1, 700) - parts[1][0]) <= 1e-13 * abs(E)
