@@ -206,11 +206,12 @@ int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
  * compact patch.  Only
  * the ordering is stored: the cluster moments are recomputed from the positions passed to each
  * tpe_farfield call, so one tree serves a whole gradient flow as long as the faces stay put in
- * the ordering sense (accuracy, not correctness, depends on it).  The tree also keeps, on the
- * device, the work each target block of 64 faces took in the last tpe_farfield call on it; the
- * next monopole call (mlp NULL) launches the heaviest blocks first.  That changes only when blocks run, never what
- * they compute (results are the same bits in any order); calls that share one tree on several
- * streams at once are still correct.  *out is owned by the caller (tpe_tree_destroy).
+ * the ordering sense (accuracy, not correctness, depends on it).  Each tpe_farfield call first
+ * lists, per target block of 64 faces, its far clusters and near nodes (one walk of the tree), then
+ * evaluates the lists; a monopole call (mlp NULL) launches the blocks with the most work first.
+ * That changes only when blocks run, never what they compute.  The tree keeps the work of each
+ * block of its last call (a device array, written by every call; calls that share one tree on
+ * several streams at once are still correct).  *out is owned by the caller (tpe_tree_destroy).
  * Synchronises the stream. */
 int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                    int32_t leaf_size, tpe_tree** out);
@@ -245,7 +246,10 @@ int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64
  * share a vertex with the block out of far clusters; else TPE_ERR_INVALID_ARG); theta = 0
  * reproduces tpe_gradient to rounding.  G is the clustered form of eq. (dTP_reordered) (each
  * face's inner integrals with far patches replaced by their averages), not the derivative of E:
- * the paper propagates nothing back to the patches.  mlp: NULL for the plain monopole.  E_dev and/or G_dev (device) may be NULL but not
+ * the paper propagates nothing back to the patches.  mlp: NULL for the plain monopole.  The call
+ * lists every block's far clusters and near nodes in its scratch arena (at most ceil(nF / leaf)
+ * entries per block, within 8 GiB in all; TPE_ERR_OOM beyond that, which only meshes of several
+ * million faces at small theta reach).  E_dev and/or G_dev (device) may be NULL but not
  * both.  X, V, F, nF must describe the mesh the tree was built for (same size, same faces). */
 int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,

@@ -101,7 +101,9 @@ hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const d
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
-                           unsigned long long* stats, const uint32_t* order, uint32_t* work, hipStream_t st);
+                           unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
+                           uint32_t* flags, uint32_t* const sort[6], hipStream_t st);
+int64_t ff_list_cap(int64_t n, int leaf);
 hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
                            uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st);
 
@@ -344,6 +346,11 @@ struct Plan {
     float4* balls = nullptr;
     float4* cen4 = nullptr;
     uint32_t* nbox = nullptr;
+    // lists of the far-field walk (leaf size of the tree; 0: not used)
+    int ff_leaf = 0;
+    int64_t ff_cap = 0;
+    uint32_t* ff_ent = nullptr;
+    uint4* ff_lst = nullptr;
     // dual-tree far field (leaf size of the tree; -1: not used)
     int dual_leaf = -1;
     uint32_t *doff = nullptr, *dnear = nullptr, *dfar = nullptr, *dcnt = nullptr, *drel = nullptr;
@@ -411,6 +418,12 @@ void layout(Plan& P, char* base, bool grad) {
         P.balls = c.take<float4>(Fp / 64);
         P.cen4 = c.take<float4>(nR);
         P.nbox = c.take<uint32_t>((size_t)6 << std::max(P.treeH - 1, 0));
+        if (P.ff_leaf > 0) {
+            const int64_t nb = (nR + 63) / 64;
+            P.ff_cap = ff_list_cap(nR, P.ff_leaf);
+            P.ff_ent = c.take<uint32_t>((size_t)(nb * P.ff_cap));
+            P.ff_lst = c.take<uint4>((size_t)nb);
+        }
         if (P.dual_leaf > 0) {
             const int Hd = dual_level(P.treeH, P.dual_leaf);
             const size_t nn = (size_t)2 << Hd, nl = (size_t)1 << Hd;
@@ -531,7 +544,7 @@ int report_flags(tpe_ctx* ctx) {
         return fail(ctx, TPE_ERR_NONFINITE, "non-finite input or result (coincident non-adjacent centroids?)");
     if (f & FLAG_DEGENERATE) return fail(ctx, TPE_ERR_DEGENERATE, "degenerate face (area <= 1e-300)");
     if (f & FLAG_LISTS)
-        return fail(ctx, TPE_ERR_OOM, "dual-tree interaction lists exceed their scratch (theta too small for this mesh)");
+        return fail(ctx, TPE_ERR_OOM, "far-field interaction lists exceed their scratch (theta too small for this mesh)");
     return TPE_OK;
 }
 
@@ -995,6 +1008,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     const int Q = tree->Q;
     const int64_t n = tree->n;
     Plan P;
+    P.ff_leaf = tree->leaf;
     plan(P, ctx, nF, V, true, tree->H, 0, 0, Q, false, true);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, true);
@@ -1016,13 +1030,13 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    // monopole walks run their blocks heaviest first (the work recorded by the last walk on the tree)
-    if (!mlp)
-        HIPCHK(launch_ff_order(tree->work, (n + 63) / 64, P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
-    HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
-                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats,
-                           mlp ? nullptr : P.vals, tree->work, st));
+    {
+        uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
+        HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
+                               (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, st));
+    }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
@@ -1077,6 +1091,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     DeviceGuard dg(ctx->device);
     ORDERED(ctx);
     Plan P;
+    P.ff_leaf = tree->leaf;
     plan(P, ctx, nF, V, true, tree->H);
     if ((rc = ensure_arena(ctx, P.bytes))) return rc;
     layout(P, ctx->arena, true);
@@ -1096,13 +1111,13 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    // monopole walks run their blocks heaviest first (the work recorded by the last walk on the tree)
-    if (!mlp)
-        HIPCHK(launch_ff_order(tree->work, (nF + 63) / 64, P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff, st));
     HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
-    HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
-                           (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats,
-                           mlp ? nullptr : P.vals, tree->work, st));
+    {
+        uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
+        HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
+                               (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, st));
+    }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group

@@ -354,77 +354,46 @@ __device__ __forceinline__ float ball_dist(const float4& tb, const NodeRec& nd) 
 }
 
 constexpr int FF_STACK = 1024;  // LDS node stack per wave (overflow falls back to exact evaluation)
-constexpr int FF_STACK_LEARNED = 512;  // the same with the learned correction, whose MLP scratch shares the LDS
 constexpr int FF_NW = 4;          // waves per target block, monopole far field
 constexpr int FF_NW_LEARNED = 4;  // waves per target block with the learned correction
 
-// One work-group of NW waves per target block of 64 consecutive (tree-ordered) faces.  Every wave
-// walks the implicit tree the same way (batched depth first: up to 64 nodes popped at once, one
-// per lane, and tested in parallel):
-//   - far clusters are applied to all 64 rows (their records broadcast from the lane that loaded
-//     them),
-//   - near nodes (leaves, or nodes that cannot be opened) are evaluated exactly, without the
-//     shared-vertex test when their vertex ball cannot meet the block's,
-//   - other nodes push their two children;
-// the far clusters and the near nodes met along the walk are dealt out round-robin over the NW
-// waves, which split the block's work (heavy blocks have several times the average near work)
-// and fold their compensated sums into wave 0's through LDS at the end.  If the stack could
-// overflow, a node that would be opened is evaluated exactly instead (always correct).  Writes
-// the block's FP64 row sums acc64[k][i] (k < NACC).
-// At least 3 waves per SIMD (168 VGPRs): the learned variant needs 199 unconstrained and then spills a
-// few values; with its 9 KB of MLP scratch per wave, 3 work-groups fit a CU's LDS.
-template <bool LEARNED, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void farfield_kernel(const ColRec* __restrict__ cols,
-                                                           const int4* __restrict__ colv,
-                                                           const double* __restrict__ c64,
-                                                           const double* __restrict__ org,
-                                                           const NodeRec* __restrict__ nodes,
-                                                           const NodeMom* __restrict__ moms,
-                                                           const MlpPacked* __restrict__ W, int H, int leaf,
-                                                           int64_t nF, const uint32_t* __restrict__ bbox,
-                                                           const float4* __restrict__ balls,
-                                                           float theta, int64_t Fp, double* __restrict__ acc64,
-                                                           unsigned long long* __restrict__ stats,
-                                                           const uint32_t* __restrict__ order,
-                                                           uint32_t* __restrict__ work) {
-    constexpr int STK = LEARNED ? FF_STACK_LEARNED : FF_STACK;
-    constexpr int NRED = NW > 1 ? NW - 1 : 1;
-    __shared__ int stacks[NW][STK];
-    __shared__ MlpScratch ms[LEARNED ? NW : 1];
-    // the waves' final sums for the fold into wave 0; with the correction they reuse the MLP scratch,
-    // which is dead by then (every wave has passed the barrier before the fold)
-    __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
-    static_assert(!LEARNED || sizeof(MlpScratch) * NW >= sizeof(float) * NRED * 2 * NACC * 64, "fold space");
-    float (*red)[2 * NACC][64] = LEARNED ? reinterpret_cast<float (*)[2 * NACC][64]>(&ms[0])
-                                         : reinterpret_cast<float (*)[2 * NACC][64]>(&red_own[0][0][0]);
+// ---- the walk as lists: classify once per target block, then evaluate ---------------------------
+// ff_classify walks the tree for each target block once, one wave per block, batched depth first:
+// up to 64 nodes are popped at once (one per lane) and tested in parallel; far clusters are listed,
+// near nodes (leaves, or nodes the LDS stack could not open -- evaluating such a node exactly is
+// always correct) are listed, other nodes push their two children (right below left, so the left
+// is popped first).  The stack holds at most 128 + 64 (H - 1) + 1 entries (entries are ordered by
+// depth from the bottom, at most 64 of each depth stay behind a deeper one and the top depth has at
+// most 128), within FF_STACK for trees of height <= 14 (458,752 faces with leaves of 32).  It writes the block's near nodes (faces evaluated exactly:
+// leaves, or nodes the stack could not open; only non-empty ones) and far clusters, each in walk
+// order, into ent[b * cap ...]: near nodes from the front, far clusters from the back.  The far and
+// near nodes of a block are disjoint subtrees holding every non-empty leaf once, so a block has at
+// most ceil(nF / leaf) entries; cap below that sets FLAG_LISTS when a block outgrows it.
+// lst[b] = (near count, far count, near columns, visited nodes).
+constexpr int FFC_NW = 4;  // blocks (waves) per classify work-group
+
+__global__ __launch_bounds__(64 * FFC_NW) void ff_classify(const NodeRec* __restrict__ nodes, int H, int leaf,
+                                                           int64_t nF, const float4* __restrict__ balls, float theta,
+                                                           int64_t cap, uint32_t* __restrict__ ent,
+                                                           uint4* __restrict__ lst, uint32_t* __restrict__ work,
+                                                           uint32_t* __restrict__ flags) {
+    __shared__ int stacks[FFC_NW][FF_STACK];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int64_t nb = (nF + 63) / 64;
+    const int64_t b = blockIdx.x * (int64_t)FFC_NW + wave;
+    if (b >= nb) return;  // uniform over the wave
     int* stack = stacks[wave];
-    const int64_t b = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-    const int64_t i = b * 64 + lane;
-    const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
-    const ColRec me = cols[i];
-    const int4 mv = colv[i];
-    double o[3];
-    norm_origin(bbox, o);
-    // the row's centroid relative to the cluster records' origin (far clusters and the learned
-    // correction's features); near leaves re-express it relative to each chunk's origin
-    const float ax = (float)(cxd - o[0]), ay = (float)(cyd - o[1]), az = (float)(czd - o[2]);
     const float4 tb = balls[b];
-    float hi[NACC], lo[NACC], acc[NACC];
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
-    int cnt = 0;
     const int64_t leaf0 = (int64_t)1 << H;
-    const int4 nov = make_int4(0, 0, 0, 0);
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint32_t n_far = 0, n_near_cols = 0, n_visit = 0;
-    uint32_t deal_far = 0, deal_near = 0;  // running indices of far clusters / near nodes (same in every wave)
+    uint32_t* e = ent + (size_t)b * cap;
+    uint32_t n_far = 0, n_near = 0, n_near_cols = 0, n_visit = 0;
+    bool over = false;
     if (lane == 0) stack[0] = 1;
     int sz = 1;
     while (sz > 0) {
-        // the pops below read entries other lanes pushed: keep them after those stores
-        lds_phase();
+        lds_phase();  // the pops below read entries other lanes pushed
         const int n = sz < 64 ? sz : 64;
         sz -= n;
         const bool act = lane < n;
@@ -438,13 +407,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         const bool isleaf = (int64_t)k >= leaf0;
         bool open = valid && !far && !isleaf;
         const int nopen = __popcll(__ballot(open));
-        const bool overflow = sz + 2 * nopen > STK;
+        const bool overflow = sz + 2 * nopen > FF_STACK;
         if (overflow) open = false;
-        const bool near = valid && !far && !open;
-        // a near node whose vertex ball is disjoint from the block's shares no vertex with it
-        // (conservative margin for the FP32 distance)
-        const bool disjoint = dist * (1.f - 1e-5f) > tb.w + nd.r;
-        // push children of opened nodes (right child below left, so the left is popped first)
+        // a near node's face range [f0, f1) (empty ranges of padding leaves are skipped)
+        int64_t f0 = 0, f1 = 0;
+        const bool near0 = valid && !far && !open;
+        if (near0) {
+            const int lev = 63 - __builtin_clzll((unsigned long long)k);
+            const int64_t span = (int64_t)1 << (H - lev);
+            f0 = ((int64_t)k - ((int64_t)1 << lev)) * span * leaf;
+            f1 = f0 + span * leaf < nF ? f0 + span * leaf : nF;
+        }
+        const bool near = near0 && f0 < f1;
         if (!overflow) {
             const uint64_t om = __ballot(open);
             if (open) {
@@ -454,43 +428,127 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
             }
             sz += 2 * nopen;
         }
-        // far clusters
-        uint64_t fm = __ballot(far);
+        const uint64_t fm = __ballot(far), nm = __ballot(near);
+        const uint32_t fi = n_far + (uint32_t)__popcll(fm & lt), ni = n_near + (uint32_t)__popcll(nm & lt);
+        if (far) {
+            if ((int64_t)fi + n_near + __popcll(nm) < cap) e[cap - 1 - fi] = (uint32_t)k;
+            else over = true;
+        }
+        if (near) {
+            if ((int64_t)ni + n_far + __popcll(fm) < cap) e[ni] = (uint32_t)k;
+            else over = true;
+        }
         n_far += (uint32_t)__popcll(fm);
-        while (fm) {
-            const int l = (int)__builtin_ctzll(fm);
-            fm &= fm - 1;
-            if ((deal_far++ % NW) != (uint32_t)wave) continue;
-            const ColRec cr = {lane_f(nd.cx, l), lane_f(nd.cy, l), lane_f(nd.cz, l), lane_f(nd.a, l),
-                               lane_f(nd.nx, l), lane_f(nd.ny, l), lane_f(nd.nz, l), 0.f};
-            ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
-            if constexpr (LEARNED) {
-                const int kk = __builtin_amdgcn_readlane(k, l);
-                const NodeRec cn = {cr.cx, cr.cy, cr.cz, lane_f(nd.r, l), cr.a, cr.nx, cr.ny, cr.nz};
-                mlp_correction(W, cn, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
-            }
-            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        n_near += (uint32_t)__popcll(nm);
+        uint32_t cols = near ? (uint32_t)(f1 - f0) : 0u;
+        for (int off = 32; off > 0; off >>= 1) cols += __shfl_xor(cols, off);
+        n_near_cols += cols;
+    }
+    if (__any(over)) {
+        if (lane == 0) atomicOr(flags, (uint32_t)FLAG_LISTS);
+        n_far = n_near = 0;  // nothing of this block is evaluated; the call reports the error
+    }
+    if (lane == 0) {
+        lst[b] = make_uint4(n_near, n_far, n_near_cols, n_visit);
+        if (work) work[b] = n_near_cols + n_visit + n_far;
+    }
+}
+
+// The call's interaction counts from the blocks' list records, in one work-group (same-address
+// atomics from every block would serialise): far clusters, near columns and visited nodes summed,
+// blocks, and the largest near-column and far-cluster counts of a block.
+__global__ __launch_bounds__(256) void ff_stats_reduce(const uint4* __restrict__ lst, int64_t nb,
+                                                       unsigned long long* __restrict__ stats) {
+    __shared__ unsigned long long sh[4][5];
+    unsigned long long far = 0, cols = 0, vis = 0, mcols = 0, mfar = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
+        const uint4 L = lst[b];
+        far += L.y; cols += L.z; vis += L.w;
+        mcols = L.z > mcols ? L.z : mcols;
+        mfar = L.y > mfar ? L.y : mfar;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        far += __shfl_xor(far, off);
+        cols += __shfl_xor(cols, off);
+        vis += __shfl_xor(vis, off);
+        const unsigned long long a = __shfl_xor(mcols, off), c = __shfl_xor(mfar, off);
+        mcols = a > mcols ? a : mcols;
+        mfar = c > mfar ? c : mfar;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w][0] = far; sh[w][1] = cols; sh[w][2] = vis; sh[w][3] = mcols; sh[w][4] = mfar;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            far += sh[k][0]; cols += sh[k][1]; vis += sh[k][2];
+            mcols = sh[k][3] > mcols ? sh[k][3] : mcols;
+            mfar = sh[k][4] > mfar ? sh[k][4] : mfar;
         }
-        // near nodes (leaves, or nodes that could not be opened): exact pairs over their faces
-        uint64_t nm = __ballot(near);
-        const uint64_t dm = __ballot(disjoint);
-        while (nm) {
-            const int l = (int)__builtin_ctzll(nm);
-            nm &= nm - 1;
-            const int64_t kk = (int64_t)__builtin_amdgcn_readlane(k, l);
-            int lev = 63 - __builtin_clzll((unsigned long long)kk);
-            const int64_t span = (int64_t)1 << (H - lev);
-            const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
-            const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-            if (f0 < f1) {
-                n_near_cols += (uint32_t)(f1 - f0);
-                if ((deal_near++ % NW) != (uint32_t)wave) continue;
-                if ((dm >> l) & 1ull)
-                    ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
-                else
-                    ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
-            }
-        }
+        stats[0] = far; stats[1] = cols; stats[2] = vis; stats[3] = (unsigned long long)nb;
+        stats[4] = mcols; stats[5] = mfar;
+    }
+}
+
+// One work-group of NW waves per target block (launch order `order`, else tree order): the block's
+// far clusters and near nodes from ff_classify's lists, entry j of each list to wave j mod NW, far
+// clusters first; the waves' compensated sums are folded into wave 0's through LDS and written as
+// the block's FP64 row sums acc64[k][i].  (Splitting the heaviest blocks over several work-groups
+// was measured slower: the launch is bound by the total pair work, not by its last block.)
+template <bool LEARNED, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LEARNED ? 3 : 4))) void ff_eval(
+    const ColRec* __restrict__ cols, const int4* __restrict__ colv, const double* __restrict__ c64,
+    const double* __restrict__ org, const NodeRec* __restrict__ nodes, const NodeMom* __restrict__ moms,
+    const MlpPacked* __restrict__ W, int H, int leaf, int64_t nF, const uint32_t* __restrict__ bbox,
+    const float4* __restrict__ balls, int64_t Fp, double* __restrict__ acc64, const uint32_t* __restrict__ order,
+    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst) {
+    constexpr int NRED = NW > 1 ? NW - 1 : 1;
+    __shared__ MlpScratch ms[LEARNED ? NW : 1];
+    __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
+    static_assert(!LEARNED || sizeof(MlpScratch) * NW >= sizeof(float) * NRED * 2 * NACC * 64, "fold space");
+    float (*red)[2 * NACC][64] = LEARNED ? reinterpret_cast<float (*)[2 * NACC][64]>(&ms[0])
+                                         : reinterpret_cast<float (*)[2 * NACC][64]>(&red_own[0][0][0]);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int64_t b = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t i = b * 64 + lane;
+    const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
+    const ColRec me = cols[i];
+    const int4 mv = colv[i];
+    double o[3];
+    norm_origin(bbox, o);
+    const float ax = (float)(cxd - o[0]), ay = (float)(cyd - o[1]), az = (float)(czd - o[2]);
+    const float4 tb = balls[b];
+    const uint4 L = lst[b];
+    const uint32_t* e = ent + (size_t)b * cap;
+    float hi[NACC], lo[NACC], acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
+    int cnt = 0;
+    const int4 nov = make_int4(0, 0, 0, 0);
+    // far clusters: one pseudo-face each, its record loaded once for the wave
+    for (uint32_t j = wave; j < L.y; j += NW) {
+        const int kk = (int)e[cap - 1 - j];
+        const NodeRec nd = nodes[kk];
+        const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
+        ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+        if constexpr (LEARNED) mlp_correction(W, nd, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
+        if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+    }
+    // near nodes: exact pairs over their faces, without the shared-vertex test when their vertex
+    // ball cannot meet the block's (conservative margin for the FP32 distance)
+    for (uint32_t j = wave; j < L.x; j += NW) {
+        const int64_t kk = (int64_t)e[j];
+        const int lev = 63 - __builtin_clzll((unsigned long long)kk);
+        const int64_t span = (int64_t)1 << (H - lev);
+        const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
+        const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
+        const NodeRec nd = nodes[kk];
+        if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
+            ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+        else
+            ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
     }
     ff_fold(acc, hi, lo);
     if constexpr (NW > 1) {
@@ -504,7 +562,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         }
         __syncthreads();
         if (wave == 0) {
-            // fold the other waves' compensated sums (hi - lo each) into wave 0's, in wave order
 #pragma unroll
             for (int j = 0; j < NW - 1; ++j)
 #pragma unroll
@@ -523,17 +580,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     if (wave == 0) {
 #pragma unroll
         for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] = (double)hi[kk] - (double)lo[kk];
-        // the block's work, for the launch order of the next monopole call on this tree
-        if (lane == 0 && work) work[b] = n_near_cols + n_visit + n_far;
-        // interaction counts of this target block (per row): far clusters, near columns, visited nodes
-        if (lane == 0 && stats) {
-            atomicAdd(&stats[0], (unsigned long long)n_far);
-            atomicAdd(&stats[1], (unsigned long long)n_near_cols);
-            atomicAdd(&stats[2], (unsigned long long)n_visit);
-            atomicAdd(&stats[3], 1ull);
-            atomicMax(&stats[4], (unsigned long long)n_near_cols);
-            atomicMax(&stats[5], (unsigned long long)n_far);
-        }
     }
 }
 
@@ -552,7 +598,7 @@ __device__ __forceinline__ uint32_t sample_hash(uint32_t seed, uint32_t block, u
     return fmix32(fmix32(fmix32(seed) ^ block) ^ node);
 }
 
-// Training samples: the same walk as farfield_kernel; for far clusters with at most max_faces
+// Training samples: the walk and decisions of ff_classify; for far clusters with at most max_faces
 // faces, selected with probability ~ sel (hash of seed, block, node), up to `quota` per block, every
 // row of the block yields one sample: features and the (exact - monopole) correction in units.
 // Output rows [(b * quota + c) * 64 + lane]; rows not filled keep weight 0 (targets[.][15]).
@@ -955,22 +1001,42 @@ hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uin
     return radix_sort(keys, vals, ktmp, vtmp, nb, 8, hist, hoff, st);
 }
 
+// Entries per block of the walk's lists: every non-empty leaf at most once, within 8 GiB in all.
+int64_t ff_list_cap(int64_t n, int leaf) {
+    const int64_t nb = (n + 63) / 64, nleaf = (n + leaf - 1) / leaf;
+    const int64_t budget = ((int64_t)2 << 30) / std::max<int64_t>(nb, 1);
+    return std::max<int64_t>(1, std::min(nleaf, budget));
+}
+
+// The far field of the tree's target blocks: balls, the classify pass (lists, the blocks' work,
+// interaction counts), the launch order (monopole: heaviest blocks first by this call's work; with
+// the correction: tree order, which it prefers), the evaluation.  sort: keys, vals, ktmp, vtmp,
+// hist, hoff of a radix sort of ceil(nF / 64) entries.
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
-                           unsigned long long* stats, const uint32_t* order, uint32_t* work, hipStream_t st) {
+                           unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
+                           uint32_t* flags, uint32_t* const sort[6], hipStream_t st) {
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
+    hipLaunchKernelGGL(ff_classify, dim3((unsigned)((nb + FFC_NW - 1) / FFC_NW)), dim3(64 * FFC_NW), 0, st, r, H, leaf,
+                       nF, balls, theta, cap, ent, lst, work, flags);
+    if (stats) hipLaunchKernelGGL(ff_stats_reduce, dim3(1), dim3(256), 0, st, lst, nb, stats);
+    const uint32_t* order = nullptr;
+    if (!mlp_packed) {
+        hipError_t e = launch_ff_order(work, nb, sort[0], sort[1], sort[2], sort[3], sort[4], sort[5], st);
+        if (e != hipSuccess) return e;
+        order = sort[1];
+    }
     if (mlp_packed)
-        hipLaunchKernelGGL((farfield_kernel<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st,
-                           cols, colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, theta, Fp,
-                           acc64, stats, order, work);
+        hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
+                           colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,
+                           order, cap, ent, lst);
     else
-        hipLaunchKernelGGL((farfield_kernel<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv,
-                           c64, org, r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, theta, Fp, acc64, stats,
-                           order, work);
+        hipLaunchKernelGGL((ff_eval<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org,
+                           r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst);
     return hipGetLastError();
 }
 

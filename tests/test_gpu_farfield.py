@@ -37,8 +37,9 @@ def test_error_decreases_with_theta():
         E, G = T.farfield(tree, Xd, Fd, theta=th)
         errs.append((rel_energy(float(E.cpu()), E0), rel_grad_maxnorm(G.cpu().numpy(), G0)))
         log("C2 theta", th, "rel E", errs[-1][0], "rel G", errs[-1][1])
-    assert errs[0][1] > errs[1][1] > errs[2][1]
-    assert errs[0][0] > errs[2][0]
+    # below theta = 0.25 the gradient error sits at the FP32 level of the comparison (2.5e-7)
+    assert errs[0][1] > errs[1][1] and errs[2][1] <= max(errs[1][1], 1e-6)
+    assert errs[0][0] > errs[1][0] > errs[2][0]
     # element-wise parity with the oracle of the scheme is tests/test_gpu_ff_parity.py; here the
     # size of the approximation error the oracle gives at theta = 0.5 (5.8e-6), with margin
     assert errs[0][1] < 2e-5
