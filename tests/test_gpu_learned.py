@@ -155,10 +155,56 @@ def test_committed_checkpoint_at_c4():
     eGm = rel_grad_maxnorm(Gm.cpu().numpy(), G0)
     eGl = rel_grad_maxnorm(Gl.cpu().numpy(), G0)
     eEl = rel_energy(float(El.cpu()), float(E0.cpu()))
+    eEm = rel_energy(float(Em.cpu()), float(E0.cpu()))
     log(f"C4 committed checkpoint (gate {m.gate():.3f}): exact {t_e*1e3:.1f} ms, learned {t_l*1e3:.2f} ms "
-        f"({t_e/t_l:.1f}x), rel G {eGl:.3e} (monopole {eGm:.3e}), rel E {eEl:.3e}")
+        f"({t_e/t_l:.1f}x), rel G {eGl:.3e} (monopole {eGm:.3e}), rel E {eEl:.3e} (monopole {eEm:.3e})")
     assert t_e / t_l >= 10.0
     assert eGl <= 1e-3 and eGl <= eGm
+    assert eEl < eEm  # the gain the network brings at the same theta: energy and gradient both closer
+
+
+def test_learned_against_the_monopole_at_equal_time():
+    """What the committed network is worth against the method without it at the same cost: the
+    monopole far field at the smaller theta that takes no longer than the learned far field at
+    theta 0.5.  Measured: the monopole at theta 0.35-0.4 is as fast and 3-4x more accurate, so the
+    per-face correction does not pay for its cost; the test records that ranking (a network that
+    beat it would fail the last assertion, and the conclusion should then be revised)."""
+    import os
+    import torch
+    T = tpe()
+    ckpt = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2509_22110_amd", "data",
+                        "farfield_mlp.bin")
+    m = T.MLP.load(ckpt)
+    c = M.make_config("C4")
+    Xd, Fd = upload(c.X, c.F)
+    _, G0 = T.gradient(Xd, Fd)
+    G0 = G0.cpu().numpy()
+    tree = T.build_tree(Xd, Fd)
+    ctx = T.context(Xd.device)
+    ctx.set_option(T.OPT_SYNC_CHECKS, 0)
+
+    def timed(theta, mlp, reps=5):
+        T.farfield(tree, Xd, Fd, theta=theta, mlp=mlp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E, G = T.farfield(tree, Xd, Fd, theta=theta, mlp=mlp)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, rel_grad_maxnorm(G.cpu().numpy(), G0)
+    try:
+        t_l, e_l = timed(0.5, m)
+        mono = {th: timed(th, None) for th in (0.5, 0.45, 0.4, 0.35)}
+        ctx.sync_check()
+    finally:
+        ctx.set_option(T.OPT_SYNC_CHECKS, 1)
+    log(f"learned theta 0.5: {t_l*1e3:.2f} ms, rel G {e_l:.3e}; monopole: " +
+        ", ".join(f"theta {th}: {t*1e3:.2f} ms, {e:.3e}" for th, (t, e) in mono.items()))
+    errs = [e for _, e in mono.values()]
+    assert all(a > b for a, b in zip(errs, errs[1:]))  # smaller theta, smaller error
+    within = [th for th, (t, _) in mono.items() if t <= t_l]
+    assert within, "no monopole setting as fast as the learned far field"
+    best = min(mono[th][1] for th in within)
+    assert best < e_l  # the monopole at equal time dominates the committed per-face network
 
 
 def test_c5_learned_flow_judged():
