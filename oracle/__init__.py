@@ -52,6 +52,19 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitized(out_path: str) -> str:
+    """Compile ``sanitize_driver.c`` with both oracle sources under AddressSanitizer and
+    UndefinedBehaviorSanitizer (every report fatal, the runtime linked statically) into the
+    executable `out_path`: a check of the oracle's own memory accesses and arithmetic, run by the
+    CPU tests."""
+    subprocess.check_call([
+        "gcc", "-O1", "-g", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+        "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+        "-static-libasan", _SRC, _SRC_FF, os.path.join(_HERE, "sanitize_driver.c"), "-o", out_path, "-lm",
+    ])
+    return out_path
+
+
 def _load():
     global _lib
     if _lib is None:

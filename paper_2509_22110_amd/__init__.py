@@ -537,7 +537,15 @@ class TPEFunction(torch.autograd.Function):
     hand-written gradient of the same method (tpe_gradient, or tpe_farfield which recomputes the
     cluster moments from X) and scales it by the incoming gradient.  Only X and F are saved.
     F with 10 ints per row: curved cubic elements (tpe_gradient_p3 / tpe_farfield_p3, `points`
-    quadrature points per element for the exact path)."""
+    quadrature points per element for the exact path).
+
+    With a tree and theta > 0 the backward is the cluster scheme's gradient (Sec. 3.2: the inner
+    integrals of eq. dTP_reordered approximated per far cluster), not the derivative of the
+    far-field energy that forward returns: the cluster moments and the admissibility decisions
+    are not differentiated.  Both approximate the exact pair (E, dE/dX) to the far field's
+    accuracy and agree at theta = 0; at theta = 0.5 on the 20,480-face sphere the directional
+    derivative of the far-field energy differs from <backward, v> by about the far field's own
+    error against the exact gradient."""
 
     @staticmethod
     def forward(ctx, X, F, q=6.0, p=12.0, scale=1.0, tree=None, theta=0.5, mlp=None, points=None):

@@ -116,3 +116,38 @@ def test_flow_with_farfield_judge():
     rec = gradient_flow(Xd, Fd, 10, 1e-3, scale=SCALE, tree=tree, theta=0.5, judge_every=5)
     log("far-field flow judge", rec.judge)
     assert len(rec.judge) == 2 and all(e < 0.5 for _, e in rec.judge)
+
+
+def test_autograd_farfield_backward_at_theta_half():
+    """At theta = 0.5 the backward is the cluster scheme's gradient, not the derivative of the
+    far-field energy: <G_ff, v> is compared with a central difference of the far-field energy
+    along v (the gap is recorded) and with the exact directional derivative.  Both gaps stay
+    within the far field's accuracy; the backward equals tpe_farfield's gradient bit for bit."""
+    import torch
+    T = tpe()
+    c = M.make_config("C2")
+    Xd, Fd = upload(c.X, c.F)
+    tree = T.build_tree(Xd, Fd)
+    X = Xd.clone().requires_grad_(True)
+    E = T.tpe_energy(X, Fd, tree=tree, theta=0.5)
+    E.backward()
+    g_ff = X.grad
+    E_ff, G_ff = T.farfield(tree, Xd, Fd, theta=0.5)
+    assert float(E.detach().cpu()) == float(E_ff.cpu())
+    assert torch.equal(g_ff, G_ff)
+    _, G_ex = T.gradient(Xd, Fd)
+    rng = np.random.default_rng(3)
+    dirs = [G_ex / G_ex.norm()] + [torch.from_numpy(rng.normal(size=c.X.shape)).cuda() for _ in range(2)]
+    h = 1e-5 * float(np.abs(c.X).max())
+    for k, v in enumerate(dirs):
+        v = v / v.norm()
+        Ep = float(T.farfield(tree, Xd + h * v, Fd, theta=0.5, want_grad=False)[0].cpu())
+        Em = float(T.farfield(tree, Xd - h * v, Fd, theta=0.5, want_grad=False)[0].cpu())
+        fd = (Ep - Em) / (2 * h)
+        an = float((g_ff * v).sum())
+        ex = float((G_ex * v).sum())
+        gap_fd = abs(an - fd) / abs(ex)
+        gap_ex = abs(an - ex) / abs(ex)
+        log(f"direction {k}: <G_ff,v> {an:.8e}  FD of E_ff {fd:.8e}  exact {ex:.8e}  "
+            f"gap to FD {gap_fd:.2e}  gap to exact {gap_ex:.2e}  FD to exact {abs(fd - ex) / abs(ex):.2e}")
+        assert gap_fd <= 2e-2 and gap_ex <= 2e-2
