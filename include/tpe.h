@@ -70,7 +70,7 @@ typedef enum {
 typedef enum {
     TPE_OPT_SYNC_CHECKS = 1,  /* 1 (default): every call synchronises and reports device-side
                                  errors; 0: calls stay asynchronous, tpe_check() reports */
-    TPE_OPT_TARGET_WAVES = 2, /* work-groups (of 4 waves) of the persistent exact pair kernel;
+    TPE_OPT_TARGET_WAVES = 2, /* work-groups of the persistent exact pair kernel;
                                  0 (default) = as many as the device keeps resident at once.  The
                                  work is split evenly over them; results agree to rounding */
     TPE_OPT_KERNEL_TIMING = 3, /* 1: record HIP events around every launch of the dominant
@@ -92,7 +92,13 @@ typedef enum {
                                  and that scratch can be allocated; 0, or beyond that: every
                                  ordered pair from its row face (the row-only kernel).  Results
                                  agree to rounding.  The scratch stays allocated with the context
-                                 (tpe_destroy frees it) */
+                                 (tpe_destroy frees it) */,
+    TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2 or 4 (super
+                                 blocks of 128, 256 or 512 faces); 0 (default): the fewest whose
+                                 column partial sums fit in 16 GiB (1 up to about 370,000 faces,
+                                 then 2, then 4).  Fewer waves wait less at the work-group's
+                                 barriers but write proportionally more partial sums.  Results
+                                 agree to rounding */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */

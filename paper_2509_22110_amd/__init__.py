@@ -31,6 +31,7 @@ OPT_TARGET_WAVES = 2
 OPT_KERNEL_TIMING = 3
 OPT_QUADRATURE = 4
 OPT_SYMMETRIC = 5
+OPT_SYM_WAVES = 6
 
 
 class TPEError(RuntimeError):

@@ -60,8 +60,8 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
                            uint32_t* flags, double* E, EnergyOut* in_gather, hipStream_t st);
 hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
                             const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st);
-int pair_sym_blocks_per_cu(bool grad);
-SymSched make_sym_sched(int64_t Fp, int W, int tail);
+int pair_sym_blocks_per_cu(bool grad, int nw);
+SymSched make_sym_sched(int64_t Fp, int W, int tail, int nw);
 int64_t sym_part_floats(const SymSched& sc, bool grad);
 int64_t sym_colpart_floats(const SymSched& sc, bool grad);
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
@@ -75,10 +75,15 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
                        int64_t Fp, double q, double p, uint32_t* off, uint32_t* nnear, uint32_t* nfar, uint32_t* cnt,
                        uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
                        uint32_t* flags, unsigned long long* stats, uint32_t* const sort[6], hipStream_t st);
-// the symmetric kernel is used while its column partials (32 B per face and earlier super block of
-// 512 faces) fit in this many bytes: about 1,430,000 faces, of the GPU's 288 GB of HBM; if the
-// allocation fails the call runs the row-only kernel instead
+// the symmetric kernel is used while its column partials (32 B per face and earlier super block)
+// fit in this many bytes: about 1,430,000 faces with super blocks of 512 faces, of the GPU's 288 GB
+// of HBM; if the allocation fails the call runs the row-only kernel instead
 constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
+// Work-groups of 1 or 2 waves (super blocks of 128 or 256 faces) run the symmetric kernel faster
+// than 4 (each wave waits less at the work-group's barriers: 63.8 / 65.2 / 69.9 ms at 327,680 faces)
+// but write 4 or 2 times the column partials, which the merge reads back; the fewest waves whose
+// partials fit in this budget are taken (327,680 faces: 1 wave, 12.5 GiB), else 4
+constexpr int64_t SYM_FAST_COLPART_BYTES = (int64_t)16 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
@@ -191,7 +196,8 @@ struct tpe_ctx {
     int64_t target_waves = 0;     // 0: resident-wave capacity of the pair kernel
     int quad = 1;                 // quadrature points per face of the exact path (1, 3 or 6)
     int resident[2] = {0, 0};     // pair-kernel work-groups resident on the device (energy, gradient)
-    int resident_sym[2] = {0, 0}; // the same for the symmetric pair kernel
+    int resident_sym[3][2] = {};  // the same for the symmetric pair kernel, work-groups of 1, 2, 4 waves
+    int sym_waves = 0;            // waves per work-group of the symmetric kernel (0: by size)
     bool symmetric = true;        // exact self energy (6, 12): symmetric pair kernel where it fits
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -458,21 +464,34 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
     P.Fp = round_up(P.nR, std::max(ROWB, CTILE));
     P.sym = false;
     if (sym) {
-        const int64_t Fs = round_up(P.nR, SB);
+        // waves per work-group: forced by TPE_OPT_SYM_WAVES, else the fewest whose column partials
+        // fit in SYM_FAST_COLPART_BYTES
+        int nw = ctx->sym_waves;
+        if (nw == 0) {
+            nw = 4;
+            for (int cand = 1; cand < 4; cand *= 2) {
+                const SymSched t = make_sym_sched(round_up(P.nR, (int64_t)cand * ROWB), 1, 0, cand);
+                if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_FAST_COLPART_BYTES) {
+                    nw = cand;
+                    break;
+                }
+            }
+        }
+        const int64_t Fs = round_up(P.nR, (int64_t)nw * ROWB);
         // work-groups: 1 to 8 times the resident count, one step per 16 units a resident slot
         // would get (the hardware refills the slots of early finishers, which evens out the
         // finish times; more work-groups add row segments for the merge to read), then one
         // single-unit work-group per resident slot for the end of the launch
-        const int resident = ctx->resident_sym[grad ? 1 : 0];
+        const int resident = ctx->resident_sym[nw == 1 ? 0 : nw == 2 ? 1 : 2][grad ? 1 : 0];
         int W = resident, tail = 0;
         if (ctx->target_waves > 0) {
             W = (int)ctx->target_waves;
         } else {
-            const int64_t units = make_sym_sched(Fs, 1, 0).U;
+            const int64_t units = make_sym_sched(Fs, 1, 0, nw).U;
             W *= (int)std::max<int64_t>(1, std::min<int64_t>(8, units / ((int64_t)W * 16)));
             tail = resident;
         }
-        const SymSched t = make_sym_sched(Fs, W, tail);
+        const SymSched t = make_sym_sched(Fs, W, tail, nw);
         if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_MAX_COLPART_BYTES) {
             P.sym = true;
             P.ssc = t;
@@ -760,8 +779,10 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
             ncu = 1;
         ctx->resident[0] = ncu * pair_blocks_per_cu(false);
         ctx->resident[1] = ncu * pair_blocks_per_cu(true);
-        ctx->resident_sym[0] = ncu * pair_sym_blocks_per_cu(false);
-        ctx->resident_sym[1] = ncu * pair_sym_blocks_per_cu(true);
+        for (int k = 0; k < 3; ++k) {
+            ctx->resident_sym[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k);
+            ctx->resident_sym[k][1] = ncu * pair_sym_blocks_per_cu(true, 1 << k);
+        }
     }
     if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess ||
@@ -826,6 +847,11 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
         case TPE_OPT_SYMMETRIC:
             if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric: 0 or 1");
             ctx->symmetric = value != 0;
+            return TPE_OK;
+        case TPE_OPT_SYM_WAVES:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric kernel waves: 0, 1, 2 or 4");
+            ctx->sym_waves = (int)value;
             return TPE_OK;
         case TPE_OPT_KERNEL_TIMING:
             if (value < 0 || value > 2) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0, 1 or 2");

@@ -105,22 +105,21 @@ struct Sched {
     __host__ __device__ int wave_of(int64_t x) const { return (int)(((x + 1) * (int64_t)W - 1) / U); }
 };
 
-// Symmetric schedule of the self energy's pair kernel.  A work-group of SYM_NW waves holds a super
-// block of SB = SYM_NW * ROWB rows (one row block per wave).  Super block I owns first its SBC
-// diagonal units, the CHUNK-column chunks J = SBC I, ..., SBC I + SBC - 1 of its own faces (pairs
-// inside the super block, evaluated from both sides as ordered pairs), then its symmetric units,
-// the SYM_COLS-column slices of all later chunks (every unordered pair once, credited to both
-// faces; the columns' share goes to one column partial per symmetric unit).  Units are numbered
-// super block by super block; work-group w takes the contiguous range [begin(w), begin(w+1)), a
-// diagonal unit costing DIAG_COST and a symmetric one SYM_COST.  The first W1 work-groups share
-// the cost C1 in equal parts; the other W - W1 share the rest, about one unit each, so that the
-// end of the launch is made of short ranges the hardware hands to whichever slots free up first
-// (W1 = W: equal parts for all).
+// Symmetric schedule of the self energy's pair kernel.  A work-group of nw waves (1, 2 or 4) holds
+// a super block of nw * ROWB rows (one row block per wave).  Super block I owns first its sbc =
+// nw * ROWB / CHUNK diagonal units, the CHUNK-column chunks J = sbc I, ..., sbc I + sbc - 1 of its
+// own faces (pairs inside the super block, evaluated from both sides as ordered pairs), then its
+// symmetric units, the SYM_COLS-column slices of all later chunks (every unordered pair once,
+// credited to both faces; the columns' share goes to one column partial per symmetric unit).
+// Units are numbered super block by super block; work-group w takes the contiguous range
+// [begin(w), begin(w+1)), a diagonal unit costing DIAG_COST and a symmetric one SYM_COST.  The
+// first W1 work-groups share the cost C1 in equal parts; the other W - W1 share the rest, about
+// one unit each, so that the end of the launch is made of short ranges the hardware hands to
+// whichever slots free up first (W1 = W: equal parts for all).  Fewer waves per work-group wait
+// less at the work-group's barriers but write more column partials (one per unit: the partial
+// volume is inversely proportional to nw).
 // sums per face in the symmetric kernel: K, S0, Sd (3), V = Sn - 2 Sdd (3)
 constexpr int NSYM = 8;
-constexpr int SYM_NW = 4;
-constexpr int SB = SYM_NW * ROWB;
-constexpr int SBC = SB / CHUNK;           // chunks per super block
 constexpr int SYM_COLS = 64;              // columns of a symmetric unit (64: the wave; 16: a row of lanes)
 constexpr int SUB = CHUNK / SYM_COLS;     // symmetric units per chunk
 // relative costs, measured: a diagonal unit (the row-only pass over CHUNK columns, nearly always
@@ -134,18 +133,20 @@ struct SymSched {
     int W, nsb, nch;
     int W1;        // work-groups sharing the cost C1 (the rest share C - C1)
     int64_t C1;
-    // units of super block I: SBC + SUB (nch - SBC (I + 1)) = A - D I
-    __host__ __device__ int64_t ua() const { return SBC + (int64_t)SUB * (nch - SBC); }
-    static constexpr int64_t UD = (int64_t)SUB * SBC;
+    int nw;        // waves (row blocks) per work-group: 1, 2 or 4
+    int sbc;       // chunks per super block, nw * ROWB / CHUNK
+    // units of super block I: sbc + SUB (nch - sbc (I + 1)) = A - D I
+    __host__ __device__ int64_t ua() const { return sbc + (int64_t)SUB * (nch - sbc); }
+    __host__ __device__ int64_t ud() const { return (int64_t)SUB * sbc; }
     // first unit of super block I
-    __host__ __device__ int64_t base(int64_t I) const { return I * ua() - UD * I * (I - 1) / 2; }
+    __host__ __device__ int64_t base(int64_t I) const { return I * ua() - ud() * I * (I - 1) / 2; }
     // symmetric units of the super blocks before I
     __host__ __device__ int64_t base_sym(int64_t I) const {
-        return (int64_t)SUB * (I * (nch - SBC) - (int64_t)SBC * I * (I - 1) / 2);
+        return (int64_t)SUB * (I * (nch - sbc) - (int64_t)sbc * I * (I - 1) / 2);
     }
     // super block of unit u (0 <= u < U): the root of base(I) = u, then corrected to be exact
     __host__ __device__ int block_of(int64_t u) const {
-        const double h = 0.5 * UD, b = (double)ua() + h;
+        const double h = 0.5 * (double)ud(), b = (double)ua() + h;
         const double disc = b * b - 4.0 * h * (double)u;
         int I = (int)((b - sqrt(disc > 0.0 ? disc : 0.0)) / (2.0 * h));
         I = I < 0 ? 0 : (I > nsb - 1 ? nsb - 1 : I);
@@ -158,7 +159,7 @@ struct SymSched {
         if (u >= U) return C;
         const int I = block_of(u);
         const int64_t k = u - base(I);
-        const int64_t ndiag = (int64_t)SBC * I + (k < SBC ? k : SBC);
+        const int64_t ndiag = (int64_t)sbc * I + (k < sbc ? k : sbc);
         return SYM_COST * u + (int64_t)(DIAG_COST - SYM_COST) * ndiag;
     }
     // does the range of work-group w start at or before a unit whose preceding cost is c?

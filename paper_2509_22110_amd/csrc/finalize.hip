@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict_
     }
     const int rr = (int)(i % ROWB);
     const int rb = __builtin_amdgcn_readfirstlane((int)(i / ROWB));
-    const int I = rb / SYM_NW, wv = rb % SYM_NW;
+    const int I = rb / sc.nw, wv = rb % sc.nw;
     const int w0 = __builtin_amdgcn_readfirstlane(sc.wave_of(sc.base(I)));
     const int w1 = __builtin_amdgcn_readfirstlane(sc.wave_of(sc.base(I + 1) - 1));
     // The loops are unrolled so that the loads of several terms are in flight together; the adds
@@ -329,13 +329,13 @@ __global__ __launch_bounds__(256) void sym_merge_kernel(const float* __restrict_
 #pragma unroll 8
     for (int w = w0; w <= w1; ++w) {
         const int f = first[w];
-        const float v = part[(((size_t)(w + I) * SYM_NW + wv) * NA + ks) * ROWB + rr];
+        const float v = part[(((size_t)(w + I) * sc.nw + wv) * NA + ks) * ROWB + rr];
         acc += f <= I ? (double)v : 0.0;
     }
     const int J = (int)(i / SYM_COLS), jj = (int)(i % SYM_COLS);
 #pragma unroll 8
     for (int Ip = 0; Ip < I; ++Ip)
-        acc += (double)colpart[((size_t)(sc.base_sym(Ip) + J - SUB * SBC * (Ip + 1)) * NA + ks) * SYM_COLS + jj];
+        acc += (double)colpart[((size_t)(sc.base_sym(Ip) + J - SUB * sc.sbc * (Ip + 1)) * NA + ks) * SYM_COLS + jj];
     acc64[(size_t)k * Fp + i] = acc;
 }
 

@@ -360,7 +360,7 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) __attribute__((amdgpu_waves_per_eu(
 // (l + j) mod SYM_COLS at step j from LDS.  A column's sums travel with it: after every step they
 // move one lane down (a DPP wave or row rotation fused into the add of the step's contributions), so
 // after the SYM_COLS steps every lane holds the sums of one column over the rows of its group of
-// lanes, and the work-group adds the (64 / SYM_COLS) x SYM_NW partial sums of each column in LDS,
+// lanes, and the work-group adds the (64 / SYM_COLS) x NW partial sums of each column in LDS,
 // without any cross-lane reduction.
 
 // Shared part of the pair (row face, column face) for the symmetric kernel.  Energy only: e = t^q
@@ -515,26 +515,26 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
 }
 
 // LDS of the symmetric kernel's work-group: two column buffers (records, vertex ids) and two column
-// reduction buffers [SYM_NW][WAVE / SYM_COLS][SYM_COLS][CS] (CS = NSYM with the gradient).
+// reduction buffers [NW][WAVE / SYM_COLS][SYM_COLS][CS] (CS = NSYM with the gradient).
 template <bool GRAD>
 constexpr int sym_cs() { return GRAD ? NSYM : 1; }
-template <bool GRAD>
+template <bool GRAD, int NW>
 constexpr size_t sym_lds_floats() {
-    return 2 * (size_t)SYM_COLS * (8 + 4) + 2 * (size_t)SYM_NW * WAVE * sym_cs<GRAD>();
+    return 2 * (size_t)SYM_COLS * (8 + 4) + 2 * (size_t)NW * WAVE * sym_cs<GRAD>();
 }
 
-// grid: W work-groups of SYM_NW waves (see SymSched).  part: [W + nsb][SYM_NW][NA][ROWB] FP32, one
+// grid: W work-groups of NW = sc.nw waves (see SymSched).  part: [W + nsb][NW][NA][ROWB] FP32, one
 // segment per (work-group g, super block I it touches) at slot g + I (the slots of consecutive
 // work-groups do not overlap: each super block after a work-group's first adds one slot), each wave
 // writing its own row block's compensated sums rounded to FP32 (hi minus the compensation).  colpart:
-// [symmetric unit][NA][SYM_COLS] FP32, the sums of the unit's SB rows for each of its columns, added
+// [symmetric unit][NA][SYM_COLS] FP32, the sums of the unit's NW * ROWB rows for each of its columns, added
 // over the waves and rows of lanes in a fixed order.
 // first[w]: the first super block of work-group w (INT32_MAX if its range is empty).
-template <bool GRAD>
+template <bool GRAD, int NW>
 // At least 4 waves per SIMD (128 VGPRs, against 165 unconstrained): the compiler then keeps a few
 // long-lived values (FP64 row centroids, vertex ids) in scratch, reloaded once per super block,
 // and the column loop is unchanged.
-__global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_kernel(const ColRec* __restrict__ cols,
+__global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_kernel(const ColRec* __restrict__ cols,
                                                                  const double* __restrict__ c64,
                                                                  const int4* __restrict__ colv,
                                                                  const double* __restrict__ corg,
@@ -543,10 +543,11 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
                                                                  float* __restrict__ colpart, int* __restrict__ first) {
     constexpr int NA = GRAD ? NSYM : 1;
     constexpr int CS = sym_cs<GRAD>();
+    constexpr int SBC = NW * ROWB / CHUNK;  // equals sc.sbc
     extern __shared__ float lds[];
     ColRec* lcol = reinterpret_cast<ColRec*>(lds);                 // [2][SYM_COLS]
     int4* lvid = reinterpret_cast<int4*>(lds + 2 * SYM_COLS * 8);  // [2][SYM_COLS]
-    float* red = lds + 2 * SYM_COLS * 12;                          // [2][SYM_NW][WAVE][CS]
+    float* red = lds + 2 * SYM_COLS * 12;                          // [2][NW][WAVE][CS]
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int g = blockIdx.x;
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
     int64_t k = u - sc.base(I);
     // staging of a unit's columns: SYM_COLS columns x 12 dwords (record, vertex ids); thread t
     // moves SPT consecutive dwords of column t / TPC (TPC threads per column)
-    constexpr int NT = WAVE * SYM_NW;
+    constexpr int NT = WAVE * NW;
     constexpr int TPC = NT / SYM_COLS < 12 ? NT / SYM_COLS : 12;
     constexpr int SPT = 12 / TPC;
     static_assert(TPC * SPT == 12 && SYM_COLS * TPC <= NT, "staging layout");
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
         __syncthreads();
     }
     while (u < u1) {  // uniform over the work-group
-        const int rb = I * SYM_NW + wave;
+        const int rb = I * NW + wave;
         double cxd[RPL], cyd[RPL], czd[RPL];
         float nx[RPL], ny[RPL], nz[RPL], aS[RPL], aS2[RPL];
         int rv[RPL][3];
@@ -617,7 +618,7 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
             for (int a = 0; a < NSYM; ++a) { hi[r][a] = 0.f; lo[r][a] = 0.f; }
         }
         const uint32_t* my_touch = touch + (size_t)rb * touch_words;
-        const int64_t kn = sc.ua() - SymSched::UD * I;  // units of super block I
+        const int64_t kn = sc.ua() - sc.ud() * I;  // units of super block I
         const int64_t kend = min(kn, k + (u1 - u));
         for (; k < kend; ++k, ++u) {
             // chunk of the unit (diagonal: the unit's columns; symmetric: the chunk of its slice)
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
                                                 aS, aS2, rv, hi, lo, ca);
                 // lane l holds column (l + SYM_COLS - 1) mod SYM_COLS of its group of lanes l / SYM_COLS
                 const int mycol = (lane + SYM_COLS - 1) & (SYM_COLS - 1);
-                float* mine = red + (((size_t)(b * SYM_NW + wave) * (WAVE / SYM_COLS) + lane / SYM_COLS) * SYM_COLS +
+                float* mine = red + (((size_t)(b * NW + wave) * (WAVE / SYM_COLS) + lane / SYM_COLS) * SYM_COLS +
                                      mycol) * CS;
 #pragma unroll
                 for (int a = 0; a < NA; ++a) mine[a] = ca[a];
@@ -666,19 +667,19 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
                 // by unit s + 2 only after the barrier of unit s + 1, which every wave reaches after
                 // its reads below.
                 __syncthreads();
-                const float* rbuf = red + (size_t)b * SYM_NW * WAVE * CS;
+                const float* rbuf = red + (size_t)b * NW * WAVE * CS;
                 float* out = colpart + (size_t)(sc.base_sym(I) + k - SBC) * NA * SYM_COLS;
                 for (int e = threadIdx.x; e < NA * SYM_COLS; e += NT) {
                     const int a = e / SYM_COLS, j = e % SYM_COLS;
                     float sum = 0.f;
 #pragma unroll
-                    for (int w = 0; w < SYM_NW * (WAVE / SYM_COLS); ++w) sum += rbuf[(w * SYM_COLS + j) * CS + a];
+                    for (int w = 0; w < NW * (WAVE / SYM_COLS); ++w) sum += rbuf[(w * SYM_COLS + j) * CS + a];
                     out[e] = sum;
                 }
                 ++nsym;
             }
         }
-        float* o = part + ((size_t)(g + I) * SYM_NW + wave) * NA * ROWB + lane;
+        float* o = part + ((size_t)(g + I) * NW + wave) * NA * ROWB + lane;
 #pragma unroll
         for (int r = 0; r < RPL; ++r)
 #pragma unroll
@@ -688,27 +689,36 @@ __global__ __launch_bounds__(WAVE * SYM_NW) __attribute__((amdgpu_waves_per_eu(4
     }
 }
 
+template <int NW>
 static size_t pair_sym_lds_bytes(bool grad) {
-    return sizeof(float) * (grad ? sym_lds_floats<true>() : sym_lds_floats<false>());
+    return sizeof(float) * (grad ? sym_lds_floats<true, NW>() : sym_lds_floats<false, NW>());
 }
 
-int pair_sym_blocks_per_cu(bool grad) {
+template <int NW>
+static int sym_blocks_per_cu(bool grad) {
     int nb = 0;
-    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<true>, WAVE * SYM_NW,
-                                                                       pair_sym_lds_bytes(true))
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<false>, WAVE * SYM_NW,
-                                                                       pair_sym_lds_bytes(false));
+    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<true, NW>, WAVE * NW,
+                                                                       pair_sym_lds_bytes<NW>(true))
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_kernel<false, NW>, WAVE * NW,
+                                                                       pair_sym_lds_bytes<NW>(false));
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// Fp padded faces (a multiple of SB); W work-groups in equal parts, plus `tail` work-groups of
-// about one unit each at the end (dropped when that would be more than half the cost)
-SymSched make_sym_sched(int64_t Fp, int W, int tail) {
+// resident work-groups per CU of the symmetric kernel with nw waves per work-group (1, 2 or 4)
+int pair_sym_blocks_per_cu(bool grad, int nw) {
+    return nw == 1 ? sym_blocks_per_cu<1>(grad) : nw == 2 ? sym_blocks_per_cu<2>(grad) : sym_blocks_per_cu<4>(grad);
+}
+
+// Fp padded faces (a multiple of nw * ROWB); W work-groups of nw waves in equal parts, plus `tail`
+// work-groups of about one unit each at the end (dropped when that would be more than half the cost)
+SymSched make_sym_sched(int64_t Fp, int W, int tail, int nw) {
     SymSched sc;
-    sc.nsb = (int)(Fp / SB);
+    sc.nw = nw;
+    sc.sbc = nw * ROWB / CHUNK;
+    sc.nsb = (int)(Fp / ((int64_t)nw * ROWB));
     sc.nch = (int)(Fp / CHUNK);
     sc.U = sc.base(sc.nsb);
-    sc.C = (int64_t)SYM_COST * sc.U + (int64_t)(DIAG_COST - SYM_COST) * SBC * sc.nsb;
+    sc.C = (int64_t)SYM_COST * sc.U + (int64_t)(DIAG_COST - SYM_COST) * sc.sbc * sc.nsb;
     const int64_t Ct = (int64_t)SYM_COST * std::max(tail, 0);
     if (tail > 0 && 2 * Ct <= sc.C && (int64_t)W + tail <= sc.U) {
         sc.W1 = std::max(W, 1);
@@ -723,21 +733,31 @@ SymSched make_sym_sched(int64_t Fp, int W, int tail) {
 }
 
 int64_t sym_part_floats(const SymSched& sc, bool grad) {
-    return ((int64_t)sc.W + sc.nsb) * SYM_NW * (grad ? NSYM : 1) * ROWB;
+    return ((int64_t)sc.W + sc.nsb) * sc.nw * (grad ? NSYM : 1) * ROWB;
 }
 int64_t sym_colpart_floats(const SymSched& sc, bool grad) {
     return sc.base_sym(sc.nsb) * (grad ? NSYM : 1) * SYM_COLS;
 }
 
+template <int NW>
+static void launch_sym_nw(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                          const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
+                          int* first, hipStream_t st) {
+    if (grad)
+        hipLaunchKernelGGL((pair_sym_kernel<true, NW>), dim3(sc.W), dim3(WAVE * NW), pair_sym_lds_bytes<NW>(true), st,
+                           cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
+    else
+        hipLaunchKernelGGL((pair_sym_kernel<false, NW>), dim3(sc.W), dim3(WAVE * NW), pair_sym_lds_bytes<NW>(false),
+                           st, cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
+}
+
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
                            int* first, hipStream_t st) {
-    if (grad)
-        hipLaunchKernelGGL((pair_sym_kernel<true>), dim3(sc.W), dim3(WAVE * SYM_NW), pair_sym_lds_bytes(true), st,
-                           cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
-    else
-        hipLaunchKernelGGL((pair_sym_kernel<false>), dim3(sc.W), dim3(WAVE * SYM_NW), pair_sym_lds_bytes(false), st,
-                           cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
+    if (sc.nw == 1) launch_sym_nw<1>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
+    else if (sc.nw == 2) launch_sym_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
+    else if (sc.nw == 4) launch_sym_nw<4>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

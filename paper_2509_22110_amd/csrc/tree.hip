@@ -527,14 +527,37 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LEARNED
     for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
     int cnt = 0;
     const int4 nov = make_int4(0, 0, 0, 0);
-    // far clusters: one pseudo-face each, its record loaded once for the wave
-    for (uint32_t j = wave; j < L.y; j += NW) {
-        const int kk = (int)e[cap - 1 - j];
-        const NodeRec nd = nodes[kk];
-        const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
-        ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
-        if constexpr (LEARNED) mlp_correction(W, nd, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
-        if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+    // far clusters: one pseudo-face each
+    if constexpr (LEARNED) {
+        for (uint32_t j = wave; j < L.y; j += NW) {
+            const int kk = (int)e[cap - 1 - j];
+            const NodeRec nd = nodes[kk];
+            const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
+            ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+            mlp_correction(W, nd, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
+            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        }
+    } else {
+        // the wave's entries (j = wave, wave + NW, ...) 64 at a time: every lane fetches one
+        // entry's record (independent loads in flight together), the records are staged in LDS
+        // and read back one by one at a wave-uniform address (a broadcast read); fetching them one
+        // at a time left the wave waiting on two dependent loads per cluster
+        __shared__ NodeRec fst[NW][64];
+        const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
+        for (uint32_t base = 0; base < nfw; base += 64) {
+            const uint32_t m = nfw - base < 64u ? nfw - base : 64u;
+            NodeRec nl = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if ((uint32_t)lane < m) nl = nodes[e[cap - 1 - ((uint32_t)wave + NW * (base + (uint32_t)lane))]];
+            lds_phase();  // the previous batch's reads of fst come first
+            fst[wave][lane] = nl;
+            lds_phase();  // the reads below see every lane's record
+            for (uint32_t k = 0; k < m; ++k) {
+                const NodeRec nd = fst[wave][k];
+                const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
+                ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+                if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+            }
+        }
     }
     // near nodes: exact pairs over their faces, without the shared-vertex test when their vertex
     // ball cannot meet the block's (conservative margin for the FP32 distance)

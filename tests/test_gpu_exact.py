@@ -216,17 +216,20 @@ def _sym_cases():
 
 @pytest.mark.parametrize("name,X,F", list(_sym_cases()), ids=lambda v: v if isinstance(v, str) else "")
 @pytest.mark.parametrize("waves", [0, 1, 7, 100000])
-def test_symmetric_kernel(name, X, F, waves):
-    """The symmetric pair kernel (default for (6, 12)) and the row-only kernel against the oracle,
-    for several work-group counts (uneven ranges, empty ranges, one work-group for everything)."""
+@pytest.mark.parametrize("nw", [1, 2, 4])
+def test_symmetric_kernel(name, X, F, waves, nw):
+    """The symmetric pair kernel (default for (6, 12)) with work-groups of 1, 2 and 4 waves, and the
+    row-only kernel, against the oracle, for several work-group counts (uneven ranges, empty ranges,
+    one work-group for everything)."""
     T = tpe()
     Eo, Go = oracle.gradient(X, F)
     Xd, Fd = upload(X, F)
     ctx = T.context(Xd.device)
     ctx.set_option(T.OPT_TARGET_WAVES, waves)
+    ctx.set_option(T.OPT_SYM_WAVES, nw)
     out = {}
     try:
-        for sym in (1, 0):
+        for sym in ((1, 0) if nw == 4 else (1,)):
             ctx.set_option(T.OPT_SYMMETRIC, sym)
             E, G = T.gradient(Xd, Fd)
             Ee = T.energy(Xd, Fd)
@@ -234,10 +237,20 @@ def test_symmetric_kernel(name, X, F, waves):
     finally:
         ctx.set_option(T.OPT_SYMMETRIC, 1)
         ctx.set_option(T.OPT_TARGET_WAVES, 0)
+        ctx.set_option(T.OPT_SYM_WAVES, 0)
     for sym, (E, G, Ee) in out.items():
         eE, eEe, eG = rel_energy(E, Eo), rel_energy(Ee, Eo), rel_grad_maxnorm(G, Go)
-        log(name, "waves", waves, "symmetric", sym, "rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
+        log(name, "waves", waves, "nw", nw, "symmetric", sym, "rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
         assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
+
+
+def test_symmetric_waves_option_rejects_other_values():
+    T = tpe()
+    import torch
+    ctx = T.context(torch.device("cuda", 0))
+    for bad in (3, 8, -1):
+        with pytest.raises(T.TPEError):
+            ctx.set_option(T.OPT_SYM_WAVES, bad)
 
 
 def test_pair_count():
