@@ -41,19 +41,6 @@ HBM_PEAK_GBS = 8000.0
 # geometry, vertex ids, corner positions in; three FP64 corner gradients out) + gather ~98 (corner
 # gradients and indices in, vertex gradient out)
 FINALIZE_GATHER_BYTES_PER_FACE = 276 + 98
-SYM_MAX_COLPART_BYTES = 64 << 30
-
-
-def sym_colpart_bytes(nF, na=8):
-    """Bytes of the symmetric pair kernel's column partial sums, which the merge reads once: one
-    FP32 sum per (symmetric unit, column, accumulator); super blocks of 512 faces, units of 64
-    columns, the 8 chunks of a super block's own faces excluded.  0 when the library takes the
-    row-only kernel (above its 64 GiB cap)."""
-    fp = -(-nF // 512) * 512
-    nsb, nch = fp // 512, fp // 64
-    units = nsb * (nch - 8) - 8 * nsb * (nsb - 1) // 2
-    b = units * na * 64 * 4
-    return b if b <= SYM_MAX_COLPART_BYTES else 0
 
 
 def parse():
@@ -200,14 +187,15 @@ def farfield_leg(args, T, torch, dev, ex):
     ctx.set_option(T.OPT_KERNEL_TIMING, 0)
     fg_ms /= max(fg_n, 1)
     alg = FINALIZE_GATHER_BYTES_PER_FACE * cfg.nF
-    cp = sym_colpart_bytes(cfg.nF)
+    _, sym_nw, cp, _ = ctx.exact_plan(cfg.nF, cfg.V, True)  # the library's own choice and sizes
     tr = read_summary(f"gather_passes_{args.config}_traffic.txt", "finalize")
     fg = {"kernels": "sym_merge_kernel + finalize_kernel<true> + vertex_gather", "bound": "hbm",
           "ms": round(fg_ms, 4), "algorithmic_bytes": alg, "bytes_per_face": FINALIZE_GATHER_BYTES_PER_FACE,
           "achieved": round(alg / (fg_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": round(alg / (fg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
           "overhead": {"what": "the symmetric pair kernel's column partial sums, read once by the merge",
-                       "bytes": cp, "with_overhead_gbs": round((alg + cp) / (fg_ms * 1e-3) / 1e9, 1)},
+                       "bytes": cp, "sym_waves_per_workgroup": sym_nw,
+                       "with_overhead_gbs": round((alg + cp) / (fg_ms * 1e-3) / 1e9, 1)},
           "traffic": summary_float(tr, "bytes_per_call")}
     t_tree, tree = timed(lambda: T.build_tree(X, F, leaf=32), args.ff_reps)
     g0 = float(G0.abs().max())

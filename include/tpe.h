@@ -95,8 +95,8 @@ typedef enum {
                                  (tpe_destroy frees it) */,
     TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2 or 4 (super
                                  blocks of 128, 256 or 512 faces); 0 (default): the fewest whose
-                                 column partial sums fit in 16 GiB (1 up to about 370,000 faces,
-                                 then 2, then 4).  Fewer waves wait less at the work-group's
+                                 column partial sums fit in 8 GiB (1 up to about 262,000 faces,
+                                 then 2 up to about 370,000, then 4; tpe_exact_plan tells).  Fewer waves wait less at the work-group's
                                  barriers but write proportionally more partial sums.  Results
                                  agree to rounding */
 } tpe_option;
@@ -217,7 +217,10 @@ int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
  * evaluates the lists; a monopole call (mlp NULL) launches the blocks with the most work first.
  * That changes only when blocks run, never what they compute.  The tree keeps the work of each
  * block of its last call (a device array, written by every call; calls that share one tree on
- * several streams at once are still correct).  *out is owned by the caller (tpe_tree_destroy).
+ * several streams at once are still correct), the vertex -> (face, corner) lists of the gradient's
+ * vertex gather in tree order (they depend only on F and the order; 12 B per face) and a checksum
+ * of F: every far-field call recomputes the checksum of the F it is given and fails with
+ * TPE_ERR_INVALID_ARG if it differs.  *out is owned by the caller (tpe_tree_destroy).
  * Synchronises the stream. */
 int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                    int32_t leaf_size, tpe_tree** out);
@@ -256,7 +259,8 @@ int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64
  * lists every block's far clusters and near nodes in its scratch arena (at most ceil(nF / leaf)
  * entries per block, within 8 GiB in all; TPE_ERR_OOM beyond that, which only meshes of several
  * million faces at small theta reach).  E_dev and/or G_dev (device) may be NULL but not
- * both.  X, V, F, nF must describe the mesh the tree was built for (same size, same faces). */
+ * both.  X, V, F, nF must describe the mesh the tree was built for (same size, same faces: a face
+ * list whose checksum differs from the tree's fails the call with TPE_ERR_INVALID_ARG). */
 int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
                  const int32_t* F, int64_t nF, double q, double p, double scale, double theta,
                  const tpe_mlp* mlp, double* E_dev, double* G_dev);
@@ -376,6 +380,13 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
  * far cluster pairs, [1] = exactly evaluated face pairs, the rest 0.  Host array of 6 int64.
  * Synchronises the stream. */
 int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
+
+/* How tpe_gradient (grad = 1) or tpe_energy (grad = 0) would run a mesh of nF faces and V vertices
+ * with the context's current options (host only, nothing is launched): out_host[0] = 1 if the
+ * symmetric pair kernel is taken, [1] = its waves per work-group (0 for the row-only kernel),
+ * [2] = the bytes of its column partial sums (read back by the merge), [3] = the scratch arena the
+ * call needs.  Host array of 4 int64. */
+int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host);
 
 /* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed
  * duration of the dominant-kernel launches (the exact pair kernel, or the far-field traversal) recorded since the last call and *count (host) <- their

@@ -74,6 +74,7 @@ def lib():
             "tpe_conf_gradient": ([P, P, I64, P, I64, P, I64, P, I64, D, D, D, P, P], I),
             "tpe_pair_count": ([P, P, I64, I64, ctypes.POINTER(I64)], I),
             "tpe_kernel_time": ([P, ctypes.POINTER(D), ctypes.POINTER(I64)], I),
+            "tpe_exact_plan": ([P, I64, I64, ctypes.c_int32, P], I),
             "tpe_build_tree": ([P, P, I64, P, I64, ctypes.c_int32, ctypes.POINTER(P)], I),
             "tpe_tree_destroy": ([P], I),
             "tpe_tree_order": ([P, P, P, I64], I),
@@ -134,6 +135,13 @@ class _Ctx:
         ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
         self.check(lib().tpe_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def exact_plan(self, nF: int, V: int, grad: bool = True):
+        """(symmetric kernel taken, its waves per work-group, bytes of its column partial sums,
+        scratch bytes) of an exact call on a mesh of nF faces and V vertices (see tpe_exact_plan)."""
+        out = (ctypes.c_int64 * 4)()
+        self.check(lib().tpe_exact_plan(self.h, int(nF), int(V), 1 if grad else 0, out))
+        return bool(out[0]), int(out[1]), int(out[2]), int(out[3])
 
     def farfield_stats(self):
         """(far clusters, near columns, visited nodes, target blocks, max near columns of a block,

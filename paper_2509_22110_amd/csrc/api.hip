@@ -22,7 +22,7 @@ namespace tpe {
 hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st);
 hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox, uint32_t* flags,
-                       hipStream_t st);
+                       hipStream_t st, const uint32_t* expect = nullptr);
 hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, int Q, const uint32_t* bbox,
                          int bits, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
@@ -80,10 +80,11 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
 // of HBM; if the allocation fails the call runs the row-only kernel instead
 constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
 // Work-groups of 1 or 2 waves (super blocks of 128 or 256 faces) run the symmetric kernel faster
-// than 4 (each wave waits less at the work-group's barriers: 63.8 / 65.2 / 69.9 ms at 327,680 faces)
-// but write 4 or 2 times the column partials, which the merge reads back; the fewest waves whose
-// partials fit in this budget are taken (327,680 faces: 1 wave, 12.5 GiB), else 4
-constexpr int64_t SYM_FAST_COLPART_BYTES = (int64_t)16 << 30;
+// than 4 (each wave waits less at the work-group's barriers: 64.8 / 65.0 / 70.3 ms at 327,680 faces)
+// but write 4 or 2 times the column partials, which the merge reads back (the whole step: 67.7 /
+// 66.6 / 71.3 ms); the fewest waves whose partials fit in this budget are taken (20,480 faces:
+// 1 wave; 327,680 faces: 2, 6.2 GiB), else 4
+constexpr int64_t SYM_FAST_COLPART_BYTES = (int64_t)8 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
                             hipStream_t st);
@@ -97,7 +98,7 @@ hipError_t build_kd_order(const double* X, int64_t V, const int32_t* F, int64_t 
 size_t tree_node_bytes(int H);
 size_t tree_rec_bytes(int H);
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
-                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
+                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs, bool mom2,
                                hipStream_t st);
 hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const double* c64, const double* X,
                                   const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF, float theta,
@@ -109,8 +110,6 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
                            uint32_t* flags, uint32_t* const sort[6], hipStream_t st);
 int64_t ff_list_cap(int64_t n, int leaf);
-hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
-                           uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -240,6 +239,11 @@ struct tpe_tree {
     int64_t n = 0;             // items: nF faces, or nF Q points
     uint32_t* perm = nullptr;  // sorted position -> input item (face f, or point r = Q f + point) (device, n entries)
     uint32_t* work = nullptr;  // work of each 64-item target block in the last far-field walk (device, (n + 63) / 64)
+    // flat trees: the vertex -> (sorted face, corner) lists of the gather (3 nF slots, V + 1
+    // offsets), which depend only on F and the order, and the checksum of F they were built from
+    uint32_t* voff = nullptr;
+    uint32_t* vlist = nullptr;
+    uint32_t* fsum = nullptr;
 };
 
 namespace {
@@ -377,7 +381,7 @@ void layout(Plan& P, char* base, bool grad) {
     P.vtmp = c.take<uint32_t>(ns);
     P.hist = c.take<uint32_t>((size_t)radix_hist_words(ns));
     P.hoff = c.take<uint32_t>((size_t)radix_hist_words(ns));
-    P.bbox = c.take<uint32_t>(8);
+    P.bbox = c.take<uint32_t>(BBOX_WORDS);
     P.counter = c.take<unsigned long long>(1);
     // one contiguous zero-initialised region
     P.zero_begin = c.take<uint32_t>(0);
@@ -562,6 +566,8 @@ int report_flags(tpe_ctx* ctx) {
     if (f & FLAG_NONFINITE)
         return fail(ctx, TPE_ERR_NONFINITE, "non-finite input or result (coincident non-adjacent centroids?)");
     if (f & FLAG_DEGENERATE) return fail(ctx, TPE_ERR_DEGENERATE, "degenerate face (area <= 1e-300)");
+    if (f & FLAG_TREE_FACES)
+        return fail(ctx, TPE_ERR_INVALID_ARG, "the faces differ from those the tree was built with");
     if (f & FLAG_LISTS)
         return fail(ctx, TPE_ERR_OOM, "far-field interaction lists exceed their scratch (theta too small for this mesh)");
     return TPE_OK;
@@ -722,21 +728,36 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
 // Device arrays of a new tree: the permutation (copied from the build's sort) and the per-block
 // work record of the far-field walk (zero: the first walk runs in tree order).  Frees the tree on
 // failure.
-int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out) {
+void free_tree(tpe_tree* t) {
+    for (uint32_t* p : {t->perm, t->work, t->voff, t->vlist, t->fsum})
+        if (p) (void)hipFree(p);
+    delete t;
+}
+
+// voff, vlist, fsum (device, nullable: a tree over curved elements keeps none): the gather's vertex
+// lists (V + 1 offsets, 3 n slots) and the face-list checksum, copied into the tree
+int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out, const uint32_t* voff = nullptr,
+                const uint32_t* vlist = nullptr, const uint32_t* fsum = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t nb = (t->n + 63) / 64;
     auto drop = [&](int code) {
-        if (t->perm) (void)hipFree(t->perm);
-        if (t->work) (void)hipFree(t->work);
-        delete t;
+        free_tree(t);
         return code;
     };
     if (hipMalloc(&t->perm, t->n * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&t->work, nb * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc(&t->work, nb * sizeof(uint32_t)) != hipSuccess ||
+        (voff && (hipMalloc(&t->voff, (t->V + 1) * sizeof(uint32_t)) != hipSuccess ||
+                  hipMalloc(&t->vlist, 3 * t->n * sizeof(uint32_t)) != hipSuccess ||
+                  hipMalloc(&t->fsum, sizeof(uint32_t)) != hipSuccess))) {
         (void)hipGetLastError();
         return drop(fail(ctx, TPE_ERR_OOM, "tree allocation failed"));
     }
     hipError_t e = hipMemcpyAsync(t->perm, perm, t->n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && voff)
+        e = hipMemcpyAsync(t->voff, voff, (t->V + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && voff)
+        e = hipMemcpyAsync(t->vlist, vlist, 3 * t->n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && voff) e = hipMemcpyAsync(t->fsum, fsum, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_fill(t->work, 0u, nb, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return drop(hip_fail(ctx, e, "tree set-up"));
@@ -966,6 +987,10 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
     HIPCHK(build_kd_order(X, V, F, nF, 0, leaf_size, H, P.cen4, P.nbox, P.vals, P.keys, P.ktmp, P.vtmp, P.hist,
                           P.hoff, st));
+    // the gather's vertex lists in tree order, kept with the tree (they depend only on F and the order)
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, P.vals, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+                          ctx->dflags, st));
+    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, st));
     tpe_tree* t = new tpe_tree();
     t->device = ctx->device;
     t->nF = nF;
@@ -973,7 +998,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     t->leaf = leaf_size;
     t->H = tree_height(nF, leaf_size);
     t->n = nF;
-    return finish_tree(ctx, t, P.vals, out);
+    return finish_tree(ctx, t, P.vals, out, P.voff, P.list, P.bbox + BBOX_FSUM);
 }
 
 int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, int32_t leaf_size,
@@ -1043,7 +1068,8 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     HIPCHK(launch_bbox(X, V, F10, P3_NODES, nF, P.bbox, ctx->dflags, st));
     HIPCHK(launch_p3_records(X, V, F10, nF, Q, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                              ctx->dflags, st));
-    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, n, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, n, tree->leaf, tree->H, P.nodes64, P.recs,
+                               mlp != nullptr, st));
     if (G_dev) {  // the node CSR only serves the gather: built on the side stream during the walk
         HIPCHK(hipEventRecord(ctx->fork, st));
         HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
@@ -1056,8 +1082,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
-    {
+    {  // the walk writes all six counts of ctx->dstats
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
@@ -1092,9 +1117,7 @@ int tpe_tree_order(tpe_ctx* ctx, const tpe_tree* tree, uint32_t* perm_dev, int64
 int tpe_tree_destroy(tpe_tree* t) {
     if (!t) return TPE_ERR_INVALID_ARG;
     DeviceGuard dg(t->device);
-    if (t->perm) (void)hipFree(t->perm);
-    if (t->work) (void)hipFree(t->work);
-    delete t;
+    free_tree(t);
     return TPE_OK;
 }
 
@@ -1123,22 +1146,18 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    // the face list must be the tree's (its gather lists are kept with the tree)
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st, tree->fsum));
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
-    // the vertex CSR only serves the gather: it is built on the side stream during the walk
-    HIPCHK(hipEventRecord(ctx->fork, st));
-    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, ctx->side));
-    HIPCHK(hipEventRecord(ctx->join, ctx->side));
-    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs,
+                               mlp != nullptr, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    HIPCHK(launch_fill(reinterpret_cast<uint32_t*>(ctx->dstats), 0u, 12, st));
-    {
+    {  // the walk writes all six counts of ctx->dstats
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
@@ -1149,8 +1168,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
                            P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
-    HIPCHK(hipStreamWaitEvent(st, ctx->join, 0));
-    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
+    if (G_dev) HIPCHK(launch_gather(tree->voff, tree->vlist, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -1180,15 +1198,12 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    // the face list must be the tree's (its gather lists are kept with the tree)
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st, tree->fsum));
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
-    // the vertex CSR only serves the gather: it is built on the side stream during the walk
-    HIPCHK(hipEventRecord(ctx->fork, st));
-    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-    HIPCHK(launch_adjacency(P.colv, nF, V, P.cnt, P.voff, P.cursor, P.list, P.scanws, ctx->side));
-    HIPCHK(hipEventRecord(ctx->join, ctx->side));
-    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, false,
+                               st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -1204,8 +1219,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,
                            P.corner, P.epart, ctx->dflags, E_dev, G_dev ? &en : nullptr, st));
-    HIPCHK(hipStreamWaitEvent(st, ctx->join, 0));
-    if (G_dev) HIPCHK(launch_gather(P.voff, P.list, V, P.corner, G_dev, en, st));
+    if (G_dev) HIPCHK(launch_gather(tree->voff, tree->vlist, V, P.corner, G_dev, en, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->sync_checks) return report_flags(ctx);
     return TPE_OK;
@@ -1231,10 +1245,11 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
     layout(P, ctx->arena, true);
     hipStream_t st = ctx->stream;
     HIPCHK(launch_init(P.zero_begin, P.zero_end - P.zero_begin, P.bbox, ctx->sync_checks ? ctx->dflags : nullptr, st));
-    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st));
-    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
+    HIPCHK(launch_bbox(X, V, F, 3, nF, P.bbox, ctx->dflags, st, tree->fsum));
+    HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
-    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, st));
+    HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, true,
+                               st));
     const uint32_t sel = select_prob >= 1.0 ? 0xffffffffu : (uint32_t)(select_prob * 4294967296.0);
     HIPCHK(launch_farfield_samples(P.cols, P.colv, P.c64, X, P.bbox, P.recs, tree->H, tree->leaf, nF, (float)theta,
                                    (uint32_t)(seed ^ (seed >> 32)), sel, quota, max_cluster_faces, P.balls, feats,
@@ -1480,6 +1495,18 @@ int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count) {
     *total_ms = tot;
     *count = (int64_t)(ctx->ev_used / 2);
     ctx->ev_used = 0;
+    return TPE_OK;
+}
+
+int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host) {
+    if (!ctx) return TPE_ERR_INVALID_ARG;
+    if (!out_host || nF < 1 || V < 1 || (grad != 0 && grad != 1)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
+    Plan P;
+    plan(P, ctx, nF, V, grad != 0, -1, 0, 0, ctx->quad, ctx->symmetric, false);
+    out_host[0] = P.sym ? 1 : 0;
+    out_host[1] = P.sym ? P.ssc.nw : 0;
+    out_host[2] = P.sym ? sym_colpart_floats(P.ssc, grad != 0) * (int64_t)sizeof(float) : 0;
+    out_host[3] = (int64_t)P.bytes;
     return TPE_OK;
 }
 

@@ -11,6 +11,7 @@ enum : uint32_t {
     FLAG_DEGENERATE = 2u,  // a face with area <= 1e-300
     FLAG_NONFINITE = 4u,   // non-finite coordinate, or a non-finite accumulated result
     FLAG_LISTS = 8u,       // the dual-tree interaction lists outgrew their scratch
+    FLAG_TREE_FACES = 16u, // the face list differs from the one the tree was built with
 };
 
 // Geometry of the exact all-pairs kernel.
@@ -202,6 +203,15 @@ struct EnergyOut {
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// The centroid bounding box's words: bbox[0..5] the box, bbox[BBOX_TICKET] the reduction's ticket,
+// bbox[BBOX_FSUM] the checksum of the face list, bbox[BBOX_PART + 8 g ...] the slot of work-group g
+// (BBOX_SLOTS of them)
+constexpr int BBOX_SLOTS = 256;
+constexpr int BBOX_TICKET = 6;
+constexpr int BBOX_FSUM = 7;
+constexpr int BBOX_PART = 8;
+constexpr int BBOX_WORDS = BBOX_PART + 8 * BBOX_SLOTS;
 
 __device__ __forceinline__ float ordered_to_float(uint32_t u) {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);

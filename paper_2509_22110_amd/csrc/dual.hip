@@ -328,8 +328,8 @@ int64_t dual_entry_cap(int H, int leaf) {
 
 int64_t scan_ws_words(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* ws, hipStream_t st);
-hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
-                           uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st);
+hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* order, const uint4* lst,
+                           unsigned long long* stats, hipStream_t st);
 
 // The whole dual-tree evaluation after the records and tree moments: lists, far clusters, near
 // leaves, downward pass; leaves FP64 row sums in acc64 for the finalize.
@@ -358,10 +358,9 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
     if (nn > 0)
         hipLaunchKernelGGL(dual_far_eval, dim3((unsigned)((nn + 3) / 4)), dim3(256), 0, st, Hd, recs, nodes, off,
                            nnear, nfar, ent, cap, q, p, adj, stats);
-    // leaves with the longest near lists first (work-groups start in launch order); sort: keys, vals,
-    // ktmp, vtmp, hist, hoff of a radix sort of 2^Hd entries
+    // leaves with the longest near lists first (work-groups start in launch order), into sort[1]
     const int64_t nleaf = (int64_t)1 << Hd;
-    hipError_t e = launch_ff_order(nnear + nleaf, nleaf, sort[0], sort[1], sort[2], sort[3], sort[4], sort[5], st);
+    hipError_t e = launch_ff_order(nnear + nleaf, nleaf, sort[1], nullptr, nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dual_near_eval, dim3((unsigned)nleaf, DUAL_SPLIT), dim3(64 * DUAL_NW), 0, st, Hd, span, cols,
                        colv, c64, org, recs, off, nnear, ent, cap, nF, Fp, part, stats, (const uint32_t*)sort[1]);

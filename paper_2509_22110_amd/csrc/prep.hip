@@ -22,29 +22,52 @@ __global__ void fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 }
 
 // One launch that prepares the scratch state of a call: zero [zero, zero+nzero), bbox to
-// (+max x3, 0 x3) in the order-preserving encoding, and optionally the error word.
+// (+max x3, 0 x3) in the order-preserving encoding with its ticket word at 0, and optionally the
+// error word.
 __global__ void init_scratch(uint32_t* __restrict__ zero, int64_t nzero, uint32_t* __restrict__ bbox,
                              uint32_t* __restrict__ flags) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < 6) bbox[i] = i < 3 ? 0xffffffffu : 0u;
-    if (i == 6 && flags) flags[0] = 0u;
+    if (i == 6) bbox[BBOX_TICKET] = 0u;
+    if (i == 7 && flags) flags[0] = 0u;
     for (; i < nzero; i += (int64_t)gridDim.x * blockDim.x) zero[i] = 0u;
 }
 
-// bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids (FP32); must start at
-// (0xffffffff x3, 0 x3).  Also validates indices / coordinates and flags errors.  Grid-stride
-// loop, reduction over the work-group, then six atomics per work-group.  Face f's corners are
-// F[fs f + 0..2] (fs = 3 for triangles, 10 for curved cubic elements, whose centroid here is that
-// of their corners).
+// Checksum term of face-list entry j (value v): a bijective 32-bit mix (MurmurHash3's finaliser)
+// of v and its position; the checksum is the sum of the terms modulo 2^32, whatever the order.
+__device__ __forceinline__ uint32_t face_entry_hash(uint32_t v, uint32_t j) {
+    uint32_t h = v ^ (j * 0x9e3779b9u);
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// bbox[0..2] = ordered(min), bbox[3..5] = ordered(max) of face centroids (FP32), merged into what
+// bbox holds (it starts at (0xffffffff x3, 0 x3); a second launch adds a second surface), and
+// bbox[BBOX_FSUM] = the checksum of the face list (its three corners per face); with `expect`, a
+// checksum that differs from *expect sets FLAG_TREE_FACES.  Also validates indices / coordinates
+// and flags errors.  Grid-stride loop and a reduction over the
+// work-group, whose result goes to its slot of bbox[BBOX_PART...]; the work-group that takes the
+// last ticket (bbox[BBOX_TICKET]) reduces the slots in slot order, writes the box and resets the
+// ticket.  (Six same-address atomics per work-group cost about 11 ns each: with 1,024 work-groups
+// they took 70 us.)  Face f's corners are F[fs f + 0..2] (fs = 3 for triangles, 10 for curved
+// cubic elements, whose centroid here is that of their corners).
+static_assert(BBOX_SLOTS <= 256, "one slot per thread of the last work-group");
 __global__ __launch_bounds__(256) void face_bbox(const double* __restrict__ X, int64_t V,
                                                   const int32_t* __restrict__ F, int fs, int64_t nF,
-                                                  uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags) {
+                                                  uint32_t* __restrict__ bbox, uint32_t* __restrict__ flags,
+                                                  const uint32_t* __restrict__ expect) {
     __shared__ float smn[4][3], smx[4][3];
-    __shared__ uint32_t sfl[4];
+    __shared__ uint32_t sfl[4], ssum[4];
+    __shared__ bool last;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    uint32_t fl = 0;
+    uint32_t fl = 0, sum = 0;
     for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nF; f += (int64_t)gridDim.x * blockDim.x) {
         int32_t v[3] = {F[fs * f], F[fs * f + 1], F[fs * f + 2]};
+        for (int k = 0; k < 3; ++k) sum += face_entry_hash((uint32_t)v[k], (uint32_t)(3 * f + k));
         double c[3] = {0, 0, 0};
         bool ok = true;
         for (int k = 0; k < 3; ++k) {
@@ -70,24 +93,77 @@ __global__ __launch_bounds__(256) void face_bbox(const double* __restrict__ X, i
         }
         mn[d] = a; mx[d] = b;
     }
-    for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        fl |= __shfl_xor(fl, off);
+        sum += __shfl_xor(sum, off);
+    }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         for (int d = 0; d < 3; ++d) { smn[w][d] = mn[d]; smx[w][d] = mx[d]; }
         sfl[w] = fl;
+        ssum[w] = sum;
+    }
+    __syncthreads();
+    uint32_t* part = bbox + BBOX_PART;
+    if (threadIdx.x == 0) {
+        uint32_t* my = part + 8 * (size_t)blockIdx.x;
+        for (int d = 0; d < 3; ++d) {
+            const float a = fminf(fminf(smn[0][d], smn[1][d]), fminf(smn[2][d], smn[3][d]));
+            const float b = fmaxf(fmaxf(smx[0][d], smx[1][d]), fmaxf(smx[2][d], smx[3][d]));
+            my[d] = a <= b ? float_to_ordered(a) : 0xffffffffu;  // empty: the identities of min / max
+            my[3 + d] = a <= b ? float_to_ordered(b) : 0u;
+        }
+        my[6] = sfl[0] | sfl[1] | sfl[2] | sfl[3];
+        my[7] = ssum[0] + ssum[1] + ssum[2] + ssum[3];
+        __threadfence();  // the slot is visible before the ticket is taken
+        last = atomicAdd(&bbox[BBOX_TICKET], 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;  // uniform over the work-group
+    __threadfence();
+    // the slots, one per thread (gridDim.x <= BBOX_SLOTS <= blockDim.x), reduced over the work-group
+    uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u}, f = 0u, cs = 0u;
+    if (threadIdx.x < gridDim.x) {
+        const uint32_t* q = part + 8 * (size_t)threadIdx.x;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = __hip_atomic_load(q + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            hi[d] = __hip_atomic_load(q + 3 + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        f = __hip_atomic_load(q + 6, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cs = __hip_atomic_load(q + 7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t a = __shfl_xor(lo[d], off), b = __shfl_xor(hi[d], off);
+            lo[d] = a < lo[d] ? a : lo[d];
+            hi[d] = b > hi[d] ? b : hi[d];
+        }
+        f |= __shfl_xor(f, off);
+        cs += __shfl_xor(cs, off);
+    }
+    __shared__ uint32_t rlo[4][3], rhi[4][3], rfl[4], rcs[4];
+    if ((threadIdx.x & 63) == 0) {
+        for (int d = 0; d < 3; ++d) { rlo[w][d] = lo[d]; rhi[w][d] = hi[d]; }
+        rfl[w] = f;
+        rcs[w] = cs;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t f = sfl[0] | sfl[1] | sfl[2] | sfl[3];
         for (int d = 0; d < 3; ++d) {
-            float a = fminf(fminf(smn[0][d], smn[1][d]), fminf(smn[2][d], smn[3][d]));
-            float b = fmaxf(fmaxf(smx[0][d], smx[1][d]), fmaxf(smx[2][d], smx[3][d]));
-            if (a <= b) {
-                atomicMin(&bbox[d], float_to_ordered(a));
-                atomicMax(&bbox[3 + d], float_to_ordered(b));
+            uint32_t a = bbox[d], b = bbox[3 + d];  // what an earlier launch left (or the initial box)
+            for (int k = 0; k < 4; ++k) {
+                a = rlo[k][d] < a ? rlo[k][d] : a;
+                b = rhi[k][d] > b ? rhi[k][d] : b;
             }
+            bbox[d] = a;
+            bbox[3 + d] = b;
         }
-        if (f) atomicOr(flags, f);
+        uint32_t ff = rfl[0] | rfl[1] | rfl[2] | rfl[3];
+        const uint32_t total = rcs[0] + rcs[1] + rcs[2] + rcs[3];
+        bbox[BBOX_FSUM] = total;
+        if (expect && total != *expect) ff |= FLAG_TREE_FACES;
+        bbox[BBOX_TICKET] = 0u;  // for a second launch on the same box
+        if (ff) atomicOr(flags, ff);
     }
 }
 
@@ -426,10 +502,13 @@ hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* 
 }
 
 // fs: ints per face in F (3 for triangles; 10 for curved cubic elements, corners first)
+// expect (nullable, device): the checksum the face list must have (FLAG_TREE_FACES otherwise)
 hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox,
-                       uint32_t* flags, hipStream_t st) {
-    int g = (int)std::min<int64_t>(nblk(nF, 256), 64);
-    hipLaunchKernelGGL(face_bbox, dim3(g), dim3(256), 0, st, X, V, F, fs, nF, bbox, flags);
+                       uint32_t* flags, hipStream_t st, const uint32_t* expect) {
+    // up to BBOX_SLOTS work-groups (a few faces per thread): the loads of a face's corners are
+    // dependent gathers, so the pass is bound by latency, not by its few bytes
+    int g = (int)std::max<int64_t>(1, std::min<int64_t>(nblk(nF, 256), BBOX_SLOTS));
+    hipLaunchKernelGGL(face_bbox, dim3(g), dim3(256), 0, st, X, V, F, fs, nF, bbox, flags, expect);
     return hipGetLastError();
 }
 

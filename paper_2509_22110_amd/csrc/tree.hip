@@ -39,7 +39,7 @@ __device__ __forceinline__ float round_up_f(double v) {
     return (double)f >= v ? f : nextafterf(f, INFINITY);
 }
 
-__device__ void write_mom(const NodeF64& n, NodeMom* mom) {
+__device__ __forceinline__ void write_mom(const NodeF64& n, NodeMom* mom) {
     NodeMom m = {};
     if (n.A > 0.0) {
         for (int k = 0; k < 6; ++k) {
@@ -52,7 +52,7 @@ __device__ void write_mom(const NodeF64& n, NodeMom* mom) {
 }
 
 // FP32 record of a node: centre relative to the origin o (norm_origin), radius rounded up.
-__device__ void write_rec(const NodeF64& n, const double* o, NodeRec* rec) {
+__device__ __forceinline__ void write_rec(const NodeF64& n, const double* o, NodeRec* rec) {
     NodeRec r;
     const double cx = n.cx - o[0], cy = n.cy - o[1], cz = n.cz - o[2];
     r.cx = (float)cx; r.cy = (float)cy; r.cz = (float)cz;
@@ -76,69 +76,102 @@ __device__ __forceinline__ double wave_max_d(double x) {
     return x;
 }
 
-// One wave per leaf slot j in [0, 2^H): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order, the
-// lanes striding over them; the FP64 sums are reduced across the wave in a fixed order (every
-// lane ends with the same bits: each butterfly step adds the same two values).
+// G lanes per leaf slot j in [0, 2^H) (G = the leaf size rounded up to a power of two, at most 64;
+// 64 / G slots per wave): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order, the group's lanes
+// striding over them; the FP64 sums are reduced across the group in a fixed order (every lane of
+// the group ends with the same bits: each butterfly step adds the same two values).  MOM2: also the
+// second moments (the learned correction's features); the monopole needs A, C, N and r only.
 constexpr int MOM_LEAF_WAVES = 4;
 
+__device__ __forceinline__ double group_sum_d(double x, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+__device__ __forceinline__ double group_max_d(double x, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
+template <bool MOM2>
 __global__ __launch_bounds__(64 * MOM_LEAF_WAVES) void leaf_moments(const double* __restrict__ c64,
                                                                     const double* __restrict__ geo,
                                                                     const int4* __restrict__ colv,
                                                                     const double* __restrict__ X,
                                                                     const uint32_t* __restrict__ bbox, int64_t nF,
-                                                                    int leaf, int H, NodeF64* __restrict__ nodes,
+                                                                    int leaf, int H, int G, NodeF64* __restrict__ nodes,
                                                                     NodeRec* __restrict__ recs,
                                                                     NodeMom* __restrict__ moms) {
     const int lane = threadIdx.x & 63;
-    const int64_t j = blockIdx.x * (int64_t)MOM_LEAF_WAVES + (threadIdx.x >> 6);
     const int64_t nslot = (int64_t)1 << H;
-    if (j >= nslot) return;
+    const int64_t j = (blockIdx.x * (int64_t)MOM_LEAF_WAVES + (threadIdx.x >> 6)) * (64 / G) + lane / G;
+    const int t = lane & (G - 1);
+    if (__builtin_amdgcn_readfirstlane((int)(j - lane / G >= nslot))) return;  // uniform over the wave
     const double s = norm_scale(bbox);
-    NodeF64 n = {};
-    const int64_t f0 = j * leaf, f1 = std::min<int64_t>(nF, f0 + leaf);
+    const int64_t f0 = j < nslot ? j * leaf : 0, f1 = j < nslot ? std::min<int64_t>(nF, f0 + leaf) : 0;
     double A = 0, sx = 0, sy = 0, sz = 0, nx = 0, ny = 0, nz = 0;
-    for (int64_t i = f0 + lane; i < f1; i += 64) {
+    for (int64_t i = f0 + t; i < f1; i += G) {
         const double a = geo[5 * i];
         A += a;
         sx += a * c64[3 * i]; sy += a * c64[3 * i + 1]; sz += a * c64[3 * i + 2];
         nx += a * geo[5 * i + 2]; ny += a * geo[5 * i + 3]; nz += a * geo[5 * i + 4];
     }
-    n.A = wave_sum_d(A);
-    sx = wave_sum_d(sx); sy = wave_sum_d(sy); sz = wave_sum_d(sz);
-    n.nx = wave_sum_d(nx); n.ny = wave_sum_d(ny); n.nz = wave_sum_d(nz);
-    if (n.A > 0.0) {
-        n.cx = sx / n.A; n.cy = sy / n.A; n.cz = sz / n.A;
-        double m2c[6] = {0, 0, 0, 0, 0, 0}, m2n[6] = {0, 0, 0, 0, 0, 0}, r = 0.0;
-        for (int64_t i = f0 + lane; i < f1; i += 64) {
+    NodeF64 n = {};
+    n.A = group_sum_d(A, G);
+    sx = group_sum_d(sx, G); sy = group_sum_d(sy, G); sz = group_sum_d(sz, G);
+    n.nx = group_sum_d(nx, G); n.ny = group_sum_d(ny, G); n.nz = group_sum_d(nz, G);
+    const bool has = n.A > 0.0;  // uniform over the group
+    n.cx = has ? sx / n.A : 0.0; n.cy = has ? sy / n.A : 0.0; n.cz = has ? sz / n.A : 0.0;
+    double m2c[6] = {0, 0, 0, 0, 0, 0}, m2n[6] = {0, 0, 0, 0, 0, 0}, r = 0.0;
+    for (int64_t i = has ? f0 + t : f1; i < f1; i += G) {
+        if constexpr (MOM2) {
             const double a = geo[5 * i];
             sym_add_outer(m2c, a, c64[3 * i] - n.cx, c64[3 * i + 1] - n.cy, c64[3 * i + 2] - n.cz);
             sym_add_outer(m2n, a, geo[5 * i + 2], geo[5 * i + 3], geo[5 * i + 4]);
-            const int4 v = colv[i];
-            const int vv[3] = {v.x, v.y, v.z};
-            for (int k = 0; k < 3; ++k) {
-                if (vv[k] < 0) continue;
-                const double dx = s * X[3 * (int64_t)vv[k]] - n.cx, dy = s * X[3 * (int64_t)vv[k] + 1] - n.cy,
-                             dz = s * X[3 * (int64_t)vv[k] + 2] - n.cz;
-                r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
-            }
         }
-        for (int k = 0; k < 6; ++k) {
-            n.m2c[k] = wave_sum_d(m2c[k]);
-            n.m2n[k] = wave_sum_d(m2n[k]);
+        const int4 v = colv[i];
+        const int vv[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3; ++k) {
+            if (vv[k] < 0) continue;
+            const double dx = s * X[3 * (int64_t)vv[k]] - n.cx, dy = s * X[3 * (int64_t)vv[k] + 1] - n.cy,
+                         dz = s * X[3 * (int64_t)vv[k] + 2] - n.cz;
+            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
         }
-        n.r = wave_max_d(r);
     }
-    if (lane == 0) {
+    if constexpr (MOM2)
+        for (int k = 0; k < 6; ++k) {
+            n.m2c[k] = group_sum_d(m2c[k], G);
+            n.m2n[k] = group_sum_d(m2n[k], G);
+        }
+    n.r = group_max_d(r, G);  // a group without area keeps all zeros: no face added to any sum
+    if (t == 0 && j < nslot) {
         double o[3];
         norm_origin(bbox, o);
-        nodes[nslot + j] = n;
+        store_node<MOM2>(&nodes[nslot + j], n);
         write_rec(n, o, &recs[nslot + j]);
-        write_mom(n, &moms[nslot + j]);
+        if constexpr (MOM2) write_mom(n, &moms[nslot + j]);
     }
 }
 
-// A node from its two children.
-__device__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
+// FP64 node records in global memory, field by field (without MOM2 the second moments are neither
+// read nor written: no reader of such a call looks at them)
+template <bool MOM2>
+__device__ __forceinline__ void store_node(NodeF64* __restrict__ d, const NodeF64& n) {
+    d->A = n.A; d->cx = n.cx; d->cy = n.cy; d->cz = n.cz; d->nx = n.nx; d->ny = n.ny; d->nz = n.nz; d->r = n.r;
+    if constexpr (MOM2)
+        for (int c = 0; c < 6; ++c) { d->m2c[c] = n.m2c[c]; d->m2n[c] = n.m2n[c]; }
+}
+template <bool MOM2>
+__device__ __forceinline__ NodeF64 load_node(const NodeF64* __restrict__ d) {
+    NodeF64 n = {};
+    n.A = d->A; n.cx = d->cx; n.cy = d->cy; n.cz = d->cz; n.nx = d->nx; n.ny = d->ny; n.nz = d->nz; n.r = d->r;
+    if constexpr (MOM2)
+        for (int c = 0; c < 6; ++c) { n.m2c[c] = d->m2c[c]; n.m2n[c] = d->m2n[c]; }
+    return n;
+}
+
+// A node from its two children (MOM2: with the second moments).
+template <bool MOM2>
+__device__ __forceinline__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
     NodeF64 n = {};
     n.A = a.A + b.A;
     if (n.A > 0.0) {
@@ -146,15 +179,17 @@ __device__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
         n.cy = (a.A * a.cy + b.A * b.cy) / n.A;
         n.cz = (a.A * a.cz + b.A * b.cz) / n.A;
         n.nx = a.nx + b.nx; n.ny = a.ny + b.ny; n.nz = a.nz + b.nz;
-        const NodeF64* ch[2] = {&a, &b};
-        for (int c = 0; c < 2; ++c) {
-            const NodeF64& q = *ch[c];
-            if (!(q.A > 0.0)) continue;
+        auto child = [&](const NodeF64& q) {  // the first child, then the second
+            if (!(q.A > 0.0)) return;
             const double dx = q.cx - n.cx, dy = q.cy - n.cy, dz = q.cz - n.cz;
             n.r = fmax(n.r, sqrt(dx * dx + dy * dy + dz * dz) + q.r);
-            for (int m = 0; m < 6; ++m) { n.m2c[m] += q.m2c[m]; n.m2n[m] += q.m2n[m]; }
-            sym_add_outer(n.m2c, q.A, dx, dy, dz);  // parallel-axis shift to the new centroid
-        }
+            if constexpr (MOM2) {
+                for (int m = 0; m < 6; ++m) { n.m2c[m] += q.m2c[m]; n.m2n[m] += q.m2n[m]; }
+                sym_add_outer(n.m2c, q.A, dx, dy, dz);  // parallel-axis shift to the new centroid
+            }
+        };
+        child(a);
+        child(b);
     }
     return n;
 }
@@ -162,31 +197,53 @@ __device__ NodeF64 combine_nodes(const NodeF64& a, const NodeF64& b) {
 // Levels L - 1, ..., L - nl from the nodes of level L, in one launch: work-group g loads the
 // 2^nl nodes [2^L + g 2^nl, 2^L + (g + 1) 2^nl) of level L into LDS (blockDim.x = 2^nl) and
 // combines them level by level up to their common ancestor at level L - nl, writing every node.
-// The tree's internal levels take ceil(H / MOM_SUB) launches instead of H.
+// The tree's internal levels take ceil(H / MOM_SUB) launches instead of H.  LDS holds the nodes
+// field-major (one array per field: a lane's reads of its two children fall in distinct banks,
+// where whole records would put every other lane on the same bank).
 constexpr int MOM_SUB = 8;
 
+template <bool MOM2>
 __global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, const uint32_t* __restrict__ bbox,
                                                                 NodeF64* __restrict__ nodes,
                                                                 NodeRec* __restrict__ recs,
                                                                 NodeMom* __restrict__ moms) {
-    __shared__ NodeF64 buf[1 << MOM_SUB];
+    constexpr int NF = MOM2 ? 20 : 8;  // fields: A, C (3), N (3), r, then m2c (6), m2n (6)
+    __shared__ double buf[NF][1 << MOM_SUB];
     const int t = threadIdx.x, cnt = 1 << nl;
     const int64_t g = blockIdx.x;
-    buf[t] = nodes[((int64_t)1 << L) + g * cnt + t];
+    auto get = [&](int idx) {
+        NodeF64 n = {};
+        n.A = buf[0][idx]; n.cx = buf[1][idx]; n.cy = buf[2][idx]; n.cz = buf[3][idx];
+        n.nx = buf[4][idx]; n.ny = buf[5][idx]; n.nz = buf[6][idx]; n.r = buf[7][idx];
+        if constexpr (MOM2) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) { n.m2c[c] = buf[8 + c][idx]; n.m2n[c] = buf[14 + c][idx]; }
+        }
+        return n;
+    };
+    auto put = [&](int idx, const NodeF64& n) {
+        buf[0][idx] = n.A; buf[1][idx] = n.cx; buf[2][idx] = n.cy; buf[3][idx] = n.cz;
+        buf[4][idx] = n.nx; buf[5][idx] = n.ny; buf[6][idx] = n.nz; buf[7][idx] = n.r;
+        if constexpr (MOM2) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) { buf[8 + c][idx] = n.m2c[c]; buf[14 + c][idx] = n.m2n[c]; }
+        }
+    };
+    put(t, load_node<MOM2>(&nodes[((int64_t)1 << L) + g * cnt + t]));
     __syncthreads();
+    double o[3];
+    norm_origin(bbox, o);
     for (int st = 1; st <= nl; ++st) {
         const int m = cnt >> st;
         NodeF64 par = {};
-        if (t < m) par = combine_nodes(buf[2 * t], buf[2 * t + 1]);
+        if (t < m) par = combine_nodes<MOM2>(get(2 * t), get(2 * t + 1));
         __syncthreads();
         if (t < m) {
-            buf[t] = par;
+            put(t, par);
             const int64_t k = ((int64_t)1 << (L - st)) + g * m + t;
-            nodes[k] = par;
-            double o[3];
-            norm_origin(bbox, o);
+            store_node<MOM2>(&nodes[k], par);
             write_rec(par, o, &recs[k]);
-            write_mom(par, &moms[k]);
+            if constexpr (MOM2) write_mom(par, &moms[k]);
         }
         __syncthreads();
     }
@@ -451,43 +508,6 @@ __global__ __launch_bounds__(64 * FFC_NW) void ff_classify(const NodeRec* __rest
     if (lane == 0) {
         lst[b] = make_uint4(n_near, n_far, n_near_cols, n_visit);
         if (work) work[b] = n_near_cols + n_visit + n_far;
-    }
-}
-
-// The call's interaction counts from the blocks' list records, in one work-group (same-address
-// atomics from every block would serialise): far clusters, near columns and visited nodes summed,
-// blocks, and the largest near-column and far-cluster counts of a block.
-__global__ __launch_bounds__(256) void ff_stats_reduce(const uint4* __restrict__ lst, int64_t nb,
-                                                       unsigned long long* __restrict__ stats) {
-    __shared__ unsigned long long sh[4][5];
-    unsigned long long far = 0, cols = 0, vis = 0, mcols = 0, mfar = 0;
-    for (int64_t b = threadIdx.x; b < nb; b += 256) {
-        const uint4 L = lst[b];
-        far += L.y; cols += L.z; vis += L.w;
-        mcols = L.z > mcols ? L.z : mcols;
-        mfar = L.y > mfar ? L.y : mfar;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        far += __shfl_xor(far, off);
-        cols += __shfl_xor(cols, off);
-        vis += __shfl_xor(vis, off);
-        const unsigned long long a = __shfl_xor(mcols, off), c = __shfl_xor(mfar, off);
-        mcols = a > mcols ? a : mcols;
-        mfar = c > mfar ? c : mfar;
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[w][0] = far; sh[w][1] = cols; sh[w][2] = vis; sh[w][3] = mcols; sh[w][4] = mfar;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 4; ++k) {
-            far += sh[k][0]; cols += sh[k][1]; vis += sh[k][2];
-            mcols = sh[k][3] > mcols ? sh[k][3] : mcols;
-            mfar = sh[k][4] > mfar ? sh[k][4] : mfar;
-        }
-        stats[0] = far; stats[1] = cols; stats[2] = vis; stats[3] = (unsigned long long)nb;
-        stats[4] = mcols; stats[5] = mfar;
     }
 }
 
@@ -963,18 +983,23 @@ size_t tree_node_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeF64); }
 size_t tree_rec_bytes(int H) { return ((size_t)2 << H) * (sizeof(NodeRec) + sizeof(NodeMom)); }
 
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
-                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs,
+                               const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs, bool mom2,
                                hipStream_t st) {
     NodeF64* n = (NodeF64*)nodes64;
     NodeRec* r = (NodeRec*)recs;
     NodeMom* m = (NodeMom*)(r + ((size_t)2 << H));
     const int64_t nslot = (int64_t)1 << H;
-    hipLaunchKernelGGL(leaf_moments, dim3((unsigned)((nslot + MOM_LEAF_WAVES - 1) / MOM_LEAF_WAVES)),
-                       dim3(64 * MOM_LEAF_WAVES), 0, st, c64, geo, colv, X, bbox, nF, leaf, H, n, r, m);
+    int G = 1;
+    while (G < leaf && G < 64) G *= 2;
+    const int64_t per_wg = (int64_t)MOM_LEAF_WAVES * (64 / G);  // leaf slots per work-group
+    const dim3 lg((unsigned)((nslot + per_wg - 1) / per_wg)), lb(64 * MOM_LEAF_WAVES);
+    if (mom2) hipLaunchKernelGGL(leaf_moments<true>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m);
+    else hipLaunchKernelGGL(leaf_moments<false>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m);
     for (int L = H; L > 0;) {
         const int nl = std::min(L, MOM_SUB);
-        hipLaunchKernelGGL(subtree_moments, dim3((unsigned)(((int64_t)1 << L) >> nl)), dim3(1 << nl), 0, st, L, nl, bbox,
-                           n, r, m);
+        const dim3 sg((unsigned)(((int64_t)1 << L) >> nl)), sb(1 << nl);
+        if (mom2) hipLaunchKernelGGL(subtree_moments<true>, sg, sb, 0, st, L, nl, bbox, n, r, m);
+        else hipLaunchKernelGGL(subtree_moments<false>, sg, sb, 0, st, L, nl, bbox, n, r, m);
         L -= nl;
     }
     return hipGetLastError();
@@ -993,35 +1018,121 @@ hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const d
     return hipGetLastError();
 }
 
-// Launch order of the walk's target blocks: heaviest first, by the work each block recorded in the
-// previous call on the same tree (work-groups start in launch order, so the few blocks with several
-// times the average near work no longer start late and set the end of the launch); equal keys
-// keep tree order, and all-zero work (a new tree) gives the identity.  Used for the monopole walk
-// (1.76 -> 1.55 ms at 327,680 faces); the walk with the learned correction runs in tree order,
-// which it prefers (2.76 against 2.83 ms ordered: its heavy part, the network on far clusters, is
-// spread more evenly, and neighbouring blocks share near leaves in the caches).  The key is a monotone
-// 8-bit code of the work (exponent and three mantissa bits), sorted in one radix pass.  The order
-// changes only when blocks run, never what they compute.
-__global__ void ff_order_keys(const uint32_t* __restrict__ work, int64_t nb, uint32_t* __restrict__ keys,
-                              uint32_t* __restrict__ vals) {
-    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const uint32_t w = work[b];
+// Launch order of the walk's target blocks: heaviest first, by the work each block's lists hold in
+// this call (work-groups start in launch order, so the few blocks with several times the average
+// near work no longer start late and set the end of the launch); equal keys keep tree order, and
+// all-zero work gives the identity.  Used for the monopole walk (1.76 -> 1.55 ms at 327,680 faces
+// when introduced); the walk with the learned correction runs in tree order, which it prefers (2.76
+// against 2.83 ms ordered: its heavy part, the network on far clusters, is spread more evenly, and
+// neighbouring blocks share near leaves in the caches).  The key is a monotone 8-bit code of the
+// work (exponent and three mantissa bits).  The order changes only when blocks run, never what
+// they compute.
+__device__ __forceinline__ uint32_t work_key(uint32_t w) {
     uint32_t code = w;
     if (w >= 8u) {
         const int e = 31 - __clz((int)w);
         code = ((uint32_t)(e - 2) << 3) | ((w >> (e - 3)) & 7u);
     }
-    keys[b] = 255u - code;
-    vals[b] = (uint32_t)b;
+    return 255u - code;
 }
 
-hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* keys, uint32_t* vals, uint32_t* ktmp,
-                           uint32_t* vtmp, uint32_t* hist, uint32_t* hoff, hipStream_t st) {
-    hipLaunchKernelGGL(ff_order_keys, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, work, nb, keys, vals);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return radix_sort(keys, vals, ktmp, vtmp, nb, 8, hist, hoff, st);
+// One work-group: a stable counting sort of the nb keys into `order` (null: none), chunk by chunk
+// of FO_NT blocks (ranks among equal keys from wave ballots, then across the waves in LDS), and,
+// with lst and stats, the call's interaction counts from the blocks' list records (far clusters,
+// near columns and visited nodes summed, blocks, the largest near-column and far-cluster counts of
+// a block) in the same pass.  Replaces a key kernel, a radix pass, two copies and a reduction.
+constexpr int FO_NT = 1024;
+
+__global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restrict__ work, int64_t nb,
+                                                       uint32_t* __restrict__ order, const uint4* __restrict__ lst,
+                                                       unsigned long long* __restrict__ stats) {
+    constexpr int NWV = FO_NT / 64;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[NWV][256];
+    __shared__ unsigned long long red[NWV][5];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int k = tid; k < 256; k += FO_NT) base[k] = 0u;
+    __syncthreads();
+    unsigned long long far = 0, cols = 0, vis = 0, mcols = 0, mfar = 0;
+    for (int64_t b = tid; b < nb; b += FO_NT) {
+        if (order) atomicAdd(&base[work_key(work[b])], 1u);  // counts: the order of the adds is immaterial
+        if (lst) {
+            const uint4 L = lst[b];
+            far += L.y; cols += L.z; vis += L.w;
+            mcols = L.z > mcols ? L.z : mcols;
+            mfar = L.y > mfar ? L.y : mfar;
+        }
+    }
+    if (lst && stats) {
+        for (int off = 32; off > 0; off >>= 1) {
+            far += __shfl_xor(far, off);
+            cols += __shfl_xor(cols, off);
+            vis += __shfl_xor(vis, off);
+            const unsigned long long a = __shfl_xor(mcols, off), c = __shfl_xor(mfar, off);
+            mcols = a > mcols ? a : mcols;
+            mfar = c > mfar ? c : mfar;
+        }
+        if (lane == 0) { red[w][0] = far; red[w][1] = cols; red[w][2] = vis; red[w][3] = mcols; red[w][4] = mfar; }
+    }
+    __syncthreads();
+    if (lst && stats && tid == 0) {
+        for (int k = 1; k < NWV; ++k) {
+            far += red[k][0]; cols += red[k][1]; vis += red[k][2];
+            mcols = red[k][3] > mcols ? red[k][3] : mcols;
+            mfar = red[k][4] > mfar ? red[k][4] : mfar;
+        }
+        stats[0] = far; stats[1] = cols; stats[2] = vis; stats[3] = (unsigned long long)nb;
+        stats[4] = mcols; stats[5] = mfar;
+    }
+    if (!order) return;  // uniform
+    if (w == 0) {  // exclusive scan of the 256 counts, 4 per lane
+        uint32_t v[4];
+        for (int q = 0; q < 4; ++q) v[q] = base[4 * lane + q];
+        const uint32_t s = v[0] + v[1] + v[2] + v[3];
+        uint32_t x = s;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        uint32_t e = x - s;
+        for (int q = 0; q < 4; ++q) { base[4 * lane + q] = e; e += v[q]; }
+    }
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
+        for (int k = tid; k < NWV * 256; k += FO_NT) wcnt[k >> 8][k & 255] = 0u;
+        __syncthreads();
+        const int64_t b = c0 + tid;
+        const bool valid = b < nb;
+        const uint32_t k = valid ? work_key(work[b]) : 0u;
+        uint64_t same = __ballot(valid);  // lanes of this wave with the same key
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t m = __ballot(valid && ((k >> bit) & 1u));
+            same &= ((k >> bit) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & lt);
+        if (valid && rank == 0u) wcnt[w][k] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[k] + rank;
+            for (int v = 0; v < w; ++v) pos += wcnt[v][k];
+            order[pos] = (uint32_t)b;
+        }
+        __syncthreads();
+        for (int kk = tid; kk < 256; kk += FO_NT) {
+            uint32_t t = 0u;
+            for (int v = 0; v < NWV; ++v) t += wcnt[v][kk];
+            base[kk] += t;
+        }
+        __syncthreads();
+    }
+}
+
+// order (null: none): heaviest first by work; lst and stats (nullable): the walk's counts
+hipError_t launch_ff_order(const uint32_t* work, int64_t nb, uint32_t* order, const uint4* lst,
+                           unsigned long long* stats, hipStream_t st) {
+    hipLaunchKernelGGL(ff_order_sort, dim3(1), dim3(FO_NT), 0, st, work, nb, order, lst, stats);
+    return hipGetLastError();
 }
 
 // Entries per block of the walk's lists: every non-empty leaf at most once, within 8 GiB in all.
@@ -1046,13 +1157,10 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
     hipLaunchKernelGGL(ff_classify, dim3((unsigned)((nb + FFC_NW - 1) / FFC_NW)), dim3(64 * FFC_NW), 0, st, r, H, leaf,
                        nF, balls, theta, cap, ent, lst, work, flags);
-    if (stats) hipLaunchKernelGGL(ff_stats_reduce, dim3(1), dim3(256), 0, st, lst, nb, stats);
-    const uint32_t* order = nullptr;
-    if (!mlp_packed) {
-        hipError_t e = launch_ff_order(work, nb, sort[0], sort[1], sort[2], sort[3], sort[4], sort[5], st);
-        if (e != hipSuccess) return e;
-        order = sort[1];
-    }
+    // launch order (monopole) and the interaction counts, in one work-group
+    const uint32_t* order = mlp_packed ? nullptr : sort[1];
+    hipError_t e = launch_ff_order(work, nb, mlp_packed ? nullptr : sort[1], lst, stats, st);
+    if (e != hipSuccess) return e;
     if (mlp_packed)
         hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
                            colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,

@@ -83,6 +83,16 @@ def test_farfield_errors():
         T.farfield(tree, Xd, Fd, theta=1.5)  # beyond 2 neighbours could enter far clusters; [0, 1] taken
     with pytest.raises(T.TPEError):
         T.build_tree(Xd, Fd, leaf=0)
+    # the same sizes but other faces: the tree's gather lists belong to its own face list
+    F3 = c.F.copy()
+    F3[[0, 1]] = F3[[1, 0]]
+    _, Fd3 = upload(c.X, F3)
+    for call in (lambda: T.farfield(tree, Xd, Fd3), lambda: T.farfield_dual(tree, Xd, Fd3),
+                 lambda: T.farfield_samples(tree, Xd, Fd3, theta=0.5, seed=1, select_prob=0.5)):
+        with pytest.raises(T.TPEError, match="tree was built with"):
+            call()
+    E, G = T.farfield(tree, Xd, Fd)  # the context is usable afterwards
+    assert np.isfinite(float(E.cpu()))
 
 
 def test_c4_far_field_vs_exact():
