@@ -108,8 +108,11 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
-                           uint32_t* flags, uint32_t* const sort[6], hipStream_t st);
+                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, hipStream_t st);
 int64_t ff_list_cap(int64_t n, int leaf);
+hipError_t launch_block_neighbours(const int4* colv, const uint32_t* voff, const uint32_t* vlist, int64_t nF,
+                                   int64_t V, int leaf, uint32_t* nbl, hipStream_t st);
+int64_t block_neighbour_words(int64_t n);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -244,6 +247,7 @@ struct tpe_tree {
     uint32_t* voff = nullptr;
     uint32_t* vlist = nullptr;
     uint32_t* fsum = nullptr;
+    uint32_t* nbl = nullptr;   // flat trees: per target block, the leaves sharing a vertex with it
 };
 
 namespace {
@@ -729,15 +733,16 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
 // work record of the far-field walk (zero: the first walk runs in tree order).  Frees the tree on
 // failure.
 void free_tree(tpe_tree* t) {
-    for (uint32_t* p : {t->perm, t->work, t->voff, t->vlist, t->fsum})
+    for (uint32_t* p : {t->perm, t->work, t->voff, t->vlist, t->fsum, t->nbl})
         if (p) (void)hipFree(p);
     delete t;
 }
 
 // voff, vlist, fsum (device, nullable: a tree over curved elements keeps none): the gather's vertex
-// lists (V + 1 offsets, 3 n slots) and the face-list checksum, copied into the tree
+// lists (V + 1 offsets, 3 n slots) and the face-list checksum, copied into the tree; colv: the
+// sorted faces' vertex ids, from which the per-block neighbour leaves are listed
 int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out, const uint32_t* voff = nullptr,
-                const uint32_t* vlist = nullptr, const uint32_t* fsum = nullptr) {
+                const uint32_t* vlist = nullptr, const uint32_t* fsum = nullptr, const int4* colv = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t nb = (t->n + 63) / 64;
     auto drop = [&](int code) {
@@ -748,7 +753,8 @@ int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out,
         hipMalloc(&t->work, nb * sizeof(uint32_t)) != hipSuccess ||
         (voff && (hipMalloc(&t->voff, (t->V + 1) * sizeof(uint32_t)) != hipSuccess ||
                   hipMalloc(&t->vlist, 3 * t->n * sizeof(uint32_t)) != hipSuccess ||
-                  hipMalloc(&t->fsum, sizeof(uint32_t)) != hipSuccess))) {
+                  hipMalloc(&t->fsum, sizeof(uint32_t)) != hipSuccess ||
+                  hipMalloc(&t->nbl, block_neighbour_words(t->n) * sizeof(uint32_t)) != hipSuccess))) {
         (void)hipGetLastError();
         return drop(fail(ctx, TPE_ERR_OOM, "tree allocation failed"));
     }
@@ -758,6 +764,7 @@ int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out,
     if (e == hipSuccess && voff)
         e = hipMemcpyAsync(t->vlist, vlist, 3 * t->n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && voff) e = hipMemcpyAsync(t->fsum, fsum, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && voff) e = launch_block_neighbours(colv, t->voff, t->vlist, t->n, t->V, t->leaf, t->nbl, st);
     if (e == hipSuccess) e = launch_fill(t->work, 0u, nb, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return drop(hip_fail(ctx, e, "tree set-up"));
@@ -998,7 +1005,7 @@ int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, i
     t->leaf = leaf_size;
     t->H = tree_height(nF, leaf_size);
     t->n = nF;
-    return finish_tree(ctx, t, P.vals, out, P.voff, P.list, P.bbox + BBOX_FSUM);
+    return finish_tree(ctx, t, P.vals, out, P.voff, P.list, P.bbox + BBOX_FSUM, P.colv);
 }
 
 int tpe_build_tree_p3(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F10, int64_t nF, int32_t leaf_size,
@@ -1086,7 +1093,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, nullptr, st));
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
@@ -1161,7 +1168,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, tree->nbl, st));
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));

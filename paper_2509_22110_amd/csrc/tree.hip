@@ -511,18 +511,92 @@ __global__ __launch_bounds__(64 * FFC_NW) void ff_classify(const NodeRec* __rest
     }
 }
 
+// Leaves holding a face that shares a vertex with a target block (the block's own leaves among
+// them), per block of 64 faces: nbl[b * NBL_STRIDE] = their count (NBL_OVERFLOW if more than
+// NBL_MAX), then the leaf ids in ascending order.  A near node of the walk needs the shared-vertex
+// exclusion exactly when it holds one of these leaves; masked and unmasked evaluation give the
+// same bits on a node without such a face, so the list only saves the vertex comparisons.  They
+// depend on the faces and the order only (built once per tree).  One wave per block: every lane
+// walks its face's three vertex lists and inserts the leaves into an LDS hash set.
+constexpr int NBL_MAX = 16;
+constexpr int NBL_STRIDE = NBL_MAX + 1;
+constexpr uint32_t NBL_OVERFLOW = 0xffffffffu;
+
+__global__ __launch_bounds__(64) void block_neighbour_leaves(const int4* __restrict__ colv,
+                                                             const uint32_t* __restrict__ voff,
+                                                             const uint32_t* __restrict__ vlist, int64_t nF,
+                                                             int64_t V, int leaf, uint32_t* __restrict__ nbl) {
+    constexpr int HS = 256;  // hash slots (a block touches a few dozen leaves at most on a manifold)
+    __shared__ uint32_t set[HS];
+    __shared__ uint32_t nset;
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    for (int k = lane; k < HS; k += 64) set[k] = 0xffffffffu;
+    if (lane == 0) nset = 0u;
+    __syncthreads();
+    const int64_t i = b * 64 + lane;
+    bool full = false;
+    if (i < nF) {
+        const int4 v = colv[i];
+        const int vv[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3 && !full; ++k) {
+            if (vv[k] < 0 || vv[k] >= V) continue;
+            for (uint32_t s = voff[vv[k]]; s < voff[vv[k] + 1] && !full; ++s) {
+                const uint32_t lf = (uint32_t)((vlist[s] / 3) / (uint32_t)leaf);
+                uint32_t h = (lf * 0x9e3779b9u) >> 24;  // HS = 256 slots
+                for (int probe = 0; probe < HS; ++probe, h = (h + 1) & (HS - 1)) {
+                    const uint32_t old = atomicCAS(&set[h], 0xffffffffu, lf);
+                    if (old == 0xffffffffu) {
+                        if (atomicAdd(&nset, 1u) >= (uint32_t)NBL_MAX) full = true;
+                        break;
+                    }
+                    if (old == lf) break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        uint32_t* out = nbl + (size_t)b * NBL_STRIDE;
+        if (nset > (uint32_t)NBL_MAX) {
+            out[0] = NBL_OVERFLOW;
+        } else {
+            uint32_t m = 0, L[NBL_MAX];
+            for (int k = 0; k < HS; ++k) {
+                const uint32_t x = set[k];
+                if (x == 0xffffffffu) continue;
+                int p = (int)m++;  // insertion into the sorted prefix
+                while (p > 0 && L[p - 1] > x) { L[p] = L[p - 1]; --p; }
+                L[p] = x;
+            }
+            out[0] = m;
+            for (uint32_t k = 0; k < m; ++k) out[1 + k] = L[k];
+        }
+    }
+}
+
+hipError_t launch_block_neighbours(const int4* colv, const uint32_t* voff, const uint32_t* vlist, int64_t nF,
+                                   int64_t V, int leaf, uint32_t* nbl, hipStream_t st) {
+    hipLaunchKernelGGL(block_neighbour_leaves, dim3((unsigned)((nF + 63) / 64)), dim3(64), 0, st, colv, voff, vlist,
+                       nF, V, leaf, nbl);
+    return hipGetLastError();
+}
+int64_t block_neighbour_words(int64_t n) { return ((n + 63) / 64) * NBL_STRIDE; }
+
 // One work-group of NW waves per target block (launch order `order`, else tree order): the block's
 // far clusters and near nodes from ff_classify's lists, entry j of each list to wave j mod NW, far
 // clusters first; the waves' compensated sums are folded into wave 0's through LDS and written as
 // the block's FP64 row sums acc64[k][i].  (Splitting the heaviest blocks over several work-groups
-// was measured slower: the launch is bound by the total pair work, not by its last block.)
+// was measured slower: the launch is bound by the total pair work, not by its last block.  At
+// least 3 waves per SIMD: the monopole walk at 327,680 faces takes 1.19 ms of call time at 3, 1.20
+// at 4 (128 VGPRs with spills), 1.28 at 5.)
 template <bool LEARNED, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LEARNED ? 3 : 4))) void ff_eval(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void ff_eval(
     const ColRec* __restrict__ cols, const int4* __restrict__ colv, const double* __restrict__ c64,
     const double* __restrict__ org, const NodeRec* __restrict__ nodes, const NodeMom* __restrict__ moms,
     const MlpPacked* __restrict__ W, int H, int leaf, int64_t nF, const uint32_t* __restrict__ bbox,
     const float4* __restrict__ balls, int64_t Fp, double* __restrict__ acc64, const uint32_t* __restrict__ order,
-    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst) {
+    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst, const uint32_t* __restrict__ nbl) {
     constexpr int NRED = NW > 1 ? NW - 1 : 1;
     __shared__ MlpScratch ms[LEARNED ? NW : 1];
     __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
@@ -579,16 +653,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LEARNED
             }
         }
     }
-    // near nodes: exact pairs over their faces, without the shared-vertex test when their vertex
-    // ball cannot meet the block's (conservative margin for the FP32 distance)
+    // near nodes: exact pairs over their faces, with the shared-vertex test only where the node
+    // holds a leaf of the block's neighbour list; without that list (curved elements, or more than
+    // NBL_MAX such leaves) only where their vertex balls can meet (conservative margin for FP32)
+    const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
+    // lane m < nn holds neighbour leaf m (the test of a node is then one compare and a ballot)
+    const uint32_t my_leaf = nn <= (uint32_t)NBL_MAX && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane]
+                                                                             : 0xffffffffu;
     for (uint32_t j = wave; j < L.x; j += NW) {
         const int64_t kk = (int64_t)e[j];
         const int lev = 63 - __builtin_clzll((unsigned long long)kk);
         const int64_t span = (int64_t)1 << (H - lev);
         const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
         const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-        const NodeRec nd = nodes[kk];
-        if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
+        bool disjoint;
+        if (nn <= (uint32_t)NBL_MAX) {
+            const uint32_t l0 = (uint32_t)(f0 / leaf), l1 = (uint32_t)((f1 - 1) / leaf);
+            disjoint = __ballot(my_leaf >= l0 && my_leaf <= l1) == 0ull;
+        } else {
+            const NodeRec nd = nodes[kk];
+            disjoint = ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r;
+        }
+        if (disjoint)
             ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
         else
             ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
@@ -1054,9 +1140,26 @@ __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restric
     for (int k = tid; k < 256; k += FO_NT) base[k] = 0u;
     __syncthreads();
     unsigned long long far = 0, cols = 0, vis = 0, mcols = 0, mfar = 0;
-    for (int64_t b = tid; b < nb; b += FO_NT) {
-        if (order) atomicAdd(&base[work_key(work[b])], 1u);  // counts: the order of the adds is immaterial
-        if (lst) {
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // lanes of this wave holding the same key as this lane (valid lanes only)
+    auto same_key = [&](bool valid, uint32_t k) {
+        uint64_t same = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t m = __ballot(valid && ((k >> bit) & 1u));
+            same &= ((k >> bit) & 1u) ? m : ~m;
+        }
+        return same;
+    };
+    for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
+        const int64_t b = c0 + tid;
+        const bool valid = b < nb;
+        if (order) {  // counts, one LDS add per key and wave (per-element adds on the few distinct
+                      // keys serialised); the order of the adds is immaterial
+            const uint32_t k = valid ? work_key(work[b]) : 0u;
+            const uint64_t same = same_key(valid, k);
+            if (valid && (same & lt) == 0ull) atomicAdd(&base[k], (uint32_t)__popcll(same));
+        }
+        if (lst && valid) {
             const uint4 L = lst[b];
             far += L.y; cols += L.z; vis += L.w;
             mcols = L.z > mcols ? L.z : mcols;
@@ -1098,18 +1201,13 @@ __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restric
         for (int q = 0; q < 4; ++q) { base[4 * lane + q] = e; e += v[q]; }
     }
     __syncthreads();
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
         for (int k = tid; k < NWV * 256; k += FO_NT) wcnt[k >> 8][k & 255] = 0u;
         __syncthreads();
         const int64_t b = c0 + tid;
         const bool valid = b < nb;
         const uint32_t k = valid ? work_key(work[b]) : 0u;
-        uint64_t same = __ballot(valid);  // lanes of this wave with the same key
-        for (int bit = 0; bit < 8; ++bit) {
-            const uint64_t m = __ballot(valid && ((k >> bit) & 1u));
-            same &= ((k >> bit) & 1u) ? m : ~m;
-        }
+        const uint64_t same = same_key(valid, k);
         const uint32_t rank = (uint32_t)__popcll(same & lt);
         if (valid && rank == 0u) wcnt[w][k] = (uint32_t)__popcll(same);
         __syncthreads();
@@ -1150,7 +1248,7 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
-                           uint32_t* flags, uint32_t* const sort[6], hipStream_t st) {
+                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, hipStream_t st) {
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
@@ -1164,10 +1262,11 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     if (mlp_packed)
         hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
                            colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,
-                           order, cap, ent, lst);
+                           order, cap, ent, lst, nbl);
     else
         hipLaunchKernelGGL((ff_eval<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org,
-                           r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst);
+                           r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst,
+                           nbl);
     return hipGetLastError();
 }
 
