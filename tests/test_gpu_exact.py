@@ -244,6 +244,34 @@ def test_symmetric_kernel(name, X, F, waves, nw):
         assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
 
 
+def test_exact_plan_reports_the_kernel_choice():
+    """tpe_exact_plan: the fewest waves per work-group whose column partials fit in 8 GiB, the
+    partial bytes of the schedule (8 sums x 64 columns x 4 bytes per symmetric unit), the row-only
+    kernel when the symmetric one is switched off."""
+    T = tpe()
+    import torch
+    ctx = T.context(torch.device("cuda", 0))
+
+    def colpart(nF, nw):
+        sb = 128 * nw
+        fp = -(-nF // sb) * sb
+        nsb, nch, sbc = fp // sb, fp // 64, 2 * nw
+        return (nsb * (nch - sbc) - sbc * nsb * (nsb - 1) // 2) * 8 * 64 * 4
+
+    for nF, nw in ((20480, 1), (262144, 1), (327680, 2), (370688, 2), (400000, 4), (1310720, 4)):
+        sym, w, cp, scratch = ctx.exact_plan(nF, nF // 2 + 2, True)
+        log("plan", nF, sym, w, cp, scratch)
+        assert sym and w == nw and cp == colpart(nF, nw) and scratch > cp
+    try:
+        ctx.set_option(T.OPT_SYM_WAVES, 4)
+        assert ctx.exact_plan(20480, 10242, True)[1:3] == (4, colpart(20480, 4))
+        ctx.set_option(T.OPT_SYMMETRIC, 0)
+        assert ctx.exact_plan(20480, 10242, True)[:3] == (False, 0, 0)
+    finally:
+        ctx.set_option(T.OPT_SYM_WAVES, 0)
+        ctx.set_option(T.OPT_SYMMETRIC, 1)
+
+
 def test_symmetric_waves_option_rejects_other_values():
     T = tpe()
     import torch
