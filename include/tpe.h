@@ -96,9 +96,9 @@ typedef enum {
     TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2 or 4 (super
                                  blocks of 128, 256 or 512 faces); 0 (default): the fewest whose
                                  column partial sums fit in 8 GiB (1 up to about 262,000 faces,
-                                 then 2 up to about 370,000, then 4; tpe_exact_plan tells).  Fewer waves wait less at the work-group's
-                                 barriers but write proportionally more partial sums.  Results
-                                 agree to rounding */
+                                 then 2 up to about 370,000, then 4; tpe_exact_plan tells).
+                                 Fewer waves wait less at the work-group's barriers but write
+                                 proportionally more partial sums.  Results agree to rounding */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -381,15 +381,17 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
  * Synchronises the stream. */
 int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
 
-/* How tpe_gradient (grad = 1) or tpe_energy (grad = 0) would run a mesh of nF faces and V vertices
- * with the context's current options (host only, nothing is launched): out_host[0] = 1 if the
+/* How tpe_gradient (grad = 1) or tpe_energy (grad = 0) with (q, p) = (6, 12) would run a mesh of nF
+ * faces and V vertices with the context's current options (host only, nothing is launched; other
+ * exponents take the row-only kernel): out_host[0] = 1 if the
  * symmetric pair kernel is taken, [1] = its waves per work-group (0 for the row-only kernel),
  * [2] = the bytes of its column partial sums (read back by the merge), [3] = the scratch arena the
  * call needs.  Host array of 4 int64. */
 int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host);
 
 /* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed
- * duration of the dominant-kernel launches (the exact pair kernel, or the far-field traversal) recorded since the last call and *count (host) <- their
+ * duration of the dominant-kernel launches (the exact pair kernel, or the far-field traversal)
+ * recorded since the last call and *count (host) <- their
  * number; the record is cleared. */
 int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count);
 

@@ -21,8 +21,8 @@
 namespace tpe {
 hipError_t launch_fill(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_init(uint32_t* zero, int64_t nzero, uint32_t* bbox, uint32_t* flags, hipStream_t st);
-hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox, uint32_t* flags,
-                       hipStream_t st, const uint32_t* expect = nullptr);
+hipError_t launch_bbox(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, uint32_t* bbox,
+                       uint32_t* flags, hipStream_t st, const uint32_t* expect = nullptr);
 hipError_t launch_morton(const double* X, int64_t V, const int32_t* F, int fs, int64_t nF, int Q, const uint32_t* bbox,
                          int bits, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp, int64_t n, int bits,
@@ -573,7 +573,8 @@ int report_flags(tpe_ctx* ctx) {
     if (f & FLAG_TREE_FACES)
         return fail(ctx, TPE_ERR_INVALID_ARG, "the faces differ from those the tree was built with");
     if (f & FLAG_LISTS)
-        return fail(ctx, TPE_ERR_OOM, "far-field interaction lists exceed their scratch (theta too small for this mesh)");
+        return fail(ctx, TPE_ERR_OOM,
+                    "far-field interaction lists exceed their scratch (theta too small for this mesh)");
     return TPE_OK;
 }
 
@@ -1473,7 +1474,8 @@ int tpe_mlp_load(tpe_ctx* ctx, const char* path, tpe_mlp** out) {
     m->min_s = gate[0];
     DeviceGuard dg(ctx->device);
     hipError_t e = hipMemcpy(m->P, buf.data(), MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(m->M, buf.data() + MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->M, buf.data() + MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->V, buf.data() + 2 * MLP_NPARAM, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = mlp_pack_launch(m->P, m->min_s, m->packed, nullptr);
@@ -1507,7 +1509,8 @@ int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count) {
 
 int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host) {
     if (!ctx) return TPE_ERR_INVALID_ARG;
-    if (!out_host || nF < 1 || V < 1 || (grad != 0 && grad != 1)) return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
+    if (!out_host || nF < 1 || V < 1 || (grad != 0 && grad != 1))
+        return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
     Plan P;
     plan(P, ctx, nF, V, grad != 0, -1, 0, 0, ctx->quad, ctx->symmetric, false);
     out_host[0] = P.sym ? 1 : 0;
