@@ -94,11 +94,17 @@ typedef enum {
                                  agree to rounding.  The scratch stays allocated with the context
                                  (tpe_destroy frees it) */,
     TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2 or 4 (super
-                                 blocks of 128, 256 or 512 faces); 0 (default): the fewest whose
-                                 column partial sums fit in 8 GiB (1 up to about 262,000 faces,
-                                 then 2 up to about 370,000, then 4; tpe_exact_plan tells).
-                                 Fewer waves wait less at the work-group's barriers but write
-                                 proportionally more partial sums.  Results agree to rounding */
+                                 blocks of 128, 256 or 512 faces; fewer waves write proportionally
+                                 more column partial sums).  0 (default): 4 without barriers (see
+                                 TPE_OPT_SYM_BARRIERS); with barriers, the fewest whose column
+                                 partial sums fit in 8 GiB (1 up to about 262,000 faces, then 2 up
+                                 to about 370,000, then 4), since fewer waves wait less at the
+                                 barriers.  tpe_exact_plan tells.  Results agree to rounding */,
+    TPE_OPT_SYM_BARRIERS = 7  /* 0 (default): the symmetric pair kernel with 2 or 4 waves per
+                                 work-group runs without work-group barriers (each wave stages its
+                                 own columns; the waves' column sums meet in a ring of LDS slots,
+                                 reduced in wave order by the last wave to arrive); 1: with a
+                                 barrier per unit.  The same bits either way */
 } tpe_option;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -383,8 +389,8 @@ int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
 
 /* How tpe_gradient (grad = 1) or tpe_energy (grad = 0) with (q, p) = (6, 12) would run a mesh of nF
  * faces and V vertices with the context's current options (host only, nothing is launched; other
- * exponents take the row-only kernel): out_host[0] = 1 if the
- * symmetric pair kernel is taken, [1] = its waves per work-group (0 for the row-only kernel),
+ * exponents take the row-only kernel): out_host[0] = 1 if the symmetric pair kernel is taken,
+ * 2 if it runs without work-group barriers, [1] = its waves per work-group (0 for the row-only kernel),
  * [2] = the bytes of its column partial sums (read back by the merge), [3] = the scratch arena the
  * call needs.  Host array of 4 int64. */
 int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host);

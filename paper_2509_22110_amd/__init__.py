@@ -32,6 +32,7 @@ OPT_KERNEL_TIMING = 3
 OPT_QUADRATURE = 4
 OPT_SYMMETRIC = 5
 OPT_SYM_WAVES = 6
+OPT_SYM_BARRIERS = 7
 
 
 class TPEError(RuntimeError):
@@ -137,11 +138,12 @@ class _Ctx:
         return ms.value, n.value
 
     def exact_plan(self, nF: int, V: int, grad: bool = True):
-        """(symmetric kernel taken, its waves per work-group, bytes of its column partial sums,
-        scratch bytes) of an exact call on a mesh of nF faces and V vertices (see tpe_exact_plan)."""
+        """(symmetric kernel: 0 no, 1 with barriers, 2 without; its waves per work-group, bytes of
+        its column partial sums, scratch bytes) of an exact call on a mesh of nF faces and V
+        vertices (see tpe_exact_plan)."""
         out = (ctypes.c_int64 * 4)()
         self.check(lib().tpe_exact_plan(self.h, int(nF), int(V), 1 if grad else 0, out))
-        return bool(out[0]), int(out[1]), int(out[2]), int(out[3])
+        return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
     def farfield_stats(self):
         """(far clusters, near columns, visited nodes, target blocks, max near columns of a block,

@@ -60,13 +60,13 @@ hipError_t launch_finalize(bool grad, const float* part, const Sched& sc, int64_
                            uint32_t* flags, double* E, EnergyOut* in_gather, hipStream_t st);
 hipError_t launch_sym_merge(bool grad, const float* part, const float* colpart, const int* first,
                             const SymSched& sc, int64_t nR, int64_t Fp, double* acc64, hipStream_t st);
-int pair_sym_blocks_per_cu(bool grad, int nw);
+int pair_sym_blocks_per_cu(bool grad, int nw, bool decoupled);
 SymSched make_sym_sched(int64_t Fp, int W, int tail, int nw);
 int64_t sym_part_floats(const SymSched& sc, bool grad);
 int64_t sym_colpart_floats(const SymSched& sc, bool grad);
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
-                           int* first, hipStream_t st);
+                           int* first, bool decoupled, uint32_t* flags, hipStream_t st);
 int dual_level(int H, int leaf);
 int64_t dual_entry_cap(int H, int leaf);
 int64_t dual_part_floats(int H, int leaf);
@@ -79,11 +79,12 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
 // fit in this many bytes: about 1,430,000 faces with super blocks of 512 faces, of the GPU's 288 GB
 // of HBM; if the allocation fails the call runs the row-only kernel instead
 constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
-// Work-groups of 1 or 2 waves (super blocks of 128 or 256 faces) run the symmetric kernel faster
-// than 4 (each wave waits less at the work-group's barriers: 64.8 / 65.0 / 70.3 ms at 327,680 faces)
-// but write 4 or 2 times the column partials, which the merge reads back (the whole step: 67.7 /
-// 66.6 / 71.3 ms); the fewest waves whose partials fit in this budget are taken (20,480 faces:
-// 1 wave; 327,680 faces: 2, 6.2 GiB), else 4
+// With work-group barriers (TPE_OPT_SYM_BARRIERS = 1), work-groups of 1 or 2 waves (super blocks of
+// 128 or 256 faces) run the symmetric kernel faster than 4 (each wave waits less at the barriers:
+// 64.3 / 64.6 / 70.2 ms at 327,680 faces) but write 4 or 2 times the column partials, which the
+// merge reads back (the whole step: 67.1 / 66.2 / 71.2 ms); the fewest waves whose partials fit in
+// this budget are then taken (20,480 faces: 1 wave; 327,680 faces: 2, 6.2 GiB), else 4.  Without
+// barriers (the default) 4 waves run fastest at every size: 61.9 ms, step 62.9 ms.
 constexpr int64_t SYM_FAST_COLPART_BYTES = (int64_t)8 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
@@ -199,7 +200,9 @@ struct tpe_ctx {
     int quad = 1;                 // quadrature points per face of the exact path (1, 3 or 6)
     int resident[2] = {0, 0};     // pair-kernel work-groups resident on the device (energy, gradient)
     int resident_sym[3][2] = {};  // the same for the symmetric pair kernel, work-groups of 1, 2, 4 waves
+    int resident_symf[3][2] = {}; // the same for its barrier-free form (2 and 4 waves)
     int sym_waves = 0;            // waves per work-group of the symmetric kernel (0: by size)
+    bool sym_barriers = false;    // the symmetric kernel with work-group barriers (else barrier-free)
     bool symmetric = true;        // exact self energy (6, 12): symmetric pair kernel where it fits
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -336,6 +339,7 @@ struct Plan {
     // symmetric pair kernel (exact self energy)
     bool sym = false;
     SymSched ssc{};
+    bool sym_free = false;  // the symmetric kernel without work-group barriers
     float* colpart = nullptr;
     int* first = nullptr;
     // buffers
@@ -472,9 +476,11 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
     P.Fp = round_up(P.nR, std::max(ROWB, CTILE));
     P.sym = false;
     if (sym) {
-        // waves per work-group: forced by TPE_OPT_SYM_WAVES, else the fewest whose column partials
-        // fit in SYM_FAST_COLPART_BYTES
+        // waves per work-group: forced by TPE_OPT_SYM_WAVES; else 4 without barriers (the fastest
+        // at every size, and the fewest column partials); with barriers the fewest waves whose
+        // column partials fit in SYM_FAST_COLPART_BYTES
         int nw = ctx->sym_waves;
+        if (nw == 0 && !ctx->sym_barriers) nw = 4;
         if (nw == 0) {
             nw = 4;
             for (int cand = 1; cand < 4; cand *= 2) {
@@ -490,7 +496,9 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
         // would get (the hardware refills the slots of early finishers, which evens out the
         // finish times; more work-groups add row segments for the merge to read), then one
         // single-unit work-group per resident slot for the end of the launch
-        const int resident = ctx->resident_sym[nw == 1 ? 0 : nw == 2 ? 1 : 2][grad ? 1 : 0];
+        const bool decoupled = nw >= 2 && !ctx->sym_barriers;
+        const int resident = (decoupled ? ctx->resident_symf : ctx->resident_sym)[nw == 1 ? 0 : nw == 2 ? 1 : 2]
+                                                                                   [grad ? 1 : 0];
         int W = resident, tail = 0;
         if (ctx->target_waves > 0) {
             W = (int)ctx->target_waves;
@@ -502,6 +510,7 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
         const SymSched t = make_sym_sched(Fs, W, tail, nw);
         if (sym_colpart_floats(t, grad) * (int64_t)sizeof(float) <= SYM_MAX_COLPART_BYTES) {
             P.sym = true;
+            P.sym_free = decoupled;
             P.ssc = t;
             P.Fp = Fs;
         }
@@ -570,6 +579,8 @@ int report_flags(tpe_ctx* ctx) {
     if (f & FLAG_NONFINITE)
         return fail(ctx, TPE_ERR_NONFINITE, "non-finite input or result (coincident non-adjacent centroids?)");
     if (f & FLAG_DEGENERATE) return fail(ctx, TPE_ERR_DEGENERATE, "degenerate face (area <= 1e-300)");
+    if (f & FLAG_SYNC)
+        return fail(ctx, TPE_ERR_HIP, "symmetric pair kernel: a wave gave up waiting for its work-group");
     if (f & FLAG_TREE_FACES)
         return fail(ctx, TPE_ERR_INVALID_ARG, "the faces differ from those the tree was built with");
     if (f & FLAG_LISTS)
@@ -656,7 +667,7 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     if (timing == 1) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) {
         HIPCHK(launch_pair_sym(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.ssc, P.part, P.colpart,
-                               P.first, st));
+                               P.first, P.sym_free, ctx->dflags, st));
     } else {
         HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part,
                            st));
@@ -809,8 +820,10 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
         ctx->resident[0] = ncu * pair_blocks_per_cu(false);
         ctx->resident[1] = ncu * pair_blocks_per_cu(true);
         for (int k = 0; k < 3; ++k) {
-            ctx->resident_sym[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k);
-            ctx->resident_sym[k][1] = ncu * pair_sym_blocks_per_cu(true, 1 << k);
+            ctx->resident_sym[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k, false);
+            ctx->resident_sym[k][1] = ncu * pair_sym_blocks_per_cu(true, 1 << k, false);
+            ctx->resident_symf[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k, true);
+            ctx->resident_symf[k][1] = ncu * pair_sym_blocks_per_cu(true, 1 << k, true);
         }
     }
     if (launch_fill(ctx->dflags, 0u, 64, ctx->stream) != hipSuccess ||
@@ -881,6 +894,10 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
             if (value != 0 && value != 1 && value != 2 && value != 4)
                 return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric kernel waves: 0, 1, 2 or 4");
             ctx->sym_waves = (int)value;
+            return TPE_OK;
+        case TPE_OPT_SYM_BARRIERS:
+            if (value != 0 && value != 1) return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric barriers: 0 or 1");
+            ctx->sym_barriers = value != 0;
             return TPE_OK;
         case TPE_OPT_KERNEL_TIMING:
             if (value < 0 || value > 2) return fail(ctx, TPE_ERR_INVALID_ARG, "kernel timing: 0, 1 or 2");
@@ -1513,7 +1530,7 @@ int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* o
         return fail(ctx, TPE_ERR_INVALID_ARG, "bad arguments");
     Plan P;
     plan(P, ctx, nF, V, grad != 0, -1, 0, 0, ctx->quad, ctx->symmetric, false);
-    out_host[0] = P.sym ? 1 : 0;
+    out_host[0] = P.sym ? (P.sym_free ? 2 : 1) : 0;
     out_host[1] = P.sym ? P.ssc.nw : 0;
     out_host[2] = P.sym ? sym_colpart_floats(P.ssc, grad != 0) * (int64_t)sizeof(float) : 0;
     out_host[3] = (int64_t)P.bytes;

@@ -12,6 +12,7 @@ enum : uint32_t {
     FLAG_NONFINITE = 4u,   // non-finite coordinate, or a non-finite accumulated result
     FLAG_LISTS = 8u,       // the dual-tree interaction lists outgrew their scratch
     FLAG_TREE_FACES = 16u, // the face list differs from the one the tree was built with
+    FLAG_SYNC = 32u,       // a wave of the symmetric kernel gave up waiting for its work-group
 };
 
 // Geometry of the exact all-pairs kernel.

@@ -689,6 +689,156 @@ __global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 }
 
+// The same kernel without work-group barriers (NW >= 2).  With barriers every wave waits at each
+// unit for the slowest one, and the waves of a SIMD progress at different rates (the oldest
+// first): 70.3 ms at 327,680 faces with 4 waves against 64.8 with 1.  Here each wave stages its
+// own copy of a unit's columns (LDS [NW][SYM_COLS], 48 B a column) and the work-group's column
+// partial goes through a ring of SYM_RING slots: every wave writes its column sums into the
+// unit's slot and counts itself in (an LDS atomic after its writes), and the wave that arrives
+// last adds the NW contributions in wave order (the bits of the barrier kernel) and writes the
+// partial, then frees the slot (count reset, then the slot's use counter advanced).  A wave
+// waits only before reusing a slot whose previous unit is not yet reduced, i.e. when it is
+// SYM_RING units ahead of the slowest wave of its work-group; the slowest wave never waits, so
+// every wait ends.  The wait is bounded all the same (FLAG_SYNC and a wrong result beyond it).
+constexpr int SYM_RING = 3;
+constexpr uint32_t SYM_SPIN_LIMIT = 1u << 22;  // sleeps of 2 x 64 cycles, about 0.2 s
+
+template <bool GRAD, int NW>
+constexpr size_t sym_free_lds_floats() {
+    return (size_t)NW * SYM_COLS * (8 + 4) + (size_t)SYM_RING * NW * WAVE * sym_cs<GRAD>() + 2 * SYM_RING;
+}
+
+template <bool GRAD, int NW>
+__global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_free_kernel(
+    const ColRec* __restrict__ cols, const double* __restrict__ c64, const int4* __restrict__ colv,
+    const double* __restrict__ corg, const uint32_t* __restrict__ touch, int touch_words, SymSched sc,
+    float* __restrict__ part, float* __restrict__ colpart, int* __restrict__ first, uint32_t* __restrict__ flags) {
+    static_assert(NW >= 2 && WAVE == SYM_COLS, "one column per lane, several waves");
+    constexpr int NA = GRAD ? NSYM : 1;
+    constexpr int CS = sym_cs<GRAD>();
+    constexpr int SBC = NW * ROWB / CHUNK;  // equals sc.sbc
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    ColRec* lcol = reinterpret_cast<ColRec*>(lds) + wave * SYM_COLS;                  // [NW][SYM_COLS]
+    int4* lvid = reinterpret_cast<int4*>(lds + NW * SYM_COLS * 8) + wave * SYM_COLS;  // [NW][SYM_COLS]
+    float* ring = lds + NW * SYM_COLS * 12;                                           // [SYM_RING][NW][WAVE][CS]
+    uint32_t* arrived = reinterpret_cast<uint32_t*>(ring + SYM_RING * NW * WAVE * CS);  // [SYM_RING]
+    uint32_t* done = arrived + SYM_RING;                                                // [SYM_RING] uses completed
+    const int g = blockIdx.x;
+    int64_t u = sc.begin(g);
+    const int64_t u1 = sc.begin(g + 1);
+    if (u >= u1) {  // uniform over the work-group; an empty range (more work-groups than units)
+        if (threadIdx.x == 0) first[g] = INT32_MAX;
+        return;
+    }
+    if (threadIdx.x < 2 * SYM_RING) arrived[threadIdx.x] = 0u;  // arrived and done
+    __syncthreads();  // the only barrier
+    int I = sc.block_of(u);
+    if (threadIdx.x == 0) first[g] = I;
+    int64_t k = u - sc.base(I);
+    auto slice_of = [&](int I_, int64_t k_) { return SUB * SBC * (I_ + 1) + (int)(k_ - SBC); };
+    uint32_t nsym = 0;  // symmetric units done by this wave (the same sequence in every wave)
+    bool timed_out = false;
+    while (u < u1) {
+        const int rb = I * NW + wave;
+        double cxd[RPL], cyd[RPL], czd[RPL];
+        float nx[RPL], ny[RPL], nz[RPL], aS[RPL], aS2[RPL];
+        int rv[RPL][3];
+        float hi[RPL][NSYM], lo[RPL][NSYM];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = rb * ROWB + r * WAVE + lane;
+            cxd[r] = c64[3 * (size_t)i + 0];
+            cyd[r] = c64[3 * (size_t)i + 1];
+            czd[r] = c64[3 * (size_t)i + 2];
+            const ColRec me = cols[i];
+            nx[r] = me.nx; ny[r] = me.ny; nz[r] = me.nz; aS[r] = me.a; aS2[r] = -me.wv;
+            const int4 v = colv[i];
+            rv[r][0] = v.x; rv[r][1] = v.y; rv[r][2] = v.z;
+#pragma unroll
+            for (int a = 0; a < NSYM; ++a) { hi[r][a] = 0.f; lo[r][a] = 0.f; }
+        }
+        const uint32_t* my_touch = touch + (size_t)rb * touch_words;
+        const int64_t kn = sc.ua() - sc.ud() * I;  // units of super block I
+        const int64_t kend = min(kn, k + (u1 - u));
+        for (; k < kend; ++k, ++u) {
+            const int J = k < SBC ? SBC * I + (int)k : slice_of(I, k) / SUB;
+            const double ox = corg[3 * J + 0], oy = corg[3 * J + 1], oz = corg[3 * J + 2];
+            float rx[RPL], ry[RPL], rz[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                rx[r] = (float)(cxd[r] - ox);
+                ry[r] = (float)(cyd[r] - oy);
+                rz[r] = (float)(czd[r] - oz);
+            }
+            const bool masked = (my_touch[J >> 5] >> (J & 31)) & 1u;
+            if (k < SBC) {
+                const ColRec* tc = cols + (size_t)J * CHUNK;
+                const int4* tv = colv + (size_t)J * CHUNK;
+                if (masked) chunk_pass<6, GRAD, true, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                else chunk_pass<6, GRAD, false, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                continue;
+            }
+            // this wave's copy of the unit's columns (lane l: column l); the compiler fences keep
+            // the previous unit's reads of the copy before these writes and these writes before the
+            // reads below (LDS operations of one wave complete in order)
+            {
+                const size_t c = (size_t)slice_of(I, k) * SYM_COLS + lane;
+                const ColRec cr = cols[c];
+                const int4 cv = colv[c];
+                asm volatile("" ::: "memory");
+                lcol[lane] = cr;
+                lvid[lane] = cv;
+                asm volatile("" ::: "memory");
+            }
+            float ca[NA];
+            if (masked)
+                sym_chunk_pass<GRAD, true>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca);
+            else
+                sym_chunk_pass<GRAD, false>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca);
+            // the unit's slot: wait until its previous use (unit nsym - SYM_RING) has been reduced
+            const uint32_t slot = nsym % SYM_RING, use = nsym / SYM_RING;
+            for (uint32_t it = 0; !timed_out; ++it) {
+                if (__hip_atomic_load(&done[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == use) break;
+                if (it >= SYM_SPIN_LIMIT) timed_out = true;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            float* mine = ring + (((size_t)slot * NW + wave) * WAVE + ((lane + SYM_COLS - 1) & (SYM_COLS - 1))) * CS;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) mine[a] = ca[a];
+            uint32_t before = 0u;
+            if (lane == 0)  // after the wave's writes (release), counted once per wave
+                before = __hip_atomic_fetch_add(&arrived[slot], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            before = __builtin_amdgcn_readfirstlane(before);
+            if (before == (uint32_t)(NW - 1)) {  // the last wave: reduce in wave order, free the slot
+                const float* rbuf = ring + (size_t)slot * NW * WAVE * CS;
+                float* out = colpart + (size_t)(sc.base_sym(I) + k - SBC) * NA * SYM_COLS;
+                for (int e = lane; e < NA * SYM_COLS; e += WAVE) {
+                    const int a = e / SYM_COLS, j = e % SYM_COLS;
+                    float sum = 0.f;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) sum += rbuf[(w * SYM_COLS + j) * CS + a];
+                    out[e] = sum;
+                }
+                if (lane == 0) {
+                    __hip_atomic_store(&arrived[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&done[slot], use + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+            ++nsym;
+        }
+        float* o = part + ((size_t)(g + I) * NW + wave) * NA * ROWB + lane;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) o[(size_t)a * ROWB + r * WAVE] = hi[r][a] - lo[r][a];
+        ++I;
+        k = 0;
+    }
+    if (timed_out && lane == 0) atomicOr(flags, (uint32_t)FLAG_SYNC);
+}
+
 template <int NW>
 static size_t pair_sym_lds_bytes(bool grad) {
     return sizeof(float) * (grad ? sym_lds_floats<true, NW>() : sym_lds_floats<false, NW>());
@@ -704,8 +854,26 @@ static int sym_blocks_per_cu(bool grad) {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// resident work-groups per CU of the symmetric kernel with nw waves per work-group (1, 2 or 4)
-int pair_sym_blocks_per_cu(bool grad, int nw) {
+template <int NW>
+static size_t pair_sym_free_lds_bytes(bool grad) {
+    return sizeof(float) * (grad ? sym_free_lds_floats<true, NW>() : sym_free_lds_floats<false, NW>());
+}
+
+template <int NW>
+static int sym_free_blocks_per_cu(bool grad) {
+    int nb = 0;
+    hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_free_kernel<true, NW>,
+                                                                       WAVE * NW, pair_sym_free_lds_bytes<NW>(true))
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_free_kernel<false, NW>,
+                                                                       WAVE * NW, pair_sym_free_lds_bytes<NW>(false));
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+// resident work-groups per CU of the symmetric kernel with nw waves per work-group (1, 2 or 4),
+// with barriers or without (decoupled, nw >= 2)
+int pair_sym_blocks_per_cu(bool grad, int nw, bool decoupled) {
+    if (decoupled && nw == 2) return sym_free_blocks_per_cu<2>(grad);
+    if (decoupled && nw == 4) return sym_free_blocks_per_cu<4>(grad);
     return nw == 1 ? sym_blocks_per_cu<1>(grad) : nw == 2 ? sym_blocks_per_cu<2>(grad) : sym_blocks_per_cu<4>(grad);
 }
 
@@ -751,10 +919,28 @@ static void launch_sym_nw(bool grad, const ColRec* cols, const int4* colv, const
                            st, cols, c64, colv, org, touch, touch_words, sc, part, colpart, first);
 }
 
+template <int NW>
+static void launch_sym_free_nw(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                               const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
+                               int* first, uint32_t* flags, hipStream_t st) {
+    if (grad)
+        hipLaunchKernelGGL((pair_sym_free_kernel<true, NW>), dim3(sc.W), dim3(WAVE * NW), pair_sym_free_lds_bytes<NW>(true),
+                           st, cols, c64, colv, org, touch, touch_words, sc, part, colpart, first, flags);
+    else
+        hipLaunchKernelGGL((pair_sym_free_kernel<false, NW>), dim3(sc.W), dim3(WAVE * NW),
+                           pair_sym_free_lds_bytes<NW>(false), st, cols, c64, colv, org, touch, touch_words, sc, part,
+                           colpart, first, flags);
+}
+
+// decoupled: the kernel without work-group barriers (nw >= 2; the same bits)
 hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
-                           int* first, hipStream_t st) {
-    if (sc.nw == 1) launch_sym_nw<1>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
+                           int* first, bool decoupled, uint32_t* flags, hipStream_t st) {
+    if (decoupled && sc.nw == 2)
+        launch_sym_free_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
+    else if (decoupled && sc.nw == 4)
+        launch_sym_free_nw<4>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
+    else if (sc.nw == 1) launch_sym_nw<1>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
     else if (sc.nw == 2) launch_sym_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
     else if (sc.nw == 4) launch_sym_nw<4>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
     else return hipErrorInvalidValue;

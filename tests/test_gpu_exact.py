@@ -244,10 +244,38 @@ def test_symmetric_kernel(name, X, F, waves, nw):
         assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
 
 
+@pytest.mark.parametrize("name,X,F", list(_sym_cases())[1:], ids=lambda v: v if isinstance(v, str) else "")
+def test_symmetric_kernel_without_barriers_gives_the_same_bits(name, X, F):
+    """The barrier-free symmetric kernel (2 and 4 waves per work-group) reduces the waves' column
+    sums in the same order as the kernel with barriers: energy and gradient bit for bit, for
+    several work-group counts (one work-group for everything: the waves drift the furthest)."""
+    T = tpe()
+    Xd, Fd = upload(X, F)
+    ctx = T.context(Xd.device)
+    try:
+        for nw in (2, 4):
+            ctx.set_option(T.OPT_SYM_WAVES, nw)
+            for waves in (0, 1, 7):
+                ctx.set_option(T.OPT_TARGET_WAVES, waves)
+                res = []
+                for barriers in (1, 0):
+                    ctx.set_option(T.OPT_SYM_BARRIERS, barriers)
+                    E, G = T.gradient(Xd, Fd)
+                    Ee = T.energy(Xd, Fd)
+                    res.append((float(E.cpu()), G.cpu().numpy(), float(Ee.cpu())))
+                log(name, "nw", nw, "waves", waves, "E", res[0][0], res[1][0])
+                assert res[0][0] == res[1][0] and res[0][2] == res[1][2]
+                assert np.array_equal(res[0][1], res[1][1])
+    finally:
+        ctx.set_option(T.OPT_SYM_BARRIERS, 0)
+        ctx.set_option(T.OPT_TARGET_WAVES, 0)
+        ctx.set_option(T.OPT_SYM_WAVES, 0)
+
+
 def test_exact_plan_reports_the_kernel_choice():
-    """tpe_exact_plan: the fewest waves per work-group whose column partials fit in 8 GiB, the
-    partial bytes of the schedule (8 sums x 64 columns x 4 bytes per symmetric unit), the row-only
-    kernel when the symmetric one is switched off."""
+    """tpe_exact_plan: by default the barrier-free kernel with 4 waves per work-group; with barriers
+    the fewest waves whose column partials fit in 8 GiB; the partial bytes of the schedule (8 sums x
+    64 columns x 4 bytes per symmetric unit); the row-only kernel when the symmetric one is off."""
     T = tpe()
     import torch
     ctx = T.context(torch.device("cuda", 0))
@@ -258,16 +286,25 @@ def test_exact_plan_reports_the_kernel_choice():
         nsb, nch, sbc = fp // sb, fp // 64, 2 * nw
         return (nsb * (nch - sbc) - sbc * nsb * (nsb - 1) // 2) * 8 * 64 * 4
 
-    for nF, nw in ((20480, 1), (262144, 1), (327680, 2), (370688, 2), (400000, 4), (1310720, 4)):
+    sizes = (20480, 262144, 327680, 370688, 400000, 1310720)
+    for nF in sizes:
         sym, w, cp, scratch = ctx.exact_plan(nF, nF // 2 + 2, True)
         log("plan", nF, sym, w, cp, scratch)
-        assert sym and w == nw and cp == colpart(nF, nw) and scratch > cp
+        assert sym == 2 and w == 4 and cp == colpart(nF, 4) and scratch > cp
     try:
-        ctx.set_option(T.OPT_SYM_WAVES, 4)
-        assert ctx.exact_plan(20480, 10242, True)[1:3] == (4, colpart(20480, 4))
+        ctx.set_option(T.OPT_SYM_BARRIERS, 1)
+        for nF, nw in zip(sizes, (1, 1, 2, 2, 4, 4)):
+            sym, w, cp, _ = ctx.exact_plan(nF, nF // 2 + 2, True)
+            assert sym == 1 and w == nw and cp == colpart(nF, nw)
+        ctx.set_option(T.OPT_SYM_BARRIERS, 0)
+        ctx.set_option(T.OPT_SYM_WAVES, 1)
+        assert ctx.exact_plan(20480, 10242, True)[:3] == (1, 1, colpart(20480, 1))  # one wave: no barrier to drop
+        ctx.set_option(T.OPT_SYM_WAVES, 2)
+        assert ctx.exact_plan(20480, 10242, True)[:3] == (2, 2, colpart(20480, 2))
         ctx.set_option(T.OPT_SYMMETRIC, 0)
-        assert ctx.exact_plan(20480, 10242, True)[:3] == (False, 0, 0)
+        assert ctx.exact_plan(20480, 10242, True)[:3] == (0, 0, 0)
     finally:
+        ctx.set_option(T.OPT_SYM_BARRIERS, 0)
         ctx.set_option(T.OPT_SYM_WAVES, 0)
         ctx.set_option(T.OPT_SYMMETRIC, 1)
 
