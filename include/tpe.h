@@ -93,14 +93,16 @@ typedef enum {
                                  ordered pair from its row face (the row-only kernel).  Results
                                  agree to rounding.  The scratch stays allocated with the context
                                  (tpe_destroy frees it) */,
-    TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2 or 4 (super
-                                 blocks of 128, 256 or 512 faces; fewer waves write proportionally
-                                 more column partial sums).  0 (default): 4 without barriers (see
-                                 TPE_OPT_SYM_BARRIERS); with barriers, the fewest whose column
-                                 partial sums fit in 8 GiB (1 up to about 262,000 faces, then 2 up
-                                 to about 370,000, then 4), since fewer waves wait less at the
-                                 barriers.  tpe_exact_plan tells.  Results agree to rounding */,
-    TPE_OPT_SYM_BARRIERS = 7  /* 0 (default): the symmetric pair kernel with 2 or 4 waves per
+    TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2, 4 or 8 (super
+                                 blocks of 128 to 1,024 faces; fewer waves write proportionally
+                                 more column partial sums; 8 only without barriers).  0 (default):
+                                 4 without barriers (8 where the partials of 4 would exceed 64 GiB,
+                                 above about 1,480,000 faces; see TPE_OPT_SYM_BARRIERS); with
+                                 barriers, the fewest whose column partial sums fit in 8 GiB (1
+                                 up to about 262,000 faces, then 2 up to about 370,000, then 4),
+                                 since fewer waves wait less at the barriers.  tpe_exact_plan
+                                 tells.  Results agree to rounding */,
+    TPE_OPT_SYM_BARRIERS = 7  /* 0 (default): the symmetric pair kernel with 2, 4 or 8 waves per
                                  work-group runs without work-group barriers (each wave stages its
                                  own columns; the waves' column sums meet in a ring of LDS slots,
                                  reduced in wave order by the last wave to arrive); 1: with a

@@ -84,7 +84,8 @@ constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
 // 64.3 / 64.6 / 70.2 ms at 327,680 faces) but write 4 or 2 times the column partials, which the
 // merge reads back (the whole step: 67.1 / 66.2 / 71.2 ms); the fewest waves whose partials fit in
 // this budget are then taken (20,480 faces: 1 wave; 327,680 faces: 2, 6.2 GiB), else 4.  Without
-// barriers (the default) 4 waves run fastest at every size: 61.9 ms, step 62.9 ms.
+// barriers (the default) 4 waves run fastest at every size: 61.9 ms, step 62.9 ms (8 waves, with
+// half the partials: 63.7 ms; taken only where 4 would exceed SYM_MAX_COLPART_BYTES).
 constexpr int64_t SYM_FAST_COLPART_BYTES = (int64_t)8 << 30;
 hipError_t launch_pair_conf(bool grad, const ColRec* rcols, const double* rc64, const int4* rcolv,
                             const ColRec* ccols, const int4* ccolv, const double* corg, const Sched& sc, float* part,
@@ -199,8 +200,8 @@ struct tpe_ctx {
     int64_t target_waves = 0;     // 0: resident-wave capacity of the pair kernel
     int quad = 1;                 // quadrature points per face of the exact path (1, 3 or 6)
     int resident[2] = {0, 0};     // pair-kernel work-groups resident on the device (energy, gradient)
-    int resident_sym[3][2] = {};  // the same for the symmetric pair kernel, work-groups of 1, 2, 4 waves
-    int resident_symf[3][2] = {}; // the same for its barrier-free form (2 and 4 waves)
+    int resident_sym[4][2] = {};  // the same for the symmetric pair kernel, work-groups of 1, 2, 4 waves
+    int resident_symf[4][2] = {}; // the same for its barrier-free form (2, 4 and 8 waves)
     int sym_waves = 0;            // waves per work-group of the symmetric kernel (0: by size)
     bool sym_barriers = false;    // the symmetric kernel with work-group barriers (else barrier-free)
     bool symmetric = true;        // exact self energy (6, 12): symmetric pair kernel where it fits
@@ -480,7 +481,14 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
         // at every size, and the fewest column partials); with barriers the fewest waves whose
         // column partials fit in SYM_FAST_COLPART_BYTES
         int nw = ctx->sym_waves;
-        if (nw == 0 && !ctx->sym_barriers) nw = 4;
+        if (nw == 0 && !ctx->sym_barriers) {
+            // 8 waves only where 4 would exceed the partials' cap (half the partials, 4% slower)
+            const int64_t Fs4 = round_up(P.nR, (int64_t)4 * ROWB);
+            nw = sym_colpart_floats(make_sym_sched(Fs4, 1, 0, 4), grad) * (int64_t)sizeof(float) <=
+                         SYM_MAX_COLPART_BYTES
+                     ? 4
+                     : 8;
+        }
         if (nw == 0) {
             nw = 4;
             for (int cand = 1; cand < 4; cand *= 2) {
@@ -496,9 +504,10 @@ void plan(Plan& P, const tpe_ctx* ctx, int64_t nF, int64_t V, bool grad, int tre
         // would get (the hardware refills the slots of early finishers, which evens out the
         // finish times; more work-groups add row segments for the merge to read), then one
         // single-unit work-group per resident slot for the end of the launch
+        if (nw == 8 && ctx->sym_barriers) nw = 4;  // 8 waves only without barriers
         const bool decoupled = nw >= 2 && !ctx->sym_barriers;
-        const int resident = (decoupled ? ctx->resident_symf : ctx->resident_sym)[nw == 1 ? 0 : nw == 2 ? 1 : 2]
-                                                                                   [grad ? 1 : 0];
+        const int resident = std::max(1, (decoupled ? ctx->resident_symf : ctx->resident_sym)
+                                             [nw == 1 ? 0 : nw == 2 ? 1 : nw == 4 ? 2 : 3][grad ? 1 : 0]);
         int W = resident, tail = 0;
         if (ctx->target_waves > 0) {
             W = (int)ctx->target_waves;
@@ -819,7 +828,7 @@ int tpe_create(tpe_ctx** out, int device, void* hip_stream) {
             ncu = 1;
         ctx->resident[0] = ncu * pair_blocks_per_cu(false);
         ctx->resident[1] = ncu * pair_blocks_per_cu(true);
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             ctx->resident_sym[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k, false);
             ctx->resident_sym[k][1] = ncu * pair_sym_blocks_per_cu(true, 1 << k, false);
             ctx->resident_symf[k][0] = ncu * pair_sym_blocks_per_cu(false, 1 << k, true);
@@ -891,8 +900,8 @@ int tpe_set_option(tpe_ctx* ctx, int option, int64_t value) {
             ctx->symmetric = value != 0;
             return TPE_OK;
         case TPE_OPT_SYM_WAVES:
-            if (value != 0 && value != 1 && value != 2 && value != 4)
-                return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric kernel waves: 0, 1, 2 or 4");
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+                return fail(ctx, TPE_ERR_INVALID_ARG, "symmetric kernel waves: 0, 1, 2, 4 or 8");
             ctx->sym_waves = (int)value;
             return TPE_OK;
         case TPE_OPT_SYM_BARRIERS:

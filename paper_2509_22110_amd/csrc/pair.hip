@@ -869,11 +869,13 @@ static int sym_free_blocks_per_cu(bool grad) {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// resident work-groups per CU of the symmetric kernel with nw waves per work-group (1, 2 or 4),
-// with barriers or without (decoupled, nw >= 2)
+// resident work-groups per CU of the symmetric kernel with nw waves per work-group (1, 2, 4; 8
+// without barriers), with barriers or without (decoupled, nw >= 2)
 int pair_sym_blocks_per_cu(bool grad, int nw, bool decoupled) {
     if (decoupled && nw == 2) return sym_free_blocks_per_cu<2>(grad);
     if (decoupled && nw == 4) return sym_free_blocks_per_cu<4>(grad);
+    if (decoupled && nw == 8) return sym_free_blocks_per_cu<8>(grad);
+    if (nw == 8) return 0;  // 8 waves only without barriers
     return nw == 1 ? sym_blocks_per_cu<1>(grad) : nw == 2 ? sym_blocks_per_cu<2>(grad) : sym_blocks_per_cu<4>(grad);
 }
 
@@ -940,6 +942,8 @@ hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, cons
         launch_sym_free_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
     else if (decoupled && sc.nw == 4)
         launch_sym_free_nw<4>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
+    else if (decoupled && sc.nw == 8)
+        launch_sym_free_nw<8>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
     else if (sc.nw == 1) launch_sym_nw<1>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
     else if (sc.nw == 2) launch_sym_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);
     else if (sc.nw == 4) launch_sym_nw<4>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, st);

@@ -88,7 +88,7 @@ static void check(int64_t nF, int nw, int W, int tail) {
 int main() {
     int runs = 0;
     const int64_t sizes[] = {1, 20, 127, 128, 129, 320, 1280, 2001, 5000, 20480, 81920, 327680, 1310720};
-    for (int nw : {1, 2, 4})
+    for (int nw : {1, 2, 4, 8})
         for (int64_t nF : sizes)
             for (int W : {1, 7, 1024, 4096, 32768})
                 for (int tail : {0, 1, W}) {

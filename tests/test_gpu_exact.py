@@ -216,10 +216,10 @@ def _sym_cases():
 
 @pytest.mark.parametrize("name,X,F", list(_sym_cases()), ids=lambda v: v if isinstance(v, str) else "")
 @pytest.mark.parametrize("waves", [0, 1, 7, 100000])
-@pytest.mark.parametrize("nw", [1, 2, 4])
+@pytest.mark.parametrize("nw", [1, 2, 4, 8])
 def test_symmetric_kernel(name, X, F, waves, nw):
-    """The symmetric pair kernel (default for (6, 12)) with work-groups of 1, 2 and 4 waves, and the
-    row-only kernel, against the oracle, for several work-group counts (uneven ranges, empty ranges,
+    """The symmetric pair kernel (default for (6, 12)) with work-groups of 1, 2, 4 and 8 waves, and
+    the row-only kernel, against the oracle, for several work-group counts (uneven ranges, empty ranges,
     one work-group for everything)."""
     T = tpe()
     Eo, Go = oracle.gradient(X, F)
@@ -273,7 +273,8 @@ def test_symmetric_kernel_without_barriers_gives_the_same_bits(name, X, F):
 
 
 def test_exact_plan_reports_the_kernel_choice():
-    """tpe_exact_plan: by default the barrier-free kernel with 4 waves per work-group; with barriers
+    """tpe_exact_plan: by default the barrier-free kernel with 4 waves per work-group (8 where the
+    partials of 4 would exceed 64 GiB); with barriers
     the fewest waves whose column partials fit in 8 GiB; the partial bytes of the schedule (8 sums x
     64 columns x 4 bytes per symmetric unit); the row-only kernel when the symmetric one is off."""
     T = tpe()
@@ -287,10 +288,10 @@ def test_exact_plan_reports_the_kernel_choice():
         return (nsb * (nch - sbc) - sbc * nsb * (nsb - 1) // 2) * 8 * 64 * 4
 
     sizes = (20480, 262144, 327680, 370688, 400000, 1310720)
-    for nF in sizes:
+    for nF, nw in zip(sizes + (1500000, 2000000), (4, 4, 4, 4, 4, 4, 8, 8)):  # 8 beyond 64 GiB at 4
         sym, w, cp, scratch = ctx.exact_plan(nF, nF // 2 + 2, True)
         log("plan", nF, sym, w, cp, scratch)
-        assert sym == 2 and w == 4 and cp == colpart(nF, 4) and scratch > cp
+        assert sym == 2 and w == nw and cp == colpart(nF, nw) and scratch > cp
     try:
         ctx.set_option(T.OPT_SYM_BARRIERS, 1)
         for nF, nw in zip(sizes, (1, 1, 2, 2, 4, 4)):
@@ -313,7 +314,7 @@ def test_symmetric_waves_option_rejects_other_values():
     T = tpe()
     import torch
     ctx = T.context(torch.device("cuda", 0))
-    for bad in (3, 8, -1):
+    for bad in (3, 16, -1):
         with pytest.raises(T.TPEError):
             ctx.set_option(T.OPT_SYM_WAVES, bad)
 
