@@ -43,6 +43,12 @@ HBM_PEAK_GBS = 8000.0
 FINALIZE_GATHER_BYTES_PER_FACE = 276 + 98
 
 
+def sym_kernel_name(ctx, cfg):
+    """The exact pair kernel the library runs for this mesh (tpe_exact_plan)."""
+    sym, nw, _, _ = ctx.exact_plan(cfg.nF, cfg.V, True)
+    return {2: f"pair_sym_free_kernel<true, {nw}>", 1: f"pair_sym_kernel<true, {nw}>"}.get(sym, "pair_kernel<6,true>")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -474,7 +480,7 @@ def main():
     exec_flop = summary_float(fl, "flop_per_launch")
     roofline = {"bound": "alu", "achieved": round(ex["tflops"], 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ex["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": summary_float(tr, "bytes_per_launch"), "kernel": "pair_sym_kernel<true>",
+                "traffic": summary_float(tr, "bytes_per_launch"), "kernel": sym_kernel_name(ctx, cfg),
                 "kernel_avg_ms": round(ex["kernel_avg_ms"], 4), "kernel_launches": ex["kernel_launches"],
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": P,
                 "executed_flop_per_pair": round(exec_flop / P, 2) if exec_flop else None,
@@ -501,7 +507,7 @@ def main():
         c2 = exact_leg(T, M, torch, dev, "C2", 200, 5)
         out["c2"] = {"workload": f"C2: {c2['cfg'].name} ({c2['cfg'].nF} faces), exact energy+gradient",
                      "pairs": c2["P"], "ms_per_step": round(c2["ms_per_step"], 4), "pairs_per_s": c2["value"],
-                     "kernel": "pair_sym_kernel<true>", "kernel_avg_ms": round(c2["kernel_avg_ms"], 4),
+                     "kernel": sym_kernel_name(ctx, c2["cfg"]), "kernel_avg_ms": round(c2["kernel_avg_ms"], 4),
                      "achieved": round(c2["tflops"], 3),
                      "frac": round(c2["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4)}
         if not args.no_row_only:
