@@ -88,8 +88,8 @@ typedef enum {
     TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
                                  every unordered pair of faces once and credit both faces (the
                                  symmetric pair kernel), while its column partial sums fit in 64 GiB
-                                 of the context's scratch (about 1,430,000 faces with the gradient)
-                                 and that scratch can be allocated; 0, or beyond that: every
+                                 of the context's scratch (about 2,100,000 faces with 8 waves per
+                                 work-group, 1,480,000 with 4) and that scratch can be allocated; 0, or beyond that: every
                                  ordered pair from its row face (the row-only kernel).  Results
                                  agree to rounding.  The scratch stays allocated with the context
                                  (tpe_destroy frees it) */,

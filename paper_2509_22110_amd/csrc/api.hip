@@ -76,8 +76,8 @@ hipError_t launch_dual(int H, int leaf, float theta, const ColRec* cols, const i
                        uint32_t* rel, uint32_t* ent, uint32_t* scanws, double* adj, float* part, double* acc64,
                        uint32_t* flags, unsigned long long* stats, uint32_t* const sort[6], hipStream_t st);
 // the symmetric kernel is used while its column partials (32 B per face and earlier super block)
-// fit in this many bytes: about 1,430,000 faces with super blocks of 512 faces, of the GPU's 288 GB
-// of HBM; if the allocation fails the call runs the row-only kernel instead
+// fit in this many bytes (of the GPU's 288 GB of HBM): about 1,480,000 faces with super blocks of 512
+// faces, about 2,100,000 with 1,024; if the allocation fails the call runs the row-only kernel instead
 constexpr int64_t SYM_MAX_COLPART_BYTES = (int64_t)64 << 30;
 // With work-group barriers (TPE_OPT_SYM_BARRIERS = 1), work-groups of 1 or 2 waves (super blocks of
 // 128 or 256 faces) run the symmetric kernel faster than 4 (each wave waits less at the barriers:
