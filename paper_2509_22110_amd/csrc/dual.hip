@@ -190,6 +190,8 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
     const uint32_t* __restrict__ order) {
     __shared__ float red[DUAL_NW - 1][2 * NACC][64];
     __shared__ unsigned long long wpairs[DUAL_NW];
+    __shared__ ColRec nst[DUAL_NW][64];
+    __shared__ int4 nsv[DUAL_NW][64];
     const int split = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -219,9 +221,11 @@ __global__ __launch_bounds__(64 * DUAL_NW) void dual_near_eval(
         // vertex balls apart (with FP32 slack): no face of B shares a vertex with a face of A
         const bool disjoint = sqrtf(dx * dx + dy * dy + dz * dz) * (1.f - 1e-5f) > a.r + b.r;
         if (disjoint)
-            ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+            ff_near_staged<false, 2>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane, acc,
+                                     hi, lo, cnt);
         else
-            ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+            ff_near_staged<true, 2>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane, acc,
+                                    hi, lo, cnt);
     }
     ff_fold(acc, hi, lo);
     if (wave > 0) {

@@ -181,7 +181,7 @@ __device__ __forceinline__ void pair_update_gen(const ColRec& cr, int4 cv, float
 // Kahan fold into the rows' (hi, lo) accumulators.
 // FOLDV (gradient only): fold the chunk's sums into the symmetric kernel's 8-sum layout K, S0,
 // Sd, V = Sn - 2 Sdd (see pair_sym_kernel) instead of the 11 row sums.
-template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false, bool FOLDV = false, int NH>
+template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false, bool FOLDV = false, int UNR = 4, int NH>
 __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ tc, const int4* __restrict__ tv,
                                            const float (&rx)[RPL], const float (&ry)[RPL],
                                            const float (&rz)[RPL], const float (&nx)[RPL],
@@ -195,7 +195,7 @@ __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ 
     for (int r = 0; r < RPL; ++r)
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[r][k] = 0.f;
-#pragma unroll 4
+#pragma unroll UNR
     for (int j = 0; j < CHUNK; ++j) {
         const ColRec cr = tc[j];
         int4 cv = make_int4(0, 0, 0, 0);
@@ -228,6 +228,13 @@ __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ 
 // waves' compensated sums folded into wave 0's).
 // Rows come from (rcols, rc64, rcolv), columns from (ccols, ccolv, corg): the same arrays for the
 // self energy, the confining surface's for CONF (no exclusion map then).
+// LDS floats of one wave's column slots: CHUNK records and their vertex ids
+constexpr int PAIR_STAGE_FLOATS = CHUNK * (int)((sizeof(ColRec) + sizeof(int4)) / sizeof(float));
+static_assert(CHUNK == WAVE, "one column record per lane");
+// columns per unrolled step of the row kernel: the columns now come from LDS into VGPRs
+constexpr int PAIR_UNR = 2;
+static_assert(PAIR_STAGE_FLOATS <= 2 * NACC * ROWB, "slots inside a wave's hand-over area");
+
 template <int Q, bool GRAD, bool CONF = false, bool GEN = false>
 // at least 4 waves per SIMD (128 VGPRs): the few values the generic kernel then keeps in scratch are
 // touched once per chunk, outside the column loop
@@ -247,6 +254,14 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) __attribute__((amdgpu_waves_per_eu(
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform (SGPR)
     const int g = blockIdx.x;
+    // the wave's column slots: with the gradient wave w > 0 uses its own hand-over area (written
+    // only after its last chunk of a segment, read by wave 0 between the segment's two barriers) and
+    // wave 0 the space after them; without it every wave's slots follow the hand-over areas
+    float* stg = red_lds + (size_t)(PAIR_NW - 1) * 2 * NA * ROWB;
+    if constexpr (GRAD) stg = wave == 0 ? stg : red_lds + (size_t)(wave - 1) * 2 * NA * ROWB;
+    else stg += (size_t)wave * PAIR_STAGE_FLOATS;
+    ColRec* scol = reinterpret_cast<ColRec*>(stg);
+    int4* sver = reinterpret_cast<int4*>(stg + CHUNK * (sizeof(ColRec) / sizeof(float)));
     int64_t u = sc.begin(g);
     const int64_t u1 = sc.begin(g + 1);
     int seg = 0;
@@ -289,16 +304,28 @@ __global__ __launch_bounds__(WAVE * PAIR_NW) __attribute__((amdgpu_waves_per_eu(
                 }
                 cur_t = t;
             }
-            const ColRec* tc = ccols + (size_t)cu * CHUNK;
-            const int4* tv = ccolv + (size_t)cu * CHUNK;
+            const bool masked = !CONF && ((my_touch[cu >> 5] >> (cu & 31)) & 1u);
+            {
+                // the chunk's records (one per lane; the column arrays are padded to whole chunks)
+                // through the wave's LDS slots, read back column by column as broadcasts
+                const float4* src = reinterpret_cast<const float4*>(ccols + (size_t)cu * CHUNK + lane);
+                const float4 c0 = src[0], c1 = src[1];
+                int4 v = make_int4(0, 0, 0, 0);
+                if (masked) v = ccolv[(size_t)cu * CHUNK + lane];
+                asm volatile("" ::: "memory");  // the previous chunk's reads of the slots come first
+                float4* dst = reinterpret_cast<float4*>(scol + lane);
+                dst[0] = c0;
+                dst[1] = c1;
+                if (masked) sver[lane] = v;
+                asm volatile("" ::: "memory");  // the reads below see every lane's record
+            }
             if constexpr (CONF) {
-                chunk_pass<Q, GRAD, false, true>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                chunk_pass<Q, GRAD, false, true, false, false, PAIR_UNR>(mneg, scol, sver, rx, ry, rz, nx, ny, nz, rv, hi, lo);
             } else {
-                const bool masked = (my_touch[cu >> 5] >> (cu & 31)) & 1u;
                 if (masked)
-                    chunk_pass<Q, GRAD, true, false, GEN>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                    chunk_pass<Q, GRAD, true, false, GEN, false, PAIR_UNR>(mneg, scol, sver, rx, ry, rz, nx, ny, nz, rv, hi, lo);
                 else
-                    chunk_pass<Q, GRAD, false, false, GEN>(mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                    chunk_pass<Q, GRAD, false, false, GEN, false, PAIR_UNR>(mneg, scol, sver, rx, ry, rz, nx, ny, nz, rv, hi, lo);
             }
         }
         if (wave > 0) {
@@ -951,7 +978,9 @@ hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, cons
     return hipGetLastError();
 }
 
-static size_t pair_lds_bytes(bool grad) { return sizeof(float) * (PAIR_NW - 1) * 2 * (grad ? NACC : 1) * ROWB; }
+static size_t pair_lds_bytes(bool grad) {
+    return sizeof(float) * ((PAIR_NW - 1) * 2 * (grad ? NACC : 1) * ROWB + (grad ? 1 : PAIR_NW) * PAIR_STAGE_FLOATS);
+}
 
 int pair_blocks_per_cu(bool grad) {
     int nb = 0;

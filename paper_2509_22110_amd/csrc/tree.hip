@@ -640,10 +640,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
         for (uint32_t base = 0; base < nfw; base += 64) {
             const uint32_t m = nfw - base < 64u ? nfw - base : 64u;
-            NodeRec nl = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if ((uint32_t)lane < m) nl = nodes[e[cap - 1 - ((uint32_t)wave + NW * (base + (uint32_t)lane))]];
+            // the record as two float4 halves (a whole-struct copy under the condition went
+            // through scratch memory)
+            float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+            if ((uint32_t)lane < m) {
+                const float4* src = reinterpret_cast<const float4*>(
+                    nodes + e[cap - 1 - ((uint32_t)wave + NW * (base + (uint32_t)lane))]);
+                n0 = src[0];
+                n1 = src[1];
+            }
             lds_phase();  // the previous batch's reads of fst come first
-            fst[wave][lane] = nl;
+            float4* dst = reinterpret_cast<float4*>(&fst[wave][lane]);
+            dst[0] = n0;
+            dst[1] = n1;
             lds_phase();  // the reads below see every lane's record
             for (uint32_t k = 0; k < m; ++k) {
                 const NodeRec nd = fst[wave][k];
@@ -656,6 +665,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     // near nodes: exact pairs over their faces, with the shared-vertex test only where the node
     // holds a leaf of the block's neighbour list; without that list (curved elements, or more than
     // NBL_MAX such leaves) only where their vertex balls can meet (conservative margin for FP32)
+    __shared__ ColRec nst[NW][64];
+    __shared__ int4 nsv[NW][64];
     const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
     // lane m < nn holds neighbour leaf m (the test of a node is then one compare and a ballot)
     const uint32_t my_leaf = nn <= (uint32_t)NBL_MAX && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane]
@@ -674,10 +685,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
             const NodeRec nd = nodes[kk];
             disjoint = ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r;
         }
+        // columns per step: 2 keep the monopole evaluation within 128 VGPRs (4 waves per SIMD); the
+        // learned evaluation runs at 3 either way and prefers 4
+        constexpr int SU = LEARNED ? 4 : 2;
         if (disjoint)
-            ff_near_range<false>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+            ff_near_staged<false, SU>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
+                                      acc, hi, lo, cnt);
         else
-            ff_near_range<true>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, acc, hi, lo, cnt);
+            ff_near_staged<true, SU>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
+                                     acc, hi, lo, cnt);
     }
     ff_fold(acc, hi, lo);
     if constexpr (NW > 1) {
