@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-row-only", action="store_true", help="skip the row-only kernel comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the confinement, quadrature, exponent and curved-element timings")
-    ap.add_argument("--ff-reps", type=int, default=5)
+    ap.add_argument("--ff-reps", type=int, default=20)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2509_22110_amd", "data", "farfield_mlp.bin"))
     return ap.parse_args()
@@ -179,8 +179,14 @@ def farfield_leg(args, T, torch, dev, ex):
     cfg, X, F, G0, E0 = ex["cfg"], ex["X"], ex["F"], ex["G"], ex["E"]
 
     def timed(fn, reps):
-        fn()
+        # at least 100 ms of warm-up calls (the GPU's clock ramps up over the first tens of
+        # milliseconds of load), then `reps` calls back to back
         torch.cuda.synchronize()
+        t_w = time.perf_counter()
+        while time.perf_counter() - t_w < 0.1:
+            for _ in range(4):
+                fn()
+            torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
             out = fn()
@@ -217,10 +223,16 @@ def farfield_leg(args, T, torch, dev, ex):
     E = torch.empty((), dtype=torch.float64, device=dev)
 
     def variant(mlp):
+        def call():
+            T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E)
+
+        t, _ = timed(call, args.ff_reps)
+        # the evaluation kernel's own time: HIP events around its launches, in a second pass
         ctx.set_option(T.OPT_KERNEL_TIMING, 1)
-        T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E)
+        call()
         ctx.kernel_time()
-        t, _ = timed(lambda: T.farfield(tree, X, F, theta=args.theta, mlp=mlp, out=G, energy_out=E), args.ff_reps)
+        for _ in range(args.ff_reps):
+            call()
         k_ms, k_n = ctx.kernel_time()
         ctx.set_option(T.OPT_KERNEL_TIMING, 0)
         st = ctx.farfield_stats()
