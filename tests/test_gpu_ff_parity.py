@@ -63,6 +63,33 @@ def test_farfield_is_the_oracles(name, theta):
     assert float(E2.cpu()) == float(E.cpu()) and np.array_equal(G2.cpu().numpy(), G.cpu().numpy())
 
 
+def _ragged_patch():
+    """An open patch of 2,001 faces cut from a deformed level-4 sphere (the faces nearest one
+    vertex): the last leaf is short, and the near pieces and tiles have odd lengths."""
+    X, F = M.icosphere(4)
+    X = M.sh_deform(X, 2, 6, 0.05, 3)[0]
+    c = X[F].mean(1)
+    sel = np.sort(np.argsort(np.linalg.norm(c - X[7], axis=1), kind="stable")[:2001])
+    used, inv = np.unique(F[sel], return_inverse=True)
+    return X[used].copy(), inv.reshape(-1, 3).astype(np.int32)
+
+
+@pytest.mark.parametrize("leaf", [32, 7])
+def test_farfield_on_a_ragged_open_patch_is_the_oracles(leaf):
+    T = tpe()
+    X, F = _ragged_patch()
+    log("farfield ragged patch", F.shape[0], "faces, leaf", leaf)
+    Eo, Go, so = oracle.farfield(X, F, 0.5, leaf=leaf)
+    Xd, Fd = upload(X, F)
+    tree = T.build_tree(Xd, Fd, leaf=leaf)
+    E, G = T.farfield(tree, Xd, Fd, theta=0.5)
+    st = T.context(Xd.device).farfield_stats()
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("  stats gpu", st, "oracle", so, "rel E", eE, "rel G", eG)
+    assert so[0] > 0 and tuple(st) == tuple(so)
+    assert eE <= 1e-6 and eG <= 1e-5
+
+
 @pytest.mark.parametrize("name,theta,nsample", [("L3", 1.0, 0), ("L4", 0.5, 96), ("C2", 0.5, 48)])
 def test_farfield_dual_is_the_oracles(name, theta, nsample):
     T = tpe()
