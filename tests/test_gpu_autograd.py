@@ -115,7 +115,9 @@ def test_flow_with_farfield_judge():
     tree = T.build_tree(Xd, Fd)
     rec = gradient_flow(Xd, Fd, 10, 1e-3, scale=SCALE, tree=tree, theta=0.5, judge_every=5)
     log("far-field flow judge", rec.judge)
-    assert len(rec.judge) == 2 and all(e < 0.5 for _, e in rec.judge)
+    # the far field's own error at C2, theta 0.5 (5.8e-6 at the start, 6.4e-6 after 5 steps), with
+    # margin: the flow does not move the mesh out of the regime the error was measured in
+    assert len(rec.judge) == 2 and all(e < 2e-5 for _, e in rec.judge)
 
 
 def test_autograd_farfield_backward_at_theta_half():
