@@ -111,6 +111,37 @@ def test_farfield_dual_is_the_oracles(name, theta, nsample):
     assert eE <= 1e-6 and eG <= 1e-5
 
 
+def test_farfield_and_dual_at_level_7_are_the_oracles():
+    """The level-7 workload of the far-field timing (327,680 faces, theta 0.5, leaves of 32):
+    the monopole far field element by element against the FP64 oracle of the scheme (every
+    vertex; about 8 s of oracle on 8 host threads), and the dual tree's energy and gradient at 32
+    sampled vertices (about 45 s of oracle: its energy needs every pair of the lists)."""
+    T = tpe()
+    c = M.make_config("C4")
+    X, F = c.X, c.F
+    perm = oracle.kd_order(X, F, 32)
+    log("level 7: oracle far field")
+    Eo, Go, so = oracle.farfield(X, F, 0.5, leaf=32, perm=perm)
+    Xd, Fd = upload(X, F)
+    tree = T.build_tree(Xd, Fd, leaf=32)
+    assert np.array_equal(tree.order().cpu().numpy().view(np.uint32), perm)
+    E, G = T.farfield(tree, Xd, Fd, theta=0.5)
+    st = T.context(Xd.device).farfield_stats()
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("  far field: stats gpu", st, "oracle", so, "rel E", eE, "rel G", eG)
+    assert tuple(st) == tuple(so)
+    assert eE <= 1e-6 and eG <= 1e-5
+    verts = np.random.default_rng(1).choice(X.shape[0], 32, replace=False)
+    log("level 7: oracle dual tree")
+    Eo, Go, so = oracle.farfield_dual(X, F, 0.5, leaf=32, perm=perm, verts=verts)
+    E, G = T.farfield_dual(tree, Xd, Fd, theta=0.5)
+    st = T.context(Xd.device).farfield_stats()
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy()[verts], Go)
+    log("  dual: stats gpu", st[:2], "oracle", so, "rel E", eE, "rel G", eG)
+    assert tuple(st[:2]) == tuple(so)
+    assert eE <= 1e-6 and eG <= 1e-5
+
+
 # Tolerances of the samples.  Features are dimensionless FP32 quantities of size <= 4 built from
 # FP32 centroids (relative rounding 2^-24 of coordinates <= 1 against distances >= 0.05 in the
 # kernels' frame) and FP32 moments: 2e-5 absolute, except where n_S is nearly parallel to e1 and
