@@ -104,6 +104,12 @@ def _load():
         lib.tpeo_farfield_samples.restype = I64
         lib.tpeo_farfield_dual.argtypes = [P, I64, P, I64, P, I32, D, D, D, D, P, I64, I32, P, P, P]
         lib.tpeo_farfield_dual.restype = I32
+        lib.tpeo_kd_order_p3.argtypes = [P, I64, P, I64, P, I32, I32, P]
+        lib.tpeo_kd_order_p3.restype = I32
+        lib.tpeo_farfield_p3.argtypes = [P, I64, P, I64, P, P, I32, P, I32, D, D, D, D, I32, P, P, P]
+        lib.tpeo_farfield_p3.restype = I32
+        lib.tpeo_farfield_coverage_p3.argtypes = [P, I64, P, I64, P, P, I32, P, I32, D, P]
+        lib.tpeo_farfield_coverage_p3.restype = I32
         for f in (lib.tpeo_energy, lib.tpeo_energy_rows, lib.tpeo_gradient, lib.tpeo_gradient_at):
             f.restype = I32
         _lib = lib
@@ -296,6 +302,59 @@ def farfield(X, F, theta, leaf=32, perm=None, q=6.0, p=12.0, scale=1.0, nthreads
     if rc:
         raise OracleError(rc)
     return float(E[0]), G, tuple(int(v) for v in st)
+
+
+def _rule(rule):
+    b, w = quad_rule(rule)
+    return np.ascontiguousarray(b, dtype=np.float64), np.ascontiguousarray(w, dtype=np.float64)
+
+
+def kd_order_p3(X, F10, rule, leaf=32):
+    """Tree order of the quadrature records of curved elements (record r = rule e + k: point k of
+    element e; position -> record, uint32 [nF rule]), the k-d ordering of their positions."""
+    X, F10 = _prep10(X, F10)
+    b, _ = _rule(rule)
+    perm = np.zeros(F10.shape[0] * len(b), dtype=np.uint32)
+    rc = _load().tpeo_kd_order_p3(X.ctypes.data, X.shape[0], F10.ctypes.data, F10.shape[0], b.ctypes.data, len(b),
+                                  int(leaf), perm.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return perm
+
+
+def farfield_p3(X, F10, theta, rule, leaf=32, perm=None, q=6.0, p=12.0, scale=1.0, nthreads=0, want_grad=True):
+    """(E, G, stats) of the clustering of the inner integrals on curved cubic elements, over the
+    records of the `rule`-point quadrature (see tpe_oracle_ff.c); stats as for farfield."""
+    X, F10 = _prep10(X, F10)
+    b, w = _rule(rule)
+    if perm is None:
+        perm = kd_order_p3(X, F10, rule, leaf)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    E = np.zeros(1)
+    G = np.zeros_like(X) if want_grad else None
+    st = np.zeros(6, dtype=np.int64)
+    rc = _load().tpeo_farfield_p3(X.ctypes.data, X.shape[0], F10.ctypes.data, F10.shape[0], b.ctypes.data,
+                                  w.ctypes.data, len(b), perm.ctypes.data, int(leaf), float(theta), q, p, scale,
+                                  nthreads, E.ctypes.data, G.ctypes.data if want_grad else None, st.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(E[0]), G, tuple(int(v) for v in st)
+
+
+def farfield_coverage_p3(X, F10, theta, rule, leaf=32, perm=None):
+    """farfield_coverage on the records of curved elements."""
+    X, F10 = _prep10(X, F10)
+    b, w = _rule(rule)
+    if perm is None:
+        perm = kd_order_p3(X, F10, rule, leaf)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    out = np.zeros(2, dtype=np.int64)
+    rc = _load().tpeo_farfield_coverage_p3(X.ctypes.data, X.shape[0], F10.ctypes.data, F10.shape[0], b.ctypes.data,
+                                           w.ctypes.data, len(b), perm.ctypes.data, int(leaf), float(theta),
+                                           out.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return int(out[0]), int(out[1])
 
 
 def farfield_coverage(X, F, theta, leaf=32, perm=None):

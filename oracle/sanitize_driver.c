@@ -36,6 +36,12 @@ int64_t tpeo_farfield_samples(const double*, int64_t, const int32_t*, int64_t, c
                               uint64_t, double, int64_t, int64_t, int32_t*, int32_t*, double*, double*);
 int tpeo_farfield_dual(const double*, int64_t, const int32_t*, int64_t, const uint32_t*, int, double, double,
                        double, double, const int32_t*, int64_t, int, double*, double*, int64_t*);
+int tpeo_quad_rule(int, double*, double*);
+int tpeo_kd_order_p3(const double*, int64_t, const int32_t*, int64_t, const double*, int, int, uint32_t*);
+int tpeo_farfield_p3(const double*, int64_t, const int32_t*, int64_t, const double*, const double*, int,
+                     const uint32_t*, int, double, double, double, double, int, double*, double*, int64_t*);
+int tpeo_farfield_coverage_p3(const double*, int64_t, const int32_t*, int64_t, const double*, const double*, int,
+                              const uint32_t*, int, double, int64_t*);
 
 typedef struct { int64_t V, nF; double* X; int32_t* F; } mesh;
 
@@ -127,7 +133,22 @@ int main(int argc, char** argv) {
     rc = tpeo_farfield_dual(m.X, m.V, m.F, m.nF, perm, leaf, 1.0, q, p, sc, NULL, m.V, nt, &E, G, st2);
     printf("farfield_dual %d %.17g %.17g %lld %lld\n", rc, E, abs_sum(G, n3), (long long)st2[0], (long long)st2[1]);
 
-    free(perm); free(Gc); free(G);
+    double bq[18], wq[6];
+    const int nq = tpeo_quad_rule(3, bq, wq);
+    uint32_t* perm3 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)c.nF * (size_t)nq);
+    rc = tpeo_kd_order_p3(c.X, c.V, c.F, c.nF, bq, nq, 8, perm3);
+    h = 1469598103934665603ull;
+    for (int64_t i = 0; i < c.nF * nq; ++i) h = (h ^ perm3[i]) * 1099511628211ull;
+    printf("kd_order_p3 %d %llu\n", rc, (unsigned long long)h);
+    int64_t st3[6] = {0};
+    rc = tpeo_farfield_p3(c.X, c.V, c.F, c.nF, bq, wq, nq, perm3, 8, 1.0, q, p, sc, nt, &E, Gc, st3);
+    printf("farfield_p3 %d %.17g %.17g %lld %lld %lld\n", rc, E, abs_sum(Gc, 3 * (size_t)c.V), (long long)st3[0],
+           (long long)st3[1], (long long)st3[2]);
+    int64_t cov3[2] = {-1, -1};
+    rc = tpeo_farfield_coverage_p3(c.X, c.V, c.F, c.nF, bq, wq, nq, perm3, 8, 1.0, cov3);
+    printf("farfield_coverage_p3 %d %lld %lld\n", rc, (long long)cov3[0], (long long)cov3[1]);
+
+    free(perm3); free(perm); free(Gc); free(G);
     free(m.X); free(m.F); free(y.X); free(y.F); free(c.X); free(c.F);
     return 0;
 }

@@ -666,6 +666,12 @@ static void p3_eval(const double* P, const double* l, double* x, double* xs, dou
     }
 }
 
+/* The basis at barycentric l (for the far-field oracle's curved records; pinned with the map). */
+int tpeo_p3_basis(const double* l, double* phi, double* ds, double* dt) {
+    p3_basis(l, phi, ds, dt);
+    return OK;
+}
+
 int tpeo_p3_map(const double* P, double s, double t, double* x, double* xs, double* xt) {
     const double l[3] = {1.0 - s - t, s, t};
     p3_eval(P, l, x, xs, xt);

@@ -54,6 +54,9 @@
  *       fmix32(fmix32(fmix32(s32) ^ b) ^ B) <= floor(select_prob 2^32),  s32 = seed ^ (seed >> 32),
  *   fmix32 being MurmurHash3's 32-bit finaliser (published by Austin Appleby).
  *
+ *   Curved cubic elements (tpeo_kd_order_p3, tpeo_farfield_p3, tpeo_farfield_coverage_p3): the same
+ *   scheme over the quadrature records of the elements (see the section of that name below).
+ *
  *   Dual tree (tpeo_farfield_dual; both integrals clustered, the scheme the paper compares with):
  *   level by level, the candidates of node A are the children of its parent's near list (the
  *   root is its own only near node); B is far from A when 2 max(r_A, r_B) < theta |C_A - C_B|
@@ -182,9 +185,10 @@ static void face_to_vertices(const double* X, const int32_t* F, int64_t f, const
 
 /* ---- the FP32 frame of the admissibility decisions ---------------------------------------------- */
 
-/* FP32 centroid of face f as the kernels form it: the FP64 mean of its corners, rounded. */
-static int centroid_f32(const double* X, int64_t V, const int32_t* F, int64_t f, float* c) {
-    const int32_t a = F[3 * f], b = F[3 * f + 1], e = F[3 * f + 2];
+/* FP32 centroid of face f as the kernels form it: the FP64 mean of its corners, rounded.  F holds
+ * `stride` node ids per face, the three corners first (3 for flat faces, 10 for curved elements). */
+static int centroid_f32(const double* X, int64_t V, const int32_t* F, int stride, int64_t f, float* c) {
+    const int32_t a = F[stride * f], b = F[stride * f + 1], e = F[stride * f + 2];
     c[0] = c[1] = c[2] = 0.f;
     if (a < 0 || a >= V || b < 0 || b >= V || e < 0 || e >= V) return 0;
     double x[3];
@@ -196,11 +200,11 @@ static int centroid_f32(const double* X, int64_t V, const int32_t* F, int64_t f,
 
 /* s = 2^k with (largest extent of the FP32 centroid box) * s in [0.5, 1) (1 for an empty box), and
  * the box's centre in the scaled frame (the origin of the decisions' FP32 centres). */
-static double frame_scale(const double* X, int64_t V, const int32_t* F, int64_t nF, double* origin) {
+static double frame_scale(const double* X, int64_t V, const int32_t* F, int stride, int64_t nF, double* origin) {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t f = 0; f < nF; ++f) {
         float c[3];
-        if (!centroid_f32(X, V, F, f, c)) continue;
+        if (!centroid_f32(X, V, F, stride, f, c)) continue;
         for (int d = 0; d < 3; ++d) {
             if (c[d] < lo[d]) lo[d] = c[d];
             if (c[d] > hi[d]) hi[d] = c[d];
@@ -259,16 +263,12 @@ static int kd_cmp(const void* x, const void* y) {
     return a->pos < b->pos ? -1 : (a->pos > b->pos);  /* stable */
 }
 
-int tpeo_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, uint32_t* perm) {
-    if (!X || !F || !perm || V <= 0 || nF <= 0 || leaf < 1) return FF_EINVAL;
+/* The k-d order of nF items at the FP32 positions cen (see the top of the file). */
+static int kd_core(float (*cen)[3], int64_t nF, int leaf, uint32_t* perm) {
     const int H = height_of(nF, leaf);
-    float (*cen)[3] = malloc(sizeof(float[3]) * (size_t)nF);
     kd_item* it = malloc(sizeof(kd_item) * (size_t)nF);
-    if (!cen || !it) { free(cen); free(it); return FF_EINVAL; }
-    for (int64_t f = 0; f < nF; ++f) {
-        (void)centroid_f32(X, V, F, f, cen[f]);
-        perm[f] = (uint32_t)f;
-    }
+    if (!it) return FF_EINVAL;
+    for (int64_t f = 0; f < nF; ++f) perm[f] = (uint32_t)f;
     for (int level = 0; level < H; ++level) {
         const int64_t node_faces = ((int64_t)1 << (H - level)) * leaf;
         const int qbits = 32 - level < 16 ? 32 - level : 16;
@@ -300,9 +300,18 @@ int tpeo_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int 
         qsort(it, (size_t)nF, sizeof(kd_item), kd_cmp);
         for (int64_t i = 0; i < nF; ++i) perm[i] = it[i].val;
     }
-    free(cen);
     free(it);
     return FF_OK;
+}
+
+int tpeo_kd_order(const double* X, int64_t V, const int32_t* F, int64_t nF, int leaf, uint32_t* perm) {
+    if (!X || !F || !perm || V <= 0 || nF <= 0 || leaf < 1) return FF_EINVAL;
+    float (*cen)[3] = malloc(sizeof(float[3]) * (size_t)nF);
+    if (!cen) return FF_EINVAL;
+    for (int64_t f = 0; f < nF; ++f) (void)centroid_f32(X, V, F, 3, f, cen[f]);
+    const int rc = kd_core(cen, nF, leaf, perm);
+    free(cen);
+    return rc;
 }
 
 /* ---- tree nodes (FP64 patch averages) ------------------------------------------------------------ */
@@ -314,16 +323,35 @@ typedef struct {
     float af;              /* FP32 area in the scaled frame (a node is used when it is > 0) */
 } fnode;
 
+/* A curved element's quadrature record: its tangents x_s, x_t, |J|, rule weight W and point l. */
+typedef struct { double xs[3], xt[3], Jn, W, l[3]; } p3aux;
+
 typedef struct {
-    int64_t nF, V;
+    int64_t nF, V;  /* nF: the items of the tree -- faces, or the quadrature records of curved elements */
     int leaf, H;
     double s, o[3]; /* scale and origin of the FP32 decision frame */
     const double* X;
-    const int32_t* F;
-    const uint32_t* perm; /* tree position -> face */
-    fface* g;             /* face geometry by tree position */
+    const int32_t* F;     /* node ids, cstride per face or element, its three corners first */
+    int cstride, Q;       /* item r belongs to face or element r / Q (Q = 1 for flat faces) */
+    const uint32_t* perm; /* tree position -> item */
+    fface* g;             /* item geometry by tree position (c, n, a: point, normal, weight) */
     fnode* nodes;         /* 2^(H+1) entries, 1-based heap numbering */
 } ftree;
+
+/* The three corner nodes of the face or element holding the item at tree position i. */
+static const int32_t* corners_at(const ftree* t, int64_t i) {
+    return t->F + (int64_t)t->cstride * (int64_t)(t->perm[i] / (uint32_t)t->Q);
+}
+
+/* Excluded pairs: items whose faces (elements) share a corner node -- the same face included. */
+static int items_share_corner(const ftree* t, int64_t i, int64_t j) {
+    const int32_t* a = corners_at(t, i);
+    const int32_t* b = corners_at(t, j);
+    for (int u = 0; u < 3; ++u)
+        for (int v = 0; v < 3; ++v)
+            if (a[u] == b[v]) return 1;
+    return 0;
+}
 
 static void outer_add(double* m, double w, const double* v) {
     m[0] += w * v[0] * v[0]; m[1] += w * v[0] * v[1]; m[2] += w * v[0] * v[2];
@@ -350,15 +378,15 @@ static void node_range(const ftree* t, int64_t k, int64_t* p0, int64_t* p1) {
     if (*p0 > t->nF) *p0 = t->nF;
 }
 
-static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* perm,
-                      int leaf) {
-    memset(t, 0, sizeof(*t));
-    int rc = check_mesh(X, V, F, nF);
-    if (rc) return rc;
-    if (!perm || leaf < 1) return FF_EINVAL;
-    t->nF = nF; t->V = V; t->leaf = leaf; t->X = X; t->F = F; t->perm = perm;
+/* The tree over n = nE Q items whose geometry (in item order) is `items`: FP32 frame from the
+ * corner centroids of the nE faces or elements, leaves of `leaf` consecutive tree positions, and the
+ * patch averages bottom-up.  Radii bound the corner nodes of the items' faces or elements. */
+static int tree_build_items(ftree* t, const double* X, int64_t V, const int32_t* F, int cstride, int Q, int64_t nE,
+                            const fface* items, const uint32_t* perm, int leaf) {
+    const int64_t nF = nE * Q;
+    t->nF = nF; t->V = V; t->leaf = leaf; t->X = X; t->F = F; t->cstride = cstride; t->Q = Q; t->perm = perm;
     t->H = height_of(nF, leaf);
-    t->s = frame_scale(X, V, F, nF, t->o);
+    t->s = frame_scale(X, V, F, cstride, nE, t->o);
     t->g = malloc(sizeof(fface) * (size_t)nF);
     t->nodes = calloc((size_t)2 << t->H, sizeof(fnode));
     if (!t->g || !t->nodes) return FF_EINVAL;
@@ -367,7 +395,7 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
     for (int64_t i = 0; i < nF; ++i) {
         if (perm[i] >= (uint32_t)nF || seen[perm[i]]) { free(seen); return FF_EINVAL; }
         seen[perm[i]] = 1;
-        if ((rc = ff_face(X, F, perm[i], &t->g[i]))) { free(seen); return rc; }
+        t->g[i] = items[perm[i]];
     }
     free(seen);
     const int64_t nslot = (int64_t)1 << t->H;
@@ -387,8 +415,9 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
                 const double dc[3] = {g->c[0] - n->C[0], g->c[1] - n->C[1], g->c[2] - n->C[2]};
                 outer_add(n->m2c, g->a, dc);
                 outer_add(n->m2n, g->a, g->n);
+                const int32_t* cn = corners_at(t, i);
                 for (int k = 0; k < 3; ++k) {
-                    const double* x = X + 3 * (int64_t)F[3 * (int64_t)perm[i] + k];
+                    const double* x = X + 3 * (int64_t)cn[k];
                     const double dv[3] = {x[0] - n->C[0], x[1] - n->C[1], x[2] - n->C[2]};
                     const double r = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
                     if (r > n->r) n->r = r;
@@ -420,6 +449,22 @@ static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, in
     return FF_OK;
 }
 
+/* The tree over the flat faces of (X, F). */
+static int tree_build(ftree* t, const double* X, int64_t V, const int32_t* F, int64_t nF, const uint32_t* perm,
+                      int leaf) {
+    memset(t, 0, sizeof(*t));
+    int rc = check_mesh(X, V, F, nF);
+    if (rc) return rc;
+    if (!perm || leaf < 1) return FF_EINVAL;
+    fface* items = malloc(sizeof(fface) * (size_t)nF);
+    if (!items) return FF_EINVAL;
+    for (int64_t f = 0; f < nF; ++f)
+        if ((rc = ff_face(X, F, f, &items[f]))) { free(items); return rc; }
+    rc = tree_build_items(t, X, V, F, 3, 1, nF, items, perm, leaf);
+    free(items);
+    return rc;
+}
+
 static void tree_free(ftree* t) {
     free(t->g);
     free(t->nodes);
@@ -434,7 +479,7 @@ static void block_ball(const ftree* t, int64_t b, float* out) {
     for (int d = 0; d < 3; ++d) C[d] /= (double)(i1 - i0);
     for (int64_t i = i0; i < i1; ++i)
         for (int k = 0; k < 3; ++k) {
-            const double* x = t->X + 3 * (int64_t)t->F[3 * (int64_t)t->perm[i] + k];
+            const double* x = t->X + 3 * (int64_t)corners_at(t, i)[k];
             const double dv[3] = {x[0] - C[0], x[1] - C[1], x[2] - C[2]};
             const double rr = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
             if (rr > r) r = rr;
@@ -493,7 +538,7 @@ static int ff_visit(const ftree* t, int64_t b, int64_t node, int far, void* user
     node_range(t, node, &p0, &p1);
     for (int64_t i = i0; i < i1; ++i)
         for (int64_t j = p0; j < p1; ++j) {
-            if (shares_vertex(t->F, t->perm[i], t->perm[j])) continue;
+            if (items_share_corner(t, i, j)) continue;
             if (add_inner(&t->g[i], t->g[j].c, t->g[j].a, t->g[j].n, u->q, u->p, &u->in[i])) return FF_ENONFIN;
         }
     return FF_OK;
@@ -574,8 +619,31 @@ static int cov_visit(const ftree* t, int64_t b, int64_t node, int far, void* use
         u->seen[j] += 1;
         if (far)
             for (int64_t i = i0; i < i1; ++i)
-                if (shares_vertex(t->F, t->perm[i], t->perm[j])) { u->bad_far += 1; break; }
+                if (items_share_corner(t, i, j)) { u->bad_far += 1; break; }
     }
+    return FF_OK;
+}
+
+/* out[0] <- target blocks from which some face is not reached exactly once; out[1] <- (far
+ * cluster face, block) incidences where the face shares a vertex with a face of the block. */
+/* The walk's invariants on a built tree (see tpeo_farfield_coverage). */
+static int coverage_of(const ftree* t, double theta, int64_t* out) {
+    const int64_t nF = t->nF;
+    cov_user u = {calloc((size_t)nF, sizeof(int32_t)), 0};
+    if (!u.seen) return FF_EINVAL;
+    out[0] = out[1] = 0;
+    const int64_t nb = (nF + BLOCK - 1) / BLOCK;
+    for (int64_t b = 0; b < nb; ++b) {
+        float tb[4];
+        block_ball(t, b, tb);
+        memset(u.seen, 0, sizeof(int32_t) * (size_t)nF);
+        walk_stats st = {0, 0, 0};
+        walk(t, b, tb, (float)theta, 1, &st, cov_visit, &u);
+        for (int64_t j = 0; j < nF; ++j)
+            if (u.seen[j] != 1) { out[0] += 1; break; }
+    }
+    out[1] = u.bad_far;
+    free(u.seen);
     return FF_OK;
 }
 
@@ -587,23 +655,201 @@ int tpeo_farfield_coverage(const double* X, int64_t V, const int32_t* F, int64_t
     ftree t;
     int rc = tree_build(&t, X, V, F, nF, perm, leaf);
     if (rc) { tree_free(&t); return rc; }
-    cov_user u = {calloc((size_t)nF, sizeof(int32_t)), 0};
-    if (!u.seen) { tree_free(&t); return FF_EINVAL; }
-    out[0] = out[1] = 0;
-    const int64_t nb = (nF + BLOCK - 1) / BLOCK;
+    rc = coverage_of(&t, theta, out);
+    tree_free(&t);
+    return rc;
+}
+
+/* ---- curved cubic elements: the same scheme over quadrature records ----------------------------------
+ *
+ * For curved (P3) elements (ten nodes per element, the three corners first; paper Sec. 3.1 and 3.2)
+ * the items of the tree are the quadrature records of every element: record r = Q e + k at the
+ * point l_k of the rule (barycentric, weight W_k) on element e, with position x = x(l_k), normal
+ * n = J / |J| (J = x_s x x_t) and weight alpha = W_k |J| / 2.  The tree is the k-d order of the
+ * records' FP32 positions; radii, target balls and the exclusion use the elements' corner nodes
+ * (records of elements sharing a corner are not paired, the element with itself included), the
+ * FP32 frame comes from the elements' corner centroids, and everything else is the scheme above
+ * with records in place of faces.  The inner integrals of a record reach the nodes by the chain
+ * rule through the record: with g = dE/dalpha = scale K, gn = dE/dn = scale alpha Vn and
+ * gx = dE/dx = scale alpha Vc, gJ = g (W/2) n + (I - n n^T) gn / |J|, and node k of the element
+ * receives phi_k gx + (dphi_k/ds) (x_t x gJ) + (dphi_k/dt) (gJ x x_s).  The basis is
+ * tpeo_p3_basis of tpe_oracle.c (pinned there by cubic reproduction and straight elements). */
+
+int tpeo_p3_basis(const double* l, double* phi, double* ds, double* dt);
+
+static int check_p3(const double* X, int64_t V, const int32_t* F10, int64_t nE, int nq) {
+    if (!X || !F10 || V <= 0 || nE <= 0 || nq < 1 || nq > 6) return FF_EINVAL;
+    for (int64_t i = 0; i < 10 * nE; ++i)
+        if (F10[i] < 0 || F10[i] >= V) return FF_EINVAL;
+    for (int64_t i = 0; i < 3 * V; ++i)
+        if (!isfinite(X[i])) return FF_ENONFIN;
+    return FF_OK;
+}
+
+/* x, x_s, x_t of element e at barycentric l */
+static void p3_point(const double* X, const int32_t* F10, int64_t e, const double* l, double* x, double* xs,
+                     double* xt) {
+    double phi[10], ds[10], dt[10];
+    tpeo_p3_basis(l, phi, ds, dt);
+    for (int d = 0; d < 3; ++d) x[d] = xs[d] = xt[d] = 0.0;
+    for (int k = 0; k < 10; ++k) {
+        const double* xk = X + 3 * (int64_t)F10[10 * e + k];
+        for (int d = 0; d < 3; ++d) {
+            x[d] += phi[k] * xk[d];
+            xs[d] += ds[k] * xk[d];
+            xt[d] += dt[k] * xk[d];
+        }
+    }
+}
+
+/* The records (item order) of every element under the rule (bary[nq][3], w[nq]). */
+static int p3_records_of(const double* X, const int32_t* F10, int64_t nE, const double* bary, const double* w,
+                         int nq, fface* items, p3aux* aux) {
+    for (int64_t e = 0; e < nE; ++e)
+        for (int k = 0; k < nq; ++k) {
+            const int64_t r = (int64_t)nq * e + k;
+            fface* g = &items[r];
+            p3aux* x = &aux[r];
+            for (int d = 0; d < 3; ++d) x->l[d] = bary[3 * k + d];
+            p3_point(X, F10, e, x->l, g->c, x->xs, x->xt);
+            const double J[3] = {x->xs[1] * x->xt[2] - x->xs[2] * x->xt[1], x->xs[2] * x->xt[0] - x->xs[0] * x->xt[2],
+                                 x->xs[0] * x->xt[1] - x->xs[1] * x->xt[0]};
+            x->Jn = sqrt(J[0] * J[0] + J[1] * J[1] + J[2] * J[2]);
+            if (!(x->Jn > 1e-300)) return FF_EDEGEN;
+            x->W = w[k];
+            g->wn = x->Jn;
+            g->a = 0.5 * w[k] * x->Jn;
+            for (int d = 0; d < 3; ++d) g->n[d] = J[d] / x->Jn;
+        }
+    return FF_OK;
+}
+
+/* The k-d order of the nE nq records (item r = nq e + k at the rule's point k of element e). */
+int tpeo_kd_order_p3(const double* X, int64_t V, const int32_t* F10, int64_t nE, const double* bary, int nq,
+                     int leaf, uint32_t* perm) {
+    int rc = check_p3(X, V, F10, nE, nq);
+    if (rc) return rc;
+    if (!bary || !perm || leaf < 1) return FF_EINVAL;
+    const int64_t n = nE * nq;
+    float (*cen)[3] = malloc(sizeof(float[3]) * (size_t)n);
+    if (!cen) return FF_EINVAL;
+    for (int64_t e = 0; e < nE; ++e)
+        for (int k = 0; k < nq; ++k) {
+            double x[3], xs[3], xt[3];
+            p3_point(X, F10, e, bary + 3 * k, x, xs, xt);
+            for (int d = 0; d < 3; ++d) cen[(int64_t)nq * e + k][d] = (float)x[d];
+        }
+    rc = kd_core(cen, n, leaf, perm);
+    free(cen);
+    return rc;
+}
+
+static int tree_build_p3(ftree* t, const double* X, int64_t V, const int32_t* F10, int64_t nE, const double* bary,
+                         const double* w, int nq, const uint32_t* perm, int leaf, p3aux** aux_out) {
+    memset(t, 0, sizeof(*t));
+    *aux_out = NULL;
+    int rc = check_p3(X, V, F10, nE, nq);
+    if (rc) return rc;
+    if (!bary || !w || !perm || leaf < 1) return FF_EINVAL;
+    const int64_t n = nE * nq;
+    fface* items = malloc(sizeof(fface) * (size_t)n);
+    p3aux* aux = malloc(sizeof(p3aux) * (size_t)n);
+    if (!items || !aux) { free(items); free(aux); return FF_EINVAL; }
+    rc = p3_records_of(X, F10, nE, bary, w, nq, items, aux);
+    if (!rc) rc = tree_build_items(t, X, V, F10, 10, nq, nE, items, perm, leaf);
+    free(items);
+    if (rc) { free(aux); return rc; }
+    *aux_out = aux;
+    return FF_OK;
+}
+
+/* Barnes-Hut approximation of E and dE/dX on curved elements (X [V][3], F10 [nE][10]), the rule
+ * (bary [nq][3], w [nq]) and the tree perm over its records (tpeo_kd_order_p3).  Outputs as for
+ * tpeo_farfield; G_out [V][3]. */
+int tpeo_farfield_p3(const double* X, int64_t V, const int32_t* F10, int64_t nE, const double* bary, const double* w,
+                     int nq, const uint32_t* perm, int leaf, double theta, double q, double p, double scale,
+                     int nthreads, double* E_out, double* G_out, int64_t* stats) {
+    if (!(theta >= 0.0) || !(q >= 2.0) || !(p > q)) return FF_EINVAL;
+    ftree t;
+    p3aux* aux = NULL;
+    int rc = tree_build_p3(&t, X, V, F10, nE, bary, w, nq, perm, leaf, &aux);
+    if (rc) { tree_free(&t); return rc; }
+    const int64_t n = t.nF;
+    inner_t* in = calloc((size_t)n, sizeof(inner_t));
+    const int64_t nb = (n + BLOCK - 1) / BLOCK;
+    walk_stats* bs = calloc((size_t)nb, sizeof(walk_stats));
+    if (!in || !bs) { free(in); free(bs); free(aux); tree_free(&t); return FF_EINVAL; }
+    const float th = (float)theta;
+    int err = FF_OK;
+#ifdef _OPENMP
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
     for (int64_t b = 0; b < nb; ++b) {
         float tb[4];
         block_ball(&t, b, tb);
-        memset(u.seen, 0, sizeof(int32_t) * (size_t)nF);
-        walk_stats st = {0, 0, 0};
-        walk(&t, b, tb, (float)theta, 1, &st, cov_visit, &u);
-        for (int64_t j = 0; j < nF; ++j)
-            if (u.seen[j] != 1) { out[0] += 1; break; }
+        ff_user u = {q, p, in};
+        if (walk(&t, b, tb, th, 1, &bs[b], ff_visit, &u)) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            err = FF_ENONFIN;
+        }
     }
-    out[1] = u.bad_far;
-    free(u.seen);
+    (void)nthreads;
+    if (stats) {
+        for (int k = 0; k < 6; ++k) stats[k] = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            stats[0] += bs[b].far;
+            stats[1] += bs[b].near_cols;
+            stats[2] += bs[b].visited;
+            stats[3] += 1;
+            if (bs[b].near_cols > stats[4]) stats[4] = bs[b].near_cols;
+            if (bs[b].far > stats[5]) stats[5] = bs[b].far;
+        }
+    }
+    double E = 0.0;
+    if (G_out) memset(G_out, 0, sizeof(double) * 3 * (size_t)V);
+    for (int64_t i = 0; i < n && !err; ++i) {
+        const fface* g = &t.g[i];
+        E += 0.5 * g->a * in[i].K;
+        if (!G_out) continue;
+        const int64_t r = perm[i], e = r / nq;
+        const p3aux* x = &aux[r];
+        double gn[3], gx[3], gJ[3], cs[3], ct[3];
+        const double ga = scale * in[i].K;
+        for (int d = 0; d < 3; ++d) { gn[d] = scale * g->a * in[i].Vn[d]; gx[d] = scale * g->a * in[i].Vc[d]; }
+        const double ngn = g->n[0] * gn[0] + g->n[1] * gn[1] + g->n[2] * gn[2];
+        for (int d = 0; d < 3; ++d) gJ[d] = ga * 0.5 * x->W * g->n[d] + (gn[d] - ngn * g->n[d]) / x->Jn;
+        /* x_t x gJ (the direction of d/dx_s) and gJ x x_s (that of d/dx_t) */
+        cs[0] = x->xt[1] * gJ[2] - x->xt[2] * gJ[1]; cs[1] = x->xt[2] * gJ[0] - x->xt[0] * gJ[2];
+        cs[2] = x->xt[0] * gJ[1] - x->xt[1] * gJ[0];
+        ct[0] = gJ[1] * x->xs[2] - gJ[2] * x->xs[1]; ct[1] = gJ[2] * x->xs[0] - gJ[0] * x->xs[2];
+        ct[2] = gJ[0] * x->xs[1] - gJ[1] * x->xs[0];
+        double phi[10], ds[10], dt[10];
+        tpeo_p3_basis(x->l, phi, ds, dt);
+        for (int k = 0; k < 10; ++k) {
+            double* o = G_out + 3 * (int64_t)F10[10 * e + k];
+            for (int d = 0; d < 3; ++d) o[d] += phi[k] * gx[d] + ds[k] * cs[d] + dt[k] * ct[d];
+        }
+    }
+    if (E_out) *E_out = err ? INFINITY : scale * E;
+    free(in); free(bs); free(aux); tree_free(&t);
+    return err;
+}
+
+/* tpeo_farfield_coverage on the records of curved elements. */
+int tpeo_farfield_coverage_p3(const double* X, int64_t V, const int32_t* F10, int64_t nE, const double* bary,
+                              const double* w, int nq, const uint32_t* perm, int leaf, double theta, int64_t* out) {
+    if (!out || !(theta >= 0.0)) return FF_EINVAL;
+    ftree t;
+    p3aux* aux = NULL;
+    int rc = tree_build_p3(&t, X, V, F10, nE, bary, w, nq, perm, leaf, &aux);
+    free(aux);
+    if (rc) { tree_free(&t); return rc; }
+    rc = coverage_of(&t, theta, out);
     tree_free(&t);
-    return FF_OK;
+    return rc;
 }
 
 /* ---- learned-correction samples ---------------------------------------------------------------------- */

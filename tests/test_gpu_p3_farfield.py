@@ -1,6 +1,7 @@
 """The far field on curved cubic elements (tpe_build_tree_p3 / tpe_farfield_p3): theta = 0 is the
-exact P3 scheme (GPU path and oracle), the error falls with theta, the learned correction applies,
-results are deterministic, and trees of the other kind are refused."""
+exact P3 scheme (GPU path and oracle), theta 0.5 is the FP64 oracle of the scheme on the records
+(tree order, counts, energy and gradient), the error falls with theta, the learned correction
+applies, results are deterministic, and trees of the other kind are refused."""
 import os
 
 import numpy as np
@@ -35,6 +36,28 @@ def test_theta_zero_is_exact(Q, leaf):
     Eo, Go = oracle.gradient_p3(X10, F10, Q)
     eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
     log("P3 far field theta 0, Q", Q, "leaf", leaf, "rel E", eE, "rel G", eG)
+    assert eE <= E_TOL and eG <= G_TOL
+
+
+@pytest.mark.parametrize("level,Q", [(3, 3), (4, 3), (3, 6)])
+def test_tree_order_and_farfield_are_the_oracles(level, Q):
+    """theta 0.5 against the FP64 oracle of the scheme on curved elements (records of the Q-point
+    rule, corner nodes for the radii and the exclusion): the tree order bit for bit, the walk's
+    counts equal, energy and gradient element by element."""
+    T = tpe()
+    X10, F10 = M.p3_sphere(level, 2, 8, 0.05, 3)
+    log("P3 far field vs oracle: level", level, "Q", Q, "elements", F10.shape[0])
+    Xd, Fd = upload(X10, F10)
+    tree = T.build_tree_p3(Xd, Fd, leaf=32, points=Q)
+    perm = oracle.kd_order_p3(X10, F10, Q, 32)
+    got = tree.order().cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, perm), int((got != perm).sum())
+    Eo, Go, so = oracle.farfield_p3(X10, F10, 0.5, Q, leaf=32, perm=perm)
+    E, G = T.farfield_p3(tree, Xd, Fd, theta=0.5)
+    st = T.context(Xd.device).farfield_stats()
+    eE, eG = rel_energy(float(E.cpu()), Eo), rel_grad_maxnorm(G.cpu().numpy(), Go)
+    log("  stats gpu", st, "oracle", so, "rel E", eE, "rel G", eG)
+    assert so[0] > 0 and tuple(st) == tuple(so)
     assert eE <= E_TOL and eG <= G_TOL
 
 

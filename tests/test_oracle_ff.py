@@ -263,3 +263,50 @@ def test_sample_features_follow_their_definitions():
             assert np.abs(x[k, lane, 1:19] - want).max() <= 1e-10
             # the radius bounds every vertex of the cluster
             assert rB * (1 + 1e-6) >= np.linalg.norm(X[F[faces]].reshape(-1, 3) - C, axis=1).max()
+
+
+# ---- curved cubic (P3) elements: the same scheme over the quadrature records ----------------------
+
+
+def _p3(level, seed=0):
+    return M.p3_sphere(level, 2, 8, 0.05, seed)
+
+
+@pytest.mark.parametrize("rule,leaf", [(1, 32), (3, 32), (6, 7)])
+def test_p3_theta_zero_is_the_exact_p3_gradient(rule, leaf):
+    """theta = 0: the per-record inner integrals and their chain rule through the cubic map give
+    tpeo_gradient_p3 (pair derivatives pushed to both elements' nodes there)."""
+    X10, F10 = _p3(2)
+    E0, G0 = oracle.gradient_p3(X10, F10, rule)
+    E, G, st = oracle.farfield_p3(X10, F10, 0.0, rule, leaf=leaf)
+    assert abs(E - E0) <= 1e-13 * abs(E0) and _rel(G, G0) <= 1e-13
+    assert st[0] == 0 and st[1] == st[3] * F10.shape[0] * rule  # every block saw every record
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_p3_walk_covers_every_record_once_and_keeps_neighbours_near(theta):
+    X10, F10 = _p3(4)
+    for leaf in (1, 32):
+        assert oracle.farfield_coverage_p3(X10, F10, theta, 3, leaf=leaf) == (0, 0)
+    assert oracle.farfield_p3(X10, F10, theta, 3, want_grad=False)[2][0] > 0  # clusters were used
+
+
+def test_p3_straight_elements_with_one_point_are_the_flat_far_field():
+    """Straight cubic elements (nodes on the lattice of flat triangles) with the centroid rule have
+    records equal to the faces (point = centroid, normal, weight = area, same corners); on the same
+    tree order the P3 scheme gives the flat far field and the gradient at the corner nodes."""
+    X, F = _l4()
+    X10, F10 = M.p3_lattice(X, F)
+    perm = oracle.kd_order(X, F, 32)
+    assert np.array_equal(oracle.kd_order_p3(X10, F10, 1, 32), perm)
+    E0, G0, s0 = oracle.farfield(X, F, 0.5, perm=perm)
+    E, G, st = oracle.farfield_p3(X10, F10, 0.5, 1, perm=perm)
+    assert s0[0] > 0 and st == s0
+    # every node of a straight element is a fixed affine combination of its element's corners
+    # (its lattice point): the flat gradient is the P3 gradient pulled back through that map
+    nodes, first = np.unique(F10.reshape(-1), return_index=True)
+    f, k = first // 10, first % 10
+    Gp = np.zeros_like(X)
+    for c in range(3):
+        np.add.at(Gp, F[f, c], M.P3_LATTICE[k, c][:, None] * G[nodes])
+    assert abs(E - E0) <= 1e-13 * abs(E0) and _rel(Gp, G0) <= 1e-12

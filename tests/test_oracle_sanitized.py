@@ -1,5 +1,6 @@
 """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer: every C entry point runs once on
-small meshes (flat level-3 surface with a dent, its confinement, curved cubic elements) in a
+small meshes (flat level-3 surface with a dent, its confinement, curved cubic elements -- also
+their far field's tree order, walk and coverage) in a
 sanitized build, which must finish without a report, and its results must be those of the regular
 build (the same code; only the OpenMP split of the sums may differ)."""
 import os
@@ -52,6 +53,14 @@ def _regular(X, F, Y, FY, X10, F10):
     out["farfield_samples"] = [n, n, np.abs(s["feats"]).sum(), np.abs(s["targets"]).sum()]
     E, G, st = oracle.farfield_dual(X, F, 1.0, 32, perm, nthreads=2)
     out["farfield_dual"] = [0, E, np.abs(G).sum(), st[0], st[1]]
+    perm3 = oracle.kd_order_p3(X10, F10, 3, 8)
+    h = 1469598103934665603
+    for v in perm3.tolist():
+        h = ((h ^ v) * 1099511628211) & (2**64 - 1)
+    out["kd_order_p3"] = [0, h]
+    E, G, st = oracle.farfield_p3(X10, F10, 1.0, 3, leaf=8, perm=perm3, nthreads=2)
+    out["farfield_p3"] = [0, E, np.abs(G).sum(), st[0], st[1], st[2]]
+    out["farfield_coverage_p3"] = [0, *oracle.farfield_coverage_p3(X10, F10, 1.0, 3, leaf=8, perm=perm3)]
     return out
 
 
