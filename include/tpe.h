@@ -113,9 +113,10 @@ typedef enum {
 int tpe_version(void);
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream` (a hipStream_t; NULL = the
- * null stream).  The context also owns a second stream of default priority: the far-field calls
- * fork their vertex CSR onto it (only the final gather reads it) and join it back into
- * `hip_stream` before that gather, so every call stays ordered on `hip_stream` as a whole.
+ * null stream).  The context also owns a second stream of default priority: the far field on
+ * curved elements (tpe_farfield_p3) forks its node lists onto it (only the final gather reads
+ * them) and joins it back into `hip_stream` before that gather, so every call stays ordered on
+ * `hip_stream` as a whole (the flat far field's vertex lists are built once with the tree).
  * *out receives the context; ownership passes to the caller (tpe_destroy). */
 int tpe_create(tpe_ctx** out, int device, void* hip_stream);
 
