@@ -101,7 +101,7 @@ size_t tree_node_bytes(int H);
 size_t tree_rec_bytes(int H);
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
                                const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs, bool mom2,
-                               hipStream_t st);
+                               float4* balls, hipStream_t st);
 hipError_t launch_farfield_samples(const ColRec* cols, const int4* colv, const double* c64, const double* X,
                                   const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF, float theta,
                                   uint32_t seed, uint32_t sel, int quota, int64_t max_faces, float4* balls,
@@ -1103,7 +1103,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     HIPCHK(launch_p3_records(X, V, F10, nF, Q, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, P.cnt,
                              ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, n, tree->leaf, tree->H, P.nodes64, P.recs,
-                               mlp != nullptr, st));
+                               mlp != nullptr, P.balls, st));
     if (G_dev) {  // the node CSR only serves the gather: built on the side stream during the walk
         HIPCHK(hipEventRecord(ctx->fork, st));
         HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
@@ -1185,7 +1185,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs,
-                               mlp != nullptr, st));
+                               mlp != nullptr, P.balls, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -1237,7 +1237,7 @@ int tpe_farfield_dual(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, false,
-                               st));
+                               nullptr, st));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
@@ -1283,7 +1283,7 @@ int tpe_farfield_samples(tpe_ctx* ctx, const tpe_tree* tree, const double* X, in
     HIPCHK(launch_records(X, V, F, nF, 1, P.Fp, tree->perm, P.bbox, P.org, P.cols, P.colv, P.c64, P.geo, nullptr,
                           ctx->dflags, st));
     HIPCHK(launch_tree_moments(P.c64, P.geo, P.colv, X, P.bbox, nF, tree->leaf, tree->H, P.nodes64, P.recs, true,
-                               st));
+                               nullptr, st));
     const uint32_t sel = select_prob >= 1.0 ? 0xffffffffu : (uint32_t)(select_prob * 4294967296.0);
     HIPCHK(launch_farfield_samples(P.cols, P.colv, P.c64, X, P.bbox, P.recs, tree->H, tree->leaf, nF, (float)theta,
                                    (uint32_t)(seed ^ (seed >> 32)), sel, quota, max_cluster_faces, P.balls, feats,

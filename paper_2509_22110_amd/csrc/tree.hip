@@ -76,6 +76,41 @@ __device__ __forceinline__ double wave_max_d(double x) {
     return x;
 }
 
+// The ball of target block b (its faces 64 b + lane, one per lane of the calling wave): centre the
+// mean of the faces' centres, radius the largest distance from it to a vertex of the faces, in the
+// FP32 record frame with the slack of write_rec; lane 0 writes balls[b].  Every lane of the wave
+// calls it (the sums run over the whole wave).
+__device__ __forceinline__ void block_ball_wave(const double* __restrict__ c64, const int4* __restrict__ colv,
+                                                const double* __restrict__ X, const uint32_t* __restrict__ bbox,
+                                                int64_t nF, int64_t b, int lane, float4* __restrict__ balls) {
+    const int64_t i = b * 64 + lane;
+    const bool act = i < nF;
+    const double s = norm_scale(bbox);
+    const double nact = wave_sum_d(act ? 1.0 : 0.0);
+    const double cx = wave_sum_d(act ? c64[3 * i] : 0.0) / fmax(nact, 1.0);
+    const double cy = wave_sum_d(act ? c64[3 * i + 1] : 0.0) / fmax(nact, 1.0);
+    const double cz = wave_sum_d(act ? c64[3 * i + 2] : 0.0) / fmax(nact, 1.0);
+    double r = 0.0;
+    if (act) {
+        const int4 v = colv[i];
+        const int vv[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3; ++k) {
+            if (vv[k] < 0) continue;
+            const double dx = s * X[3 * (int64_t)vv[k]] - cx, dy = s * X[3 * (int64_t)vv[k] + 1] - cy,
+                         dz = s * X[3 * (int64_t)vv[k] + 2] - cz;
+            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    }
+    r = wave_max_d(r);
+    if (lane == 0) {
+        double o[3];
+        norm_origin(bbox, o);
+        const double rx = cx - o[0], ry = cy - o[1], rz = cz - o[2];  // relative to the records' origin
+        const double slack = 1e-6 * (1.0 + fabs(rx) + fabs(ry) + fabs(rz));
+        balls[b] = make_float4((float)rx, (float)ry, (float)rz, round_up_f(r + slack));
+    }
+}
+
 // G lanes per leaf slot j in [0, 2^H) (G = the leaf size rounded up to a power of two, at most 64;
 // 64 / G slots per wave): faces [j*leaf, min((j+1)*leaf, nF)) in sorted order, the group's lanes
 // striding over them; the FP64 sums are reduced across the group in a fixed order (every lane of
@@ -100,12 +135,17 @@ __global__ __launch_bounds__(64 * MOM_LEAF_WAVES) void leaf_moments(const double
                                                                     const uint32_t* __restrict__ bbox, int64_t nF,
                                                                     int leaf, int H, int G, NodeF64* __restrict__ nodes,
                                                                     NodeRec* __restrict__ recs,
-                                                                    NodeMom* __restrict__ moms) {
+                                                                    NodeMom* __restrict__ moms,
+                                                                    float4* __restrict__ balls) {
     const int lane = threadIdx.x & 63;
     const int64_t nslot = (int64_t)1 << H;
     const int64_t j = (blockIdx.x * (int64_t)MOM_LEAF_WAVES + (threadIdx.x >> 6)) * (64 / G) + lane / G;
     const int t = lane & (G - 1);
     if (__builtin_amdgcn_readfirstlane((int)(j - lane / G >= nslot))) return;  // uniform over the wave
+    // leaves of 32 (balls given): the wave's two leaves are target block j0 / 2, whose ball it
+    // writes as target_balls would (the same wave sums, the same bits)
+    const int64_t bb = __builtin_amdgcn_readfirstlane((int)((j - lane / G) / 2));
+    if (balls && bb * 64 < nF) block_ball_wave(c64, colv, X, bbox, nF, bb, lane, balls);
     const double s = norm_scale(bbox);
     const int64_t f0 = j < nslot ? j * leaf : 0, f1 = j < nslot ? std::min<int64_t>(nF, f0 + leaf) : 0;
     double A = 0, sx = 0, sy = 0, sz = 0, nx = 0, ny = 0, nz = 0;
@@ -254,33 +294,7 @@ __global__ __launch_bounds__(1 << MOM_SUB) void subtree_moments(int L, int nl, c
 __global__ __launch_bounds__(64) void target_balls(const double* __restrict__ c64, const int4* __restrict__ colv,
                                                    const double* __restrict__ X, const uint32_t* __restrict__ bbox,
                                                    int64_t nF, float4* __restrict__ balls) {
-    const int64_t b = blockIdx.x;
-    const int64_t i = b * 64 + threadIdx.x;
-    const bool act = i < nF;
-    const double s = norm_scale(bbox);
-    const double nact = wave_sum_d(act ? 1.0 : 0.0);
-    const double cx = wave_sum_d(act ? c64[3 * i] : 0.0) / fmax(nact, 1.0);
-    const double cy = wave_sum_d(act ? c64[3 * i + 1] : 0.0) / fmax(nact, 1.0);
-    const double cz = wave_sum_d(act ? c64[3 * i + 2] : 0.0) / fmax(nact, 1.0);
-    double r = 0.0;
-    if (act) {
-        const int4 v = colv[i];
-        const int vv[3] = {v.x, v.y, v.z};
-        for (int k = 0; k < 3; ++k) {
-            if (vv[k] < 0) continue;
-            const double dx = s * X[3 * (int64_t)vv[k]] - cx, dy = s * X[3 * (int64_t)vv[k] + 1] - cy,
-                         dz = s * X[3 * (int64_t)vv[k] + 2] - cz;
-            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
-        }
-    }
-    r = wave_max_d(r);
-    if (threadIdx.x == 0) {
-        double o[3];
-        norm_origin(bbox, o);
-        const double rx = cx - o[0], ry = cy - o[1], rz = cz - o[2];  // relative to the records' origin
-        const double slack = 1e-6 * (1.0 + fabs(rx) + fabs(ry) + fabs(rz));
-        balls[b] = make_float4((float)rx, (float)ry, (float)rz, round_up_f(r + slack));
-    }
+    block_ball_wave(c64, colv, X, bbox, nF, blockIdx.x, threadIdx.x, balls);
 }
 
 // ---- learned correction: features and training samples -----------------------------------------
@@ -1084,9 +1098,11 @@ int tree_height(int64_t nF, int leaf) {
 size_t tree_node_bytes(int H) { return ((size_t)2 << H) * sizeof(NodeF64); }
 size_t tree_rec_bytes(int H) { return ((size_t)2 << H) * (sizeof(NodeRec) + sizeof(NodeMom)); }
 
+// Node moments (leaves, then the subtrees) and, with balls given, the target blocks' balls: with
+// leaves of 32 faces inside the leaf pass (a wave's two leaves are one block), else by target_balls.
 hipError_t launch_tree_moments(const double* c64, const double* geo, const int4* colv, const double* X,
                                const uint32_t* bbox, int64_t nF, int leaf, int H, void* nodes64, void* recs, bool mom2,
-                               hipStream_t st) {
+                               float4* balls, hipStream_t st) {
     NodeF64* n = (NodeF64*)nodes64;
     NodeRec* r = (NodeRec*)recs;
     NodeMom* m = (NodeMom*)(r + ((size_t)2 << H));
@@ -1095,8 +1111,14 @@ hipError_t launch_tree_moments(const double* c64, const double* geo, const int4*
     while (G < leaf && G < 64) G *= 2;
     const int64_t per_wg = (int64_t)MOM_LEAF_WAVES * (64 / G);  // leaf slots per work-group
     const dim3 lg((unsigned)((nslot + per_wg - 1) / per_wg)), lb(64 * MOM_LEAF_WAVES);
-    if (mom2) hipLaunchKernelGGL(leaf_moments<true>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m);
-    else hipLaunchKernelGGL(leaf_moments<false>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m);
+    float4* fused = leaf == 32 ? balls : nullptr;
+    if (mom2)
+        hipLaunchKernelGGL(leaf_moments<true>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m, fused);
+    else
+        hipLaunchKernelGGL(leaf_moments<false>, lg, lb, 0, st, c64, geo, colv, X, bbox, nF, leaf, H, G, n, r, m, fused);
+    if (balls && !fused)
+        hipLaunchKernelGGL(target_balls, dim3((unsigned)((nF + 63) / 64)), dim3(64), 0, st, c64, colv, X, bbox, nF,
+                           balls);
     for (int L = H; L > 0;) {
         const int nl = std::min(L, MOM_SUB);
         const dim3 sg((unsigned)(((int64_t)1 << L) >> nl)), sb(1 << nl);
@@ -1144,6 +1166,7 @@ __device__ __forceinline__ uint32_t work_key(uint32_t w) {
 // near columns and visited nodes summed, blocks, the largest near-column and far-cluster counts of
 // a block) in the same pass.  Replaces a key kernel, a radix pass, two copies and a reduction.
 constexpr int FO_NT = 1024;
+constexpr int FO_KEYS = 32768;  // blocks whose 8-bit keys the sort keeps in LDS (beyond: re-read)
 
 __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restrict__ work, int64_t nb,
                                                        uint32_t* __restrict__ order, const uint4* __restrict__ lst,
@@ -1152,10 +1175,26 @@ __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restric
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[NWV][256];
     __shared__ unsigned long long red[NWV][5];
+    __shared__ uint8_t kc[FO_KEYS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int k = tid; k < 256; k += FO_NT) base[k] = 0u;
-    __syncthreads();
     unsigned long long far = 0, cols = 0, vis = 0, mcols = 0, mfar = 0;
+    // the keys and counts first: independent loads (several in flight), keys kept in LDS
+#pragma unroll 4
+    for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
+        const int64_t b = c0 + tid;
+        if (b < nb) {
+            if (order && b < FO_KEYS) kc[b] = (uint8_t)work_key(work[b]);
+            if (lst) {
+                const uint4 L = lst[b];
+                far += L.y; cols += L.z; vis += L.w;
+                mcols = L.z > mcols ? L.z : mcols;
+                mfar = L.y > mfar ? L.y : mfar;
+            }
+        }
+    }
+    __syncthreads();
+    auto key_of = [&](int64_t b) { return b < FO_KEYS ? (uint32_t)kc[b] : work_key(work[b]); };
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // lanes of this wave holding the same key as this lane (valid lanes only)
     auto same_key = [&](bool valid, uint32_t k) {
@@ -1166,22 +1205,16 @@ __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restric
         }
         return same;
     };
-    for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
-        const int64_t b = c0 + tid;
-        const bool valid = b < nb;
-        if (order) {  // counts, one LDS add per key and wave (per-element adds on the few distinct
-                      // keys serialised); the order of the adds is immaterial
-            const uint32_t k = valid ? work_key(work[b]) : 0u;
+    if (order)
+        for (int64_t c0 = 0; c0 < nb; c0 += FO_NT) {
+            // counts, one LDS add per key and wave (per-element adds on the few distinct keys
+            // serialised); the order of the adds is immaterial
+            const int64_t b = c0 + tid;
+            const bool valid = b < nb;
+            const uint32_t k = valid ? key_of(b) : 0u;
             const uint64_t same = same_key(valid, k);
             if (valid && (same & lt) == 0ull) atomicAdd(&base[k], (uint32_t)__popcll(same));
         }
-        if (lst && valid) {
-            const uint4 L = lst[b];
-            far += L.y; cols += L.z; vis += L.w;
-            mcols = L.z > mcols ? L.z : mcols;
-            mfar = L.y > mfar ? L.y : mfar;
-        }
-    }
     if (lst && stats) {
         for (int off = 32; off > 0; off >>= 1) {
             far += __shfl_xor(far, off);
@@ -1222,7 +1255,7 @@ __global__ __launch_bounds__(FO_NT) void ff_order_sort(const uint32_t* __restric
         __syncthreads();
         const int64_t b = c0 + tid;
         const bool valid = b < nb;
-        const uint32_t k = valid ? work_key(work[b]) : 0u;
+        const uint32_t k = valid ? key_of(b) : 0u;
         const uint64_t same = same_key(valid, k);
         const uint32_t rank = (uint32_t)__popcll(same & lt);
         if (valid && rank == 0u) wcnt[w][k] = (uint32_t)__popcll(same);
@@ -1256,8 +1289,8 @@ int64_t ff_list_cap(int64_t n, int leaf) {
     return std::max<int64_t>(1, std::min(nleaf, budget));
 }
 
-// The far field of the tree's target blocks: balls, the classify pass (lists, the blocks' work,
-// interaction counts), the launch order (monopole: heaviest blocks first by this call's work; with
+// The far field of the tree's target blocks (their balls written by launch_tree_moments): the
+// classify pass (lists, the blocks' work, interaction counts), the launch order (monopole: heaviest blocks first by this call's work; with
 // the correction: tree order, which it prefers), the evaluation.  sort: keys, vals, ktmp, vtmp,
 // hist, hoff of a radix sort of ceil(nF / 64) entries.
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
@@ -1268,7 +1301,6 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
-    hipLaunchKernelGGL(target_balls, dim3((unsigned)nb), dim3(64), 0, st, c64, colv, X, bbox, nF, balls);
     hipLaunchKernelGGL(ff_classify, dim3((unsigned)((nb + FFC_NW - 1) / FFC_NW)), dim3(64 * FFC_NW), 0, st, r, H, leaf,
                        nF, balls, theta, cap, ent, lst, work, flags);
     // launch order (monopole) and the interaction counts, in one work-group
