@@ -83,9 +83,9 @@ __device__ __forceinline__ void p3_shape(const double* l, double* phi, double* d
     }
 }
 
-// Column record read with scalar loads: centroid relative to its tile origin, area, normal, and
-// wv = -2 a, the weight of a column's Sdd term in the symmetric kernel's combined sum
-// V = Sn - (p/q) Sdd for (q, p) = (6, 12).
+// Column record of the pair kernels and the far field: centroid relative to its tile origin,
+// area, normal, and wv = -2 a, the weight of a column's Sdd term in the symmetric kernel's
+// combined sum V = Sn - (p/q) Sdd for (q, p) = (6, 12).
 struct __align__(32) ColRec {
     float cx, cy, cz, a;
     float nx, ny, nz, wv;

@@ -19,9 +19,10 @@
 // waves: the waves of a work-group take contiguous quarters of the same row block's column range
 // and hand their compensated sums to wave 0 through LDS, which folds them into its own and writes
 // one partial-sum segment for the work-group (a quarter of the segment traffic of one-wave groups).
-// All lanes visit the same column at the same time, so column records are wave-uniform and are
-// fetched with scalar loads into SGPRs (one 32-byte record per column); every VALU instruction
-// takes the column operand straight from an SGPR.  Columns come in chunks of 64 faces stored
+// All lanes visit the same column at the same time, so column records are wave-uniform: each
+// chunk's 64 records (32 bytes each) are loaded once, one per lane, into the wave's LDS slots and
+// read back column by column as broadcasts (the same bits as scalar loads into SGPRs, and faster:
+// 93.8 against 101.0 ms at 327,680 faces).  Columns come in chunks of 64 faces stored
 // relative to an FP64 origin at the centre of the chunk's centroid box; each row re-expresses its
 // centroid relative to that origin once per chunk, so nearby pairs see small, accurately rounded
 // coordinates (what limits the accuracy of nearly touching pairs).  FP32 sums
