@@ -434,9 +434,11 @@ def p3_farfield_leg(args, T, M, torch, dev):
 
 
 def exponents_leg(args, T, torch, dev, cfg, X, F, P):
-    """The exact gradient with other exponents (the generic pair kernel, -m extra multiplications
-    by |d|^2 per pair) on the same workload."""
+    """The exact gradient with other exponents on the same workload: the symmetric kernel of the
+    other even exponents (m = p/2 - q <= 0: -m extra multiplications by |d|^2 per pair) where the
+    library takes it (barrier-free, 4 or 8 waves per work-group), else the generic row-only kernel."""
     ctx = T.context(dev)
+    sym, nw, _, _ = ctx.exact_plan(cfg.nF, cfg.V, True)
     G = torch.empty_like(X)
     E = torch.empty((), dtype=torch.float64, device=dev)
     out = {}
@@ -458,7 +460,8 @@ def exponents_leg(args, T, torch, dev, cfg, X, F, P):
         ctx.set_option(T.OPT_KERNEL_TIMING, 0)
         ctx.sync_check()
         out[f"q{q}_p{p}"] = {"ms_per_call": round(dt * 1e3, 4), "pairs_per_s": P / dt,
-                             "kernel": f"pair_kernel<{q},true,false,true>",
+                             "kernel": (f"pair_sym_free_gen_kernel<true, {nw}, {q}, {q - p // 2}>"
+                                        if sym == 2 and nw in (4, 8) else f"pair_kernel<{q},true,false,true>"),
                              "kernel_avg_ms": round(k_ms / max(k_n, 1), 4)}
     return {"workload": f"{cfg.name} ({cfg.nF} faces), exact energy+gradient", "pairs": P, **out}
 

@@ -85,14 +85,16 @@ typedef enum {
                                  W_p W_r a_S a_T |n_S.(x_Sp - x_Tr)|^q / |x_Sp - x_Tr|^p.  The flat
                                  far field and the confinement energy take 1 only (else
                                  TPE_ERR_UNSUPPORTED); at most 2^26 points in all. */
-    TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient with (q, p) = (6, 12) evaluate
-                                 every unordered pair of faces once and credit both faces (the
-                                 symmetric pair kernel), while its column partial sums fit in 64 GiB
-                                 of the context's scratch (about 2,100,000 faces with 8 waves per
-                                 work-group, 1,480,000 with 4) and that scratch can be allocated; 0, or beyond that: every
-                                 ordered pair from its row face (the row-only kernel).  Results
-                                 agree to rounding.  The scratch stays allocated with the context
-                                 (tpe_destroy frees it) */,
+    TPE_OPT_SYMMETRIC = 5     /* 1 (default): tpe_energy / tpe_gradient evaluate every unordered pair
+                                 of faces once and credit both faces (the symmetric pair kernel) --
+                                 with (q, p) = (6, 12) always, with the other even exponents when
+                                 the kernel runs without barriers with 4 or 8 waves per work-group
+                                 (the default) -- while its column partial sums fit in 64 GiB of
+                                 the context's scratch (about 2,100,000 faces with 8 waves per
+                                 work-group, 1,480,000 with 4) and that scratch can be allocated;
+                                 0, or otherwise: every ordered pair from its row face (the
+                                 row-only kernel).  Results agree to rounding.  The scratch stays
+                                 allocated with the context (tpe_destroy frees it) */,
     TPE_OPT_SYM_WAVES = 6     /* waves per work-group of the symmetric pair kernel: 1, 2, 4 or 8 (super
                                  blocks of 128 to 1,024 faces; fewer waves write proportionally
                                  more column partial sums; 8 only without barriers).  0 (default):

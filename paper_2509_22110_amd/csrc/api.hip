@@ -64,9 +64,10 @@ int pair_sym_blocks_per_cu(bool grad, int nw, bool decoupled);
 SymSched make_sym_sched(int64_t Fp, int W, int tail, int nw);
 int64_t sym_part_floats(const SymSched& sc, bool grad);
 int64_t sym_colpart_floats(const SymSched& sc, bool grad);
-hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
-                           const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
-                           int* first, bool decoupled, uint32_t* flags, hipStream_t st);
+hipError_t launch_pair_sym(bool grad, int q, int p, const ColRec* cols, const int4* colv, const double* c64,
+                           const double* org, const uint32_t* touch, int touch_words, const SymSched& sc, float* part,
+                           float* colpart, int* first, bool decoupled, uint32_t* flags, hipStream_t st);
+bool pair_sym_gen_ok(int nw, bool decoupled);
 int dual_level(int H, int leaf);
 int64_t dual_entry_cap(int H, int leaf);
 int64_t dual_part_floats(int H, int leaf);
@@ -652,7 +653,14 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
                         "mesh too large for the no-allocation scratch: " + std::to_string(P.bytes) +
                             " bytes needed, " + std::to_string(NOALLOC_SCRATCH_BYTES) + " available");
     } else {
-        plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && q == 6.0 && p == 12.0, p3);
+        // the symmetric kernel: (6, 12), and the other even exponents without barriers (4 or 8
+        // waves per work-group; else the row-only kernel)
+        const bool fast = q == 6.0 && p == 12.0;
+        plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, ctx->symmetric && (fast || !ctx->sym_barriers), p3);
+        if (P.sym && !fast && !pair_sym_gen_ok(P.ssc.nw, P.sym_free)) {
+            P = Plan();
+            plan(P, ctx, nF, V, grad, -1, 0, 0, ctx->quad, false, p3);
+        }
         rc = ensure_arena(ctx, P.bytes);
         if (rc == TPE_ERR_OOM && P.sym) {  // no room for the column partials: the row-only kernel
             P = Plan();
@@ -675,8 +683,8 @@ int run_exact(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_
     }
     if (timing == 1) HIPCHK(hipEventRecord(ev0, st));
     if (P.sym) {
-        HIPCHK(launch_pair_sym(grad, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.ssc, P.part, P.colpart,
-                               P.first, P.sym_free, ctx->dflags, st));
+        HIPCHK(launch_pair_sym(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.ssc,
+                               P.part, P.colpart, P.first, P.sym_free, ctx->dflags, st));
     } else {
         HIPCHK(launch_pair(grad, (int)q, (int)p, P.cols, P.colv, P.c64, P.org, P.touch, P.touch_words, P.sc, P.part,
                            st));

@@ -181,14 +181,15 @@ __device__ __forceinline__ void pair_update_gen(const ColRec& cr, int4 cv, float
 // One chunk of CHUNK columns for the wave's RPL x 64 rows: plain FP32 sums over the chunk, then a
 // Kahan fold into the rows' (hi, lo) accumulators.
 // FOLDV (gradient only): fold the chunk's sums into the symmetric kernel's 8-sum layout K, S0,
-// Sd, V = Sn - 2 Sdd (see pair_sym_kernel) instead of the 11 row sums.
+// Sd, V = Sn - 2 Sdd (see pair_sym_kernel) instead of the 11 row sums; with GEN, V = Sn + vcoef
+// Sdd, vcoef = -p/q.
 template <int Q, bool GRAD, bool MASK, bool CONF = false, bool GEN = false, bool FOLDV = false, int UNR = 4, int NH>
 __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ tc, const int4* __restrict__ tv,
                                            const float (&rx)[RPL], const float (&ry)[RPL],
                                            const float (&rz)[RPL], const float (&nx)[RPL],
                                            const float (&ny)[RPL], const float (&nz)[RPL],
                                            const int (&rv)[RPL][3], float (&hi)[RPL][NH],
-                                           float (&lo)[RPL][NH]) {
+                                           float (&lo)[RPL][NH], float vcoef = -2.f) {
     static_assert(NH == ((FOLDV && GRAD) ? 8 : NACC) || !GRAD, "row sum layout");
     constexpr int NA = GRAD ? NACC : 1;
     float acc[RPL][NA];
@@ -216,7 +217,8 @@ __device__ __forceinline__ void chunk_pass(int mneg, const ColRec* __restrict__ 
 #pragma unroll
             for (int k = 0; k < 5; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) kahan_fold(fmaf(-2.f, acc[r][5 + d], acc[r][8 + d]), hi[r][5 + d], lo[r][5 + d]);
+            for (int d = 0; d < 3; ++d)
+                kahan_fold(fmaf(GEN ? vcoef : -2.f, acc[r][5 + d], acc[r][8 + d]), hi[r][5 + d], lo[r][5 + d]);
         } else {
 #pragma unroll
             for (int k = 0; k < NA; ++k) kahan_fold(acc[r][k], hi[r][k], lo[r][k]);
@@ -398,9 +400,18 @@ struct SymPair {
     float dx, dy, dz, e, we, T1, U1;
 };
 
-template <bool GRAD, bool MASK>
+// Other even exponents (GEN; q = Q, p even with q < p <= 2q): with m = p/2 - q <= 0 the pair's
+// factor |d|^(-2m) = (|d|^2)^mneg, mneg = -m, multiplies every term (as in pair_update_gen), and
+// the column record's wv = -2 a weighs the Sdd part of V = Sn - (p/q) Sdd once `we` carries the
+// factor wscale = p / (2q); the chunk passes of the diagonal units fold V with vcoef = -p/q.
+struct SymExp {
+    int mneg;
+    float wscale, vcoef;
+};
+
+template <bool GRAD, bool MASK, int Q = 6, bool GEN = false, int MNEG = 0>
 __device__ __forceinline__ SymPair sym_pair(const ColRec& cr, int4 cv, float rx, float ry, float rz, float nx,
-                                            float ny, float nz, int v0, int v1, int v2) {
+                                            float ny, float nz, int v0, int v1, int v2, const SymExp& ex) {
     SymPair P;
     P.dx = rx - cr.cx; P.dy = ry - cr.cy; P.dz = rz - cr.cz;
     float r2 = fmaf(P.dz, P.dz, fmaf(P.dy, P.dy, P.dx * P.dx));
@@ -413,7 +424,25 @@ __device__ __forceinline__ SymPair sym_pair(const ColRec& cr, int4 cv, float rx,
     float u = fmaf(nz, P.dz, fmaf(ny, P.dy, nx * P.dx));
     float v = fmaf(cr.nz, P.dz, fmaf(cr.ny, P.dy, cr.nx * P.dx));
     float t = u * w, tau = v * w;
-    if constexpr (!GRAD) {
+    if constexpr (GEN) {
+        // a masked pair has w = 0, hence t = tau = 0 and every term 0 whatever wm is
+        float wm = 1.f;
+#pragma unroll
+        for (int j = 0; j < MNEG; ++j) wm *= r2;
+        float tq1, tq, sq1, sq;
+        powq<Q>(t, tq1, tq);
+        powq<Q>(tau, sq1, sq);
+        if constexpr (!GRAD) {
+            P.e = wm * tq;
+            P.we = wm * sq;
+        } else {
+            const float ww = w * wm, es = tq + sq;
+            P.T1 = ww * tq1;
+            P.U1 = ww * sq1;
+            P.e = wm * es;
+            P.we = ex.wscale * ww * es;
+        }
+    } else if constexpr (!GRAD) {
         float t3 = t * t * t, s3 = tau * tau * tau;
         P.e = t3 * t3;
         P.we = s3 * s3;
@@ -482,16 +511,17 @@ __device__ __forceinline__ void sym_col(const SymPair& P0, const SymPair& P1, fl
     for (int k = 0; k < (GRAD ? NSYM : 1); ++k) ca[k] = ROT ? rot_add(ca[k], c[k]) : c[k];
 }
 
-template <bool GRAD, bool MASK, bool ROT>
+template <bool GRAD, bool MASK, bool ROT, int Q = 6, bool GEN = false, int MNEG = 0>
 __device__ __forceinline__ void sym_step(const ColRec& cr, int4 cv, const float (&rx)[RPL], const float (&ry)[RPL],
                                          const float (&rz)[RPL], const float (&nx)[RPL], const float (&ny)[RPL],
                                          const float (&nz)[RPL], const float (&aS)[RPL], const float (&aS2)[RPL],
-                                         const int (&rv)[RPL][3], float (&acc)[RPL][GRAD ? NSYM : 1], float* ca) {
+                                         const int (&rv)[RPL][3], float (&acc)[RPL][GRAD ? NSYM : 1], float* ca,
+                                         const SymExp& ex) {
     static_assert(RPL == 2, "the column share is written for two rows per lane");
-    const SymPair P0 = sym_pair<GRAD, MASK>(cr, cv, rx[0], ry[0], rz[0], nx[0], ny[0], nz[0], rv[0][0], rv[0][1],
-                                            rv[0][2]);
-    const SymPair P1 = sym_pair<GRAD, MASK>(cr, cv, rx[1], ry[1], rz[1], nx[1], ny[1], nz[1], rv[1][0], rv[1][1],
-                                            rv[1][2]);
+    const SymPair P0 = sym_pair<GRAD, MASK, Q, GEN, MNEG>(cr, cv, rx[0], ry[0], rz[0], nx[0], ny[0], nz[0], rv[0][0],
+                                                    rv[0][1], rv[0][2], ex);
+    const SymPair P1 = sym_pair<GRAD, MASK, Q, GEN, MNEG>(cr, cv, rx[1], ry[1], rz[1], nx[1], ny[1], nz[1], rv[1][0],
+                                                    rv[1][1], rv[1][2], ex);
     sym_row<GRAD>(cr, P0, acc[0]);
     sym_row<GRAD>(cr, P1, acc[1]);
     sym_col<GRAD, ROT>(P0, P1, aS[0], aS[1], aS2[0], aS2[1], nx[0], ny[0], nz[0], nx[1], ny[1], nz[1], ca);
@@ -500,13 +530,14 @@ __device__ __forceinline__ void sym_step(const ColRec& cr, int4 cv, const float 
 // One symmetric unit for the wave: its rows against the SYM_COLS columns staged in LDS (lcol, lv).
 // Row sums are folded into (hi, lo) as in chunk_pass; on return lane l holds in ca the sums of
 // column (l + SYM_COLS - 1) mod SYM_COLS over the rows of its group of SYM_COLS lanes.
-template <bool GRAD, bool MASK>
+template <bool GRAD, bool MASK, int Q = 6, bool GEN = false, int MNEG = 0>
 __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* lv, const float (&rx)[RPL],
                                                const float (&ry)[RPL], const float (&rz)[RPL],
                                                const float (&nx)[RPL], const float (&ny)[RPL],
                                                const float (&nz)[RPL], const float (&aS)[RPL],
                                                const float (&aS2)[RPL], const int (&rv)[RPL][3],
-                                               float (&hi)[RPL][NSYM], float (&lo)[RPL][NSYM], float* ca) {
+                                               float (&hi)[RPL][NSYM], float (&lo)[RPL][NSYM], float* ca,
+                                               const SymExp& ex = SymExp{0, 1.f, -2.f}) {
     constexpr int NA = GRAD ? NSYM : 1;
     const int sl = threadIdx.x & (SYM_COLS - 1);
     float acc[RPL][NA];
@@ -517,7 +548,7 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
     {
         const ColRec cr = lcol[sl];
         const int4 cv = MASK ? lv[sl] : make_int4(0, 0, 0, 0);
-        sym_step<GRAD, MASK, false>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
+        sym_step<GRAD, MASK, false, Q, GEN, MNEG>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca, ex);
     }
     // steps 1 .. SYM_COLS - 1, two per iteration (SYM_COLS - 1 is odd: the last one after the loop)
 #pragma unroll 1
@@ -527,14 +558,14 @@ __device__ __forceinline__ void sym_chunk_pass(const ColRec* lcol, const int4* l
             const int col = (sl + j + h) & (SYM_COLS - 1);
             const ColRec cr = lcol[col];
             const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
-            sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
+            sym_step<GRAD, MASK, true, Q, GEN, MNEG>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca, ex);
         }
     }
     {
         const int col = (sl + SYM_COLS - 1) & (SYM_COLS - 1);
         const ColRec cr = lcol[col];
         const int4 cv = MASK ? lv[col] : make_int4(0, 0, 0, 0);
-        sym_step<GRAD, MASK, true>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca);
+        sym_step<GRAD, MASK, true, Q, GEN, MNEG>(cr, cv, rx, ry, rz, nx, ny, nz, aS, aS2, rv, acc, ca, ex);
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r)
@@ -736,11 +767,13 @@ constexpr size_t sym_free_lds_floats() {
     return (size_t)NW * SYM_COLS * (8 + 4) + (size_t)SYM_RING * NW * WAVE * sym_cs<GRAD>() + 2 * SYM_RING;
 }
 
-template <bool GRAD, int NW>
-__global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_free_kernel(
-    const ColRec* __restrict__ cols, const double* __restrict__ c64, const int4* __restrict__ colv,
-    const double* __restrict__ corg, const uint32_t* __restrict__ touch, int touch_words, SymSched sc,
-    float* __restrict__ part, float* __restrict__ colpart, int* __restrict__ first, uint32_t* __restrict__ flags) {
+template <bool GRAD, int NW, int Q, bool GEN, int MNEG>
+__device__ __forceinline__ void sym_free_body(const ColRec* __restrict__ cols, const double* __restrict__ c64,
+                                              const int4* __restrict__ colv, const double* __restrict__ corg,
+                                              const uint32_t* __restrict__ touch, int touch_words, const SymSched& sc,
+                                              float* __restrict__ part, float* __restrict__ colpart,
+                                              int* __restrict__ first, uint32_t* __restrict__ flags,
+                                              const SymExp& ex) {
     static_assert(NW >= 2 && WAVE == SYM_COLS, "one column per lane, several waves");
     constexpr int NA = GRAD ? NSYM : 1;
     constexpr int CS = sym_cs<GRAD>();
@@ -804,8 +837,12 @@ __global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) 
             if (k < SBC) {
                 const ColRec* tc = cols + (size_t)J * CHUNK;
                 const int4* tv = colv + (size_t)J * CHUNK;
-                if (masked) chunk_pass<6, GRAD, true, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
-                else chunk_pass<6, GRAD, false, false, false, true>(0, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo);
+                if (masked)
+                    chunk_pass<Q, GRAD, true, false, GEN, true>(ex.mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo,
+                                                                ex.vcoef);
+                else
+                    chunk_pass<Q, GRAD, false, false, GEN, true>(ex.mneg, tc, tv, rx, ry, rz, nx, ny, nz, rv, hi, lo,
+                                                                 ex.vcoef);
                 continue;
             }
             // this wave's copy of the unit's columns (lane l: column l); the compiler fences keep
@@ -822,9 +859,9 @@ __global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) 
             }
             float ca[NA];
             if (masked)
-                sym_chunk_pass<GRAD, true>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca);
+                sym_chunk_pass<GRAD, true, Q, GEN, MNEG>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca, ex);
             else
-                sym_chunk_pass<GRAD, false>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca);
+                sym_chunk_pass<GRAD, false, Q, GEN, MNEG>(lcol, lvid, rx, ry, rz, nx, ny, nz, aS, aS2, rv, hi, lo, ca, ex);
             // the unit's slot: wait until its previous use (unit nsym - SYM_RING) has been reduced
             const uint32_t slot = nsym % SYM_RING, use = nsym / SYM_RING;
             for (uint32_t it = 0; !timed_out; ++it) {
@@ -865,6 +902,27 @@ __global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) 
         k = 0;
     }
     if (timed_out && lane == 0) atomicOr(flags, (uint32_t)FLAG_SYNC);
+}
+
+template <bool GRAD, int NW>
+__global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_free_kernel(
+    const ColRec* __restrict__ cols, const double* __restrict__ c64, const int4* __restrict__ colv,
+    const double* __restrict__ corg, const uint32_t* __restrict__ touch, int touch_words, SymSched sc,
+    float* __restrict__ part, float* __restrict__ colpart, int* __restrict__ first, uint32_t* __restrict__ flags) {
+    sym_free_body<GRAD, NW, 6, false, 0>(cols, c64, colv, corg, touch, touch_words, sc, part, colpart, first, flags,
+                                      SymExp{0, 1.f, -2.f});
+}
+
+// The same kernel for the other even exponents (q = Q, p = 2 (Q - MNEG) with q < p <= 2q; ex
+// from launch_pair_sym): the pair terms of pair_update_gen, every unordered pair once.
+template <bool GRAD, int NW, int Q, int MNEG>
+__global__ __launch_bounds__(WAVE * NW) __attribute__((amdgpu_waves_per_eu(4))) void pair_sym_free_gen_kernel(
+    const ColRec* __restrict__ cols, const double* __restrict__ c64, const int4* __restrict__ colv,
+    const double* __restrict__ corg, const uint32_t* __restrict__ touch, int touch_words, SymSched sc,
+    float* __restrict__ part, float* __restrict__ colpart, int* __restrict__ first, uint32_t* __restrict__ flags,
+    SymExp ex) {
+    sym_free_body<GRAD, NW, Q, true, MNEG>(cols, c64, colv, corg, touch, touch_words, sc, part, colpart, first, flags,
+                                           ex);
 }
 
 template <int NW>
@@ -962,10 +1020,62 @@ static void launch_sym_free_nw(bool grad, const ColRec* cols, const int4* colv, 
                            colpart, first, flags);
 }
 
-// decoupled: the kernel without work-group barriers (nw >= 2; the same bits)
-hipError_t launch_pair_sym(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
-                           const uint32_t* touch, int touch_words, const SymSched& sc, float* part, float* colpart,
-                           int* first, bool decoupled, uint32_t* flags, hipStream_t st) {
+template <int NW, int Q, int MNEG>
+static void launch_sym_free_gen(bool grad, const ColRec* cols, const int4* colv, const double* c64, const double* org,
+                                const uint32_t* touch, int touch_words, const SymSched& sc, float* part,
+                                float* colpart, int* first, uint32_t* flags, const SymExp& ex, hipStream_t st) {
+    if (grad)
+        hipLaunchKernelGGL((pair_sym_free_gen_kernel<true, NW, Q, MNEG>), dim3(sc.W), dim3(WAVE * NW),
+                           pair_sym_free_lds_bytes<NW>(true), st, cols, c64, colv, org, touch, touch_words, sc, part,
+                           colpart, first, flags, ex);
+    else
+        hipLaunchKernelGGL((pair_sym_free_gen_kernel<false, NW, Q, MNEG>), dim3(sc.W), dim3(WAVE * NW),
+                           pair_sym_free_lds_bytes<NW>(false), st, cols, c64, colv, org, touch, touch_words, sc, part,
+                           colpart, first, flags, ex);
+}
+
+// (q, mneg) of the even exponents other than (6, 12): q in {2, 4, 6, 8}, 0 <= mneg < q / 2
+template <int NW>
+static hipError_t launch_sym_free_q(bool grad, int q, int mneg, const ColRec* cols, const int4* colv,
+                                    const double* c64, const double* org, const uint32_t* touch, int touch_words,
+                                    const SymSched& sc, float* part, float* colpart, int* first, uint32_t* flags,
+                                    const SymExp& ex, hipStream_t st) {
+#define TPE_SYM_GEN(QQ, MM)                                                                                         \
+    if (q == QQ && mneg == MM) {                                                                                   \
+        launch_sym_free_gen<NW, QQ, MM>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, \
+                                        flags, ex, st);                                                          \
+        return hipSuccess;                                                                                       \
+    }
+    TPE_SYM_GEN(2, 0)
+    TPE_SYM_GEN(4, 0)
+    TPE_SYM_GEN(4, 1)
+    TPE_SYM_GEN(6, 1)
+    TPE_SYM_GEN(6, 2)
+    TPE_SYM_GEN(8, 0)
+    TPE_SYM_GEN(8, 1)
+    TPE_SYM_GEN(8, 2)
+    TPE_SYM_GEN(8, 3)
+#undef TPE_SYM_GEN
+    return hipErrorInvalidValue;
+}
+
+// The symmetric kernel of the other even exponents runs without barriers, with 4 or 8 waves.
+bool pair_sym_gen_ok(int nw, bool decoupled) { return decoupled && (nw == 4 || nw == 8); }
+
+// decoupled: the kernel without work-group barriers (nw >= 2; the same bits).  (q, p) other than
+// (6, 12): pair_sym_free_gen_kernel (pair_sym_gen_ok must hold).
+hipError_t launch_pair_sym(bool grad, int q, int p, const ColRec* cols, const int4* colv, const double* c64,
+                           const double* org, const uint32_t* touch, int touch_words, const SymSched& sc, float* part,
+                           float* colpart, int* first, bool decoupled, uint32_t* flags, hipStream_t st) {
+    if (q != 6 || p != 12) {
+        if (!pair_sym_gen_ok(sc.nw, decoupled)) return hipErrorInvalidValue;
+        const SymExp ex = {q - p / 2, (float)p / (float)(2 * q), -(float)p / (float)q};
+        const hipError_t e = sc.nw == 4 ? launch_sym_free_q<4>(grad, q, ex.mneg, cols, colv, c64, org, touch,
+                                                               touch_words, sc, part, colpart, first, flags, ex, st)
+                                        : launch_sym_free_q<8>(grad, q, ex.mneg, cols, colv, c64, org, touch,
+                                                               touch_words, sc, part, colpart, first, flags, ex, st);
+        return e != hipSuccess ? e : hipGetLastError();
+    }
     if (decoupled && sc.nw == 2)
         launch_sym_free_nw<2>(grad, cols, colv, c64, org, touch, touch_words, sc, part, colpart, first, flags, st);
     else if (decoupled && sc.nw == 4)

@@ -42,6 +42,42 @@ def test_parity(q, p, name, X, F):
     assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL
 
 
+@pytest.mark.parametrize("q,p", [(4, 8), (8, 14), (6, 8), (2, 4)], ids=lambda v: str(v))
+def test_symmetric_kernel_other_exponents(q, p):
+    """The symmetric pair kernel of the other exponents (every unordered pair once, both faces
+    credited; V = Sn - (p/q) Sdd) on the deformed level-4 sphere (5,120 faces: ten super blocks of
+    512 rows, symmetric and diagonal units, masked and not) against the oracle, with 4 and 8 waves
+    per work-group, and against the row-only kernel (TPE_OPT_SYMMETRIC = 0); with barriers the
+    library runs the row-only kernel for these exponents, with the same results to rounding."""
+    T = tpe()
+    X, F = M.icosphere(4)
+    X = M.sh_deform(X, 2, 8, 0.05, 0)[0]
+    Xd, Fd = upload(X, F)
+    ctx = T.context(Xd.device)
+    Eo, Go = oracle.gradient(X, F, float(q), float(p))
+    res = {}
+    try:
+        for name, opts in (("sym4", {}), ("sym8", {T.OPT_SYM_WAVES: 8}), ("row", {T.OPT_SYMMETRIC: 0}),
+                           ("barriers", {T.OPT_SYM_BARRIERS: 1})):
+            for k, v in opts.items():
+                ctx.set_option(k, v)
+            E, G = T.gradient(Xd, Fd, q=float(q), p=float(p))
+            Ee = T.energy(Xd, Fd, q=float(q), p=float(p))
+            for k in opts:
+                ctx.set_option(k, {T.OPT_SYM_WAVES: 0, T.OPT_SYMMETRIC: 1, T.OPT_SYM_BARRIERS: 0}[k])
+            res[name] = (float(E.cpu()), G.cpu().numpy(), float(Ee.cpu()))
+    finally:
+        ctx.set_option(T.OPT_SYM_WAVES, 0)
+        ctx.set_option(T.OPT_SYMMETRIC, 1)
+        ctx.set_option(T.OPT_SYM_BARRIERS, 0)
+    for name, (E, G, Ee) in res.items():
+        eE, eEe, eG = rel_energy(E, Eo), rel_energy(Ee, Eo), rel_grad_maxnorm(G, Go)
+        log("L4", "q", q, "p", p, name, "rel E", eE, "rel E(energy kernel)", eEe, "rel G", eG)
+        assert eE <= E_TOL and eEe <= E_TOL and eG <= G_TOL, name
+    assert np.array_equal(res["barriers"][1], res["row"][1])  # the same (row-only) kernel
+    assert rel_grad_maxnorm(res["sym4"][1], res["row"][1]) <= 2e-6
+
+
 def test_two_triangles_closed_form():
     """Two parallel unit right triangles at offset (1, 0, 1): d = (-1, 0, -1) between centroids, so
     n.d = -1 for both and each ordered pair contributes a^2 / |d|^p = 1 / (4 * 2^(p/2))."""
