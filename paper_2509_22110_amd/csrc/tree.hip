@@ -128,6 +128,9 @@ __device__ __forceinline__ double group_max_d(double x, int G) {
 }
 
 template <bool MOM2>
+__device__ __forceinline__ void store_node(NodeF64* __restrict__ d, const NodeF64& n);
+
+template <bool MOM2>
 __global__ __launch_bounds__(64 * MOM_LEAF_WAVES) void leaf_moments(const double* __restrict__ c64,
                                                                     const double* __restrict__ geo,
                                                                     const int4* __restrict__ colv,
