@@ -19,6 +19,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtpe.so")
+# stand-alone measurement tool (not part of libtpe): FP32 VALU issue rates of the pair kernels' mixes
+PROBE_SRC = os.path.join(PKG, "measure", "valu_issue.hip")
+PROBE_BIN = os.path.join(PKG, "measure", "valu_issue")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 DEVICE_FLAGS = [
@@ -44,12 +47,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _build_probe() -> str:
+    """Compile the VALU issue-rate tool (measure/valu_issue.hip) into an executable beside it."""
+    cmd = [HIPCC, *[f for f in DEVICE_FLAGS if f != "-fPIC"], PROBE_SRC, "-o", PROBE_BIN]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        msgs = [l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l and l.strip()]
+        raise RuntimeError("hipcc failed for " + PROBE_SRC + ":\n" + "\n".join(msgs))
+    return PROBE_BIN
+
+
 def build(jobs: int = 8) -> str:
-    """Compile all HIP sources and link libtpe.so; always rebuilds.  Returns the library path."""
+    """Compile all HIP sources and link libtpe.so, and the measurement tool; always rebuilds.
+    Returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs) + 1))) as ex:
+        probe = ex.submit(_build_probe)
         objs = list(ex.map(_compile, srcs))
+        probe.result()
     tmp = LIB + ".tmp"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp],
                        capture_output=True, text=True)
