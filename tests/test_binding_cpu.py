@@ -64,3 +64,14 @@ def test_version_and_null_args():
     L.tpe_last_error.restype = ctypes.c_char_p
     L.tpe_last_error.argtypes = [ctypes.c_void_p]
     assert L.tpe_last_error(None) == b"null context"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N with N > 1 exits with status 2 and says so, before any
+    GPU call (so this runs without a GPU)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
