@@ -74,11 +74,34 @@ __device__ __forceinline__ void ff_fold(float (&acc)[NACC], float (&hi)[NACC], f
     }
 }
 
-// The pairs of the block's rows with m <= 64 column records already staged in the wave's slots.
-template <bool MASK, int SU>
+// The same fold with the compensation terms in LDS (LOL): slot k * 64 + lane of the wave's own
+// area lol, touched only here, once per 64 columns, so the registers lo stay free.  The same values
+// and operations, so the same bits.
+template <bool LOL>
+__device__ __forceinline__ void ff_fold_at(float (&acc)[NACC], float (&hi)[NACC], float (&lo)[NACC], float* lol,
+                                           int lane) {
+    if constexpr (!LOL) {
+        ff_fold(acc, hi, lo);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k) {
+            const float l = lol[k * 64 + lane];
+            float y = acc[k] - l;
+            float t = hi[k] + y;
+            lol[k * 64 + lane] = (t - hi[k]) - y;
+            hi[k] = t;
+            acc[k] = 0.f;
+        }
+    }
+}
+
+// The pairs of the block's rows with m <= 64 column records already staged in the wave's slots,
+// SU independent pair chains per step; LOL: compensation terms in the wave's LDS slots lol.
+template <bool MASK, int SU, bool LOL = false>
 __device__ __forceinline__ void ff_staged_pairs(const ColRec* st, const int4* sv, int m, float rx, float ry, float rz,
                                                 const ColRec& me, const int4& mv, float (&acc)[NACC],
-                                                float (&hi)[NACC], float (&lo)[NACC], int& cnt) {
+                                                float (&hi)[NACC], float (&lo)[NACC], float* lol, int lane,
+                                                int& cnt) {
     const int4 nov = make_int4(0, 0, 0, 0);
     int k = 0;
     for (; k + SU <= m; k += SU) {
@@ -87,11 +110,11 @@ __device__ __forceinline__ void ff_staged_pairs(const ColRec* st, const int4* sv
             ff_pair<6, true, MASK>(st[k + u], MASK ? sv[k + u] : nov, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y,
                                    mv.z, acc);
         cnt += SU;
-        if (cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        if (cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
     }
     for (; k < m; ++k) {
         ff_pair<6, true, MASK>(st[k], MASK ? sv[k] : nov, rx, ry, rz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
-        if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        if (++cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
     }
 }
 
@@ -101,14 +124,17 @@ __device__ __forceinline__ void ff_staged_pairs(const ColRec* st, const int4* sv
 // LDS slots st[64] / sv[64]: every piece of at most 64 faces within one origin tile is fetched with
 // one coalesced load per lane and read back column by column at a wave-uniform address (a
 // broadcast), SU columns per step.  At 327,680 faces the monopole far field took 0.95 ms per call
-// this way against 1.12 ms with the columns read by scalar loads four at a time (the same pairs in
-// the same order; loading the next piece into registers while evaluating this one: 0.97 ms).
-template <bool MASK, int SU>
+// this way with 2 columns per step against 1.12 ms with the columns read by scalar loads four at a
+// time (the same pairs in the same order; loading the next piece into registers while evaluating
+// this one: 0.97 ms).  With LOL the compensation terms live in LDS (ff_fold_at) and the registers
+// allow 8 columns per step: 0.92 ms.
+template <bool MASK, int SU, bool LOL = false>
 __device__ __forceinline__ void ff_near_staged(const ColRec* __restrict__ cols, const int4* __restrict__ colv,
                                                const double* __restrict__ org, int64_t f0, int64_t f1, double cxd,
                                                double cyd, double czd, const ColRec& me, const int4& mv,
                                                ColRec* st, int4* sv, int lane, float (&acc)[NACC],
-                                               float (&hi)[NACC], float (&lo)[NACC], int& cnt) {
+                                               float (&hi)[NACC], float (&lo)[NACC], int& cnt,
+                                               float* lol = nullptr) {
     static_assert(CTILE <= 64, "a piece must fit the wave's 64 slots");
     const int4 nov = make_int4(0, 0, 0, 0);
     int64_t f = f0;
@@ -133,7 +159,7 @@ __device__ __forceinline__ void ff_near_staged(const ColRec* __restrict__ cols, 
         dst[1] = c1;
         if constexpr (MASK) sv[lane] = v;
         asm volatile("" ::: "memory");  // the reads below see every lane's record
-        ff_staged_pairs<MASK, SU>(st, sv, m, rx, ry, rz, me, mv, acc, hi, lo, cnt);
+        ff_staged_pairs<MASK, SU, LOL>(st, sv, m, rx, ry, rz, me, mv, acc, hi, lo, lol, lane, cnt);
         f = fend;
     }
 }

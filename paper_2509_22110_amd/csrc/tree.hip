@@ -636,6 +636,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     float hi[NACC], lo[NACC], acc[NACC];
 #pragma unroll
     for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
+    // the monopole evaluation keeps its compensation terms in the fold area during the walk (LOL,
+    // each wave its own slots, touched once per 64 columns): the registers go to more columns per
+    // step below
+    constexpr bool LOL = !LEARNED && NW > 1;
+    static_assert(!LOL || NW * NACC <= NRED * 2 * NACC, "the waves' compensation terms fit the fold area");
+    float* lol = LOL ? &red_own[0][0][0] + (size_t)wave * NACC * 64 : nullptr;
+    if constexpr (LOL) {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k) lol[k * 64 + lane] = 0.f;
+    }
     int cnt = 0;
     const int4 nov = make_int4(0, 0, 0, 0);
     // far clusters: one pseudo-face each
@@ -675,7 +685,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
                 const NodeRec nd = fst[wave][k];
                 const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
                 ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
-                if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+                if (++cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
             }
         }
     }
@@ -702,17 +712,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
             const NodeRec nd = nodes[kk];
             disjoint = ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r;
         }
-        // columns per step: 2 keep the monopole evaluation within 128 VGPRs (4 waves per SIMD); the
-        // learned evaluation runs at 3 either way and prefers 4
-        constexpr int SU = LEARNED ? 4 : 2;
+        // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with
+        // the compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2,
+        // 0.922 with 4 and 0.915 with 8); the learned evaluation runs at 3 waves either way and
+        // prefers 4
+        constexpr int SU = LEARNED ? 4 : 8;
         if (disjoint)
-            ff_near_staged<false, SU>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
-                                      acc, hi, lo, cnt);
+            ff_near_staged<false, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave],
+                                           lane, acc, hi, lo, cnt, lol);
         else
-            ff_near_staged<true, SU>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
-                                     acc, hi, lo, cnt);
+            ff_near_staged<true, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
+                                          acc, hi, lo, cnt, lol);
     }
-    ff_fold(acc, hi, lo);
+    ff_fold_at<LOL>(acc, hi, lo, lol, lane);
+    if constexpr (LOL) {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k) lo[k] = lol[k * 64 + lane];
+        __syncthreads();  // every wave has its terms back before the fold area is reused below
+    }
     if constexpr (NW > 1) {
         if constexpr (LEARNED) __syncthreads();  // the MLP scratch is reused below
         if (wave > 0) {
