@@ -111,11 +111,13 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
-                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, hipStream_t st);
+                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, const uint2* xm,
+                           hipStream_t st);
 int64_t ff_list_cap(int64_t n, int leaf);
 hipError_t launch_block_neighbours(const int4* colv, const uint32_t* voff, const uint32_t* vlist, int64_t nF,
-                                   int64_t V, int leaf, uint32_t* nbl, hipStream_t st);
+                                   int64_t V, uint32_t* nbl, uint2* xm, hipStream_t st);
 int64_t block_neighbour_words(int64_t n);
+int64_t block_exclusion_mask_words(int64_t n);
 
 // Per sorted face: number of faces (itself included) that share at least one vertex with it.
 __global__ void excluded_count(const int4* __restrict__ colv, int64_t nF, int64_t V, const uint32_t* __restrict__ off,
@@ -252,7 +254,8 @@ struct tpe_tree {
     uint32_t* voff = nullptr;
     uint32_t* vlist = nullptr;
     uint32_t* fsum = nullptr;
-    uint32_t* nbl = nullptr;   // flat trees: per target block, the leaves sharing a vertex with it
+    uint32_t* nbl = nullptr;   // flat trees: per target block, the tiles holding a face that shares a vertex with it
+    uint2* xm = nullptr;       // flat trees: per (target block, listed tile, row) the 64-bit exclusion mask
 };
 
 namespace {
@@ -764,6 +767,7 @@ int run_conf(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t
 void free_tree(tpe_tree* t) {
     for (uint32_t* p : {t->perm, t->work, t->voff, t->vlist, t->fsum, t->nbl})
         if (p) (void)hipFree(p);
+    if (t->xm) (void)hipFree(t->xm);
     delete t;
 }
 
@@ -783,7 +787,8 @@ int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out,
         (voff && (hipMalloc(&t->voff, (t->V + 1) * sizeof(uint32_t)) != hipSuccess ||
                   hipMalloc(&t->vlist, 3 * t->n * sizeof(uint32_t)) != hipSuccess ||
                   hipMalloc(&t->fsum, sizeof(uint32_t)) != hipSuccess ||
-                  hipMalloc(&t->nbl, block_neighbour_words(t->n) * sizeof(uint32_t)) != hipSuccess))) {
+                  hipMalloc(&t->nbl, block_neighbour_words(t->n) * sizeof(uint32_t)) != hipSuccess ||
+                  hipMalloc(&t->xm, block_exclusion_mask_words(t->n) * sizeof(uint2)) != hipSuccess))) {
         (void)hipGetLastError();
         return drop(fail(ctx, TPE_ERR_OOM, "tree allocation failed"));
     }
@@ -793,7 +798,7 @@ int finish_tree(tpe_ctx* ctx, tpe_tree* t, const uint32_t* perm, tpe_tree** out,
     if (e == hipSuccess && voff)
         e = hipMemcpyAsync(t->vlist, vlist, 3 * t->n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && voff) e = hipMemcpyAsync(t->fsum, fsum, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && voff) e = launch_block_neighbours(colv, t->voff, t->vlist, t->n, t->V, t->leaf, t->nbl, st);
+    if (e == hipSuccess && voff) e = launch_block_neighbours(colv, t->voff, t->vlist, t->n, t->V, t->nbl, t->xm, st);
     if (e == hipSuccess) e = launch_fill(t->work, 0u, nb, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return drop(hip_fail(ctx, e, "tree set-up"));
@@ -1128,7 +1133,7 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, nullptr, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, nullptr, nullptr, st));
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
@@ -1203,7 +1208,7 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, tree->nbl, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, tree->nbl, tree->xm, st));
     }
     if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));

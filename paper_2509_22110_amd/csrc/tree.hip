@@ -528,22 +528,25 @@ __global__ __launch_bounds__(64 * FFC_NW) void ff_classify(const NodeRec* __rest
     }
 }
 
-// Leaves holding a face that shares a vertex with a target block (the block's own leaves among
-// them), per block of 64 faces: nbl[b * NBL_STRIDE] = their count (NBL_OVERFLOW if more than
-// NBL_MAX), then the leaf ids in ascending order.  A near node of the walk needs the shared-vertex
-// exclusion exactly when it holds one of these leaves; masked and unmasked evaluation give the
-// same bits on a node without such a face, so the list only saves the vertex comparisons.  They
-// depend on the faces and the order only (built once per tree).  One wave per block: every lane
-// walks its face's three vertex lists and inserts the leaves into an LDS hash set.
+// Tiles (CTILE = 64 consecutive sorted faces, the unit the near loop stages) holding a face that
+// shares a vertex with a target block (the block's own tile among them), per block of 64 faces:
+// nbl[b * NBL_STRIDE] = their count (NBL_OVERFLOW if more than NBL_MAX), then the tile ids in
+// ascending order; and per (block, listed tile s, row lane) the 64-bit exclusion mask
+// xm[(b * NBL_MAX + s) * 64 + lane], bit j set when the block's face 64 b + lane shares a vertex
+// with the tile's face 64 t + j (itself included).  A piece of a near node needs the exclusion
+// exactly when its tile is listed, and then tests one bit per pair instead of comparing nine vertex
+// ids; the unmasked and masked loops give the same bits wherever no pair is excluded.  Both depend
+// on the faces and the order only (built once per tree).  One wave per block: every lane walks its
+// face's three vertex lists and inserts the tiles into an LDS hash set.
 constexpr int NBL_MAX = 16;
 constexpr int NBL_STRIDE = NBL_MAX + 1;
 constexpr uint32_t NBL_OVERFLOW = 0xffffffffu;
 
-__global__ __launch_bounds__(64) void block_neighbour_leaves(const int4* __restrict__ colv,
-                                                             const uint32_t* __restrict__ voff,
-                                                             const uint32_t* __restrict__ vlist, int64_t nF,
-                                                             int64_t V, int leaf, uint32_t* __restrict__ nbl) {
-    constexpr int HS = 256;  // hash slots (a block touches a few dozen leaves at most on a manifold)
+__global__ __launch_bounds__(64) void block_neighbour_tiles(const int4* __restrict__ colv,
+                                                            const uint32_t* __restrict__ voff,
+                                                            const uint32_t* __restrict__ vlist, int64_t nF,
+                                                            int64_t V, uint32_t* __restrict__ nbl) {
+    constexpr int HS = 256;  // hash slots (a block touches a few dozen tiles at most on a manifold)
     __shared__ uint32_t set[HS];
     __shared__ uint32_t nset;
     const int lane = threadIdx.x;
@@ -559,7 +562,7 @@ __global__ __launch_bounds__(64) void block_neighbour_leaves(const int4* __restr
         for (int k = 0; k < 3 && !full; ++k) {
             if (vv[k] < 0 || vv[k] >= V) continue;
             for (uint32_t s = voff[vv[k]]; s < voff[vv[k] + 1] && !full; ++s) {
-                const uint32_t lf = (uint32_t)((vlist[s] / 3) / (uint32_t)leaf);
+                const uint32_t lf = (uint32_t)((vlist[s] / 3) / (uint32_t)CTILE);
                 uint32_t h = (lf * 0x9e3779b9u) >> 24;  // HS = 256 slots
                 for (int probe = 0; probe < HS; ++probe, h = (h + 1) & (HS - 1)) {
                     const uint32_t old = atomicCAS(&set[h], 0xffffffffu, lf);
@@ -592,13 +595,41 @@ __global__ __launch_bounds__(64) void block_neighbour_leaves(const int4* __restr
     }
 }
 
+// One wave per (block, listed tile): the rows' exclusion masks of that tile.
+__global__ __launch_bounds__(64) void block_exclusion_masks(const int4* __restrict__ colv, int64_t nF,
+                                                            const uint32_t* __restrict__ nbl, uint2* __restrict__ xm) {
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const uint32_t s = blockIdx.y;
+    const uint32_t n = nbl[(size_t)b * NBL_STRIDE];
+    if (n > (uint32_t)NBL_MAX || s >= n) return;
+    const int64_t t = nbl[(size_t)b * NBL_STRIDE + 1 + s];
+    const int64_t i = b * 64 + lane;
+    uint32_t lo = 0u, hi = 0u;
+    if (i < nF) {
+        const int4 r = colv[i];
+        for (int j = 0; j < CTILE && t * CTILE + j < nF; ++j) {
+            const int4 v = colv[t * CTILE + j];
+            const bool shared = (r.x == v.x) | (r.x == v.y) | (r.x == v.z) | (r.y == v.x) | (r.y == v.y) |
+                                (r.y == v.z) | (r.z == v.x) | (r.z == v.y) | (r.z == v.z);
+            if (shared) {
+                if (j < 32) lo |= 1u << j;
+                else hi |= 1u << (j - 32);
+            }
+        }
+    }
+    xm[((size_t)b * NBL_MAX + s) * 64 + lane] = make_uint2(lo, hi);
+}
+
 hipError_t launch_block_neighbours(const int4* colv, const uint32_t* voff, const uint32_t* vlist, int64_t nF,
-                                   int64_t V, int leaf, uint32_t* nbl, hipStream_t st) {
-    hipLaunchKernelGGL(block_neighbour_leaves, dim3((unsigned)((nF + 63) / 64)), dim3(64), 0, st, colv, voff, vlist,
-                       nF, V, leaf, nbl);
+                                   int64_t V, uint32_t* nbl, uint2* xm, hipStream_t st) {
+    const unsigned nb = (unsigned)((nF + 63) / 64);
+    hipLaunchKernelGGL(block_neighbour_tiles, dim3(nb), dim3(64), 0, st, colv, voff, vlist, nF, V, nbl);
+    hipLaunchKernelGGL(block_exclusion_masks, dim3(nb, NBL_MAX), dim3(64), 0, st, colv, nF, nbl, xm);
     return hipGetLastError();
 }
 int64_t block_neighbour_words(int64_t n) { return ((n + 63) / 64) * NBL_STRIDE; }
+int64_t block_exclusion_mask_words(int64_t n) { return ((n + 63) / 64) * NBL_MAX * 64; }
 
 // One work-group of NW waves per target block (launch order `order`, else tree order): the block's
 // far clusters and near nodes from ff_classify's lists, entry j of each list to wave j mod NW, far
@@ -613,7 +644,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     const double* __restrict__ org, const NodeRec* __restrict__ nodes, const NodeMom* __restrict__ moms,
     const MlpPacked* __restrict__ W, int H, int leaf, int64_t nF, const uint32_t* __restrict__ bbox,
     const float4* __restrict__ balls, int64_t Fp, double* __restrict__ acc64, const uint32_t* __restrict__ order,
-    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst, const uint32_t* __restrict__ nbl) {
+    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst, const uint32_t* __restrict__ nbl,
+    const uint2* __restrict__ xm) {
     constexpr int NRED = NW > 1 ? NW - 1 : 1;
     __shared__ MlpScratch ms[LEARNED ? NW : 1];
     __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
@@ -703,35 +735,34 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
             }
         }
     }
-    // near nodes: exact pairs over their faces, with the shared-vertex test only where the node
-    // holds a leaf of the block's neighbour list; without that list (curved elements, or more than
-    // NBL_MAX such leaves) only where their vertex balls can meet (conservative margin for FP32)
+    // near nodes: exact pairs over their faces.  With the block's neighbour tiles listed, each piece
+    // of a node tests its tile against the list (one compare and a ballot) and reads the rows'
+    // exclusion bits where it is listed; without the list (curved elements, or more than NBL_MAX
+    // such tiles) the vertex ids are compared wherever the node's and the block's vertex balls can
+    // meet (conservative margin for FP32)
     __shared__ ColRec nst[NW][64];
     __shared__ int4 nsv[NW][64];
     const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
-    // lane m < nn holds neighbour leaf m (the test of a node is then one compare and a ballot)
-    const uint32_t my_leaf = nn <= (uint32_t)NBL_MAX && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane]
-                                                                             : 0xffffffffu;
+    const bool listed = nn <= (uint32_t)NBL_MAX;
+    const uint32_t my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
+    const uint2* xmb = xm ? xm + (size_t)b * NBL_MAX * 64 : nullptr;
+    // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with the
+    // compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2, 0.922 with 4
+    // and 0.915 with 8); the learned evaluation runs at 3 waves either way and prefers 4
+    constexpr int SU = LEARNED ? 4 : 8;
     for (uint32_t j = wave; j < L.x; j += NW) {
         const int64_t kk = (int64_t)e[j];
         const int lev = 63 - __builtin_clzll((unsigned long long)kk);
         const int64_t span = (int64_t)1 << (H - lev);
         const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
         const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-        bool disjoint;
-        if (nn <= (uint32_t)NBL_MAX) {
-            const uint32_t l0 = (uint32_t)(f0 / leaf), l1 = (uint32_t)((f1 - 1) / leaf);
-            disjoint = __ballot(my_leaf >= l0 && my_leaf <= l1) == 0ull;
-        } else {
-            const NodeRec nd = nodes[kk];
-            disjoint = ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r;
+        if (listed) {
+            ff_near_tiles<SU, LOL>(cols, org, f0, f1, cxd, cyd, czd, me, my_tile, xmb, nst[wave], lane, acc, hi, lo,
+                                   cnt, lol);
+            continue;
         }
-        // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with
-        // the compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2,
-        // 0.922 with 4 and 0.915 with 8); the learned evaluation runs at 3 waves either way and
-        // prefers 4
-        constexpr int SU = LEARNED ? 4 : 8;
-        if (disjoint)
+        const NodeRec nd = nodes[kk];
+        if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
             ff_near_staged<false, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave],
                                            lane, acc, hi, lo, cnt, lol);
         else
@@ -1331,7 +1362,8 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
-                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, hipStream_t st) {
+                           uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, const uint2* xm,
+                           hipStream_t st) {
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
@@ -1344,11 +1376,11 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     if (mlp_packed)
         hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
                            colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,
-                           order, cap, ent, lst, nbl);
+                           order, cap, ent, lst, nbl, xm);
     else
         hipLaunchKernelGGL((ff_eval<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org,
                            r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst,
-                           nbl);
+                           nbl, xm);
     return hipGetLastError();
 }
 
