@@ -74,9 +74,11 @@ typedef enum {
                                  0 (default) = as many as the device keeps resident at once.  The
                                  work is split evenly over them; results agree to rounding */
     TPE_OPT_KERNEL_TIMING = 3, /* 1: record HIP events around every launch of the dominant
-                                 kernel (the pair kernel, or the far-field walk) on the context's
-                                 stream; 2: around the finalize + vertex-gather launches; read
-                                 back with tpe_kernel_time(); 0 (default): off */
+                                 kernel (the pair kernel; the far-field evaluation kernel of
+                                 tpe_farfield / tpe_farfield_p3, after its classify and launch-order
+                                 passes; the whole dual-tree pipeline of tpe_farfield_dual) on the
+                                 context's stream; 2: around the finalize + vertex-gather launches;
+                                 read back with tpe_kernel_time(); 0 (default): off */
     TPE_OPT_QUADRATURE = 4,   /* quadrature points per face of tpe_energy / tpe_gradient and per
                                  element of tpe_energy_p3 / tpe_gradient_p3 / tpe_build_tree_p3:
                                  1 (default, the centroid), 3 (degree 2) or 6 (degree 4); the
@@ -401,7 +403,7 @@ int tpe_farfield_stats(tpe_ctx* ctx, int64_t* out_host);
 int tpe_exact_plan(tpe_ctx* ctx, int64_t nF, int64_t V, int32_t grad, int64_t* out_host);
 
 /* With TPE_OPT_KERNEL_TIMING on: synchronise the stream, then *total_ms (host) <- summed
- * duration of the dominant-kernel launches (the exact pair kernel, or the far-field traversal)
+ * duration of the dominant-kernel launches (see TPE_OPT_KERNEL_TIMING)
  * recorded since the last call and *count (host) <- their
  * number; the record is cleared. */
 int tpe_kernel_time(tpe_ctx* ctx, double* total_ms, int64_t* count);

@@ -112,7 +112,7 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
                            uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, const uint2* xm,
-                           hipStream_t st);
+                           hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
 int64_t ff_list_cap(int64_t n, int leaf);
 hipError_t launch_block_neighbours(const int4* colv, const uint32_t* voff, const uint32_t* vlist, int64_t nF,
                                    int64_t V, uint32_t* nbl, uint2* xm, hipStream_t st);
@@ -1128,14 +1128,14 @@ int tpe_farfield_p3(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    {  // the walk writes all six counts of ctx->dstats
+    {  // the walk writes all six counts of ctx->dstats; kernel timing 1: events around the evaluation
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
+        const bool t1 = ctx->kernel_timing == 1;
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, n, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, nullptr, nullptr, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, nullptr, nullptr,
+                               t1 ? ev0 : nullptr, t1 ? ev1 : nullptr, st));
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_p3_finalize(true, nullptr, P.sc, P.Fp, n, 1, Q, P.acc64, tree->perm, F10, V, X, P.bbox, q, p, scale,
@@ -1203,14 +1203,14 @@ int tpe_farfield(tpe_ctx* ctx, const tpe_tree* tree, const double* X, int64_t V,
     if (ctx->kernel_timing) {
         if ((rc = timing_events(ctx, &ev0, &ev1))) return rc;
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev0, st));
-    {  // the walk writes all six counts of ctx->dstats
+    {  // the walk writes all six counts of ctx->dstats; kernel timing 1: events around the evaluation
         uint32_t* const sortbuf[6] = {P.keys, P.vals, P.ktmp, P.vtmp, P.hist, P.hoff};
+        const bool t1 = ctx->kernel_timing == 1;
         HIPCHK(launch_farfield(P.cols, P.colv, P.c64, P.org, X, P.bbox, P.recs, tree->H, tree->leaf, nF, P.Fp,
                                (float)theta, mlp ? mlp->packed : nullptr, P.balls, P.acc64, ctx->dstats, tree->work,
-                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, tree->nbl, tree->xm, st));
+                               P.ff_ent, P.ff_lst, P.ff_cap, ctx->dflags, sortbuf, tree->nbl, tree->xm,
+                               t1 ? ev0 : nullptr, t1 ? ev1 : nullptr, st));
     }
-    if (ctx->kernel_timing == 1) HIPCHK(hipEventRecord(ev1, st));
     if (ctx->kernel_timing == 2) HIPCHK(hipEventRecord(ev0, st));
     EnergyOut en = {};  // with the gradient, the energy is summed by the gather's extra work-group
     HIPCHK(launch_finalize(true, nullptr, P.sc, P.Fp, nF, P.acc64, P.geo, P.colv, X, P.bbox, q, p, scale, 0.5, 1,

@@ -1357,13 +1357,14 @@ int64_t ff_list_cap(int64_t n, int leaf) {
 // The far field of the tree's target blocks (their balls written by launch_tree_moments): the
 // classify pass (lists, the blocks' work, interaction counts), the launch order (monopole: heaviest blocks first by this call's work; with
 // the correction: tree order, which it prefers), the evaluation.  sort: keys, vals, ktmp, vtmp,
-// hist, hoff of a radix sort of ceil(nF / 64) entries.
+// hist, hoff of a radix sort of ceil(nF / 64) entries.  ev0 / ev1 (nullable): HIP events recorded
+// around the evaluation launch alone.
 hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c64, const double* org,
                            const double* X, const uint32_t* bbox, const void* recs, int H, int leaf, int64_t nF,
                            int64_t Fp, float theta, const void* mlp_packed, float4* balls, double* acc64,
                            unsigned long long* stats, uint32_t* work, uint32_t* ent, uint4* lst, int64_t cap,
                            uint32_t* flags, uint32_t* const sort[6], const uint32_t* nbl, const uint2* xm,
-                           hipStream_t st) {
+                           hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
     const int64_t nb = (nF + 63) / 64;  // padding rows past nF ride along in the last block only
     const NodeRec* r = (const NodeRec*)recs;
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
@@ -1373,6 +1374,7 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     const uint32_t* order = mlp_packed ? nullptr : sort[1];
     hipError_t e = launch_ff_order(work, nb, mlp_packed ? nullptr : sort[1], lst, stats, st);
     if (e != hipSuccess) return e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;  // timing: the evaluation alone
     if (mlp_packed)
         hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
                            colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,
@@ -1381,7 +1383,8 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
         hipLaunchKernelGGL((ff_eval<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org,
                            r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst,
                            nbl, xm);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return ev1 ? hipEventRecord(ev1, st) : hipSuccess;
 }
 
 }  // namespace tpe
