@@ -680,8 +680,26 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     }
     int cnt = 0;
     const int4 nov = make_int4(0, 0, 0, 0);
-    // far clusters: one pseudo-face each
+    // near nodes: exact pairs over their faces.  With the block's neighbour tiles listed, each piece
+    // of a node (its faces within one tile) tests its tile against the list (one compare and a
+    // ballot) and reads the rows' exclusion bits where it is listed; without the list (curved
+    // elements, or more than NBL_MAX such tiles) the vertex ids are compared wherever the node's
+    // and the block's vertex balls can meet (conservative margin for FP32)
+    __shared__ ColRec nst[NW][64];
+    __shared__ int4 nsv[NW][64];
+    // the block's neighbour tiles: lane m holds listed tile m
+    auto tile_list = [&](bool& listed, uint32_t& my_tile) {
+        const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
+        listed = nn <= (uint32_t)NBL_MAX;
+        my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
+    };
+    const uint2* xmb = xm ? xm + (size_t)b * NBL_MAX * 64 : nullptr;
+    // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with the
+    // compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2, 0.922 with 4
+    // and 0.915 with 8); the learned evaluation runs at 3 waves either way and prefers 4
+    constexpr int SU = LEARNED ? 4 : 8;
     if constexpr (LEARNED) {
+        // far clusters: one pseudo-face each, with the network's correction
         for (uint32_t j = wave; j < L.y; j += NW) {
             const int kk = (int)e[cap - 1 - j];
             const NodeRec nd = nodes[kk];
@@ -690,84 +708,149 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
             mlp_correction(W, nd, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
             if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
         }
-    } else {
-        // the wave's entries (j = wave, wave + NW, ...) 64 at a time: every lane fetches one
-        // entry's record (independent loads in flight together), the records are staged in LDS
-        // and read back one by one at a wave-uniform address (a broadcast read); fetching them one
-        // at a time left the wave waiting on two dependent loads per cluster
-        __shared__ NodeRec fst[NW][64];
-        const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
-        for (uint32_t base = 0; base < nfw; base += 64) {
-            const uint32_t m = nfw - base < 64u ? nfw - base : 64u;
-            // the record as two float4 halves (a whole-struct copy under the condition went
-            // through scratch memory)
-            float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
-            if ((uint32_t)lane < m) {
-                const float4* src = reinterpret_cast<const float4*>(
-                    nodes + e[cap - 1 - ((uint32_t)wave + NW * (base + (uint32_t)lane))]);
-                n0 = src[0];
-                n1 = src[1];
+        bool listed;
+        uint32_t my_tile;
+        tile_list(listed, my_tile);
+        for (uint32_t j = wave; j < L.x; j += NW) {
+            const int64_t kk = (int64_t)e[j];
+            const int lev = 63 - __builtin_clzll((unsigned long long)kk);
+            const int64_t span = (int64_t)1 << (H - lev);
+            const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
+            const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
+            if (listed) {
+                ff_near_tiles<SU, LOL>(cols, org, f0, f1, cxd, cyd, czd, me, my_tile, xmb, nst[wave], lane, acc, hi,
+                                       lo, cnt, lol);
+                continue;
             }
-            lds_phase();  // the previous batch's reads of fst come first
-            float4* dst = reinterpret_cast<float4*>(&fst[wave][lane]);
-            dst[0] = n0;
-            dst[1] = n1;
-            lds_phase();  // the reads below see every lane's record
-            // FSU clusters per step: independent pair chains, accumulated in cluster order (the
-            // level-7 call took 0.920-0.928 ms with 1 per step, 0.912-0.916 ms with 4 or 8)
-            constexpr uint32_t FSU = 8;
-            uint32_t k = 0;
-            for (; k + FSU <= m; k += FSU) {
-#pragma unroll
-                for (uint32_t u = 0; u < FSU; ++u) {
-                    const NodeRec nd = fst[wave][k + u];
-                    const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
-                    ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+            const NodeRec nd = nodes[kk];
+            if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
+                ff_near_staged<false, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave],
+                                               nsv[wave], lane, acc, hi, lo, cnt, lol);
+            else
+                ff_near_staged<true, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave],
+                                              lane, acc, hi, lo, cnt, lol);
+        }
+    } else {
+        // One inner loop for every batch of up to 64 columns: the wave's far clusters (entries
+        // j = wave, wave + NW, ... of the far list), 64 at a time as pseudo-faces, then the pieces
+        // of its near nodes.  Every lane fetches one column's record (independent loads in flight
+        // together); the records are staged in the wave's LDS slots and read back column by column
+        // at a wave-uniform address (a broadcast).  A single loop keeps one register assignment for
+        // the sums (four inlined loops had the compiler copying 22 of them at every switch between
+        // loops).  The exclusion mode is uniform per batch: none, the tile's mask bits, or the
+        // vertex compares of the fall-back.  The same pairs in the same order as separate loops.
+        bool listed;
+        uint32_t my_tile;
+        tile_list(listed, my_tile);
+        const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
+        uint32_t fb = 0;          // far clusters staged so far
+        uint32_t jn = wave;       // next near entry
+        int64_t f = 0, f1 = 0;    // the current near node's remaining faces
+        bool cmp_node = false;    // fall-back: the current node compares vertex ids
+        ColRec* st = nst[wave];
+        int4* sv = nsv[wave];
+        for (;;) {
+            int m, mode = 0, pos0 = 0;  // mode 0: no exclusion, 1: mask bits, 2: vertex compares
+            float px, py, pz;
+            float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
+            int4 v = nov;
+            uint2 mk = make_uint2(0u, 0u);
+            if (fb < nfw) {
+                m = (int)(nfw - fb < 64u ? nfw - fb : 64u);
+                if (lane < m) {
+                    // NodeRec (cx, cy, cz, r | a, nx, ny, nz) as a column record (cx, cy, cz, a | nx, ny, nz, 0),
+                    // two float4 halves (a whole-struct copy under the condition went through scratch)
+                    const float4* src = reinterpret_cast<const float4*>(
+                        nodes + e[cap - 1 - ((uint32_t)wave + NW * (fb + (uint32_t)lane))]);
+                    const float4 n0 = src[0], n1 = src[1];
+                    c0 = make_float4(n0.x, n0.y, n0.z, n1.x);
+                    c1 = make_float4(n1.y, n1.z, n1.w, 0.f);
                 }
-                cnt += (int)FSU;
+                px = ax;
+                py = ay;
+                pz = az;
+                fb += (uint32_t)m;
+            } else {
+                if (f >= f1) {  // the next near node
+                    if (jn >= L.x) break;
+                    const int64_t kk = (int64_t)e[jn];
+                    jn += NW;
+                    const int lev = 63 - __builtin_clzll((unsigned long long)kk);
+                    const int64_t span = (int64_t)1 << (H - lev);
+                    f = (kk - ((int64_t)1 << lev)) * span * leaf;
+                    f1 = std::min<int64_t>(nF, f + span * leaf);
+                    if (!listed) {
+                        const NodeRec nd = nodes[kk];
+                        cmp_node = !(ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r);
+                    }
+                    continue;
+                }
+                const int64_t t = f / CTILE;
+                const int64_t fend = std::min<int64_t>(f1, (t + 1) * CTILE);
+                m = (int)(fend - f);
+                if (lane < m) {
+                    const float4* src = reinterpret_cast<const float4*>(cols + f + lane);
+                    c0 = src[0];
+                    c1 = src[1];
+                    if (!listed && cmp_node) v = colv[f + lane];
+                }
+                px = (float)(cxd - org[3 * t]);
+                py = (float)(cyd - org[3 * t + 1]);
+                pz = (float)(czd - org[3 * t + 2]);
+                if (listed) {
+                    const uint64_t hit = __ballot(my_tile == (uint32_t)t);
+                    if (hit) {
+                        mode = 1;
+                        mk = xmb[(size_t)(__ffsll((unsigned long long)hit) - 1) * 64 + lane];
+                        pos0 = (int)(f - t * CTILE);
+                    }
+                } else if (cmp_node) {
+                    mode = 2;
+                }
+                f = fend;
+            }
+            lds_phase();  // the previous batch's reads of the slots come first
+            float4* dst = reinterpret_cast<float4*>(st + lane);
+            dst[0] = c0;
+            dst[1] = c1;
+            if (mode == 2) sv[lane] = v;
+            lds_phase();  // the reads below see every lane's record
+            const uint64_t m64 = ((((uint64_t)mk.y) << 32) | (uint64_t)mk.x) >> pos0;  // bit k: column k
+            const uint32_t mlo = (uint32_t)m64, mhi = (uint32_t)(m64 >> 32);
+            static_assert(32 % SU == 0, "a step's columns read one 32-bit word of the mask");
+            int k = 0;
+            for (; k + SU <= m; k += SU) {
+                if (mode == 1) {
+                    const uint32_t wd = k < 32 ? mlo : mhi;
+#pragma unroll
+                    for (int u = 0; u < SU; ++u)
+                        ff_pair<6, true, 2>(st[k + u], make_int4((int)((wd >> ((k & 31) + u)) & 1u), 0, 0, 0), px, py,
+                                            pz, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+                } else if (mode == 2) {
+#pragma unroll
+                    for (int u = 0; u < SU; ++u)
+                        ff_pair<6, true, 1>(st[k + u], sv[k + u], px, py, pz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z,
+                                            acc);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < SU; ++u)
+                        ff_pair<6, true, 0>(st[k + u], nov, px, py, pz, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+                }
+                cnt += SU;
                 if (cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
             }
             for (; k < m; ++k) {
-                const NodeRec nd = fst[wave][k];
-                const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
-                ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
+                const uint32_t wd = k < 32 ? mlo : mhi;
+                if (mode == 1)
+                    ff_pair<6, true, 2>(st[k], make_int4((int)((wd >> (k & 31)) & 1u), 0, 0, 0), px, py, pz, me.nx,
+                                        me.ny, me.nz, 0, 0, 0, acc);
+                else if (mode == 2)
+                    ff_pair<6, true, 1>(st[k], sv[k], px, py, pz, me.nx, me.ny, me.nz, mv.x, mv.y, mv.z, acc);
+                else
+                    ff_pair<6, true, 0>(st[k], nov, px, py, pz, me.nx, me.ny, me.nz, 0, 0, 0, acc);
                 if (++cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
             }
         }
-    }
-    // near nodes: exact pairs over their faces.  With the block's neighbour tiles listed, each piece
-    // of a node tests its tile against the list (one compare and a ballot) and reads the rows'
-    // exclusion bits where it is listed; without the list (curved elements, or more than NBL_MAX
-    // such tiles) the vertex ids are compared wherever the node's and the block's vertex balls can
-    // meet (conservative margin for FP32)
-    __shared__ ColRec nst[NW][64];
-    __shared__ int4 nsv[NW][64];
-    const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
-    const bool listed = nn <= (uint32_t)NBL_MAX;
-    const uint32_t my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
-    const uint2* xmb = xm ? xm + (size_t)b * NBL_MAX * 64 : nullptr;
-    // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with the
-    // compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2, 0.922 with 4
-    // and 0.915 with 8); the learned evaluation runs at 3 waves either way and prefers 4
-    constexpr int SU = LEARNED ? 4 : 8;
-    for (uint32_t j = wave; j < L.x; j += NW) {
-        const int64_t kk = (int64_t)e[j];
-        const int lev = 63 - __builtin_clzll((unsigned long long)kk);
-        const int64_t span = (int64_t)1 << (H - lev);
-        const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
-        const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-        if (listed) {
-            ff_near_tiles<SU, LOL>(cols, org, f0, f1, cxd, cyd, czd, me, my_tile, xmb, nst[wave], lane, acc, hi, lo,
-                                   cnt, lol);
-            continue;
-        }
-        const NodeRec nd = nodes[kk];
-        if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
-            ff_near_staged<false, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave],
-                                           lane, acc, hi, lo, cnt, lol);
-        else
-            ff_near_staged<true, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave], lane,
-                                          acc, hi, lo, cnt, lol);
     }
     ff_fold_at<LOL>(acc, hi, lo, lol, lane);
     if constexpr (LOL) {
