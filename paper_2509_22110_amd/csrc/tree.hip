@@ -694,10 +694,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
     };
     const uint2* xmb = xm ? xm + (size_t)b * NBL_MAX * 64 : nullptr;
-    // columns per step: 8 independent pair chains for the monopole evaluation (109 VGPRs with the
-    // compensation terms in LDS, 4 waves per SIMD; the level-7 call took 0.943 ms with 2, 0.922 with 4
-    // and 0.915 with 8); the learned evaluation runs at 3 waves either way and prefers 4
-    constexpr int SU = LEARNED ? 4 : 8;
+    // columns per step: 32 independent pair chains for the monopole evaluation (96 VGPRs with the
+    // compensation terms in LDS and one inner loop; the level-7 call took 0.943 ms with 2, 0.922 with
+    // 4 and 0.915 with 8 in four separate loops, then 0.913 / 0.901 / 0.897 ms with 8 / 16 / 32 in
+    // one); the learned evaluation runs at 3 waves either way and prefers 4
+    constexpr int SU = LEARNED ? 4 : 32;
     if constexpr (LEARNED) {
         // far clusters: one pseudo-face each, with the network's correction
         for (uint32_t j = wave; j < L.y; j += NW) {
