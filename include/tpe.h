@@ -231,9 +231,12 @@ int tpe_conf_gradient(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F
  * That changes only when blocks run, never what they compute.  The tree keeps the work of each
  * block of its last call (a device array, written by every call; calls that share one tree on
  * several streams at once are still correct), the vertex -> (face, corner) lists of the gradient's
- * vertex gather in tree order (they depend only on F and the order; 12 B per face) and a checksum
- * of F: every far-field call recomputes the checksum of the F it is given and fails with
- * TPE_ERR_INVALID_ARG if it differs.  *out is owned by the caller (tpe_tree_destroy).
+ * vertex gather in tree order (they depend only on F and the order; 12 B per face), per target
+ * block the tiles of 64 faces that hold a face sharing a vertex with it, with a 64-bit exclusion
+ * mask per (row, listed tile) that the evaluation tests instead of comparing vertex ids (at most 16
+ * tiles: 68 B + 8 KB per block, about 130 B per face), and a checksum of F: every far-field call
+ * recomputes the checksum of the F it is given and fails with TPE_ERR_INVALID_ARG if it differs.
+ * *out is owned by the caller (tpe_tree_destroy).
  * Synchronises the stream. */
 int tpe_build_tree(tpe_ctx* ctx, const double* X, int64_t V, const int32_t* F, int64_t nF,
                    int32_t leaf_size, tpe_tree** out);
