@@ -122,35 +122,6 @@ __device__ __forceinline__ void ff_staged_pairs(const ColRec* st, const int4* sv
     }
 }
 
-// The same pairs with the exclusion read from the lane's 64-bit mask mk of the piece's tile (bit j:
-// the row face shares a vertex with the tile's face j); the piece starts at position pos0 of its
-// tile.  One bit test per pair instead of nine vertex comparisons.
-template <int SU, bool LOL = false>
-__device__ __forceinline__ void ff_staged_pairs_bits(const ColRec* st, int m, int pos0, uint2 mk, float rx, float ry,
-                                                     float rz, const ColRec& me, float (&acc)[NACC],
-                                                     float (&hi)[NACC], float (&lo)[NACC], float* lol, int lane,
-                                                     int& cnt) {
-    static_assert(32 % SU == 0, "a step's columns read one 32-bit word of the mask");
-    const uint64_t m64 = ((((uint64_t)mk.y) << 32) | (uint64_t)mk.x) >> pos0;  // bit k: column k
-    const uint32_t mlo = (uint32_t)m64, mhi = (uint32_t)(m64 >> 32);
-    int k = 0;
-    for (; k + SU <= m; k += SU) {
-        const uint32_t wd = k < 32 ? mlo : mhi;
-#pragma unroll
-        for (int u = 0; u < SU; ++u)
-            ff_pair<6, true, 2>(st[k + u], make_int4((int)((wd >> ((k & 31) + u)) & 1u), 0, 0, 0), rx, ry, rz,
-                                me.nx, me.ny, me.nz, 0, 0, 0, acc);
-        cnt += SU;
-        if (cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
-    }
-    for (; k < m; ++k) {
-        const uint32_t wd = k < 32 ? mlo : mhi;
-        ff_pair<6, true, 2>(st[k], make_int4((int)((wd >> (k & 31)) & 1u), 0, 0, 0), rx, ry, rz, me.nx, me.ny, me.nz,
-                            0, 0, 0, acc);
-        if (++cnt >= 64) { ff_fold_at<LOL>(acc, hi, lo, lol, lane); cnt = 0; }
-    }
-}
-
 // Exact pairs of the block's rows with the faces [f0, f1) (a near node), with the shared-vertex
 // exclusion when MASK (a node whose vertices cannot reach the block's needs none); rows are
 // re-expressed relative to each tile's FP64 origin.  The column records go through the wave's own
@@ -193,48 +164,6 @@ __device__ __forceinline__ void ff_near_staged(const ColRec* __restrict__ cols, 
         if constexpr (MASK) sv[lane] = v;
         asm volatile("" ::: "memory");  // the reads below see every lane's record
         ff_staged_pairs<MASK, SU, LOL>(st, sv, m, rx, ry, rz, me, mv, acc, hi, lo, lol, lane, cnt);
-        f = fend;
-    }
-}
-
-// ff_near_staged with the exclusion decided per piece: a piece (the node's faces within one tile)
-// whose tile is one of the block's listed neighbour tiles (my_tile: lane m holds listed tile m)
-// tests the lane's precomputed mask bits (xmb[slot * 64 + lane]); any other piece holds no face
-// sharing a vertex with the block and runs unmasked.  The same pairs in the same order as the
-// vertex comparisons give.
-template <int SU, bool LOL = false>
-__device__ __forceinline__ void ff_near_tiles(const ColRec* __restrict__ cols, const double* __restrict__ org,
-                                              int64_t f0, int64_t f1, double cxd, double cyd, double czd,
-                                              const ColRec& me, uint32_t my_tile, const uint2* __restrict__ xmb,
-                                              ColRec* st, int lane, float (&acc)[NACC], float (&hi)[NACC],
-                                              float (&lo)[NACC], int& cnt, float* lol = nullptr) {
-    static_assert(CTILE == 64, "a tile's exclusion mask is one 64-bit word per row");
-    int64_t f = f0;
-    while (f < f1) {
-        const int64_t t = f / CTILE;
-        const int64_t fend = std::min<int64_t>(f1, (t + 1) * CTILE);
-        const int m = (int)(fend - f);
-        float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = c0;
-        if (lane < m) {
-            const float4* src = reinterpret_cast<const float4*>(cols + f + lane);
-            c0 = src[0];
-            c1 = src[1];
-        }
-        const uint64_t listed = __ballot(my_tile == (uint32_t)t);
-        uint2 mk = make_uint2(0u, 0u);
-        if (listed) mk = xmb[(size_t)(__ffsll((unsigned long long)listed) - 1) * 64 + lane];
-        const float rx = (float)(cxd - org[3 * t]), ry = (float)(cyd - org[3 * t + 1]), rz = (float)(czd - org[3 * t + 2]);
-        asm volatile("" ::: "memory");  // the previous piece's reads of the slots come first
-        float4* dst = reinterpret_cast<float4*>(st + lane);
-        dst[0] = c0;
-        dst[1] = c1;
-        asm volatile("" ::: "memory");  // the reads below see every lane's record
-        if (listed)
-            ff_staged_pairs_bits<SU, LOL>(st, m, (int)(f - t * CTILE), mk, rx, ry, rz, me, acc, hi, lo, lol, lane,
-                                          cnt);
-        else
-            ff_staged_pairs<false, SU, LOL>(st, nullptr, m, rx, ry, rz, me, make_int4(0, 0, 0, 0), acc, hi, lo, lol,
-                                            lane, cnt);
         f = fend;
     }
 }

@@ -395,13 +395,21 @@ __device__ __forceinline__ void to_frame(const float* v, const Frame& fr, float*
 
 // Learned correction of one far cluster for the wave's 64 rows: features per row, the MLP on the
 // 64 x 32 feature block (MFMA, LDS scratch), and the corrections added to the row sums.
+// The correction's gate, r_B / rho >= min_s for the row at (ax, ay, az), in one fixed evaluation
+// (explicit FMAs): ff_correct's batch filter and mlp_correction take the same decision.
+__device__ __forceinline__ bool mlp_gate(const MlpPacked* __restrict__ W, const NodeRec& cn, float ax, float ay,
+                                         float az) {
+    const float gx = ax - cn.cx, gy = ay - cn.cy, gz = az - cn.cz;
+    const float d2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+    const float s2 = W->min_s * W->min_s;
+    return cn.r * cn.r >= s2 * d2;
+}
+
 __device__ __forceinline__ void mlp_correction(const MlpPacked* __restrict__ W, const NodeRec& cn, const NodeMom& mm,
                                                float ax, float ay, float az, float nx, float ny, float nz,
                                                MlpScratch& ms, float (&acc)[NACC]) {
-    // the gate (r_B / rho >= min_s), checked before the features: the wave skips the network when
-    // no row needs it
-    const float gx = ax - cn.cx, gy = ay - cn.cy, gz = az - cn.cz;
-    const bool gate = cn.r * cn.r >= W->min_s * W->min_s * (gx * gx + gy * gy + gz * gz);
+    // the gate, checked before the features: the wave skips the network when no row needs it
+    const bool gate = mlp_gate(W, cn, ax, ay, az);
     if (!__any(gate)) return;
     Frame fr;
     float x[32], y[16];
@@ -638,20 +646,15 @@ int64_t block_exclusion_mask_words(int64_t n) { return ((n + 63) / 64) * NBL_MAX
 // was measured slower: the launch is bound by the total pair work, not by its last block.  At
 // least 3 waves per SIMD: the monopole walk at 327,680 faces takes 1.19 ms of call time at 3, 1.20
 // at 4 (128 VGPRs with spills), 1.28 at 5.)
-template <bool LEARNED, int NW>
+template <int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void ff_eval(
     const ColRec* __restrict__ cols, const int4* __restrict__ colv, const double* __restrict__ c64,
-    const double* __restrict__ org, const NodeRec* __restrict__ nodes, const NodeMom* __restrict__ moms,
-    const MlpPacked* __restrict__ W, int H, int leaf, int64_t nF, const uint32_t* __restrict__ bbox,
-    const float4* __restrict__ balls, int64_t Fp, double* __restrict__ acc64, const uint32_t* __restrict__ order,
-    int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst, const uint32_t* __restrict__ nbl,
-    const uint2* __restrict__ xm) {
+    const double* __restrict__ org, const NodeRec* __restrict__ nodes, int H, int leaf, int64_t nF,
+    const uint32_t* __restrict__ bbox, const float4* __restrict__ balls, int64_t Fp, double* __restrict__ acc64,
+    const uint32_t* __restrict__ order, int64_t cap, const uint32_t* __restrict__ ent, const uint4* __restrict__ lst,
+    const uint32_t* __restrict__ nbl, const uint2* __restrict__ xm) {
     constexpr int NRED = NW > 1 ? NW - 1 : 1;
-    __shared__ MlpScratch ms[LEARNED ? NW : 1];
-    __shared__ float red_own[LEARNED ? 1 : NRED][LEARNED ? 1 : 2 * NACC][64];
-    static_assert(!LEARNED || sizeof(MlpScratch) * NW >= sizeof(float) * NRED * 2 * NACC * 64, "fold space");
-    float (*red)[2 * NACC][64] = LEARNED ? reinterpret_cast<float (*)[2 * NACC][64]>(&ms[0])
-                                         : reinterpret_cast<float (*)[2 * NACC][64]>(&red_own[0][0][0]);
+    __shared__ float red[NRED][2 * NACC][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int64_t b = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
@@ -671,9 +674,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     // the monopole evaluation keeps its compensation terms in the fold area during the walk (LOL,
     // each wave its own slots, touched once per 64 columns): the registers go to more columns per
     // step below
-    constexpr bool LOL = !LEARNED && NW > 1;
+    constexpr bool LOL = NW > 1;
     static_assert(!LOL || NW * NACC <= NRED * 2 * NACC, "the waves' compensation terms fit the fold area");
-    float* lol = LOL ? &red_own[0][0][0] + (size_t)wave * NACC * 64 : nullptr;
+    float* lol = LOL ? &red[0][0][0] + (size_t)wave * NACC * 64 : nullptr;
     if constexpr (LOL) {
 #pragma unroll
         for (int k = 0; k < NACC; ++k) lol[k * 64 + lane] = 0.f;
@@ -688,50 +691,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     __shared__ ColRec nst[NW][64];
     __shared__ int4 nsv[NW][64];
     // the block's neighbour tiles: lane m holds listed tile m
-    auto tile_list = [&](bool& listed, uint32_t& my_tile) {
-        const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
-        listed = nn <= (uint32_t)NBL_MAX;
-        my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
-    };
+    const uint32_t nn = nbl ? nbl[(size_t)b * NBL_STRIDE] : NBL_OVERFLOW;
+    const bool listed = nn <= (uint32_t)NBL_MAX;
+    const uint32_t my_tile = listed && (uint32_t)lane < nn ? nbl[(size_t)b * NBL_STRIDE + 1 + lane] : 0xffffffffu;
     const uint2* xmb = xm ? xm + (size_t)b * NBL_MAX * 64 : nullptr;
-    // columns per step: 32 independent pair chains for the monopole evaluation (96 VGPRs with the
-    // compensation terms in LDS and one inner loop; the level-7 call took 0.943 ms with 2, 0.922 with
-    // 4 and 0.915 with 8 in four separate loops, then 0.913 / 0.901 / 0.897 ms with 8 / 16 / 32 in
-    // one); the learned evaluation runs at 3 waves either way and prefers 4
-    constexpr int SU = LEARNED ? 4 : 32;
-    if constexpr (LEARNED) {
-        // far clusters: one pseudo-face each, with the network's correction
-        for (uint32_t j = wave; j < L.y; j += NW) {
-            const int kk = (int)e[cap - 1 - j];
-            const NodeRec nd = nodes[kk];
-            const ColRec cr = {nd.cx, nd.cy, nd.cz, nd.a, nd.nx, nd.ny, nd.nz, 0.f};
-            ff_pair<6, true, false>(cr, nov, ax, ay, az, me.nx, me.ny, me.nz, 0, 0, 0, acc);
-            mlp_correction(W, nd, moms[kk], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
-            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
-        }
-        bool listed;
-        uint32_t my_tile;
-        tile_list(listed, my_tile);
-        for (uint32_t j = wave; j < L.x; j += NW) {
-            const int64_t kk = (int64_t)e[j];
-            const int lev = 63 - __builtin_clzll((unsigned long long)kk);
-            const int64_t span = (int64_t)1 << (H - lev);
-            const int64_t f0 = (kk - ((int64_t)1 << lev)) * span * leaf;
-            const int64_t f1 = std::min<int64_t>(nF, f0 + span * leaf);
-            if (listed) {
-                ff_near_tiles<SU, LOL>(cols, org, f0, f1, cxd, cyd, czd, me, my_tile, xmb, nst[wave], lane, acc, hi,
-                                       lo, cnt, lol);
-                continue;
-            }
-            const NodeRec nd = nodes[kk];
-            if (ball_dist(tb, nd) * (1.f - 1e-5f) > tb.w + nd.r)
-                ff_near_staged<false, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave],
-                                               nsv[wave], lane, acc, hi, lo, cnt, lol);
-            else
-                ff_near_staged<true, SU, LOL>(cols, colv, org, f0, f1, cxd, cyd, czd, me, mv, nst[wave], nsv[wave],
-                                              lane, acc, hi, lo, cnt, lol);
-        }
-    } else {
+    // columns per step: 32 independent pair chains (96 VGPRs with the compensation terms in LDS and
+    // one inner loop; the level-7 call took 0.943 ms with 2, 0.922 with 4 and 0.915 with 8 in four
+    // separate loops, then 0.913 / 0.901 / 0.897 ms with 8 / 16 / 32 in one)
+    constexpr int SU = 32;
+    {
         // One inner loop for every batch of up to 64 columns: the wave's far clusters (entries
         // j = wave, wave + NW, ... of the far list), 64 at a time as pseudo-faces, then the pieces
         // of its near nodes.  Every lane fetches one column's record (independent loads in flight
@@ -740,9 +708,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         // the sums (four inlined loops had the compiler copying 22 of them at every switch between
         // loops).  The exclusion mode is uniform per batch: none, the tile's mask bits, or the
         // vertex compares of the fall-back.  The same pairs in the same order as separate loops.
-        bool listed;
-        uint32_t my_tile;
-        tile_list(listed, my_tile);
         const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
         uint32_t fb = 0;          // far clusters staged so far
         uint32_t jn = wave;       // next near entry
@@ -860,7 +825,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         __syncthreads();  // every wave has its terms back before the fold area is reused below
     }
     if constexpr (NW > 1) {
-        if constexpr (LEARNED) __syncthreads();  // the MLP scratch is reused below
         if (wave > 0) {
 #pragma unroll
             for (int kk = 0; kk < NACC; ++kk) {
@@ -888,6 +852,109 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
     if (wave == 0) {
 #pragma unroll
         for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] = (double)hi[kk] - (double)lo[kk];
+    }
+}
+
+// The learned correction of the far field: one work-group of NW waves per target block (tree
+// order), after ff_eval has written the block's exact near pairs and monopole far pairs to acc64.
+// Entry j of the block's far list goes to wave j mod NW; mlp_correction gates each cluster (the
+// wave skips the network when no row qualifies) and adds the network's predicted corrections to the
+// wave's FP32 sums, folded every 64 clusters as in ff_eval and across the waves through the MLP
+// scratch; wave 0 adds them to acc64.  Keeping the network out of ff_eval lets the pairs run at
+// that kernel's occupancy (the level-7 learned call took 2.06 ms in one kernel, whose pairs alone,
+// with the gate closed, took 0.98 ms against the monopole kernel's 0.72 ms).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void ff_correct(
+    const ColRec* __restrict__ cols, const double* __restrict__ c64, const NodeRec* __restrict__ nodes,
+    const NodeMom* __restrict__ moms, const MlpPacked* __restrict__ W, const uint32_t* __restrict__ bbox,
+    int64_t Fp, double* __restrict__ acc64, int64_t cap, const uint32_t* __restrict__ ent,
+    const uint4* __restrict__ lst) {
+    constexpr int NRED = NW > 1 ? NW - 1 : 1;
+    __shared__ MlpScratch ms[NW];
+    static_assert(sizeof(MlpScratch) * NW >= sizeof(float) * NRED * 2 * NACC * 64, "fold space");
+    float (*red)[2 * NACC][64] = reinterpret_cast<float (*)[2 * NACC][64]>(&ms[0]);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int64_t b = blockIdx.x;
+    const int64_t i = b * 64 + lane;
+    const double cxd = c64[3 * i], cyd = c64[3 * i + 1], czd = c64[3 * i + 2];
+    const ColRec me = cols[i];
+    double o[3];
+    norm_origin(bbox, o);
+    const float ax = (float)(cxd - o[0]), ay = (float)(cyd - o[1]), az = (float)(czd - o[2]);
+    const uint4 L = lst[b];
+    const uint32_t* e = ent + (size_t)b * cap;
+    float hi[NACC], lo[NACC], acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) { hi[k] = 0.f; lo[k] = 0.f; acc[k] = 0.f; }
+    int cnt = 0;
+    // the wave's clusters 64 at a time: every lane fetches one record (independent loads in flight
+    // together), staged in LDS and read back one by one at a wave-uniform address, so that the gate
+    // of a cluster the network skips costs no dependent load
+    __shared__ NodeRec cst[NW][64];
+    __shared__ uint32_t cix[NW][64];
+    const uint32_t nfw = L.y > (uint32_t)wave ? (L.y - 1 - (uint32_t)wave) / NW + 1 : 0u;
+    for (uint32_t base = 0; base < nfw; base += 64) {
+        const uint32_t m = nfw - base < 64u ? nfw - base : 64u;
+        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+        uint32_t kx = 0u;
+        if ((uint32_t)lane < m) {
+            kx = e[cap - 1 - ((uint32_t)wave + NW * (base + (uint32_t)lane))];
+            const float4* src = reinterpret_cast<const float4*>(nodes + kx);
+            n0 = src[0];
+            n1 = src[1];
+        }
+        lds_phase();  // the previous batch's reads of the slots come first
+        float4* dst = reinterpret_cast<float4*>(&cst[wave][lane]);
+        dst[0] = n0;
+        dst[1] = n1;
+        cix[wave][lane] = kx;
+        lds_phase();  // the reads below see every lane's record
+        // the batch's gates first (a few instructions per cluster, no branch), then the network on
+        // the clusters some row needs, in order
+        uint64_t need = 0ull;
+        for (uint32_t k = 0; k < m; ++k) {
+            const NodeRec nd = cst[wave][k];
+            if (__any(mlp_gate(W, nd, ax, ay, az))) need |= 1ull << k;
+        }
+        while (need) {
+            const uint32_t k = (uint32_t)(__ffsll((unsigned long long)need) - 1);
+            need &= need - 1ull;
+            const NodeRec nd = cst[wave][k];
+            mlp_correction(W, nd, moms[cix[wave][k]], ax, ay, az, me.nx, me.ny, me.nz, ms[wave], acc);
+            if (++cnt >= 64) { ff_fold(acc, hi, lo); cnt = 0; }
+        }
+    }
+    ff_fold(acc, hi, lo);
+    if constexpr (NW > 1) {
+        __syncthreads();  // the MLP scratch is reused below
+        if (wave > 0) {
+#pragma unroll
+            for (int kk = 0; kk < NACC; ++kk) {
+                red[wave - 1][kk][lane] = hi[kk];
+                red[wave - 1][NACC + kk][lane] = lo[kk];
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int j = 0; j < NW - 1; ++j)
+#pragma unroll
+                for (int kk = 0; kk < NACC; ++kk) {
+                    float y = red[j][kk][lane] - lo[kk];
+                    float t = hi[kk] + y;
+                    lo[kk] = (t - hi[kk]) - y;
+                    hi[kk] = t;
+                    y = -red[j][NACC + kk][lane] - lo[kk];
+                    t = hi[kk] + y;
+                    lo[kk] = (t - hi[kk]) - y;
+                    hi[kk] = t;
+                }
+        }
+    }
+    if (wave == 0) {
+#pragma unroll
+        for (int kk = 0; kk < NACC; ++kk) acc64[(size_t)kk * Fp + i] += (double)hi[kk] - (double)lo[kk];
     }
 }
 
@@ -1454,19 +1521,17 @@ hipError_t launch_farfield(const ColRec* cols, const int4* colv, const double* c
     const NodeMom* m = (const NodeMom*)(r + ((size_t)2 << H));
     hipLaunchKernelGGL(ff_classify, dim3((unsigned)((nb + FFC_NW - 1) / FFC_NW)), dim3(64 * FFC_NW), 0, st, r, H, leaf,
                        nF, balls, theta, cap, ent, lst, work, flags);
-    // launch order (monopole) and the interaction counts, in one work-group
-    const uint32_t* order = mlp_packed ? nullptr : sort[1];
-    hipError_t e = launch_ff_order(work, nb, mlp_packed ? nullptr : sort[1], lst, stats, st);
+    // launch order (heaviest blocks first) and the interaction counts, in one work-group
+    const uint32_t* order = sort[1];
+    hipError_t e = launch_ff_order(work, nb, sort[1], lst, stats, st);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;  // timing: the evaluation alone
-    if (mlp_packed)
-        hipLaunchKernelGGL((ff_eval<true, FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols,
-                           colv, c64, org, r, m, (const MlpPacked*)mlp_packed, H, leaf, nF, bbox, balls, Fp, acc64,
-                           order, cap, ent, lst, nbl, xm);
-    else
-        hipLaunchKernelGGL((ff_eval<false, FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org,
-                           r, m, (const MlpPacked*)nullptr, H, leaf, nF, bbox, balls, Fp, acc64, order, cap, ent, lst,
-                           nbl, xm);
+    hipLaunchKernelGGL((ff_eval<FF_NW>), dim3((unsigned)nb), dim3(64 * FF_NW), 0, st, cols, colv, c64, org, r, H, leaf,
+                       nF, bbox, balls, Fp, acc64, order, cap, ent, lst, nbl, xm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (mlp_packed)  // the learned correction, added to the row sums
+        hipLaunchKernelGGL((ff_correct<FF_NW_LEARNED>), dim3((unsigned)nb), dim3(64 * FF_NW_LEARNED), 0, st, cols, c64,
+                           r, m, (const MlpPacked*)mlp_packed, bbox, Fp, acc64, cap, ent, lst);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return ev1 ? hipEventRecord(ev1, st) : hipSuccess;
 }
